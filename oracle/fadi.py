@@ -1,0 +1,193 @@
+"""Oracle (test infrastructure only): the low-rank factored ADI iteration for
+A X + X B = -f g^T (eq. (sylv)) with sparse-direct ("exact") inner solves.
+
+This follows Algorithm 1 (inexact LR-ADI) with M = I, C = I, in the
+residual-factor form of eq. (lradi_basic):
+
+    z_k = (A + beta_k I)^{-1} w_{k-1},        w_k = w_{k-1} + gamma_k z_k,
+    y_k = (B + alpha_k I)^{-*} t_{k-1},       t_k = t_{k-1} + conj(gamma_k) y_k,
+    gamma_k = -(beta_k + alpha_k),            w_0 = f, t_0 = g,
+
+and returns Z_k, Gamma_k = diag(gamma_1 I_r, ..., gamma_k I_r), Y_k with
+X ~ Z_k Gamma_k Y_k^*.  The loop runs while ||w_{k-1} t_{k-1}^*|| >= tau ||f g^T||
+(the while-condition of Algorithm 1; spectral norm, Sec. 1.1).
+
+Shift naming used throughout: pA[k] is the shift added to A (beta_k of
+Algorithm 1), pB[k] the shift added to B^T (conj(alpha_k)); so
+gamma_k = -(pA[k] + pB[k]) for real shifts.  Shift arrays are cycled when the
+iteration runs longer than they are.
+
+Only tests/, the smoke check and the bench's CPU baseline use this module;
+the product path never imports it.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def spectral_norm(M: np.ndarray) -> float:
+    """||M||_2 (largest singular value) by a dense SVD."""
+    if M.size == 0:
+        return 0.0
+    return float(np.linalg.svd(M, compute_uv=False)[0])
+
+
+def lowrank_product_norm(W: np.ndarray, T: np.ndarray) -> float:
+    """||W T^*||_2 without forming the n x m product: with thin QR factors
+    W = Q_w R_w and T = Q_t R_t, ||W T^*|| = ||R_w R_t^*|| (Sec. 2.1 uses this
+    to evaluate the residual norm cheaply from the rank-r factors)."""
+    Rw = np.linalg.qr(W, mode="r")
+    Rt = np.linalg.qr(T, mode="r")
+    return spectral_norm(Rw @ Rt.conj().T)
+
+
+def rescale_rhs(f: np.ndarray, g: np.ndarray):
+    """Scale f and g to equal spectral norm keeping f g^T unchanged (the
+    experiments of Sec. 4 rescale the random factors so that ||f|| = ||g||)."""
+    nf, ng = spectral_norm(f), spectral_norm(g)
+    s = np.sqrt(ng / nf)
+    return f * s, g / s
+
+
+@dataclasses.dataclass
+class FadiResult:
+    Z: np.ndarray            # n x (k r)
+    Y: np.ndarray            # m x (k r)
+    gammas: np.ndarray       # k
+    W: np.ndarray            # final residual factor w_k
+    T: np.ndarray            # final residual factor t_k
+    res_hist: List[float]    # ||w_j t_j^*|| / ||f g^T||, j = 1..k
+    norm_fg: float
+    k: int
+    rA: List[np.ndarray]     # inner residuals r^A_j = w_{j-1} - (A + pA_j I) z_j
+    rB: List[np.ndarray]     # inner residuals r^B_j = t_{j-1} - (B^T + pB_j I) y_j
+
+    def D(self) -> np.ndarray:
+        r = self.Z.shape[1] // max(self.k, 1) if self.k else 0
+        return np.repeat(self.gammas, r)
+
+    def X(self) -> np.ndarray:
+        """Dense Z Gamma Y^T (small problems only)."""
+        return (self.Z * self.D()) @ self.Y.T
+
+
+def _direct_solver(M: sp.spmatrix, cache: dict, shift: float) -> Callable:
+    key = float(shift)
+    if key not in cache:
+        n = M.shape[0]
+        cache[key] = spla.splu((M + shift * sp.identity(n, format="csr")).tocsc())
+    lu = cache[key]
+    return lu.solve
+
+
+def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
+         pA: np.ndarray, pB: np.ndarray, tol: float = 1e-8, kmax: int = 50,
+         rescale: bool = True, solve_A: Optional[Callable] = None,
+         solve_B: Optional[Callable] = None, kfixed: Optional[int] = None) -> FadiResult:
+    """Algorithm 1 with direct inner solves (the "direct solves" rows of Table 2).
+
+    solve_A(k, shift, rhs) / solve_B(k, shift, rhs) may replace the direct
+    solves (used by tests that plant inexact solves); by default each distinct
+    shift is LU-factorised once (SuperLU).  kfixed runs exactly that many steps
+    ignoring tau.  Returns the factors, the computed residual history and the
+    inner residual blocks."""
+    A = sp.csr_matrix(A)
+    Bt = sp.csr_matrix(B).T.tocsr()
+    f = np.array(f, dtype=np.float64, copy=True)
+    g = np.array(g, dtype=np.float64, copy=True)
+    if rescale:
+        f, g = rescale_rhs(f, g)
+    norm_fg = lowrank_product_norm(f, g)
+    cacheA, cacheB = {}, {}
+    W, T = f.copy(), g.copy()
+    Zs, Ys, gam, hist, rA, rB = [], [], [], [], [], []
+    J = len(pA)
+    k = 0
+    while True:
+        if norm_fg == 0.0:
+            break          # f g^T = 0: X = 0 is exact, nothing to iterate
+        if kfixed is not None:
+            if k >= kfixed:
+                break
+        else:
+            if k >= kmax or lowrank_product_norm(W, T) < tol * norm_fg:
+                break
+        a, b = float(pA[k % J]), float(pB[k % J])
+        if solve_A is None:
+            z = _direct_solver(A, cacheA, a)(W)
+        else:
+            z = solve_A(k, a, W)
+        if solve_B is None:
+            y = _direct_solver(Bt, cacheB, b)(T)
+        else:
+            y = solve_B(k, b, T)
+        z = np.asarray(z).reshape(W.shape)
+        y = np.asarray(y).reshape(T.shape)
+        rA.append(W - (A @ z + a * z))
+        rB.append(T - (Bt @ y + b * y))
+        gk = -(a + b)
+        W = W + gk * z
+        T = T + gk * y
+        Zs.append(z)
+        Ys.append(y)
+        gam.append(gk)
+        k += 1
+        hist.append(lowrank_product_norm(W, T) / norm_fg)
+    n, r = f.shape
+    m = g.shape[0]
+    Z = np.hstack(Zs) if Zs else np.zeros((n, 0))
+    Y = np.hstack(Ys) if Ys else np.zeros((m, 0))
+    return FadiResult(Z, Y, np.asarray(gam), W, T, hist, norm_fg, k, rA, rB)
+
+
+def true_residual_dense(A, B, f, g, X) -> np.ndarray:
+    """Sylvester residual A X + X B + f g^T as a dense matrix (the sign that
+    makes the k = 0 residual equal f g^T, eq. (adi_res_inexact))."""
+    A = sp.csr_matrix(A)
+    B = sp.csr_matrix(B)
+    return np.asarray(A @ X) + np.asarray((B.T @ X.T).T) + f @ g.T
+
+
+def lowrank_residual_norm(A, B, f, g, Z, d, Y) -> float:
+    """||A Z D Y^T + Z D Y^T B + f g^T||_2 exactly, without forming n x m
+    matrices: the residual equals U V^T with U = [A Z, Z, f] and
+    V = [Y D, B^T Y D, g]; with thin QRs U = Q_u R_u, V = Q_v R_v its norm is
+    ||R_u R_v^T||_2.  d holds the diagonal of D."""
+    A = sp.csr_matrix(A)
+    Bt = sp.csr_matrix(B).T.tocsr()
+    YD = Y * d
+    U = np.hstack([np.asarray(A @ Z), Z, f])
+    V = np.hstack([YD, np.asarray(Bt @ YD), g])
+    Ru = np.linalg.qr(U, mode="r")
+    Rv = np.linalg.qr(V, mode="r")
+    return spectral_norm(Ru @ Rv.T)
+
+
+def lowrank_diff_fro(Z1, d1, Y1, Z2, d2, Y2) -> float:
+    """||Z1 D1 Y1^T - Z2 D2 Y2^T||_F without forming the n x m matrices."""
+    L = np.hstack([Z1 * d1, -(Z2 * d2)])
+    R = np.hstack([Y1, Y2])
+    Rl = np.linalg.qr(L, mode="r")
+    Rr = np.linalg.qr(R, mode="r")
+    return float(np.linalg.norm(Rl @ Rr.T, "fro"))
+
+
+def lowrank_fro(Z, d, Y) -> float:
+    """||Z D Y^T||_F without forming it."""
+    Rl = np.linalg.qr(Z * d, mode="r")
+    Rr = np.linalg.qr(Y, mode="r")
+    return float(np.linalg.norm(Rl @ Rr.T, "fro"))
+
+
+def bartels_stewart(A, B, f, g) -> np.ndarray:
+    """Dense reference solution of A X + X B = -f g^T (Bartels-Stewart via
+    scipy.linalg.solve_sylvester); small n, m only."""
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A)
+    Bd = B.toarray() if sp.issparse(B) else np.asarray(B)
+    return sla.solve_sylvester(Ad, Bd, -f @ g.T)
