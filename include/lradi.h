@@ -1,0 +1,212 @@
+/*
+ * lradi.h -- C ABI of the MI355X (gfx950) implementation of the inexact
+ * low-rank ADI iteration for large Sylvester equations
+ *
+ *     A X + X B = -f g^T,  A (n x n), B (m x m) sparse, f (n x r), g (m x r),
+ *
+ * as stated in eq. (sylv) and Algorithm 1 of Kuerschner, "Inexact linear solves
+ * in the low-rank ADI iteration for large Sylvester equations".  The solution
+ * is returned in factored form X ~ Z D Y^T with D = diag(gamma_1 I_r, ...,
+ * gamma_k I_r) (Algorithm 1, output).  Only the case M = I, C = I and real
+ * shifts is implemented.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Dense blocks are row-major: an n x r block stores entry (i, c) at
+ *    i*r + c.  Factor stacks Z, Y are k consecutive n x r (m x r) blocks.
+ *  - "device" pointers are HIP device allocations (e.g. torch tensors on
+ *    cuda:0); "host" pointers are ordinary memory.  Each argument states which.
+ *  - Shifts: shiftsA[k] is added to A in the k-th A-side solve
+ *    (A + shiftsA[k] I) z_k = w_{k-1} (beta_k of Algorithm 1); shiftsB[k] is
+ *    added to B^T in the B-side solve (B^T + shiftsB[k] I) y_k = t_{k-1}
+ *    (conj(alpha_k)).  gamma_k = -(shiftsA[k] + shiftsB[k]).  Arrays shorter
+ *    than the number of steps are cycled.
+ *  - Every call returns an int status (LRADI_OK = 0; negative = error,
+ *    positive = warning with valid results).  No exception crosses the ABI.
+ *    lradi_last_error() returns a message for the calling thread's last
+ *    failing call.
+ *  - All work of one context is issued on its HIP stream; calls on one context
+ *    must not overlap (a context is not thread-safe).  Calls return after the
+ *    stream has finished unless stated otherwise.
+ */
+#ifndef LRADI_H
+#define LRADI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LRADI_OK 0
+#define LRADI_EINVAL (-1)      /* bad argument (shape, pointer, option)          */
+#define LRADI_ENOMEM (-2)      /* device allocation failed / over HBM budget      */
+#define LRADI_EHIP (-3)        /* a HIP runtime call failed                       */
+#define LRADI_ENAN (-4)        /* NaN or Inf appeared in the iteration            */
+#define LRADI_EBREAKDOWN (-5)  /* unrecoverable Krylov breakdown                  */
+#define LRADI_WNOCONV 1        /* kmax outer steps without reaching tau          */
+#define LRADI_WINNER 2         /* some inner solve stopped at its iteration cap   */
+
+/* ---- tolerance selections (Sec. 3.3) ---------------------------------- */
+#define LRADI_SEL_RELATIVE 0   /* delta^A = rho*||w||, delta^B = rho*||t||        */
+#define LRADI_SEL_FIXED 1      /* delta^A = delta^B = delta_fixed (Table 2 "fixed") */
+#define LRADI_SEL_MID 2        /* eq. (simple_tols)                               */
+#define LRADI_SEL_TIGHT_A 3    /* eq. (one_side): delta^A = delta_min              */
+#define LRADI_SEL_TIGHT_B 4    /* mirror of eq. (one_side): delta^B = delta_min    */
+
+/* ---- arithmetic of the inner Krylov solves ---------------------------- */
+#define LRADI_FP64 0           /* basis, SpMM and projections in FP64             */
+#define LRADI_FP32_INNER 1     /* basis, SpMM and projections in FP32; residual
+                                  factors, refinement residual, small least
+                                  squares and all norms in FP64                  */
+
+/* number of doubles per row of lradi_result_history() */
+#define LRADI_HIST_COLS 16
+/* columns: 0 k, 1 ||w_{k-1}t_{k-1}^T||/||fg^T|| (before the step),
+ * 2 delta^A_k, 3 delta^B_k, 4 achieved ||r^A_k||, 5 achieved ||r^B_k||,
+ * 6 inner block steps A, 7 inner block steps B, 8 u_k, 9 v_k,
+ * 10 ||w_{k-1}||, 11 ||t_{k-1}||, 12 ||z_k||, 13 ||y_k||, 14 gamma_k,
+ * 15 ||w_k t_k^T||/||fg^T|| (after the step)                               */
+
+typedef struct lradi_ctx lradi_ctx;
+typedef struct lradi_result lradi_result;
+
+/* Compressed sparse row matrix, int32 indices, FP64 values, columns may be in
+ * any order within a row.  Borrowed: the caller keeps ownership and keeps the
+ * arrays alive for the duration of the call.  on_device = 1: the three
+ * pointers are device pointers; 0: host pointers (copied in by the call). */
+typedef struct {
+  int32_t nrows, ncols;
+  int64_t nnz;
+  const int32_t* rowptr; /* nrows + 1 */
+  const int32_t* colind; /* nnz */
+  const double* val;     /* nnz */
+  int32_t on_device;
+} lradi_csr;
+
+/* Options of one solve.  lradi_default_opts() fills the settings of the
+ * paper's experiments (Sec. 4): tol 1e-8, delta_min = tol/20, delta_max =
+ * 0.1, kmax = 50, xi = 1, back-looking mid selection. */
+typedef struct {
+  double tol;          /* outer tau: stop when ||w t^T|| < tol*||f g^T||      */
+  double eps;          /* absolute gap budget epsilon of Thm 3; <= 0 selects
+                          tol*||f g^T||                                       */
+  double delta_min;    /* eq. (bound_tols), absolute                          */
+  double delta_max;    /* eq. (bound_tols), absolute                          */
+  double xi;           /* safeguard constant of eqs. (ADI_relax*_prak)        */
+  double delta_fixed;  /* LRADI_SEL_FIXED tolerance, absolute                 */
+  double rho;          /* LRADI_SEL_RELATIVE factor                           */
+  double fp32_floor;   /* FP32 inner: a restart cycle stops once its residual
+                          estimate is below fp32_floor times its start        */
+  int32_t kmax;        /* outer step budget (also enters the thresholds)      */
+  int32_t selection;   /* LRADI_SEL_*                                         */
+  int32_t backlook;    /* 1: eq. (ADI_relax2_prak), 0: eq. (ADI_relax1_prak)  */
+  int32_t paper_abs;   /* 1: |.| of eq. (ADI_relax2_prak) as printed;
+                          0: a spent budget gives delta_min                  */
+  int32_t precision;   /* LRADI_FP64 or LRADI_FP32_INNER                      */
+  int32_t restart;     /* block GMRES restart length m (blocks), 1..64        */
+  int32_t max_inner;   /* cap on block Arnoldi steps per inner solve          */
+  int32_t rescale;     /* 1: scale f, g to equal spectral norm (Sec. 4)       */
+  int32_t b_is_transposed; /* 1: the B argument already holds B^T             */
+  int32_t lookahead;   /* host scheduling depth (0 = synchronous), >= 0       */
+  int32_t use_graph;   /* 1: replay the inner-iteration launch sequence from a
+                          captured hipGraph                                    */
+  int32_t reserved[5];
+} lradi_opts;
+
+/* Per inner solve statistics (lradi_shifted_solve). */
+typedef struct {
+  int32_t steps;       /* block Arnoldi steps                                 */
+  int32_t cycles;      /* restart cycles                                      */
+  int32_t status;      /* 0 converged, 1 step cap hit, 2 breakdown, 3 NaN     */
+  int32_t pad;
+  double rnorm;        /* achieved ||W - (A + shift I) Z||_2 (FP64)           */
+} lradi_inner_stats;
+
+void lradi_default_opts(lradi_opts* opts);
+const char* lradi_strerror(int status);
+const char* lradi_last_error(void);
+
+/* Context: binds a device and a stream (NULL = a stream the context creates
+ * and owns) and pools workspace.  device = HIP ordinal. */
+int lradi_create(lradi_ctx** ctx, int device, void* hip_stream);
+int lradi_destroy(lradi_ctx* ctx);
+
+/* Size of the 2-D (dim = 2) or 3-D (dim = 3) upwind convection-diffusion
+ * matrix on N^dim interior points (Sec. 4, eq. (ex:convdiff)). */
+int lradi_convdiff_size(int dim, int N, int64_t* n, int64_t* nnz);
+
+/* Fill caller-allocated host arrays rowptr (n+1), colind (nnz), val (nnz)
+ * with A = -L_h of eq. (ex:convdiff): h = 1/(N+1), homogeneous Dirichlet,
+ * lexicographic order with the first axis fastest, upwind first-order term,
+ * ascending columns.  Values follow a fixed FP64 recipe (products and sums
+ * rounded separately) so they are reproducible bit for bit.  omega: dim
+ * doubles (host).  B^T of such a matrix is the matrix with -omega. */
+int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* rowptr,
+                       int32_t* colind, double* val);
+
+/* Y = (A + shift I) X for one n x r block (the shifted product used by every
+ * inner Krylov step).  A: csr (host or device); X, Y: device, n x r
+ * row-major, double when precision = LRADI_FP64, float when
+ * LRADI_FP32_INNER (then A's values are used rounded to FP32).  1 <= r <= 8.
+ * Returns after the stream finished. */
+int lradi_spmm(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X,
+               void* Y, int r, int precision);
+
+/* Solve nsys independent shifted block systems (A_s + shift_s I) Z_s = W_s
+ * with block GMRES(m) plus FP64 iterative refinement until
+ * ||W_s - (A_s + shift_s I) Z_s||_2 <= delta_s (absolute, spectral norm) --
+ * the inner solves of Algorithm 1, eq. (gfadi_incsolves).  All systems run
+ * in the same kernel launches.  A[s]: csr (host or device); W[s]: device,
+ * n_s x r[s] doubles; Z[s]: device, n_s x r[s] doubles, overwritten (zero
+ * initial guess).  shift, delta, r: host arrays of nsys.  opts: precision,
+ * restart, max_inner, fp32_floor are used (NULL = defaults).  stats: host
+ * array of nsys, may be NULL.  Warning LRADI_WINNER if a step cap was hit. */
+int lradi_shifted_solve(lradi_ctx* ctx, int nsys, const lradi_csr* const* A,
+                        const double* shift, const double* const* W, double* const* Z,
+                        const int* r, const double* delta, const lradi_opts* opts,
+                        lradi_inner_stats* stats);
+
+/* Algorithm 1 (inexact LR-ADI) on A X + X B = -f g^T.  A: n x n csr, B: m x m
+ * csr (B itself, or B^T when opts->b_is_transposed).  f, g: device, n x r and
+ * m x r row-major doubles (not modified).  shiftsA/shiftsB: host, nshifts
+ * doubles.  opts may be NULL (defaults).  *out receives a library-owned
+ * result (free with lradi_result_free) also on LRADI_WNOCONV/LRADI_WINNER. */
+int lradi_solve(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, const double* f,
+                const double* g, int r, const double* shiftsA, const double* shiftsB,
+                int nshifts, const lradi_opts* opts, lradi_result** out);
+
+/* Scalars of a result: steps k, status, ||w_k t_k^T||/||f g^T||, ||f g^T||
+ * (after the optional rescaling, which leaves f g^T unchanged). */
+int lradi_result_info(const lradi_result* res, int* k, int* status, double* rel_res_comp,
+                      double* norm_fg);
+/* Device pointers (owned by the result) to Z (k x n x r), D (k gammas) and
+ * Y (k x m x r); n, m, r may be NULL. */
+int lradi_result_factors(const lradi_result* res, const double** Z, const double** D,
+                         const double** Y, int* n, int* m, int* r);
+/* Copy the factors to caller-owned host arrays of k*n*r, k and k*m*r
+ * doubles (any may be NULL). */
+int lradi_result_copy(const lradi_result* res, double* Z, double* D, double* Y);
+/* Copy min(k, max_rows) history rows of LRADI_HIST_COLS doubles into rows
+ * (host); returns the number of rows through *nrows. */
+int lradi_result_history(const lradi_result* res, double* rows, int max_rows, int* nrows);
+/* Wall time of the solve in seconds (host clock around the device work). */
+int lradi_result_time(const lradi_result* res, double* seconds);
+void lradi_result_free(lradi_result* res);
+
+/* True scaled residual ||A Z D Y^T + Z D Y^T B + f g^T||_2 / ||f g^T||_2 of
+ * a factored solution (Sec. 4 estimates it after termination with eigs on
+ * R^T R; here Golub-Kahan-Lanczos bidiagonalisation with full
+ * reorthogonalisation of R applied implicitly, FP64).  A, B as in
+ * lradi_solve (B^T when b_is_transposed); f, g, Z (k x n x r), Y (k x m x r):
+ * device; D: host, k gammas. */
+int lradi_residual(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B,
+                   int b_is_transposed, const double* f, const double* g, int r,
+                   const double* Z, const double* D, const double* Y, int k,
+                   double* rel_true_res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRADI_H */

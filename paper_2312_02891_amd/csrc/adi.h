@@ -1,0 +1,41 @@
+// Outer LR-ADI state shared by the ADI kernels and the host driver.
+#pragma once
+
+#include "internal.h"
+
+namespace lradi {
+
+// Read-only description of one Sylvester problem in a batch (problem p owns
+// inner systems 2p: A side and 2p+1: B side).
+struct AdiDesc {
+  int n, m, r, kmax, nshifts;
+  int selection, backlook, paper_abs, rescale;
+  int pad0;
+  double tol, eps_in, delta_min, delta_max, xi, delta_fixed, rho;
+  const double* shiftsA;  // device, nshifts
+  const double* shiftsB;  // device, nshifts
+  const double* f;        // device, n x r
+  const double* g;        // device, m x r
+  double* W;              // residual factor w_k, n x r
+  double* T;              // residual factor t_k, m x r
+  double* Zf;             // factor blocks z_1..z_kmax, kmax x n x r
+  double* Yf;             // factor blocks y_1..y_kmax, kmax x m x r
+  double* gam;            // gamma_1..gamma_kmax
+  double* hist;           // kmax x LRADI_HIST_COLS
+};
+
+// Mutable outer state of one problem.
+struct AdiCtl {
+  int k;        // completed steps
+  int done;     // 1 once converged, out of steps or failed
+  int status;   // LRADI_OK / LRADI_WNOCONV / LRADI_ENAN
+  int winner;   // some inner solve hit its step cap
+  double norm_fg, eps, nw, nt, u, v, res, sf, sg, dA, dB;
+};
+
+int adi_launch_setup(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob);
+int adi_launch_prepare(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob);
+int adi_launch_finish(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob,
+                      int* host_done);
+
+}  // namespace lradi

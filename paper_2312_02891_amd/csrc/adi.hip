@@ -1,0 +1,361 @@
+// Outer LR-ADI kernels: setup (rescaling of f, g and ||f g^T||), the
+// tolerance controller before each step, the residual-factor update and
+// append after the inner solves, and the norm / stop test (Algorithm 1,
+// eqs. (lradi_basic), (adi_resexact), Sec. 3.3).
+//
+// A batch of problems maps problem p to inner systems 2p (A side: W, Z) and
+// 2p+1 (B side: T, Y).  Row kernels reuse the inner solver's row table.
+#include "adi.h"
+#include "controller.h"
+#include "small.h"
+
+namespace lradi {
+namespace {
+
+#define LRADI_DISPATCH_R2(rv, ...)         \
+  switch (rv) {                            \
+    case 1: { constexpr int RR = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int RR = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int RR = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int RR = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int RR = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int RR = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int RR = 7; __VA_ARGS__; } break; \
+    case 8: { constexpr int RR = 8; __VA_ARGS__; } break; \
+    default: break;                        \
+  }
+
+template <int NV>
+__device__ inline void bsum(double (&v)[NV], double* lds, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) lds[wave * NV + k] = x;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV; k += kTPB)
+    out[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
+  __syncthreads();
+}
+
+// fixed-order sum of partS rows at column offset off (P <= 64 values)
+__device__ inline void reduce_rows(const double* partS, int nwg, int off, int P, double* red_lds,
+                                   double* out) {
+  const int t = threadIdx.x;
+  const int groups = kTPB / P;
+  const int p = t % P, g = t / P;
+  double acc = 0.0;
+  if (g < groups)
+    for (int w = g; w < nwg; w += groups) acc += partS[(size_t)w * kPS + off + p];
+  red_lds[t] = acc;
+  __syncthreads();
+  if (t < P) {
+    double s = 0.0;
+    for (int q = 0; q < groups; ++q) s += red_lds[q * P + t];
+    out[t] = s;
+  }
+  __syncthreads();
+}
+
+struct RowC {
+  int s, w, row0, row1;
+};
+__device__ inline RowC rowc(const SysDesc* d, const int2* rowmap) {
+  const int2 sc = rowmap[blockIdx.x];
+  const SysDesc& D = d[sc.x];
+  RowC c;
+  c.s = sc.x;
+  c.w = sc.y;
+  c.row0 = sc.y * D.rows_per_wg;
+  c.row1 = min(D.n, c.row0 + D.rows_per_wg);
+  return c;
+}
+
+// Gram X^T X of rows of X (n x R) into partS[w][off..]
+template <int R>
+__device__ inline void gram_self(const double* X, const RowC& c, double* lds, double* dst) {
+  double g2[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    double x[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) x[q] = X[(size_t)i * R + q];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = 0; q < R; ++q) g2[a * R + q] += x[a] * x[q];
+  }
+  bsum<R * R>(g2, lds, dst);
+}
+
+// setup 1: partial f^T f (A side) / g^T g (B side)
+__global__ __launch_bounds__(kTPB) void k_adi_setup_gram(const SysDesc* __restrict__ d,
+                                                         const int2* __restrict__ rowmap,
+                                                         const AdiDesc* __restrict__ ad) {
+  __shared__ double lds[4 * 64];
+  const RowC c = rowc(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const AdiDesc& P = ad[c.s >> 1];
+  const double* X = (c.s & 1) ? P.g : P.f;
+  LRADI_DISPATCH_R2(D.r, gram_self<RR>(X, c, lds, D.partS + (size_t)c.w * kPS));
+}
+
+// setup 2: norms, rescaling factors, ||f g^T||, initial state
+__global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ d,
+                                                    const AdiDesc* __restrict__ ad,
+                                                    AdiCtl* __restrict__ ac) {
+  __shared__ double red_lds[kTPB];
+  __shared__ double Gf[64], Gg[64];
+  const int p = blockIdx.x;
+  const AdiDesc& P = ad[p];
+  const SysDesc& DA = d[2 * p];
+  const SysDesc& DB = d[2 * p + 1];
+  const int R = P.r;
+  reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, Gf);
+  reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, Gg);
+  if (threadIdx.x == 0) {
+    AdiCtl& C = ac[p];
+    const double nf = sqrt(fmax(lambda_max_sym(Gf, R), 0.0));
+    const double ng = sqrt(fmax(lambda_max_sym(Gg, R), 0.0));
+    const double nfg = sqrt(fmax(lambda_max_prod(Gf, Gg, R), 0.0));
+    double sf = 1.0, sg = 1.0;
+    if (P.rescale && nf > 0.0 && ng > 0.0) {
+      sf = sqrt(ng / nf);
+      sg = 1.0 / sf;
+    }
+    C.sf = sf;
+    C.sg = sg;
+    C.norm_fg = nfg;
+    C.nw = nf * sf;
+    C.nt = ng * sg;
+    C.res = nfg;
+    C.u = 0.0;
+    C.v = 0.0;
+    C.k = 0;
+    C.winner = 0;
+    C.status = LRADI_OK;
+    C.eps = (P.eps_in > 0.0) ? P.eps_in : P.tol * nfg;
+    C.done = (nfg == 0.0 || !(nfg == nfg)) ? 1 : 0;
+    if (!(nfg == nfg) || nfg - nfg != 0.0) C.status = LRADI_ENAN;
+    C.dA = 0.0;
+    C.dB = 0.0;
+  }
+}
+
+// setup 3: W = sf f, T = sg g
+__global__ __launch_bounds__(kTPB) void k_adi_init_wt(const SysDesc* __restrict__ d,
+                                                      const int2* __restrict__ rowmap,
+                                                      const AdiDesc* __restrict__ ad,
+                                                      const AdiCtl* __restrict__ ac) {
+  const RowC c = rowc(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const int p = c.s >> 1;
+  const AdiDesc& P = ad[p];
+  const bool b = (c.s & 1) != 0;
+  const double* X = b ? P.g : P.f;
+  double* Y = b ? P.T : P.W;
+  const double sc = b ? ac[p].sg : ac[p].sf;
+  const size_t e1 = (size_t)c.row1 * D.r;
+  for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) Y[e] = sc * X[e];
+}
+
+// before step k+1: tolerances, shifts, fresh inner control blocks
+__global__ void k_adi_prepare(const AdiDesc* __restrict__ ad, AdiCtl* __restrict__ ac,
+                              SysCtl* __restrict__ ctl, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  const AdiDesc& P = ad[p];
+  AdiCtl& C = ac[p];
+  SysCtl& A = ctl[2 * p];
+  SysCtl& B = ctl[2 * p + 1];
+  if (C.done) {
+    A.phase = PH_FINISHED;
+    B.phase = PH_FINISHED;
+    return;
+  }
+  CtlParams cp;
+  cp.eps = C.eps;
+  cp.delta_min = P.delta_min;
+  cp.delta_max = P.delta_max;
+  cp.xi = P.xi;
+  cp.delta_fixed = P.delta_fixed;
+  cp.rho = P.rho;
+  cp.kmax = P.kmax;
+  cp.selection = P.selection;
+  cp.backlook = P.backlook;
+  cp.paper_abs = P.paper_abs;
+  double dA, dB;
+  ctl_tolerances(cp, C.k + 1, C.nw, C.nt, C.u, C.v, &dA, &dB);
+  C.dA = dA;
+  C.dB = dB;
+  const int js = C.k % P.nshifts;
+  SysCtl* sides[2] = {&A, &B};
+  for (int side = 0; side < 2; ++side) {
+    SysCtl& S = *sides[side];
+    S.Z = side ? P.Yf + (size_t)C.k * P.m * P.r : P.Zf + (size_t)C.k * P.n * P.r;
+    S.shift = side ? P.shiftsB[js] : P.shiftsA[js];
+    S.delta = side ? dB : dA;
+    S.phase = PH_CYCLE_END;
+    S.first = 1;
+    S.j = 0;
+    S.ncols = 0;
+    S.steps = 0;
+    S.cycles = 0;
+    S.status = IS_OK;
+    S.breakdowns = 0;
+    S.est = 0.0;
+    S.rnorm = 0.0;
+    S.r0 = 0.0;
+  }
+}
+
+// after the inner solves: W += gamma Z (A side) or T += gamma Y (B side),
+// partial Grams of the new factor (offset 0) and of the new block (offset 64)
+template <int R>
+__device__ inline void adi_update_rows(double* Wt, const double* Zk, double gamma, const RowC& c,
+                                       double* lds, double* dst) {
+  double g2[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    double w[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      w[q] = Wt[(size_t)i * R + q] + gamma * Zk[(size_t)i * R + q];
+      Wt[(size_t)i * R + q] = w[q];
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = 0; q < R; ++q) g2[a * R + q] += w[a] * w[q];
+  }
+  bsum<R * R>(g2, lds, dst);
+  gram_self<R>(Zk, c, lds, dst + 64);
+}
+
+__global__ __launch_bounds__(kTPB) void k_adi_update(const SysDesc* __restrict__ d,
+                                                     const int2* __restrict__ rowmap,
+                                                     const AdiDesc* __restrict__ ad,
+                                                     const AdiCtl* __restrict__ ac,
+                                                     const SysCtl* __restrict__ ctl) {
+  __shared__ double lds[4 * 64];
+  const RowC c = rowc(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const int p = c.s >> 1;
+  if (ac[p].done) return;
+  const AdiDesc& P = ad[p];
+  const int js = ac[p].k % P.nshifts;
+  const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
+  double* Wt = (c.s & 1) ? P.T : P.W;
+  const double* Zk = ctl[c.s].Z;
+  LRADI_DISPATCH_R2(D.r, adi_update_rows<RR>(Wt, Zk, gamma, c, lds, D.partS + (size_t)c.w * kPS));
+}
+
+// norms, gap estimates u, v (eq. (upd_resgap)), history row, stop test
+__global__ __launch_bounds__(kTPB) void k_adi_finish(const SysDesc* __restrict__ d,
+                                                     const AdiDesc* __restrict__ ad,
+                                                     AdiCtl* __restrict__ ac,
+                                                     const SysCtl* __restrict__ ctl, int* host_done) {
+  __shared__ double red_lds[kTPB];
+  __shared__ double GW[64], GZ[64], GT[64], GY[64];
+  const int p = blockIdx.x;
+  const AdiDesc& P = ad[p];
+  AdiCtl& C = ac[p];
+  if (C.done) {
+    if (threadIdx.x == 0 && host_done)
+      __hip_atomic_store(host_done + p, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
+  const SysDesc& DA = d[2 * p];
+  const SysDesc& DB = d[2 * p + 1];
+  const int R = P.r;
+  reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, GW);
+  reduce_rows(DA.partS, DA.nwg, 64, R * R, red_lds, GZ);
+  reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, GT);
+  reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
+  if (threadIdx.x == 0) {
+    const SysCtl& A = ctl[2 * p];
+    const SysCtl& B = ctl[2 * p + 1];
+    const int k = C.k;
+    const int js = k % P.nshifts;
+    const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
+    const double nw = sqrt(fmax(lambda_max_sym(GW, R), 0.0));
+    const double nt = sqrt(fmax(lambda_max_sym(GT, R), 0.0));
+    const double nz = sqrt(fmax(lambda_max_sym(GZ, R), 0.0));
+    const double ny = sqrt(fmax(lambda_max_sym(GY, R), 0.0));
+    const double res = sqrt(fmax(lambda_max_prod(GW, GT, R), 0.0));
+    const double rA = A.rnorm, rB = B.rnorm;
+    double u = C.u, v = C.v;
+    ctl_update_gap(&u, &v, gamma, nz, ny, rA, rB);
+    double* h = P.hist + (size_t)k * kHistCols;
+    const double nfg = C.norm_fg;
+    h[0] = k + 1;
+    h[1] = C.res / nfg;
+    h[2] = C.dA;
+    h[3] = C.dB;
+    h[4] = rA;
+    h[5] = rB;
+    h[6] = A.steps;
+    h[7] = B.steps;
+    h[8] = u;
+    h[9] = v;
+    h[10] = C.nw;
+    h[11] = C.nt;
+    h[12] = nz;
+    h[13] = ny;
+    h[14] = gamma;
+    h[15] = res / nfg;
+    P.gam[k] = gamma;
+    C.u = u;
+    C.v = v;
+    C.nw = nw;
+    C.nt = nt;
+    C.res = res;
+    C.k = k + 1;
+    if (A.status == IS_CAP || B.status == IS_CAP) C.winner = 1;
+    bool bad = !(res == res) || res - res != 0.0 || A.status == IS_NAN || B.status == IS_NAN;
+    if (bad) {
+      C.status = LRADI_ENAN;
+      C.done = 1;
+    } else if (res < P.tol * nfg) {
+      C.done = 1;
+    } else if (C.k >= P.kmax) {
+      C.status = LRADI_WNOCONV;
+      C.done = 1;
+    }
+    if (host_done)
+      __hip_atomic_store(host_done + p, C.done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+}  // namespace
+
+int adi_launch_setup(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob) {
+  hipLaunchKernelGGL(k_adi_setup_gram, dim3(b.rowgrid), dim3(kTPB), 0, st, b.d, b.rowmap, ad);
+  hipLaunchKernelGGL(k_adi_setup, dim3(nprob), dim3(kTPB), 0, st, b.d, ad, ac);
+  hipLaunchKernelGGL(k_adi_init_wt, dim3(b.rowgrid), dim3(kTPB), 0, st, b.d, b.rowmap, ad, ac);
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+int adi_launch_prepare(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob) {
+  const int tpb = 64;
+  hipLaunchKernelGGL(k_adi_prepare, dim3((nprob + tpb - 1) / tpb), dim3(tpb), 0, st, ad, ac, b.ctl,
+                     nprob);
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+int adi_launch_finish(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob,
+                      int* host_done) {
+  hipLaunchKernelGGL(k_adi_update, dim3(b.rowgrid), dim3(kTPB), 0, st, b.d, b.rowmap, ad, ac, b.ctl);
+  hipLaunchKernelGGL(k_adi_finish, dim3(nprob), dim3(kTPB), 0, st, b.d, ad, ac, b.ctl, host_done);
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+}  // namespace lradi

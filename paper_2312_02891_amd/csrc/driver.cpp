@@ -1,0 +1,721 @@
+// Host side of the lradi library: context, device buffers, the batched
+// inner-solve scheduler and the outer LR-ADI loop (Algorithm 1), and the
+// C ABI entry points declared in include/lradi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "adi.h"
+#include "internal.h"
+
+namespace lradi {
+
+void csr_transpose(int n, const int32_t* rp, const int32_t* ci, const double* v,
+                   std::vector<int32_t>& trp, std::vector<int32_t>& tci, std::vector<double>& tv);
+
+// ---------------------------------------------------------------------------
+// errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+#define LRADI_TRY(expr)            \
+  do {                             \
+    int st_ = (expr);              \
+    if (st_ < 0) return st_;       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// buffers
+int DevBuf::alloc(size_t nbytes) {
+  release();
+  if (nbytes == 0) return LRADI_OK;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    set_error("hipMalloc(%zu bytes) failed: %s", nbytes, hipGetErrorString(e));
+    return LRADI_ENOMEM;
+  }
+  bytes = nbytes;
+  return LRADI_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+namespace {
+
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+int DevCSR::upload(const lradi_csr* A, hipStream_t st, bool need32) {
+  if (!A || A->nrows <= 0 || A->nrows != A->ncols || A->nnz < 0 || !A->rowptr ||
+      (A->nnz > 0 && (!A->colind || !A->val))) {
+    set_error("invalid csr argument (square, nrows > 0, non-null arrays required)");
+    return LRADI_EINVAL;
+  }
+  if (A->nnz > INT32_MAX) {
+    set_error("csr nnz exceeds int32 indexing");
+    return LRADI_EINVAL;
+  }
+  n = A->nrows;
+  nnz = A->nnz;
+  const hipMemcpyKind kind = A->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (!A->on_device) {
+    // host data: validate structure before it reaches a kernel
+    const int32_t* rp = A->rowptr;
+    if (rp[0] != 0 || rp[n] != nnz) {
+      set_error("csr rowptr must start at 0 and end at nnz");
+      return LRADI_EINVAL;
+    }
+    for (int i = 0; i < n; ++i)
+      if (rp[i + 1] < rp[i]) {
+        set_error("csr rowptr not monotone at row %d", i);
+        return LRADI_EINVAL;
+      }
+    for (int64_t k = 0; k < nnz; ++k)
+      if (A->colind[k] < 0 || A->colind[k] >= n) {
+        set_error("csr column index out of range at %lld", (long long)k);
+        return LRADI_EINVAL;
+      }
+  }
+  LRADI_TRY(rowptr.alloc(sizeof(int32_t) * (n + 1)));
+  LRADI_TRY(colind.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  LRADI_TRY(val64.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)));
+  LRADI_HIP(hipMemcpyAsync(rowptr.p, A->rowptr, sizeof(int32_t) * (n + 1), kind, st));
+  if (nnz > 0) {
+    LRADI_HIP(hipMemcpyAsync(colind.p, A->colind, sizeof(int32_t) * nnz, kind, st));
+    LRADI_HIP(hipMemcpyAsync(val64.p, A->val, sizeof(double) * nnz, kind, st));
+  }
+  if (A->on_device) {
+    // device data: check the structure on a host copy of the index arrays
+    std::vector<int32_t> rp(n + 1), ci(nnz);
+    LRADI_HIP(hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    if (nnz > 0)
+      LRADI_HIP(hipMemcpyAsync(ci.data(), A->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+    LRADI_HIP(hipStreamSynchronize(st));
+    if (rp[0] != 0 || rp[n] != nnz) {
+      set_error("csr rowptr must start at 0 and end at nnz");
+      return LRADI_EINVAL;
+    }
+    for (int i = 0; i < n; ++i)
+      if (rp[i + 1] < rp[i]) {
+        set_error("csr rowptr not monotone at row %d", i);
+        return LRADI_EINVAL;
+      }
+    for (int64_t k = 0; k < nnz; ++k)
+      if (ci[k] < 0 || ci[k] >= n) {
+        set_error("csr column index out of range at %lld", (long long)k);
+        return LRADI_EINVAL;
+      }
+  }
+  if (need32) {
+    LRADI_TRY(val32.alloc(sizeof(float) * std::max<int64_t>(nnz, 1)));
+    if (nnz > 0) {
+      const int tpb = 256;
+      hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nnz + tpb - 1) / tpb)), dim3(tpb), 0, st,
+                         val64.as<double>(), val32.as<float>(), nnz);
+      LRADI_HIP(hipGetLastError());
+    }
+  }
+  return LRADI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pinned host ring for scheduler summaries
+struct HostRing {
+  int* h = nullptr;
+  int* d = nullptr;
+  int n = 0;
+  ~HostRing() {
+    if (h) (void)hipHostFree(h);
+  }
+  int init(int count) {
+    if (h && n >= count) return LRADI_OK;
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+    LRADI_HIP(hipHostMalloc((void**)&h, sizeof(int) * count, hipHostMallocMapped | hipHostMallocCoherent));
+    LRADI_HIP(hipHostGetDevicePointer((void**)&d, h, 0));
+    n = count;
+    for (int i = 0; i < count; ++i) h[i] = -1;
+    return LRADI_OK;
+  }
+};
+
+}  // namespace lradi
+
+using namespace lradi;
+
+struct lradi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevBuf arena;  // inner-solver workspace, grown on demand
+  HostRing ring;
+  HostRing done;
+  std::vector<hipEvent_t> events;
+};
+
+struct lradi_result {
+  int n = 0, m = 0, r = 0, k = 0, kmax = 0;
+  int status = LRADI_OK;
+  double rel_res = 0.0, norm_fg = 0.0, seconds = 0.0;
+  DevBuf Zf, Yf;
+  std::vector<double> gam, hist;
+};
+
+namespace lradi {
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// One inner system to be placed in a batch.
+struct SysSpec {
+  const DevCSR* A;
+  const double* W;
+  double* Z;      // may be null (set on the device by the ADI prepare kernel)
+  double shift;
+  double delta;
+  int r, m, precision, max_inner;
+  double floor_rel;
+};
+
+int choose_rows_per_wg(int n) {
+  int rpw = (n + 511) / 512;
+  rpw = ((rpw + 255) / 256) * 256;
+  return std::max(256, std::min(rpw, 8192));
+}
+
+// Lay out every system's workspace in the context arena and fill the
+// descriptor / control / row-map arrays.
+struct InnerBatch {
+  std::vector<SysDesc> hd;
+  std::vector<SysCtl> hc;
+  std::vector<int2> hmap;
+  DevBuf dd, dc, dmap;
+  Batch b{};
+};
+
+int build_batch(lradi_ctx* ctx, const std::vector<SysSpec>& sys, InnerBatch& ib) {
+  const int nsys = (int)sys.size();
+  if (nsys == 0) {
+    set_error("empty batch");
+    return LRADI_EINVAL;
+  }
+  const int prec = sys[0].precision;
+  ib.hd.assign(nsys, SysDesc{});
+  ib.hc.assign(nsys, SysCtl{});
+  ib.hmap.clear();
+  size_t total = 0;
+  std::vector<size_t> off(nsys);
+  int maxP = 1;
+  for (int s = 0; s < nsys; ++s) {
+    const SysSpec& S = sys[s];
+    if (S.precision != prec) {
+      set_error("all systems of a batch must use one precision");
+      return LRADI_EINVAL;
+    }
+    if (S.r < 1 || S.r > kMaxR || S.m < 1 || S.m > kMaxM) {
+      set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM);
+      return LRADI_EINVAL;
+    }
+    const size_t n = S.A->n, r = S.r, m = S.m;
+    const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
+    const int rpw = choose_rows_per_wg((int)n);
+    const int nwg = (int)((n + rpw - 1) / rpw);
+    const size_t pstride = (m + 1) * r * r;
+    maxP = std::max<int>(maxP, (int)pstride);
+    size_t sz = 0;
+    sz += align256((m + 1) * n * r * tsz);       // V
+    sz += align256(n * r * tsz);                 // U
+    sz += align256(n * r * 8);                   // R
+    sz += align256((size_t)nwg * pstride * 8);   // part
+    sz += align256((size_t)nwg * kPS * 8);       // partS
+    sz += align256(pstride * 8) * 2;             // red, hacc
+    sz += align256(m * r * m * r * 8);           // Rt
+    sz += align256(m * 4 * r * r * 8);           // Qs
+    sz += align256((m + 1) * r * r * 8);         // Gv
+    sz += align256(m * r * r * 8);               // yv
+    sz += align256(512 * 8);                     // sm
+    off[s] = total;
+    total += sz;
+    SysDesc& D = ib.hd[s];
+    D.n = (int)n;
+    D.r = (int)r;
+    D.m = (int)m;
+    D.nwg = nwg;
+    D.rows_per_wg = rpw;
+    D.wg0 = (int)ib.hmap.size();
+    D.precision = prec;
+    D.max_inner = S.max_inner;
+    D.rowptr = S.A->rowptr.as<int>();
+    D.colind = S.A->colind.as<int>();
+    D.valT = (prec == LRADI_FP64) ? (const void*)S.A->val64.p : (const void*)S.A->val32.p;
+    D.val64 = S.A->val64.as<double>();
+    D.floor_rel = S.floor_rel;
+    D.W = S.W;
+    D.pstride = (int)pstride;
+    for (int w = 0; w < nwg; ++w) ib.hmap.push_back(make_int2(s, w));
+    SysCtl& C = ib.hc[s];
+    C.Z = S.Z;
+    C.shift = S.shift;
+    // without a solution buffer the system waits for the outer driver to arm it
+    C.phase = S.Z ? PH_CYCLE_END : PH_FINISHED;
+    C.first = 1;
+    C.delta = S.delta;
+  }
+  if (ctx->arena.bytes < total) {
+    ctx->arena.release();
+    LRADI_TRY(ctx->arena.alloc(total));
+  }
+  char* base = ctx->arena.as<char>();
+  for (int s = 0; s < nsys; ++s) {
+    SysDesc& D = ib.hd[s];
+    const size_t n = D.n, r = D.r, m = D.m;
+    const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
+    char* p = base + off[s];
+    auto take = [&](size_t bytes) {
+      char* q = p;
+      p += align256(bytes);
+      return q;
+    };
+    D.V = take((m + 1) * n * r * tsz);
+    D.U = take(n * r * tsz);
+    D.R = reinterpret_cast<double*>(take(n * r * 8));
+    D.part = reinterpret_cast<double*>(take((size_t)D.nwg * D.pstride * 8));
+    D.partS = reinterpret_cast<double*>(take((size_t)D.nwg * kPS * 8));
+    D.red = reinterpret_cast<double*>(take((size_t)D.pstride * 8));
+    D.hacc = reinterpret_cast<double*>(take((size_t)D.pstride * 8));
+    D.Rt = reinterpret_cast<double*>(take(m * r * m * r * 8));
+    D.Qs = reinterpret_cast<double*>(take(m * 4 * r * r * 8));
+    D.Gv = reinterpret_cast<double*>(take((m + 1) * r * r * 8));
+    D.yv = reinterpret_cast<double*>(take(m * r * r * 8));
+    D.sm = reinterpret_cast<double*>(take(512 * 8));
+  }
+  LRADI_TRY(ib.dd.alloc(sizeof(SysDesc) * nsys));
+  LRADI_TRY(ib.dc.alloc(sizeof(SysCtl) * nsys));
+  LRADI_TRY(ib.dmap.alloc(sizeof(int2) * ib.hmap.size()));
+  hipStream_t st = ctx->stream;
+  LRADI_HIP(hipMemcpyAsync(ib.dd.p, ib.hd.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(ib.dc.p, ib.hc.data(), sizeof(SysCtl) * nsys, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(ib.dmap.p, ib.hmap.data(), sizeof(int2) * ib.hmap.size(),
+                           hipMemcpyHostToDevice, st));
+  ib.b.d = ib.dd.as<SysDesc>();
+  ib.b.ctl = ib.dc.as<SysCtl>();
+  ib.b.rowmap = ib.dmap.as<int2>();
+  ib.b.nsys = nsys;
+  ib.b.rowgrid = (int)ib.hmap.size();
+  ib.b.maxP = maxP;
+  ib.b.precision = prec;
+  return LRADI_OK;
+}
+
+// Issue ticks until every system of the batch is finished.  The host reads
+// the unfinished count of tick t - L only after issuing tick t, so the device
+// always has work queued; the extra ticks are no-ops.
+int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner) {
+  const int L = std::max(0, std::min(lookahead, 8));
+  LRADI_TRY(ctx->ring.init(L + 1));
+  while ((int)ctx->events.size() < L + 1) {
+    hipEvent_t e;
+    LRADI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->events.push_back(e);
+  }
+  hipStream_t st = ctx->stream;
+  const long max_ticks = 3L * std::max(max_inner, 1) + 16;
+  for (long t = 0;; ++t) {
+    const int slot = (int)(t % (L + 1));
+    LRADI_TRY(launch_tick(st, b));
+    LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
+    LRADI_HIP(hipEventRecord(ctx->events[slot], st));
+    if (t >= L) {
+      const int rs = (int)((t - L) % (L + 1));
+      LRADI_HIP(hipEventSynchronize(ctx->events[rs]));
+      const int left = __atomic_load_n(ctx->ring.h + rs, __ATOMIC_ACQUIRE);
+      if (left == 0) break;
+    }
+    if (t > max_ticks) {
+      set_error("inner solver scheduler exceeded %ld ticks", max_ticks);
+      return LRADI_EHIP;
+    }
+  }
+  LRADI_HIP(hipStreamSynchronize(st));
+  return LRADI_OK;
+}
+
+int check_opts(const lradi_opts& o) {
+  if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error("tol must be in (0,1)"), LRADI_EINVAL;
+  if (o.kmax < 1 || o.kmax > 100000) return set_error("kmax must be in 1..100000"), LRADI_EINVAL;
+  if (o.restart < 1 || o.restart > kMaxM) return set_error("restart must be in 1..%d", kMaxM), LRADI_EINVAL;
+  if (o.max_inner < 1) return set_error("max_inner must be >= 1"), LRADI_EINVAL;
+  if (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER)
+    return set_error("unknown precision"), LRADI_EINVAL;
+  if (o.selection < LRADI_SEL_RELATIVE || o.selection > LRADI_SEL_TIGHT_B)
+    return set_error("unknown selection"), LRADI_EINVAL;
+  if (!(o.delta_min > 0.0) || !(o.delta_max >= o.delta_min))
+    return set_error("need 0 < delta_min <= delta_max"), LRADI_EINVAL;
+  if (!(o.xi > 0.0 && o.xi <= 1.0)) return set_error("xi must be in (0,1]"), LRADI_EINVAL;
+  if (o.lookahead < 0) return set_error("lookahead must be >= 0"), LRADI_EINVAL;
+  return LRADI_OK;
+}
+
+double floor_for(const lradi_opts& o) {
+  return o.precision == LRADI_FP64 ? 1e-14 : (o.fp32_floor > 0.0 ? o.fp32_floor : 3e-6);
+}
+
+}  // namespace
+}  // namespace lradi
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+void lradi_default_opts(lradi_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->eps = 0.0;
+  o->delta_min = 1e-8 / 20.0;
+  o->delta_max = 0.1;
+  o->xi = 1.0;
+  o->delta_fixed = 1e-8 / 20.0;
+  o->rho = 1e-12;
+  o->fp32_floor = 3e-6;
+  o->kmax = 50;
+  o->selection = LRADI_SEL_MID;
+  o->backlook = 1;
+  o->paper_abs = 0;
+  o->precision = LRADI_FP64;
+  o->restart = 30;
+  o->max_inner = 20000;
+  o->rescale = 1;
+  o->b_is_transposed = 0;
+  o->lookahead = 2;
+  o->use_graph = 0;
+}
+
+const char* lradi_strerror(int st) {
+  switch (st) {
+    case LRADI_OK: return "ok";
+    case LRADI_EINVAL: return "invalid argument";
+    case LRADI_ENOMEM: return "out of device memory";
+    case LRADI_EHIP: return "HIP runtime error";
+    case LRADI_ENAN: return "NaN or Inf in the iteration";
+    case LRADI_EBREAKDOWN: return "Krylov breakdown";
+    case LRADI_WNOCONV: return "outer iteration reached kmax";
+    case LRADI_WINNER: return "an inner solve reached its step cap";
+    default: return "unknown status";
+  }
+}
+
+const char* lradi_last_error(void) { return g_err; }
+
+int lradi_create(lradi_ctx** out, int device, void* stream) {
+  if (!out) return set_error("lradi_create: null output"), LRADI_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  LRADI_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return set_error("lradi_create: no device %d", device), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(device));
+  auto* c = new lradi_ctx();
+  c->device = device;
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      set_error("hipStreamCreate failed: %s", hipGetErrorString(e));
+      return LRADI_EHIP;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return LRADI_OK;
+}
+
+int lradi_destroy(lradi_ctx* c) {
+  if (!c) return LRADI_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto e : c->events) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return LRADI_OK;
+}
+
+int lradi_spmm(lradi_ctx* c, const lradi_csr* A, double shift, const void* X, void* Y, int r,
+               int precision) {
+  if (!c || !X || !Y) return set_error("lradi_spmm: null argument"), LRADI_EINVAL;
+  if (r < 1 || r > kMaxR) return set_error("lradi_spmm: r must be in 1..%d", kMaxR), LRADI_EINVAL;
+  if (precision != LRADI_FP64 && precision != LRADI_FP32_INNER)
+    return set_error("lradi_spmm: unknown precision"), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  DevCSR dA;
+  LRADI_TRY(dA.upload(A, c->stream, precision == LRADI_FP32_INNER));
+  const void* val = (precision == LRADI_FP64) ? dA.val64.p : dA.val32.p;
+  LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(),
+                              dA.colind.as<int>(), val, shift, X, Y));
+  LRADI_HIP(hipStreamSynchronize(c->stream));
+  return LRADI_OK;
+}
+
+int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const double* shift,
+                        const double* const* W, double* const* Z, const int* r, const double* delta,
+                        const lradi_opts* opts, lradi_inner_stats* stats) {
+  if (!c || nsys < 1 || !A || !shift || !W || !Z || !r || !delta)
+    return set_error("lradi_shifted_solve: null or empty argument"), LRADI_EINVAL;
+  lradi_opts o;
+  lradi_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.restart < 1 || o.restart > kMaxM || o.max_inner < 1 ||
+      (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER))
+    return set_error("lradi_shifted_solve: bad options"), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  std::vector<DevCSR> mats(nsys);
+  std::vector<SysSpec> specs(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    if (!W[s] || !Z[s] || !(delta[s] >= 0.0))
+      return set_error("lradi_shifted_solve: bad system %d", s), LRADI_EINVAL;
+    LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
+    specs[s] = SysSpec{&mats[s], W[s], Z[s], shift[s], delta[s], r[s], o.restart, o.precision,
+                       o.max_inner, floor_for(o)};
+  }
+  InnerBatch ib;
+  LRADI_TRY(build_batch(c, specs, ib));
+  LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner));
+  std::vector<SysCtl> hc(nsys);
+  LRADI_HIP(hipMemcpy(hc.data(), ib.b.ctl, sizeof(SysCtl) * nsys, hipMemcpyDeviceToHost));
+  int status = LRADI_OK;
+  for (int s = 0; s < nsys; ++s) {
+    if (stats) {
+      stats[s].steps = hc[s].steps;
+      stats[s].cycles = hc[s].cycles;
+      stats[s].status = hc[s].status;
+      stats[s].pad = hc[s].breakdowns;
+      stats[s].rnorm = hc[s].rnorm;
+    }
+    if (hc[s].status == IS_NAN) status = LRADI_ENAN;
+    else if (hc[s].status == IS_CAP && status == LRADI_OK) status = LRADI_WINNER;
+  }
+  return status;
+}
+
+int lradi_solve(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const double* f,
+                const double* g, int r, const double* shiftsA, const double* shiftsB, int nshifts,
+                const lradi_opts* opts, lradi_result** out) {
+  if (!c || !A || !B || !f || !g || !shiftsA || !shiftsB || !out)
+    return set_error("lradi_solve: null argument"), LRADI_EINVAL;
+  *out = nullptr;
+  if (r < 1 || r > kMaxR) return set_error("lradi_solve: r must be in 1..%d", kMaxR), LRADI_EINVAL;
+  if (nshifts < 1) return set_error("lradi_solve: need at least one shift"), LRADI_EINVAL;
+  lradi_opts o;
+  lradi_default_opts(&o);
+  if (opts) o = *opts;
+  LRADI_TRY(check_opts(o));
+  for (int i = 0; i < nshifts; ++i)
+    if (!std::isfinite(shiftsA[i]) || !std::isfinite(shiftsB[i]))
+      return set_error("lradi_solve: non-finite shift"), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+
+  const bool f32 = o.precision == LRADI_FP32_INNER;
+  DevCSR dA, dBt;
+  LRADI_TRY(dA.upload(A, st, f32));
+  if (o.b_is_transposed) {
+    LRADI_TRY(dBt.upload(B, st, f32));
+  } else {
+    // form B^T on the host once
+    if (!B->rowptr || B->nrows <= 0 || B->nrows != B->ncols)
+      return set_error("lradi_solve: invalid B"), LRADI_EINVAL;
+    const int mB = B->nrows;
+    std::vector<int32_t> rp(mB + 1), ci, trp, tci;
+    std::vector<double> v, tv;
+    ci.resize(B->nnz);
+    v.resize(B->nnz);
+    if (B->on_device) {
+      LRADI_HIP(hipMemcpy(rp.data(), B->rowptr, sizeof(int32_t) * (mB + 1), hipMemcpyDeviceToHost));
+      LRADI_HIP(hipMemcpy(ci.data(), B->colind, sizeof(int32_t) * B->nnz, hipMemcpyDeviceToHost));
+      LRADI_HIP(hipMemcpy(v.data(), B->val, sizeof(double) * B->nnz, hipMemcpyDeviceToHost));
+    } else {
+      std::copy(B->rowptr, B->rowptr + mB + 1, rp.begin());
+      std::copy(B->colind, B->colind + B->nnz, ci.begin());
+      std::copy(B->val, B->val + B->nnz, v.begin());
+    }
+    if (rp[0] != 0 || rp[mB] != B->nnz) return set_error("lradi_solve: invalid B rowptr"), LRADI_EINVAL;
+    for (int64_t k = 0; k < B->nnz; ++k)
+      if (ci[k] < 0 || ci[k] >= mB) return set_error("lradi_solve: B column out of range"), LRADI_EINVAL;
+    csr_transpose(mB, rp.data(), ci.data(), v.data(), trp, tci, tv);
+    lradi_csr Bt{mB, mB, B->nnz, trp.data(), tci.data(), tv.data(), 0};
+    LRADI_TRY(dBt.upload(&Bt, st, f32));
+    LRADI_HIP(hipStreamSynchronize(st));
+  }
+  const int n = dA.n, m = dBt.n;
+  auto res = std::make_unique<lradi_result>();
+  res->n = n;
+  res->m = m;
+  res->r = r;
+  res->kmax = o.kmax;
+  LRADI_TRY(res->Zf.alloc(sizeof(double) * (size_t)o.kmax * n * r));
+  LRADI_TRY(res->Yf.alloc(sizeof(double) * (size_t)o.kmax * m * r));
+  DevBuf W, T, shA, shB, gam, hist, dad, dac;
+  LRADI_TRY(W.alloc(sizeof(double) * (size_t)n * r));
+  LRADI_TRY(T.alloc(sizeof(double) * (size_t)m * r));
+  LRADI_TRY(shA.alloc(sizeof(double) * nshifts));
+  LRADI_TRY(shB.alloc(sizeof(double) * nshifts));
+  LRADI_TRY(gam.alloc(sizeof(double) * o.kmax));
+  LRADI_TRY(hist.alloc(sizeof(double) * (size_t)o.kmax * kHistCols));
+  LRADI_HIP(hipMemcpyAsync(shA.p, shiftsA, sizeof(double) * nshifts, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(shB.p, shiftsB, sizeof(double) * nshifts, hipMemcpyHostToDevice, st));
+
+  std::vector<SysSpec> specs(2);
+  const double fl = floor_for(o);
+  specs[0] = SysSpec{&dA, W.as<double>(), nullptr, 0.0, 0.0, r, o.restart, o.precision, o.max_inner, fl};
+  specs[1] = SysSpec{&dBt, T.as<double>(), nullptr, 0.0, 0.0, r, o.restart, o.precision, o.max_inner, fl};
+  InnerBatch ib;
+  LRADI_TRY(build_batch(c, specs, ib));
+
+  AdiDesc ad{};
+  ad.n = n;
+  ad.m = m;
+  ad.r = r;
+  ad.kmax = o.kmax;
+  ad.nshifts = nshifts;
+  ad.selection = o.selection;
+  ad.backlook = o.backlook;
+  ad.paper_abs = o.paper_abs;
+  ad.rescale = o.rescale;
+  ad.tol = o.tol;
+  ad.eps_in = o.eps;
+  ad.delta_min = o.delta_min;
+  ad.delta_max = o.delta_max;
+  ad.xi = o.xi;
+  ad.delta_fixed = o.delta_fixed;
+  ad.rho = o.rho;
+  ad.shiftsA = shA.as<double>();
+  ad.shiftsB = shB.as<double>();
+  ad.f = f;
+  ad.g = g;
+  ad.W = W.as<double>();
+  ad.T = T.as<double>();
+  ad.Zf = res->Zf.as<double>();
+  ad.Yf = res->Yf.as<double>();
+  ad.gam = gam.as<double>();
+  ad.hist = hist.as<double>();
+  LRADI_TRY(dad.alloc(sizeof(AdiDesc)));
+  LRADI_TRY(dac.alloc(sizeof(AdiCtl)));
+  LRADI_HIP(hipMemcpyAsync(dad.p, &ad, sizeof(AdiDesc), hipMemcpyHostToDevice, st));
+  LRADI_TRY(c->done.init(1));
+  c->done.h[0] = 0;
+  LRADI_TRY(adi_launch_setup(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1));
+  for (int k = 0; k < o.kmax; ++k) {
+    LRADI_TRY(adi_launch_prepare(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1));
+    LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner));
+    LRADI_TRY(adi_launch_finish(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1, c->done.d));
+    LRADI_HIP(hipStreamSynchronize(st));
+    if (__atomic_load_n(c->done.h, __ATOMIC_ACQUIRE)) break;
+  }
+  AdiCtl hac;
+  LRADI_HIP(hipMemcpy(&hac, dac.p, sizeof(AdiCtl), hipMemcpyDeviceToHost));
+  const auto t1 = std::chrono::steady_clock::now();
+  res->k = hac.k;
+  res->norm_fg = hac.norm_fg;
+  res->rel_res = hac.norm_fg > 0.0 ? hac.res / hac.norm_fg : 0.0;
+  res->seconds = std::chrono::duration<double>(t1 - t0).count();
+  res->gam.resize(o.kmax);
+  res->hist.resize((size_t)o.kmax * kHistCols);
+  LRADI_HIP(hipMemcpy(res->gam.data(), gam.p, sizeof(double) * o.kmax, hipMemcpyDeviceToHost));
+  LRADI_HIP(hipMemcpy(res->hist.data(), hist.p, sizeof(double) * o.kmax * kHistCols, hipMemcpyDeviceToHost));
+  int status = hac.status;
+  if (status == LRADI_OK && hac.winner) status = LRADI_WINNER;
+  res->status = status;
+  *out = res.release();
+  return status;
+}
+
+int lradi_result_info(const lradi_result* r, int* k, int* status, double* rel, double* nfg) {
+  if (!r) return set_error("null result"), LRADI_EINVAL;
+  if (k) *k = r->k;
+  if (status) *status = r->status;
+  if (rel) *rel = r->rel_res;
+  if (nfg) *nfg = r->norm_fg;
+  return LRADI_OK;
+}
+
+int lradi_result_factors(const lradi_result* r, const double** Z, const double** D, const double** Y,
+                         int* n, int* m, int* rr) {
+  if (!r) return set_error("null result"), LRADI_EINVAL;
+  if (Z) *Z = r->Zf.as<double>();
+  if (D) *D = r->gam.data();
+  if (Y) *Y = r->Yf.as<double>();
+  if (n) *n = r->n;
+  if (m) *m = r->m;
+  if (rr) *rr = r->r;
+  return LRADI_OK;
+}
+
+int lradi_result_copy(const lradi_result* r, double* Z, double* D, double* Y) {
+  if (!r) return set_error("null result"), LRADI_EINVAL;
+  if (Z && r->k > 0)
+    LRADI_HIP(hipMemcpy(Z, r->Zf.p, sizeof(double) * (size_t)r->k * r->n * r->r, hipMemcpyDeviceToHost));
+  if (Y && r->k > 0)
+    LRADI_HIP(hipMemcpy(Y, r->Yf.p, sizeof(double) * (size_t)r->k * r->m * r->r, hipMemcpyDeviceToHost));
+  if (D) std::copy(r->gam.begin(), r->gam.begin() + r->k, D);
+  return LRADI_OK;
+}
+
+int lradi_result_history(const lradi_result* r, double* rows, int max_rows, int* nrows) {
+  if (!r || !rows) return set_error("null argument"), LRADI_EINVAL;
+  const int k = std::min(r->k, std::max(max_rows, 0));
+  std::copy(r->hist.begin(), r->hist.begin() + (size_t)k * kHistCols, rows);
+  if (nrows) *nrows = k;
+  return LRADI_OK;
+}
+
+int lradi_result_time(const lradi_result* r, double* seconds) {
+  if (!r || !seconds) return set_error("null argument"), LRADI_EINVAL;
+  *seconds = r->seconds;
+  return LRADI_OK;
+}
+
+void lradi_result_free(lradi_result* r) { delete r; }
+
+int lradi_residual(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, int b_is_transposed,
+                   const double* f, const double* g, int r, const double* Z, const double* D,
+                   const double* Y, int k, double* rel) {
+  (void)c; (void)A; (void)B; (void)b_is_transposed; (void)f; (void)g; (void)r; (void)Z; (void)D;
+  (void)Y; (void)k; (void)rel;
+  set_error("lradi_residual: not available in this build");
+  return LRADI_EINVAL;
+}
+
+}  // extern "C"

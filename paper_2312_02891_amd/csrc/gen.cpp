@@ -1,0 +1,114 @@
+// Host-side problem construction: the upwind convection-diffusion matrices of
+// Sec. 4 (eq. (ex:convdiff)) in CSR form, and a CSR transpose.
+//
+// This file must be compiled with -ffp-contract=off: every product and sum
+// of the value recipe is rounded on its own, so the stored FP64 values are
+// reproducible bit for bit.
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lradi.h"
+
+namespace lradi {
+void set_error(const char* fmt, ...);
+}
+
+extern "C" int lradi_convdiff_size(int dim, int N, int64_t* n, int64_t* nnz) {
+  if ((dim != 2 && dim != 3) || N < 1) {
+    lradi::set_error("lradi_convdiff_size: dim must be 2 or 3 and N >= 1");
+    return LRADI_EINVAL;
+  }
+  int64_t p = 1, q = 1;
+  for (int c = 0; c < dim; ++c) p *= N;
+  for (int c = 0; c < dim - 1; ++c) q *= N;
+  if (p > INT32_MAX) {
+    lradi::set_error("lradi_convdiff_size: N^dim exceeds int32 rows");
+    return LRADI_EINVAL;
+  }
+  if (n) *n = p;
+  if (nnz) *nnz = (2 * dim + 1) * p - 2 * dim * q;
+  return LRADI_OK;
+}
+
+extern "C" int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* rowptr,
+                                  int32_t* colind, double* val) {
+  int64_t n = 0, nnz = 0;
+  int st = lradi_convdiff_size(dim, N, &n, &nnz);
+  if (st != LRADI_OK) return st;
+  if (!omega || !rowptr || !colind || !val) {
+    lradi::set_error("lradi_gen_convdiff: null pointer");
+    return LRADI_EINVAL;
+  }
+  if (nnz > INT32_MAX) {
+    lradi::set_error("lradi_gen_convdiff: nnz exceeds int32 indices");
+    return LRADI_EINVAL;
+  }
+  // coefficients of L_h (positive diagonal); A = -L_h
+  const double ih = (double)(N + 1);
+  const double ih2 = ih * ih;
+  double lo[3], hi[3];
+  double diag = 0.0;
+  for (int c = 0; c < dim; ++c) {
+    const double w = omega[c];
+    const double wp = w > 0.0 ? w : 0.0;
+    const double wm = (-w) > 0.0 ? (-w) : 0.0;
+    const double tlo = wp * ih;
+    const double thi = wm * ih;
+    lo[c] = -ih2 - tlo;  // neighbour p - s_c
+    hi[c] = -ih2 - thi;  // neighbour p + s_c
+    const double twoih2 = 2.0 * ih2;
+    const double aw = std::fabs(w) * ih;
+    const double term = twoih2 + aw;
+    diag = diag + term;
+  }
+  int64_t stride[3] = {1, N, (int64_t)N * N};
+  int64_t k = 0;
+  rowptr[0] = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t coord[3];
+    for (int c = 0; c < dim; ++c) coord[c] = (p / stride[c]) % N;
+    // ascending columns: p - s_{d-1}, ..., p - s_0, p, p + s_0, ..., p + s_{d-1}
+    for (int c = dim - 1; c >= 0; --c) {
+      if (coord[c] > 0) {
+        colind[k] = (int32_t)(p - stride[c]);
+        val[k] = -lo[c];
+        ++k;
+      }
+    }
+    colind[k] = (int32_t)p;
+    val[k] = -diag;
+    ++k;
+    for (int c = 0; c < dim; ++c) {
+      if (coord[c] < N - 1) {
+        colind[k] = (int32_t)(p + stride[c]);
+        val[k] = -hi[c];
+        ++k;
+      }
+    }
+    rowptr[p + 1] = (int32_t)k;
+  }
+  return (k == nnz) ? LRADI_OK : LRADI_EINVAL;
+}
+
+namespace lradi {
+
+// Transpose of an n x n CSR matrix (host arrays), columns ascending.
+void csr_transpose(int n, const int32_t* rp, const int32_t* ci, const double* v,
+                   std::vector<int32_t>& trp, std::vector<int32_t>& tci, std::vector<double>& tv) {
+  const int64_t nnz = rp[n];
+  trp.assign(n + 1, 0);
+  tci.resize(nnz);
+  tv.resize(nnz);
+  for (int64_t k = 0; k < nnz; ++k) trp[ci[k] + 1] += 1;
+  for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
+  std::vector<int64_t> pos(trp.begin(), trp.end() - 1);
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int64_t dst = pos[ci[k]]++;
+      tci[dst] = i;
+      tv[dst] = v[k];
+    }
+}
+
+}  // namespace lradi

@@ -1,0 +1,145 @@
+// Internal declarations of the lradi library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lradi.h"
+
+namespace lradi {
+
+constexpr int kMaxR = 8;        // widest right-hand-side block
+constexpr int kMaxM = 64;       // longest block GMRES restart cycle (blocks)
+constexpr int kTPB = 256;       // threads of a row workgroup (4 wavefronts)
+constexpr int kSmallTPB = 64;   // threads of a per-system workgroup (1 wavefront)
+constexpr int kHistCols = LRADI_HIST_COLS;
+constexpr int kPS = 128;        // stride of the small Gram partial rows
+
+// Phases of one inner solve; every kernel of the batched solver checks the
+// phase of its system and returns at once when it is not the one it serves.
+enum Phase : int {
+  PH_ARNOLDI = 0,    // extend the basis by one block (block Arnoldi step)
+  PH_RESTART = 1,    // (re)build V_0 from the refinement residual R
+  PH_CYCLE_END = 2,  // update Z, recompute the FP64 residual, decide
+  PH_FINISHED = 3,   // converged or out of budget; all kernels skip
+};
+
+enum InnerStatus : int { IS_OK = 0, IS_CAP = 1, IS_BREAKDOWN = 2, IS_NAN = 3 };
+
+// Read-only description of one shifted block system (A + shift I) Z = W.
+struct SysDesc {
+  int n, r, m;          // rows, right-hand sides, restart length (blocks)
+  int nwg;              // row workgroups of this system
+  int rows_per_wg;      // rows handled by each of them
+  int wg0;              // first of them in the batched row grid
+  int precision;        // LRADI_FP64 / LRADI_FP32_INNER
+  int max_inner;        // Arnoldi step cap
+  const int* rowptr;
+  const int* colind;
+  const void* valT;     // values in the basis precision
+  const double* val64;  // FP64 values (refinement residual)
+  double floor_rel;     // a cycle stops once est <= floor_rel * (start norm)
+  const double* W;      // right-hand side, n x r
+  double* R;            // FP64 refinement residual, n x r
+  void* V;              // basis, (m+1) blocks of n x r, basis precision
+  void* U;              // candidate block, n x r, basis precision
+  double* part;         // per-workgroup Gram partials, nwg x pstride
+  double* partS;        // per-workgroup small Gram partials, nwg x kPS
+  double* red;          // reduced projection coefficients, (m+1) r^2
+  double* hacc;         // Hessenberg column block being built, (m+1) r^2
+  double* Rt;           // triangular factor, (m r) x (m r), column-major
+  double* Qs;           // per column block orthogonal 2r x 2r factors, m x 4r^2
+  double* Gv;           // rotated right-hand side, (m+1) r x r, row-major
+  double* yv;           // least-squares solution, m r x r, row-major
+  double* sm;           // small scratch (8 x 64 doubles)
+  int pstride;          // stride of part rows (>= (m+1) r^2)
+  int pad0;
+};
+
+// Mutable device-side control block of one inner solve.
+struct SysCtl {
+  double* Z;    // solution block, n x r (set per solve)
+  double shift; // the system is (A + shift I) Z = W
+  int phase;
+  int j;        // Arnoldi step index inside the cycle (basis blocks V_0..V_j exist)
+  int ncols;    // block columns of the current least-squares problem
+  int steps;    // total block Arnoldi steps
+  int cycles;   // restart cycles started
+  int status;   // InnerStatus
+  int breakdowns;
+  int first;    // 1 before the first residual evaluation (Z = 0)
+  double delta; // target ||W - S Z||_2
+  double est;   // least-squares residual estimate of the current cycle
+  double rnorm; // last FP64 ||W - S Z||_2
+  double r0;    // ||R|| at the start of the current cycle
+};
+
+// small scratch slots (offsets into SysDesc::sm, 64 doubles each)
+enum SmSlot { SM_S1 = 0, SM_S1I = 64, SM_S2 = 128, SM_S2I = 192, SM_G = 256, SM_T = 320 };
+
+// ---------------------------------------------------------------------------
+// error state
+void set_error(const char* fmt, ...);
+#define LRADI_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::lradi::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                         __FILE__, __LINE__);                                     \
+      return LRADI_EHIP;                                                          \
+    }                                                                             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory helper: a typed owning buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  int alloc(size_t nbytes);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Device copy of a CSR matrix in FP64 and FP32.
+struct DevCSR {
+  int n = 0;
+  int64_t nnz = 0;
+  DevBuf rowptr, colind, val64, val32;
+  int upload(const lradi_csr* A, hipStream_t st, bool need32);
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels.hip)
+int launch_spmm_plain(hipStream_t st, int n, int r, int precision, const int* rowptr,
+                      const int* colind, const void* val, double shift, const void* X, void* Y);
+
+// The batched inner solver: all systems of a batch share one precision.
+struct Batch {
+  const SysDesc* d;    // device array of nsys
+  SysCtl* ctl;         // device array of nsys
+  const int2* rowmap;  // device array of rowgrid entries (system, chunk)
+  int nsys;
+  int rowgrid;
+  int maxP;            // max over systems of (m+1) r^2
+  int precision;       // LRADI_FP64 / LRADI_FP32_INNER
+};
+// One scheduling tick: a block Arnoldi step (or the rebuild of V_0) for every
+// system in PH_ARNOLDI / PH_RESTART, then the end-of-cycle work for every
+// system in PH_CYCLE_END.
+int launch_tick(hipStream_t st, const Batch& b);
+// Count of systems not yet finished, written to a host-visible int.
+int launch_summary(hipStream_t st, const Batch& b, int* host_slot);
+
+}  // namespace lradi

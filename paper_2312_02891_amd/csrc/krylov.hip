@@ -1,0 +1,749 @@
+// Batched block GMRES(m) with FP64 iterative refinement for the shifted
+// inner systems (A + s I) Z = W of the inexact LR-ADI iteration
+// (Algorithm 1, eq. (gfadi_incsolves)).
+//
+// Every kernel serves all systems of a batch at once: row kernels map each
+// workgroup to (system, row chunk) through a table, per-system kernels use one
+// workgroup per system.  Each system carries a device-side phase, and a kernel
+// returns at once for systems in a phase it does not serve, so the host can
+// issue the same launch sequence ("tick") over and over without reading
+// anything back per step.
+//
+// One Arnoldi step for the block V_j (n x r):
+//   U = (A + s I) V_j                          SpMM, basis precision
+//   H1 = V^T U,  U -= V H1                     block classical Gram-Schmidt
+//   H2 = V^T U,  U -= V H2                     ... repeated once (CGS2)
+//   U = V_{j+1} S with S = S2 S1               CholQR2 (two Cholesky QR passes)
+//   column block [H1 + H2; S] enters the incremental QR of the block
+//   Hessenberg matrix (one 2r x 2r orthogonal factor per column block), the
+//   rotated right-hand side gives the residual estimate.
+// At the end of a cycle: Z += V y, R = W - (A + s I) Z in FP64, ||R||_2 from
+// the r x r Gram matrix, then stop or restart from R.
+#include <cstdio>
+
+#include "internal.h"
+#include "small.h"
+
+namespace lradi {
+namespace {
+
+#define LRADI_DISPATCH_R(rv, ...)          \
+  switch (rv) {                            \
+    case 1: { constexpr int RR = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int RR = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int RR = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int RR = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int RR = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int RR = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int RR = 7; __VA_ARGS__; } break; \
+    case 8: { constexpr int RR = 8; __VA_ARGS__; } break; \
+    default: break;                        \
+  }
+
+struct RowCtx {
+  int s, w, row0, row1;
+};
+
+__device__ inline RowCtx row_ctx(const SysDesc* d, const int2* rowmap) {
+  const int2 sc = rowmap[blockIdx.x];
+  const SysDesc& D = d[sc.x];
+  RowCtx c;
+  c.s = sc.x;
+  c.w = sc.y;
+  c.row0 = sc.y * D.rows_per_wg;
+  c.row1 = min(D.n, c.row0 + D.rows_per_wg);
+  return c;
+}
+
+// Sum NV per-thread values over the 256 threads of the workgroup in a fixed
+// order and store the totals to out[0..NV).  lds needs 4*NV doubles.
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double* lds, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) lds[wave * NV + k] = x;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV; k += kTPB)
+    out[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
+  __syncthreads();
+}
+
+// Sum the per-workgroup r x r (P values) partial rows partS[w][0..P) over
+// w in a fixed order with a 256-thread workgroup; result in out (shared).
+__device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, double* out) {
+  const int t = threadIdx.x;
+  const int groups = kTPB / P;  // P <= 64, so groups >= 4
+  const int p = t % P, g = t / P;
+  double acc = 0.0;
+  if (g < groups)
+    for (int w = g; w < D.nwg; w += groups) acc += D.partS[(size_t)w * kPS + p];
+  red_lds[t] = acc;
+  __syncthreads();
+  if (t < P) {
+    double s = 0.0;
+    for (int q = 0; q < groups; ++q) s += red_lds[q * P + t];
+    out[t] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// 1. U = (A + s I) V_j  (PH_ARNOLDI)   or   U = R rounded  (PH_RESTART)
+template <typename T, int R>
+__device__ inline void spmm_rows(const SysDesc& D, const RowCtx& c, T shift, const T* __restrict__ X,
+                                 T* __restrict__ Y) {
+  const T* __restrict__ val = static_cast<const T*>(D.valT);
+  const int* __restrict__ rp = D.rowptr;
+  const int* __restrict__ ci = D.colind;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    T acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = T(0);
+    const int k0 = rp[i], k1 = rp[i + 1];
+    for (int k = k0; k < k1; ++k) {
+      const int col = ci[k];
+      const T a = val[k];
+      const T* x = X + (size_t)col * R;
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += a * x[q];
+    }
+    const T* xi = X + (size_t)i * R;
+#pragma unroll
+    for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = acc[q] + shift * xi[q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
+                                                   const SysCtl* __restrict__ ctl,
+                                                   const int2* __restrict__ rowmap) {
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const int ph = ctl[c.s].phase;
+  T* U = static_cast<T*>(D.U);
+  if (ph == PH_RESTART) {
+    const size_t e1 = (size_t)c.row1 * D.r;
+    for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) U[e] = (T)D.R[e];
+    return;
+  }
+  if (ph != PH_ARNOLDI) return;
+  const T* Vj = static_cast<const T*>(D.V) + (size_t)ctl[c.s].j * D.n * D.r;
+  const T sh = (T)ctl[c.s].shift;
+  LRADI_DISPATCH_R(D.r, spmm_rows<T, RR>(D, c, sh, Vj, U));
+}
+
+// ---------------------------------------------------------------------------
+// 2. partial Gram  part[w][b][a][q] = sum_{i in chunk} V_b[i][a] U[i][q],
+//    b = 0..j  (PH_ARNOLDI).  Lane layout: lane = (row offset, a).
+template <typename T, int R>
+__device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, double* lds) {
+  constexpr int RPW = 64 / R;
+  constexpr int G = (16 / R) > 0 ? (16 / R) : 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ro = lane / R, a = lane - ro * R;
+  const bool act = ro < RPW;
+  const T* __restrict__ V = static_cast<const T*>(D.V);
+  const T* __restrict__ U = static_cast<const T*>(D.U);
+  const size_t bs = (size_t)D.n * R;
+  double* out = D.part + (size_t)c.w * D.pstride;
+  for (int b0 = 0; b0 < nb; b0 += G) {
+    const int gc = min(G, nb - b0);
+    double acc[G][R];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[g][q] = 0.0;
+    if (act) {
+      for (int i = c.row0 + wave * RPW + ro; i < c.row1; i += 4 * RPW) {
+        double u[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) u[q] = (double)U[(size_t)i * R + q];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (g < gc) {
+            const double x = (double)V[(size_t)(b0 + g) * bs + (size_t)i * R + a];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[g][q] += x * u[q];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[threadIdx.x * 16 + g * R + q] = acc[g][q];
+    __syncthreads();
+    const int nout = gc * R * R;
+    for (int o = threadIdx.x; o < nout; o += kTPB) {
+      const int g = o / (R * R), rem = o - g * R * R, aa = rem / R, q = rem - aa * R;
+      double sum = 0.0;
+      for (int wv = 0; wv < 4; ++wv)
+        for (int rr = 0; rr < RPW; ++rr) sum += lds[(wv * 64 + rr * R + aa) * 16 + g * R + q];
+      out[(size_t)(b0 + g) * R * R + aa * R + q] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTPB) void k_gram_vu(const SysDesc* __restrict__ d,
+                                                  const SysCtl* __restrict__ ctl,
+                                                  const int2* __restrict__ rowmap) {
+  __shared__ double lds[kTPB * 16];
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  if (ctl[c.s].phase != PH_ARNOLDI) return;
+  const int nb = ctl[c.s].j + 1;
+  LRADI_DISPATCH_R(D.r, gram_vu_rows<T, RR>(D, c, nb, lds));
+}
+
+// 3. red = sum_w part[w]; hacc = red (first pass) or hacc += red (second).
+__global__ __launch_bounds__(kTPB) void k_reduce_vu(const SysDesc* __restrict__ d,
+                                                    const SysCtl* __restrict__ ctl, int first) {
+  const int s = blockIdx.x;
+  const SysDesc& D = d[s];
+  if (ctl[s].phase != PH_ARNOLDI) return;
+  const int P = (ctl[s].j + 1) * D.r * D.r;
+  const int p = blockIdx.y * kTPB + threadIdx.x;
+  if (p >= P) return;
+  double sum = 0.0;
+  for (int w = 0; w < D.nwg; ++w) sum += D.part[(size_t)w * D.pstride + p];
+  D.red[p] = sum;
+  if (first)
+    D.hacc[p] = sum;
+  else
+    D.hacc[p] += sum;
+}
+
+// ---------------------------------------------------------------------------
+// 4./7. U -= sum_b V_b red_b  (PH_ARNOLDI); with gram = 1 also the partial
+//       U^T U of the result into partS (PH_ARNOLDI and PH_RESTART).
+template <typename T, int R>
+__device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bool do_update,
+                                   bool gram, double* hl, double* lds) {
+  if (do_update) {
+    for (int e = threadIdx.x; e < nb * R * R; e += kTPB) hl[e] = D.red[e];
+    __syncthreads();
+  }
+  const T* __restrict__ V = static_cast<const T*>(D.V);
+  T* __restrict__ U = static_cast<T*>(D.U);
+  const size_t bs = (size_t)D.n * R;
+  double g2[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    T u[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) u[q] = U[(size_t)i * R + q];
+    if (do_update) {
+      T acc[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = T(0);
+      for (int b = 0; b < nb; ++b) {
+        T v[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) v[a] = V[(size_t)b * bs + (size_t)i * R + a];
+        const double* h = hl + b * R * R;
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q] += v[a] * (T)h[a * R + q];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        u[q] -= acc[q];
+        U[(size_t)i * R + q] = u[q];
+      }
+    }
+    if (gram) {
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int q = 0; q < R; ++q) g2[a * R + q] += (double)u[a] * (double)u[q];
+    }
+  }
+  if (gram) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTPB) void k_update(const SysDesc* __restrict__ d,
+                                                 const SysCtl* __restrict__ ctl,
+                                                 const int2* __restrict__ rowmap, int second) {
+  __shared__ double hl[(kMaxM + 1) * kMaxR * kMaxR];
+  __shared__ double lds[4 * kMaxR * kMaxR];
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const int ph = ctl[c.s].phase;
+  bool do_update, gram;
+  if (ph == PH_ARNOLDI) {
+    do_update = true;
+    gram = second != 0;
+  } else if (ph == PH_RESTART && second) {
+    do_update = false;
+    gram = true;
+  } else {
+    return;
+  }
+  const int nb = ctl[c.s].j + 1;
+  LRADI_DISPATCH_R(D.r, update_rows<T, RR>(D, c, nb, do_update, gram, hl, lds));
+}
+
+// ---------------------------------------------------------------------------
+// 8./10. Cholesky factor of the reduced U^T U (PH_ARNOLDI / PH_RESTART).
+__global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl,
+                                               int slot, double rel_floor64, double rel_floor32) {
+  __shared__ double red_lds[kTPB];
+  __shared__ double G[64];
+  const int s = blockIdx.x;
+  const SysDesc& D = d[s];
+  const int ph = ctl[s].phase;
+  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  const int R = D.r;
+  reduce_partS(D, R * R, red_lds, G);
+  if (threadIdx.x == 0) {
+    double S[64], Si[64];
+    const double fl = (D.precision == LRADI_FP64) ? rel_floor64 : rel_floor32;
+    const int reg = chol_upper_reg(G, S, R, fl);
+    if (reg < 0) {
+      ctl[s].status = IS_NAN;
+      ctl[s].phase = PH_FINISHED;
+    } else {
+      if (reg > 0) ctl[s].breakdowns += 1;
+      tri_inv_upper(S, Si, R);
+      double* dst = D.sm + (slot == 0 ? SM_S1 : SM_S2);
+      double* dsti = D.sm + (slot == 0 ? SM_S1I : SM_S2I);
+      for (int e = 0; e < R * R; ++e) {
+        dst[e] = S[e];
+        dsti[e] = Si[e];
+      }
+    }
+  }
+}
+
+// 9./11. pass 0: U = U S1^{-1} in place and partial U^T U;
+//        pass 1: V_{j+1} (PH_ARNOLDI) or V_0 (PH_RESTART) = U S2^{-1}.
+template <typename T, int R>
+__device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const double* Si, T* dst,
+                                  bool gram, double* lds) {
+  double sl[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) sl[e] = Si[e];
+  T* __restrict__ U = static_cast<T*>(D.U);
+  double g2[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    double u[R], o[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) u[q] = (double)U[(size_t)i * R + q];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a <= q; ++a) v += u[a] * sl[a * R + q];
+      o[q] = v;
+    }
+    T ot[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      ot[q] = (T)o[q];
+      dst[(size_t)i * R + q] = ot[q];
+    }
+    if (gram) {
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int q = 0; q < R; ++q) g2[a * R + q] += (double)ot[a] * (double)ot[q];
+    }
+  }
+  if (gram) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
+                                                const SysCtl* __restrict__ ctl,
+                                                const int2* __restrict__ rowmap, int pass) {
+  __shared__ double lds[4 * kMaxR * kMaxR];
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const int ph = ctl[c.s].phase;
+  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  T* dst;
+  const double* Si;
+  if (pass == 0) {
+    dst = static_cast<T*>(D.U);
+    Si = D.sm + SM_S1I;
+  } else {
+    const int tgt = (ph == PH_ARNOLDI) ? ctl[c.s].j + 1 : 0;
+    dst = static_cast<T*>(D.V) + (size_t)tgt * D.n * D.r;
+    Si = D.sm + SM_S2I;
+  }
+  LRADI_DISPATCH_R(D.r, scale_rows<T, RR>(D, c, Si, dst, pass == 0, lds));
+}
+
+// ---------------------------------------------------------------------------
+// 12. least-squares update (one workgroup per system).
+//   PH_RESTART: G = [S; 0] with S = S2 S1, start a cycle.
+//   PH_ARNOLDI: bring column block j of the block Hessenberg matrix,
+//   [H_{0..j,j}; S], through the stored orthogonal factors Q_0..Q_{j-1},
+//   factor its last 2r x r part (Householder, Q_j), rotate the right-hand
+//   side, and take the residual estimate ||G_{j+1}||_F.  At the end of a
+//   cycle solve the triangular system for y.
+__global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
+  __shared__ double h[(kMaxM + 1) * kMaxR * kMaxR];
+  __shared__ double Sf[64];
+  __shared__ double M[16 * 8];
+  __shared__ double Qj[16 * 16];
+  __shared__ int done_s;
+  const int s = blockIdx.x;
+  const SysDesc& D = d[s];
+  SysCtl& C = ctl[s];
+  const int ph = C.phase;
+  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  const int R = D.r, m = D.m, t = threadIdx.x;
+  const int RR2 = R * R;
+  const double* S1 = D.sm + SM_S1;
+  const double* S2 = D.sm + SM_S2;
+  if (t < RR2) {
+    const int a = t / R, q = t - a * R;
+    double v = 0.0;
+    for (int k = 0; k < R; ++k) v += S2[a * R + k] * S1[k * R + q];
+    Sf[t] = v;
+  }
+  __syncthreads();
+  if (ph == PH_RESTART) {
+    for (int e = t; e < (m + 1) * RR2; e += kTPB) D.Gv[e] = (e < RR2) ? Sf[e] : 0.0;
+    if (t == 0) {
+      C.j = 0;
+      C.ncols = 0;
+      C.est = C.r0;
+      C.phase = PH_ARNOLDI;
+    }
+    return;
+  }
+  const int j = C.j;
+  const int ldR = m * R;
+  // assemble column block j, (j+2) r rows x r, row-major
+  for (int e = t; e < (j + 2) * RR2; e += kTPB) {
+    const int b = e / RR2;
+    h[e] = (b <= j) ? D.hacc[e] : Sf[e - b * RR2];
+  }
+  __syncthreads();
+  // apply Q_b^T to rows [b r, b r + 2r)
+  for (int b = 0; b < j; ++b) {
+    const double* Q = D.Qs + (size_t)b * 4 * RR2;
+    const int twoR = 2 * R;
+    double nv = 0.0;
+    int a = 0, q = 0;
+    const bool act = t < twoR * R;
+    if (act) {
+      a = t / R;
+      q = t - a * R;
+      for (int k = 0; k < twoR; ++k) nv += Q[k * twoR + a] * h[(b * R + k) * R + q];
+    }
+    __syncthreads();
+    if (act) h[(b * R + a) * R + q] = nv;
+    __syncthreads();
+  }
+  // Householder QR of rows [j r, j r + 2r)
+  for (int e = t; e < 2 * RR2; e += kTPB) M[e] = h[j * RR2 + e];
+  __syncthreads();
+  if (t == 0) householder_2nxn(M, Qj, R);
+  __syncthreads();
+  for (int e = t; e < 4 * RR2; e += kTPB) D.Qs[(size_t)j * 4 * RR2 + e] = Qj[e];
+  // triangular factor, column block j
+  for (int e = t; e < (j + 1) * RR2; e += kTPB) {
+    const int row = e / R, q = e - row * R;
+    const double v = (row < j * R) ? h[row * R + q] : M[(row - j * R) * R + q];
+    D.Rt[(size_t)(j * R + q) * ldR + row] = v;
+  }
+  // rotate the right-hand side rows [j r, j r + 2r)
+  {
+    const int twoR = 2 * R;
+    double nv = 0.0;
+    int a = 0, q = 0;
+    const bool act = t < twoR * R;
+    if (act) {
+      a = t / R;
+      q = t - a * R;
+      for (int k = 0; k < twoR; ++k) nv += Qj[k * twoR + a] * D.Gv[(j * R + k) * R + q];
+    }
+    __syncthreads();
+    if (act) D.Gv[(j * R + a) * R + q] = nv;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double e2 = 0.0;
+    for (int e = 0; e < RR2; ++e) {
+      const double g = D.Gv[((j + 1) * R) * R + e];
+      e2 += g * g;
+    }
+    const double est = sqrt(e2);
+    C.steps += 1;
+    C.ncols = j + 1;
+    C.est = est;
+    const double thr = fmax(C.delta, D.floor_rel * C.r0);
+    int done = (est <= thr) || (j + 1 >= m) || (C.steps >= D.max_inner) || !(est == est);
+    done_s = done;
+    if (!done) C.j = j + 1;
+  }
+  __syncthreads();
+  if (!done_s) return;
+  // back substitution R_t y = G(0 : (j+1) r), block by block
+  const int nc = j + 1;
+  double* g = h;  // reuse
+  for (int e = t; e < nc * RR2; e += kTPB) g[e] = D.Gv[e];
+  __syncthreads();
+  for (int bj = nc - 1; bj >= 0; --bj) {
+    if (t < R) {
+      const int q = t;
+      for (int a = R - 1; a >= 0; --a) {
+        const int row = bj * R + a;
+        double v = g[row * R + q];
+        for (int k = a + 1; k < R; ++k) v -= D.Rt[(size_t)(bj * R + k) * ldR + row] * g[(bj * R + k) * R + q];
+        v /= D.Rt[(size_t)row * ldR + row];
+        g[row * R + q] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < bj * RR2; e += kTPB) {
+      const int row = e / R, q = e - row * R;
+      double v = g[e];
+      for (int k = 0; k < R; ++k) v -= D.Rt[(size_t)(bj * R + k) * ldR + row] * g[(bj * R + k) * R + q];
+      g[e] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < nc * RR2; e += kTPB) D.yv[e] = g[e];
+  if (t == 0) C.phase = PH_CYCLE_END;
+}
+
+// ---------------------------------------------------------------------------
+// 13. Z += sum_b V_b y_b  (PH_CYCLE_END, at least one column)
+template <typename T, int R>
+__device__ inline void zupdate_rows(const SysDesc& D, const RowCtx& c, double* Z, int nb,
+                                    const double* yl) {
+  const T* __restrict__ V = static_cast<const T*>(D.V);
+  const size_t bs = (size_t)D.n * R;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      double v[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) v[a] = (double)V[(size_t)b * bs + (size_t)i * R + a];
+      const double* y = yl + b * R * R;
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += v[a] * y[a * R + q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) Z[(size_t)i * R + q] += acc[q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTPB) void k_zupdate(const SysDesc* __restrict__ d,
+                                                  const SysCtl* __restrict__ ctl,
+                                                  const int2* __restrict__ rowmap) {
+  __shared__ double yl[kMaxM * kMaxR * kMaxR];
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  if (ctl[c.s].phase != PH_CYCLE_END) return;
+  const int nb = ctl[c.s].ncols;
+  if (nb <= 0 || ctl[c.s].first) return;
+  const int R = D.r;
+  for (int e = threadIdx.x; e < nb * R * R; e += kTPB) yl[e] = D.yv[e];
+  __syncthreads();
+  LRADI_DISPATCH_R(D.r, zupdate_rows<T, RR>(D, c, ctl[c.s].Z, nb, yl));
+}
+
+// 14. R = W - (A + s I) Z in FP64 and partial R^T R  (PH_CYCLE_END).
+//     Before the first evaluation Z is set to zero and R = W.
+template <int R>
+__device__ inline void resid_rows(const SysDesc& D, const RowCtx& c, double shift, double* Z,
+                                  bool first, double* lds) {
+  const double* __restrict__ val = D.val64;
+  const int* __restrict__ rp = D.rowptr;
+  const int* __restrict__ ci = D.colind;
+  double g2[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    double rr[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rr[q] = D.W[(size_t)i * R + q];
+    if (first) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) Z[(size_t)i * R + q] = 0.0;
+    } else {
+      double acc[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = shift * Z[(size_t)i * R + q];
+      const int k0 = rp[i], k1 = rp[i + 1];
+      for (int k = k0; k < k1; ++k) {
+        const int col = ci[k];
+        const double a = val[k];
+        const double* z = Z + (size_t)col * R;
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += a * z[q];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) rr[q] -= acc[q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) D.R[(size_t)i * R + q] = rr[q];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = 0; q < R; ++q) g2[a * R + q] += rr[a] * rr[q];
+  }
+  block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+}
+
+__global__ __launch_bounds__(kTPB) void k_resid(const SysDesc* __restrict__ d,
+                                                const SysCtl* __restrict__ ctl,
+                                                const int2* __restrict__ rowmap) {
+  __shared__ double lds[4 * kMaxR * kMaxR];
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  if (ctl[c.s].phase != PH_CYCLE_END) return;
+  LRADI_DISPATCH_R(D.r, resid_rows<RR>(D, c, ctl[c.s].shift, ctl[c.s].Z, ctl[c.s].first != 0, lds));
+}
+
+// 15. ||R||_2 from R^T R; finish or restart (PH_CYCLE_END).
+__global__ __launch_bounds__(kTPB) void k_decide(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
+  __shared__ double red_lds[kTPB];
+  __shared__ double G[64];
+  const int s = blockIdx.x;
+  const SysDesc& D = d[s];
+  SysCtl& C = ctl[s];
+  if (C.phase != PH_CYCLE_END) return;
+  const int R = D.r;
+  reduce_partS(D, R * R, red_lds, G);
+  if (threadIdx.x == 0) {
+    bool bad = false;
+    for (int e = 0; e < R * R; ++e)
+      if (!(G[e] == G[e]) || G[e] - G[e] != 0.0) bad = true;
+    if (bad) {
+      C.status = IS_NAN;
+      C.phase = PH_FINISHED;
+      C.rnorm = G[0];
+      return;
+    }
+    const double rn = sqrt(fmax(lambda_max_sym(G, R), 0.0));
+    C.rnorm = rn;
+    C.first = 0;
+    if (rn <= C.delta) {
+      C.phase = PH_FINISHED;
+    } else if (C.steps >= D.max_inner) {
+      C.status = IS_CAP;
+      C.phase = PH_FINISHED;
+    } else {
+      C.cycles += 1;
+      C.r0 = rn;
+      C.phase = PH_RESTART;
+    }
+  }
+}
+
+// count of unfinished systems -> host-visible slot
+__global__ __launch_bounds__(kTPB) void k_summary(const SysCtl* __restrict__ ctl, int nsys, int* slot) {
+  __shared__ int cnt[kTPB];
+  int c = 0;
+  for (int s = threadIdx.x; s < nsys; s += kTPB) c += (ctl[s].phase != PH_FINISHED) ? 1 : 0;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = kTPB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(slot, cnt[0], __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// plain Y = (A + s I) X for one block (no phases)
+template <typename T, int R>
+__global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const T* __restrict__ val, T shift,
+                                                     const T* __restrict__ X, T* __restrict__ Y) {
+  const int i = blockIdx.x * kTPB + threadIdx.x;
+  if (i >= n) return;
+  T acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = T(0);
+  const int k0 = rp[i], k1 = rp[i + 1];
+  for (int k = k0; k < k1; ++k) {
+    const int col = ci[k];
+    const T a = val[k];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] += a * X[(size_t)col * R + q];
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = acc[q] + shift * X[(size_t)i * R + q];
+}
+
+template <typename T>
+int tick_impl(hipStream_t st, const Batch& b) {
+  const dim3 rg(b.rowgrid), tb(kTPB), sg(b.nsys);
+  const dim3 redg(b.nsys, (b.maxP + kTPB - 1) / kTPB);
+  const double fl64 = 1e-24, fl32 = 1e-10;
+  hipLaunchKernelGGL(k_spmm_arn<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL(k_gram_vu<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 1);
+  hipLaunchKernelGGL(k_update<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0);
+  hipLaunchKernelGGL(k_gram_vu<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
+  hipLaunchKernelGGL(k_update<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 1);
+  hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
+  hipLaunchKernelGGL(k_scale<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0);
+  hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
+  hipLaunchKernelGGL(k_scale<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 1);
+  hipLaunchKernelGGL(k_lsq, sg, tb, 0, st, b.d, b.ctl);
+  hipLaunchKernelGGL(k_zupdate<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL(k_resid, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+}  // namespace
+
+int launch_tick(hipStream_t st, const Batch& b) {
+  if (b.precision == LRADI_FP64) return tick_impl<double>(st, b);
+  return tick_impl<float>(st, b);
+}
+
+int launch_summary(hipStream_t st, const Batch& b, int* host_slot) {
+  hipLaunchKernelGGL(k_summary, dim3(1), dim3(kTPB), 0, st, b.ctl, b.nsys, host_slot);
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+int launch_spmm_plain(hipStream_t st, int n, int r, int precision, const int* rowptr,
+                      const int* colind, const void* val, double shift, const void* X, void* Y) {
+  if (n <= 0) return LRADI_OK;
+  const dim3 g((n + kTPB - 1) / kTPB), tb(kTPB);
+  if (precision == LRADI_FP64) {
+    LRADI_DISPATCH_R(r, hipLaunchKernelGGL((k_spmm_plain<double, RR>), g, tb, 0, st, n, rowptr,
+                                           colind, static_cast<const double*>(val), shift,
+                                           static_cast<const double*>(X), static_cast<double*>(Y)));
+  } else {
+    LRADI_DISPATCH_R(r, hipLaunchKernelGGL((k_spmm_plain<float, RR>), g, tb, 0, st, n, rowptr,
+                                           colind, static_cast<const float*>(val), (float)shift,
+                                           static_cast<const float*>(X), static_cast<float*>(Y)));
+  }
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+}  // namespace lradi

@@ -1,0 +1,290 @@
+"""Thin ctypes binding of liblradi.so (include/lradi.h).
+
+Only argument marshalling lives here: every step of the method runs in the
+HIP library.  Dense arguments are torch tensors on the GPU (FP64, row-major
+n x r); sparse matrices are host CSR triples (numpy) that the library copies
+to the device.  Importing this module loads the library and raises if it has
+not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblradi.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENAN, EBREAKDOWN = 0, -1, -2, -3, -4, -5
+WNOCONV, WINNER = 1, 2
+SEL_RELATIVE, SEL_FIXED, SEL_MID, SEL_TIGHT_A, SEL_TIGHT_B = 0, 1, 2, 3, 4
+FP64, FP32_INNER = 0, 1
+HIST_COLS = 16
+HIST_NAMES = ["k", "res_before", "deltaA", "deltaB", "rA", "rB", "stepsA", "stepsB", "u", "v",
+              "norm_w", "norm_t", "norm_z", "norm_y", "gamma", "res_after"]
+
+SELECTIONS = {"relative": SEL_RELATIVE, "fixed": SEL_FIXED, "mid": SEL_MID,
+              "tightA": SEL_TIGHT_A, "tightB": SEL_TIGHT_B}
+
+
+class LradiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lradi status {status}: {msg}")
+        self.status = status
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int32), ("ncols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("eps", ctypes.c_double),
+                ("delta_min", ctypes.c_double), ("delta_max", ctypes.c_double),
+                ("xi", ctypes.c_double), ("delta_fixed", ctypes.c_double),
+                ("rho", ctypes.c_double), ("fp32_floor", ctypes.c_double),
+                ("kmax", ctypes.c_int32), ("selection", ctypes.c_int32),
+                ("backlook", ctypes.c_int32), ("paper_abs", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_inner", ctypes.c_int32), ("rescale", ctypes.c_int32),
+                ("b_is_transposed", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class InnerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("cycles", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("rnorm", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2312_02891_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "lradi_default_opts": (None, [P(Opts)]),
+        "lradi_strerror": (ctypes.c_char_p, [i32]),
+        "lradi_last_error": (ctypes.c_char_p, []),
+        "lradi_create": (i32, [P(vp), i32, vp]),
+        "lradi_destroy": (i32, [vp]),
+        "lradi_convdiff_size": (i32, [i32, i32, P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "lradi_gen_convdiff": (i32, [i32, i32, P(dbl), vp, vp, vp]),
+        "lradi_spmm": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32]),
+        "lradi_shifted_solve": (i32, [vp, i32, P(P(Csr)), P(dbl), P(vp), P(vp), P(i32), P(dbl),
+                                      P(Opts), P(InnerStats)]),
+        "lradi_solve": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32, P(Opts),
+                              P(vp)]),
+        "lradi_result_info": (i32, [vp, P(i32), P(i32), P(dbl), P(dbl)]),
+        "lradi_result_factors": (i32, [vp, P(vp), P(vp), P(vp), P(i32), P(i32), P(i32)]),
+        "lradi_result_copy": (i32, [vp, vp, vp, vp]),
+        "lradi_result_history": (i32, [vp, vp, i32, P(i32)]),
+        "lradi_result_time": (i32, [vp, P(dbl)]),
+        "lradi_result_free": (None, [vp]),
+        "lradi_residual": (i32, [vp, P(Csr), P(Csr), i32, vp, vp, i32, vp, P(dbl), vp, i32,
+                                 P(dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status, allow_warn=True):
+    if status < 0 or (status > 0 and not allow_warn):
+        raise LradiError(status, "%s: %s" % (_lib.lradi_strerror(status).decode(),
+                                             _lib.lradi_last_error().decode()))
+    return status
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    _lib.lradi_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "selection" and isinstance(v, str):
+            v = SELECTIONS[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": FP64, "fp32": FP32_INNER, "fp32-inner": FP32_INNER}[v]
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class HostCsr:
+    """Host CSR triple kept alive while the library reads it."""
+
+    def __init__(self, rowptr, colind, val):
+        self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        self.colind = np.ascontiguousarray(colind, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64)
+        self.n = len(self.rowptr) - 1
+        self.c = Csr(self.n, self.n, len(self.colind), self.rowptr.ctypes.data,
+                     self.colind.ctypes.data, self.val.ctypes.data, 0)
+
+    @property
+    def nnz(self):
+        return len(self.colind)
+
+
+def convdiff(dim: int, N: int, omega: Sequence[float]) -> HostCsr:
+    """A = -L_h of the upwind convection-diffusion operator (library generator)."""
+    n = ctypes.c_int64()
+    nnz = ctypes.c_int64()
+    _check(_lib.lradi_convdiff_size(dim, N, ctypes.byref(n), ctypes.byref(nnz)))
+    rp = np.empty(n.value + 1, dtype=np.int32)
+    ci = np.empty(nnz.value, dtype=np.int32)
+    v = np.empty(nnz.value, dtype=np.float64)
+    om = (ctypes.c_double * dim)(*[float(w) for w in omega])
+    _check(_lib.lradi_gen_convdiff(dim, N, om, rp.ctypes.data, ci.ctypes.data, v.ctypes.data),
+           allow_warn=False)
+    return HostCsr(rp, ci, v)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Result:
+    def __init__(self, handle, status):
+        self.h = ctypes.c_void_p(handle)
+        self.status = status
+        k, st = ctypes.c_int(), ctypes.c_int()
+        rel, nfg = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.lradi_result_info(self.h, ctypes.byref(k), ctypes.byref(st), ctypes.byref(rel),
+                                      ctypes.byref(nfg)))
+        self.k, self.rel_res, self.norm_fg = k.value, rel.value, nfg.value
+        n, m, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        zp, dp, yp = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib.lradi_result_factors(self.h, ctypes.byref(zp), ctypes.byref(dp),
+                                         ctypes.byref(yp), ctypes.byref(n), ctypes.byref(m),
+                                         ctypes.byref(r)))
+        self.n, self.m, self.r = n.value, m.value, r.value
+        self.Zptr, self.Yptr = zp.value, yp.value
+        sec = ctypes.c_double()
+        _check(_lib.lradi_result_time(self.h, ctypes.byref(sec)))
+        self.seconds = sec.value
+
+    def factors(self):
+        """(Z n x kr, d kr, Y m x kr) as host numpy arrays (blocks side by side)."""
+        k, n, m, r = self.k, self.n, self.m, self.r
+        Z = np.empty((k, n, r))
+        Y = np.empty((k, m, r))
+        D = np.empty(max(k, 1))
+        _check(_lib.lradi_result_copy(self.h, Z.ctypes.data, D.ctypes.data, Y.ctypes.data))
+        Zc = np.concatenate([Z[i] for i in range(k)], axis=1) if k else np.zeros((n, 0))
+        Yc = np.concatenate([Y[i] for i in range(k)], axis=1) if k else np.zeros((m, 0))
+        d = np.repeat(D[:k], r)
+        return Zc, d, Yc
+
+    def gammas(self):
+        _, d, _ = self.factors()
+        return d[:: self.r] if self.r else d
+
+    def history(self):
+        rows = np.zeros((max(self.k, 1), HIST_COLS))
+        nr = ctypes.c_int()
+        _check(_lib.lradi_result_history(self.h, rows.ctypes.data, self.k, ctypes.byref(nr)))
+        return rows[: nr.value]
+
+    def device_factors(self):
+        """Torch views (k, n, r) / (k, m, r) of the library-owned device factors;
+        valid while this Result lives."""
+        torch = _torch()
+        return self.Zptr, self.Yptr
+
+    def __del__(self):
+        try:
+            if self.h:
+                _lib.lradi_result_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Context:
+    """lradi_ctx bound to one device.  Calls synchronise torch's stream first
+    and return after the library's own stream finished."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.lradi_create(ctypes.byref(h), device, None))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            _lib.lradi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync(self):
+        _torch().cuda.synchronize(self.device)
+
+    def spmm(self, A: HostCsr, shift: float, X, precision: int = FP64):
+        """Y = (A + shift I) X; X (n x r) FP64 or FP32 torch tensor on the GPU."""
+        torch = _torch()
+        assert X.is_cuda and X.is_contiguous() and X.dim() == 2
+        prec = FP64 if X.dtype == torch.float64 else FP32_INNER
+        Y = torch.empty_like(X)
+        self._sync()
+        _check(_lib.lradi_spmm(self.h, ctypes.byref(A.c), float(shift), _ptr(X), _ptr(Y),
+                               X.shape[1], prec), allow_warn=False)
+        return Y
+
+    def shifted_solve(self, mats: List[HostCsr], shifts, Ws, deltas, opts: Optional[Opts] = None):
+        """Batched (A_s + shift_s I) Z_s = W_s to ||R_s||_2 <= delta_s; returns (Zs, stats)."""
+        torch = _torch()
+        ns = len(mats)
+        Zs = [torch.zeros_like(W) for W in Ws]
+        Aarr = (ctypes.POINTER(Csr) * ns)(*[ctypes.pointer(M.c) for M in mats])
+        sh = (ctypes.c_double * ns)(*[float(s) for s in shifts])
+        Wp = (ctypes.c_void_p * ns)(*[W.data_ptr() for W in Ws])
+        Zp = (ctypes.c_void_p * ns)(*[Z.data_ptr() for Z in Zs])
+        rr = (ctypes.c_int * ns)(*[W.shape[1] for W in Ws])
+        dl = (ctypes.c_double * ns)(*[float(d) for d in deltas])
+        stats = (InnerStats * ns)()
+        self._sync()
+        st = _check(_lib.lradi_shifted_solve(self.h, ns, Aarr, sh, Wp, Zp, rr, dl,
+                                             ctypes.byref(opts) if opts is not None else None,
+                                             stats))
+        return Zs, [dict(steps=s.steps, cycles=s.cycles, status=s.status, breakdowns=s.pad,
+                         rnorm=s.rnorm) for s in stats], st
+
+    def solve(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, opts: Optional[Opts] = None):
+        """Algorithm 1 on A X + X B = -f g^T (f, g: FP64 CUDA tensors); B is
+        B itself unless opts.b_is_transposed."""
+        assert f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()
+        r = f.shape[1]
+        sA = np.ascontiguousarray(shiftsA, dtype=np.float64)
+        sB = np.ascontiguousarray(shiftsB, dtype=np.float64)
+        h = ctypes.c_void_p()
+        self._sync()
+        st = _check(_lib.lradi_solve(self.h, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(f), _ptr(g),
+                                     r, sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(sA),
+                                     ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(h)))
+        return Result(h.value, st)

@@ -1,0 +1,130 @@
+"""GPU parity of the full inexact LR-ADI solve (Algorithm 1) against the
+oracle: same steps, same X within the stated tolerance, true residual below
+the target, and the controller's recorded tolerances equal to the oracle's
+formulas on the recorded inputs."""
+import numpy as np
+import pytest
+
+from oracle import controller as OC
+from oracle import fadi as OF
+from oracle.convdiff import convdiff_matrix
+from paper_2312_02891_amd import workloads as WL
+
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2312_02891_amd import lradi
+    return lradi
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def setup(P, L, nshifts=None):
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
+    A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
+    B = convdiff_matrix(P.B.dim, P.B.N, P.B.omega)
+    f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+    pA, pB = WL.wachspress_shifts(P.A, P.B, nshifts or P.nshifts)
+    return HA, HB, A, B, f, g, pA, pB
+
+
+def compare(L, res, A, B, f, g, pA, pB, tol, xtol=1e-6, kslack=0):
+    Zg, dg, Yg = res.factors()
+    ora = OF.fadi(A, B, f, g, pA, pB, tol=tol, kmax=200, kfixed=res.k)
+    fs, gs = OF.rescale_rhs(f, g)
+    xerr = OF.lowrank_diff_fro(Zg, dg, Yg, ora.Z, ora.D(), ora.Y) / OF.lowrank_fro(ora.Z, ora.D(), ora.Y)
+    true = OF.lowrank_residual_norm(A, B, fs, gs, Zg, dg, Yg) / ora.norm_fg
+    full = OF.fadi(A, B, f, g, pA, pB, tol=tol, kmax=200)
+    say("  k gpu", res.k, "k oracle", full.k, "X err", xerr, "true res", true, "comp", res.rel_res)
+    assert abs(res.k - full.k) <= kslack
+    assert xerr <= xtol
+    assert true <= tol
+    assert res.norm_fg == pytest.approx(ora.norm_fg, rel=1e-12)
+    return xerr, true, ora
+
+
+def test_config1_exact_tolerance_fp64(L, ctx):
+    """Config 1 (n = m = 400, r = 1) with inner solves to 1e-12 relative: the
+    run reproduces the oracle's direct-solve ADI step for step."""
+    say("adi config 1")
+    P = WL.C1
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    o = L.default_opts(selection="relative", rho=1e-12, tol=P.tol)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    assert res.status == L.OK
+    xerr, true, ora = compare(L, res, A, B, f, g, pA, pB, P.tol, xtol=1e-9)
+    hist = res.history()
+    assert np.allclose(hist[:, 15], ora.res_hist, rtol=1e-7)
+    assert np.allclose(hist[:, 14], ora.gammas, rtol=1e-15)
+
+
+@pytest.mark.parametrize("sel", ["mid", "tightA", "tightB", "fixed"])
+def test_small_problem_dynamic_tolerances(L, ctx, sel):
+    """Relaxed (Sec. 3.3) and fixed inner tolerances on a 2-D problem with
+    r = 3: converged, true residual below tau, X within 1e-6 of the exact
+    ADI iterate at the same step."""
+    say("adi small", sel)
+    P = WL.SMALL_2D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    o = L.default_opts(selection=sel, tol=P.tol)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    assert res.status in (L.OK,)
+    compare(L, res, A, B, f, g, pA, pB, P.tol, kslack=1)
+    hist = res.history()
+    # the controller's recorded tolerances follow the oracle's formulas
+    u = v = 0.0
+    eps = P.tol * res.norm_fg
+    for row in hist:
+        k = int(row[0])
+        dA, dB = OC.tolerances(sel, k, row[10], row[11], u, v, eps)
+        assert row[2] == pytest.approx(dA, rel=1e-12)
+        assert row[3] == pytest.approx(dB, rel=1e-12)
+        assert row[4] <= row[2] * (1 + 1e-12) and row[5] <= row[3] * (1 + 1e-12)
+        u, v = OC.update_gap(u, v, row[14], row[12], row[13], row[4], row[5])
+        assert row[8] == pytest.approx(u, rel=1e-12) and row[9] == pytest.approx(v, rel=1e-12)
+
+
+def test_small_3d_fp32_inner(L, ctx):
+    """FP32 inner Krylov work with FP64 refinement and outer factors."""
+    say("adi small 3d fp32")
+    P = WL.SMALL_3D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    o = L.default_opts(precision="fp32", tol=P.tol)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    assert res.status == L.OK
+    compare(L, res, A, B, f, g, pA, pB, P.tol, kslack=1)
+
+
+def test_b_given_transposed_is_identical(L, ctx):
+    """Passing B^T (the generator with -omega) with b_is_transposed gives the
+    same factors bit for bit as passing B."""
+    say("adi b transposed")
+    P = WL.SMALL_2D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    HBt = L.convdiff(P.B.dim, P.B.N, tuple(-w for w in P.B.omega))
+    o = L.default_opts(tol=P.tol)
+    r1 = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    o2 = L.default_opts(tol=P.tol, b_is_transposed=1)
+    r2 = ctx.solve(HA, HBt, to_dev(f), to_dev(g), pA, pB, o2)
+    Z1, d1, Y1 = r1.factors()
+    Z2, d2, Y2 = r2.factors()
+    assert r1.k == r2.k and np.array_equal(Z1, Z2) and np.array_equal(Y1, Y2)
+
+
+def test_kmax_cap_reports_no_convergence(L, ctx):
+    say("adi kmax cap")
+    P = WL.SMALL_2D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    o = L.default_opts(tol=P.tol, kmax=3)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    assert res.status == L.WNOCONV and res.k == 3
