@@ -60,6 +60,11 @@ class InnerStats(ctypes.Structure):
 
 
 def _load():
+    # torch must be loaded first: its bundled HIP runtime (soname
+    # libamdhip64.so.7) then satisfies the library's dependency, so the
+    # process holds a single HIP/HSA runtime.  Loading the library first
+    # would bring in a second runtime that cannot open the device.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2312_02891_amd.build` (no CPU fallback exists)")
