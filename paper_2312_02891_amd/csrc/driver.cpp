@@ -335,6 +335,9 @@ int build_batch(lradi_ctx* ctx, const std::vector<SysSpec>& sys, InnerBatch& ib)
   ib.b.rowgrid = (int)ib.hmap.size();
   ib.b.maxP = maxP;
   ib.b.precision = prec;
+  ib.b.rfix = sys[0].r;
+  for (int s = 1; s < nsys; ++s)
+    if (sys[s].r != sys[0].r) ib.b.rfix = 0;
   return LRADI_OK;
 }
 

@@ -134,6 +134,7 @@ struct Batch {
   int rowgrid;
   int maxP;            // max over systems of (m+1) r^2
   int precision;       // LRADI_FP64 / LRADI_FP32_INNER
+  int rfix;            // common r of all systems, or 0 when they differ
 };
 // One scheduling tick: a block Arnoldi step (or the rebuild of V_0) for every
 // system in PH_ARNOLDI / PH_RESTART, then the end-of-cycle work for every

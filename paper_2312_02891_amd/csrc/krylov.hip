@@ -40,6 +40,16 @@ namespace {
     default: break;                        \
   }
 
+// RF > 0: the kernel is instantiated for that block width only (batches whose
+// systems share r); RF == 0: dispatch on the system's r at run time.
+#define LRADI_RSEL(RF, rv, ...)                               \
+  if constexpr ((RF) > 0) {                                   \
+    constexpr int RR = (RF);                                  \
+    __VA_ARGS__;                                              \
+  } else {                                                    \
+    LRADI_DISPATCH_R(rv, __VA_ARGS__);                        \
+  }
+
 struct RowCtx {
   int s, w, row0, row1;
 };
@@ -118,7 +128,7 @@ __device__ inline void spmm_rows(const SysDesc& D, const RowCtx& c, T shift, con
   }
 }
 
-template <typename T>
+template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
                                                    const SysCtl* __restrict__ ctl,
                                                    const int2* __restrict__ rowmap) {
@@ -134,19 +144,27 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
   if (ph != PH_ARNOLDI) return;
   const T* Vj = static_cast<const T*>(D.V) + (size_t)ctl[c.s].j * D.n * D.r;
   const T sh = (T)ctl[c.s].shift;
-  LRADI_DISPATCH_R(D.r, spmm_rows<T, RR>(D, c, sh, Vj, U));
+  LRADI_RSEL(RF, D.r, spmm_rows<T, RR>(D, c, sh, Vj, U));
 }
 
 // ---------------------------------------------------------------------------
 // 2. partial Gram  part[w][b][a][q] = sum_{i in chunk} V_b[i][a] U[i][q],
-//    b = 0..j  (PH_ARNOLDI).  Lane layout: lane = (row offset, a).
+//    b = 0..j  (PH_ARNOLDI).  Lane layout: lane = (row offset, a) with the
+//    column index padded to RP = next power of two >= R, so the sum over the
+//    rows of a wavefront is an xor-shuffle butterfly over the high lane bits.
+template <int R>
+struct Pad {
+  static constexpr int v = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : 8;
+};
+
 template <typename T, int R>
 __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, double* lds) {
-  constexpr int RPW = 64 / R;
-  constexpr int G = (16 / R) > 0 ? (16 / R) : 1;
+  constexpr int RP = Pad<R>::v;
+  constexpr int RPW = 64 / RP;                     // rows per wavefront pass
+  constexpr int G = (16 / R) > 0 ? (16 / R) : 1;   // basis blocks per pass
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ro = lane / R, a = lane - ro * R;
-  const bool act = ro < RPW;
+  const int ro = lane / RP, a = lane - ro * RP;
+  const bool act = a < R;
   const T* __restrict__ V = static_cast<const T*>(D.V);
   const T* __restrict__ U = static_cast<const T*>(D.U);
   const size_t bs = (size_t)D.n * R;
@@ -173,59 +191,87 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, d
         }
       }
     }
+    // butterfly over the row offset (lane bits >= log2 RP)
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[threadIdx.x * 16 + g * R + q] = acc[g][q];
+      for (int q = 0; q < R; ++q) {
+        double x = acc[g][q];
+#pragma unroll
+        for (int off = RP; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
+        acc[g][q] = x;
+      }
+    if (lane < R) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int q = 0; q < R; ++q) lds[((wave * G + g) * R + lane) * R + q] = acc[g][q];
+    }
     __syncthreads();
     const int nout = gc * R * R;
     for (int o = threadIdx.x; o < nout; o += kTPB) {
-      const int g = o / (R * R), rem = o - g * R * R, aa = rem / R, q = rem - aa * R;
-      double sum = 0.0;
-      for (int wv = 0; wv < 4; ++wv)
-        for (int rr = 0; rr < RPW; ++rr) sum += lds[(wv * 64 + rr * R + aa) * 16 + g * R + q];
-      out[(size_t)(b0 + g) * R * R + aa * R + q] = sum;
+      const int g = o / (R * R), rem = o - g * R * R;
+      const double sum = ((lds[(0 * G + g) * R * R + rem] + lds[(1 * G + g) * R * R + rem]) +
+                          lds[(2 * G + g) * R * R + rem]) + lds[(3 * G + g) * R * R + rem];
+      out[(size_t)(b0 + g) * R * R + rem] = sum;
     }
     __syncthreads();
   }
 }
 
-template <typename T>
+template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_gram_vu(const SysDesc* __restrict__ d,
                                                   const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap) {
-  __shared__ double lds[kTPB * 16];
+  __shared__ double lds[4 * 16 * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI) return;
   const int nb = ctl[c.s].j + 1;
-  LRADI_DISPATCH_R(D.r, gram_vu_rows<T, RR>(D, c, nb, lds));
+  if constexpr (RF > 0) {
+    gram_vu_rows<T, RF>(D, c, nb, lds);
+  } else {
+    LRADI_DISPATCH_R(D.r, gram_vu_rows<T, RR>(D, c, nb, lds));
+  }
 }
 
 // 3. red = sum_w part[w]; hacc = red (first pass) or hacc += red (second).
+//    A workgroup covers 16 coefficients; 16 thread groups split the sum over
+//    the workgroups of the Gram kernel and are combined in a fixed order.
+constexpr int kRedOut = 16;
 __global__ __launch_bounds__(kTPB) void k_reduce_vu(const SysDesc* __restrict__ d,
                                                     const SysCtl* __restrict__ ctl, int first) {
+  __shared__ double red[kTPB];
   const int s = blockIdx.x;
   const SysDesc& D = d[s];
   if (ctl[s].phase != PH_ARNOLDI) return;
   const int P = (ctl[s].j + 1) * D.r * D.r;
-  const int p = blockIdx.y * kTPB + threadIdx.x;
-  if (p >= P) return;
-  double sum = 0.0;
-  for (int w = 0; w < D.nwg; ++w) sum += D.part[(size_t)w * D.pstride + p];
-  D.red[p] = sum;
-  if (first)
-    D.hacc[p] = sum;
-  else
-    D.hacc[p] += sum;
+  const int p0 = blockIdx.y * kRedOut;
+  if (p0 >= P) return;
+  const int o = threadIdx.x % kRedOut, g = threadIdx.x / kRedOut;
+  const int p = p0 + o;
+  double acc = 0.0;
+  if (p < P)
+    for (int w = g; w < D.nwg; w += kTPB / kRedOut) acc += D.part[(size_t)w * D.pstride + p];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < kRedOut && p < P) {
+    double sum = 0.0;
+    for (int q = 0; q < kTPB / kRedOut; ++q) sum += red[q * kRedOut + threadIdx.x];
+    D.red[p] = sum;
+    if (first)
+      D.hacc[p] = sum;
+    else
+      D.hacc[p] += sum;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// 4./7. U -= sum_b V_b red_b  (PH_ARNOLDI); with gram = 1 also the partial
-//       U^T U of the result into partS (PH_ARNOLDI and PH_RESTART).
-template <typename T, int R>
+// 4./7. U -= sum_b V_b red_b  (PH_ARNOLDI); the second pass also forms the
+//       partial U^T U of the result into partS (PH_ARNOLDI and PH_RESTART).
+template <typename T, int R, bool GRAM>
 __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bool do_update,
-                                   bool gram, double* hl, double* lds) {
+                                   double* hl, double* lds) {
   if (do_update) {
     for (int e = threadIdx.x; e < nb * R * R; e += kTPB) hl[e] = D.red[e];
     __syncthreads();
@@ -233,9 +279,11 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
   const T* __restrict__ V = static_cast<const T*>(D.V);
   T* __restrict__ U = static_cast<T*>(D.U);
   const size_t bs = (size_t)D.n * R;
-  double g2[R * R];
+  double g2[GRAM ? R * R : 1];
+  if constexpr (GRAM) {
 #pragma unroll
-  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+    for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  }
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     T u[R];
 #pragma unroll
@@ -260,41 +308,59 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
         U[(size_t)i * R + q] = u[q];
       }
     }
-    if (gram) {
+    if constexpr (GRAM) {
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
         for (int q = 0; q < R; ++q) g2[a * R + q] += (double)u[a] * (double)u[q];
     }
   }
-  if (gram) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+  if constexpr (GRAM) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
 }
 
-template <typename T>
+template <typename T, int RF, bool SECOND>
 __global__ __launch_bounds__(kTPB) void k_update(const SysDesc* __restrict__ d,
                                                  const SysCtl* __restrict__ ctl,
-                                                 const int2* __restrict__ rowmap, int second) {
+                                                 const int2* __restrict__ rowmap) {
   __shared__ double hl[(kMaxM + 1) * kMaxR * kMaxR];
   __shared__ double lds[4 * kMaxR * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   const int ph = ctl[c.s].phase;
-  bool do_update, gram;
+  bool do_update;
   if (ph == PH_ARNOLDI) {
     do_update = true;
-    gram = second != 0;
-  } else if (ph == PH_RESTART && second) {
+  } else if (ph == PH_RESTART && SECOND) {
     do_update = false;
-    gram = true;
   } else {
     return;
   }
   const int nb = ctl[c.s].j + 1;
-  LRADI_DISPATCH_R(D.r, update_rows<T, RR>(D, c, nb, do_update, gram, hl, lds));
+  LRADI_RSEL(RF, D.r, update_rows<T, RR, SECOND>(D, c, nb, do_update, hl, lds));
 }
 
 // ---------------------------------------------------------------------------
 // 8./10. Cholesky factor of the reduced U^T U (PH_ARNOLDI / PH_RESTART).
+template <int R>
+__device__ inline void chol_body(const SysDesc& D, SysCtl& C, int slot, double fl, const double* G) {
+  double S[R * R], Si[R * R];
+  const int reg = chol_upper_reg_t<R>(G, S, fl);
+  if (reg < 0) {
+    C.status = IS_NAN;
+    C.phase = PH_FINISHED;
+    return;
+  }
+  if (reg > 0) C.breakdowns += 1;
+  tri_inv_upper_t<R>(S, Si);
+  double* dst = D.sm + (slot == 0 ? SM_S1 : SM_S2);
+  double* dsti = D.sm + (slot == 0 ? SM_S1I : SM_S2I);
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) {
+    dst[e] = S[e];
+    dsti[e] = Si[e];
+  }
+}
+
 __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl,
                                                int slot, double rel_floor64, double rel_floor32) {
   __shared__ double red_lds[kTPB];
@@ -306,37 +372,25 @@ __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, Sy
   const int R = D.r;
   reduce_partS(D, R * R, red_lds, G);
   if (threadIdx.x == 0) {
-    double S[64], Si[64];
     const double fl = (D.precision == LRADI_FP64) ? rel_floor64 : rel_floor32;
-    const int reg = chol_upper_reg(G, S, R, fl);
-    if (reg < 0) {
-      ctl[s].status = IS_NAN;
-      ctl[s].phase = PH_FINISHED;
-    } else {
-      if (reg > 0) ctl[s].breakdowns += 1;
-      tri_inv_upper(S, Si, R);
-      double* dst = D.sm + (slot == 0 ? SM_S1 : SM_S2);
-      double* dsti = D.sm + (slot == 0 ? SM_S1I : SM_S2I);
-      for (int e = 0; e < R * R; ++e) {
-        dst[e] = S[e];
-        dsti[e] = Si[e];
-      }
-    }
+    LRADI_DISPATCH_R(R, chol_body<RR>(D, ctl[s], slot, fl, G));
   }
 }
 
 // 9./11. pass 0: U = U S1^{-1} in place and partial U^T U;
 //        pass 1: V_{j+1} (PH_ARNOLDI) or V_0 (PH_RESTART) = U S2^{-1}.
-template <typename T, int R>
+template <typename T, int R, bool GRAM>
 __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const double* Si, T* dst,
-                                  bool gram, double* lds) {
+                                  double* lds) {
   double sl[R * R];
 #pragma unroll
   for (int e = 0; e < R * R; ++e) sl[e] = Si[e];
   T* __restrict__ U = static_cast<T*>(D.U);
-  double g2[R * R];
+  double g2[GRAM ? R * R : 1];
+  if constexpr (GRAM) {
 #pragma unroll
-  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+    for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  }
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     double u[R], o[R];
 #pragma unroll
@@ -354,20 +408,20 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
       ot[q] = (T)o[q];
       dst[(size_t)i * R + q] = ot[q];
     }
-    if (gram) {
+    if constexpr (GRAM) {
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
         for (int q = 0; q < R; ++q) g2[a * R + q] += (double)ot[a] * (double)ot[q];
     }
   }
-  if (gram) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+  if constexpr (GRAM) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
 }
 
-template <typename T>
+template <typename T, int RF, int PASS>
 __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
                                                 const SysCtl* __restrict__ ctl,
-                                                const int2* __restrict__ rowmap, int pass) {
+                                                const int2* __restrict__ rowmap) {
   __shared__ double lds[4 * kMaxR * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
@@ -375,7 +429,7 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
   T* dst;
   const double* Si;
-  if (pass == 0) {
+  if (PASS == 0) {
     dst = static_cast<T*>(D.U);
     Si = D.sm + SM_S1I;
   } else {
@@ -383,7 +437,7 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
     dst = static_cast<T*>(D.V) + (size_t)tgt * D.n * D.r;
     Si = D.sm + SM_S2I;
   }
-  LRADI_DISPATCH_R(D.r, scale_rows<T, RR>(D, c, Si, dst, pass == 0, lds));
+  LRADI_RSEL(RF, D.r, scale_rows<T, RR, PASS == 0>(D, c, Si, dst, lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -394,24 +448,73 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
 //   factor its last 2r x r part (Householder, Q_j), rotate the right-hand
 //   side, and take the residual estimate ||G_{j+1}||_F.  At the end of a
 //   cycle solve the triangular system for y.
-__global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
-  __shared__ double h[(kMaxM + 1) * kMaxR * kMaxR];
-  __shared__ double Sf[64];
-  __shared__ double M[16 * 8];
-  __shared__ double Qj[16 * 16];
-  __shared__ int done_s;
-  const int s = blockIdx.x;
-  const SysDesc& D = d[s];
-  SysCtl& C = ctl[s];
-  const int ph = C.phase;
-  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
-  const int R = D.r, m = D.m, t = threadIdx.x;
-  const int RR2 = R * R;
+
+// Sum over the 16 lanes of a lane group (xor butterfly).
+__device__ inline double sum16(double x) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off, 16);
+  return x;
+}
+
+// Householder QR of the 2R x R block hb (LDS, row-major, overwritten with
+// [R_jj; 0]); Q (LDS, 2R x 2R row-major) receives the orthogonal factor.
+// Run by wavefront 0; lane i < 2R owns row i of the block and of Q.
+template <int R>
+__device__ inline void house_wave(double* hb, double* Q) {
+  constexpr int M2 = 2 * R;
+  const int lane = threadIdx.x;
+  const bool own = lane < M2;
+  double mr[R], qr[M2];
+#pragma unroll
+  for (int c = 0; c < R; ++c) mr[c] = own ? hb[lane * R + c] : 0.0;
+#pragma unroll
+  for (int k = 0; k < M2; ++k) qr[k] = (own && k == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const double x = (own && lane >= c) ? mr[c] : 0.0;
+    const double nx2 = sum16(x * x);
+    if (nx2 == 0.0) continue;
+    const double x0 = __shfl(x, c, 64);
+    const double alpha = (x0 >= 0.0) ? -sqrt(nx2) : sqrt(nx2);
+    const double v = x - ((lane == c) ? alpha : 0.0);
+    const double vv = sum16(v * v);
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+#pragma unroll
+    for (int jc = c + 1; jc < R; ++jc) {
+      const double dd = sum16(v * mr[jc]);
+      mr[jc] -= beta * dd * v;
+    }
+    if (own && lane == c) mr[c] = alpha;
+    else if (own && lane > c) mr[c] = 0.0;
+    double vk[M2];
+#pragma unroll
+    for (int k = 0; k < M2; ++k) vk[k] = __shfl(v, k, 64);
+    double dq = 0.0;
+#pragma unroll
+    for (int k = 0; k < M2; ++k) dq += qr[k] * vk[k];
+#pragma unroll
+    for (int k = 0; k < M2; ++k) qr[k] -= beta * dq * vk[k];
+  }
+  if (own) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) hb[lane * R + c] = mr[c];
+#pragma unroll
+    for (int k = 0; k < M2; ++k) Q[lane * M2 + k] = qr[k];
+  }
+}
+
+template <int R>
+__device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, double* Sf,
+                                double* Qj, int* done_s) {
+  constexpr int RR2 = R * R, twoR = 2 * R;
+  const int m = D.m, t = threadIdx.x;
   const double* S1 = D.sm + SM_S1;
   const double* S2 = D.sm + SM_S2;
   if (t < RR2) {
     const int a = t / R, q = t - a * R;
     double v = 0.0;
+#pragma unroll
     for (int k = 0; k < R; ++k) v += S2[a * R + k] * S1[k * R + q];
     Sf[t] = v;
   }
@@ -428,49 +531,49 @@ __global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, Sys
   }
   const int j = C.j;
   const int ldR = m * R;
-  // assemble column block j, (j+2) r rows x r, row-major
   for (int e = t; e < (j + 2) * RR2; e += kTPB) {
     const int b = e / RR2;
     h[e] = (b <= j) ? D.hacc[e] : Sf[e - b * RR2];
   }
+  // apply Q_b^T to rows [b r, b r + 2r); the column of Q_b a thread needs is
+  // prefetched into registers one step ahead
+  const bool act = t < twoR * R;
+  const int a = act ? t / R : 0, q = act ? t - (t / R) * R : 0;
+  double qa[twoR], qn[twoR];
+  if (act && j > 0) {
+#pragma unroll
+    for (int k = 0; k < twoR; ++k) qa[k] = D.Qs[k * twoR + a];
+  }
   __syncthreads();
-  // apply Q_b^T to rows [b r, b r + 2r)
   for (int b = 0; b < j; ++b) {
-    const double* Q = D.Qs + (size_t)b * 4 * RR2;
-    const int twoR = 2 * R;
+    if (act && b + 1 < j) {
+#pragma unroll
+      for (int k = 0; k < twoR; ++k) qn[k] = D.Qs[(size_t)(b + 1) * 4 * RR2 + k * twoR + a];
+    }
     double nv = 0.0;
-    int a = 0, q = 0;
-    const bool act = t < twoR * R;
     if (act) {
-      a = t / R;
-      q = t - a * R;
-      for (int k = 0; k < twoR; ++k) nv += Q[k * twoR + a] * h[(b * R + k) * R + q];
+#pragma unroll
+      for (int k = 0; k < twoR; ++k) nv += qa[k] * h[(b * R + k) * R + q];
     }
     __syncthreads();
     if (act) h[(b * R + a) * R + q] = nv;
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < twoR; ++k) qa[k] = qn[k];
   }
   // Householder QR of rows [j r, j r + 2r)
-  for (int e = t; e < 2 * RR2; e += kTPB) M[e] = h[j * RR2 + e];
-  __syncthreads();
-  if (t == 0) householder_2nxn(M, Qj, R);
+  if (t < 64) house_wave<R>(h + j * RR2, Qj);
   __syncthreads();
   for (int e = t; e < 4 * RR2; e += kTPB) D.Qs[(size_t)j * 4 * RR2 + e] = Qj[e];
-  // triangular factor, column block j
   for (int e = t; e < (j + 1) * RR2; e += kTPB) {
-    const int row = e / R, q = e - row * R;
-    const double v = (row < j * R) ? h[row * R + q] : M[(row - j * R) * R + q];
-    D.Rt[(size_t)(j * R + q) * ldR + row] = v;
+    const int row = e / R, qq = e - row * R;
+    D.Rt[(size_t)(j * R + qq) * ldR + row] = h[e];
   }
   // rotate the right-hand side rows [j r, j r + 2r)
   {
-    const int twoR = 2 * R;
     double nv = 0.0;
-    int a = 0, q = 0;
-    const bool act = t < twoR * R;
     if (act) {
-      a = t / R;
-      q = t - a * R;
+#pragma unroll
       for (int k = 0; k < twoR; ++k) nv += Qj[k * twoR + a] * D.Gv[(j * R + k) * R + q];
     }
     __syncthreads();
@@ -479,6 +582,7 @@ __global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, Sys
   __syncthreads();
   if (t == 0) {
     double e2 = 0.0;
+#pragma unroll
     for (int e = 0; e < RR2; ++e) {
       const double g = D.Gv[((j + 1) * R) * R + e];
       e2 += g * g;
@@ -488,39 +592,54 @@ __global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, Sys
     C.ncols = j + 1;
     C.est = est;
     const double thr = fmax(C.delta, D.floor_rel * C.r0);
-    int done = (est <= thr) || (j + 1 >= m) || (C.steps >= D.max_inner) || !(est == est);
-    done_s = done;
+    const int done = (est <= thr) || (j + 1 >= m) || (C.steps >= D.max_inner) || !(est == est);
+    *done_s = done;
     if (!done) C.j = j + 1;
   }
   __syncthreads();
-  if (!done_s) return;
+  if (!*done_s) return;
   // back substitution R_t y = G(0 : (j+1) r), block by block
   const int nc = j + 1;
-  double* g = h;  // reuse
+  double* g = h;
   for (int e = t; e < nc * RR2; e += kTPB) g[e] = D.Gv[e];
   __syncthreads();
   for (int bj = nc - 1; bj >= 0; --bj) {
     if (t < R) {
-      const int q = t;
-      for (int a = R - 1; a >= 0; --a) {
-        const int row = bj * R + a;
-        double v = g[row * R + q];
-        for (int k = a + 1; k < R; ++k) v -= D.Rt[(size_t)(bj * R + k) * ldR + row] * g[(bj * R + k) * R + q];
+      const int qq = t;
+      for (int aa = R - 1; aa >= 0; --aa) {
+        const int row = bj * R + aa;
+        double v = g[row * R + qq];
+        for (int k = aa + 1; k < R; ++k) v -= D.Rt[(size_t)(bj * R + k) * ldR + row] * g[(bj * R + k) * R + qq];
         v /= D.Rt[(size_t)row * ldR + row];
-        g[row * R + q] = v;
+        g[row * R + qq] = v;
       }
     }
     __syncthreads();
     for (int e = t; e < bj * RR2; e += kTPB) {
-      const int row = e / R, q = e - row * R;
+      const int row = e / R, qq = e - row * R;
       double v = g[e];
-      for (int k = 0; k < R; ++k) v -= D.Rt[(size_t)(bj * R + k) * ldR + row] * g[(bj * R + k) * R + q];
+#pragma unroll
+      for (int k = 0; k < R; ++k) v -= D.Rt[(size_t)(bj * R + k) * ldR + row] * g[(bj * R + k) * R + qq];
       g[e] = v;
     }
     __syncthreads();
   }
   for (int e = t; e < nc * RR2; e += kTPB) D.yv[e] = g[e];
   if (t == 0) C.phase = PH_CYCLE_END;
+}
+
+template <int RF>
+__global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
+  __shared__ double h[(kMaxM + 1) * kMaxR * kMaxR];
+  __shared__ double Sf[64];
+  __shared__ double Qj[16 * 16];
+  __shared__ int done_s;
+  const int s = blockIdx.x;
+  const SysDesc& D = d[s];
+  SysCtl& C = ctl[s];
+  const int ph = C.phase;
+  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  LRADI_RSEL(RF, D.r, lsq_body<RR>(D, C, ph, h, Sf, Qj, &done_s));
 }
 
 // ---------------------------------------------------------------------------
@@ -549,7 +668,7 @@ __device__ inline void zupdate_rows(const SysDesc& D, const RowCtx& c, double* Z
   }
 }
 
-template <typename T>
+template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_zupdate(const SysDesc* __restrict__ d,
                                                   const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap) {
@@ -562,7 +681,7 @@ __global__ __launch_bounds__(kTPB) void k_zupdate(const SysDesc* __restrict__ d,
   const int R = D.r;
   for (int e = threadIdx.x; e < nb * R * R; e += kTPB) yl[e] = D.yv[e];
   __syncthreads();
-  LRADI_DISPATCH_R(D.r, zupdate_rows<T, RR>(D, c, ctl[c.s].Z, nb, yl));
+  LRADI_RSEL(RF, D.r, zupdate_rows<T, RR>(D, c, ctl[c.s].Z, nb, yl));
 }
 
 // 14. R = W - (A + s I) Z in FP64 and partial R^T R  (PH_CYCLE_END).
@@ -608,6 +727,7 @@ __device__ inline void resid_rows(const SysDesc& D, const RowCtx& c, double shif
   block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
 }
 
+template <int RF>
 __global__ __launch_bounds__(kTPB) void k_resid(const SysDesc* __restrict__ d,
                                                 const SysCtl* __restrict__ ctl,
                                                 const int2* __restrict__ rowmap) {
@@ -615,7 +735,7 @@ __global__ __launch_bounds__(kTPB) void k_resid(const SysDesc* __restrict__ d,
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_CYCLE_END) return;
-  LRADI_DISPATCH_R(D.r, resid_rows<RR>(D, c, ctl[c.s].shift, ctl[c.s].Z, ctl[c.s].first != 0, lds));
+  LRADI_RSEL(RF, D.r, resid_rows<RR>(D, c, ctl[c.s].shift, ctl[c.s].Z, ctl[c.s].first != 0, lds));
 }
 
 // 15. ||R||_2 from R^T R; finish or restart (PH_CYCLE_END).
@@ -692,35 +812,50 @@ __global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restric
   for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = acc[q] + shift * X[(size_t)i * R + q];
 }
 
-template <typename T>
+template <typename T, int RF>
 int tick_impl(hipStream_t st, const Batch& b) {
   const dim3 rg(b.rowgrid), tb(kTPB), sg(b.nsys);
-  const dim3 redg(b.nsys, (b.maxP + kTPB - 1) / kTPB);
+  const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
-  hipLaunchKernelGGL(k_spmm_arn<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL(k_gram_vu<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_spmm_arn<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 1);
-  hipLaunchKernelGGL(k_update<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0);
-  hipLaunchKernelGGL(k_gram_vu<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
-  hipLaunchKernelGGL(k_update<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 1);
+  hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
-  hipLaunchKernelGGL(k_scale<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0);
+  hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
-  hipLaunchKernelGGL(k_scale<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap, 1);
-  hipLaunchKernelGGL(k_lsq, sg, tb, 0, st, b.d, b.ctl);
-  hipLaunchKernelGGL(k_zupdate<T>, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL(k_resid, rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_lsq<RF>), sg, tb, 0, st, b.d, b.ctl);
+  hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);
   LRADI_HIP(hipGetLastError());
   return LRADI_OK;
 }
 
+template <typename T>
+int tick_dispatch(hipStream_t st, const Batch& b) {
+  switch (b.rfix) {
+    case 1: return tick_impl<T, 1>(st, b);
+    case 2: return tick_impl<T, 2>(st, b);
+    case 3: return tick_impl<T, 3>(st, b);
+    case 4: return tick_impl<T, 4>(st, b);
+    case 5: return tick_impl<T, 5>(st, b);
+    case 6: return tick_impl<T, 6>(st, b);
+    case 7: return tick_impl<T, 7>(st, b);
+    case 8: return tick_impl<T, 8>(st, b);
+    default: return tick_impl<T, 0>(st, b);
+  }
+}
+
 }  // namespace
 
 int launch_tick(hipStream_t st, const Batch& b) {
-  if (b.precision == LRADI_FP64) return tick_impl<double>(st, b);
-  return tick_impl<float>(st, b);
+  if (b.precision == LRADI_FP64) return tick_dispatch<double>(st, b);
+  return tick_dispatch<float>(st, b);
 }
 
 int launch_summary(hipStream_t st, const Batch& b, int* host_slot) {

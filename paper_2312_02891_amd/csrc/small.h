@@ -1,6 +1,8 @@
 // Small dense FP64 kernels on r x r (r <= 8) and 2r x r matrices, run by a
-// single thread.  They are __host__ __device__ so the host self-test can
-// exercise exactly the code the GPU runs.
+// single thread.  Each routine is a template on the dimension so that on the
+// GPU every array is indexed with compile-time constants and lives in
+// registers; the runtime-n wrappers dispatch to the instantiations.  They are
+// __host__ __device__ so the host self-test exercises the code the GPU runs.
 #pragma once
 
 #include <cmath>
@@ -11,194 +13,249 @@
 #define LRADI_HD
 #endif
 
+#define LRADI_UNROLL _Pragma("unroll")
+
 namespace lradi {
 
 // Upper Cholesky factor S of a symmetric positive semidefinite G (row-major
-// n x n): G = S^T S.  A pivot below rel_floor * max_i G_ii (or not positive)
+// N x N): G = S^T S.  A pivot below rel_floor * max_i G_ii (or not positive)
 // is replaced by that floor and the rest of its row is zeroed; the returned
 // count says how many pivots were replaced.  Returns -1 if G holds a NaN/Inf.
-LRADI_HD inline int chol_upper_reg(const double* G, double* S, int n, double rel_floor) {
+template <int N>
+LRADI_HD inline int chol_upper_reg_t(const double* G, double* S, double rel_floor) {
+  double g[N * N], s[N * N];
   double dmax = 0.0;
-  for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < n; ++j) {
-      double g = G[i * n + j];
-      if (!(g == g) || g - g != 0.0) return -1;
-    }
-    dmax = fmax(dmax, G[i * n + i]);
+  bool bad = false;
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) {
+    g[e] = G[e];
+    bad = bad || !(g[e] == g[e]) || (g[e] - g[e] != 0.0);
+    s[e] = 0.0;
   }
+  if (bad) return -1;
+  LRADI_UNROLL for (int i = 0; i < N; ++i) dmax = fmax(dmax, g[i * N + i]);
   double fl = rel_floor * dmax;
   if (!(fl > 0.0)) fl = 1e-300;
   int reg = 0;
-  for (int i = 0; i < n * n; ++i) S[i] = 0.0;
-  for (int c = 0; c < n; ++c) {
-    double d = G[c * n + c];
-    for (int k = 0; k < c; ++k) d -= S[k * n + c] * S[k * n + c];
+  LRADI_UNROLL for (int c = 0; c < N; ++c) {
+    double d = g[c * N + c];
+    LRADI_UNROLL for (int k = 0; k < c; ++k) d -= s[k * N + c] * s[k * N + c];
     if (d > fl) {
-      double s = sqrt(d);
-      S[c * n + c] = s;
-      for (int q = c + 1; q < n; ++q) {
-        double v = G[c * n + q];
-        for (int k = 0; k < c; ++k) v -= S[k * n + c] * S[k * n + q];
-        S[c * n + q] = v / s;
+      const double sc = sqrt(d);
+      const double inv = 1.0 / sc;
+      s[c * N + c] = sc;
+      LRADI_UNROLL for (int q = c + 1; q < N; ++q) {
+        double v = g[c * N + q];
+        LRADI_UNROLL for (int k = 0; k < c; ++k) v -= s[k * N + c] * s[k * N + q];
+        s[c * N + q] = v * inv;
       }
     } else {
-      S[c * n + c] = sqrt(fl);
+      s[c * N + c] = sqrt(fl);
       ++reg;
     }
   }
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) S[e] = s[e];
   return reg;
 }
 
-// X = S^{-1} for upper triangular S (row-major n x n); X is upper triangular.
-LRADI_HD inline void tri_inv_upper(const double* S, double* X, int n) {
-  for (int i = 0; i < n * n; ++i) X[i] = 0.0;
-  for (int c = n - 1; c >= 0; --c) {
-    X[c * n + c] = 1.0 / S[c * n + c];
-    for (int q = c + 1; q < n; ++q) {
+// X = S^{-1} for upper triangular S (row-major N x N).
+template <int N>
+LRADI_HD inline void tri_inv_upper_t(const double* S, double* X) {
+  double s[N * N], x[N * N];
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) {
+    s[e] = S[e];
+    x[e] = 0.0;
+  }
+  LRADI_UNROLL for (int c = N - 1; c >= 0; --c) {
+    const double inv = 1.0 / s[c * N + c];
+    x[c * N + c] = inv;
+    LRADI_UNROLL for (int q = c + 1; q < N; ++q) {
       double v = 0.0;
-      for (int k = c + 1; k <= q; ++k) v += S[c * n + k] * X[k * n + q];
-      X[c * n + q] = -v / S[c * n + c];
+      LRADI_UNROLL for (int k = c + 1; k <= q; ++k) v += s[c * N + k] * x[k * N + q];
+      x[c * N + q] = -v * inv;
     }
   }
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) X[e] = x[e];
 }
 
-// C = A B for n x n row-major matrices (C distinct from A and B).
-LRADI_HD inline void matmul_sq(const double* A, const double* B, double* C, int n) {
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double v = 0.0;
-      for (int k = 0; k < n; ++k) v += A[i * n + k] * B[k * n + j];
-      C[i * n + j] = v;
-    }
-}
-
-// Cyclic Jacobi eigenvalue iteration on a symmetric n x n row-major A
-// (overwritten; its diagonal ends up holding the eigenvalues).  If Q is not
-// null it receives the eigenvectors as columns.  At most 50 sweeps.
-LRADI_HD inline void jacobi_eig(double* A, double* Q, int n) {
-  if (Q)
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) Q[i * n + j] = (i == j) ? 1.0 : 0.0;
+// Cyclic Jacobi eigenvalue iteration on a symmetric N x N row-major matrix
+// held in a (overwritten; its diagonal ends up holding the eigenvalues).  If
+// WANTQ, q receives the eigenvectors as columns.  At most 50 sweeps.
+template <int N, bool WANTQ>
+LRADI_HD inline void jacobi_eig_t(double* a, double* q) {
+  if (WANTQ) {
+    LRADI_UNROLL for (int i = 0; i < N; ++i)
+      LRADI_UNROLL for (int j = 0; j < N; ++j) q[i * N + j] = (i == j) ? 1.0 : 0.0;
+  }
   for (int sweep = 0; sweep < 50; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int p = 0; p < n; ++p)
-      for (int q = 0; q < n; ++q) {
-        double a = A[p * n + q];
-        tot += a * a;
-        if (p != q) off += a * a;
+    LRADI_UNROLL for (int i = 0; i < N; ++i)
+      LRADI_UNROLL for (int j = 0; j < N; ++j) {
+        const double v = a[i * N + j];
+        tot += v * v;
+        if (i != j) off += v * v;
       }
     if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        double apq = A[p * n + q];
-        if (apq == 0.0) continue;
-        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
-        double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        double c = 1.0 / sqrt(t * t + 1.0);
-        double s = t * c;
-        for (int k = 0; k < n; ++k) {
-          double akp = A[k * n + p], akq = A[k * n + q];
-          A[k * n + p] = c * akp - s * akq;
-          A[k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          double apk = A[p * n + k], aqk = A[q * n + k];
-          A[p * n + k] = c * apk - s * aqk;
-          A[q * n + k] = s * apk + c * aqk;
-        }
-        if (Q)
-          for (int k = 0; k < n; ++k) {
-            double qkp = Q[k * n + p], qkq = Q[k * n + q];
-            Q[k * n + p] = c * qkp - s * qkq;
-            Q[k * n + q] = s * qkp + c * qkq;
+    LRADI_UNROLL for (int p = 0; p < N - 1; ++p)
+      LRADI_UNROLL for (int r = p + 1; r < N; ++r) {
+        const double apq = a[p * N + r];
+        if (apq != 0.0) {
+          const double theta = (a[r * N + r] - a[p * N + p]) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          const double c = 1.0 / sqrt(t * t + 1.0);
+          const double s = t * c;
+          LRADI_UNROLL for (int k = 0; k < N; ++k) {
+            const double akp = a[k * N + p], akq = a[k * N + r];
+            a[k * N + p] = c * akp - s * akq;
+            a[k * N + r] = s * akp + c * akq;
           }
+          LRADI_UNROLL for (int k = 0; k < N; ++k) {
+            const double apk = a[p * N + k], aqk = a[r * N + k];
+            a[p * N + k] = c * apk - s * aqk;
+            a[r * N + k] = s * apk + c * aqk;
+          }
+          if (WANTQ) {
+            LRADI_UNROLL for (int k = 0; k < N; ++k) {
+              const double qkp = q[k * N + p], qkq = q[k * N + r];
+              q[k * N + p] = c * qkp - s * qkq;
+              q[k * N + r] = s * qkp + c * qkq;
+            }
+          }
+        }
       }
   }
 }
 
-// Largest eigenvalue of a symmetric positive semidefinite n x n matrix
-// (row-major, copied; G itself is left alone).
-LRADI_HD inline double lambda_max_sym(const double* G, int n) {
-  double A[64];
-  for (int i = 0; i < n * n; ++i) A[i] = G[i];
-  jacobi_eig(A, nullptr, n);
+// Largest eigenvalue of a symmetric positive semidefinite N x N matrix.
+template <int N>
+LRADI_HD inline double lambda_max_sym_t(const double* G) {
+  double a[N * N];
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) a[e] = G[e];
+  jacobi_eig_t<N, false>(a, nullptr);
   double m = 0.0;
-  for (int i = 0; i < n; ++i) m = fmax(m, A[i * n + i]);
+  LRADI_UNROLL for (int i = 0; i < N; ++i) m = fmax(m, a[i * N + i]);
   return m;
 }
 
 // Largest eigenvalue of the product Gw Gt of two symmetric positive
-// semidefinite n x n matrices: with Gw = Q diag(l) Q^T it equals
+// semidefinite N x N matrices: with Gw = Q diag(l) Q^T it equals
 // lambda_max(diag(sqrt l) Q^T Gt Q diag(sqrt l)), a symmetric matrix.  So
 // ||W T^T||_2^2 = lambda_max((W^T W)(T^T T)) for tall blocks W, T.
-LRADI_HD inline double lambda_max_prod(const double* Gw, const double* Gt, int n) {
-  double A[64], Q[64], M[64], tmp[64];
-  for (int i = 0; i < n * n; ++i) A[i] = Gw[i];
-  jacobi_eig(A, Q, n);
-  double sl[8];
-  for (int i = 0; i < n; ++i) sl[i] = sqrt(fmax(A[i * n + i], 0.0));
-  // tmp = Gt Q
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
+template <int N>
+LRADI_HD inline double lambda_max_prod_t(const double* Gw, const double* Gt) {
+  double a[N * N], q[N * N], m[N * N], t[N * N];
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) {
+    a[e] = Gw[e];
+    t[e] = Gt[e];
+  }
+  jacobi_eig_t<N, true>(a, q);
+  double sl[N];
+  LRADI_UNROLL for (int i = 0; i < N; ++i) sl[i] = sqrt(fmax(a[i * N + i], 0.0));
+  // a <- Gt Q
+  LRADI_UNROLL for (int i = 0; i < N; ++i)
+    LRADI_UNROLL for (int j = 0; j < N; ++j) {
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += Gt[i * n + k] * Q[k * n + j];
-      tmp[i * n + j] = v;
+      LRADI_UNROLL for (int k = 0; k < N; ++k) v += t[i * N + k] * q[k * N + j];
+      a[i * N + j] = v;
     }
-  // M = diag(sl) Q^T tmp diag(sl)
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
+  LRADI_UNROLL for (int i = 0; i < N; ++i)
+    LRADI_UNROLL for (int j = 0; j < N; ++j) {
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += Q[k * n + i] * tmp[k * n + j];
-      M[i * n + j] = sl[i] * v * sl[j];
+      LRADI_UNROLL for (int k = 0; k < N; ++k) v += q[k * N + i] * a[k * N + j];
+      m[i * N + j] = sl[i] * v * sl[j];
     }
-  for (int i = 0; i < n; ++i)
-    for (int j = i + 1; j < n; ++j) {
-      double a = 0.5 * (M[i * n + j] + M[j * n + i]);
-      M[i * n + j] = a;
-      M[j * n + i] = a;
+  LRADI_UNROLL for (int i = 0; i < N; ++i)
+    LRADI_UNROLL for (int j = i + 1; j < N; ++j) {
+      const double v = 0.5 * (m[i * N + j] + m[j * N + i]);
+      m[i * N + j] = v;
+      m[j * N + i] = v;
     }
-  return lambda_max_sym(M, n);
+  return lambda_max_sym_t<N>(m);
 }
 
-// Householder QR of the 2n x n matrix M (row-major, overwritten with R in
-// its top n rows and zeros below).  Q (2n x 2n, row-major) is returned
+// Householder QR of the 2N x N matrix M (row-major, overwritten with R in
+// its top N rows and zeros below).  Q (2N x 2N, row-major) is returned
 // explicitly with Q^T M_in = [R; 0].
-LRADI_HD inline void householder_2nxn(double* M, double* Q, int n) {
-  const int m = 2 * n;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) Q[i * m + j] = (i == j) ? 1.0 : 0.0;
-  double v[16];
-  for (int c = 0; c < n; ++c) {
+template <int N>
+LRADI_HD inline void householder_2nxn_t(double* M, double* Q) {
+  constexpr int m = 2 * N;
+  double a[m * N], qq[m * m], v[m];
+  LRADI_UNROLL for (int e = 0; e < m * N; ++e) a[e] = M[e];
+  LRADI_UNROLL for (int i = 0; i < m; ++i)
+    LRADI_UNROLL for (int j = 0; j < m; ++j) qq[i * m + j] = (i == j) ? 1.0 : 0.0;
+  LRADI_UNROLL for (int c = 0; c < N; ++c) {
     double nx = 0.0;
-    for (int i = c; i < m; ++i) nx += M[i * n + c] * M[i * n + c];
+    LRADI_UNROLL for (int i = c; i < m; ++i) nx += a[i * N + c] * a[i * N + c];
     nx = sqrt(nx);
-    if (nx == 0.0) continue;
-    double x0 = M[c * n + c];
-    double alpha = (x0 >= 0.0) ? -nx : nx;
-    for (int i = 0; i < m; ++i) v[i] = 0.0;
-    for (int i = c; i < m; ++i) v[i] = M[i * n + c];
-    v[c] -= alpha;
-    double vv = 0.0;
-    for (int i = c; i < m; ++i) vv += v[i] * v[i];
-    if (vv == 0.0) continue;
-    double beta = 2.0 / vv;
-    // M <- H M on columns c..n-1
-    for (int j = c; j < n; ++j) {
-      double d = 0.0;
-      for (int i = c; i < m; ++i) d += v[i] * M[i * n + j];
-      d *= beta;
-      for (int i = c; i < m; ++i) M[i * n + j] -= d * v[i];
-    }
-    for (int i = c + 1; i < m; ++i) M[i * n + c] = 0.0;
-    M[c * n + c] = alpha;
-    // Q <- Q H
-    for (int i = 0; i < m; ++i) {
-      double d = 0.0;
-      for (int k = c; k < m; ++k) d += Q[i * m + k] * v[k];
-      d *= beta;
-      for (int k = c; k < m; ++k) Q[i * m + k] -= d * v[k];
+    if (nx != 0.0) {
+      const double x0 = a[c * N + c];
+      const double alpha = (x0 >= 0.0) ? -nx : nx;
+      LRADI_UNROLL for (int i = 0; i < m; ++i) v[i] = (i >= c) ? a[i * N + c] : 0.0;
+      v[c] -= alpha;
+      double vv = 0.0;
+      LRADI_UNROLL for (int i = c; i < m; ++i) vv += v[i] * v[i];
+      if (vv != 0.0) {
+        const double beta = 2.0 / vv;
+        LRADI_UNROLL for (int j = c; j < N; ++j) {
+          double d = 0.0;
+          LRADI_UNROLL for (int i = c; i < m; ++i) d += v[i] * a[i * N + j];
+          d *= beta;
+          LRADI_UNROLL for (int i = c; i < m; ++i) a[i * N + j] -= d * v[i];
+        }
+        LRADI_UNROLL for (int i = c + 1; i < m; ++i) a[i * N + c] = 0.0;
+        a[c * N + c] = alpha;
+        LRADI_UNROLL for (int i = 0; i < m; ++i) {
+          double d = 0.0;
+          LRADI_UNROLL for (int k = c; k < m; ++k) d += qq[i * m + k] * v[k];
+          d *= beta;
+          LRADI_UNROLL for (int k = c; k < m; ++k) qq[i * m + k] -= d * v[k];
+        }
+      }
     }
   }
+  LRADI_UNROLL for (int e = 0; e < m * N; ++e) M[e] = a[e];
+  LRADI_UNROLL for (int e = 0; e < m * m; ++e) Q[e] = qq[e];
+}
+
+// ---- runtime-dimension wrappers ------------------------------------------
+#define LRADI_SMALL_SWITCH(n, ...) \
+  switch (n) {                      \
+    case 1: { constexpr int NN = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int NN = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int NN = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int NN = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int NN = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int NN = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int NN = 7; __VA_ARGS__; } break; \
+    default: { constexpr int NN = 8; __VA_ARGS__; } break; \
+  }
+
+LRADI_HD inline int chol_upper_reg(const double* G, double* S, int n, double rel_floor) {
+  int r = 0;
+  LRADI_SMALL_SWITCH(n, r = chol_upper_reg_t<NN>(G, S, rel_floor));
+  return r;
+}
+LRADI_HD inline void tri_inv_upper(const double* S, double* X, int n) {
+  LRADI_SMALL_SWITCH(n, tri_inv_upper_t<NN>(S, X));
+}
+LRADI_HD inline void jacobi_eig(double* A, double* Q, int n) {
+  if (Q) {
+    LRADI_SMALL_SWITCH(n, jacobi_eig_t<NN, true>(A, Q));
+  } else {
+    LRADI_SMALL_SWITCH(n, jacobi_eig_t<NN, false>(A, nullptr));
+  }
+}
+LRADI_HD inline double lambda_max_sym(const double* G, int n) {
+  double r = 0.0;
+  LRADI_SMALL_SWITCH(n, r = lambda_max_sym_t<NN>(G));
+  return r;
+}
+LRADI_HD inline double lambda_max_prod(const double* Gw, const double* Gt, int n) {
+  double r = 0.0;
+  LRADI_SMALL_SWITCH(n, r = lambda_max_prod_t<NN>(Gw, Gt));
+  return r;
+}
+LRADI_HD inline void householder_2nxn(double* M, double* Q, int n) {
+  LRADI_SMALL_SWITCH(n, householder_2nxn_t<NN>(M, Q));
 }
 
 }  // namespace lradi
