@@ -112,7 +112,10 @@ typedef struct {
   int32_t lookahead;   /* host scheduling depth (0 = synchronous), >= 0       */
   int32_t use_graph;   /* 1: replay the inner-iteration launch sequence from a
                           captured hipGraph                                    */
-  int32_t reserved[5];
+  int32_t profile;     /* 1: time the projection (Gram) and shifted-product
+                          launches with HIP events and count their
+                          algorithmic bytes (see lradi_profile_read)         */
+  int32_t reserved[4];
 } lradi_opts;
 
 /* Per inner solve statistics (lradi_shifted_solve). */
@@ -123,6 +126,22 @@ typedef struct {
   int32_t pad;
   double rnorm;        /* achieved ||W - (A + shift I) Z||_2 (FP64)           */
 } lradi_inner_stats;
+
+/* Kernel classes reported by lradi_profile_read. */
+#define LRADI_PROF_GRAM 0      /* block projection V^T U (two launches per step)  */
+#define LRADI_PROF_SPMM 1      /* shifted product U = (A + s I) V_j               */
+#define LRADI_PROF_CLASSES 2
+
+/* Accumulated measurements of one kernel class over the solves run with
+ * opts.profile = 1 since the last lradi_profile_reset.  ms: summed
+ * event-timed launch durations; bytes: summed algorithmic bytes (data the
+ * method must read and write: basis blocks and candidate block for the
+ * projection; values, indices, input and output block for the product). */
+typedef struct {
+  double ms;
+  int64_t launches;
+  int64_t bytes;
+} lradi_kernel_profile;
 
 void lradi_default_opts(lradi_opts* opts);
 const char* lradi_strerror(int status);
@@ -194,6 +213,10 @@ int lradi_result_history(const lradi_result* res, double* rows, int max_rows, in
 /* Wall time of the solve in seconds (host clock around the device work). */
 int lradi_result_time(const lradi_result* res, double* seconds);
 void lradi_result_free(lradi_result* res);
+
+/* Read (host struct) or clear the per-context kernel measurements. */
+int lradi_profile_read(lradi_ctx* ctx, int kernel_class, lradi_kernel_profile* out);
+int lradi_profile_reset(lradi_ctx* ctx);
 
 /* True scaled residual ||A Z D Y^T + Z D Y^T B + f g^T||_2 / ||f g^T||_2 of
  * a factored solution (Sec. 4 estimates it after termination with eigs on

@@ -19,6 +19,9 @@ namespace lradi {
 
 void csr_transpose(int n, const int32_t* rp, const int32_t* ci, const double* v,
                    std::vector<int32_t>& trp, std::vector<int32_t>& tci, std::vector<double>& tv);
+int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
+                  const double* f, const double* g, int r, const double* Z, const double* gam_d,
+                  const double* Y, int k, int maxit, double* sigma_out);
 
 // ---------------------------------------------------------------------------
 // errors
@@ -31,11 +34,6 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
-#define LRADI_TRY(expr)            \
-  do {                             \
-    int st_ = (expr);              \
-    if (st_ < 0) return st_;       \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // buffers
@@ -182,6 +180,11 @@ struct lradi_ctx {
   HostRing ring;
   HostRing done;
   std::vector<hipEvent_t> events;
+  // kernel measurements (opts.profile)
+  std::vector<TickProbe> probes;
+  DevBuf prof_dev;  // LRADI_PROF_CLASSES unsigned long long byte counters
+  double prof_ms[LRADI_PROF_CLASSES] = {0.0, 0.0};
+  int64_t prof_launches[LRADI_PROF_CLASSES] = {0, 0};
 };
 
 struct lradi_result {
@@ -283,6 +286,7 @@ int build_batch(lradi_ctx* ctx, const std::vector<SysSpec>& sys, InnerBatch& ib)
     D.floor_rel = S.floor_rel;
     D.W = S.W;
     D.pstride = (int)pstride;
+    D.nnz = (int)S.A->nnz;
     for (int w = 0; w < nwg; ++w) ib.hmap.push_back(make_int2(s, w));
     SysCtl& C = ib.hc[s];
     C.Z = S.Z;
@@ -344,7 +348,19 @@ int build_batch(lradi_ctx* ctx, const std::vector<SysSpec>& sys, InnerBatch& ib)
 // Issue ticks until every system of the batch is finished.  The host reads
 // the unfinished count of tick t - L only after issuing tick t, so the device
 // always has work queued; the extra ticks are no-ops.
-int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner) {
+int probe_account(lradi_ctx* ctx, const TickProbe& p) {
+  float a = 0.f, b = 0.f, c = 0.f;
+  LRADI_HIP(hipEventElapsedTime(&a, p.ev[0], p.ev[1]));
+  LRADI_HIP(hipEventElapsedTime(&b, p.ev[2], p.ev[3]));
+  LRADI_HIP(hipEventElapsedTime(&c, p.ev[4], p.ev[5]));
+  ctx->prof_ms[LRADI_PROF_GRAM] += (double)a + (double)b;
+  ctx->prof_launches[LRADI_PROF_GRAM] += 2;
+  ctx->prof_ms[LRADI_PROF_SPMM] += (double)c;
+  ctx->prof_launches[LRADI_PROF_SPMM] += 1;
+  return LRADI_OK;
+}
+
+int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner, bool profile) {
   const int L = std::max(0, std::min(lookahead, 8));
   LRADI_TRY(ctx->ring.init(L + 1));
   while ((int)ctx->events.size() < L + 1) {
@@ -352,16 +368,25 @@ int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner) {
     LRADI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ctx->events.push_back(e);
   }
+  if (profile) {
+    while ((int)ctx->probes.size() < L + 1) {
+      TickProbe p;
+      for (auto& e : p.ev) LRADI_HIP(hipEventCreate(&e));
+      ctx->probes.push_back(p);
+    }
+  }
   hipStream_t st = ctx->stream;
   const long max_ticks = 3L * std::max(max_inner, 1) + 16;
-  for (long t = 0;; ++t) {
+  long t = 0;
+  for (;; ++t) {
     const int slot = (int)(t % (L + 1));
-    LRADI_TRY(launch_tick(st, b));
+    LRADI_TRY(launch_tick(st, b, profile ? &ctx->probes[slot] : nullptr));
     LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
     LRADI_HIP(hipEventRecord(ctx->events[slot], st));
     if (t >= L) {
       const int rs = (int)((t - L) % (L + 1));
       LRADI_HIP(hipEventSynchronize(ctx->events[rs]));
+      if (profile) LRADI_TRY(probe_account(ctx, ctx->probes[rs]));
       const int left = __atomic_load_n(ctx->ring.h + rs, __ATOMIC_ACQUIRE);
       if (left == 0) break;
     }
@@ -370,6 +395,63 @@ int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner) {
       return LRADI_EHIP;
     }
   }
+  LRADI_HIP(hipStreamSynchronize(st));
+  if (profile)  // ticks issued after the last one read back
+    for (long u = std::max(0L, t - L + 1); u <= t; ++u)
+      LRADI_TRY(probe_account(ctx, ctx->probes[u % (L + 1)]));
+  return LRADI_OK;
+}
+
+int prof_counters(lradi_ctx* ctx, bool profile, unsigned long long** out) {
+  *out = nullptr;
+  if (!profile) return LRADI_OK;
+  if (!ctx->prof_dev.p) {
+    LRADI_TRY(ctx->prof_dev.alloc(sizeof(unsigned long long) * LRADI_PROF_CLASSES));
+    LRADI_HIP(hipMemset(ctx->prof_dev.p, 0, sizeof(unsigned long long) * LRADI_PROF_CLASSES));
+  }
+  *out = ctx->prof_dev.as<unsigned long long>();
+  return LRADI_OK;
+}
+
+// Host copy of a (host or device) CSR matrix, validated.
+int host_csr(const lradi_csr* M, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+             std::vector<double>& v) {
+  if (!M || !M->rowptr || M->nrows <= 0 || M->nrows != M->ncols || M->nnz < 0)
+    return set_error("invalid csr"), LRADI_EINVAL;
+  const int n = M->nrows;
+  rp.resize(n + 1);
+  ci.resize(M->nnz);
+  v.resize(M->nnz);
+  if (M->on_device) {
+    LRADI_HIP(hipMemcpy(rp.data(), M->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (M->nnz > 0) {
+      LRADI_HIP(hipMemcpy(ci.data(), M->colind, sizeof(int32_t) * M->nnz, hipMemcpyDeviceToHost));
+      LRADI_HIP(hipMemcpy(v.data(), M->val, sizeof(double) * M->nnz, hipMemcpyDeviceToHost));
+    }
+  } else {
+    std::copy(M->rowptr, M->rowptr + n + 1, rp.begin());
+    std::copy(M->colind, M->colind + M->nnz, ci.begin());
+    std::copy(M->val, M->val + M->nnz, v.begin());
+  }
+  if (rp[0] != 0 || rp[n] != M->nnz) return set_error("csr rowptr must start at 0 and end at nnz"), LRADI_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return set_error("csr rowptr not monotone"), LRADI_EINVAL;
+  for (int64_t k = 0; k < M->nnz; ++k)
+    if (ci[k] < 0 || ci[k] >= n) return set_error("csr column index out of range"), LRADI_EINVAL;
+  return LRADI_OK;
+}
+
+// Upload a matrix and its transpose.
+int upload_pair(const lradi_csr* M, hipStream_t st, DevCSR& dM, DevCSR& dMt) {
+  std::vector<int32_t> rp, ci, trp, tci;
+  std::vector<double> v, tv;
+  LRADI_TRY(host_csr(M, rp, ci, v));
+  const int n = M->nrows;
+  csr_transpose(n, rp.data(), ci.data(), v.data(), trp, tci, tv);
+  lradi_csr a{n, n, M->nnz, rp.data(), ci.data(), v.data(), 0};
+  lradi_csr t{n, n, M->nnz, trp.data(), tci.data(), tv.data(), 0};
+  LRADI_TRY(dM.upload(&a, st, false));
+  LRADI_TRY(dMt.upload(&t, st, false));
   LRADI_HIP(hipStreamSynchronize(st));
   return LRADI_OK;
 }
@@ -470,6 +552,8 @@ int lradi_destroy(lradi_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto e : c->events) (void)hipEventDestroy(e);
+  for (auto& p : c->probes)
+    for (auto e : p.ev) (void)hipEventDestroy(e);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return LRADI_OK;
@@ -514,7 +598,8 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
   }
   InnerBatch ib;
   LRADI_TRY(build_batch(c, specs, ib));
-  LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner));
+  LRADI_TRY(prof_counters(c, o.profile != 0, &ib.b.prof_bytes));
+  LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner, o.profile != 0));
   std::vector<SysCtl> hc(nsys);
   LRADI_HIP(hipMemcpy(hc.data(), ib.b.ctl, sizeof(SysCtl) * nsys, hipMemcpyDeviceToHost));
   int status = LRADI_OK;
@@ -606,6 +691,7 @@ int lradi_solve(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const doub
   specs[1] = SysSpec{&dBt, T.as<double>(), nullptr, 0.0, 0.0, r, o.restart, o.precision, o.max_inner, fl};
   InnerBatch ib;
   LRADI_TRY(build_batch(c, specs, ib));
+  LRADI_TRY(prof_counters(c, o.profile != 0, &ib.b.prof_bytes));
 
   AdiDesc ad{};
   ad.n = n;
@@ -642,7 +728,7 @@ int lradi_solve(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const doub
   LRADI_TRY(adi_launch_setup(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1));
   for (int k = 0; k < o.kmax; ++k) {
     LRADI_TRY(adi_launch_prepare(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1));
-    LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner));
+    LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner, o.profile != 0));
     LRADI_TRY(adi_launch_finish(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1, c->done.d));
     LRADI_HIP(hipStreamSynchronize(st));
     if (__atomic_load_n(c->done.h, __ATOMIC_ACQUIRE)) break;
@@ -663,6 +749,33 @@ int lradi_solve(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const doub
   res->status = status;
   *out = res.release();
   return status;
+}
+
+int lradi_profile_read(lradi_ctx* c, int kc, lradi_kernel_profile* out) {
+  if (!c || !out || kc < 0 || kc >= LRADI_PROF_CLASSES)
+    return set_error("lradi_profile_read: bad argument"), LRADI_EINVAL;
+  unsigned long long bytes[LRADI_PROF_CLASSES] = {0, 0};
+  if (c->prof_dev.p) {
+    LRADI_HIP(hipSetDevice(c->device));
+    LRADI_HIP(hipMemcpy(bytes, c->prof_dev.p, sizeof(bytes), hipMemcpyDeviceToHost));
+  }
+  out->ms = c->prof_ms[kc];
+  out->launches = c->prof_launches[kc];
+  out->bytes = (int64_t)bytes[kc];
+  return LRADI_OK;
+}
+
+int lradi_profile_reset(lradi_ctx* c) {
+  if (!c) return set_error("lradi_profile_reset: null context"), LRADI_EINVAL;
+  for (int k = 0; k < LRADI_PROF_CLASSES; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_launches[k] = 0;
+  }
+  if (c->prof_dev.p) {
+    LRADI_HIP(hipSetDevice(c->device));
+    LRADI_HIP(hipMemset(c->prof_dev.p, 0, sizeof(unsigned long long) * LRADI_PROF_CLASSES));
+  }
+  return LRADI_OK;
 }
 
 int lradi_result_info(const lradi_result* r, int* k, int* status, double* rel, double* nfg) {
@@ -715,10 +828,28 @@ void lradi_result_free(lradi_result* r) { delete r; }
 int lradi_residual(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, int b_is_transposed,
                    const double* f, const double* g, int r, const double* Z, const double* D,
                    const double* Y, int k, double* rel) {
-  (void)c; (void)A; (void)B; (void)b_is_transposed; (void)f; (void)g; (void)r; (void)Z; (void)D;
-  (void)Y; (void)k; (void)rel;
-  set_error("lradi_residual: not available in this build");
-  return LRADI_EINVAL;
+  if (!c || !A || !B || !f || !g || !rel || (k > 0 && (!Z || !D || !Y)))
+    return set_error("lradi_residual: null argument"), LRADI_EINVAL;
+  if (r < 1 || r > kMaxR || k < 0) return set_error("lradi_residual: bad r or k"), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  DevCSR dA, dAt, dB, dBt;
+  LRADI_TRY(upload_pair(A, st, dA, dAt));
+  if (b_is_transposed) {
+    LRADI_TRY(upload_pair(B, st, dBt, dB));
+  } else {
+    LRADI_TRY(upload_pair(B, st, dB, dBt));
+  }
+  DevBuf gam;
+  LRADI_TRY(gam.alloc(sizeof(double) * std::max(k, 1)));
+  if (k > 0) LRADI_HIP(hipMemcpyAsync(gam.p, D, sizeof(double) * k, hipMemcpyHostToDevice, st));
+  const int maxit = std::min(2 * k * r + r + 2, 400);
+  double sres = 0.0, sfg = 0.0;
+  LRADI_TRY(residual_norm(st, dA, dAt, dB, dBt, f, g, r, Z, gam.as<double>(), Y, k, maxit, &sres));
+  LRADI_TRY(residual_norm(st, dA, dAt, dB, dBt, f, g, r, Z, gam.as<double>(), Y, 0, r + 2, &sfg));
+  LRADI_HIP(hipStreamSynchronize(st));
+  *rel = (sfg > 0.0) ? sres / sfg : 0.0;
+  return LRADI_OK;
 }
 
 }  // extern "C"

@@ -56,7 +56,7 @@ struct SysDesc {
   double* yv;           // least-squares solution, m r x r, row-major
   double* sm;           // small scratch (8 x 64 doubles)
   int pstride;          // stride of part rows (>= (m+1) r^2)
-  int pad0;
+  int nnz;              // nonzeros of A
 };
 
 // Mutable device-side control block of one inner solve.
@@ -91,6 +91,12 @@ void set_error(const char* fmt, ...);
                          __FILE__, __LINE__);                                     \
       return LRADI_EHIP;                                                          \
     }                                                                             \
+  } while (0)
+
+#define LRADI_TRY(expr)      \
+  do {                       \
+    int st_ = (expr);        \
+    if (st_ < 0) return st_; \
   } while (0)
 
 // ---------------------------------------------------------------------------
@@ -135,11 +141,18 @@ struct Batch {
   int maxP;            // max over systems of (m+1) r^2
   int precision;       // LRADI_FP64 / LRADI_FP32_INNER
   int rfix;            // common r of all systems, or 0 when they differ
+  unsigned long long* prof_bytes;  // device counters per kernel class, or null
+};
+
+// Optional timing events around the instrumented launches of one tick:
+// [0,1] first projection, [2,3] second projection, [4,5] shifted product.
+struct TickProbe {
+  hipEvent_t ev[6];
 };
 // One scheduling tick: a block Arnoldi step (or the rebuild of V_0) for every
 // system in PH_ARNOLDI / PH_RESTART, then the end-of-cycle work for every
 // system in PH_CYCLE_END.
-int launch_tick(hipStream_t st, const Batch& b);
+int launch_tick(hipStream_t st, const Batch& b, const TickProbe* probe = nullptr);
 // Count of systems not yet finished, written to a host-visible int.
 int launch_summary(hipStream_t st, const Batch& b, int* host_slot);
 

@@ -131,7 +131,8 @@ __device__ inline void spmm_rows(const SysDesc& D, const RowCtx& c, T shift, con
 template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
                                                    const SysCtl* __restrict__ ctl,
-                                                   const int2* __restrict__ rowmap) {
+                                                   const int2* __restrict__ rowmap,
+                                                   unsigned long long* __restrict__ prof) {
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   const int ph = ctl[c.s].phase;
@@ -144,6 +145,12 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
   if (ph != PH_ARNOLDI) return;
   const T* Vj = static_cast<const T*>(D.V) + (size_t)ctl[c.s].j * D.n * D.r;
   const T sh = (T)ctl[c.s].shift;
+  if (prof && c.w == 0 && threadIdx.x == 0) {
+    // values + column indices + row pointers + input block + output block
+    const unsigned long long bytes = (unsigned long long)D.nnz * (sizeof(T) + 4) +
+                                     4ull * (D.n + 1) + 2ull * sizeof(T) * D.n * D.r;
+    atomicAdd(prof + LRADI_PROF_SPMM, bytes);
+  }
   LRADI_RSEL(RF, D.r, spmm_rows<T, RR>(D, c, sh, Vj, U));
 }
 
@@ -222,12 +229,18 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, d
 template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_gram_vu(const SysDesc* __restrict__ d,
                                                   const SysCtl* __restrict__ ctl,
-                                                  const int2* __restrict__ rowmap) {
+                                                  const int2* __restrict__ rowmap,
+                                                  unsigned long long* __restrict__ prof) {
   __shared__ double lds[4 * 16 * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI) return;
   const int nb = ctl[c.s].j + 1;
+  if (prof && c.w == 0 && threadIdx.x == 0) {
+    // basis blocks V_0..V_j and the candidate block U
+    const unsigned long long bytes = (unsigned long long)(nb + 1) * sizeof(T) * D.n * D.r;
+    atomicAdd(prof + LRADI_PROF_GRAM, bytes);
+  }
   if constexpr (RF > 0) {
     gram_vu_rows<T, RF>(D, c, nb, lds);
   } else {
@@ -813,15 +826,21 @@ __global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restric
 }
 
 template <typename T, int RF>
-int tick_impl(hipStream_t st, const Batch& b) {
+int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 rg(b.rowgrid), tb(kTPB), sg(b.nsys);
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
-  hipLaunchKernelGGL((k_spmm_arn<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
+  hipLaunchKernelGGL((k_spmm_arn<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[5], st));
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[0], st));
+  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[1], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 1);
   hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[2], st));
+  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[3], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
   hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
@@ -837,25 +856,25 @@ int tick_impl(hipStream_t st, const Batch& b) {
 }
 
 template <typename T>
-int tick_dispatch(hipStream_t st, const Batch& b) {
+int tick_dispatch(hipStream_t st, const Batch& b, const TickProbe* pr) {
   switch (b.rfix) {
-    case 1: return tick_impl<T, 1>(st, b);
-    case 2: return tick_impl<T, 2>(st, b);
-    case 3: return tick_impl<T, 3>(st, b);
-    case 4: return tick_impl<T, 4>(st, b);
-    case 5: return tick_impl<T, 5>(st, b);
-    case 6: return tick_impl<T, 6>(st, b);
-    case 7: return tick_impl<T, 7>(st, b);
-    case 8: return tick_impl<T, 8>(st, b);
-    default: return tick_impl<T, 0>(st, b);
+    case 1: return tick_impl<T, 1>(st, b, pr);
+    case 2: return tick_impl<T, 2>(st, b, pr);
+    case 3: return tick_impl<T, 3>(st, b, pr);
+    case 4: return tick_impl<T, 4>(st, b, pr);
+    case 5: return tick_impl<T, 5>(st, b, pr);
+    case 6: return tick_impl<T, 6>(st, b, pr);
+    case 7: return tick_impl<T, 7>(st, b, pr);
+    case 8: return tick_impl<T, 8>(st, b, pr);
+    default: return tick_impl<T, 0>(st, b, pr);
   }
 }
 
 }  // namespace
 
-int launch_tick(hipStream_t st, const Batch& b) {
-  if (b.precision == LRADI_FP64) return tick_dispatch<double>(st, b);
-  return tick_dispatch<float>(st, b);
+int launch_tick(hipStream_t st, const Batch& b, const TickProbe* probe) {
+  if (b.precision == LRADI_FP64) return tick_dispatch<double>(st, b, probe);
+  return tick_dispatch<float>(st, b, probe);
 }
 
 int launch_summary(hipStream_t st, const Batch& b, int* host_slot) {

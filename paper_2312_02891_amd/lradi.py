@@ -51,7 +51,15 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_inner", ctypes.c_int32), ("rescale", ctypes.c_int32),
                 ("b_is_transposed", ctypes.c_int32), ("lookahead", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("bytes", ctypes.c_int64)]
+
+
+PROF_GRAM, PROF_SPMM = 0, 1
 
 
 class InnerStats(ctypes.Structure):
@@ -90,6 +98,8 @@ def _load():
         "lradi_result_history": (i32, [vp, vp, i32, P(i32)]),
         "lradi_result_time": (i32, [vp, P(dbl)]),
         "lradi_result_free": (None, [vp]),
+        "lradi_profile_read": (i32, [vp, i32, P(KernelProfile)]),
+        "lradi_profile_reset": (i32, [vp]),
         "lradi_residual": (i32, [vp, P(Csr), P(Csr), i32, vp, vp, i32, vp, P(dbl), vp, i32,
                                  P(dbl)]),
     }
@@ -200,8 +210,9 @@ class Result:
         return Zc, d, Yc
 
     def gammas(self):
-        _, d, _ = self.factors()
-        return d[:: self.r] if self.r else d
+        D = np.empty(max(self.k, 1))
+        _check(_lib.lradi_result_copy(self.h, None, D.ctypes.data, None))
+        return D[: self.k]
 
     def history(self):
         rows = np.zeros((max(self.k, 1), HIST_COLS))
@@ -248,6 +259,15 @@ class Context:
     def _sync(self):
         _torch().cuda.synchronize(self.device)
 
+    def profile_read(self, kernel_class: int):
+        """(ms, launches, algorithmic bytes) accumulated for a kernel class."""
+        p = KernelProfile()
+        _check(_lib.lradi_profile_read(self.h, kernel_class, ctypes.byref(p)))
+        return p.ms, p.launches, p.bytes
+
+    def profile_reset(self):
+        _check(_lib.lradi_profile_reset(self.h))
+
     def spmm(self, A: HostCsr, shift: float, X, precision: int = FP64):
         """Y = (A + shift I) X; X (n x r) FP64 or FP32 torch tensor on the GPU."""
         torch = _torch()
@@ -277,6 +297,30 @@ class Context:
                                              stats))
         return Zs, [dict(steps=s.steps, cycles=s.cycles, status=s.status, breakdowns=s.pad,
                          rnorm=s.rnorm) for s in stats], st
+
+    def residual(self, A: HostCsr, B: HostCsr, f, g, result: "Result", b_is_transposed=False):
+        """True ||A X + X B + f g^T||_2 / ||f g^T||_2 of a solve result
+        (lradi_residual on the result's device factors)."""
+        D = np.ascontiguousarray(result.gammas(), dtype=np.float64)
+        out = ctypes.c_double()
+        self._sync()
+        _check(_lib.lradi_residual(self.h, ctypes.byref(A.c), ctypes.byref(B.c), int(bool(b_is_transposed)),
+                                   _ptr(f), _ptr(g), f.shape[1], ctypes.c_void_p(result.Zptr),
+                                   D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.c_void_p(result.Yptr), result.k, ctypes.byref(out)),
+               allow_warn=False)
+        return out.value
+
+    def residual_factors(self, A: HostCsr, B: HostCsr, f, g, Zs, gammas, Ys, b_is_transposed=False):
+        """lradi_residual on device factor stacks Zs (k, n, r) and Ys (k, m, r)."""
+        D = np.ascontiguousarray(gammas, dtype=np.float64)
+        out = ctypes.c_double()
+        self._sync()
+        _check(_lib.lradi_residual(self.h, ctypes.byref(A.c), ctypes.byref(B.c), int(bool(b_is_transposed)),
+                                   _ptr(f), _ptr(g), f.shape[1], _ptr(Zs),
+                                   D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(Ys),
+                                   len(D), ctypes.byref(out)), allow_warn=False)
+        return out.value
 
     def solve(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, opts: Optional[Opts] = None):
         """Algorithm 1 on A X + X B = -f g^T (f, g: FP64 CUDA tensors); B is

@@ -128,3 +128,41 @@ def test_kmax_cap_reports_no_convergence(L, ctx):
     o = L.default_opts(tol=P.tol, kmax=3)
     res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
     assert res.status == L.WNOCONV and res.k == 3
+
+
+def test_true_residual_of_solution_matches_oracle(L, ctx):
+    """lradi_residual (Golub-Kahan-Lanczos on R applied through the factors)
+    equals the oracle's exact low-rank QR evaluation of ||R||_2/||fg^T||_2."""
+    say("residual of solve")
+    P = WL.SMALL_2D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    fd, gd = to_dev(f), to_dev(g)
+    res = ctx.solve(HA, HB, fd, gd, pA, pB, L.default_opts(tol=P.tol))
+    gpu = ctx.residual(HA, HB, fd, gd, res)
+    Z, d, Y = res.factors()
+    ora = OF.lowrank_residual_norm(A, B, f, g, Z, d, Y) / OF.lowrank_product_norm(f, g)
+    say("  gpu", gpu, "oracle", ora)
+    assert gpu == pytest.approx(ora, rel=1e-6)
+    # same value when B^T is passed instead of B
+    HBt = L.convdiff(P.B.dim, P.B.N, tuple(-w for w in P.B.omega))
+    assert ctx.residual(HA, HBt, fd, gd, res, b_is_transposed=True) == pytest.approx(gpu, rel=1e-12)
+
+
+@pytest.mark.parametrize("r,k", [(1, 1), (2, 3), (3, 5), (8, 2)])
+def test_true_residual_random_factors_matches_dense(L, ctx, r, k):
+    """Arbitrary factors (large residual): equals the dense ||R||_2."""
+    import torch
+    say("residual random", r, k)
+    HA = L.convdiff(2, 9, (4.0, -2.0))
+    HB = L.convdiff(2, 7, (-3.0, 5.0))
+    A = convdiff_matrix(2, 9, (4.0, -2.0))
+    B = convdiff_matrix(2, 7, (-3.0, 5.0))
+    rng = np.random.default_rng(r * 10 + k)
+    n, m = 81, 49
+    f, g = rng.standard_normal((n, r)), rng.standard_normal((m, r))
+    Zs, Ys = rng.standard_normal((k, n, r)), rng.standard_normal((k, m, r))
+    gam = rng.uniform(1.0, 50.0, k)
+    X = sum(gam[i] * Zs[i] @ Ys[i].T for i in range(k))
+    dense = np.linalg.norm(OF.true_residual_dense(A, B, f, g, X), 2) / np.linalg.norm(f @ g.T, 2)
+    got = ctx.residual_factors(HA, HB, to_dev(f), to_dev(g), to_dev(Zs), gam, to_dev(Ys))
+    assert got == pytest.approx(dense, rel=1e-9)
