@@ -164,11 +164,20 @@ struct Pad {
   static constexpr int v = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : 8;
 };
 
+// Tile shape per block width: K rows per lane per super-row and G basis
+// blocks per pass, so that K*G independent loads are in flight per lane.
+template <int R>
+struct GramTile {
+  static constexpr int K = R >= 5 ? 2 : 4;
+  static constexpr int G = R >= 5 ? 4 : 8;
+};
+
 template <typename T, int R>
 __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, double* lds) {
   constexpr int RP = Pad<R>::v;
-  constexpr int RPW = 64 / RP;                     // rows per wavefront pass
-  constexpr int G = (16 / R) > 0 ? (16 / R) : 1;   // basis blocks per pass
+  constexpr int RPW = 64 / RP;                  // rows per wavefront and row step
+  constexpr int K = GramTile<R>::K, G = GramTile<R>::G;
+  constexpr int SUPER = 4 * RPW * K;            // rows of one super-row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ro = lane / RP, a = lane - ro * RP;
   const bool act = a < R;
@@ -184,18 +193,29 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, d
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[g][q] = 0.0;
     if (act) {
-      for (int i = c.row0 + wave * RPW + ro; i < c.row1; i += 4 * RPW) {
-        double u[R];
+      for (int base = c.row0; base < c.row1; base += SUPER) {
+        double u[K][R];
+        int rows[K];
 #pragma unroll
-        for (int q = 0; q < R; ++q) u[q] = (double)U[(size_t)i * R + q];
+        for (int k = 0; k < K; ++k) {
+          rows[k] = base + (k * 4 + wave) * RPW + ro;
+          const bool ok = rows[k] < c.row1;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          if (g < gc) {
-            const double x = (double)V[(size_t)(b0 + g) * bs + (size_t)i * R + a];
-#pragma unroll
-            for (int q = 0; q < R; ++q) acc[g][q] += x * u[q];
-          }
+          for (int q = 0; q < R; ++q) u[k][q] = ok ? (double)U[(size_t)rows[k] * R + q] : 0.0;
         }
+        T x[K][G];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            x[k][g] = (g < gc && rows[k] < c.row1) ? V[(size_t)(b0 + g) * bs + (size_t)rows[k] * R + a]
+                                                    : T(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[g][q] += (double)x[k][g] * u[k][q];
       }
     }
     // butterfly over the row offset (lane bits >= log2 RP)
@@ -203,10 +223,10 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, d
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        double x = acc[g][q];
+        double v = acc[g][q];
 #pragma unroll
-        for (int off = RP; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
-        acc[g][q] = x;
+        for (int off = RP; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        acc[g][q] = v;
       }
     if (lane < R) {
 #pragma unroll
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(kTPB) void k_gram_vu(const SysDesc* __restrict__ d,
                                                   const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap,
                                                   unsigned long long* __restrict__ prof) {
-  __shared__ double lds[4 * 16 * kMaxR];
+  __shared__ double lds[4 * 8 * kMaxR * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI) return;
@@ -305,7 +325,24 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
       T acc[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] = T(0);
-      for (int b = 0; b < nb; ++b) {
+      constexpr int UB = R >= 5 ? 2 : 4;  // blocks whose loads are in flight together
+      int b = 0;
+      for (; b + UB <= nb; b += UB) {
+        T v[UB][R];
+#pragma unroll
+        for (int bb = 0; bb < UB; ++bb)
+#pragma unroll
+          for (int a = 0; a < R; ++a) v[bb][a] = V[(size_t)(b + bb) * bs + (size_t)i * R + a];
+#pragma unroll
+        for (int bb = 0; bb < UB; ++bb) {
+          const double* h = hl + (b + bb) * R * R;
+#pragma unroll
+          for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] += v[bb][a] * (T)h[a * R + q];
+        }
+      }
+      for (; b < nb; ++b) {
         T v[R];
 #pragma unroll
         for (int a = 0; a < R; ++a) v[a] = V[(size_t)b * bs + (size_t)i * R + a];
@@ -335,7 +372,7 @@ template <typename T, int RF, bool SECOND>
 __global__ __launch_bounds__(kTPB) void k_update(const SysDesc* __restrict__ d,
                                                  const SysCtl* __restrict__ ctl,
                                                  const int2* __restrict__ rowmap) {
-  __shared__ double hl[(kMaxM + 1) * kMaxR * kMaxR];
+  extern __shared__ double hl[];  // maxP doubles: the projection coefficients
   __shared__ double lds[4 * kMaxR * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
@@ -643,7 +680,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
 
 template <int RF>
 __global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
-  __shared__ double h[(kMaxM + 1) * kMaxR * kMaxR];
+  extern __shared__ double h[];  // maxP doubles: the Hessenberg column block
   __shared__ double Sf[64];
   __shared__ double Qj[16 * 16];
   __shared__ int done_s;
@@ -685,7 +722,7 @@ template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_zupdate(const SysDesc* __restrict__ d,
                                                   const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap) {
-  __shared__ double yl[kMaxM * kMaxR * kMaxR];
+  extern __shared__ double yl[];  // maxP doubles: the least-squares solution
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_CYCLE_END) return;
@@ -837,18 +874,19 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[1], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 1);
-  hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  const size_t shP = sizeof(double) * (size_t)b.maxP;
+  hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[2], st));
   hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[3], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
-  hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
   hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
   hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL((k_lsq<RF>), sg, tb, 0, st, b.d, b.ctl);
-  hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_lsq<RF>), sg, tb, shP, st, b.d, b.ctl);
+  hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);
   LRADI_HIP(hipGetLastError());

@@ -211,7 +211,7 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   const size_t sZ = (size_t)n * r, sY = (size_t)m * r;
   auto nb256 = [](int x) { return dim3((x + 255) / 256); };
 
-  // R v -> p (n-vector)
+  // R v -> p (n-vector); p must not be tn or tm
   auto apply_R = [&](const double* v, double* p) -> int {
     LRADI_TRY(dv.proj(Y, k, m, r, sY, v, c1));          // c1 = Y^T v
     LRADI_TRY(dv.spmv(B, v, tm.as<double>(), 0));       // tm = B v
@@ -223,7 +223,7 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
     LRADI_TRY(dv.expand(f, 1, n, r, sZ, nullptr, c3, 1.0, 1.0, p));
     return LRADI_OK;
   };
-  // R^T u -> q (m-vector)
+  // R^T u -> q (m-vector); q must not be tn2 or tm2
   auto apply_Rt = [&](const double* u, double* q) -> int {
     LRADI_TRY(dv.spmv(At, u, tn2.as<double>(), 0));     // A^T u
     LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn2.as<double>(), c1));  // Z^T A^T u
@@ -253,9 +253,8 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   // v_1
   hipLaunchKernelGGL(k_start, nb256(m), dim3(256), 0, st, m, tm.as<double>());
   LRADI_TRY(normalize(tm.as<double>(), m, V, S + 2 * J + 6));
-  // u_1 = R v_1 / alpha_1
-  LRADI_TRY(apply_R(V, tn.as<double>()));
-  LRADI_HIP(hipMemcpyAsync(U, tn.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  // u_1 = R v_1 / alpha_1 (apply_R uses tn internally, so write into U)
+  LRADI_TRY(apply_R(V, U));
   LRADI_TRY(normalize(U, n, U, alpha));
   double prev = -1.0, cur = 0.0;
   std::vector<double> hb(2);

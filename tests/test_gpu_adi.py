@@ -148,17 +148,18 @@ def test_true_residual_of_solution_matches_oracle(L, ctx):
     assert ctx.residual(HA, HBt, fd, gd, res, b_is_transposed=True) == pytest.approx(gpu, rel=1e-12)
 
 
-@pytest.mark.parametrize("r,k", [(1, 1), (2, 3), (3, 5), (8, 2)])
-def test_true_residual_random_factors_matches_dense(L, ctx, r, k):
-    """Arbitrary factors (large residual): equals the dense ||R||_2."""
-    import torch
-    say("residual random", r, k)
-    HA = L.convdiff(2, 9, (4.0, -2.0))
-    HB = L.convdiff(2, 7, (-3.0, 5.0))
-    A = convdiff_matrix(2, 9, (4.0, -2.0))
-    B = convdiff_matrix(2, 7, (-3.0, 5.0))
+@pytest.mark.parametrize("r,k,NA,NB", [(1, 1, 9, 7), (2, 3, 9, 7), (3, 5, 9, 7), (8, 2, 9, 7),
+                                        (3, 6, 37, 29), (4, 4, 40, 23)])
+def test_true_residual_random_factors_matches_dense(L, ctx, r, k, NA, NB):
+    """Arbitrary factors (large residual): equals the dense ||R||_2; the
+    larger cases span several workgroups of every kernel."""
+    say("residual random", r, k, NA, NB)
+    HA = L.convdiff(2, NA, (4.0, -2.0))
+    HB = L.convdiff(2, NB, (-3.0, 5.0))
+    A = convdiff_matrix(2, NA, (4.0, -2.0))
+    B = convdiff_matrix(2, NB, (-3.0, 5.0))
     rng = np.random.default_rng(r * 10 + k)
-    n, m = 81, 49
+    n, m = NA * NA, NB * NB
     f, g = rng.standard_normal((n, r)), rng.standard_normal((m, r))
     Zs, Ys = rng.standard_normal((k, n, r)), rng.standard_normal((k, m, r))
     gam = rng.uniform(1.0, 50.0, k)
