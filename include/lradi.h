@@ -196,6 +196,29 @@ int lradi_solve(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, const do
                 const double* g, int r, const double* shiftsA, const double* shiftsB,
                 int nshifts, const lradi_opts* opts, lradi_result** out);
 
+/* One Sylvester problem for lradi_batch_solve and the serving loop. */
+typedef struct {
+  const lradi_csr* A;      /* n x n (host or device)                           */
+  const lradi_csr* B;      /* m x m: B, or B^T when opts->b_is_transposed      */
+  const double* f;         /* device, n x r row-major (not modified)           */
+  const double* g;         /* device, m x r row-major (not modified)           */
+  int32_t r;               /* 1..8                                             */
+  int32_t nshifts;
+  const double* shiftsA;   /* host, nshifts (added to A)                       */
+  const double* shiftsB;   /* host, nshifts (added to B^T)                     */
+  double tol;              /* outer tau of this problem; <= 0 uses opts->tol   */
+} lradi_problem;
+
+/* Algorithm 1 on nprob independent problems of uneven n, m, r advanced
+ * together: every outer step of all unfinished problems runs in the same
+ * kernel launches (the inner solves of all 2*nprob shifted systems share one
+ * launch sequence per block Arnoldi step); finished problems leave the batch
+ * at step boundaries.  opts is shared (its tol is the default per problem).
+ * outs: caller array of nprob, each receives a library-owned result.  The
+ * return value is the most severe status over the problems. */
+int lradi_batch_solve(lradi_ctx* ctx, int nprob, const lradi_problem* probs,
+                      const lradi_opts* opts, lradi_result** outs);
+
 /* Scalars of a result: steps k, status, ||w_k t_k^T||/||f g^T||, ||f g^T||
  * (after the optional rescaling, which leaves f g^T unchanged). */
 int lradi_result_info(const lradi_result* res, int* k, int* status, double* rel_res_comp,

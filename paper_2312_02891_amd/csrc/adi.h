@@ -10,7 +10,7 @@ namespace lradi {
 struct AdiDesc {
   int n, m, r, kmax, nshifts;
   int selection, backlook, paper_abs, rescale;
-  int pad0;
+  int setup;              // 1: the setup kernels initialise this problem
   double tol, eps_in, delta_min, delta_max, xi, delta_fixed, rho;
   const double* shiftsA;  // device, nshifts
   const double* shiftsB;  // device, nshifts

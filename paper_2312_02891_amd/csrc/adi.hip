@@ -100,6 +100,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup_gram(const SysDesc* __restri
   const RowC c = rowc(d, rowmap);
   const SysDesc& D = d[c.s];
   const AdiDesc& P = ad[c.s >> 1];
+  if (!P.setup) return;
   const double* X = (c.s & 1) ? P.g : P.f;
   LRADI_DISPATCH_R2(D.r, gram_self<RR>(X, c, lds, D.partS + (size_t)c.w * kPS));
 }
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ 
   __shared__ double Gf[64], Gg[64];
   const int p = blockIdx.x;
   const AdiDesc& P = ad[p];
+  if (!P.setup) return;
   const SysDesc& DA = d[2 * p];
   const SysDesc& DB = d[2 * p + 1];
   const int R = P.r;
@@ -155,6 +157,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_init_wt(const SysDesc* __restrict_
   const SysDesc& D = d[c.s];
   const int p = c.s >> 1;
   const AdiDesc& P = ad[p];
+  if (!P.setup) return;
   const bool b = (c.s & 1) != 0;
   const double* X = b ? P.g : P.f;
   double* Y = b ? P.T : P.W;

@@ -479,6 +479,233 @@ double floor_for(const lradi_opts& o) {
 }  // namespace
 }  // namespace lradi
 
+// ---------------------------------------------------------------------------
+// Outer engine: a set of Sylvester problems advanced together one LR-ADI step
+// at a time (Algorithm 1).  Problem p owns inner systems 2p (A side) and 2p+1
+// (B side).  The batch is rebuilt at step boundaries whenever its membership
+// changes; between steps a problem's whole state is W, T, the factor stacks,
+// gamma, the history and its AdiCtl, so problems can join and leave freely.
+namespace lradi {
+namespace {
+
+struct Prob {
+  DevCSR A, Bt;
+  DevBuf fown, gown;   // owned copies of f, g (serving), else empty
+  const double* f = nullptr;
+  const double* g = nullptr;
+  int n = 0, m = 0, r = 0, nshifts = 0;
+  double tol = 0.0;
+  DevBuf shA, shB, W, T, gam, hist;
+  std::unique_ptr<lradi_result> res;
+  AdiCtl hc{};
+  bool set_up = false;
+  std::chrono::steady_clock::time_point t0;
+  size_t footprint = 0;  // device bytes held by this problem (serving admission)
+};
+
+// Validate and upload one problem (transposing B on the host when needed).
+int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool copy_rhs, Prob& q) {
+  hipStream_t st = c->stream;
+  if (!P.A || !P.B || !P.f || !P.g || !P.shiftsA || !P.shiftsB)
+    return set_error("problem: null argument"), LRADI_EINVAL;
+  if (P.r < 1 || P.r > kMaxR) return set_error("problem: r must be in 1..%d", kMaxR), LRADI_EINVAL;
+  if (P.nshifts < 1) return set_error("problem: need at least one shift"), LRADI_EINVAL;
+  for (int i = 0; i < P.nshifts; ++i)
+    if (!std::isfinite(P.shiftsA[i]) || !std::isfinite(P.shiftsB[i]))
+      return set_error("problem: non-finite shift"), LRADI_EINVAL;
+  const double tol = (P.tol > 0.0) ? P.tol : o.tol;
+  if (!(tol > 0.0 && tol < 1.0)) return set_error("problem: tol must be in (0,1)"), LRADI_EINVAL;
+  q.t0 = std::chrono::steady_clock::now();
+  const bool f32 = o.precision == LRADI_FP32_INNER;
+  LRADI_TRY(q.A.upload(P.A, st, f32));
+  if (o.b_is_transposed) {
+    LRADI_TRY(q.Bt.upload(P.B, st, f32));
+  } else {
+    std::vector<int32_t> rp, ci, trp, tci;
+    std::vector<double> v, tv;
+    LRADI_TRY(host_csr(P.B, rp, ci, v));
+    const int mB = P.B->nrows;
+    csr_transpose(mB, rp.data(), ci.data(), v.data(), trp, tci, tv);
+    lradi_csr Bt{mB, mB, P.B->nnz, trp.data(), tci.data(), tv.data(), 0};
+    LRADI_TRY(q.Bt.upload(&Bt, st, f32));
+    LRADI_HIP(hipStreamSynchronize(st));
+  }
+  q.n = q.A.n;
+  q.m = q.Bt.n;
+  q.r = P.r;
+  q.nshifts = P.nshifts;
+  q.tol = tol;
+  const size_t n = q.n, m = q.m, r = q.r, K = o.kmax;
+  if (copy_rhs) {
+    LRADI_TRY(q.fown.alloc(sizeof(double) * n * r));
+    LRADI_TRY(q.gown.alloc(sizeof(double) * m * r));
+    LRADI_HIP(hipMemcpyAsync(q.fown.p, P.f, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
+    LRADI_HIP(hipMemcpyAsync(q.gown.p, P.g, sizeof(double) * m * r, hipMemcpyDeviceToDevice, st));
+    q.f = q.fown.as<double>();
+    q.g = q.gown.as<double>();
+  } else {
+    q.f = P.f;
+    q.g = P.g;
+  }
+  q.res = std::make_unique<lradi_result>();
+  q.res->n = q.n;
+  q.res->m = q.m;
+  q.res->r = q.r;
+  q.res->kmax = o.kmax;
+  LRADI_TRY(q.res->Zf.alloc(sizeof(double) * K * n * r));
+  LRADI_TRY(q.res->Yf.alloc(sizeof(double) * K * m * r));
+  LRADI_TRY(q.W.alloc(sizeof(double) * n * r));
+  LRADI_TRY(q.T.alloc(sizeof(double) * m * r));
+  LRADI_TRY(q.shA.alloc(sizeof(double) * P.nshifts));
+  LRADI_TRY(q.shB.alloc(sizeof(double) * P.nshifts));
+  LRADI_TRY(q.gam.alloc(sizeof(double) * K));
+  LRADI_TRY(q.hist.alloc(sizeof(double) * K * kHistCols));
+  LRADI_HIP(hipMemcpyAsync(q.shA.p, P.shiftsA, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipStreamSynchronize(st));
+  return LRADI_OK;
+}
+
+// Device bytes one problem needs while in flight: matrices, right-hand
+// sides, residual and solution factors, and its two inner systems' workspace.
+size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lradi_opts& o) {
+  const size_t tsz = o.precision == LRADI_FP64 ? 8 : 4;
+  const size_t K = o.kmax, mm = o.restart;
+  auto mat = [&](int64_t nrow, int64_t nnz) {
+    return (size_t)(nrow + 1) * 4 + (size_t)nnz * (4 + 8 + (tsz == 4 ? 4 : 0));
+  };
+  auto inner = [&](size_t rows) {
+    const size_t rpw = 256, nwg = (rows + rpw - 1) / rpw;
+    return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + kPS) * 8 +
+           (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 4096;
+  };
+  return mat(n, nnzA) + mat(m, nnzB) + (size_t)(n + m) * r * 8 * (3 + K) + K * (kHistCols + 1) * 8 +
+         inner(n) + inner(m);
+}
+
+struct Engine {
+  lradi_ctx* c;
+  lradi_opts o;
+  std::vector<Prob*> act;
+  std::vector<Prob*> finished;  // filled by step(); the caller takes them
+  InnerBatch ib;
+  DevBuf dad, dac;
+  std::vector<AdiCtl> hac;
+  bool dirty = true;
+
+  Engine(lradi_ctx* ctx, const lradi_opts& opts) : c(ctx), o(opts) {}
+
+  int rebuild() {
+    hipStream_t st = c->stream;
+    const int np = (int)act.size();
+    std::vector<SysSpec> specs;
+    specs.reserve(2 * np);
+    const double fl = floor_for(o);
+    for (Prob* q : act) {
+      specs.push_back(SysSpec{&q->A, q->W.as<double>(), nullptr, 0.0, 0.0, q->r, o.restart, o.precision,
+                              o.max_inner, fl});
+      specs.push_back(SysSpec{&q->Bt, q->T.as<double>(), nullptr, 0.0, 0.0, q->r, o.restart, o.precision,
+                              o.max_inner, fl});
+    }
+    LRADI_TRY(build_batch(c, specs, ib));
+    LRADI_TRY(prof_counters(c, o.profile != 0, &ib.b.prof_bytes));
+    std::vector<AdiDesc> hd(np);
+    hac.assign(np, AdiCtl{});
+    bool any_setup = false;
+    for (int p = 0; p < np; ++p) {
+      Prob* q = act[p];
+      AdiDesc& ad = hd[p];
+      ad.n = q->n;
+      ad.m = q->m;
+      ad.r = q->r;
+      ad.kmax = o.kmax;
+      ad.nshifts = q->nshifts;
+      ad.selection = o.selection;
+      ad.backlook = o.backlook;
+      ad.paper_abs = o.paper_abs;
+      ad.rescale = o.rescale;
+      ad.setup = q->set_up ? 0 : 1;
+      any_setup = any_setup || !q->set_up;
+      ad.tol = q->tol;
+      ad.eps_in = o.eps;
+      ad.delta_min = o.delta_min;
+      ad.delta_max = o.delta_max;
+      ad.xi = o.xi;
+      ad.delta_fixed = o.delta_fixed;
+      ad.rho = o.rho;
+      ad.shiftsA = q->shA.as<double>();
+      ad.shiftsB = q->shB.as<double>();
+      ad.f = q->f;
+      ad.g = q->g;
+      ad.W = q->W.as<double>();
+      ad.T = q->T.as<double>();
+      ad.Zf = q->res->Zf.as<double>();
+      ad.Yf = q->res->Yf.as<double>();
+      ad.gam = q->gam.as<double>();
+      ad.hist = q->hist.as<double>();
+      hac[p] = q->hc;
+    }
+    if (dad.bytes < sizeof(AdiDesc) * np) LRADI_TRY(dad.alloc(sizeof(AdiDesc) * np));
+    if (dac.bytes < sizeof(AdiCtl) * np) LRADI_TRY(dac.alloc(sizeof(AdiCtl) * np));
+    LRADI_HIP(hipMemcpyAsync(dad.p, hd.data(), sizeof(AdiDesc) * np, hipMemcpyHostToDevice, st));
+    LRADI_HIP(hipMemcpyAsync(dac.p, hac.data(), sizeof(AdiCtl) * np, hipMemcpyHostToDevice, st));
+    if (any_setup) LRADI_TRY(adi_launch_setup(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np));
+    for (Prob* q : act) q->set_up = true;
+    dirty = false;
+    return LRADI_OK;
+  }
+
+  int finalize(Prob* q) {
+    lradi_result* R = q->res.get();
+    const AdiCtl& h = q->hc;
+    R->k = h.k;
+    R->norm_fg = h.norm_fg;
+    R->rel_res = h.norm_fg > 0.0 ? h.res / h.norm_fg : 0.0;
+    R->gam.assign(std::max(h.k, 0), 0.0);
+    R->hist.assign((size_t)std::max(h.k, 0) * kHistCols, 0.0);
+    if (h.k > 0) {
+      LRADI_HIP(hipMemcpy(R->gam.data(), q->gam.p, sizeof(double) * h.k, hipMemcpyDeviceToHost));
+      LRADI_HIP(hipMemcpy(R->hist.data(), q->hist.p, sizeof(double) * h.k * kHistCols, hipMemcpyDeviceToHost));
+    }
+    int status = h.status;
+    if (status == LRADI_OK && h.winner) status = LRADI_WINNER;
+    R->status = status;
+    R->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q->t0).count();
+    return LRADI_OK;
+  }
+
+  // One outer step of every active problem; finished problems are finalised,
+  // moved to `finished` and removed from the active set.
+  int step() {
+    if (act.empty()) return LRADI_OK;
+    hipStream_t st = c->stream;
+    if (dirty) LRADI_TRY(rebuild());
+    const int np = (int)act.size();
+    LRADI_TRY(c->done.init(np));
+    LRADI_TRY(adi_launch_prepare(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np));
+    LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner, o.profile != 0));
+    LRADI_TRY(adi_launch_finish(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np, c->done.d));
+    LRADI_HIP(hipMemcpyAsync(hac.data(), dac.p, sizeof(AdiCtl) * np, hipMemcpyDeviceToHost, st));
+    LRADI_HIP(hipStreamSynchronize(st));
+    std::vector<Prob*> keep;
+    for (int p = 0; p < np; ++p) {
+      act[p]->hc = hac[p];
+      if (hac[p].done) {
+        LRADI_TRY(finalize(act[p]));
+        finished.push_back(act[p]);
+        dirty = true;
+      } else {
+        keep.push_back(act[p]);
+      }
+    }
+    act.swap(keep);
+    return LRADI_OK;
+  }
+};
+
+}  // namespace
+}  // namespace lradi
+
 // ===========================================================================
 // C ABI
 extern "C" {
@@ -620,134 +847,36 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
 int lradi_solve(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const double* f,
                 const double* g, int r, const double* shiftsA, const double* shiftsB, int nshifts,
                 const lradi_opts* opts, lradi_result** out) {
-  if (!c || !A || !B || !f || !g || !shiftsA || !shiftsB || !out)
-    return set_error("lradi_solve: null argument"), LRADI_EINVAL;
-  *out = nullptr;
-  if (r < 1 || r > kMaxR) return set_error("lradi_solve: r must be in 1..%d", kMaxR), LRADI_EINVAL;
-  if (nshifts < 1) return set_error("lradi_solve: need at least one shift"), LRADI_EINVAL;
+  if (!out) return set_error("lradi_solve: null output"), LRADI_EINVAL;
+  lradi_problem P{A, B, f, g, r, nshifts, shiftsA, shiftsB, 0.0};
+  return lradi_batch_solve(c, 1, &P, opts, out);
+}
+
+int lradi_batch_solve(lradi_ctx* c, int nprob, const lradi_problem* probs, const lradi_opts* opts,
+                      lradi_result** outs) {
+  if (!c || nprob < 1 || !probs || !outs) return set_error("lradi_batch_solve: bad argument"), LRADI_EINVAL;
+  for (int i = 0; i < nprob; ++i) outs[i] = nullptr;
   lradi_opts o;
   lradi_default_opts(&o);
   if (opts) o = *opts;
   LRADI_TRY(check_opts(o));
-  for (int i = 0; i < nshifts; ++i)
-    if (!std::isfinite(shiftsA[i]) || !std::isfinite(shiftsB[i]))
-      return set_error("lradi_solve: non-finite shift"), LRADI_EINVAL;
   LRADI_HIP(hipSetDevice(c->device));
-  hipStream_t st = c->stream;
-  const auto t0 = std::chrono::steady_clock::now();
-
-  const bool f32 = o.precision == LRADI_FP32_INNER;
-  DevCSR dA, dBt;
-  LRADI_TRY(dA.upload(A, st, f32));
-  if (o.b_is_transposed) {
-    LRADI_TRY(dBt.upload(B, st, f32));
-  } else {
-    // form B^T on the host once
-    if (!B->rowptr || B->nrows <= 0 || B->nrows != B->ncols)
-      return set_error("lradi_solve: invalid B"), LRADI_EINVAL;
-    const int mB = B->nrows;
-    std::vector<int32_t> rp(mB + 1), ci, trp, tci;
-    std::vector<double> v, tv;
-    ci.resize(B->nnz);
-    v.resize(B->nnz);
-    if (B->on_device) {
-      LRADI_HIP(hipMemcpy(rp.data(), B->rowptr, sizeof(int32_t) * (mB + 1), hipMemcpyDeviceToHost));
-      LRADI_HIP(hipMemcpy(ci.data(), B->colind, sizeof(int32_t) * B->nnz, hipMemcpyDeviceToHost));
-      LRADI_HIP(hipMemcpy(v.data(), B->val, sizeof(double) * B->nnz, hipMemcpyDeviceToHost));
-    } else {
-      std::copy(B->rowptr, B->rowptr + mB + 1, rp.begin());
-      std::copy(B->colind, B->colind + B->nnz, ci.begin());
-      std::copy(B->val, B->val + B->nnz, v.begin());
-    }
-    if (rp[0] != 0 || rp[mB] != B->nnz) return set_error("lradi_solve: invalid B rowptr"), LRADI_EINVAL;
-    for (int64_t k = 0; k < B->nnz; ++k)
-      if (ci[k] < 0 || ci[k] >= mB) return set_error("lradi_solve: B column out of range"), LRADI_EINVAL;
-    csr_transpose(mB, rp.data(), ci.data(), v.data(), trp, tci, tv);
-    lradi_csr Bt{mB, mB, B->nnz, trp.data(), tci.data(), tv.data(), 0};
-    LRADI_TRY(dBt.upload(&Bt, st, f32));
-    LRADI_HIP(hipStreamSynchronize(st));
+  std::vector<std::unique_ptr<Prob>> ps(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    ps[i] = std::make_unique<Prob>();
+    LRADI_TRY(prob_init(c, o, probs[i], false, *ps[i]));
   }
-  const int n = dA.n, m = dBt.n;
-  auto res = std::make_unique<lradi_result>();
-  res->n = n;
-  res->m = m;
-  res->r = r;
-  res->kmax = o.kmax;
-  LRADI_TRY(res->Zf.alloc(sizeof(double) * (size_t)o.kmax * n * r));
-  LRADI_TRY(res->Yf.alloc(sizeof(double) * (size_t)o.kmax * m * r));
-  DevBuf W, T, shA, shB, gam, hist, dad, dac;
-  LRADI_TRY(W.alloc(sizeof(double) * (size_t)n * r));
-  LRADI_TRY(T.alloc(sizeof(double) * (size_t)m * r));
-  LRADI_TRY(shA.alloc(sizeof(double) * nshifts));
-  LRADI_TRY(shB.alloc(sizeof(double) * nshifts));
-  LRADI_TRY(gam.alloc(sizeof(double) * o.kmax));
-  LRADI_TRY(hist.alloc(sizeof(double) * (size_t)o.kmax * kHistCols));
-  LRADI_HIP(hipMemcpyAsync(shA.p, shiftsA, sizeof(double) * nshifts, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(shB.p, shiftsB, sizeof(double) * nshifts, hipMemcpyHostToDevice, st));
-
-  std::vector<SysSpec> specs(2);
-  const double fl = floor_for(o);
-  specs[0] = SysSpec{&dA, W.as<double>(), nullptr, 0.0, 0.0, r, o.restart, o.precision, o.max_inner, fl};
-  specs[1] = SysSpec{&dBt, T.as<double>(), nullptr, 0.0, 0.0, r, o.restart, o.precision, o.max_inner, fl};
-  InnerBatch ib;
-  LRADI_TRY(build_batch(c, specs, ib));
-  LRADI_TRY(prof_counters(c, o.profile != 0, &ib.b.prof_bytes));
-
-  AdiDesc ad{};
-  ad.n = n;
-  ad.m = m;
-  ad.r = r;
-  ad.kmax = o.kmax;
-  ad.nshifts = nshifts;
-  ad.selection = o.selection;
-  ad.backlook = o.backlook;
-  ad.paper_abs = o.paper_abs;
-  ad.rescale = o.rescale;
-  ad.tol = o.tol;
-  ad.eps_in = o.eps;
-  ad.delta_min = o.delta_min;
-  ad.delta_max = o.delta_max;
-  ad.xi = o.xi;
-  ad.delta_fixed = o.delta_fixed;
-  ad.rho = o.rho;
-  ad.shiftsA = shA.as<double>();
-  ad.shiftsB = shB.as<double>();
-  ad.f = f;
-  ad.g = g;
-  ad.W = W.as<double>();
-  ad.T = T.as<double>();
-  ad.Zf = res->Zf.as<double>();
-  ad.Yf = res->Yf.as<double>();
-  ad.gam = gam.as<double>();
-  ad.hist = hist.as<double>();
-  LRADI_TRY(dad.alloc(sizeof(AdiDesc)));
-  LRADI_TRY(dac.alloc(sizeof(AdiCtl)));
-  LRADI_HIP(hipMemcpyAsync(dad.p, &ad, sizeof(AdiDesc), hipMemcpyHostToDevice, st));
-  LRADI_TRY(c->done.init(1));
-  c->done.h[0] = 0;
-  LRADI_TRY(adi_launch_setup(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1));
-  for (int k = 0; k < o.kmax; ++k) {
-    LRADI_TRY(adi_launch_prepare(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1));
-    LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner, o.profile != 0));
-    LRADI_TRY(adi_launch_finish(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), 1, c->done.d));
-    LRADI_HIP(hipStreamSynchronize(st));
-    if (__atomic_load_n(c->done.h, __ATOMIC_ACQUIRE)) break;
+  Engine E(c, o);
+  for (auto& q : ps) E.act.push_back(q.get());
+  for (int k = 0; k < o.kmax + 1 && !E.act.empty(); ++k) LRADI_TRY(E.step());
+  if (!E.act.empty()) return set_error("lradi_batch_solve: problems left after kmax steps"), LRADI_EHIP;
+  int status = LRADI_OK;
+  for (int i = 0; i < nprob; ++i) {
+    const int st = ps[i]->res->status;
+    if (st < 0 && (status >= 0 || st < status)) status = st;
+    else if (status >= 0 && st > status) status = st;
+    outs[i] = ps[i]->res.release();
   }
-  AdiCtl hac;
-  LRADI_HIP(hipMemcpy(&hac, dac.p, sizeof(AdiCtl), hipMemcpyDeviceToHost));
-  const auto t1 = std::chrono::steady_clock::now();
-  res->k = hac.k;
-  res->norm_fg = hac.norm_fg;
-  res->rel_res = hac.norm_fg > 0.0 ? hac.res / hac.norm_fg : 0.0;
-  res->seconds = std::chrono::duration<double>(t1 - t0).count();
-  res->gam.resize(o.kmax);
-  res->hist.resize((size_t)o.kmax * kHistCols);
-  LRADI_HIP(hipMemcpy(res->gam.data(), gam.p, sizeof(double) * o.kmax, hipMemcpyDeviceToHost));
-  LRADI_HIP(hipMemcpy(res->hist.data(), hist.p, sizeof(double) * o.kmax * kHistCols, hipMemcpyDeviceToHost));
-  int status = hac.status;
-  if (status == LRADI_OK && hac.winner) status = LRADI_WINNER;
-  res->status = status;
-  *out = res.release();
   return status;
 }
 

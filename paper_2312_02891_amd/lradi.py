@@ -55,6 +55,13 @@ class Opts(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 4)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.POINTER(Csr)), ("B", ctypes.POINTER(Csr)), ("f", ctypes.c_void_p),
+                ("g", ctypes.c_void_p), ("r", ctypes.c_int32), ("nshifts", ctypes.c_int32),
+                ("shiftsA", ctypes.POINTER(ctypes.c_double)),
+                ("shiftsB", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double)]
+
+
 class KernelProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("bytes", ctypes.c_int64)]
 
@@ -92,6 +99,7 @@ def _load():
                                       P(Opts), P(InnerStats)]),
         "lradi_solve": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32, P(Opts),
                               P(vp)]),
+        "lradi_batch_solve": (i32, [vp, i32, P(Problem), P(Opts), P(vp)]),
         "lradi_result_info": (i32, [vp, P(i32), P(i32), P(dbl), P(dbl)]),
         "lradi_result_factors": (i32, [vp, P(vp), P(vp), P(vp), P(i32), P(i32), P(i32)]),
         "lradi_result_copy": (i32, [vp, vp, vp, vp]),
@@ -186,6 +194,7 @@ class Result:
         _check(_lib.lradi_result_info(self.h, ctypes.byref(k), ctypes.byref(st), ctypes.byref(rel),
                                       ctypes.byref(nfg)))
         self.k, self.rel_res, self.norm_fg = k.value, rel.value, nfg.value
+        self.status = st.value
         n, m, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         zp, dp, yp = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
         _check(_lib.lradi_result_factors(self.h, ctypes.byref(zp), ctypes.byref(dp),
@@ -298,6 +307,34 @@ class Context:
         return Zs, [dict(steps=s.steps, cycles=s.cycles, status=s.status, breakdowns=s.pad,
                          rnorm=s.rnorm) for s in stats], st
 
+    @staticmethod
+    def make_problem(A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0):
+        """(Problem struct, keep-alive list) for batch and serving calls."""
+        sA = np.ascontiguousarray(shiftsA, dtype=np.float64)
+        sB = np.ascontiguousarray(shiftsB, dtype=np.float64)
+        assert f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()
+        pr = Problem(ctypes.pointer(A.c), ctypes.pointer(B.c), f.data_ptr(), g.data_ptr(), f.shape[1],
+                     len(sA), sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tol))
+        return pr, [A, B, f, g, sA, sB]
+
+    def batch_solve(self, problems, opts: Optional[Opts] = None):
+        """problems: list of (A, B, f, g, shiftsA, shiftsB[, tol]); returns
+        (list of Result, overall status)."""
+        structs, keep = [], []
+        for pr in problems:
+            s_, k_ = self.make_problem(*pr)
+            structs.append(s_)
+            keep.append(k_)
+        n = len(structs)
+        arr = (Problem * n)(*structs)
+        outs = (ctypes.c_void_p * n)()
+        self._sync()
+        st = _lib.lradi_batch_solve(self.h, n, arr, ctypes.byref(opts) if opts is not None else None, outs)
+        results = [Result(outs[i], 0) if outs[i] else None for i in range(n)]
+        _check(st)
+        return results, st
+
     def residual(self, A: HostCsr, B: HostCsr, f, g, result: "Result", b_is_transposed=False):
         """True ||A X + X B + f g^T||_2 / ||f g^T||_2 of a solve result
         (lradi_residual on the result's device factors)."""
@@ -336,4 +373,5 @@ class Context:
                                      sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(sA),
                                      ctypes.byref(opts) if opts is not None else None,
                                      ctypes.byref(h)))
-        return Result(h.value, st)
+        res = Result(h.value, st)
+        return res

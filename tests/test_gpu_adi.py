@@ -167,3 +167,38 @@ def test_true_residual_random_factors_matches_dense(L, ctx, r, k, NA, NB):
     dense = np.linalg.norm(OF.true_residual_dense(A, B, f, g, X), 2) / np.linalg.norm(f @ g.T, 2)
     got = ctx.residual_factors(HA, HB, to_dev(f), to_dev(g), to_dev(Zs), gam, to_dev(Ys))
     assert got == pytest.approx(dense, rel=1e-9)
+
+
+def batch_inputs(L, count, seed=4):
+    probs = WL.batch_problems(count, seed=seed)
+    items = []
+    for P in probs:
+        # smaller grids than the full batched workload, same distributions
+        A = WL._op(2, max(8, P.A.N // 4), P.A.omega)
+        B = WL._op(2, max(8, P.B.N // 4), P.B.omega)
+        Q = WL.Problem(A, B, P.r, P.nshifts, P.seed)
+        HA, HB = L.convdiff(2, A.N, A.omega), L.convdiff(2, B.N, B.omega)
+        f, g = WL.rhs_factors(Q.seed, A.n, B.n, Q.r)
+        pA, pB = WL.wachspress_shifts(A, B, Q.nshifts)
+        items.append((Q, HA, HB, f, g, pA, pB))
+    return items
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_problems_equal_solo_and_oracle(L, ctx, prec):
+    """Uneven problems (grid sides 8..32, r in {1,2,4}) solved together give
+    exactly the factors of solving each alone, and each matches the oracle."""
+    say("batched", prec)
+    items = batch_inputs(L, 10)
+    o = L.default_opts(precision=prec)
+    devs = [(HA, HB, to_dev(f), to_dev(g), pA, pB) for (_, HA, HB, f, g, pA, pB) in items]
+    results, st = ctx.batch_solve(devs, o)
+    assert st in (L.OK,)
+    for (Q, HA, HB, f, g, pA, pB), dv, rb in zip(items, devs, results):
+        rs = ctx.solve(*dv, opts=o)
+        Zb, db, Yb = rb.factors()
+        Zs, ds, Ys = rs.factors()
+        assert rb.k == rs.k and np.array_equal(Zb, Zs) and np.array_equal(Yb, Ys)
+        A = convdiff_matrix(2, Q.A.N, Q.A.omega)
+        B = convdiff_matrix(2, Q.B.N, Q.B.omega)
+        compare(L, rb, A, B, f, g, pA, pB, Q.tol, kslack=1)
