@@ -45,6 +45,7 @@ extern "C" {
 #define LRADI_EHIP (-3)        /* a HIP runtime call failed                       */
 #define LRADI_ENAN (-4)        /* NaN or Inf appeared in the iteration            */
 #define LRADI_EBREAKDOWN (-5)  /* unrecoverable Krylov breakdown                  */
+#define LRADI_ECANCELED (-6)   /* serving request cancelled before completion    */
 #define LRADI_WNOCONV 1        /* kmax outer steps without reaching tau          */
 #define LRADI_WINNER 2         /* some inner solve stopped at its iteration cap   */
 
@@ -218,6 +219,44 @@ typedef struct {
  * return value is the most severe status over the problems. */
 int lradi_batch_solve(lradi_ctx* ctx, int nprob, const lradi_problem* probs,
                       const lradi_opts* opts, lradi_result** outs);
+
+/* ---- serving: continuous batching over one context --------------------
+ * A worker thread owned by the server admits queued problems whenever their
+ * device footprint fits in hbm_budget bytes (and fewer than max_active are
+ * in flight), advances every admitted problem one outer LR-ADI step per
+ * iteration in shared kernel launches (as lradi_batch_solve), and completes
+ * finished problems at step boundaries, so requests that arrive while
+ * others run join as memory and slots free up.  Admission is first come,
+ * first served.  While a server exists its context must not be used by the
+ * caller.  submit / poll / cancel / stats may be called from any one thread. */
+typedef struct lradi_server lradi_server;
+typedef struct {
+  int32_t active;          /* problems in flight                              */
+  int32_t queued;          /* submitted, not yet admitted                     */
+  int64_t completed;       /* finished (including failed and cancelled)       */
+  int64_t steps;           /* outer steps run by the worker                   */
+  int64_t bytes_in_use;    /* summed footprint of the problems in flight      */
+  int64_t bytes_budget;
+} lradi_server_counters;
+
+/* max_active <= 0: no slot limit.  hbm_budget == 0: 80% of the device's
+ * free memory at creation. */
+int lradi_server_create(lradi_ctx* ctx, const lradi_opts* opts, int64_t hbm_budget,
+                        int max_active, lradi_server** out);
+/* Queue one problem.  The inputs are copied before the call returns (f, g
+ * device, shifts host, matrices host or device).  *ticket identifies it.
+ * LRADI_ENOMEM if the problem alone exceeds the budget (it is rejected). */
+int lradi_server_submit(lradi_server* srv, const lradi_problem* prob, uint64_t* ticket);
+/* 0: done, *out receives the result (caller frees it) and *latency_s the
+ * time from submit to completion; 1: still pending; LRADI_EINVAL: unknown
+ * ticket (or already collected). */
+int lradi_server_poll(lradi_server* srv, uint64_t ticket, lradi_result** out, double* latency_s);
+/* Cancel a queued or running request; it completes with LRADI_ECANCELED. */
+int lradi_server_cancel(lradi_server* srv, uint64_t ticket);
+int lradi_server_stats(lradi_server* srv, lradi_server_counters* out);
+/* Stop the worker (running problems are cancelled) and free everything not
+ * yet collected. */
+int lradi_server_destroy(lradi_server* srv);
 
 /* Scalars of a result: steps k, status, ||w_k t_k^T||/||f g^T||, ||f g^T||
  * (after the optional rescaling, which leaves f g^T unchanged). */

@@ -9,7 +9,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "adi.h"
@@ -744,6 +749,7 @@ const char* lradi_strerror(int st) {
     case LRADI_EBREAKDOWN: return "Krylov breakdown";
     case LRADI_WNOCONV: return "outer iteration reached kmax";
     case LRADI_WINNER: return "an inner solve reached its step cap";
+    case LRADI_ECANCELED: return "request cancelled";
     default: return "unknown status";
   }
 }
@@ -978,6 +984,287 @@ int lradi_residual(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, int b_i
   LRADI_TRY(residual_norm(st, dA, dAt, dB, dBt, f, g, r, Z, gam.as<double>(), Y, 0, r + 2, &sfg));
   LRADI_HIP(hipStreamSynchronize(st));
   *rel = (sfg > 0.0) ? sres / sfg : 0.0;
+  return LRADI_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// serving
+}  // extern "C"
+
+struct lradi_server {
+  lradi_ctx* ctx = nullptr;
+  lradi_opts opts{};
+  int64_t budget = 0;
+  int max_active = 0;
+  // host copies of a submitted problem until the worker uploads it
+  struct Pending {
+    uint64_t ticket;
+    std::vector<int32_t> arp, aci, brp, bci;
+    std::vector<double> aval, bval, f, g, sA, sB;
+    int r = 0, n = 0, m = 0;
+    double tol = 0.0;
+    size_t footprint = 0;
+    std::chrono::steady_clock::time_point t_submit;
+  };
+  struct Done {
+    lradi_result* res = nullptr;
+    double latency = 0.0;
+  };
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Pending> queue;
+  std::map<uint64_t, Done> done;
+  std::map<uint64_t, std::chrono::steady_clock::time_point> submitted;
+  std::vector<uint64_t> cancel_req;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int worker_error = LRADI_OK;
+  lradi_server_counters st{};
+  std::thread worker;
+  void run();
+};
+
+namespace lradi {
+namespace {
+struct Live {
+  std::unique_ptr<Prob> prob;
+  uint64_t ticket;
+  size_t footprint;
+};
+}  // namespace
+}  // namespace lradi
+
+void lradi_server::run() {
+  (void)hipSetDevice(ctx->device);
+  Engine E(ctx, opts);
+  std::map<Prob*, Live> live;
+  int64_t used = 0;
+  auto complete = [&](Prob* q, int status_override) {
+    auto it = live.find(q);
+    Live L = std::move(it->second);
+    live.erase(it);
+    used -= (int64_t)L.footprint;
+    lradi_result* R = L.prob->res.release();
+    if (status_override != 0) R->status = status_override;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto now = std::chrono::steady_clock::now();
+    Done d;
+    d.res = R;
+    d.latency = std::chrono::duration<double>(now - submitted[L.ticket]).count();
+    submitted.erase(L.ticket);
+    done[L.ticket] = d;
+    st.completed += 1;
+  };
+  for (;;) {
+    std::vector<Pending> admit;
+    std::vector<uint64_t> cancels;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (E.act.empty() && queue.empty() && !stop)
+        cv.wait_for(lk, std::chrono::milliseconds(50));
+      if (stop) break;
+      while (!queue.empty() && (max_active <= 0 || (int)E.act.size() + (int)admit.size() < max_active) &&
+             used + (int64_t)queue.front().footprint <= budget) {
+        used += (int64_t)queue.front().footprint;
+        admit.push_back(std::move(queue.front()));
+        queue.pop_front();
+      }
+      cancels.swap(cancel_req);
+      st.queued = (int)queue.size();
+    }
+    for (Pending& P : admit) {
+      auto q = std::make_unique<Prob>();
+      lradi_csr A{P.n, P.n, (int64_t)P.aci.size(), P.arp.data(), P.aci.data(), P.aval.data(), 0};
+      lradi_csr B{P.m, P.m, (int64_t)P.bci.size(), P.brp.data(), P.bci.data(), P.bval.data(), 0};
+      DevBuf fd, gd;
+      int rc = fd.alloc(sizeof(double) * P.f.size());
+      if (rc == LRADI_OK) rc = gd.alloc(sizeof(double) * P.g.size());
+      if (rc == LRADI_OK && hipMemcpy(fd.p, P.f.data(), sizeof(double) * P.f.size(), hipMemcpyHostToDevice) != hipSuccess)
+        rc = LRADI_EHIP;
+      if (rc == LRADI_OK && hipMemcpy(gd.p, P.g.data(), sizeof(double) * P.g.size(), hipMemcpyHostToDevice) != hipSuccess)
+        rc = LRADI_EHIP;
+      lradi_problem pr{&A, &B, fd.as<double>(), gd.as<double>(), P.r, (int32_t)P.sA.size(), P.sA.data(),
+                       P.sB.data(), P.tol};
+      if (rc == LRADI_OK) rc = prob_init(ctx, opts, pr, true, *q);
+      Prob* raw = q.get();
+      live[raw] = Live{std::move(q), P.ticket, P.footprint};
+      if (rc != LRADI_OK) {
+        if (!raw->res) raw->res = std::make_unique<lradi_result>();
+        complete(raw, rc);
+        continue;
+      }
+      E.act.push_back(raw);
+      E.dirty = true;
+    }
+    // cancellations of running problems
+    if (!cancels.empty()) {
+      std::vector<Prob*> keep;
+      for (Prob* q : E.act) {
+        const uint64_t t = live[q].ticket;
+        if (std::find(cancels.begin(), cancels.end(), t) != cancels.end()) {
+          E.dirty = true;
+          if (E.finalize(q) == LRADI_OK) complete(q, LRADI_ECANCELED);
+        } else {
+          keep.push_back(q);
+        }
+      }
+      E.act.swap(keep);
+    }
+    if (E.act.empty()) {
+      std::lock_guard<std::mutex> lk(mu);
+      st.active = 0;
+      st.bytes_in_use = used;
+      continue;
+    }
+    const int rc = E.step();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      st.steps += 1;
+    }
+    if (rc < 0) {
+      // a device error ends every problem in flight with that status
+      std::vector<Prob*> all = E.act;
+      E.act.clear();
+      for (Prob* q : all) {
+        (void)E.finalize(q);
+        complete(q, rc);
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      worker_error = rc;
+    }
+    std::vector<Prob*> fin;
+    fin.swap(E.finished);
+    for (Prob* q : fin) complete(q, 0);
+    std::lock_guard<std::mutex> lk(mu);
+    st.active = (int)E.act.size();
+    st.bytes_in_use = used;
+  }
+  // shutdown: cancel whatever is still running
+  std::vector<Prob*> all = E.act;
+  E.act.clear();
+  for (Prob* q : all) {
+    (void)E.finalize(q);
+    complete(q, LRADI_ECANCELED);
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+}
+
+extern "C" {
+
+int lradi_server_create(lradi_ctx* c, const lradi_opts* opts, int64_t hbm_budget, int max_active,
+                        lradi_server** out) {
+  if (!c || !out) return set_error("lradi_server_create: null argument"), LRADI_EINVAL;
+  *out = nullptr;
+  lradi_opts o;
+  lradi_default_opts(&o);
+  if (opts) o = *opts;
+  LRADI_TRY(check_opts(o));
+  LRADI_HIP(hipSetDevice(c->device));
+  if (hbm_budget <= 0) {
+    size_t fr = 0, tot = 0;
+    LRADI_HIP(hipMemGetInfo(&fr, &tot));
+    hbm_budget = (int64_t)(0.8 * (double)fr);
+  }
+  auto* s = new lradi_server();
+  s->ctx = c;
+  s->opts = o;
+  s->budget = hbm_budget;
+  s->max_active = max_active;
+  s->st.bytes_budget = hbm_budget;
+  s->worker = std::thread([s] { s->run(); });
+  *out = s;
+  return LRADI_OK;
+}
+
+int lradi_server_submit(lradi_server* s, const lradi_problem* P, uint64_t* ticket) {
+  if (!s || !P || !ticket || !P->A || !P->B || !P->f || !P->g || !P->shiftsA || !P->shiftsB)
+    return set_error("lradi_server_submit: null argument"), LRADI_EINVAL;
+  if (P->r < 1 || P->r > kMaxR || P->nshifts < 1)
+    return set_error("lradi_server_submit: bad r or nshifts"), LRADI_EINVAL;
+  lradi_server::Pending q;
+  q.r = P->r;
+  q.tol = P->tol;
+  LRADI_TRY(host_csr(P->A, q.arp, q.aci, q.aval));
+  LRADI_TRY(host_csr(P->B, q.brp, q.bci, q.bval));
+  q.n = P->A->nrows;
+  q.m = P->B->nrows;
+  q.f.resize((size_t)q.n * q.r);
+  q.g.resize((size_t)q.m * q.r);
+  LRADI_HIP(hipMemcpy(q.f.data(), P->f, sizeof(double) * q.f.size(), hipMemcpyDeviceToHost));
+  LRADI_HIP(hipMemcpy(q.g.data(), P->g, sizeof(double) * q.g.size(), hipMemcpyDeviceToHost));
+  q.sA.assign(P->shiftsA, P->shiftsA + P->nshifts);
+  q.sB.assign(P->shiftsB, P->shiftsB + P->nshifts);
+  q.footprint = prob_footprint(q.n, q.m, q.r, (int64_t)q.aci.size(), (int64_t)q.bci.size(), s->opts);
+  if ((int64_t)q.footprint > s->budget)
+    return set_error("lradi_server_submit: footprint %zu bytes exceeds the budget", q.footprint), LRADI_ENOMEM;
+  q.t_submit = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    q.ticket = s->next_ticket++;
+    *ticket = q.ticket;
+    s->submitted[q.ticket] = q.t_submit;
+    s->queue.push_back(std::move(q));
+    s->st.queued = (int)s->queue.size();
+  }
+  s->cv.notify_one();
+  return LRADI_OK;
+}
+
+int lradi_server_poll(lradi_server* s, uint64_t ticket, lradi_result** out, double* latency) {
+  if (!s || !out) return set_error("lradi_server_poll: null argument"), LRADI_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->done.find(ticket);
+  if (it != s->done.end()) {
+    *out = it->second.res;
+    if (latency) *latency = it->second.latency;
+    s->done.erase(it);
+    return 0;
+  }
+  if (s->submitted.count(ticket)) return 1;
+  return set_error("lradi_server_poll: unknown ticket"), LRADI_EINVAL;
+}
+
+int lradi_server_cancel(lradi_server* s, uint64_t ticket) {
+  if (!s) return set_error("lradi_server_cancel: null server"), LRADI_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+    if (it->ticket == ticket) {
+      auto* R = new lradi_result();
+      R->status = LRADI_ECANCELED;
+      lradi_server::Done d;
+      d.res = R;
+      d.latency = std::chrono::duration<double>(std::chrono::steady_clock::now() - it->t_submit).count();
+      s->done[ticket] = d;
+      s->submitted.erase(ticket);
+      s->queue.erase(it);
+      s->st.completed += 1;
+      s->st.queued = (int)s->queue.size();
+      return LRADI_OK;
+    }
+  }
+  if (!s->submitted.count(ticket)) return set_error("lradi_server_cancel: unknown ticket"), LRADI_EINVAL;
+  s->cancel_req.push_back(ticket);
+  return LRADI_OK;
+}
+
+int lradi_server_stats(lradi_server* s, lradi_server_counters* out) {
+  if (!s || !out) return set_error("lradi_server_stats: null argument"), LRADI_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  return s->worker_error < 0 ? s->worker_error : LRADI_OK;
+}
+
+int lradi_server_destroy(lradi_server* s) {
+  if (!s) return LRADI_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->done) delete kv.second.res;
+  delete s;
   return LRADI_OK;
 }
 

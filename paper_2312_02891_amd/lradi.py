@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblradi.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENAN, EBREAKDOWN = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENAN, EBREAKDOWN, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 WNOCONV, WINNER = 1, 2
 SEL_RELATIVE, SEL_FIXED, SEL_MID, SEL_TIGHT_A, SEL_TIGHT_B = 0, 1, 2, 3, 4
 FP64, FP32_INNER = 0, 1
@@ -62,6 +62,12 @@ class Problem(ctypes.Structure):
                 ("shiftsB", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double)]
 
 
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("queued", ctypes.c_int32), ("completed", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("bytes_in_use", ctypes.c_int64),
+                ("bytes_budget", ctypes.c_int64)]
+
+
 class KernelProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("bytes", ctypes.c_int64)]
 
@@ -100,6 +106,12 @@ def _load():
         "lradi_solve": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32, P(Opts),
                               P(vp)]),
         "lradi_batch_solve": (i32, [vp, i32, P(Problem), P(Opts), P(vp)]),
+        "lradi_server_create": (i32, [vp, P(Opts), ctypes.c_int64, i32, P(vp)]),
+        "lradi_server_submit": (i32, [vp, P(Problem), P(ctypes.c_uint64)]),
+        "lradi_server_poll": (i32, [vp, ctypes.c_uint64, P(vp), P(dbl)]),
+        "lradi_server_cancel": (i32, [vp, ctypes.c_uint64]),
+        "lradi_server_stats": (i32, [vp, P(ServerCounters)]),
+        "lradi_server_destroy": (i32, [vp]),
         "lradi_result_info": (i32, [vp, P(i32), P(i32), P(dbl), P(dbl)]),
         "lradi_result_factors": (i32, [vp, P(vp), P(vp), P(vp), P(i32), P(i32), P(i32)]),
         "lradi_result_copy": (i32, [vp, vp, vp, vp]),
@@ -375,3 +387,53 @@ class Context:
                                      ctypes.byref(h)))
         res = Result(h.value, st)
         return res
+
+
+class Server:
+    """Continuous-batching request loop (lradi_server_*) on a context that the
+    caller must not use while the server lives."""
+
+    def __init__(self, ctx: Context, opts: Optional[Opts] = None, hbm_budget: int = 0,
+                 max_active: int = 0):
+        h = ctypes.c_void_p()
+        ctx._sync()
+        _check(_lib.lradi_server_create(ctx.h, ctypes.byref(opts) if opts is not None else None,
+                                        int(hbm_budget), int(max_active), ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+
+    def submit(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0) -> int:
+        pr, keep = Context.make_problem(A, B, f, g, shiftsA, shiftsB, tol)
+        t = ctypes.c_uint64()
+        _torch().cuda.synchronize()
+        _check(_lib.lradi_server_submit(self.h, ctypes.byref(pr), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """(Result, latency seconds) when done, else None."""
+        out = ctypes.c_void_p()
+        lat = ctypes.c_double()
+        st = _lib.lradi_server_poll(self.h, ticket, ctypes.byref(out), ctypes.byref(lat))
+        if st == 1:
+            return None
+        _check(st)
+        return Result(out.value, 0), lat.value
+
+    def cancel(self, ticket: int):
+        _check(_lib.lradi_server_cancel(self.h, ticket))
+
+    def stats(self):
+        c = ServerCounters()
+        _check(_lib.lradi_server_stats(self.h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in ServerCounters._fields_}
+
+    def close(self):
+        if self.h:
+            _lib.lradi_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
