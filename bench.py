@@ -40,6 +40,12 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the tight / FP32 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented solve")
+    ap.add_argument("--no-probe", action="store_true", help="skip the beyond-LLC SpMM probe")
+    ap.add_argument("--workload", default="c2", choices=["c2", "batch", "serve"],
+                    help="c2: the metric's configuration (default); batch: 256 independent "
+                         "problems; serve: Poisson request stream")
+    ap.add_argument("--count", type=int, default=0, help="problems (batch) or requests (serve)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     return ap.parse_args()
 
 
@@ -55,6 +61,10 @@ def main():
     from paper_2312_02891_amd import lradi as L
     from paper_2312_02891_amd import workloads as WL
 
+    if args.workload == "batch":
+        return bench_batch(args, L, WL)
+    if args.workload == "serve":
+        return bench_serve(args, L, WL)
     P = WL.C2
     HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
     HBt = L.convdiff(P.B.dim, P.B.N, tuple(-w for w in P.B.omega))   # B^T (bit-identical)
@@ -125,6 +135,20 @@ def main():
               f"{extra['spmm_avg_launch_us']} us, {extra['spmm_effective_GBs']} GB/s", file=sys.stderr,
               flush=True)
 
+    if not args.no_probe:
+        # beyond-LLC shape: 3-D N=160 (n = 4.1M, nnz = 28.5M), r = 8, FP32 (507 MB per product)
+        Hp = L.convdiff(3, WL.PROBE.N, WL.PROBE.omega)
+        Xp = torch.randn(Hp.n, WL.PROBE_R, dtype=torch.float32, device="cuda",
+                         generator=torch.Generator(device="cuda").manual_seed(WL.PROBE_SEED))
+        pms, pbytes = ctx.spmm_bench(Hp, -1000.0, Xp, reps=20)
+        extra["spmm_probe_n"] = Hp.n
+        extra["spmm_probe_us"] = round(pms * 1e3, 2)
+        extra["spmm_probe_GBs"] = round(pbytes / (pms * 1e-3) / 1e9, 1)
+        extra["spmm_probe_frac_hbm"] = round(pbytes / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        print(f"[bench] spmm probe: {pms * 1e3:.1f} us, {extra['spmm_probe_GBs']} GB/s", file=sys.stderr,
+              flush=True)
+        del Xp
+
     cpu = None
     if not args.no_cpu:
         cpu, xerr = cpu_baseline(P, f, g, pA, pB, res)
@@ -184,6 +208,95 @@ def cpu_baseline(P, f, g, pA, pB, res):
              "sample": "one full oracle solve of the same problem (SciPy SuperLU per distinct "
                        "shift, single-threaded factorisations, BLAS threads for the small "
                        "dense steps)"}, float(xerr))
+
+
+def _batch_items(WL, L, count):
+    import torch
+    items = []
+    for P in WL.batch_problems(count):
+        HA = L.convdiff(2, P.A.N, P.A.omega)
+        HB = L.convdiff(2, P.B.N, P.B.omega)
+        f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+        pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+        items.append((HA, HB, torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), pA, pB))
+    return items
+
+
+def bench_batch(args, L, WL):
+    """256 independent 2-D problems (grid side 32..128, r in {1,2,4}), FP32
+    inner / FP64 outer, all advanced together; compared with solving them one
+    after another on the same GPU."""
+    import torch
+    count = args.count or 256
+    items = _batch_items(WL, L, count)
+    ctx = L.Context(0)
+    o = L.default_opts(precision="fp32")
+    ctx.batch_solve(items[: min(8, count)], o)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, st = ctx.batch_solve(items, o)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    nseq = min(count, 32)
+    t0 = time.perf_counter()
+    for it in items[:nseq]:
+        ctx.solve(*it, opts=o)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) * count / nseq
+    ks = [r.k for r in res]
+    ctx.close()
+    print(json.dumps({"workload": f"batch of {count} 2-D problems, FP32 inner / FP64 outer",
+                      "batched_s": round(tb, 4), "sequential_s_est": round(ts, 4),
+                      "sequential_sample": nseq, "speedup": round(ts / tb, 2),
+                      "solves_per_s": round(count / tb, 2), "status": st,
+                      "outer_steps_min_max": [min(ks), max(ks)],
+                      "all_converged": all(r.status == 0 for r in res)}))
+
+
+def bench_serve(args, L, WL):
+    """Poisson stream of Sylvester solves (2-D/3-D, n, m log-uniform, r 1..8,
+    residual target log-uniform in [1e-10, 1e-6]) through the continuous-
+    batching server; latency = completion - submission."""
+    import numpy as np
+    import torch
+    count = args.count or 200
+    reqs = WL.serving_requests(count, rate=args.rate, nmax=args.nmax if hasattr(args, "nmax") else 262144)
+    prepared = []
+    for t, P in reqs:
+        HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+        HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
+        f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+        pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+        prepared.append((t, P, HA, HB, torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), pA, pB))
+    ctx = L.Context(0)
+    srv = L.Server(ctx, L.default_opts(), hbm_budget=0, max_active=64)
+    tickets, lat, status = [], {}, {}
+    t0 = time.perf_counter()
+    i = 0
+    while len(lat) < count:
+        now = time.perf_counter() - t0
+        while i < count and prepared[i][0] <= now:
+            t, P, HA, HB, fd, gd, pA, pB = prepared[i]
+            tickets.append(srv.submit(HA, HB, fd, gd, pA, pB, tol=P.tol))
+            i += 1
+        for tk in tickets:
+            if tk not in lat:
+                got = srv.poll(tk)
+                if got is not None:
+                    lat[tk] = got[1]
+                    status[tk] = got[0].status
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    ctx.close()
+    arr = np.array([lat[t] for t in tickets])
+    print(json.dumps({"workload": f"{count} Poisson requests at {args.rate}/s",
+                      "p50_s": round(float(np.percentile(arr, 50)), 4),
+                      "p99_s": round(float(np.percentile(arr, 99)), 4),
+                      "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
+                      "offered_rate": args.rate, "ok": sum(1 for v in status.values() if v == 0),
+                      "outer_steps_run": stats["steps"]}))
 
 
 if __name__ == "__main__":

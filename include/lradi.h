@@ -174,6 +174,14 @@ int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* rowptr,
 int lradi_spmm(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X,
                void* Y, int r, int precision);
 
+/* Measurement helper for the shifted product: copies A to the device once,
+ * then launches the product Y = (A + shift I) X reps times back to back and
+ * returns the average launch time in milliseconds (HIP events on the
+ * context's stream) and the algorithmic bytes of one launch (values,
+ * column indices, row pointers, X read once, Y written once). */
+int lradi_spmm_bench(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X, void* Y,
+                     int r, int precision, int reps, double* avg_ms, int64_t* bytes);
+
 /* Solve nsys independent shifted block systems (A_s + shift_s I) Z_s = W_s
  * with block GMRES(m) plus FP64 iterative refinement until
  * ||W_s - (A_s + shift_s I) Z_s||_2 <= delta_s (absolute, spectral norm) --
@@ -207,7 +215,9 @@ typedef struct {
   int32_t nshifts;
   const double* shiftsA;   /* host, nshifts (added to A)                       */
   const double* shiftsB;   /* host, nshifts (added to B^T)                     */
-  double tol;              /* outer tau of this problem; <= 0 uses opts->tol   */
+  double tol;              /* outer tau of this problem; <= 0 uses opts->tol.
+                              opts->delta_min and opts->delta_fixed refer to
+                              opts->tol and are scaled by tol / opts->tol     */
 } lradi_problem;
 
 /* Algorithm 1 on nprob independent problems of uneven n, m, r advanced

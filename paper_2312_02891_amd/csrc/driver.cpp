@@ -633,10 +633,13 @@ struct Engine {
       any_setup = any_setup || !q->set_up;
       ad.tol = q->tol;
       ad.eps_in = o.eps;
-      ad.delta_min = o.delta_min;
+      // delta_min and delta_fixed are given for opts.tol (the paper's tau/20);
+      // a problem with its own tolerance scales them with it
+      const double ts = q->tol / o.tol;
+      ad.delta_min = o.delta_min * ts;
       ad.delta_max = o.delta_max;
       ad.xi = o.xi;
-      ad.delta_fixed = o.delta_fixed;
+      ad.delta_fixed = o.delta_fixed * ts;
       ad.rho = o.rho;
       ad.shiftsA = q->shA.as<double>();
       ad.shiftsB = q->shB.as<double>();
@@ -805,6 +808,38 @@ int lradi_spmm(lradi_ctx* c, const lradi_csr* A, double shift, const void* X, vo
   LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(),
                               dA.colind.as<int>(), val, shift, X, Y));
   LRADI_HIP(hipStreamSynchronize(c->stream));
+  return LRADI_OK;
+}
+
+int lradi_spmm_bench(lradi_ctx* c, const lradi_csr* A, double shift, const void* X, void* Y, int r,
+                     int precision, int reps, double* avg_ms, int64_t* bytes) {
+  if (!c || !X || !Y || !avg_ms || reps < 1) return set_error("lradi_spmm_bench: bad argument"), LRADI_EINVAL;
+  if (r < 1 || r > kMaxR) return set_error("lradi_spmm_bench: r must be in 1..%d", kMaxR), LRADI_EINVAL;
+  if (precision != LRADI_FP64 && precision != LRADI_FP32_INNER)
+    return set_error("lradi_spmm_bench: unknown precision"), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  DevCSR dA;
+  LRADI_TRY(dA.upload(A, c->stream, precision == LRADI_FP32_INNER));
+  const void* val = (precision == LRADI_FP64) ? dA.val64.p : dA.val32.p;
+  hipEvent_t e0, e1;
+  LRADI_HIP(hipEventCreate(&e0));
+  LRADI_HIP(hipEventCreate(&e1));
+  int rc = launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(), dA.colind.as<int>(), val,
+                             shift, X, Y);  // warm-up
+  if (rc == LRADI_OK) rc = hipEventRecord(e0, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  for (int i = 0; i < reps && rc == LRADI_OK; ++i)
+    rc = launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(), dA.colind.as<int>(), val,
+                           shift, X, Y);
+  if (rc == LRADI_OK) rc = hipEventRecord(e1, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  float ms = 0.f;
+  if (rc == LRADI_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  if (rc == LRADI_OK) rc = hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != LRADI_OK) return set_error("lradi_spmm_bench: launch or event failure"), LRADI_EHIP;
+  *avg_ms = (double)ms / reps;
+  const int64_t tsz = precision == LRADI_FP64 ? 8 : 4;
+  if (bytes) *bytes = dA.nnz * (tsz + 4) + 4 * ((int64_t)dA.n + 1) + 2 * tsz * (int64_t)dA.n * r;
   return LRADI_OK;
 }
 

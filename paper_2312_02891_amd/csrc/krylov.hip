@@ -840,26 +840,24 @@ __global__ __launch_bounds__(kTPB) void k_summary(const SysCtl* __restrict__ ctl
   }
 }
 
-// plain Y = (A + s I) X for one block (no phases)
+// plain Y = (A + s I) X for one block (no phases); the same row routine as
+// the solver's shifted product
 template <typename T, int R>
 __global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
                                                      const T* __restrict__ val, T shift,
                                                      const T* __restrict__ X, T* __restrict__ Y) {
-  const int i = blockIdx.x * kTPB + threadIdx.x;
-  if (i >= n) return;
-  T acc[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) acc[q] = T(0);
-  const int k0 = rp[i], k1 = rp[i + 1];
-  for (int k = k0; k < k1; ++k) {
-    const int col = ci[k];
-    const T a = val[k];
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] += a * X[(size_t)col * R + q];
-  }
-#pragma unroll
-  for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = acc[q] + shift * X[(size_t)i * R + q];
+  SysDesc D{};
+  D.n = n;
+  D.rowptr = rp;
+  D.colind = ci;
+  D.valT = val;
+  RowCtx c;
+  c.s = 0;
+  c.w = blockIdx.x;
+  c.row0 = blockIdx.x * kTPB;
+  c.row1 = min(n, c.row0 + kTPB);
+  spmm_rows<T, R>(D, c, shift, X, Y);
 }
 
 template <typename T, int RF>

@@ -101,6 +101,7 @@ def _load():
         "lradi_convdiff_size": (i32, [i32, i32, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "lradi_gen_convdiff": (i32, [i32, i32, P(dbl), vp, vp, vp]),
         "lradi_spmm": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32]),
+        "lradi_spmm_bench": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32, i32, P(dbl), P(ctypes.c_int64)]),
         "lradi_shifted_solve": (i32, [vp, i32, P(P(Csr)), P(dbl), P(vp), P(vp), P(i32), P(dbl),
                                       P(Opts), P(InnerStats)]),
         "lradi_solve": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32, P(Opts),
@@ -299,6 +300,18 @@ class Context:
         _check(_lib.lradi_spmm(self.h, ctypes.byref(A.c), float(shift), _ptr(X), _ptr(Y),
                                X.shape[1], prec), allow_warn=False)
         return Y
+
+    def spmm_bench(self, A: HostCsr, shift: float, X, reps: int = 20):
+        """(average ms per launch, algorithmic bytes per launch) of the
+        shifted product on X (FP64 or FP32 CUDA tensor)."""
+        torch = _torch()
+        prec = FP64 if X.dtype == torch.float64 else FP32_INNER
+        Y = torch.empty_like(X)
+        ms, nb = ctypes.c_double(), ctypes.c_int64()
+        self._sync()
+        _check(_lib.lradi_spmm_bench(self.h, ctypes.byref(A.c), float(shift), _ptr(X), _ptr(Y), X.shape[1],
+                                     prec, reps, ctypes.byref(ms), ctypes.byref(nb)), allow_warn=False)
+        return ms.value, nb.value
 
     def shifted_solve(self, mats: List[HostCsr], shifts, Ws, deltas, opts: Optional[Opts] = None):
         """Batched (A_s + shift_s I) Z_s = W_s to ||R_s||_2 <= delta_s; returns (Zs, stats)."""
