@@ -273,8 +273,12 @@ def bench_serve(args, L, WL):
     tickets, lat, status = [], {}, {}
     t0 = time.perf_counter()
     i = 0
+    t_note = 0.0
     while len(lat) < count:
         now = time.perf_counter() - t0
+        if now - t_note > 5.0:
+            t_note = now
+            print(f"serve: t={now:.1f}s submitted={i} completed={len(lat)}", file=sys.stderr, flush=True)
         while i < count and prepared[i][0] <= now:
             t, P, HA, HB, fd, gd, pA, pB = prepared[i]
             tickets.append(srv.submit(HA, HB, fd, gd, pA, pB, tol=P.tol))

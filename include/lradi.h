@@ -244,7 +244,7 @@ typedef struct {
   int32_t active;          /* problems in flight                              */
   int32_t queued;          /* submitted, not yet admitted                     */
   int64_t completed;       /* finished (including failed and cancelled)       */
-  int64_t steps;           /* outer steps run by the worker                   */
+  int64_t steps;           /* scheduling rounds run by the worker             */
   int64_t bytes_in_use;    /* summed footprint of the problems in flight      */
   int64_t bytes_budget;
 } lradi_server_counters;

@@ -22,6 +22,7 @@ struct AdiDesc {
   double* Yf;             // factor blocks y_1..y_kmax, kmax x m x r
   double* gam;            // gamma_1..gamma_kmax
   double* hist;           // kmax x LRADI_HIST_COLS
+  int* host_done;         // host-visible flag set to 1 when the problem finishes
 };
 
 // Mutable outer state of one problem.
@@ -33,9 +34,12 @@ struct AdiCtl {
   double norm_fg, eps, nw, nt, u, v, res, sf, sg, dA, dB;
 };
 
+// Setup of the problems flagged `setup`: rescaling, norms, W = sf f,
+// T = sg g, and arming of step 1.
 int adi_launch_setup(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob);
-int adi_launch_prepare(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob);
-int adi_launch_finish(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob,
-                      int* host_done);
+// End of an outer step for every problem whose two inner solves have both
+// finished: residual-factor update, norms, stop test, arming of the next
+// step.  Issued after every tick, so problems advance independently.
+int adi_launch_step_end(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob);
 
 }  // namespace lradi

@@ -105,81 +105,10 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup_gram(const SysDesc* __restri
   LRADI_DISPATCH_R2(D.r, gram_self<RR>(X, c, lds, D.partS + (size_t)c.w * kPS));
 }
 
-// setup 2: norms, rescaling factors, ||f g^T||, initial state
-__global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ d,
-                                                    const AdiDesc* __restrict__ ad,
-                                                    AdiCtl* __restrict__ ac) {
-  __shared__ double red_lds[kTPB];
-  __shared__ double Gf[64], Gg[64];
-  const int p = blockIdx.x;
-  const AdiDesc& P = ad[p];
-  if (!P.setup) return;
-  const SysDesc& DA = d[2 * p];
-  const SysDesc& DB = d[2 * p + 1];
-  const int R = P.r;
-  reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, Gf);
-  reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, Gg);
-  if (threadIdx.x == 0) {
-    AdiCtl& C = ac[p];
-    const double nf = sqrt(fmax(lambda_max_sym(Gf, R), 0.0));
-    const double ng = sqrt(fmax(lambda_max_sym(Gg, R), 0.0));
-    const double nfg = sqrt(fmax(lambda_max_prod(Gf, Gg, R), 0.0));
-    double sf = 1.0, sg = 1.0;
-    if (P.rescale && nf > 0.0 && ng > 0.0) {
-      sf = sqrt(ng / nf);
-      sg = 1.0 / sf;
-    }
-    C.sf = sf;
-    C.sg = sg;
-    C.norm_fg = nfg;
-    C.nw = nf * sf;
-    C.nt = ng * sg;
-    C.res = nfg;
-    C.u = 0.0;
-    C.v = 0.0;
-    C.k = 0;
-    C.winner = 0;
-    C.status = LRADI_OK;
-    C.eps = (P.eps_in > 0.0) ? P.eps_in : P.tol * nfg;
-    C.done = (nfg == 0.0 || !(nfg == nfg)) ? 1 : 0;
-    if (!(nfg == nfg) || nfg - nfg != 0.0) C.status = LRADI_ENAN;
-    C.dA = 0.0;
-    C.dB = 0.0;
-  }
-}
-
-// setup 3: W = sf f, T = sg g
-__global__ __launch_bounds__(kTPB) void k_adi_init_wt(const SysDesc* __restrict__ d,
-                                                      const int2* __restrict__ rowmap,
-                                                      const AdiDesc* __restrict__ ad,
-                                                      const AdiCtl* __restrict__ ac) {
-  const RowC c = rowc(d, rowmap);
-  const SysDesc& D = d[c.s];
-  const int p = c.s >> 1;
-  const AdiDesc& P = ad[p];
-  if (!P.setup) return;
-  const bool b = (c.s & 1) != 0;
-  const double* X = b ? P.g : P.f;
-  double* Y = b ? P.T : P.W;
-  const double sc = b ? ac[p].sg : ac[p].sf;
-  const size_t e1 = (size_t)c.row1 * D.r;
-  for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) Y[e] = sc * X[e];
-}
-
-// before step k+1: tolerances, shifts, fresh inner control blocks
-__global__ void k_adi_prepare(const AdiDesc* __restrict__ ad, AdiCtl* __restrict__ ac,
-                              SysCtl* __restrict__ ctl, int nprob) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
-  const AdiDesc& P = ad[p];
-  AdiCtl& C = ac[p];
-  SysCtl& A = ctl[2 * p];
-  SysCtl& B = ctl[2 * p + 1];
-  if (C.done) {
-    A.phase = PH_FINISHED;
-    B.phase = PH_FINISHED;
-    return;
-  }
+// Arm the inner systems of problem P for outer step C.k + 1: tolerances of
+// Sec. 3.3 from (||w||, ||t||, u, v), the step's shifts, the solution slots
+// z_{k+1}, y_{k+1}, and fresh inner control blocks (Algorithm 1 loop body).
+__device__ inline void arm_step(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& B) {
   CtlParams cp;
   cp.eps = C.eps;
   cp.delta_min = P.delta_min;
@@ -216,6 +145,88 @@ __global__ void k_adi_prepare(const AdiDesc* __restrict__ ad, AdiCtl* __restrict
   }
 }
 
+__device__ inline void mark_done(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& B) {
+  C.done = 1;
+  A.phase = PH_FINISHED;
+  B.phase = PH_FINISHED;
+  if (P.host_done) __hip_atomic_store(P.host_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// a problem's step is complete once both of its inner solves finished
+__device__ inline bool step_ready(const AdiCtl& C, const SysCtl& A, const SysCtl& B) {
+  return !C.done && A.phase == PH_FINISHED && B.phase == PH_FINISHED;
+}
+
+// setup 2: norms, rescaling factors, ||f g^T||, initial state, arm step 1
+__global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ d,
+                                                    const AdiDesc* __restrict__ ad,
+                                                    AdiCtl* __restrict__ ac, SysCtl* __restrict__ ctl) {
+  __shared__ double red_lds[kTPB];
+  __shared__ double Gf[64], Gg[64];
+  const int p = blockIdx.x;
+  const AdiDesc& P = ad[p];
+  if (!P.setup) return;
+  const SysDesc& DA = d[2 * p];
+  const SysDesc& DB = d[2 * p + 1];
+  const int R = P.r;
+  reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, Gf);
+  reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, Gg);
+  if (threadIdx.x == 0) {
+    AdiCtl& C = ac[p];
+    const double nf = sqrt(fmax(lambda_max_sym(Gf, R), 0.0));
+    const double ng = sqrt(fmax(lambda_max_sym(Gg, R), 0.0));
+    const double nfg = sqrt(fmax(lambda_max_prod(Gf, Gg, R), 0.0));
+    double sf = 1.0, sg = 1.0;
+    if (P.rescale && nf > 0.0 && ng > 0.0) {
+      sf = sqrt(ng / nf);
+      sg = 1.0 / sf;
+    }
+    C.sf = sf;
+    C.sg = sg;
+    C.norm_fg = nfg;
+    C.nw = nf * sf;
+    C.nt = ng * sg;
+    C.res = nfg;
+    C.u = 0.0;
+    C.v = 0.0;
+    C.k = 0;
+    C.winner = 0;
+    C.status = LRADI_OK;
+    C.eps = (P.eps_in > 0.0) ? P.eps_in : P.tol * nfg;
+    C.done = 0;
+    C.dA = 0.0;
+    C.dB = 0.0;
+    SysCtl& A = ctl[2 * p];
+    SysCtl& B = ctl[2 * p + 1];
+    if (!(nfg == nfg) || nfg - nfg != 0.0) {
+      C.status = LRADI_ENAN;
+      mark_done(P, C, A, B);
+    } else if (nfg == 0.0) {
+      mark_done(P, C, A, B);  // f g^T = 0: X = 0 is exact
+    } else {
+      arm_step(P, C, A, B);
+    }
+  }
+}
+
+// setup 3: W = sf f, T = sg g
+__global__ __launch_bounds__(kTPB) void k_adi_init_wt(const SysDesc* __restrict__ d,
+                                                      const int2* __restrict__ rowmap,
+                                                      const AdiDesc* __restrict__ ad,
+                                                      const AdiCtl* __restrict__ ac) {
+  const RowC c = rowc(d, rowmap);
+  const SysDesc& D = d[c.s];
+  const int p = c.s >> 1;
+  const AdiDesc& P = ad[p];
+  if (!P.setup) return;
+  const bool b = (c.s & 1) != 0;
+  const double* X = b ? P.g : P.f;
+  double* Y = b ? P.T : P.W;
+  const double sc = b ? ac[p].sg : ac[p].sf;
+  const size_t e1 = (size_t)c.row1 * D.r;
+  for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) Y[e] = sc * X[e];
+}
+
 // after the inner solves: W += gamma Z (A side) or T += gamma Y (B side),
 // partial Grams of the new factor (offset 0) and of the new block (offset 64)
 template <int R>
@@ -249,7 +260,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_update(const SysDesc* __restrict__
   const RowC c = rowc(d, rowmap);
   const SysDesc& D = d[c.s];
   const int p = c.s >> 1;
-  if (ac[p].done) return;
+  if (!step_ready(ac[p], ctl[2 * p], ctl[2 * p + 1])) return;
   const AdiDesc& P = ad[p];
   const int js = ac[p].k % P.nshifts;
   const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
@@ -258,21 +269,19 @@ __global__ __launch_bounds__(kTPB) void k_adi_update(const SysDesc* __restrict__
   LRADI_DISPATCH_R2(D.r, adi_update_rows<RR>(Wt, Zk, gamma, c, lds, D.partS + (size_t)c.w * kPS));
 }
 
-// norms, gap estimates u, v (eq. (upd_resgap)), history row, stop test
-__global__ __launch_bounds__(kTPB) void k_adi_finish(const SysDesc* __restrict__ d,
-                                                     const AdiDesc* __restrict__ ad,
-                                                     AdiCtl* __restrict__ ac,
-                                                     const SysCtl* __restrict__ ctl, int* host_done) {
+// norms, gap estimates u, v (eq. (upd_resgap)), history row, stop test; then
+// either finish the problem or arm its next step
+__global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict__ d,
+                                                       const AdiDesc* __restrict__ ad,
+                                                       AdiCtl* __restrict__ ac, SysCtl* __restrict__ ctl) {
   __shared__ double red_lds[kTPB];
   __shared__ double GW[64], GZ[64], GT[64], GY[64];
   const int p = blockIdx.x;
   const AdiDesc& P = ad[p];
   AdiCtl& C = ac[p];
-  if (C.done) {
-    if (threadIdx.x == 0 && host_done)
-      __hip_atomic_store(host_done + p, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    return;
-  }
+  SysCtl& A = ctl[2 * p];
+  SysCtl& B = ctl[2 * p + 1];
+  if (!step_ready(C, A, B)) return;
   const SysDesc& DA = d[2 * p];
   const SysDesc& DB = d[2 * p + 1];
   const int R = P.r;
@@ -281,8 +290,6 @@ __global__ __launch_bounds__(kTPB) void k_adi_finish(const SysDesc* __restrict__
   reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, GT);
   reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
   if (threadIdx.x == 0) {
-    const SysCtl& A = ctl[2 * p];
-    const SysCtl& B = ctl[2 * p + 1];
     const int k = C.k;
     const int js = k % P.nshifts;
     const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
@@ -320,18 +327,18 @@ __global__ __launch_bounds__(kTPB) void k_adi_finish(const SysDesc* __restrict__
     C.res = res;
     C.k = k + 1;
     if (A.status == IS_CAP || B.status == IS_CAP) C.winner = 1;
-    bool bad = !(res == res) || res - res != 0.0 || A.status == IS_NAN || B.status == IS_NAN;
+    const bool bad = !(res == res) || res - res != 0.0 || A.status == IS_NAN || B.status == IS_NAN;
     if (bad) {
       C.status = LRADI_ENAN;
-      C.done = 1;
+      mark_done(P, C, A, B);
     } else if (res < P.tol * nfg) {
-      C.done = 1;
+      mark_done(P, C, A, B);
     } else if (C.k >= P.kmax) {
       C.status = LRADI_WNOCONV;
-      C.done = 1;
+      mark_done(P, C, A, B);
+    } else {
+      arm_step(P, C, A, B);
     }
-    if (host_done)
-      __hip_atomic_store(host_done + p, C.done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -339,24 +346,15 @@ __global__ __launch_bounds__(kTPB) void k_adi_finish(const SysDesc* __restrict__
 
 int adi_launch_setup(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob) {
   hipLaunchKernelGGL(k_adi_setup_gram, dim3(b.rowgrid), dim3(kTPB), 0, st, b.d, b.rowmap, ad);
-  hipLaunchKernelGGL(k_adi_setup, dim3(nprob), dim3(kTPB), 0, st, b.d, ad, ac);
+  hipLaunchKernelGGL(k_adi_setup, dim3(nprob), dim3(kTPB), 0, st, b.d, ad, ac, b.ctl);
   hipLaunchKernelGGL(k_adi_init_wt, dim3(b.rowgrid), dim3(kTPB), 0, st, b.d, b.rowmap, ad, ac);
   LRADI_HIP(hipGetLastError());
   return LRADI_OK;
 }
 
-int adi_launch_prepare(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob) {
-  const int tpb = 64;
-  hipLaunchKernelGGL(k_adi_prepare, dim3((nprob + tpb - 1) / tpb), dim3(tpb), 0, st, ad, ac, b.ctl,
-                     nprob);
-  LRADI_HIP(hipGetLastError());
-  return LRADI_OK;
-}
-
-int adi_launch_finish(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob,
-                      int* host_done) {
+int adi_launch_step_end(hipStream_t st, const Batch& b, const AdiDesc* ad, AdiCtl* ac, int nprob) {
   hipLaunchKernelGGL(k_adi_update, dim3(b.rowgrid), dim3(kTPB), 0, st, b.d, b.rowmap, ad, ac, b.ctl);
-  hipLaunchKernelGGL(k_adi_finish, dim3(nprob), dim3(kTPB), 0, st, b.d, ad, ac, b.ctl, host_done);
+  hipLaunchKernelGGL(k_adi_step_end, dim3(nprob), dim3(kTPB), 0, st, b.d, ad, ac, b.ctl);
   LRADI_HIP(hipGetLastError());
   return LRADI_OK;
 }

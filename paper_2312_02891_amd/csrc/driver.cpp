@@ -11,6 +11,7 @@
 #include <cstring>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -181,9 +182,7 @@ struct lradi_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  DevBuf arena;  // inner-solver workspace, grown on demand
   HostRing ring;
-  HostRing done;
   std::vector<hipEvent_t> events;
   // kernel measurements (opts.profile)
   std::vector<TickProbe> probes;
@@ -205,26 +204,96 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// One inner system to be placed in a batch.
-struct SysSpec {
-  const DevCSR* A;
-  const double* W;
-  double* Z;      // may be null (set on the device by the ADI prepare kernel)
-  double shift;
-  double delta;
-  int r, m, precision, max_inner;
-  double floor_rel;
-};
-
 int choose_rows_per_wg(int n) {
   int rpw = (n + 511) / 512;
   rpw = ((rpw + 255) / 256) * 256;
   return std::max(256, std::min(rpw, 8192));
 }
 
-// Lay out every system's workspace in the context arena and fill the
-// descriptor / control / row-map arrays.
-struct InnerBatch {
+// Workspace of one inner system: every device array the solver keeps for it
+// across ticks.  Its address never changes while the system is alive, so the
+// descriptor tables can be rebuilt (systems joining or leaving) at any point
+// where the stream is drained.
+struct SysWork {
+  DevBuf buf;
+  SysDesc d{};
+  SysCtl c{};  // host copy of the control block, valid at drain points
+
+  int init(const DevCSR* A, const double* W, int r, int m, int prec, int max_inner, double floor_rel) {
+    if (r < 1 || r > kMaxR || m < 1 || m > kMaxM)
+      return set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM), LRADI_EINVAL;
+    const size_t n = A->n, rr = r, mm = m;
+    const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
+    const int rpw = choose_rows_per_wg((int)n);
+    const int nwg = (int)((n + rpw - 1) / rpw);
+    const size_t pstride = (mm + 1) * rr * rr;
+    const size_t sizes[] = {(mm + 1) * n * rr * tsz,  // V
+                            n * rr * tsz,              // U
+                            n * rr * 8,                // R
+                            (size_t)nwg * pstride * 8, // part
+                            (size_t)nwg * kPS * 8,     // partS
+                            pstride * 8,               // red
+                            pstride * 8,               // hacc
+                            mm * rr * mm * rr * 8,     // Rt
+                            mm * 4 * rr * rr * 8,      // Qs
+                            (mm + 1) * rr * rr * 8,    // Gv
+                            mm * rr * rr * 8,          // yv
+                            512 * 8};                  // sm
+    size_t total = 0;
+    for (size_t z : sizes) total += align256(z);
+    LRADI_TRY(buf.alloc(total));
+    char* p = buf.as<char>();
+    auto take = [&](size_t bytes) {
+      char* q = p;
+      p += align256(bytes);
+      return q;
+    };
+    d = SysDesc{};
+    d.n = (int)n;
+    d.r = r;
+    d.m = m;
+    d.nwg = nwg;
+    d.rows_per_wg = rpw;
+    d.precision = prec;
+    d.max_inner = max_inner;
+    d.rowptr = A->rowptr.as<int>();
+    d.colind = A->colind.as<int>();
+    d.valT = (prec == LRADI_FP64) ? (const void*)A->val64.p : (const void*)A->val32.p;
+    d.val64 = A->val64.as<double>();
+    d.floor_rel = floor_rel;
+    d.W = W;
+    d.pstride = (int)pstride;
+    d.nnz = (int)A->nnz;
+    d.V = take(sizes[0]);
+    d.U = take(sizes[1]);
+    d.R = reinterpret_cast<double*>(take(sizes[2]));
+    d.part = reinterpret_cast<double*>(take(sizes[3]));
+    d.partS = reinterpret_cast<double*>(take(sizes[4]));
+    d.red = reinterpret_cast<double*>(take(sizes[5]));
+    d.hacc = reinterpret_cast<double*>(take(sizes[6]));
+    d.Rt = reinterpret_cast<double*>(take(sizes[7]));
+    d.Qs = reinterpret_cast<double*>(take(sizes[8]));
+    d.Gv = reinterpret_cast<double*>(take(sizes[9]));
+    d.yv = reinterpret_cast<double*>(take(sizes[10]));
+    d.sm = reinterpret_cast<double*>(take(sizes[11]));
+    c = SysCtl{};
+    c.phase = PH_FINISHED;  // armed by the caller or by the outer kernels
+    return LRADI_OK;
+  }
+
+  // a standalone solve of (A + shift I) Z = W to ||R||_2 <= delta
+  void arm(double* Z, double shift, double delta) {
+    c = SysCtl{};
+    c.Z = Z;
+    c.shift = shift;
+    c.delta = delta;
+    c.phase = PH_CYCLE_END;
+    c.first = 1;
+  }
+};
+
+// Device tables of a set of systems: descriptors, control blocks, row map.
+struct Table {
   std::vector<SysDesc> hd;
   std::vector<SysCtl> hc;
   std::vector<int2> hmap;
@@ -232,127 +301,52 @@ struct InnerBatch {
   Batch b{};
 };
 
-int build_batch(lradi_ctx* ctx, const std::vector<SysSpec>& sys, InnerBatch& ib) {
-  const int nsys = (int)sys.size();
-  if (nsys == 0) {
-    set_error("empty batch");
-    return LRADI_EINVAL;
-  }
-  const int prec = sys[0].precision;
-  ib.hd.assign(nsys, SysDesc{});
-  ib.hc.assign(nsys, SysCtl{});
-  ib.hmap.clear();
-  size_t total = 0;
-  std::vector<size_t> off(nsys);
-  int maxP = 1;
+int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
+  const int nsys = (int)ws.size();
+  if (nsys == 0) return set_error("empty batch"), LRADI_EINVAL;
+  const int prec = ws[0]->d.precision;
+  t.hd.resize(nsys);
+  t.hc.resize(nsys);
+  t.hmap.clear();
+  int maxP = 1, rfix = ws[0]->d.r;
   for (int s = 0; s < nsys; ++s) {
-    const SysSpec& S = sys[s];
-    if (S.precision != prec) {
-      set_error("all systems of a batch must use one precision");
-      return LRADI_EINVAL;
-    }
-    if (S.r < 1 || S.r > kMaxR || S.m < 1 || S.m > kMaxM) {
-      set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM);
-      return LRADI_EINVAL;
-    }
-    const size_t n = S.A->n, r = S.r, m = S.m;
-    const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
-    const int rpw = choose_rows_per_wg((int)n);
-    const int nwg = (int)((n + rpw - 1) / rpw);
-    const size_t pstride = (m + 1) * r * r;
-    maxP = std::max<int>(maxP, (int)pstride);
-    size_t sz = 0;
-    sz += align256((m + 1) * n * r * tsz);       // V
-    sz += align256(n * r * tsz);                 // U
-    sz += align256(n * r * 8);                   // R
-    sz += align256((size_t)nwg * pstride * 8);   // part
-    sz += align256((size_t)nwg * kPS * 8);       // partS
-    sz += align256(pstride * 8) * 2;             // red, hacc
-    sz += align256(m * r * m * r * 8);           // Rt
-    sz += align256(m * 4 * r * r * 8);           // Qs
-    sz += align256((m + 1) * r * r * 8);         // Gv
-    sz += align256(m * r * r * 8);               // yv
-    sz += align256(512 * 8);                     // sm
-    off[s] = total;
-    total += sz;
-    SysDesc& D = ib.hd[s];
-    D.n = (int)n;
-    D.r = (int)r;
-    D.m = (int)m;
-    D.nwg = nwg;
-    D.rows_per_wg = rpw;
-    D.wg0 = (int)ib.hmap.size();
-    D.precision = prec;
-    D.max_inner = S.max_inner;
-    D.rowptr = S.A->rowptr.as<int>();
-    D.colind = S.A->colind.as<int>();
-    D.valT = (prec == LRADI_FP64) ? (const void*)S.A->val64.p : (const void*)S.A->val32.p;
-    D.val64 = S.A->val64.as<double>();
-    D.floor_rel = S.floor_rel;
-    D.W = S.W;
-    D.pstride = (int)pstride;
-    D.nnz = (int)S.A->nnz;
-    for (int w = 0; w < nwg; ++w) ib.hmap.push_back(make_int2(s, w));
-    SysCtl& C = ib.hc[s];
-    C.Z = S.Z;
-    C.shift = S.shift;
-    // without a solution buffer the system waits for the outer driver to arm it
-    C.phase = S.Z ? PH_CYCLE_END : PH_FINISHED;
-    C.first = 1;
-    C.delta = S.delta;
+    if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
+    t.hd[s] = ws[s]->d;
+    t.hd[s].wg0 = (int)t.hmap.size();
+    t.hc[s] = ws[s]->c;
+    for (int w = 0; w < ws[s]->d.nwg; ++w) t.hmap.push_back(make_int2(s, w));
+    maxP = std::max(maxP, ws[s]->d.pstride);
+    if (ws[s]->d.r != rfix) rfix = 0;
   }
-  if (ctx->arena.bytes < total) {
-    ctx->arena.release();
-    LRADI_TRY(ctx->arena.alloc(total));
-  }
-  char* base = ctx->arena.as<char>();
-  for (int s = 0; s < nsys; ++s) {
-    SysDesc& D = ib.hd[s];
-    const size_t n = D.n, r = D.r, m = D.m;
-    const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
-    char* p = base + off[s];
-    auto take = [&](size_t bytes) {
-      char* q = p;
-      p += align256(bytes);
-      return q;
-    };
-    D.V = take((m + 1) * n * r * tsz);
-    D.U = take(n * r * tsz);
-    D.R = reinterpret_cast<double*>(take(n * r * 8));
-    D.part = reinterpret_cast<double*>(take((size_t)D.nwg * D.pstride * 8));
-    D.partS = reinterpret_cast<double*>(take((size_t)D.nwg * kPS * 8));
-    D.red = reinterpret_cast<double*>(take((size_t)D.pstride * 8));
-    D.hacc = reinterpret_cast<double*>(take((size_t)D.pstride * 8));
-    D.Rt = reinterpret_cast<double*>(take(m * r * m * r * 8));
-    D.Qs = reinterpret_cast<double*>(take(m * 4 * r * r * 8));
-    D.Gv = reinterpret_cast<double*>(take((m + 1) * r * r * 8));
-    D.yv = reinterpret_cast<double*>(take(m * r * r * 8));
-    D.sm = reinterpret_cast<double*>(take(512 * 8));
-  }
-  LRADI_TRY(ib.dd.alloc(sizeof(SysDesc) * nsys));
-  LRADI_TRY(ib.dc.alloc(sizeof(SysCtl) * nsys));
-  LRADI_TRY(ib.dmap.alloc(sizeof(int2) * ib.hmap.size()));
+  if (t.dd.bytes < sizeof(SysDesc) * nsys) LRADI_TRY(t.dd.alloc(sizeof(SysDesc) * nsys));
+  if (t.dc.bytes < sizeof(SysCtl) * nsys) LRADI_TRY(t.dc.alloc(sizeof(SysCtl) * nsys));
+  if (t.dmap.bytes < sizeof(int2) * t.hmap.size()) LRADI_TRY(t.dmap.alloc(sizeof(int2) * t.hmap.size()));
   hipStream_t st = ctx->stream;
-  LRADI_HIP(hipMemcpyAsync(ib.dd.p, ib.hd.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(ib.dc.p, ib.hc.data(), sizeof(SysCtl) * nsys, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(ib.dmap.p, ib.hmap.data(), sizeof(int2) * ib.hmap.size(),
-                           hipMemcpyHostToDevice, st));
-  ib.b.d = ib.dd.as<SysDesc>();
-  ib.b.ctl = ib.dc.as<SysCtl>();
-  ib.b.rowmap = ib.dmap.as<int2>();
-  ib.b.nsys = nsys;
-  ib.b.rowgrid = (int)ib.hmap.size();
-  ib.b.maxP = maxP;
-  ib.b.precision = prec;
-  ib.b.rfix = sys[0].r;
-  for (int s = 1; s < nsys; ++s)
-    if (sys[s].r != sys[0].r) ib.b.rfix = 0;
+  LRADI_HIP(hipMemcpyAsync(t.dd.p, t.hd.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(t.dc.p, t.hc.data(), sizeof(SysCtl) * nsys, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(t.dmap.p, t.hmap.data(), sizeof(int2) * t.hmap.size(), hipMemcpyHostToDevice, st));
+  // the host vectors must outlive the copies
+  LRADI_HIP(hipStreamSynchronize(st));
+  t.b.d = t.dd.as<SysDesc>();
+  t.b.ctl = t.dc.as<SysCtl>();
+  t.b.rowmap = t.dmap.as<int2>();
+  t.b.nsys = nsys;
+  t.b.rowgrid = (int)t.hmap.size();
+  t.b.maxP = maxP;
+  t.b.precision = prec;
+  t.b.rfix = rfix;
   return LRADI_OK;
 }
 
-// Issue ticks until every system of the batch is finished.  The host reads
-// the unfinished count of tick t - L only after issuing tick t, so the device
-// always has work queued; the extra ticks are no-ops.
+// Copy the device control blocks back into the workspaces (stream drained).
+int download_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
+  const int nsys = (int)ws.size();
+  LRADI_HIP(hipMemcpyAsync(t.hc.data(), t.dc.p, sizeof(SysCtl) * nsys, hipMemcpyDeviceToHost, ctx->stream));
+  LRADI_HIP(hipStreamSynchronize(ctx->stream));
+  for (int s = 0; s < nsys; ++s) ws[s]->c = t.hc[s];
+  return LRADI_OK;
+}
+
 int probe_account(lradi_ctx* ctx, const TickProbe& p) {
   float a = 0.f, b = 0.f, c = 0.f;
   LRADI_HIP(hipEventElapsedTime(&a, p.ev[0], p.ev[1]));
@@ -365,7 +359,13 @@ int probe_account(lradi_ctx* ctx, const TickProbe& p) {
   return LRADI_OK;
 }
 
-int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner, bool profile) {
+// Issue ticks (plus `after`, e.g. the outer step-end kernels) until every
+// system of the table is finished, or until `stop` (checked at each read
+// back) asks to return.  The host reads the unfinished count of tick t - L
+// only after issuing tick t, so the device always has queued work; the
+// extra ticks are no-ops.  Returns with the stream drained.
+int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, bool profile,
+              const std::function<int()>& after, const std::function<bool()>& stop) {
   const int L = std::max(0, std::min(lookahead, 8));
   LRADI_TRY(ctx->ring.init(L + 1));
   while ((int)ctx->events.size() < L + 1) {
@@ -381,11 +381,11 @@ int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner, bool
     }
   }
   hipStream_t st = ctx->stream;
-  const long max_ticks = 3L * std::max(max_inner, 1) + 16;
   long t = 0;
   for (;; ++t) {
     const int slot = (int)(t % (L + 1));
     LRADI_TRY(launch_tick(st, b, profile ? &ctx->probes[slot] : nullptr));
+    if (after) LRADI_TRY(after());
     LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
     LRADI_HIP(hipEventRecord(ctx->events[slot], st));
     if (t >= L) {
@@ -394,6 +394,7 @@ int run_inner(lradi_ctx* ctx, const Batch& b, int lookahead, int max_inner, bool
       if (profile) LRADI_TRY(probe_account(ctx, ctx->probes[rs]));
       const int left = __atomic_load_n(ctx->ring.h + rs, __ATOMIC_ACQUIRE);
       if (left == 0) break;
+      if (stop && stop()) break;
     }
     if (t > max_ticks) {
       set_error("inner solver scheduler exceeded %ld ticks", max_ticks);
@@ -485,13 +486,33 @@ double floor_for(const lradi_opts& o) {
 }  // namespace lradi
 
 // ---------------------------------------------------------------------------
-// Outer engine: a set of Sylvester problems advanced together one LR-ADI step
-// at a time (Algorithm 1).  Problem p owns inner systems 2p (A side) and 2p+1
-// (B side).  The batch is rebuilt at step boundaries whenever its membership
-// changes; between steps a problem's whole state is W, T, the factor stacks,
-// gamma, the history and its AdiCtl, so problems can join and leave freely.
+// Outer engine: a set of Sylvester problems, each advancing through Algorithm 1
+// on its own.  Problem p owns inner systems 2p (A side) and 2p+1 (B side) in
+// the tables; after every tick the step-end kernels close the outer step of
+// every problem whose two inner solves have finished and arm its next step,
+// so no problem waits for another.  Problems join (setup kernels) and leave
+// (finished, cancelled) at drain points, where the tables are rebuilt; their
+// workspaces never move.
 namespace lradi {
 namespace {
+
+struct PinnedInt {
+  int* h = nullptr;
+  int* d = nullptr;
+  PinnedInt() = default;
+  PinnedInt(const PinnedInt&) = delete;
+  PinnedInt& operator=(const PinnedInt&) = delete;
+  ~PinnedInt() {
+    if (h) (void)hipHostFree(h);
+  }
+  int init() {
+    LRADI_HIP(hipHostMalloc((void**)&h, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    LRADI_HIP(hipHostGetDevicePointer((void**)&d, h, 0));
+    *h = 0;
+    return LRADI_OK;
+  }
+  int get() const { return __atomic_load_n(h, __ATOMIC_ACQUIRE); }
+};
 
 struct Prob {
   DevCSR A, Bt;
@@ -501,11 +522,12 @@ struct Prob {
   int n = 0, m = 0, r = 0, nshifts = 0;
   double tol = 0.0;
   DevBuf shA, shB, W, T, gam, hist;
+  SysWork wa, wb;
+  PinnedInt done;
   std::unique_ptr<lradi_result> res;
   AdiCtl hc{};
   bool set_up = false;
   std::chrono::steady_clock::time_point t0;
-  size_t footprint = 0;  // device bytes held by this problem (serving admission)
 };
 
 // Validate and upload one problem (transposing B on the host when needed).
@@ -567,12 +589,16 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
   LRADI_TRY(q.hist.alloc(sizeof(double) * K * kHistCols));
   LRADI_HIP(hipMemcpyAsync(q.shA.p, P.shiftsA, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
+  const double fl = floor_for(o);
+  LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
+  LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
+  LRADI_TRY(q.done.init());
   LRADI_HIP(hipStreamSynchronize(st));
   return LRADI_OK;
 }
 
-// Device bytes one problem needs while in flight: matrices, right-hand
-// sides, residual and solution factors, and its two inner systems' workspace.
+// Device bytes one problem holds while in flight: matrices, right-hand
+// sides, residual and solution factors, and its two inner workspaces.
 size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lradi_opts& o) {
   const size_t tsz = o.precision == LRADI_FP64 ? 8 : 4;
   const size_t K = o.kmax, mm = o.restart;
@@ -580,9 +606,9 @@ size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lra
     return (size_t)(nrow + 1) * 4 + (size_t)nnz * (4 + 8 + (tsz == 4 ? 4 : 0));
   };
   auto inner = [&](size_t rows) {
-    const size_t rpw = 256, nwg = (rows + rpw - 1) / rpw;
+    const size_t rpw = (size_t)choose_rows_per_wg((int)rows), nwg = (rows + rpw - 1) / rpw;
     return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + kPS) * 8 +
-           (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 4096;
+           (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 12 * 256 + 4096;
   };
   return mat(n, nnzA) + mat(m, nnzB) + (size_t)(n + m) * r * 8 * (3 + K) + K * (kHistCols + 1) * 8 +
          inner(n) + inner(m);
@@ -592,28 +618,28 @@ struct Engine {
   lradi_ctx* c;
   lradi_opts o;
   std::vector<Prob*> act;
-  std::vector<Prob*> finished;  // filled by step(); the caller takes them
-  InnerBatch ib;
+  std::vector<Prob*> finished;  // filled by drain(); the caller takes them
+  std::vector<SysWork*> ws;
+  Table tab;
   DevBuf dad, dac;
   std::vector<AdiCtl> hac;
   bool dirty = true;
+  long ticks = 0;
 
   Engine(lradi_ctx* ctx, const lradi_opts& opts) : c(ctx), o(opts) {}
 
   int rebuild() {
     hipStream_t st = c->stream;
     const int np = (int)act.size();
-    std::vector<SysSpec> specs;
-    specs.reserve(2 * np);
-    const double fl = floor_for(o);
+    dirty = false;
+    if (np == 0) return LRADI_OK;
+    ws.clear();
     for (Prob* q : act) {
-      specs.push_back(SysSpec{&q->A, q->W.as<double>(), nullptr, 0.0, 0.0, q->r, o.restart, o.precision,
-                              o.max_inner, fl});
-      specs.push_back(SysSpec{&q->Bt, q->T.as<double>(), nullptr, 0.0, 0.0, q->r, o.restart, o.precision,
-                              o.max_inner, fl});
+      ws.push_back(&q->wa);
+      ws.push_back(&q->wb);
     }
-    LRADI_TRY(build_batch(c, specs, ib));
-    LRADI_TRY(prof_counters(c, o.profile != 0, &ib.b.prof_bytes));
+    LRADI_TRY(upload_table(c, ws, tab));
+    LRADI_TRY(prof_counters(c, o.profile != 0, &tab.b.prof_bytes));
     std::vector<AdiDesc> hd(np);
     hac.assign(np, AdiCtl{});
     bool any_setup = false;
@@ -651,15 +677,16 @@ struct Engine {
       ad.Yf = q->res->Yf.as<double>();
       ad.gam = q->gam.as<double>();
       ad.hist = q->hist.as<double>();
+      ad.host_done = q->done.d;
       hac[p] = q->hc;
     }
     if (dad.bytes < sizeof(AdiDesc) * np) LRADI_TRY(dad.alloc(sizeof(AdiDesc) * np));
     if (dac.bytes < sizeof(AdiCtl) * np) LRADI_TRY(dac.alloc(sizeof(AdiCtl) * np));
     LRADI_HIP(hipMemcpyAsync(dad.p, hd.data(), sizeof(AdiDesc) * np, hipMemcpyHostToDevice, st));
     LRADI_HIP(hipMemcpyAsync(dac.p, hac.data(), sizeof(AdiCtl) * np, hipMemcpyHostToDevice, st));
-    if (any_setup) LRADI_TRY(adi_launch_setup(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np));
+    if (any_setup) LRADI_TRY(adi_launch_setup(st, tab.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np));
+    LRADI_HIP(hipStreamSynchronize(st));
     for (Prob* q : act) q->set_up = true;
-    dirty = false;
     return LRADI_OK;
   }
 
@@ -682,19 +709,13 @@ struct Engine {
     return LRADI_OK;
   }
 
-  // One outer step of every active problem; finished problems are finalised,
-  // moved to `finished` and removed from the active set.
-  int step() {
-    if (act.empty()) return LRADI_OK;
-    hipStream_t st = c->stream;
-    if (dirty) LRADI_TRY(rebuild());
+  // Stream drained: pull the control blocks back, move finished problems to
+  // `finished`.
+  int drain() {
     const int np = (int)act.size();
-    LRADI_TRY(c->done.init(np));
-    LRADI_TRY(adi_launch_prepare(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np));
-    LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner, o.profile != 0));
-    LRADI_TRY(adi_launch_finish(st, ib.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np, c->done.d));
-    LRADI_HIP(hipMemcpyAsync(hac.data(), dac.p, sizeof(AdiCtl) * np, hipMemcpyDeviceToHost, st));
-    LRADI_HIP(hipStreamSynchronize(st));
+    if (np == 0) return LRADI_OK;
+    LRADI_TRY(download_table(c, ws, tab));
+    LRADI_HIP(hipMemcpy(hac.data(), dac.p, sizeof(AdiCtl) * np, hipMemcpyDeviceToHost));
     std::vector<Prob*> keep;
     for (int p = 0; p < np; ++p) {
       act[p]->hc = hac[p];
@@ -708,6 +729,30 @@ struct Engine {
     }
     act.swap(keep);
     return LRADI_OK;
+  }
+
+  // Run ticks until every problem finished, or (retire > 0) until at least
+  // `retire` problems finished, so the tables can shrink, or until `stop`
+  // asks to return.  Ends drained.
+  int run(int retire, const std::function<bool()>& stop) {
+    if (dirty) LRADI_TRY(rebuild());
+    if (act.empty()) return LRADI_OK;
+    const int np = (int)act.size();
+    auto after = [&]() { return adi_launch_step_end(c->stream, tab.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np); };
+    auto check = [&]() {
+      if (stop && stop()) return true;
+      if (retire <= 0) return false;
+      int k = 0;
+      for (Prob* q : act) k += q->done.get();
+      return k >= retire;
+    };
+    const long max_ticks = (3L * std::max(o.max_inner, 1) + 16) * (long)(o.kmax + 1);
+    const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, after, check);
+    if (rc != LRADI_OK) {
+      (void)hipStreamSynchronize(c->stream);
+      return rc;
+    }
+    return drain();
   }
 };
 
@@ -856,31 +901,39 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     return set_error("lradi_shifted_solve: bad options"), LRADI_EINVAL;
   LRADI_HIP(hipSetDevice(c->device));
   std::vector<DevCSR> mats(nsys);
-  std::vector<SysSpec> specs(nsys);
+  std::vector<std::unique_ptr<SysWork>> work(nsys);
+  std::vector<SysWork*> ws(nsys);
   for (int s = 0; s < nsys; ++s) {
-    if (!W[s] || !Z[s] || !(delta[s] >= 0.0))
+    if (!W[s] || !Z[s] || !(delta[s] >= 0.0) || !std::isfinite(shift[s]))
       return set_error("lradi_shifted_solve: bad system %d", s), LRADI_EINVAL;
     LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
-    specs[s] = SysSpec{&mats[s], W[s], Z[s], shift[s], delta[s], r[s], o.restart, o.precision,
-                       o.max_inner, floor_for(o)};
+    work[s] = std::make_unique<SysWork>();
+    LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o)));
+    work[s]->arm(Z[s], shift[s], delta[s]);
+    ws[s] = work[s].get();
   }
-  InnerBatch ib;
-  LRADI_TRY(build_batch(c, specs, ib));
-  LRADI_TRY(prof_counters(c, o.profile != 0, &ib.b.prof_bytes));
-  LRADI_TRY(run_inner(c, ib.b, o.lookahead, o.max_inner, o.profile != 0));
-  std::vector<SysCtl> hc(nsys);
-  LRADI_HIP(hipMemcpy(hc.data(), ib.b.ctl, sizeof(SysCtl) * nsys, hipMemcpyDeviceToHost));
+  Table tab;
+  LRADI_TRY(upload_table(c, ws, tab));
+  LRADI_TRY(prof_counters(c, o.profile != 0, &tab.b.prof_bytes));
+  const long max_ticks = 3L * o.max_inner + 16;
+  const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, nullptr, nullptr);
+  if (rc != LRADI_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    return rc;
+  }
+  LRADI_TRY(download_table(c, ws, tab));
   int status = LRADI_OK;
   for (int s = 0; s < nsys; ++s) {
+    const SysCtl& h = ws[s]->c;
     if (stats) {
-      stats[s].steps = hc[s].steps;
-      stats[s].cycles = hc[s].cycles;
-      stats[s].status = hc[s].status;
-      stats[s].pad = hc[s].breakdowns;
-      stats[s].rnorm = hc[s].rnorm;
+      stats[s].steps = h.steps;
+      stats[s].cycles = h.cycles;
+      stats[s].status = h.status;
+      stats[s].pad = h.breakdowns;
+      stats[s].rnorm = h.rnorm;
     }
-    if (hc[s].status == IS_NAN) status = LRADI_ENAN;
-    else if (hc[s].status == IS_CAP && status == LRADI_OK) status = LRADI_WINNER;
+    if (h.status == IS_NAN) status = LRADI_ENAN;
+    else if (h.status == IS_CAP && status == LRADI_OK) status = LRADI_WINNER;
   }
   return status;
 }
@@ -909,8 +962,10 @@ int lradi_batch_solve(lradi_ctx* c, int nprob, const lradi_problem* probs, const
   }
   Engine E(c, o);
   for (auto& q : ps) E.act.push_back(q.get());
-  for (int k = 0; k < o.kmax + 1 && !E.act.empty(); ++k) LRADI_TRY(E.step());
-  if (!E.act.empty()) return set_error("lradi_batch_solve: problems left after kmax steps"), LRADI_EHIP;
+  // each run retires at least one problem (or fails)
+  for (int k = 0; k <= nprob && !E.act.empty(); ++k)
+    LRADI_TRY(E.run(std::max(1, (int)E.act.size() / 8), nullptr));
+  if (!E.act.empty()) return set_error("lradi_batch_solve: problems left unfinished"), LRADI_EHIP;
   int status = LRADI_OK;
   for (int i = 0; i < nprob; ++i) {
     const int st = ps[i]->res->status;
@@ -1032,6 +1087,7 @@ struct lradi_server {
   lradi_opts opts{};
   int64_t budget = 0;
   int max_active = 0;
+  int admit_ms = 2;
   // host copies of a submitted problem until the worker uploads it
   struct Pending {
     uint64_t ticket;
@@ -1152,7 +1208,19 @@ void lradi_server::run() {
       st.bytes_in_use = used;
       continue;
     }
-    const int rc = E.step();
+    // Return to this loop as soon as a problem finished (its result goes
+    // out at once), a cancellation or shutdown came in, or a queued request
+    // fits; admissions are batched over at least admit_ms.
+    const auto t_run = std::chrono::steady_clock::now();
+    auto interrupt = [&]() {
+      std::lock_guard<std::mutex> lk(mu);
+      if (stop || !cancel_req.empty()) return true;
+      if (queue.empty()) return false;
+      if (max_active > 0 && (int)E.act.size() >= max_active) return false;
+      if (used + (int64_t)queue.front().footprint > budget) return false;
+      return std::chrono::steady_clock::now() - t_run > std::chrono::milliseconds(admit_ms);
+    };
+    const int rc = E.run(1, interrupt);
     {
       std::lock_guard<std::mutex> lk(mu);
       st.steps += 1;
@@ -1161,6 +1229,7 @@ void lradi_server::run() {
       // a device error ends every problem in flight with that status
       std::vector<Prob*> all = E.act;
       E.act.clear();
+      E.dirty = true;
       for (Prob* q : all) {
         (void)E.finalize(q);
         complete(q, rc);

@@ -40,7 +40,9 @@ def test_mixed_stream_equals_solo_runs(L):
     ctx = L.Context(0)
     solo = []
     for (_, P, HA, HB, f, g, pA, pB) in reqs:
-        solo.append(ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, L.default_opts(tol=P.tol)))
+        # alone: the same problem (with its own tolerance) as a batch of one
+        rs, _ = ctx.batch_solve([(HA, HB, to_dev(f), to_dev(g), pA, pB, P.tol)], o)
+        solo.append(rs[0])
     srv = L.Server(ctx, o, hbm_budget=0, max_active=4)
     tickets = []
     t0 = time.perf_counter()
