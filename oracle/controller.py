@@ -81,8 +81,17 @@ def select_tightB(eh: float, nw: float, nt: float, dmin: float, dmax: float):
 def tolerances(selection: str, k: int, nw: float, nt: float, u: float, v: float,
                eps: float, kmax: int = 50, xi: float = 1.0, dmin: float = 5e-10,
                dmax: float = 0.1, backlook: bool = True, fixed: float = 5e-10,
-               rho: float = 1e-12, paper_abs: bool = False):
-    """(delta^A_k, delta^B_k) for outer step k."""
+               rho: float = 1e-12, paper_abs: bool = False, balance: bool = False):
+    """(delta^A_k, delta^B_k) for outer step k.
+
+    balance (an extension; the paper balances only f and g, Sec. 4): the
+    dynamic selections are evaluated for the pair (s w, t / s) with
+    s = sqrt(||t|| / ||w||), i.e. both factors at the norm sqrt(||w|| ||t||),
+    and mapped back (delta^A / s, delta^B s).  The product w t^T, every ADI
+    iterate and the left-hand side of eqs. (ADI_relax1_prak)/(ADI_relax2_prak)
+    do not change under that rescaling, so admissibility carries over; only
+    the clamps of eq. (bound_tols) and the split of eq. (simple_tols) now act
+    in the balanced frame."""
     if selection == "relative":
         return rho * nw, rho * nt
     if selection == "fixed":
@@ -91,13 +100,19 @@ def tolerances(selection: str, k: int, nw: float, nt: float, u: float, v: float,
         eh = eps_hat_2(eps, kmax, k, u, v, xi, paper_abs)
     else:
         eh = eps_hat_1(eps, kmax, xi)
+    s = 1.0
+    if balance and nw > 0.0 and nt > 0.0:
+        s = math.sqrt(nt / nw)
+        nw = nt = math.sqrt(nw * nt)
     if selection == "mid":
-        return select_mid(eh, nw, nt, dmin, dmax)
-    if selection == "tightA":
-        return select_tightA(eh, nw, nt, dmin, dmax)
-    if selection == "tightB":
-        return select_tightB(eh, nw, nt, dmin, dmax)
-    raise ValueError(selection)
+        dA, dB = select_mid(eh, nw, nt, dmin, dmax)
+    elif selection == "tightA":
+        dA, dB = select_tightA(eh, nw, nt, dmin, dmax)
+    elif selection == "tightB":
+        dA, dB = select_tightB(eh, nw, nt, dmin, dmax)
+    else:
+        raise ValueError(selection)
+    return dA / s, dB * s
 
 
 def update_gap(u: float, v: float, gamma: float, nz: float, ny: float,

@@ -114,3 +114,47 @@ def test_gap_update_recurrence():
         u, v = C.update_gap(u, v, gam, nz, ny, rA, rB)
     assert u == pytest.approx(3 * 2 * 2e-3 + 7 * 0.5 * 1e-4)
     assert v == pytest.approx(3 * 5 * 1e-3 + 7 * 0.25 * 4e-4)
+
+
+# --- balanced frame (an extension: the selection evaluated for (s w, t / s)) ---
+
+@pytest.mark.parametrize("sel", ["mid", "tightA", "tightB"])
+def test_balance_is_identity_for_equal_norms(sel):
+    for nw in (1e-3, 1.0, 37.0):
+        a = C.tolerances(sel, 4, nw, nw, 1e-12, 2e-12, eps=1e-6)
+        b = C.tolerances(sel, 4, nw, nw, 1e-12, 2e-12, eps=1e-6, balance=True)
+        assert a == pytest.approx(b, rel=1e-15)
+
+
+@pytest.mark.parametrize("sel", ["mid", "tightA", "tightB"])
+def test_balance_is_scale_covariant(sel):
+    # w -> c w, t -> t / c leaves w t^T unchanged; the balanced tolerances
+    # must follow as (c delta^A, delta^B / c)
+    nw, nt = 3.0e2, 4.0e-3
+    dA, dB = C.tolerances(sel, 7, nw, nt, 1e-11, 3e-11, eps=1e-5, balance=True)
+    for c in (1e-4, 0.5, 3.0, 1e5):
+        eA, eB = C.tolerances(sel, 7, nw * c, nt / c, 1e-11, 3e-11, eps=1e-5, balance=True)
+        assert eA == pytest.approx(dA * c, rel=1e-13)
+        assert eB == pytest.approx(dB / c, rel=1e-13)
+
+
+def test_balance_mid_lies_on_the_boundary_curve():
+    # unclamped "mid" picks delta^B on the boundary of eq. (ADI_relax2_prak);
+    # the left-hand side is invariant under the rescaling, so it equals
+    # eps_hat in the original frame too
+    nw, nt, k, eps, u, v = 2.6e4, 5.9e-4, 6, 2.7e-5, 1e-9, 2e-9
+    eh = C.eps_hat_2(eps, 50, k, u, v, 1.0, False)
+    dA, dB = C.tolerances("mid", k, nw, nt, u, v, eps, dmin=1e-16, balance=True)
+    assert C.gap_lhs(dA, dB, nw, nt) == pytest.approx(eh, rel=1e-12)
+
+
+def test_balance_keeps_unbalanced_factors_admissible():
+    # ||w|| >> ||t||: in the original frame delta^B falls below delta_min and
+    # the clamp breaks the budget; in the balanced frame the same delta_min
+    # is admissible
+    nw, nt, k, eps, dmin = 2.6e4, 5.9e-4, 6, 2.7e-5, 5e-10
+    eh = C.eps_hat_2(eps, 50, k, 0.0, 0.0, 1.0, False)
+    dA, dB = C.tolerances("mid", k, nw, nt, 0.0, 0.0, eps, dmin=dmin)
+    assert dB == dmin and C.gap_lhs(dA, dB, nw, nt) > 10 * eh
+    dA, dB = C.tolerances("mid", k, nw, nt, 0.0, 0.0, eps, dmin=dmin, balance=True)
+    assert C.gap_lhs(dA, dB, nw, nt) <= eh * (1 + 1e-12)
