@@ -230,7 +230,8 @@ def bench_batch(args, L, WL):
     count = args.count or 256
     items = _batch_items(WL, L, count)
     ctx = L.Context(0)
-    o = L.default_opts(precision="fp32")
+    # controller in the balanced frame: the batch mixes grid sides 32..128
+    o = L.default_opts(precision="fp32", rescale=2)
     ctx.batch_solve(items[: min(8, count)], o)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -269,7 +270,9 @@ def bench_serve(args, L, WL):
         pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
         prepared.append((t, P, HA, HB, torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), pA, pB))
     ctx = L.Context(0)
-    srv = L.Server(ctx, L.default_opts(), hbm_budget=0, max_active=64)
+    # FP32 inner / FP64 outer; the controller works in the balanced frame,
+    # since n and m of one request can differ by three orders of magnitude
+    srv = L.Server(ctx, L.default_opts(precision="fp32", rescale=2), hbm_budget=0, max_active=64)
     tickets, lat, status = [], {}, {}
     t0 = time.perf_counter()
     i = 0

@@ -108,7 +108,11 @@ typedef struct {
   int32_t precision;   /* LRADI_FP64 or LRADI_FP32_INNER                      */
   int32_t restart;     /* block GMRES restart length m (blocks), 1..64        */
   int32_t max_inner;   /* cap on block Arnoldi steps per inner solve          */
-  int32_t rescale;     /* 1: scale f, g to equal spectral norm (Sec. 4)       */
+  int32_t rescale;     /* 1: scale f, g to equal spectral norm (Sec. 4).       *
+                        * 2: also evaluate the dynamic selections for the      *
+                        * pair (s w, t/s) at equal norms and map them back     *
+                        * (an extension: keeps delta_min admissible when the   *
+                        * factor norms drift apart; iterates are unchanged)    */
   int32_t b_is_transposed; /* 1: the B argument already holds B^T             */
   int32_t lookahead;   /* host scheduling depth (0 = synchronous), >= 0       */
   int32_t use_graph;   /* 1: replay the inner-iteration launch sequence from a

@@ -9,7 +9,7 @@ namespace lradi {
 // inner systems 2p: A side and 2p+1: B side).
 struct AdiDesc {
   int n, m, r, kmax, nshifts;
-  int selection, backlook, paper_abs, rescale;
+  int selection, backlook, paper_abs, rescale;  // rescale 2: controller in the balanced frame
   int setup;              // 1: the setup kernels initialise this problem
   double tol, eps_in, delta_min, delta_max, xi, delta_fixed, rho;
   const double* shiftsA;  // device, nshifts

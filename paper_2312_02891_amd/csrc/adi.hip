@@ -120,6 +120,7 @@ __device__ inline void arm_step(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& 
   cp.selection = P.selection;
   cp.backlook = P.backlook;
   cp.paper_abs = P.paper_abs;
+  cp.balance = P.rescale == 2;
   double dA, dB;
   ctl_tolerances(cp, C.k + 1, C.nw, C.nt, C.u, C.v, &dA, &dB);
   C.dA = dA;

@@ -15,6 +15,7 @@ struct CtlParams {
   double eps;        // absolute residual-gap budget
   double delta_min, delta_max, xi, delta_fixed, rho;
   int kmax, selection, backlook, paper_abs;
+  int balance;  // evaluate the dynamic selections in the balanced frame
 };
 
 // c = 2 + sqrt(2): bound on max(||C_k(A)||, ||C_k(B)||) + 1 from the
@@ -46,6 +47,16 @@ LRADI_HD inline void ctl_tolerances(const CtlParams& p, int k, double nw, double
   }
   const double eh = ctl_eps_hat(p, k, u, v);
   const double lo = p.delta_min, hi = p.delta_max;
+  // Balanced frame: (s w, t / s) with s = sqrt(||t|| / ||w||) has equal
+  // factor norms and the same w t^T; the left-hand side of the admissibility
+  // condition is invariant, so a selection made there and mapped back
+  // (delta^A / s, delta^B s) stays admissible, with the clamps of
+  // eq. (bound_tols) acting on the balanced pair.
+  double s = 1.0;
+  if (p.balance && nw > 0.0 && nt > 0.0) {
+    s = sqrt(nt / nw);
+    nw = nt = sqrt(nw * nt);
+  }
   double a, b;
   if (p.selection == LRADI_SEL_TIGHT_A) {
     a = lo;
@@ -57,8 +68,8 @@ LRADI_HD inline void ctl_tolerances(const CtlParams& p, int k, double nw, double
     a = fmax(0.5 * (fmin(hi, eh / nt) - lo), lo);
     b = fmax(fmin((eh - a * nt) / (2.0 * a + nw), hi), lo);
   }
-  *dA = a;
-  *dB = b;
+  *dA = a / s;
+  *dB = b * s;
 }
 
 // eq. (upd_resgap) with M = C = I.

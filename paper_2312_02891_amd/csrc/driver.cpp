@@ -475,6 +475,7 @@ int check_opts(const lradi_opts& o) {
     return set_error("need 0 < delta_min <= delta_max"), LRADI_EINVAL;
   if (!(o.xi > 0.0 && o.xi <= 1.0)) return set_error("xi must be in (0,1]"), LRADI_EINVAL;
   if (o.lookahead < 0) return set_error("lookahead must be >= 0"), LRADI_EINVAL;
+  if (o.rescale < 0 || o.rescale > 2) return set_error("rescale must be 0, 1 or 2"), LRADI_EINVAL;
   return LRADI_OK;
 }
 

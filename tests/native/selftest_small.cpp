@@ -13,11 +13,11 @@ double st_lmax_prod(const double* A, const double* B, int n) { return lradi::lam
 void st_house(double* M, double* Q, int n) { lradi::householder_2nxn(M, Q, n); }
 void st_tol(int selection, int backlook, int paper_abs, int k, double nw, double nt, double u,
             double v, double eps, int kmax, double xi, double dmin, double dmax, double dfix,
-            double rho, double* dA, double* dB) {
+            double rho, int balance, double* dA, double* dB) {
   lradi::CtlParams p;
   p.eps = eps; p.delta_min = dmin; p.delta_max = dmax; p.xi = xi; p.delta_fixed = dfix;
   p.rho = rho; p.kmax = kmax; p.selection = selection; p.backlook = backlook;
-  p.paper_abs = paper_abs;
+  p.paper_abs = paper_abs; p.balance = balance;
   lradi::ctl_tolerances(p, k, nw, nt, u, v, dA, dB);
 }
 void st_gap(double* u, double* v, double g, double nz, double ny, double rA, double rB) {

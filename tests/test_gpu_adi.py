@@ -94,6 +94,35 @@ def test_small_problem_dynamic_tolerances(L, ctx, sel):
         assert row[8] == pytest.approx(u, rel=1e-12) and row[9] == pytest.approx(v, rel=1e-12)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_unbalanced_factors_balanced_frame(L, ctx, precision):
+    """n = 3600 against m = 64, where ||w_k|| / ||t_k|| reaches 1e14: with the
+    controller in the balanced frame (rescale = 2) the run converges, matches
+    the direct-solve ADI iterate, and its recorded tolerances follow the
+    oracle's balanced formulas."""
+    say("adi unbalanced", precision)
+    P = WL.SMALL_UNBAL
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    o = L.default_opts(selection="mid", tol=P.tol, rescale=2, max_inner=3000,
+                       delta_min=P.tol / 20, delta_fixed=P.tol / 20, precision=precision)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    assert res.status == L.OK
+    compare(L, res, A, B, f, g, pA, pB, P.tol, kslack=1)
+    hist = res.history()
+    u = v = 0.0
+    eps = P.tol * res.norm_fg
+    for row in hist:
+        k = int(row[0])
+        dA, dB = OC.tolerances("mid", k, row[10], row[11], u, v, eps, dmin=P.tol / 20,
+                               balance=True)
+        assert row[2] == pytest.approx(dA, rel=1e-12)
+        assert row[3] == pytest.approx(dB, rel=1e-12)
+        assert row[4] <= row[2] * (1 + 1e-12) and row[5] <= row[3] * (1 + 1e-12)
+        u, v = OC.update_gap(u, v, row[14], row[12], row[13], row[4], row[5])
+    # the gap estimates stay inside the budget of eq. (ADI_relax2_prak)
+    assert u + v <= eps
+
+
 def test_small_3d_fp32_inner(L, ctx):
     """FP32 inner Krylov work with FP64 refinement and outer factors."""
     say("adi small 3d fp32")

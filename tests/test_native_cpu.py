@@ -81,7 +81,7 @@ def ST(tmp_path_factory):
     P = ctypes.POINTER(D)
     lib.st_lmax.restype = D
     lib.st_lmax_prod.restype = D
-    lib.st_tol.argtypes = [ctypes.c_int] * 4 + [D] * 5 + [ctypes.c_int] + [D] * 5 + [P, P]
+    lib.st_tol.argtypes = [ctypes.c_int] * 4 + [D] * 5 + [ctypes.c_int] + [D] * 5 + [ctypes.c_int, P, P]
     lib.st_gap.argtypes = [P, P] + [D] * 5
     return lib
 
@@ -171,11 +171,12 @@ def test_controller_matches_oracle(ST, seed):
     kmax, xi = int(rng.integers(10, 120)), float(rng.uniform(0.1, 1.0))
     dmin, dmax, dfix, rho = 5e-10, 0.1, 5e-10, 1e-12
     dA, dB = ctypes.c_double(), ctypes.c_double()
-    ST.st_tol(sel, bl, pabs, k, nw, nt, u, v, eps, kmax, xi, dmin, dmax, dfix, rho,
+    bal = int(rng.integers(0, 2))
+    ST.st_tol(sel, bl, pabs, k, nw, nt, u, v, eps, kmax, xi, dmin, dmax, dfix, rho, bal,
               ctypes.byref(dA), ctypes.byref(dB))
     wA, wB = OC.tolerances(sel_names[sel], k, nw, nt, u, v, eps, kmax=kmax, xi=xi, dmin=dmin,
                            dmax=dmax, backlook=bool(bl), fixed=dfix, rho=rho,
-                           paper_abs=bool(pabs))
+                           paper_abs=bool(pabs), balance=bool(bal))
     assert dA.value == pytest.approx(wA, rel=1e-13)
     assert dB.value == pytest.approx(wB, rel=1e-13)
     uu, vv = ctypes.c_double(u), ctypes.c_double(v)
