@@ -140,6 +140,7 @@ def main():
         Hp = L.convdiff(3, WL.PROBE.N, WL.PROBE.omega)
         Xp = torch.randn(Hp.n, WL.PROBE_R, dtype=torch.float32, device="cuda",
                          generator=torch.Generator(device="cuda").manual_seed(WL.PROBE_SEED))
+        extra["spmm_probe_lanes"] = ctx.spmm_tune(Hp, WL.PROBE_R, L.FP32_INNER)
         pms, pbytes = ctx.spmm_bench(Hp, -1000.0, Xp, reps=20)
         extra["spmm_probe_n"] = Hp.n
         extra["spmm_probe_us"] = round(pms * 1e3, 2)

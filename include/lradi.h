@@ -120,7 +120,12 @@ typedef struct {
   int32_t profile;     /* 1: time the projection (Gram) and shifted-product
                           launches with HIP events and count their
                           algorithmic bytes (see lradi_profile_read)         */
-  int32_t reserved[4];
+  int32_t spmm_lanes;  /* shifted-product tiling: lanes per matrix row, each
+                          owning r/lanes columns.  0: autotuned per matrix
+                          shape (timed once per context, see
+                          lradi_spmm_tune); -1: built-in rule without timing;
+                          1, 2, 4: forced (must divide r)                    */
+  int32_t reserved[3];
 } lradi_opts;
 
 /* Per inner solve statistics (lradi_shifted_solve). */
@@ -182,9 +187,19 @@ int lradi_spmm(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X,
  * then launches the product Y = (A + shift I) X reps times back to back and
  * returns the average launch time in milliseconds (HIP events on the
  * context's stream) and the algorithmic bytes of one launch (values,
- * column indices, row pointers, X read once, Y written once). */
+ * column indices, row pointers, X read once, Y written once).  lanes: the
+ * tiling (1, 2, 4 lanes per row, dividing r), or 0 for the one the solver
+ * would pick (lradi_spmm_tune). */
 int lradi_spmm_bench(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X, void* Y,
-                     int r, int precision, int reps, double* avg_ms, int64_t* bytes);
+                     int r, int precision, int lanes, int reps, double* avg_ms, int64_t* bytes);
+
+/* Autotuner of the shifted-product tiling: times every admissible lanes per
+ * row (1, 2, 4 dividing r) on A with r columns in the given precision and
+ * returns the fastest in *lanes; the choice is cached in the context per
+ * (n, nnz, r, precision) and reused by every later solve.  Products smaller
+ * than 1 MiB of X are launch-bound and take the built-in rule untimed.  All
+ * tilings give bitwise identical products. */
+int lradi_spmm_tune(lradi_ctx* ctx, const lradi_csr* A, int r, int precision, int* lanes);
 
 /* Solve nsys independent shifted block systems (A_s + shift_s I) Z_s = W_s
  * with block GMRES(m) plus FP64 iterative refinement until

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -189,6 +190,8 @@ struct lradi_ctx {
   DevBuf prof_dev;  // LRADI_PROF_CLASSES unsigned long long byte counters
   double prof_ms[LRADI_PROF_CLASSES] = {0.0, 0.0};
   int64_t prof_launches[LRADI_PROF_CLASSES] = {0, 0};
+  // autotuned shifted-product tiling per (n, nnz, r, precision)
+  std::map<std::array<int64_t, 4>, int> lanes_cache;
 };
 
 struct lradi_result {
@@ -208,6 +211,66 @@ int choose_rows_per_wg(int n) {
   int rpw = (n + 511) / 512;
   rpw = ((rpw + 255) / 256) * 256;
   return std::max(256, std::min(rpw, 8192));
+}
+
+// ---------------------------------------------------------------------------
+// Shifted-product autotuner: lanes per row (1, 2, 4 dividing r), timed with
+// HIP events on the context's stream; results cached per matrix shape.
+int spmm_time(lradi_ctx* c, const DevCSR& A, int r, int prec, int lanes, const void* X, void* Y,
+              int reps, double* ms) {
+  const void* val = prec == LRADI_FP64 ? A.val64.p : A.val32.p;
+  hipEvent_t e0, e1;
+  LRADI_HIP(hipEventCreate(&e0));
+  LRADI_HIP(hipEventCreate(&e1));
+  int rc = launch_spmm_plain(c->stream, A.n, r, prec, lanes, A.rowptr.as<int>(), A.colind.as<int>(), val,
+                             0.5, X, Y);  // warm-up
+  if (rc == LRADI_OK) rc = hipEventRecord(e0, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  for (int i = 0; i < reps && rc == LRADI_OK; ++i)
+    rc = launch_spmm_plain(c->stream, A.n, r, prec, lanes, A.rowptr.as<int>(), A.colind.as<int>(), val, 0.5,
+                           X, Y);
+  if (rc == LRADI_OK) rc = hipEventRecord(e1, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  float t = 0.f;
+  if (rc == LRADI_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  if (rc == LRADI_OK) rc = hipEventElapsedTime(&t, e0, e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != LRADI_OK) return set_error("shifted product: launch or event failure"), LRADI_EHIP;
+  *ms = (double)t / reps;
+  return LRADI_OK;
+}
+
+// policy: 0 autotune, -1 rule, 1/2/4 forced.  X is read, Y overwritten.
+int spmm_lanes_for(lradi_ctx* c, const DevCSR& A, int r, int prec, int policy, const void* X, void* Y,
+                   int* out) {
+  const int tsz = prec == LRADI_FP64 ? 8 : 4;
+  if (policy > 0) {
+    if (!(policy == 1 || policy == 2 || policy == 4) || r % policy != 0)
+      return set_error("spmm_lanes must be 1, 2 or 4 and divide r"), LRADI_EINVAL;
+    *out = policy;
+    return LRADI_OK;
+  }
+  const int rule = spmm_rule_lanes(r, tsz);
+  const std::array<int64_t, 4> key{A.n, A.nnz, r, prec};
+  auto it = c->lanes_cache.find(key);
+  if (it != c->lanes_cache.end()) {
+    *out = it->second;
+    return LRADI_OK;
+  }
+  *out = rule;
+  if (policy < 0 || r == 1 || (int64_t)A.n * r * tsz < (1 << 20) || !X || !Y) return LRADI_OK;
+  double best = 0.0;
+  LRADI_TRY(spmm_time(c, A, r, prec, rule, X, Y, 3, &best));
+  for (int lanes : {1, 2, 4}) {
+    if (lanes == rule || r % lanes != 0) continue;
+    double ms = 0.0;
+    LRADI_TRY(spmm_time(c, A, r, prec, lanes, X, Y, 3, &ms));
+    if (ms < 0.97 * best) {  // the rule keeps ties
+      best = ms;
+      *out = lanes;
+    }
+  }
+  c->lanes_cache[key] = *out;
+  return LRADI_OK;
 }
 
 // Workspace of one inner system: every device array the solver keeps for it
@@ -264,6 +327,7 @@ struct SysWork {
     d.W = W;
     d.pstride = (int)pstride;
     d.nnz = (int)A->nnz;
+    d.spmm_lanes = spmm_rule_lanes(r, (int)tsz);
     d.V = take(sizes[0]);
     d.U = take(sizes[1]);
     d.R = reinterpret_cast<double*>(take(sizes[2]));
@@ -281,6 +345,15 @@ struct SysWork {
     return LRADI_OK;
   }
 
+  // pick the shifted-product tiling (V's first two blocks serve as scratch;
+  // the solver overwrites them before use)
+  int tune(lradi_ctx* ctx, const DevCSR& A, int policy) {
+    const size_t blk = (size_t)d.n * d.r * (d.precision == LRADI_FP64 ? 8 : 4);
+    char* V = static_cast<char*>(d.V);
+    if (policy == 0) LRADI_HIP(hipMemsetAsync(V, 0, blk, ctx->stream));
+    return spmm_lanes_for(ctx, A, d.r, d.precision, policy, V, V + blk, &d.spmm_lanes);
+  }
+
   // a standalone solve of (A + shift I) Z = W to ||R||_2 <= delta
   void arm(double* Z, double shift, double delta) {
     c = SysCtl{};
@@ -296,8 +369,8 @@ struct SysWork {
 struct Table {
   std::vector<SysDesc> hd;
   std::vector<SysCtl> hc;
-  std::vector<int2> hmap;
-  DevBuf dd, dc, dmap;
+  std::vector<int2> hmap, hsp;
+  DevBuf dd, dc, dmap, dsp;
   Batch b{};
 };
 
@@ -318,6 +391,21 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
     maxP = std::max(maxP, ws[s]->d.pstride);
     if (ws[s]->d.r != rfix) rfix = 0;
   }
+  // shifted-product tiles, grouped by lanes per row
+  t.hsp.clear();
+  for (int g = 0; g < 3; ++g) {
+    const int lanes = 1 << g;
+    t.b.spoff[g] = (int)t.hsp.size();
+    for (int s = 0; s < nsys; ++s) {
+      if (ws[s]->d.spmm_lanes != lanes) continue;
+      if (ws[s]->d.r % lanes != 0) return set_error("lanes per row must divide r"), LRADI_EINVAL;
+      const int tr = spmm_tile_rows(lanes);
+      const int tiles = (ws[s]->d.n + tr - 1) / tr;
+      for (int w = 0; w < tiles; ++w) t.hsp.push_back(make_int2(s, w));
+    }
+    t.b.spcount[g] = (int)t.hsp.size() - t.b.spoff[g];
+  }
+  if (t.dsp.bytes < sizeof(int2) * t.hsp.size()) LRADI_TRY(t.dsp.alloc(sizeof(int2) * t.hsp.size()));
   if (t.dd.bytes < sizeof(SysDesc) * nsys) LRADI_TRY(t.dd.alloc(sizeof(SysDesc) * nsys));
   if (t.dc.bytes < sizeof(SysCtl) * nsys) LRADI_TRY(t.dc.alloc(sizeof(SysCtl) * nsys));
   if (t.dmap.bytes < sizeof(int2) * t.hmap.size()) LRADI_TRY(t.dmap.alloc(sizeof(int2) * t.hmap.size()));
@@ -325,11 +413,13 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   LRADI_HIP(hipMemcpyAsync(t.dd.p, t.hd.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(t.dc.p, t.hc.data(), sizeof(SysCtl) * nsys, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(t.dmap.p, t.hmap.data(), sizeof(int2) * t.hmap.size(), hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(t.dsp.p, t.hsp.data(), sizeof(int2) * t.hsp.size(), hipMemcpyHostToDevice, st));
   // the host vectors must outlive the copies
   LRADI_HIP(hipStreamSynchronize(st));
   t.b.d = t.dd.as<SysDesc>();
   t.b.ctl = t.dc.as<SysCtl>();
   t.b.rowmap = t.dmap.as<int2>();
+  t.b.spmap = t.dsp.as<int2>();
   t.b.nsys = nsys;
   t.b.rowgrid = (int)t.hmap.size();
   t.b.maxP = maxP;
@@ -476,6 +566,8 @@ int check_opts(const lradi_opts& o) {
   if (!(o.xi > 0.0 && o.xi <= 1.0)) return set_error("xi must be in (0,1]"), LRADI_EINVAL;
   if (o.lookahead < 0) return set_error("lookahead must be >= 0"), LRADI_EINVAL;
   if (o.rescale < 0 || o.rescale > 2) return set_error("rescale must be 0, 1 or 2"), LRADI_EINVAL;
+  if (!(o.spmm_lanes >= -1 && o.spmm_lanes <= 4 && o.spmm_lanes != 3))
+    return set_error("spmm_lanes must be -1, 0, 1, 2 or 4"), LRADI_EINVAL;
   return LRADI_OK;
 }
 
@@ -593,6 +685,8 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
   const double fl = floor_for(o);
   LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
   LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
+  LRADI_TRY(q.wa.tune(c, q.A, o.spmm_lanes));
+  LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
   LRADI_TRY(q.done.init());
   LRADI_HIP(hipStreamSynchronize(st));
   return LRADI_OK;
@@ -850,15 +944,17 @@ int lradi_spmm(lradi_ctx* c, const lradi_csr* A, double shift, const void* X, vo
   LRADI_HIP(hipSetDevice(c->device));
   DevCSR dA;
   LRADI_TRY(dA.upload(A, c->stream, precision == LRADI_FP32_INNER));
+  int lanes = 1;
+  LRADI_TRY(spmm_lanes_for(c, dA, r, precision, -1, nullptr, nullptr, &lanes));
   const void* val = (precision == LRADI_FP64) ? dA.val64.p : dA.val32.p;
-  LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(),
+  LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, lanes, dA.rowptr.as<int>(),
                               dA.colind.as<int>(), val, shift, X, Y));
   LRADI_HIP(hipStreamSynchronize(c->stream));
   return LRADI_OK;
 }
 
 int lradi_spmm_bench(lradi_ctx* c, const lradi_csr* A, double shift, const void* X, void* Y, int r,
-                     int precision, int reps, double* avg_ms, int64_t* bytes) {
+                     int precision, int lanes, int reps, double* avg_ms, int64_t* bytes) {
   if (!c || !X || !Y || !avg_ms || reps < 1) return set_error("lradi_spmm_bench: bad argument"), LRADI_EINVAL;
   if (r < 1 || r > kMaxR) return set_error("lradi_spmm_bench: r must be in 1..%d", kMaxR), LRADI_EINVAL;
   if (precision != LRADI_FP64 && precision != LRADI_FP32_INNER)
@@ -866,26 +962,36 @@ int lradi_spmm_bench(lradi_ctx* c, const lradi_csr* A, double shift, const void*
   LRADI_HIP(hipSetDevice(c->device));
   DevCSR dA;
   LRADI_TRY(dA.upload(A, c->stream, precision == LRADI_FP32_INNER));
+  int use = 1;
+  LRADI_TRY(spmm_lanes_for(c, dA, r, precision, lanes, X, Y, &use));
+  double ms = 0.0;
+  LRADI_TRY(spmm_time(c, dA, r, precision, use, X, Y, reps, &ms));
+  // leave Y = (A + shift I) X
   const void* val = (precision == LRADI_FP64) ? dA.val64.p : dA.val32.p;
-  hipEvent_t e0, e1;
-  LRADI_HIP(hipEventCreate(&e0));
-  LRADI_HIP(hipEventCreate(&e1));
-  int rc = launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(), dA.colind.as<int>(), val,
-                             shift, X, Y);  // warm-up
-  if (rc == LRADI_OK) rc = hipEventRecord(e0, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
-  for (int i = 0; i < reps && rc == LRADI_OK; ++i)
-    rc = launch_spmm_plain(c->stream, dA.n, r, precision, dA.rowptr.as<int>(), dA.colind.as<int>(), val,
-                           shift, X, Y);
-  if (rc == LRADI_OK) rc = hipEventRecord(e1, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
-  float ms = 0.f;
-  if (rc == LRADI_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
-  if (rc == LRADI_OK) rc = hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc != LRADI_OK) return set_error("lradi_spmm_bench: launch or event failure"), LRADI_EHIP;
-  *avg_ms = (double)ms / reps;
+  LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, use, dA.rowptr.as<int>(), dA.colind.as<int>(),
+                              val, shift, X, Y));
+  LRADI_HIP(hipStreamSynchronize(c->stream));
+  *avg_ms = ms;
   const int64_t tsz = precision == LRADI_FP64 ? 8 : 4;
   if (bytes) *bytes = dA.nnz * (tsz + 4) + 4 * ((int64_t)dA.n + 1) + 2 * tsz * (int64_t)dA.n * r;
+  return LRADI_OK;
+}
+
+int lradi_spmm_tune(lradi_ctx* c, const lradi_csr* A, int r, int precision, int* lanes) {
+  if (!c || !lanes) return set_error("lradi_spmm_tune: null argument"), LRADI_EINVAL;
+  if (r < 1 || r > kMaxR) return set_error("lradi_spmm_tune: r must be in 1..%d", kMaxR), LRADI_EINVAL;
+  if (precision != LRADI_FP64 && precision != LRADI_FP32_INNER)
+    return set_error("lradi_spmm_tune: unknown precision"), LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  DevCSR dA;
+  LRADI_TRY(dA.upload(A, c->stream, precision == LRADI_FP32_INNER));
+  const size_t blk = (size_t)dA.n * r * (precision == LRADI_FP64 ? 8 : 4);
+  DevBuf X, Y;
+  LRADI_TRY(X.alloc(blk));
+  LRADI_TRY(Y.alloc(blk));
+  LRADI_HIP(hipMemsetAsync(X.p, 0, blk, c->stream));
+  LRADI_TRY(spmm_lanes_for(c, dA, r, precision, 0, X.p, Y.p, lanes));
+  LRADI_HIP(hipStreamSynchronize(c->stream));
   return LRADI_OK;
 }
 
@@ -910,6 +1016,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
     work[s] = std::make_unique<SysWork>();
     LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o)));
+    LRADI_TRY(work[s]->tune(c, mats[s], o.spmm_lanes));
     work[s]->arm(Z[s], shift[s], delta[s]);
     ws[s] = work[s].get();
   }

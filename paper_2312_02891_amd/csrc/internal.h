@@ -17,6 +17,19 @@ constexpr int kTPB = 256;       // threads of a row workgroup (4 wavefronts)
 constexpr int kSmallTPB = 64;   // threads of a per-system workgroup (1 wavefront)
 constexpr int kHistCols = LRADI_HIST_COLS;
 constexpr int kPS = 128;        // stride of the small Gram partial rows
+constexpr int kSpmmCap = 2048;  // nonzeros of one SpMM tile staged in LDS
+
+// Shifted-product tiling: `lanes` lanes share one matrix row, each owning
+// r / lanes of its columns, so a tile covers kTPB / lanes rows.  lanes is 1,
+// 2 or 4 and divides r.
+constexpr int spmm_tile_rows(int lanes) { return kTPB / lanes; }
+// Default lanes per row: the widest split that still leaves each lane 16
+// contiguous bytes of every gathered row of X (one 128-bit load).
+inline int spmm_rule_lanes(int r, int tsz) {
+  int rl = 1;
+  while (rl < 4 && r % (2 * rl) == 0 && r * tsz / (2 * rl) >= 16) rl *= 2;
+  return rl;
+}
 
 // Phases of one inner solve; every kernel of the batched solver checks the
 // phase of its system and returns at once when it is not the one it serves.
@@ -57,6 +70,7 @@ struct SysDesc {
   double* sm;           // small scratch (8 x 64 doubles)
   int pstride;          // stride of part rows (>= (m+1) r^2)
   int nnz;              // nonzeros of A
+  int spmm_lanes;       // lanes per row of the shifted product (1, 2, 4)
 };
 
 // Mutable device-side control block of one inner solve.
@@ -128,7 +142,7 @@ struct DevCSR {
 
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels.hip)
-int launch_spmm_plain(hipStream_t st, int n, int r, int precision, const int* rowptr,
+int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* rowptr,
                       const int* colind, const void* val, double shift, const void* X, void* Y);
 
 // The batched inner solver: all systems of a batch share one precision.
@@ -138,6 +152,10 @@ struct Batch {
   const int2* rowmap;  // device array of rowgrid entries (system, chunk)
   int nsys;
   int rowgrid;
+  // shifted-product tiles (system, tile), grouped by lanes per row: group g
+  // (lanes 1, 2, 4) holds spcount[g] entries starting at spmap + spoff[g]
+  const int2* spmap;
+  int spoff[3], spcount[3];
   int maxP;            // max over systems of (m+1) r^2
   int precision;       // LRADI_FP64 / LRADI_FP32_INNER
   int rfix;            // common r of all systems, or 0 when they differ

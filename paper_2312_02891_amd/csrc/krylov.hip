@@ -104,54 +104,132 @@ __device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, do
 
 // ---------------------------------------------------------------------------
 // 1. U = (A + s I) V_j  (PH_ARNOLDI)   or   U = R rounded  (PH_RESTART)
-template <typename T, int R>
-__device__ inline void spmm_rows(const SysDesc& D, const RowCtx& c, T shift, const T* __restrict__ X,
-                                 T* __restrict__ Y) {
-  const T* __restrict__ val = static_cast<const T*>(D.valT);
-  const int* __restrict__ rp = D.rowptr;
-  const int* __restrict__ ci = D.colind;
-  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
-    T acc[R];
+//
+// One tile = kTPB / RL consecutive rows.  Its nonzeros (a contiguous range
+// of the CSR arrays) are first copied to LDS with coalesced loads; then RL
+// lanes work on each row, each for R / RL columns, and walk the row's
+// nonzeros SU at a time with all gathers of a group in flight together.
+// Every output element sums its terms in the same order for every RL, so
+// the result does not depend on the tiling.
+template <typename T>
+struct SpmmUnroll {
+  static constexpr int v = sizeof(T) == 8 ? 4 : 8;
+};
+
+// One row, columns q0..q0+RC: nonzeros SU at a time; a group's last slots
+// beyond the row repeat its final entry with a zero coefficient, so every
+// load stays unconditional (and in bounds) and all gathers of a group are in
+// flight together.  ci/val point either to LDS (offset base) or to the CSR
+// arrays (offset 0).
+template <typename T, int R, int RC, int SU>
+__device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, const T* val, int off,
+                                T shift, const T* __restrict__ X, T* __restrict__ Y) {
+  T acc[RC];
 #pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = T(0);
-    const int k0 = rp[i], k1 = rp[i + 1];
-    for (int k = k0; k < k1; ++k) {
-      const int col = ci[k];
-      const T a = val[k];
-      const T* x = X + (size_t)col * R;
+  for (int q = 0; q < RC; ++q) acc[q] = T(0);
+  for (int k = k0; k < k1; k += SU) {
+    int col[SU];
+    T a[SU];
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += a * x[q];
+    for (int u = 0; u < SU; ++u) {
+      const int kk = min(k + u, k1 - 1) - off;
+      col[u] = ci[kk];
+      a[u] = val[kk] * (T)(k + u < k1);
     }
-    const T* xi = X + (size_t)i * R;
+    T xv[SU][RC];
 #pragma unroll
-    for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = acc[q] + shift * xi[q];
+    for (int u = 0; u < SU; ++u) {
+      const T* x = X + (size_t)col[u] * R + q0;
+#pragma unroll
+      for (int q = 0; q < RC; ++q) xv[u][q] = x[q];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+#pragma unroll
+      for (int q = 0; q < RC; ++q) acc[q] += a[u] * xv[u][q];
   }
+  const T* xi = X + (size_t)i * R + q0;
+  T* y = Y + (size_t)i * R + q0;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) y[q] = acc[q] + shift * xi[q];
 }
 
-template <typename T, int RF>
+template <typename T, int R, int RL>
+__device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                 const T* __restrict__ val, T shift, const T* __restrict__ X,
+                                 T* __restrict__ Y, int r0, int* s_ci, T* s_val) {
+  constexpr int RC = R / RL;
+  constexpr int SU = SpmmUnroll<T>::v;
+  constexpr int PER = kSpmmCap / kTPB;
+  const int r1 = min(n, r0 + spmm_tile_rows(RL));
+  const int i = r0 + (int)threadIdx.x / RL;
+  const bool live = i < r1;
+  int k0 = 0, k1 = 0;
+  if (live) {
+    k0 = rp[i];
+    k1 = rp[i + 1];
+  }
+  const int base = rp[r0], cnt = rp[r1] - base;
+  const bool staged = cnt <= kSpmmCap;
+  if (staged && cnt > 0) {
+    // all PER loads of a thread in flight at once (indices clamped into the
+    // tile), then the stores of the ones inside it
+    int cv[PER];
+    T vv[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = base + min(p * kTPB + (int)threadIdx.x, cnt - 1);
+      cv[p] = ci[e];
+      vv[p] = val[e];
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = p * kTPB + (int)threadIdx.x;
+      if (e < cnt) {
+        s_ci[e] = cv[p];
+        s_val[e] = vv[p];
+      }
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  const int q0 = ((int)threadIdx.x % RL) * RC;
+  if (staged)
+    spmm_row<T, R, RC, SU>(i, q0, k0, k1, s_ci, s_val, base, shift, X, Y);
+  else
+    spmm_row<T, R, RC, SU>(i, q0, k0, k1, ci, val, 0, shift, X, Y);
+}
+
+// RL lanes per row; the kernel for group RL serves the systems whose tiling
+// uses RL (RF > 0: all systems have r = RF; RF == 0: r read at run time)
+template <typename T, int RF, int RL>
 __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
                                                    const SysCtl* __restrict__ ctl,
-                                                   const int2* __restrict__ rowmap,
+                                                   const int2* __restrict__ spmap,
                                                    unsigned long long* __restrict__ prof) {
-  const RowCtx c = row_ctx(d, rowmap);
-  const SysDesc& D = d[c.s];
-  const int ph = ctl[c.s].phase;
+  __shared__ int s_ci[kSpmmCap];
+  __shared__ T s_val[kSpmmCap];
+  const int2 e = spmap[blockIdx.x];
+  const SysDesc& D = d[e.x];
+  const int ph = ctl[e.x].phase;
+  const int r0 = e.y * spmm_tile_rows(RL);
   T* U = static_cast<T*>(D.U);
   if (ph == PH_RESTART) {
-    const size_t e1 = (size_t)c.row1 * D.r;
-    for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) U[e] = (T)D.R[e];
+    const size_t e1 = (size_t)min(D.n, r0 + spmm_tile_rows(RL)) * D.r;
+    for (size_t q = (size_t)r0 * D.r + threadIdx.x; q < e1; q += kTPB) U[q] = (T)D.R[q];
     return;
   }
   if (ph != PH_ARNOLDI) return;
-  const T* Vj = static_cast<const T*>(D.V) + (size_t)ctl[c.s].j * D.n * D.r;
-  const T sh = (T)ctl[c.s].shift;
-  if (prof && c.w == 0 && threadIdx.x == 0) {
+  const T* Vj = static_cast<const T*>(D.V) + (size_t)ctl[e.x].j * D.n * D.r;
+  const T sh = (T)ctl[e.x].shift;
+  if (prof && e.y == 0 && threadIdx.x == 0) {
     // values + column indices + row pointers + input block + output block
     const unsigned long long bytes = (unsigned long long)D.nnz * (sizeof(T) + 4) +
                                      4ull * (D.n + 1) + 2ull * sizeof(T) * D.n * D.r;
     atomicAdd(prof + LRADI_PROF_SPMM, bytes);
   }
-  LRADI_RSEL(RF, D.r, spmm_rows<T, RR>(D, c, sh, Vj, U));
+  const T* val = static_cast<const T*>(D.valT);
+  LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.n, D.rowptr, D.colind, val, sh, Vj, U, r0, s_ci, s_val));
 }
 
 // ---------------------------------------------------------------------------
@@ -840,24 +918,16 @@ __global__ __launch_bounds__(kTPB) void k_summary(const SysCtl* __restrict__ ctl
   }
 }
 
-// plain Y = (A + s I) X for one block (no phases); the same row routine as
+// plain Y = (A + s I) X for one block (no phases); the same tile routine as
 // the solver's shifted product
-template <typename T, int R>
+template <typename T, int R, int RL>
 __global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
                                                      const T* __restrict__ val, T shift,
                                                      const T* __restrict__ X, T* __restrict__ Y) {
-  SysDesc D{};
-  D.n = n;
-  D.rowptr = rp;
-  D.colind = ci;
-  D.valT = val;
-  RowCtx c;
-  c.s = 0;
-  c.w = blockIdx.x;
-  c.row0 = blockIdx.x * kTPB;
-  c.row1 = min(n, c.row0 + kTPB);
-  spmm_rows<T, R>(D, c, shift, X, Y);
+  __shared__ int s_ci[kSpmmCap];
+  __shared__ T s_val[kSpmmCap];
+  spmm_tile<T, R, RL>(n, rp, ci, val, shift, X, Y, (int)blockIdx.x * spmm_tile_rows(RL), s_ci, s_val);
 }
 
 template <typename T, int RF>
@@ -866,7 +936,17 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
-  hipLaunchKernelGGL((k_spmm_arn<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
+  if (b.spcount[0] > 0)
+    hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,
+                       b.spmap + b.spoff[0], b.prof_bytes);
+  if constexpr (RF == 0 || RF % 2 == 0)
+    if (b.spcount[1] > 0)
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(b.spcount[1]), tb, 0, st, b.d, b.ctl,
+                         b.spmap + b.spoff[1], b.prof_bytes);
+  if constexpr (RF == 0 || RF % 4 == 0)
+    if (b.spcount[2] > 0)
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(b.spcount[2]), tb, 0, st, b.d, b.ctl,
+                         b.spmap + b.spoff[2], b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[5], st));
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[0], st));
   hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
@@ -919,21 +999,37 @@ int launch_summary(hipStream_t st, const Batch& b, int* host_slot) {
   return LRADI_OK;
 }
 
-int launch_spmm_plain(hipStream_t st, int n, int r, int precision, const int* rowptr,
-                      const int* colind, const void* val, double shift, const void* X, void* Y) {
-  if (n <= 0) return LRADI_OK;
-  const dim3 g((n + kTPB - 1) / kTPB), tb(kTPB);
-  if (precision == LRADI_FP64) {
-    LRADI_DISPATCH_R(r, hipLaunchKernelGGL((k_spmm_plain<double, RR>), g, tb, 0, st, n, rowptr,
-                                           colind, static_cast<const double*>(val), shift,
-                                           static_cast<const double*>(X), static_cast<double*>(Y)));
-  } else {
-    LRADI_DISPATCH_R(r, hipLaunchKernelGGL((k_spmm_plain<float, RR>), g, tb, 0, st, n, rowptr,
-                                           colind, static_cast<const float*>(val), (float)shift,
-                                           static_cast<const float*>(X), static_cast<float*>(Y)));
-  }
+namespace {
+template <typename T>
+int spmm_plain_t(hipStream_t st, int n, int r, int lanes, const int* rowptr, const int* colind,
+                 const T* val, T shift, const T* X, T* Y) {
+  const dim3 g((n + spmm_tile_rows(lanes) - 1) / spmm_tile_rows(lanes)), tb(kTPB);
+  LRADI_DISPATCH_R(r, {
+    if (lanes == 1) {
+      hipLaunchKernelGGL((k_spmm_plain<T, RR, 1>), g, tb, 0, st, n, rowptr, colind, val, shift, X, Y);
+    } else if (lanes == 2) {
+      if constexpr (RR % 2 == 0)
+        hipLaunchKernelGGL((k_spmm_plain<T, RR, 2>), g, tb, 0, st, n, rowptr, colind, val, shift, X, Y);
+    } else {
+      if constexpr (RR % 4 == 0)
+        hipLaunchKernelGGL((k_spmm_plain<T, RR, 4>), g, tb, 0, st, n, rowptr, colind, val, shift, X, Y);
+    }
+  });
   LRADI_HIP(hipGetLastError());
   return LRADI_OK;
+}
+}  // namespace
+
+int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* rowptr,
+                      const int* colind, const void* val, double shift, const void* X, void* Y) {
+  if (n <= 0) return LRADI_OK;
+  if (r < 1 || r > kMaxR || !(lanes == 1 || lanes == 2 || lanes == 4) || r % lanes != 0)
+    return LRADI_EINVAL;
+  if (precision == LRADI_FP64)
+    return spmm_plain_t<double>(st, n, r, lanes, rowptr, colind, static_cast<const double*>(val), shift,
+                                static_cast<const double*>(X), static_cast<double*>(Y));
+  return spmm_plain_t<float>(st, n, r, lanes, rowptr, colind, static_cast<const float*>(val), (float)shift,
+                             static_cast<const float*>(X), static_cast<float*>(Y));
 }
 
 }  // namespace lradi

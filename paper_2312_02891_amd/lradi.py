@@ -52,7 +52,7 @@ class Opts(ctypes.Structure):
                 ("max_inner", ctypes.c_int32), ("rescale", ctypes.c_int32),
                 ("b_is_transposed", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("spmm_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Problem(ctypes.Structure):
@@ -101,7 +101,9 @@ def _load():
         "lradi_convdiff_size": (i32, [i32, i32, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "lradi_gen_convdiff": (i32, [i32, i32, P(dbl), vp, vp, vp]),
         "lradi_spmm": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32]),
-        "lradi_spmm_bench": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32, i32, P(dbl), P(ctypes.c_int64)]),
+        "lradi_spmm_bench": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32, i32, i32, P(dbl),
+                                   P(ctypes.c_int64)]),
+        "lradi_spmm_tune": (i32, [vp, P(Csr), i32, i32, P(i32)]),
         "lradi_shifted_solve": (i32, [vp, i32, P(P(Csr)), P(dbl), P(vp), P(vp), P(i32), P(dbl),
                                       P(Opts), P(InnerStats)]),
         "lradi_solve": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32, P(Opts),
@@ -301,17 +303,27 @@ class Context:
                                X.shape[1], prec), allow_warn=False)
         return Y
 
-    def spmm_bench(self, A: HostCsr, shift: float, X, reps: int = 20):
+    def spmm_bench(self, A: HostCsr, shift: float, X, reps: int = 20, lanes: int = 0, out=None):
         """(average ms per launch, algorithmic bytes per launch) of the
-        shifted product on X (FP64 or FP32 CUDA tensor)."""
+        shifted product on X (FP64 or FP32 CUDA tensor); lanes = 0 uses the
+        tiling the solver would pick.  `out` (like X) receives the product."""
         torch = _torch()
         prec = FP64 if X.dtype == torch.float64 else FP32_INNER
-        Y = torch.empty_like(X)
+        Y = torch.empty_like(X) if out is None else out
+        assert Y.shape == X.shape and Y.dtype == X.dtype and Y.is_cuda and Y.is_contiguous()
         ms, nb = ctypes.c_double(), ctypes.c_int64()
         self._sync()
         _check(_lib.lradi_spmm_bench(self.h, ctypes.byref(A.c), float(shift), _ptr(X), _ptr(Y), X.shape[1],
-                                     prec, reps, ctypes.byref(ms), ctypes.byref(nb)), allow_warn=False)
+                                     prec, lanes, reps, ctypes.byref(ms), ctypes.byref(nb)), allow_warn=False)
         return ms.value, nb.value
+
+    def spmm_tune(self, A: HostCsr, r: int, precision: int = FP64) -> int:
+        """Lanes per row the autotuner picks for A with r columns."""
+        lanes = ctypes.c_int()
+        self._sync()
+        _check(_lib.lradi_spmm_tune(self.h, ctypes.byref(A.c), r, precision, ctypes.byref(lanes)),
+               allow_warn=False)
+        return lanes.value
 
     def shifted_solve(self, mats: List[HostCsr], shifts, Ws, deltas, opts: Optional[Opts] = None):
         """Batched (A_s + shift_s I) Z_s = W_s to ||R_s||_2 <= delta_s; returns (Zs, stats)."""

@@ -123,6 +123,24 @@ def test_unbalanced_factors_balanced_frame(L, ctx, precision):
     assert u + v <= eps
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_independent_of_spmm_tiling(L, ctx, precision):
+    """Forcing 1, 2 or 4 lanes per row in the shifted product leaves every
+    factor of the solve bit for bit unchanged."""
+    say("adi tiling", precision)
+    P = WL.Problem(WL.SMALL_3D.A, WL.SMALL_3D.B, r=4, nshifts=12, seed=21)
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    got = []
+    for lanes in (1, 2, 4):
+        o = L.default_opts(precision=precision, tol=P.tol, spmm_lanes=lanes)
+        res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+        assert res.status == L.OK
+        got.append(res.factors())
+    for Z, d, Y in got[1:]:
+        assert np.array_equal(Z, got[0][0]) and np.array_equal(d, got[0][1])
+        assert np.array_equal(Y, got[0][2])
+
+
 def test_small_3d_fp32_inner(L, ctx):
     """FP32 inner Krylov work with FP64 refinement and outer factors."""
     say("adi small 3d fp32")

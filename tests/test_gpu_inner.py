@@ -66,6 +66,78 @@ def test_spmm_fp32_matches_oracle(L, ctx, dim, N, omega, r):
     assert np.abs(Y - want).max() <= 2e-6 * scale
 
 
+def _wide_csr(n, per_row, seed):
+    """Random sparse matrix with per_row nonzeros in every row (plus the
+    diagonal): a 256-row tile holds more nonzeros than fit in LDS."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        cols = np.unique(np.concatenate([[i], rng.integers(0, n, per_row)]))
+        rows.append(cols)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(c) for c in rows])
+    ci = np.concatenate(rows)
+    v = rng.standard_normal(len(ci))
+    return rp, ci, v
+
+
+TILING_CASES = [("cd3", 4, "f64"), ("cd3", 8, "f64"), ("cd3", 8, "f32"), ("cd3", 6, "f64"),
+                ("cd2", 2, "f32"), ("cd2", 4, "f64"), ("wide", 4, "f64"), ("wide", 8, "f32")]
+
+
+@pytest.mark.parametrize("mat,r,prec", TILING_CASES)
+def test_spmm_tilings_are_bitwise_identical(L, ctx, mat, r, prec):
+    """Every admissible tiling (1, 2, 4 lanes per row) gives the same bits as
+    the default one, on stencil matrices with a ragged last tile and on a
+    matrix whose tiles overflow the LDS staging buffer; the product also
+    matches the oracle's matrix."""
+    import torch
+    say("spmm tilings", mat, r, prec)
+    if mat == "cd3":
+        H = L.convdiff(3, 29, (10.0, -15.0, -5.0))
+        A = convdiff_matrix(3, 29, (10.0, -15.0, -5.0))
+    elif mat == "cd2":
+        H = L.convdiff(2, 301, (50.0, 20.0))
+        A = convdiff_matrix(2, 301, (50.0, 20.0))
+    else:
+        rp, ci, v = _wide_csr(3001, 40, 7)
+        H = L.HostCsr(rp, ci, v)
+        A = sp.csr_matrix((v, ci, rp), shape=(3001, 3001))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rng = np.random.default_rng(r)
+    X = torch.from_numpy(rng.standard_normal((H.n, r))).to(dt).cuda()
+    s = -321.75
+    ref = ctx.spmm(H, s, X)
+    outs = []
+    for lanes in (1, 2, 4):
+        if r % lanes:
+            continue
+        Y = torch.empty_like(X)
+        ctx.spmm_bench(H, s, X, reps=1, lanes=lanes, out=Y)
+        torch.cuda.synchronize()
+        outs.append((lanes, Y))
+    for lanes, Y in outs:
+        assert torch.equal(Y, ref), f"lanes={lanes} differs"
+    Xd = X.double().cpu().numpy()
+    Ad = A if prec == "f64" else sp.csr_matrix(
+        (A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), A.shape)
+    want = Ad @ Xd + s * Xd
+    scale = (abs(Ad) @ np.abs(Xd) + abs(s) * np.abs(Xd)).max()
+    tol = 1e-14 if prec == "f64" else 2e-6
+    assert np.abs(ref.double().cpu().numpy() - want).max() <= tol * scale
+
+
+def test_spmm_autotuner_choice_is_valid_and_cached(L, ctx):
+    """The tuner returns an admissible tiling for a product above its size
+    threshold, and the same one again from its cache."""
+    say("spmm tune")
+    H = L.convdiff(3, 64, (20.0, 10.0, 5.0))
+    for r, prec in ((8, L.FP32_INNER), (4, L.FP64), (3, L.FP64)):
+        a = ctx.spmm_tune(H, r, prec)
+        assert a in (1, 2, 4) and r % a == 0
+        assert ctx.spmm_tune(H, r, prec) == a
+
+
 @pytest.mark.parametrize("r", [1, 2, 3, 4, 8])
 @pytest.mark.parametrize("j", [1, 3, 7])
 def test_first_cycle_equals_block_minres_definition(L, ctx, r, j):
