@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented solve")
     ap.add_argument("--no-probe", action="store_true", help="skip the beyond-LLC SpMM probe")
-    ap.add_argument("--workload", default="c2", choices=["c2", "batch", "serve"],
-                    help="c2: the metric's configuration (default); batch: 256 independent "
-                         "problems; serve: Poisson request stream")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "batch", "serve"],
+                    help="c2: the metric's configuration (default); c3: 3-D mixed-precision "
+                         "configuration, FP32-inner relaxed vs FP64 exact tolerance; batch: "
+                         "256 independent problems; serve: Poisson request stream")
     ap.add_argument("--count", type=int, default=0, help="problems (batch) or requests (serve)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     return ap.parse_args()
@@ -65,6 +66,8 @@ def main():
         return bench_batch(args, L, WL)
     if args.workload == "serve":
         return bench_serve(args, L, WL)
+    if args.workload == "c3":
+        return bench_c3(args, L, WL)
     P = WL.C2
     HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
     HBt = L.convdiff(P.B.dim, P.B.N, tuple(-w for w in P.B.omega))   # B^T (bit-identical)
@@ -209,6 +212,78 @@ def cpu_baseline(P, f, g, pA, pB, res):
              "sample": "one full oracle solve of the same problem (SciPy SuperLU per distinct "
                        "shift, single-threaded factorisations, BLAS threads for the small "
                        "dense steps)"}, float(xerr))
+
+
+def _lowrank_diff(res_a, res_b):
+    """||X_a - X_b||_F / ||X_b||_F for X = Z diag(gamma) Y^T, without forming
+    X: QR of the stacked left and right factors on the GPU, then the small
+    core product."""
+    import torch
+    Za, Ya = (t.clone() for t in res_a.device_factors())
+    Zb, Yb = (t.clone() for t in res_b.device_factors())
+    ga = torch.from_numpy(res_a.gammas()).cuda().repeat_interleave(res_a.r)
+    gb = torch.from_numpy(res_b.gammas()).cuda().repeat_interleave(res_b.r)
+    Za = Za.reshape(res_a.k, res_a.n, res_a.r).permute(1, 0, 2).reshape(res_a.n, -1)
+    Zb = Zb.reshape(res_b.k, res_b.n, res_b.r).permute(1, 0, 2).reshape(res_b.n, -1)
+    Ya = Ya.reshape(res_a.k, res_a.m, res_a.r).permute(1, 0, 2).reshape(res_a.m, -1)
+    Yb = Yb.reshape(res_b.k, res_b.m, res_b.r).permute(1, 0, 2).reshape(res_b.m, -1)
+    _, R1 = torch.linalg.qr(torch.cat([Za * ga, -Zb * gb], dim=1))
+    _, R2 = torch.linalg.qr(torch.cat([Ya, Yb], dim=1))
+    _, Rb1 = torch.linalg.qr(Zb * gb)
+    _, Rb2 = torch.linalg.qr(Yb)
+    return float(torch.linalg.norm(R1 @ R2.T) / torch.linalg.norm(Rb1 @ Rb2.T))
+
+
+def bench_c3(args, L, WL):
+    """3-D configuration (A 64^3 omega (20,10,5), B 48^3 omega (-10,15,5),
+    r = 8, tau = 1e-8): FP32 inner Krylov work with the relaxed (back-looking
+    mid) tolerances against FP64 inner work at the exact tolerance
+    ||R|| <= 1e-12 ||W|| per solve; X of the FP32 run against the FP64 run."""
+    import torch
+    P = WL.C3
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    HBt = L.convdiff(P.B.dim, P.B.N, tuple(-w for w in P.B.omega))
+    f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+    pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+    fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    ctx = L.Context(0)
+    base = dict(tol=P.tol, b_is_transposed=1)
+    variants = [("fp32_relaxed", L.default_opts(selection="mid", precision="fp32", **base)),
+                ("fp64_relaxed", L.default_opts(selection="mid", **base)),
+                ("fp64_exact", L.default_opts(selection="relative", rho=1e-12, **base))]
+    out, keep = {}, {}
+    for name, o in variants:
+        for _ in range(args.warmup):
+            ctx.solve(HA, HBt, fd, gd, pA, pB, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = ctx.solve(HA, HBt, fd, gd, pA, pB, o)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / max(args.steps, 1)
+        true = ctx.residual(HA, HBt, fd, gd, r, b_is_transposed=True)
+        h = r.history()
+        out[name] = {"s": round(sec, 4), "k": r.k, "rel_res_true": true,
+                     "inner_block_steps": [int(h[:, 6].sum()), int(h[:, 7].sum())]}
+        # one instrumented solve: event-timed projection and product kernels
+        ctx.profile_reset()
+        o.profile = 1
+        ctx.solve(HA, HBt, fd, gd, pA, pB, o)
+        o.profile = 0
+        for cls, key in ((L.PROF_GRAM, "gram"), (L.PROF_SPMM, "spmm")):
+            ms, launches, nbytes = ctx.profile_read(cls)
+            out[name][key + "_avg_us"] = round(ms * 1e3 / max(launches, 1), 2)
+            out[name][key + "_GBs"] = round(nbytes / max(ms * 1e-3, 1e-12) / 1e9, 1)
+        keep[name] = r
+        print(f"[bench c3] {name}: {sec * 1e3:.1f} ms, k={r.k}, true res {true:.2e}", file=sys.stderr,
+              flush=True)
+    out["fp32_relaxed"]["x_rel_err_vs_fp64_exact"] = _lowrank_diff(keep["fp32_relaxed"], keep["fp64_exact"])
+    out["fp64_relaxed"]["x_rel_err_vs_fp64_exact"] = _lowrank_diff(keep["fp64_relaxed"], keep["fp64_exact"])
+    out["speedup_fp32_relaxed_vs_fp64_exact"] = round(out["fp64_exact"]["s"] / out["fp32_relaxed"]["s"], 3)
+    ctx.close()
+    print(json.dumps({"workload": "3-D upwind conv-diff Sylvester, A 64^3 omega (20,10,5), B 48^3 "
+                                  "omega (-10,15,5), r=8, 24 shifts, tau=1e-8",
+                      "n": P.A.n, "m": P.B.n, "steps": args.steps, **out}))
 
 
 def _batch_items(WL, L, count):

@@ -197,7 +197,7 @@ int lradi_spmm_bench(lradi_ctx* ctx, const lradi_csr* A, double shift, const voi
  * row (1, 2, 4 dividing r) on A with r columns in the given precision and
  * returns the fastest in *lanes; the choice is cached in the context per
  * (n, nnz, r, precision) and reused by every later solve.  Products smaller
- * than 1 MiB of X are launch-bound and take the built-in rule untimed.  All
+ * than 8 MiB of X are launch-bound and take the built-in rule untimed.  All
  * tilings give bitwise identical products. */
 int lradi_spmm_tune(lradi_ctx* ctx, const lradi_csr* A, int r, int precision, int* lanes);
 

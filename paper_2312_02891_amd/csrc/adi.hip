@@ -48,8 +48,20 @@ __device__ inline void reduce_rows(const double* partS, int nwg, int off, int P,
   const int groups = kTPB / P;
   const int p = t % P, g = t / P;
   double acc = 0.0;
-  if (g < groups)
-    for (int w = g; w < nwg; w += groups) acc += partS[(size_t)w * kPS + off + p];
+  if (g < groups) {
+    // four independent sums keep four loads in flight per thread
+    const double* X = partS + off + p;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int w = g;
+    for (; w + 3 * groups < nwg; w += 4 * groups) {
+      a0 += X[(size_t)w * kPS];
+      a1 += X[(size_t)(w + groups) * kPS];
+      a2 += X[(size_t)(w + 2 * groups) * kPS];
+      a3 += X[(size_t)(w + 3 * groups) * kPS];
+    }
+    for (; w < nwg; w += groups) a0 += X[(size_t)w * kPS];
+    acc = (a0 + a1) + (a2 + a3);
+  }
   red_lds[t] = acc;
   __syncthreads();
   if (t < P) {

@@ -257,7 +257,9 @@ int spmm_lanes_for(lradi_ctx* c, const DevCSR& A, int r, int prec, int policy, c
     return LRADI_OK;
   }
   *out = rule;
-  if (policy < 0 || r == 1 || (int64_t)A.n * r * tsz < (1 << 20) || !X || !Y) return LRADI_OK;
+  // small products are launch-bound: timing them is noise, and a batch whose
+  // systems share one tiling needs one launch per tick instead of several
+  if (policy < 0 || r == 1 || (int64_t)A.n * r * tsz < (8 << 20) || !X || !Y) return LRADI_OK;
   double best = 0.0;
   LRADI_TRY(spmm_time(c, A, r, prec, rule, X, Y, 3, &best));
   for (int lanes : {1, 2, 4}) {
@@ -381,7 +383,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hd.resize(nsys);
   t.hc.resize(nsys);
   t.hmap.clear();
-  int maxP = 1, rfix = ws[0]->d.r;
+  int maxP = 1, maxB = 1, rfix = ws[0]->d.r;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -389,6 +391,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
     t.hc[s] = ws[s]->c;
     for (int w = 0; w < ws[s]->d.nwg; ++w) t.hmap.push_back(make_int2(s, w));
     maxP = std::max(maxP, ws[s]->d.pstride);
+    maxB = std::max(maxB, ws[s]->d.m + 1);
     if (ws[s]->d.r != rfix) rfix = 0;
   }
   // shifted-product tiles, grouped by lanes per row
@@ -423,6 +426,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.nsys = nsys;
   t.b.rowgrid = (int)t.hmap.size();
   t.b.maxP = maxP;
+  t.b.maxB = maxB;
   t.b.precision = prec;
   t.b.rfix = rfix;
   return LRADI_OK;

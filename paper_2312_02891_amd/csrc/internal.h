@@ -157,6 +157,7 @@ struct Batch {
   const int2* spmap;
   int spoff[3], spcount[3];
   int maxP;            // max over systems of (m+1) r^2
+  int maxB;            // max over systems of m+1 (basis blocks)
   int precision;       // LRADI_FP64 / LRADI_FP32_INNER
   int rfix;            // common r of all systems, or 0 when they differ
   unsigned long long* prof_bytes;  // device counters per kernel class, or null

@@ -85,13 +85,26 @@ __device__ inline void block_sum_store(double (&v)[NV], double* lds, double* out
 
 // Sum the per-workgroup r x r (P values) partial rows partS[w][0..P) over
 // w in a fixed order with a 256-thread workgroup; result in out (shared).
+// Each thread keeps four independent partial sums so that its loads are in
+// flight together.
 __device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, double* out) {
   const int t = threadIdx.x;
   const int groups = kTPB / P;  // P <= 64, so groups >= 4
   const int p = t % P, g = t / P;
   double acc = 0.0;
-  if (g < groups)
-    for (int w = g; w < D.nwg; w += groups) acc += D.partS[(size_t)w * kPS + p];
+  if (g < groups) {
+    const double* X = D.partS + p;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int w = g;
+    for (; w + 3 * groups < D.nwg; w += 4 * groups) {
+      a0 += X[(size_t)w * kPS];
+      a1 += X[(size_t)(w + groups) * kPS];
+      a2 += X[(size_t)(w + 2 * groups) * kPS];
+      a3 += X[(size_t)(w + 3 * groups) * kPS];
+    }
+    for (; w < D.nwg; w += groups) a0 += X[(size_t)w * kPS];
+    acc = (a0 + a1) + (a2 + a3);
+  }
   red_lds[t] = acc;
   __syncthreads();
   if (t < P) {
@@ -250,8 +263,13 @@ struct GramTile {
   static constexpr int G = R >= 5 ? 4 : 8;
 };
 
+// Basis blocks per Gram workgroup: the launch grid's second dimension splits
+// V_0..V_j into groups of this many blocks, so a short basis (small n)
+// still spreads over many workgroups.
+constexpr int kGramBlocks = 8;
+
 template <typename T, int R>
-__device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, double* lds) {
+__device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int bfirst, int nb, double* lds) {
   constexpr int RP = Pad<R>::v;
   constexpr int RPW = 64 / RP;                  // rows per wavefront and row step
   constexpr int K = GramTile<R>::K, G = GramTile<R>::G;
@@ -263,7 +281,7 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int nb, d
   const T* __restrict__ U = static_cast<const T*>(D.U);
   const size_t bs = (size_t)D.n * R;
   double* out = D.part + (size_t)c.w * D.pstride;
-  for (int b0 = 0; b0 < nb; b0 += G) {
+  for (int b0 = bfirst; b0 < nb; b0 += G) {
     const int gc = min(G, nb - b0);
     double acc[G][R];
 #pragma unroll
@@ -333,47 +351,58 @@ __global__ __launch_bounds__(kTPB) void k_gram_vu(const SysDesc* __restrict__ d,
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI) return;
-  const int nb = ctl[c.s].j + 1;
-  if (prof && c.w == 0 && threadIdx.x == 0) {
+  const int bfirst = (int)blockIdx.y * kGramBlocks;
+  const int nb = min(ctl[c.s].j + 1, bfirst + kGramBlocks);
+  if (bfirst >= nb) return;
+  if (prof && c.w == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     // basis blocks V_0..V_j and the candidate block U
-    const unsigned long long bytes = (unsigned long long)(nb + 1) * sizeof(T) * D.n * D.r;
+    const unsigned long long bytes = (unsigned long long)(ctl[c.s].j + 2) * sizeof(T) * D.n * D.r;
     atomicAdd(prof + LRADI_PROF_GRAM, bytes);
   }
   if constexpr (RF > 0) {
-    gram_vu_rows<T, RF>(D, c, nb, lds);
+    gram_vu_rows<T, RF>(D, c, bfirst, nb, lds);
   } else {
-    LRADI_DISPATCH_R(D.r, gram_vu_rows<T, RR>(D, c, nb, lds));
+    LRADI_DISPATCH_R(D.r, gram_vu_rows<T, RR>(D, c, bfirst, nb, lds));
   }
 }
 
 // 3. red = sum_w part[w]; hacc = red (first pass) or hacc += red (second).
-//    A workgroup covers 16 coefficients; 16 thread groups split the sum over
-//    the workgroups of the Gram kernel and are combined in a fixed order.
-constexpr int kRedOut = 16;
+//    One wavefront per coefficient: each lane sums every 64th workgroup's
+//    partial with four independent accumulators, then a fixed-order xor
+//    butterfly combines the lanes.
+constexpr int kRedOut = 4;  // coefficients per workgroup (one per wavefront)
 __global__ __launch_bounds__(kTPB) void k_reduce_vu(const SysDesc* __restrict__ d,
                                                     const SysCtl* __restrict__ ctl, int first) {
-  __shared__ double red[kTPB];
   const int s = blockIdx.x;
   const SysDesc& D = d[s];
   if (ctl[s].phase != PH_ARNOLDI) return;
   const int P = (ctl[s].j + 1) * D.r * D.r;
   const int p0 = blockIdx.y * kRedOut;
   if (p0 >= P) return;
-  const int o = threadIdx.x % kRedOut, g = threadIdx.x / kRedOut;
-  const int p = p0 + o;
+  const int lane = threadIdx.x & 63;
+  const int p = p0 + (threadIdx.x >> 6);
   double acc = 0.0;
-  if (p < P)
-    for (int w = g; w < D.nwg; w += kTPB / kRedOut) acc += D.part[(size_t)w * D.pstride + p];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < kRedOut && p < P) {
-    double sum = 0.0;
-    for (int q = 0; q < kTPB / kRedOut; ++q) sum += red[q * kRedOut + threadIdx.x];
-    D.red[p] = sum;
+  if (p < P) {
+    const double* X = D.part + p;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int w = lane;
+    for (; w + 192 < D.nwg; w += 256) {
+      a0 += X[(size_t)w * D.pstride];
+      a1 += X[(size_t)(w + 64) * D.pstride];
+      a2 += X[(size_t)(w + 128) * D.pstride];
+      a3 += X[(size_t)(w + 192) * D.pstride];
+    }
+    for (; w < D.nwg; w += 64) a0 += X[(size_t)w * D.pstride];
+    acc = (a0 + a1) + (a2 + a3);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0 && p < P) {
+    D.red[p] = acc;
     if (first)
-      D.hacc[p] = sum;
+      D.hacc[p] = acc;
     else
-      D.hacc[p] += sum;
+      D.hacc[p] += acc;
   }
 }
 
@@ -577,6 +606,11 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
 //   side, and take the residual estimate ||G_{j+1}||_F.  At the end of a
 //   cycle solve the triangular system for y.
 
+// threads of the least-squares workgroup: 2r x r <= 128 lanes own one entry
+// of a rotated block each, so the sequential updates synchronise two
+// wavefronts instead of four
+constexpr int kLsqTPB = 128;
+
 // Sum over the 16 lanes of a lane group (xor butterfly).
 __device__ inline double sum16(double x) {
 #pragma unroll
@@ -648,7 +682,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
   }
   __syncthreads();
   if (ph == PH_RESTART) {
-    for (int e = t; e < (m + 1) * RR2; e += kTPB) D.Gv[e] = (e < RR2) ? Sf[e] : 0.0;
+    for (int e = t; e < (m + 1) * RR2; e += kLsqTPB) D.Gv[e] = (e < RR2) ? Sf[e] : 0.0;
     if (t == 0) {
       C.j = 0;
       C.ncols = 0;
@@ -659,7 +693,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
   }
   const int j = C.j;
   const int ldR = m * R;
-  for (int e = t; e < (j + 2) * RR2; e += kTPB) {
+  for (int e = t; e < (j + 2) * RR2; e += kLsqTPB) {
     const int b = e / RR2;
     h[e] = (b <= j) ? D.hacc[e] : Sf[e - b * RR2];
   }
@@ -692,8 +726,8 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
   // Householder QR of rows [j r, j r + 2r)
   if (t < 64) house_wave<R>(h + j * RR2, Qj);
   __syncthreads();
-  for (int e = t; e < 4 * RR2; e += kTPB) D.Qs[(size_t)j * 4 * RR2 + e] = Qj[e];
-  for (int e = t; e < (j + 1) * RR2; e += kTPB) {
+  for (int e = t; e < 4 * RR2; e += kLsqTPB) D.Qs[(size_t)j * 4 * RR2 + e] = Qj[e];
+  for (int e = t; e < (j + 1) * RR2; e += kLsqTPB) {
     const int row = e / R, qq = e - row * R;
     D.Rt[(size_t)(j * R + qq) * ldR + row] = h[e];
   }
@@ -729,7 +763,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
   // back substitution R_t y = G(0 : (j+1) r), block by block
   const int nc = j + 1;
   double* g = h;
-  for (int e = t; e < nc * RR2; e += kTPB) g[e] = D.Gv[e];
+  for (int e = t; e < nc * RR2; e += kLsqTPB) g[e] = D.Gv[e];
   __syncthreads();
   for (int bj = nc - 1; bj >= 0; --bj) {
     if (t < R) {
@@ -743,7 +777,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
       }
     }
     __syncthreads();
-    for (int e = t; e < bj * RR2; e += kTPB) {
+    for (int e = t; e < bj * RR2; e += kLsqTPB) {
       const int row = e / R, qq = e - row * R;
       double v = g[e];
 #pragma unroll
@@ -752,12 +786,12 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
     }
     __syncthreads();
   }
-  for (int e = t; e < nc * RR2; e += kTPB) D.yv[e] = g[e];
+  for (int e = t; e < nc * RR2; e += kLsqTPB) D.yv[e] = g[e];
   if (t == 0) C.phase = PH_CYCLE_END;
 }
 
 template <int RF>
-__global__ __launch_bounds__(kTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
+__global__ __launch_bounds__(kLsqTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
   extern __shared__ double h[];  // maxP doubles: the Hessenberg column block
   __shared__ double Sf[64];
   __shared__ double Qj[16 * 16];
@@ -948,14 +982,15 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
       hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(b.spcount[2]), tb, 0, st, b.d, b.ctl,
                          b.spmap + b.spoff[2], b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[5], st));
+  const dim3 gg(b.rowgrid, (b.maxB + kGramBlocks - 1) / kGramBlocks);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[0], st));
-  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
+  hipLaunchKernelGGL((k_gram_vu<T, RF>), gg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[1], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 1);
   const size_t shP = sizeof(double) * (size_t)b.maxP;
   hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[2], st));
-  hipLaunchKernelGGL((k_gram_vu<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
+  hipLaunchKernelGGL((k_gram_vu<T, RF>), gg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[3], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
   hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
@@ -963,7 +998,7 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
   hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL((k_lsq<RF>), sg, tb, shP, st, b.d, b.ctl);
+  hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(kLsqTPB), shP, st, b.d, b.ctl);
   hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);

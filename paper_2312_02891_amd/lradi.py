@@ -245,10 +245,20 @@ class Result:
         return rows[: nr.value]
 
     def device_factors(self):
-        """Torch views (k, n, r) / (k, m, r) of the library-owned device factors;
-        valid while this Result lives."""
+        """Torch views (k, n, r) / (k, m, r) of the library-owned device factors
+        (no copy); valid while this Result lives."""
         torch = _torch()
-        return self.Zptr, self.Yptr
+
+        class _View:
+            def __init__(self, ptr, shape):
+                self.__cuda_array_interface__ = {"shape": shape, "typestr": "<f8",
+                                                 "data": (ptr, False), "version": 3,
+                                                 "strides": None}
+
+        k = max(self.k, 0)
+        Z = torch.as_tensor(_View(self.Zptr, (k, self.n, self.r)), device="cuda")
+        Y = torch.as_tensor(_View(self.Yptr, (k, self.m, self.r)), device="cuda")
+        return Z, Y
 
     def __del__(self):
         try:

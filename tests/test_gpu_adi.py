@@ -141,6 +141,21 @@ def test_solve_independent_of_spmm_tiling(L, ctx, precision):
         assert np.array_equal(Y, got[0][2])
 
 
+def test_device_factor_views_match_host_copies(L, ctx):
+    """Result.device_factors() views the library's device memory (no copy)
+    and holds the same factors as the host copies."""
+    P = WL.SMALL_2D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, L.default_opts(tol=P.tol))
+    Zd, Yd = res.device_factors()
+    Z, d, Y = res.factors()
+    assert tuple(Zd.shape) == (res.k, res.n, res.r) and tuple(Yd.shape) == (res.k, res.m, res.r)
+    Zh = Zd.cpu().numpy().transpose(1, 0, 2).reshape(res.n, -1)
+    Yh = Yd.cpu().numpy().transpose(1, 0, 2).reshape(res.m, -1)
+    assert np.array_equal(Zh, Z) and np.array_equal(Yh, Y)
+    assert Zd.data_ptr() == res.Zptr
+
+
 def test_small_3d_fp32_inner(L, ctx):
     """FP32 inner Krylov work with FP64 refinement and outer factors."""
     say("adi small 3d fp32")
