@@ -19,6 +19,18 @@ constexpr int kHistCols = LRADI_HIST_COLS;
 constexpr int kPS = 128;        // stride of the small Gram partial rows
 constexpr int kSpmmCap = 2048;  // nonzeros of one SpMM tile staged in LDS
 
+// Device pointers held in descriptor tables are generic (flat) to the
+// compiler; casting them to the global address space lets it issue global
+// loads (no LDS-aperture check, vector-memory counter only).
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* gmem_w(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Shifted-product tiling: `lanes` lanes share one matrix row, each owning
 // r / lanes of its columns, so a tile covers kTPB / lanes rows.  lanes is 1,
 // 2 or 4 and divides r.

@@ -257,9 +257,11 @@ struct Pad {
 
 // Tile shape per block width: K rows per lane per super-row and G basis
 // blocks per pass, so that K*G independent loads are in flight per lane.
-template <int R>
+// (FP32 bases take twice the rows per lane for wide blocks: their loads are
+// half as wide.)
+template <typename T, int R>
 struct GramTile {
-  static constexpr int K = R >= 5 ? 2 : 4;
+  static constexpr int K = R >= 5 ? (sizeof(T) == 4 ? 4 : 2) : 4;
   static constexpr int G = R >= 5 ? 4 : 8;
 };
 
@@ -272,13 +274,13 @@ template <typename T, int R>
 __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int bfirst, int nb, double* lds) {
   constexpr int RP = Pad<R>::v;
   constexpr int RPW = 64 / RP;                  // rows per wavefront and row step
-  constexpr int K = GramTile<R>::K, G = GramTile<R>::G;
+  constexpr int K = GramTile<T, R>::K, G = GramTile<T, R>::G;
   constexpr int SUPER = 4 * RPW * K;            // rows of one super-row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ro = lane / RP, a = lane - ro * RP;
   const bool act = a < R;
-  const T* __restrict__ V = static_cast<const T*>(D.V);
-  const T* __restrict__ U = static_cast<const T*>(D.U);
+  const auto V = gmem(static_cast<const T*>(D.V));
+  const auto U = gmem(static_cast<const T*>(D.U));
   const size_t bs = (size_t)D.n * R;
   double* out = D.part + (size_t)c.w * D.pstride;
   for (int b0 = bfirst; b0 < nb; b0 += G) {
@@ -290,28 +292,38 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int bfirs
       for (int q = 0; q < R; ++q) acc[g][q] = 0.0;
     if (act) {
       for (int base = c.row0; base < c.row1; base += SUPER) {
-        double u[K][R];
+        // every load is unconditional (row and block indices clamped into
+        // range) and masked afterwards, so all K x G + K x R loads of a lane
+        // are in flight together
+        T ut[K][R];
         int rows[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           rows[k] = base + (k * 4 + wave) * RPW + ro;
-          const bool ok = rows[k] < c.row1;
+          const size_t rc = (size_t)min(rows[k], c.row1 - 1);
 #pragma unroll
-          for (int q = 0; q < R; ++q) u[k][q] = ok ? (double)U[(size_t)rows[k] * R + q] : 0.0;
+          for (int q = 0; q < R; ++q) ut[k][q] = U[rc * R + q];
         }
         T x[K][G];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+          const size_t rc = (size_t)min(rows[k], c.row1 - 1);
 #pragma unroll
-          for (int g = 0; g < G; ++g)
-            x[k][g] = (g < gc && rows[k] < c.row1) ? V[(size_t)(b0 + g) * bs + (size_t)rows[k] * R + a]
-                                                    : T(0);
+          for (int g = 0; g < G; ++g) x[k][g] = V[(size_t)(b0 + min(g, gc - 1)) * bs + rc * R + a];
+        }
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+          const bool okr = rows[k] < c.row1;
+          double u[R];
 #pragma unroll
-          for (int g = 0; g < G; ++g)
+          for (int q = 0; q < R; ++q) u[q] = okr ? (double)ut[k][q] : 0.0;
 #pragma unroll
-            for (int q = 0; q < R; ++q) acc[g][q] += (double)x[k][g] * u[k][q];
+          for (int g = 0; g < G; ++g) {
+            const double xv = (g < gc) ? (double)x[k][g] : 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[g][q] += xv * u[q];
+          }
+        }
       }
     }
     // butterfly over the row offset (lane bits >= log2 RP)
@@ -412,12 +424,14 @@ __global__ __launch_bounds__(kTPB) void k_reduce_vu(const SysDesc* __restrict__ 
 template <typename T, int R, bool GRAM>
 __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bool do_update,
                                    double* hl, double* lds) {
+  // the coefficients, rounded once to the basis precision
+  T* ht = reinterpret_cast<T*>(hl);
   if (do_update) {
-    for (int e = threadIdx.x; e < nb * R * R; e += kTPB) hl[e] = D.red[e];
+    for (int e = threadIdx.x; e < nb * R * R; e += kTPB) ht[e] = (T)D.red[e];
     __syncthreads();
   }
-  const T* __restrict__ V = static_cast<const T*>(D.V);
-  T* __restrict__ U = static_cast<T*>(D.U);
+  const auto V = gmem(static_cast<const T*>(D.V));
+  const auto U = gmem_w(static_cast<T*>(D.U));
   const size_t bs = (size_t)D.n * R;
   double g2[GRAM ? R * R : 1];
   if constexpr (GRAM) {
@@ -442,22 +456,22 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
           for (int a = 0; a < R; ++a) v[bb][a] = V[(size_t)(b + bb) * bs + (size_t)i * R + a];
 #pragma unroll
         for (int bb = 0; bb < UB; ++bb) {
-          const double* h = hl + (b + bb) * R * R;
+          const T* h = ht + (b + bb) * R * R;
 #pragma unroll
           for (int a = 0; a < R; ++a)
 #pragma unroll
-            for (int q = 0; q < R; ++q) acc[q] += v[bb][a] * (T)h[a * R + q];
+            for (int q = 0; q < R; ++q) acc[q] += v[bb][a] * h[a * R + q];
         }
       }
       for (; b < nb; ++b) {
         T v[R];
 #pragma unroll
         for (int a = 0; a < R; ++a) v[a] = V[(size_t)b * bs + (size_t)i * R + a];
-        const double* h = hl + b * R * R;
+        const T* h = ht + b * R * R;
 #pragma unroll
         for (int a = 0; a < R; ++a)
 #pragma unroll
-          for (int q = 0; q < R; ++q) acc[q] += v[a] * (T)h[a * R + q];
+          for (int q = 0; q < R; ++q) acc[q] += v[a] * h[a * R + q];
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -542,7 +556,8 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
   double sl[R * R];
 #pragma unroll
   for (int e = 0; e < R * R; ++e) sl[e] = Si[e];
-  T* __restrict__ U = static_cast<T*>(D.U);
+  const auto U = gmem(static_cast<const T*>(D.U));
+  const auto dg = gmem_w(dst);
   double g2[GRAM ? R * R : 1];
   if constexpr (GRAM) {
 #pragma unroll
@@ -563,7 +578,7 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       ot[q] = (T)o[q];
-      dst[(size_t)i * R + q] = ot[q];
+      dg[(size_t)i * R + q] = ot[q];
     }
     if constexpr (GRAM) {
 #pragma unroll
@@ -809,7 +824,7 @@ __global__ __launch_bounds__(kLsqTPB) void k_lsq(const SysDesc* __restrict__ d, 
 template <typename T, int R>
 __device__ inline void zupdate_rows(const SysDesc& D, const RowCtx& c, double* Z, int nb,
                                     const double* yl) {
-  const T* __restrict__ V = static_cast<const T*>(D.V);
+  const auto V = gmem(static_cast<const T*>(D.V));
   const size_t bs = (size_t)D.n * R;
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     double acc[R];
