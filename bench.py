@@ -128,7 +128,7 @@ def main():
         per_launch = nbytes / max(launches, 1)
         achieved = per_launch / (avg_us * 1e-6) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_gram_vu<double,4> (block projection V^T U)",
                 "bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
                 "launches": launches}
@@ -182,6 +182,25 @@ def main():
         "compare": extra,
     }
     print(json.dumps(line))
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gram_vu_config2_fp64_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the projection kernel on this workload from the
+    committed FETCH_SIZE / WRITE_SIZE counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    from paper_2312_02891_amd.pmc import source_digest
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        files = [os.path.join(ROOT, p) for p in t["source_files"]]
+        if source_digest(files) != t["source_sha256"]:
+            return None
+        return t["traffic_bytes_per_dispatch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(P, f, g, pA, pB, res):
