@@ -104,7 +104,8 @@ def main():
 
     if not args.no_compare:
         for name, kw in [("tight_fixed", dict(selection="fixed")),
-                         ("fp32_inner_relaxed", dict(selection="mid", precision="fp32"))]:
+                         ("fp32_inner_relaxed", dict(selection="mid", precision="fp32")),
+                         ("relaxed_graph_replay", dict(selection="mid", use_graph=1))]:
             o = L.default_opts(**base, **kw)
             solve(o)
             torch.cuda.synchronize()

@@ -115,8 +115,11 @@ typedef struct {
                         * factor norms drift apart; iterates are unchanged)    */
   int32_t b_is_transposed; /* 1: the B argument already holds B^T             */
   int32_t lookahead;   /* host scheduling depth (0 = synchronous), >= 0       */
-  int32_t use_graph;   /* 1: replay the inner-iteration launch sequence from a
-                          captured hipGraph                                    */
+  int32_t use_graph;   /* 1: capture one tick (inner step kernels, outer step
+                          end, unfinished count) into a hipGraph per
+                          look-ahead slot and replay it; captured again when
+                          the set of systems changes.  Ignored with
+                          profile = 1 or on the null stream               */
   int32_t profile;     /* 1: time the projection (Gram) and shifted-product
                           launches with HIP events and count their
                           algorithmic bytes (see lradi_profile_read)         */

@@ -458,8 +458,48 @@ int probe_account(lradi_ctx* ctx, const TickProbe& p) {
 // back) asks to return.  The host reads the unfinished count of tick t - L
 // only after issuing tick t, so the device always has queued work; the
 // extra ticks are no-ops.  Returns with the stream drained.
+// Graphs of one tick each (tick, `after`, summary into ring slot s), captured
+// on the context's stream; destroyed with the object.
+struct TickGraphs {
+  std::vector<hipGraphExec_t> exec;
+  ~TickGraphs() {
+    for (auto e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+  }
+  // false: capture is not possible on this stream (launch directly instead)
+  int build(lradi_ctx* ctx, const Batch& b, int slots, const std::function<int()>& after, bool* ok) {
+    *ok = false;
+    hipStream_t st = ctx->stream;
+    if (!st) return LRADI_OK;  // the null stream cannot be captured
+    for (int s = 0; s < slots; ++s) {
+      LRADI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      int rc = launch_tick(st, b, nullptr);
+      if (rc == LRADI_OK && after) rc = after();
+      if (rc == LRADI_OK) rc = launch_summary(st, b, ctx->ring.d + s);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (rc != LRADI_OK || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc != LRADI_OK ? rc : LRADI_OK;  // capture unsupported: ok stays false
+      }
+      hipGraphExec_t e = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        return LRADI_OK;
+      }
+      exec.push_back(e);
+    }
+    *ok = true;
+    return LRADI_OK;
+  }
+};
+
 int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, bool profile,
-              const std::function<int()>& after, const std::function<bool()>& stop) {
+              const std::function<int()>& after, const std::function<bool()>& stop,
+              bool use_graph = false) {
   const int L = std::max(0, std::min(lookahead, 8));
   LRADI_TRY(ctx->ring.init(L + 1));
   while ((int)ctx->events.size() < L + 1) {
@@ -475,12 +515,20 @@ int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, boo
     }
   }
   hipStream_t st = ctx->stream;
+  // optional replay of captured ticks (not with per-launch timing events)
+  TickGraphs graphs;
+  bool graphed = false;
+  if (use_graph && !profile) LRADI_TRY(graphs.build(ctx, b, L + 1, after, &graphed));
   long t = 0;
   for (;; ++t) {
     const int slot = (int)(t % (L + 1));
-    LRADI_TRY(launch_tick(st, b, profile ? &ctx->probes[slot] : nullptr));
-    if (after) LRADI_TRY(after());
-    LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
+    if (graphed) {
+      LRADI_HIP(hipGraphLaunch(graphs.exec[slot], st));
+    } else {
+      LRADI_TRY(launch_tick(st, b, profile ? &ctx->probes[slot] : nullptr));
+      if (after) LRADI_TRY(after());
+      LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
+    }
     LRADI_HIP(hipEventRecord(ctx->events[slot], st));
     if (t >= L) {
       const int rs = (int)((t - L) % (L + 1));
@@ -846,7 +894,7 @@ struct Engine {
       return k >= retire;
     };
     const long max_ticks = (3L * std::max(o.max_inner, 1) + 16) * (long)(o.kmax + 1);
-    const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, after, check);
+    const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, after, check, o.use_graph != 0);
     if (rc != LRADI_OK) {
       (void)hipStreamSynchronize(c->stream);
       return rc;
@@ -1028,7 +1076,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
   LRADI_TRY(upload_table(c, ws, tab));
   LRADI_TRY(prof_counters(c, o.profile != 0, &tab.b.prof_bytes));
   const long max_ticks = 3L * o.max_inner + 16;
-  const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, nullptr, nullptr);
+  const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, nullptr, nullptr, o.use_graph != 0);
   if (rc != LRADI_OK) {
     (void)hipStreamSynchronize(c->stream);
     return rc;

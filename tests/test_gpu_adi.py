@@ -156,6 +156,37 @@ def test_device_factor_views_match_host_copies(L, ctx):
     assert Zd.data_ptr() == res.Zptr
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replay_equals_direct_launches(L, ctx, precision):
+    """Replaying captured ticks (thousands of replays, with the host's own
+    read-backs in between) gives the same bits as launching them directly,
+    for one solve and for a batch whose problems finish at different steps."""
+    say("adi graph", precision)
+    P = WL.SMALL_3D
+    HA, HB, A, B, f, g, pA, pB = setup(P, L)
+    runs = []
+    for graph in (0, 1):
+        o = L.default_opts(precision=precision, tol=P.tol, use_graph=graph)
+        res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+        assert res.status == L.OK
+        runs.append(res.factors())
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    items = []
+    for i, tol in enumerate((1e-6, 1e-8, 1e-10)):
+        Q = WL.Problem(WL.SMALL_2D.A, WL.SMALL_3D.B, r=2, nshifts=12, seed=30 + i, tol=tol)
+        HA2, HB2, _, _, f2, g2, pA2, pB2 = setup(Q, L)
+        items.append((HA2, HB2, to_dev(f2), to_dev(g2), pA2, pB2, tol))
+    outs = []
+    for graph in (0, 1):
+        o = L.default_opts(precision=precision, use_graph=graph)
+        res, st = ctx.batch_solve(items, o)
+        outs.append([r.factors() for r in res])
+    for ra, rb in zip(outs[0], outs[1]):
+        for a, b in zip(ra, rb):
+            assert np.array_equal(a, b)
+
+
 def test_small_3d_fp32_inner(L, ctx):
     """FP32 inner Krylov work with FP64 refinement and outer factors."""
     say("adi small 3d fp32")
