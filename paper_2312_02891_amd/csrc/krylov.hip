@@ -262,7 +262,7 @@ struct Pad {
 template <typename T, int R>
 struct GramTile {
   static constexpr int K = R >= 5 ? (sizeof(T) == 4 ? 4 : 2) : 4;
-  static constexpr int G = R >= 5 ? 4 : 8;
+  static constexpr int G = R >= 5 ? 4 : (sizeof(T) == 4 ? 8 : 4);
 };
 
 // Basis blocks per Gram workgroup: the launch grid's second dimension splits
@@ -626,21 +626,21 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
 // wavefronts instead of four
 constexpr int kLsqTPB = 128;
 
-// Sum over the 16 lanes of a lane group (xor butterfly).
-__device__ inline double sum16(double x) {
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off, 16);
-  return x;
-}
-
 // Householder QR of the 2R x R block hb (LDS, row-major, overwritten with
 // [R_jj; 0]); Q (LDS, 2R x 2R row-major) receives the orthogonal factor.
-// Run by wavefront 0; lane i < 2R owns row i of the block and of Q.
+// Run by wavefront 0; lane i < 2R owns row i of the block and of Q.  The
+// column sums go through LDS (hw, 2R (R + 2) doubles): every lane writes its
+// terms, then each lane adds all 2R of them in the same order, so all lanes
+// hold the same sums.  One wavefront executes its LDS operations in order;
+// wave_barrier keeps the compiler from moving them across each other.
 template <int R>
-__device__ inline void house_wave(double* hb, double* Q) {
+__device__ inline void house_wave(double* hb, double* Q, double* hw) {
   constexpr int M2 = 2 * R;
   const int lane = threadIdx.x;
   const bool own = lane < M2;
+  double* xs = hw;            // x (2R)
+  double* vs = hw + M2;       // v (2R)
+  double* pr = hw + 2 * M2;   // v * column jc (R x 2R)
   double mr[R], qr[M2];
 #pragma unroll
   for (int c = 0; c < R; ++c) mr[c] = own ? hb[lane * R + c] : 0.0;
@@ -649,24 +649,38 @@ __device__ inline void house_wave(double* hb, double* Q) {
 #pragma unroll
   for (int c = 0; c < R; ++c) {
     const double x = (own && lane >= c) ? mr[c] : 0.0;
-    const double nx2 = sum16(x * x);
+    if (own) xs[lane] = x;
+    __builtin_amdgcn_wave_barrier();
+    double nx2 = 0.0;
+#pragma unroll
+    for (int k = c; k < M2; ++k) nx2 += xs[k] * xs[k];
+    const double x0 = xs[c];
+    __builtin_amdgcn_wave_barrier();
     if (nx2 == 0.0) continue;
-    const double x0 = __shfl(x, c, 64);
     const double alpha = (x0 >= 0.0) ? -sqrt(nx2) : sqrt(nx2);
     const double v = x - ((lane == c) ? alpha : 0.0);
-    const double vv = sum16(v * v);
-    if (vv == 0.0) continue;
+    // ||v||^2 = ||x||^2 - 2 alpha x0 + alpha^2, all terms >= 0
+    const double vv = (nx2 - 2.0 * alpha * x0) + alpha * alpha;
     const double beta = 2.0 / vv;
+    if (own) {
+      vs[lane] = v;
+#pragma unroll
+      for (int jc = c + 1; jc < R; ++jc) pr[jc * M2 + lane] = v * mr[jc];
+    }
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int jc = c + 1; jc < R; ++jc) {
-      const double dd = sum16(v * mr[jc]);
+      double dd = 0.0;
+#pragma unroll
+      for (int k = 0; k < M2; ++k) dd += pr[jc * M2 + k];
       mr[jc] -= beta * dd * v;
     }
     if (own && lane == c) mr[c] = alpha;
     else if (own && lane > c) mr[c] = 0.0;
     double vk[M2];
 #pragma unroll
-    for (int k = 0; k < M2; ++k) vk[k] = __shfl(v, k, 64);
+    for (int k = 0; k < M2; ++k) vk[k] = vs[k];
+    __builtin_amdgcn_wave_barrier();
     double dq = 0.0;
 #pragma unroll
     for (int k = 0; k < M2; ++k) dq += qr[k] * vk[k];
@@ -683,17 +697,43 @@ __device__ inline void house_wave(double* hb, double* Q) {
 
 template <int R>
 __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, double* Sf,
-                                double* Qj, int* done_s) {
+                                double* Qj, double* hw, int* done_s) {
   constexpr int RR2 = R * R, twoR = 2 * R;
   const int m = D.m, t = threadIdx.x;
-  const double* S1 = D.sm + SM_S1;
-  const double* S2 = D.sm + SM_S2;
+  const int j = C.j;
+  const int ldR = m * R;
+  // issue every independent load first: S = S2 S1, the Hessenberg column
+  // block, the right-hand-side rows this step rotates, the first factor
+  const bool act = t < twoR * R;
+  const int a = act ? t / R : 0, q = act ? t - (t / R) * R : 0;
+  double s1c[R], s2r[R];
   if (t < RR2) {
-    const int a = t / R, q = t - a * R;
+    const int sa = t / R, sq = t - sa * R;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      s2r[k] = D.sm[SM_S2 + sa * R + k];
+      s1c[k] = D.sm[SM_S1 + k * R + sq];
+    }
+  }
+  double gcol[twoR];
+  double qa[twoR], qn[twoR];
+  if (ph == PH_ARNOLDI) {
+    for (int e = t; e < (j + 1) * RR2; e += kLsqTPB) h[e] = D.hacc[e];
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < twoR; ++k) gcol[k] = D.Gv[(j * R + k) * R + q];
+      if (j > 0) {
+#pragma unroll
+        for (int k = 0; k < twoR; ++k) qa[k] = D.Qs[k * twoR + a];
+      }
+    }
+  }
+  if (t < RR2) {
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) v += S2[a * R + k] * S1[k * R + q];
+    for (int k = 0; k < R; ++k) v += s2r[k] * s1c[k];
     Sf[t] = v;
+    if (ph == PH_ARNOLDI) h[(j + 1) * RR2 + t] = v;
   }
   __syncthreads();
   if (ph == PH_RESTART) {
@@ -706,22 +746,8 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
     }
     return;
   }
-  const int j = C.j;
-  const int ldR = m * R;
-  for (int e = t; e < (j + 2) * RR2; e += kLsqTPB) {
-    const int b = e / RR2;
-    h[e] = (b <= j) ? D.hacc[e] : Sf[e - b * RR2];
-  }
   // apply Q_b^T to rows [b r, b r + 2r); the column of Q_b a thread needs is
   // prefetched into registers one step ahead
-  const bool act = t < twoR * R;
-  const int a = act ? t / R : 0, q = act ? t - (t / R) * R : 0;
-  double qa[twoR], qn[twoR];
-  if (act && j > 0) {
-#pragma unroll
-    for (int k = 0; k < twoR; ++k) qa[k] = D.Qs[k * twoR + a];
-  }
-  __syncthreads();
   for (int b = 0; b < j; ++b) {
     if (act && b + 1 < j) {
 #pragma unroll
@@ -739,29 +765,29 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
     for (int k = 0; k < twoR; ++k) qa[k] = qn[k];
   }
   // Householder QR of rows [j r, j r + 2r)
-  if (t < 64) house_wave<R>(h + j * RR2, Qj);
+  if (t < 64) house_wave<R>(h + j * RR2, Qj, hw);
   __syncthreads();
   for (int e = t; e < 4 * RR2; e += kLsqTPB) D.Qs[(size_t)j * 4 * RR2 + e] = Qj[e];
   for (int e = t; e < (j + 1) * RR2; e += kLsqTPB) {
     const int row = e / R, qq = e - row * R;
     D.Rt[(size_t)(j * R + qq) * ldR + row] = h[e];
   }
-  // rotate the right-hand side rows [j r, j r + 2r)
-  {
+  // rotate the right-hand side rows [j r, j r + 2r) (prefetched into gcol);
+  // the new last block row also goes to LDS (Sf is free again) for the
+  // residual estimate
+  if (act) {
     double nv = 0.0;
-    if (act) {
 #pragma unroll
-      for (int k = 0; k < twoR; ++k) nv += Qj[k * twoR + a] * D.Gv[(j * R + k) * R + q];
-    }
-    __syncthreads();
-    if (act) D.Gv[(j * R + a) * R + q] = nv;
+    for (int k = 0; k < twoR; ++k) nv += Qj[k * twoR + a] * gcol[k];
+    D.Gv[(j * R + a) * R + q] = nv;
+    if (a >= R) Sf[(a - R) * R + q] = nv;
   }
   __syncthreads();
   if (t == 0) {
     double e2 = 0.0;
 #pragma unroll
     for (int e = 0; e < RR2; ++e) {
-      const double g = D.Gv[((j + 1) * R) * R + e];
+      const double g = Sf[e];
       e2 += g * g;
     }
     const double est = sqrt(e2);
@@ -810,13 +836,14 @@ __global__ __launch_bounds__(kLsqTPB) void k_lsq(const SysDesc* __restrict__ d, 
   extern __shared__ double h[];  // maxP doubles: the Hessenberg column block
   __shared__ double Sf[64];
   __shared__ double Qj[16 * 16];
+  __shared__ double hw[2 * kMaxR * (kMaxR + 2)];
   __shared__ int done_s;
   const int s = blockIdx.x;
   const SysDesc& D = d[s];
   SysCtl& C = ctl[s];
   const int ph = C.phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
-  LRADI_RSEL(RF, D.r, lsq_body<RR>(D, C, ph, h, Sf, Qj, &done_s));
+  LRADI_RSEL(RF, D.r, lsq_body<RR>(D, C, ph, h, Sf, Qj, hw, &done_s));
 }
 
 // ---------------------------------------------------------------------------
