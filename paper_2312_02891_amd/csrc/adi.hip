@@ -27,14 +27,16 @@ namespace {
 
 template <int NV>
 __device__ inline void bsum(double (&v)[NV], double* lds, double* out) {
+  constexpr int P2 = pow2c(NV);
+  using RS = WaveRS<P2, 1>;
+  static_assert(RS::NOUT == 1, "at most 64 values");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double w[P2];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) lds[wave * NV + k] = x;
-  }
+  for (int k = 0; k < P2; ++k) w[k] = k < NV ? v[k] : 0.0;
+  wave_reduce_scatter<P2, 1>(w, lane);
+  const int idx = wave_rs_base<P2, 1>(lane);
+  if ((lane & RS::DUP) == 0 && idx < NV) lds[wave * NV + idx] = w[0];
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += kTPB)
     out[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];

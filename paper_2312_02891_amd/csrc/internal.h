@@ -31,6 +31,64 @@ __device__ inline __attribute__((address_space(1))) T* gmem_w(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
+// ---------------------------------------------------------------------------
+// Reduce-scatter of per-lane values across a wavefront.  Every lane holds
+// NV (a power of two) values; the sum runs over the lanes that differ only
+// in lane-index bits LO, 2 LO, ..., 32.  At each xor step a lane keeps one
+// half of its values and adds the partner's copy of that half, so the step
+// costs NV/2 shuffles instead of NV; once a lane holds one value the
+// remaining steps are plain butterflies.  Afterwards v[0..NV >> H) (H =
+// halving steps) hold complete sums of value indices wave_rs_base() + i.
+// The order of every addition is fixed by the lane pattern alone.
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+constexpr int pow2c(int x) { return x <= 1 ? 1 : 2 * pow2c((x + 1) / 2); }
+
+template <int CNT, int OFF, int LO, int NV>
+__device__ inline void wave_rs_step(double (&v)[NV], int lane) {
+  if constexpr (OFF >= LO) {
+    if constexpr (CNT > 1) {
+      constexpr int h = CNT / 2;
+      const bool up = (lane & OFF) != 0;
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const double send = up ? v[i] : v[i + h];
+        const double keep = up ? v[i + h] : v[i];
+        v[i] = keep + __shfl_xor(send, OFF, 64);
+      }
+      wave_rs_step<h, OFF / 2, LO, NV>(v, lane);
+    } else {
+      v[0] += __shfl_xor(v[0], OFF, 64);
+      wave_rs_step<1, OFF / 2, LO, NV>(v, lane);
+    }
+  }
+}
+
+template <int NV, int LO>
+__device__ inline void wave_reduce_scatter(double (&v)[NV], int lane) {
+  wave_rs_step<NV, 32, LO, NV>(v, lane);
+}
+
+template <int NV, int LO>
+struct WaveRS {
+  static constexpr int S = ilog2c(64 / LO);               // xor steps
+  static constexpr int H = S < ilog2c(NV) ? S : ilog2c(NV);  // halving steps
+  static constexpr int NOUT = NV >> H;                    // sums left per lane
+  static constexpr int DUP = (64 >> H) - LO;              // lane bits of equal copies
+};
+
+template <int NV, int LO>
+__device__ inline int wave_rs_base(int lane) {
+  int base = 0, cnt = NV;
+#pragma unroll
+  for (int off = 32; off >= LO; off >>= 1) {
+    if (cnt > 1) {
+      cnt >>= 1;
+      if (lane & off) base += cnt;
+    }
+  }
+  return base;
+}
+
 // Shifted-product tiling: `lanes` lanes share one matrix row, each owning
 // r / lanes of its columns, so a tile covers kTPB / lanes rows.  lanes is 1,
 // 2 or 4 and divides r.

@@ -69,14 +69,16 @@ __device__ inline RowCtx row_ctx(const SysDesc* d, const int2* rowmap) {
 // order and store the totals to out[0..NV).  lds needs 4*NV doubles.
 template <int NV>
 __device__ inline void block_sum_store(double (&v)[NV], double* lds, double* out) {
+  constexpr int P2 = pow2c(NV);
+  using RS = WaveRS<P2, 1>;
+  static_assert(RS::NOUT == 1, "at most 64 values");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double w[P2];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) lds[wave * NV + k] = x;
-  }
+  for (int k = 0; k < P2; ++k) w[k] = k < NV ? v[k] : 0.0;
+  wave_reduce_scatter<P2, 1>(w, lane);
+  const int idx = wave_rs_base<P2, 1>(lane);
+  if ((lane & RS::DUP) == 0 && idx < NV) lds[wave * NV + idx] = w[0];
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += kTPB)
     out[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
@@ -326,21 +328,21 @@ __device__ inline void gram_vu_rows(const SysDesc& D, const RowCtx& c, int bfirs
         }
       }
     }
-    // butterfly over the row offset (lane bits >= log2 RP)
+    // reduce-scatter over the row offset (lane bits >= log2 RP): afterwards
+    // the lanes of column a hold the sums of (g, q) = index / R
+    constexpr int NV = G * R, P2 = pow2c(NV);
+    using RS = WaveRS<P2, RP>;
+    double w[P2];
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int k = 0; k < P2; ++k) w[k] = k < NV ? acc[k / R][k % R] : 0.0;
+    wave_reduce_scatter<P2, RP>(w, lane);
+    if (act && (lane & RS::DUP) == 0) {
+      const int base = wave_rs_base<P2, RP>(lane);
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double v = acc[g][q];
-#pragma unroll
-        for (int off = RP; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        acc[g][q] = v;
+      for (int i = 0; i < RS::NOUT; ++i) {
+        const int idx = base + i;
+        if (idx < NV) lds[((wave * G + idx / R) * R + a) * R + idx % R] = w[i];
       }
-    if (lane < R) {
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int q = 0; q < R; ++q) lds[((wave * G + g) * R + lane) * R + q] = acc[g][q];
     }
     __syncthreads();
     const int nout = gc * R * R;
