@@ -623,10 +623,13 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
 //   side, and take the residual estimate ||G_{j+1}||_F.  At the end of a
 //   cycle solve the triangular system for y.
 
-// threads of the least-squares workgroup: 2r x r <= 128 lanes own one entry
-// of a rotated block each, so the sequential updates synchronise two
-// wavefronts instead of four
-constexpr int kLsqTPB = 128;
+// threads of the least-squares workgroup: one lane per entry of a rotated
+// 2r x r block; for r <= 5 that is a single wavefront, whose barriers are
+// cheap, wider blocks (and batches of mixed r) take two
+template <int RF>
+struct LsqTPB {
+  static constexpr int v = (RF > 0 && RF <= 5) ? 64 : 128;
+};
 
 // Householder QR of the 2R x R block hb (LDS, row-major, overwritten with
 // [R_jj; 0]); Q (LDS, 2R x 2R row-major) receives the orthogonal factor.
@@ -697,17 +700,27 @@ __device__ inline void house_wave(double* hb, double* Q, double* hw) {
   }
 }
 
-template <int R>
+template <int R, int kLsqTPB>
 __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, double* Sf,
                                 double* Qj, double* hw, int* done_s) {
   constexpr int RR2 = R * R, twoR = 2 * R;
+  // entries (a, q) of a 2r x r block per lane
+  constexpr int NE = (twoR * R + kLsqTPB - 1) / kLsqTPB;
+  static_assert(NE == 1, "one entry per lane");
   const int m = D.m, t = threadIdx.x;
   const int j = C.j;
   const int ldR = m * R;
+  int ea[NE], eq[NE];
+  bool ev[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = t + u * kLsqTPB;
+    ev[u] = e < twoR * R;
+    ea[u] = ev[u] ? e / R : 0;
+    eq[u] = ev[u] ? e - (e / R) * R : 0;
+  }
   // issue every independent load first: S = S2 S1, the Hessenberg column
-  // block, the right-hand-side rows this step rotates, the first factor
-  const bool act = t < twoR * R;
-  const int a = act ? t / R : 0, q = act ? t - (t / R) * R : 0;
+  // block, the first orthogonal factor
   double s1c[R], s2r[R];
   if (t < RR2) {
     const int sa = t / R, sq = t - sa * R;
@@ -717,17 +730,14 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
       s1c[k] = D.sm[SM_S1 + k * R + sq];
     }
   }
-  double gcol[twoR];
-  double qa[twoR], qn[twoR];
+  double qa[NE][twoR], qn[NE][twoR];
   if (ph == PH_ARNOLDI) {
     for (int e = t; e < (j + 1) * RR2; e += kLsqTPB) h[e] = D.hacc[e];
-    if (act) {
+    if (j > 0) {
 #pragma unroll
-      for (int k = 0; k < twoR; ++k) gcol[k] = D.Gv[(j * R + k) * R + q];
-      if (j > 0) {
+      for (int u = 0; u < NE; ++u)
 #pragma unroll
-        for (int k = 0; k < twoR; ++k) qa[k] = D.Qs[k * twoR + a];
-      }
+        for (int k = 0; k < twoR; ++k) qa[u][k] = ev[u] ? D.Qs[k * twoR + ea[u]] : 0.0;
     }
   }
   if (t < RR2) {
@@ -748,24 +758,40 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
     }
     return;
   }
-  // apply Q_b^T to rows [b r, b r + 2r); the column of Q_b a thread needs is
-  // prefetched into registers one step ahead
+  // apply Q_b^T to rows [b r, b r + 2r); the columns of Q_b a lane needs are
+  // prefetched into registers one step ahead.  The workgroup is one
+  // wavefront, so its barriers are cheap.
   for (int b = 0; b < j; ++b) {
-    if (act && b + 1 < j) {
+    if (b + 1 < j) {
 #pragma unroll
-      for (int k = 0; k < twoR; ++k) qn[k] = D.Qs[(size_t)(b + 1) * 4 * RR2 + k * twoR + a];
+      for (int u = 0; u < NE; ++u)
+#pragma unroll
+        for (int k = 0; k < twoR; ++k)
+          qn[u][k] = ev[u] ? D.Qs[(size_t)(b + 1) * 4 * RR2 + k * twoR + ea[u]] : 0.0;
     }
-    double nv = 0.0;
-    if (act) {
+    double nv[NE];
 #pragma unroll
-      for (int k = 0; k < twoR; ++k) nv += qa[k] * h[(b * R + k) * R + q];
+    for (int u = 0; u < NE; ++u) {
+      nv[u] = 0.0;
+#pragma unroll
+      for (int k = 0; k < twoR; ++k) nv[u] += qa[u][k] * h[(b * R + k) * R + eq[u]];
     }
     __syncthreads();
-    if (act) h[(b * R + a) * R + q] = nv;
+#pragma unroll
+    for (int u = 0; u < NE; ++u)
+      if (ev[u]) h[(b * R + ea[u]) * R + eq[u]] = nv[u];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < twoR; ++k) qa[k] = qn[k];
+    for (int u = 0; u < NE; ++u)
+#pragma unroll
+      for (int k = 0; k < twoR; ++k) qa[u][k] = qn[u][k];
   }
+  // the right-hand-side rows this step rotates (in flight during the QR)
+  double gcol[NE][twoR];
+#pragma unroll
+  for (int u = 0; u < NE; ++u)
+#pragma unroll
+    for (int k = 0; k < twoR; ++k) gcol[u][k] = ev[u] ? D.Gv[(j * R + k) * R + eq[u]] : 0.0;
   // Householder QR of rows [j r, j r + 2r)
   if (t < 64) house_wave<R>(h + j * RR2, Qj, hw);
   __syncthreads();
@@ -777,12 +803,14 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
   // rotate the right-hand side rows [j r, j r + 2r) (prefetched into gcol);
   // the new last block row also goes to LDS (Sf is free again) for the
   // residual estimate
-  if (act) {
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    if (!ev[u]) continue;
     double nv = 0.0;
 #pragma unroll
-    for (int k = 0; k < twoR; ++k) nv += Qj[k * twoR + a] * gcol[k];
-    D.Gv[(j * R + a) * R + q] = nv;
-    if (a >= R) Sf[(a - R) * R + q] = nv;
+    for (int k = 0; k < twoR; ++k) nv += Qj[k * twoR + ea[u]] * gcol[u][k];
+    D.Gv[(j * R + ea[u]) * R + eq[u]] = nv;
+    if (ea[u] >= R) Sf[(ea[u] - R) * R + eq[u]] = nv;
   }
   __syncthreads();
   if (t == 0) {
@@ -834,7 +862,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
 }
 
 template <int RF>
-__global__ __launch_bounds__(kLsqTPB) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
+__global__ __launch_bounds__(LsqTPB<RF>::v) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
   extern __shared__ double h[];  // maxP doubles: the Hessenberg column block
   __shared__ double Sf[64];
   __shared__ double Qj[16 * 16];
@@ -845,7 +873,7 @@ __global__ __launch_bounds__(kLsqTPB) void k_lsq(const SysDesc* __restrict__ d, 
   SysCtl& C = ctl[s];
   const int ph = C.phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
-  LRADI_RSEL(RF, D.r, lsq_body<RR>(D, C, ph, h, Sf, Qj, hw, &done_s));
+  LRADI_RSEL(RF, D.r, lsq_body<RR, LsqTPB<RF>::v>(D, C, ph, h, Sf, Qj, hw, &done_s));
 }
 
 // ---------------------------------------------------------------------------
@@ -1042,7 +1070,7 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
   hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(kLsqTPB), shP, st, b.d, b.ctl);
+  hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(LsqTPB<RF>::v), shP, st, b.d, b.ctl);
   hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);
