@@ -467,7 +467,8 @@ struct TickGraphs {
       if (e) (void)hipGraphExecDestroy(e);
   }
   // false: capture is not possible on this stream (launch directly instead)
-  int build(lradi_ctx* ctx, const Batch& b, int slots, const std::function<int()>& after, bool* ok) {
+  int build(lradi_ctx* ctx, const Batch& b, int slots, const std::function<int()>& after, bool summary,
+            bool* ok) {
     *ok = false;
     hipStream_t st = ctx->stream;
     if (!st) return LRADI_OK;  // the null stream cannot be captured
@@ -475,7 +476,7 @@ struct TickGraphs {
       LRADI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       int rc = launch_tick(st, b, nullptr);
       if (rc == LRADI_OK && after) rc = after();
-      if (rc == LRADI_OK) rc = launch_summary(st, b, ctx->ring.d + s);
+      if (rc == LRADI_OK && summary) rc = launch_summary(st, b, ctx->ring.d + s);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &g);
       if (rc != LRADI_OK || ec != hipSuccess || !g) {
@@ -497,9 +498,11 @@ struct TickGraphs {
   }
 };
 
+// summary = false: no count of unfinished systems is produced; `stop` alone
+// ends the loop (the outer engine reads its problems' completion flags).
 int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, bool profile,
               const std::function<int()>& after, const std::function<bool()>& stop,
-              bool use_graph = false) {
+              bool use_graph = false, bool summary = true) {
   const int L = std::max(0, std::min(lookahead, 8));
   LRADI_TRY(ctx->ring.init(L + 1));
   while ((int)ctx->events.size() < L + 1) {
@@ -518,7 +521,7 @@ int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, boo
   // optional replay of captured ticks (not with per-launch timing events)
   TickGraphs graphs;
   bool graphed = false;
-  if (use_graph && !profile) LRADI_TRY(graphs.build(ctx, b, L + 1, after, &graphed));
+  if (use_graph && !profile) LRADI_TRY(graphs.build(ctx, b, L + 1, after, summary, &graphed));
   long t = 0;
   for (;; ++t) {
     const int slot = (int)(t % (L + 1));
@@ -527,15 +530,14 @@ int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, boo
     } else {
       LRADI_TRY(launch_tick(st, b, profile ? &ctx->probes[slot] : nullptr));
       if (after) LRADI_TRY(after());
-      LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
+      if (summary) LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
     }
     LRADI_HIP(hipEventRecord(ctx->events[slot], st));
     if (t >= L) {
       const int rs = (int)((t - L) % (L + 1));
       LRADI_HIP(hipEventSynchronize(ctx->events[rs]));
       if (profile) LRADI_TRY(probe_account(ctx, ctx->probes[rs]));
-      const int left = __atomic_load_n(ctx->ring.h + rs, __ATOMIC_ACQUIRE);
-      if (left == 0) break;
+      if (summary && __atomic_load_n(ctx->ring.h + rs, __ATOMIC_ACQUIRE) == 0) break;
       if (stop && stop()) break;
     }
     if (t > max_ticks) {
@@ -886,15 +888,18 @@ struct Engine {
     if (act.empty()) return LRADI_OK;
     const int np = (int)act.size();
     auto after = [&]() { return adi_launch_step_end(c->stream, tab.b, dad.as<AdiDesc>(), dac.as<AdiCtl>(), np); };
+    // the problems' completion flags (written by the device when a problem
+    // finishes) end the run: all of them, or `retire` of them
+    const int need = retire > 0 ? std::min(retire, np) : np;
     auto check = [&]() {
       if (stop && stop()) return true;
-      if (retire <= 0) return false;
       int k = 0;
       for (Prob* q : act) k += q->done.get();
-      return k >= retire;
+      return k >= need;
     };
     const long max_ticks = (3L * std::max(o.max_inner, 1) + 16) * (long)(o.kmax + 1);
-    const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, after, check, o.use_graph != 0);
+    const int rc = run_ticks(c, tab.b, o.lookahead, max_ticks, o.profile != 0, after, check, o.use_graph != 0,
+                             false);
     if (rc != LRADI_OK) {
       (void)hipStreamSynchronize(c->stream);
       return rc;
