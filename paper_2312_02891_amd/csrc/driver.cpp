@@ -297,6 +297,7 @@ struct SysWork {
                             n * rr * 8,                // R
                             (size_t)nwg * pstride * 8, // part
                             (size_t)nwg * kPS * 8,     // partS
+                            (size_t)nwg * kPS * 8,     // partS2
                             pstride * 8,               // red
                             pstride * 8,               // hacc
                             mm * rr * mm * rr * 8,     // Rt
@@ -335,13 +336,14 @@ struct SysWork {
     d.R = reinterpret_cast<double*>(take(sizes[2]));
     d.part = reinterpret_cast<double*>(take(sizes[3]));
     d.partS = reinterpret_cast<double*>(take(sizes[4]));
-    d.red = reinterpret_cast<double*>(take(sizes[5]));
-    d.hacc = reinterpret_cast<double*>(take(sizes[6]));
-    d.Rt = reinterpret_cast<double*>(take(sizes[7]));
-    d.Qs = reinterpret_cast<double*>(take(sizes[8]));
-    d.Gv = reinterpret_cast<double*>(take(sizes[9]));
-    d.yv = reinterpret_cast<double*>(take(sizes[10]));
-    d.sm = reinterpret_cast<double*>(take(sizes[11]));
+    d.partS2 = reinterpret_cast<double*>(take(sizes[5]));
+    d.red = reinterpret_cast<double*>(take(sizes[6]));
+    d.hacc = reinterpret_cast<double*>(take(sizes[7]));
+    d.Rt = reinterpret_cast<double*>(take(sizes[8]));
+    d.Qs = reinterpret_cast<double*>(take(sizes[9]));
+    d.Gv = reinterpret_cast<double*>(take(sizes[10]));
+    d.yv = reinterpret_cast<double*>(take(sizes[11]));
+    d.sm = reinterpret_cast<double*>(take(sizes[12]));
     c = SysCtl{};
     c.phase = PH_FINISHED;  // armed by the caller or by the outer kernels
     return LRADI_OK;
@@ -383,7 +385,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hd.resize(nsys);
   t.hc.resize(nsys);
   t.hmap.clear();
-  int maxP = 1, maxB = 1, rfix = ws[0]->d.r;
+  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -392,6 +394,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
     for (int w = 0; w < ws[s]->d.nwg; ++w) t.hmap.push_back(make_int2(s, w));
     maxP = std::max(maxP, ws[s]->d.pstride);
     maxB = std::max(maxB, ws[s]->d.m + 1);
+    if (ws[s]->d.nwg * ws[s]->d.r * ws[s]->d.r > kFuseCholMax) fuse = 0;
     if (ws[s]->d.r != rfix) rfix = 0;
   }
   // shifted-product tiles, grouped by lanes per row
@@ -427,6 +430,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.rowgrid = (int)t.hmap.size();
   t.b.maxP = maxP;
   t.b.maxB = maxB;
+  // (the scale kernels carry the fused factor for narrow blocks only)
+  t.b.fuse_chol = fuse && rfix >= 1 && rfix <= 4;
   t.b.precision = prec;
   t.b.rfix = rfix;
   return LRADI_OK;
@@ -756,7 +761,7 @@ size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lra
   };
   auto inner = [&](size_t rows) {
     const size_t rpw = (size_t)choose_rows_per_wg((int)rows), nwg = (rows + rpw - 1) / rpw;
-    return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + kPS) * 8 +
+    return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + 2 * kPS) * 8 +
            (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 12 * 256 + 4096;
   };
   return mat(n, nnzA) + mat(m, nnzB) + (size_t)(n + m) * r * 8 * (3 + K) + K * (kHistCols + 1) * 8 +

@@ -18,6 +18,9 @@ constexpr int kSmallTPB = 64;   // threads of a per-system workgroup (1 wavefron
 constexpr int kHistCols = LRADI_HIST_COLS;
 constexpr int kPS = 128;        // stride of the small Gram partial rows
 constexpr int kSpmmCap = 2048;  // nonzeros of one SpMM tile staged in LDS
+// CholQR factors are formed inside the scale kernels when every system's
+// small Gram partials (nwg x r^2 values) are at most this many
+constexpr int kFuseCholMax = 8192;
 
 // Device pointers held in descriptor tables are generic (flat) to the
 // compiler; casting them to the global address space lets it issue global
@@ -131,6 +134,7 @@ struct SysDesc {
   void* U;              // candidate block, n x r, basis precision
   double* part;         // per-workgroup Gram partials, nwg x pstride
   double* partS;        // per-workgroup small Gram partials, nwg x kPS
+  double* partS2;       // the same for the second CholQR pass, nwg x kPS
   double* red;          // reduced projection coefficients, (m+1) r^2
   double* hacc;         // Hessenberg column block being built, (m+1) r^2
   double* Rt;           // triangular factor, (m r) x (m r), column-major
@@ -230,6 +234,9 @@ struct Batch {
   int maxB;            // max over systems of m+1 (basis blocks)
   int precision;       // LRADI_FP64 / LRADI_FP32_INNER
   int rfix;            // common r of all systems, or 0 when they differ
+  int fuse_chol;       // 1: every scale workgroup reduces the small Gram
+                       // partials and factors them itself (common r <= 4
+                       // and small nwg r^2)
   unsigned long long* prof_bytes;  // device counters per kernel class, or null
 };
 

@@ -89,22 +89,22 @@ __device__ inline void block_sum_store(double (&v)[NV], double* lds, double* out
 // w in a fixed order with a 256-thread workgroup; result in out (shared).
 // Each thread keeps four independent partial sums so that its loads are in
 // flight together.
-__device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, double* out) {
+__device__ inline void reduce_small(const double* src, int nwg, int P, double* red_lds, double* out) {
   const int t = threadIdx.x;
   const int groups = kTPB / P;  // P <= 64, so groups >= 4
   const int p = t % P, g = t / P;
   double acc = 0.0;
   if (g < groups) {
-    const double* X = D.partS + p;
+    const double* X = src + p;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int w = g;
-    for (; w + 3 * groups < D.nwg; w += 4 * groups) {
+    for (; w + 3 * groups < nwg; w += 4 * groups) {
       a0 += X[(size_t)w * kPS];
       a1 += X[(size_t)(w + groups) * kPS];
       a2 += X[(size_t)(w + 2 * groups) * kPS];
       a3 += X[(size_t)(w + 3 * groups) * kPS];
     }
-    for (; w < D.nwg; w += groups) a0 += X[(size_t)w * kPS];
+    for (; w < nwg; w += groups) a0 += X[(size_t)w * kPS];
     acc = (a0 + a1) + (a2 + a3);
   }
   red_lds[t] = acc;
@@ -115,6 +115,10 @@ __device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, do
     out[t] = s;
   }
   __syncthreads();
+}
+
+__device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, double* out) {
+  reduce_small(D.partS, D.nwg, P, red_lds, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,24 +518,43 @@ __global__ __launch_bounds__(kTPB) void k_update(const SysDesc* __restrict__ d,
 
 // ---------------------------------------------------------------------------
 // 8./10. Cholesky factor of the reduced U^T U (PH_ARNOLDI / PH_RESTART).
+// S (upper Cholesky factor, regularised, of G) and its inverse into Sl, Sil;
+// slot >= 0 also stores both to the system's small scratch for later
+// kernels.  Returns chol_upper_reg_t's flag (< 0: not finite).
 template <int R>
-__device__ inline void chol_body(const SysDesc& D, SysCtl& C, int slot, double fl, const double* G) {
+__device__ inline int chol_factor(const SysDesc& D, const double* G, double fl, double* Sl, double* Sil,
+                                  int slot) {
   double S[R * R], Si[R * R];
   const int reg = chol_upper_reg_t<R>(G, S, fl);
+  if (reg < 0) return reg;
+  tri_inv_upper_t<R>(S, Si);
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) {
+    Sl[e] = S[e];
+    Sil[e] = Si[e];
+  }
+  if (slot >= 0) {
+    double* dst = D.sm + (slot == 0 ? SM_S1 : SM_S2);
+    double* dsti = D.sm + (slot == 0 ? SM_S1I : SM_S2I);
+#pragma unroll
+    for (int e = 0; e < R * R; ++e) {
+      dst[e] = S[e];
+      dsti[e] = Si[e];
+    }
+  }
+  return reg;
+}
+
+template <int R>
+__device__ inline void chol_body(const SysDesc& D, SysCtl& C, int slot, double fl, const double* G) {
+  double Sl[R * R], Sil[R * R];
+  const int reg = chol_factor<R>(D, G, fl, Sl, Sil, slot);
   if (reg < 0) {
     C.status = IS_NAN;
     C.phase = PH_FINISHED;
     return;
   }
   if (reg > 0) C.breakdowns += 1;
-  tri_inv_upper_t<R>(S, Si);
-  double* dst = D.sm + (slot == 0 ? SM_S1 : SM_S2);
-  double* dsti = D.sm + (slot == 0 ? SM_S1I : SM_S2I);
-#pragma unroll
-  for (int e = 0; e < R * R; ++e) {
-    dst[e] = S[e];
-    dsti[e] = Si[e];
-  }
 }
 
 __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl,
@@ -543,7 +566,7 @@ __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, Sy
   const int ph = ctl[s].phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
   const int R = D.r;
-  reduce_partS(D, R * R, red_lds, G);
+  reduce_small(slot == 0 ? D.partS : D.partS2, D.nwg, R * R, red_lds, G);
   if (threadIdx.x == 0) {
     const double fl = (D.precision == LRADI_FP64) ? rel_floor64 : rel_floor32;
     LRADI_DISPATCH_R(R, chol_body<RR>(D, ctl[s], slot, fl, G));
@@ -554,7 +577,7 @@ __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, Sy
 //        pass 1: V_{j+1} (PH_ARNOLDI) or V_0 (PH_RESTART) = U S2^{-1}.
 template <typename T, int R, bool GRAM>
 __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const double* Si, T* dst,
-                                  double* lds) {
+                                  double* lds, double* gout) {
   double sl[R * R];
 #pragma unroll
   for (int e = 0; e < R * R; ++e) sl[e] = Si[e];
@@ -589,29 +612,58 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
         for (int q = 0; q < R; ++q) g2[a * R + q] += (double)ot[a] * (double)ot[q];
     }
   }
-  if constexpr (GRAM) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+  if constexpr (GRAM) block_sum_store<R * R>(g2, lds, gout + (size_t)c.w * kPS);
 }
 
 template <typename T, int RF, int PASS>
 __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
-                                                const SysCtl* __restrict__ ctl,
-                                                const int2* __restrict__ rowmap) {
+                                                SysCtl* __restrict__ ctl,
+                                                const int2* __restrict__ rowmap, int fuse,
+                                                double fl64, double fl32) {
   __shared__ double lds[4 * kMaxR * kMaxR];
+  __shared__ double red_lds[kTPB];
+  __shared__ double G[64];
+  __shared__ double SS[2 * kMaxR * kMaxR];
+  __shared__ int ok;
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   const int ph = ctl[c.s].phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  const double* Si = D.sm + (PASS == 0 ? SM_S1I : SM_S2I);
+  if constexpr (RF >= 1 && RF <= 4) {
+   if (fuse) {
+    // this pass's Cholesky factor, formed by every workgroup from the small
+    // Gram partials in the same order (identical in all of them); workgroup
+    // 0 publishes it and the control-block updates
+    reduce_small(PASS == 0 ? D.partS : D.partS2, D.nwg, D.r * D.r, red_lds, G);
+    if (threadIdx.x == 0) {
+      const double fl = (D.precision == LRADI_FP64) ? fl64 : fl32;
+      int reg = 0;
+      LRADI_RSEL(RF, D.r, reg = chol_factor<RR>(D, G, fl, SS, SS + RR * RR, c.w == 0 ? PASS : -1));
+      ok = reg >= 0;
+      if (c.w == 0) {
+        SysCtl& C = ctl[c.s];
+        if (reg < 0) {
+          C.status = IS_NAN;
+          C.phase = PH_FINISHED;
+        } else if (reg > 0) {
+          C.breakdowns += 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (!ok) return;
+    Si = SS + D.r * D.r;
+   }
+  }
   T* dst;
-  const double* Si;
   if (PASS == 0) {
     dst = static_cast<T*>(D.U);
-    Si = D.sm + SM_S1I;
   } else {
     const int tgt = (ph == PH_ARNOLDI) ? ctl[c.s].j + 1 : 0;
     dst = static_cast<T*>(D.V) + (size_t)tgt * D.n * D.r;
-    Si = D.sm + SM_S2I;
   }
-  LRADI_RSEL(RF, D.r, scale_rows<T, RR, PASS == 0>(D, c, Si, dst, lds));
+  LRADI_RSEL(RF, D.r, scale_rows<T, RR, PASS == 0>(D, c, Si, dst, lds, D.partS2));
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,10 +1118,10 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[3], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
   hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
-  hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
-  hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
-  hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
+  hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32);
+  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
+  hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32);
   hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(LsqTPB<RF>::v), shP, st, b.d, b.ctl);
   hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
