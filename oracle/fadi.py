@@ -1,12 +1,18 @@
 """Oracle (test infrastructure only): the low-rank factored ADI iteration for
 A X + X B = -f g^T (eq. (sylv)) with sparse-direct ("exact") inner solves.
 
-This follows Algorithm 1 (inexact LR-ADI) with M = I, C = I, in the
-residual-factor form of eq. (lradi_basic):
+This follows Algorithm 1 (inexact LR-ADI) in the residual-factor form of
+eq. (lradi_basic):
 
     z_k = (A + beta_k I)^{-1} w_{k-1},        w_k = w_{k-1} + gamma_k z_k,
     y_k = (B + alpha_k I)^{-*} t_{k-1},       t_k = t_{k-1} + conj(gamma_k) y_k,
     gamma_k = -(beta_k + alpha_k),            w_0 = f, t_0 = g,
+
+and, given M and C, for the generalized equation A X C + M X B = -f g^T
+(eq. (gsylv)) in the form of eq. (lradi_g):
+
+    z_k = (A + beta_k M)^{-1} w_{k-1},        w_k = w_{k-1} + gamma_k M z_k,
+    y_k = (B + alpha_k C)^{-*} t_{k-1},       t_k = t_{k-1} + conj(gamma_k) C^* y_k,
 
 and returns Z_k, Gamma_k = diag(gamma_1 I_r, ..., gamma_k I_r), Y_k with
 X ~ Z_k Gamma_k Y_k^*.  The loop runs while ||w_{k-1} t_{k-1}^*|| >= tau ||f g^T||
@@ -65,8 +71,10 @@ class FadiResult:
     res_hist: List[float]    # ||w_j t_j^*|| / ||f g^T||, j = 1..k
     norm_fg: float
     k: int
-    rA: List[np.ndarray]     # inner residuals r^A_j = w_{j-1} - (A + pA_j I) z_j
-    rB: List[np.ndarray]     # inner residuals r^B_j = t_{j-1} - (B^T + pB_j I) y_j
+    rA: List[np.ndarray]     # inner residuals r^A_j = w_{j-1} - (A + pA_j M) z_j
+    rB: List[np.ndarray]     # inner residuals r^B_j = t_{j-1} - (B^T + pB_j C^T) y_j
+    nMz: List[float] = dataclasses.field(default_factory=list)  # ||M z_j||
+    nCy: List[float] = dataclasses.field(default_factory=list)  # ||C^T y_j||
 
     def D(self) -> np.ndarray:
         r = self.Z.shape[1] // max(self.k, 1) if self.k else 0
@@ -77,11 +85,13 @@ class FadiResult:
         return (self.Z * self.D()) @ self.Y.T
 
 
-def _direct_solver(M: sp.spmatrix, cache: dict, shift: float) -> Callable:
+def _direct_solver(Op: sp.spmatrix, cache: dict, shift: float, mass=None) -> Callable:
+    """LU of Op + shift * mass (mass = I when None), once per distinct shift."""
     key = float(shift)
     if key not in cache:
-        n = M.shape[0]
-        cache[key] = spla.splu((M + shift * sp.identity(n, format="csr")).tocsc())
+        n = Op.shape[0]
+        E = sp.identity(n, format="csr") if mass is None else mass
+        cache[key] = spla.splu((Op + shift * E).tocsc())
     lu = cache[key]
     return lu.solve
 
@@ -89,16 +99,20 @@ def _direct_solver(M: sp.spmatrix, cache: dict, shift: float) -> Callable:
 def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
          pA: np.ndarray, pB: np.ndarray, tol: float = 1e-8, kmax: int = 50,
          rescale: bool = True, solve_A: Optional[Callable] = None,
-         solve_B: Optional[Callable] = None, kfixed: Optional[int] = None) -> FadiResult:
+         solve_B: Optional[Callable] = None, kfixed: Optional[int] = None,
+         M=None, C=None) -> FadiResult:
     """Algorithm 1 with direct inner solves (the "direct solves" rows of Table 2).
 
     solve_A(k, shift, rhs) / solve_B(k, shift, rhs) may replace the direct
     solves (used by tests that plant inexact solves); by default each distinct
     shift is LU-factorised once (SuperLU).  kfixed runs exactly that many steps
-    ignoring tau.  Returns the factors, the computed residual history and the
-    inner residual blocks."""
+    ignoring tau.  M, C (None = identity) give the generalized equation
+    (eq. (gsylv), iteration (lradi_g)).  Returns the factors, the computed
+    residual history and the inner residual blocks."""
     A = sp.csr_matrix(A)
     Bt = sp.csr_matrix(B).T.tocsr()
+    Mm = None if M is None else sp.csr_matrix(M)
+    Ct = None if C is None else sp.csr_matrix(C).T.tocsr()
     f = np.array(f, dtype=np.float64, copy=True)
     g = np.array(g, dtype=np.float64, copy=True)
     if rescale:
@@ -106,7 +120,7 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
     norm_fg = lowrank_product_norm(f, g)
     cacheA, cacheB = {}, {}
     W, T = f.copy(), g.copy()
-    Zs, Ys, gam, hist, rA, rB = [], [], [], [], [], []
+    Zs, Ys, gam, hist, rA, rB, nMz, nCy = [], [], [], [], [], [], [], []
     J = len(pA)
     k = 0
     while True:
@@ -120,20 +134,24 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
                 break
         a, b = float(pA[k % J]), float(pB[k % J])
         if solve_A is None:
-            z = _direct_solver(A, cacheA, a)(W)
+            z = _direct_solver(A, cacheA, a, Mm)(W)
         else:
             z = solve_A(k, a, W)
         if solve_B is None:
-            y = _direct_solver(Bt, cacheB, b)(T)
+            y = _direct_solver(Bt, cacheB, b, Ct)(T)
         else:
             y = solve_B(k, b, T)
         z = np.asarray(z).reshape(W.shape)
         y = np.asarray(y).reshape(T.shape)
-        rA.append(W - (A @ z + a * z))
-        rB.append(T - (Bt @ y + b * y))
+        Mz = z if Mm is None else np.asarray(Mm @ z)
+        Cy = y if Ct is None else np.asarray(Ct @ y)
+        rA.append(W - (A @ z + a * Mz))
+        rB.append(T - (Bt @ y + b * Cy))
         gk = -(a + b)
-        W = W + gk * z
-        T = T + gk * y
+        W = W + gk * Mz
+        T = T + gk * Cy
+        nMz.append(spectral_norm(Mz))
+        nCy.append(spectral_norm(Cy))
         Zs.append(z)
         Ys.append(y)
         gam.append(gk)
@@ -143,27 +161,33 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
     m = g.shape[0]
     Z = np.hstack(Zs) if Zs else np.zeros((n, 0))
     Y = np.hstack(Ys) if Ys else np.zeros((m, 0))
-    return FadiResult(Z, Y, np.asarray(gam), W, T, hist, norm_fg, k, rA, rB)
+    return FadiResult(Z, Y, np.asarray(gam), W, T, hist, norm_fg, k, rA, rB, nMz, nCy)
 
 
-def true_residual_dense(A, B, f, g, X) -> np.ndarray:
-    """Sylvester residual A X + X B + f g^T as a dense matrix (the sign that
-    makes the k = 0 residual equal f g^T, eq. (adi_res_inexact))."""
+def true_residual_dense(A, B, f, g, X, M=None, C=None) -> np.ndarray:
+    """Sylvester residual A X C + M X B + f g^T as a dense matrix (the sign
+    that makes the k = 0 residual equal f g^T, eq. (adi_res_inexact));
+    M, C = None mean identity."""
     A = sp.csr_matrix(A)
     B = sp.csr_matrix(B)
-    return np.asarray(A @ X) + np.asarray((B.T @ X.T).T) + f @ g.T
+    AX = np.asarray(A @ X)
+    AXC = AX if C is None else np.asarray((sp.csr_matrix(C).T @ AX.T).T)
+    MX = X if M is None else np.asarray(sp.csr_matrix(M) @ X)
+    return AXC + np.asarray((B.T @ MX.T).T) + f @ g.T
 
 
-def lowrank_residual_norm(A, B, f, g, Z, d, Y) -> float:
-    """||A Z D Y^T + Z D Y^T B + f g^T||_2 exactly, without forming n x m
-    matrices: the residual equals U V^T with U = [A Z, Z, f] and
-    V = [Y D, B^T Y D, g]; with thin QRs U = Q_u R_u, V = Q_v R_v its norm is
-    ||R_u R_v^T||_2.  d holds the diagonal of D."""
+def lowrank_residual_norm(A, B, f, g, Z, d, Y, M=None, C=None) -> float:
+    """||A Z D Y^T C + M Z D Y^T B + f g^T||_2 exactly, without forming n x m
+    matrices: the residual equals U V^T with U = [A Z, M Z, f] and
+    V = [C^T Y D, B^T Y D, g]; with thin QRs U = Q_u R_u, V = Q_v R_v its norm
+    is ||R_u R_v^T||_2.  d holds the diagonal of D; M, C = None mean identity."""
     A = sp.csr_matrix(A)
     Bt = sp.csr_matrix(B).T.tocsr()
     YD = Y * d
-    U = np.hstack([np.asarray(A @ Z), Z, f])
-    V = np.hstack([YD, np.asarray(Bt @ YD), g])
+    MZ = Z if M is None else np.asarray(sp.csr_matrix(M) @ Z)
+    CtYD = YD if C is None else np.asarray(sp.csr_matrix(C).T @ YD)
+    U = np.hstack([np.asarray(A @ Z), MZ, f])
+    V = np.hstack([CtYD, np.asarray(Bt @ YD), g])
     Ru = np.linalg.qr(U, mode="r")
     Rv = np.linalg.qr(V, mode="r")
     return spectral_norm(Ru @ Rv.T)
