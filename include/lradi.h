@@ -227,6 +227,20 @@ int lradi_solve(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, const do
                 const double* g, int r, const double* shiftsA, const double* shiftsB,
                 int nshifts, const lradi_opts* opts, lradi_result** out);
 
+/* Algorithm 1 with M and C: A X C + M X B = -f g^T (eq. (gsylv)) by the
+ * iteration of eq. (lradi_g): (A + beta_k M) z_k = w_{k-1},
+ * w_k = w_{k-1} + gamma_k M z_k, (B + alpha_k C)^T y_k = t_{k-1},
+ * t_k = t_{k-1} + gamma_k C^T y_k; the gap recursion of eq. (upd_resgap)
+ * uses ||M z_k|| and ||C^T y_k||.  M (n x n) and C (m x m, or C^T when
+ * opts->b_is_transposed) are csr matrices; either may be NULL (identity).
+ * The inner systems are stored as pencils: the union pattern of A and M
+ * with both value arrays, combined per shift inside the kernels.  Other
+ * arguments as lradi_solve. */
+int lradi_solve_gen(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, const lradi_csr* M,
+                    const lradi_csr* C, const double* f, const double* g, int r,
+                    const double* shiftsA, const double* shiftsB, int nshifts,
+                    const lradi_opts* opts, lradi_result** out);
+
 /* One Sylvester problem for lradi_batch_solve and the serving loop. */
 typedef struct {
   const lradi_csr* A;      /* n x n (host or device)                           */
@@ -240,6 +254,11 @@ typedef struct {
   double tol;              /* outer tau of this problem; <= 0 uses opts->tol.
                               opts->delta_min and opts->delta_fixed refer to
                               opts->tol and are scaled by tol / opts->tol     */
+  const lradi_csr* M;      /* generalized equation A X C + M X B = -f g^T
+                              (eq. (gsylv), iteration (lradi_g)): n x n, or
+                              NULL for M = I                                  */
+  const lradi_csr* C;      /* m x m (C^T when opts->b_is_transposed), or NULL
+                              for C = I                                       */
 } lradi_problem;
 
 /* Algorithm 1 on nprob independent problems of uneven n, m, r advanced

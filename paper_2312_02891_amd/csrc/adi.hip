@@ -242,11 +242,55 @@ __global__ __launch_bounds__(kTPB) void k_adi_init_wt(const SysDesc* __restrict_
   for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) Y[e] = sc * X[e];
 }
 
+// generalized equation (eq. (lradi_g)): W += gamma M Z with M's rows on the
+// system's pattern, and the Gram of M Z in place of Z's for the gap
+// recursion of eq. (upd_resgap)
+template <int R>
+__device__ inline void adi_update_rows_mass(const SysDesc& D, double* Wt, const double* Zk, double gamma,
+                                            const RowC& c, double* lds, double* dst) {
+  double g2[R * R], g3[R * R];
+#pragma unroll
+  for (int e = 0; e < R * R; ++e) g2[e] = g3[e] = 0.0;
+  const int* __restrict__ rp = D.rowptr;
+  const int* __restrict__ ci = D.colind;
+  const double* __restrict__ mv = D.mval64;
+  for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
+    double mz[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) mz[q] = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const double a = mv[k];
+      const double* z = Zk + (size_t)ci[k] * R;
+#pragma unroll
+      for (int q = 0; q < R; ++q) mz[q] += a * z[q];
+    }
+    double w[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      w[q] = Wt[(size_t)i * R + q] + gamma * mz[q];
+      Wt[(size_t)i * R + q] = w[q];
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        g2[a * R + q] += w[a] * w[q];
+        g3[a * R + q] += mz[a] * mz[q];
+      }
+  }
+  bsum<R * R>(g2, lds, dst);
+  bsum<R * R>(g3, lds, dst + 64);
+}
+
 // after the inner solves: W += gamma Z (A side) or T += gamma Y (B side),
 // partial Grams of the new factor (offset 0) and of the new block (offset 64)
 template <int R>
-__device__ inline void adi_update_rows(double* Wt, const double* Zk, double gamma, const RowC& c,
-                                       double* lds, double* dst) {
+__device__ inline void adi_update_rows(const SysDesc& D, double* Wt, const double* Zk, double gamma,
+                                       const RowC& c, double* lds, double* dst) {
+  if (D.mval64) {
+    adi_update_rows_mass<R>(D, Wt, Zk, gamma, c, lds, dst);
+    return;
+  }
   double g2[R * R];
 #pragma unroll
   for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
@@ -281,7 +325,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_update(const SysDesc* __restrict__
   const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
   double* Wt = (c.s & 1) ? P.T : P.W;
   const double* Zk = ctl[c.s].Z;
-  LRADI_DISPATCH_R2(D.r, adi_update_rows<RR>(Wt, Zk, gamma, c, lds, D.partS + (size_t)c.w * kPS));
+  LRADI_DISPATCH_R2(D.r, adi_update_rows<RR>(D, Wt, Zk, gamma, c, lds, D.partS + (size_t)c.w * kPS));
 }
 
 // norms, gap estimates u, v (eq. (upd_resgap)), history row, stop test; then

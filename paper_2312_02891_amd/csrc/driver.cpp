@@ -26,6 +26,9 @@ namespace lradi {
 
 void csr_transpose(int n, const int32_t* rp, const int32_t* ci, const double* v,
                    std::vector<int32_t>& trp, std::vector<int32_t>& tci, std::vector<double>& tv);
+void csr_union(int n, const int32_t* prp, const int32_t* pci, const double* pv, const int32_t* qrp,
+               const int32_t* qci, const double* qv, std::vector<int32_t>& urp,
+               std::vector<int32_t>& uci, std::vector<double>& upv, std::vector<double>& uqv);
 int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
                   const double* f, const double* g, int r, const double* Z, const double* gam_d,
                   const double* Y, int k, int maxit, double* sigma_out);
@@ -326,6 +329,9 @@ struct SysWork {
     d.colind = A->colind.as<int>();
     d.valT = (prec == LRADI_FP64) ? (const void*)A->val64.p : (const void*)A->val32.p;
     d.val64 = A->val64.as<double>();
+    d.mvalT = A->has_mass() ? ((prec == LRADI_FP64) ? (const void*)A->mval64.p : (const void*)A->mval32.p)
+                            : nullptr;
+    d.mval64 = A->has_mass() ? A->mval64.as<double>() : nullptr;
     d.floor_rel = floor_rel;
     d.W = W;
     d.pstride = (int)pstride;
@@ -611,6 +617,16 @@ int upload_pair(const lradi_csr* M, hipStream_t st, DevCSR& dM, DevCSR& dMt) {
   return LRADI_OK;
 }
 
+// transposed host copy of a (host or device) csr matrix
+int host_csr_t(const lradi_csr* M, std::vector<int32_t>& trp, std::vector<int32_t>& tci,
+               std::vector<double>& tv) {
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+  LRADI_TRY(host_csr(M, rp, ci, v));
+  csr_transpose(M->nrows, rp.data(), ci.data(), v.data(), trp, tci, tv);
+  return LRADI_OK;
+}
+
 int check_opts(const lradi_opts& o) {
   if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error("tol must be in (0,1)"), LRADI_EINVAL;
   if (o.kmax < 1 || o.kmax > 100000) return set_error("kmax must be in 1..100000"), LRADI_EINVAL;
@@ -635,6 +651,33 @@ double floor_for(const lradi_opts& o) {
 }
 
 }  // namespace
+
+int DevCSR::upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32) {
+  std::vector<int32_t> arp, aci, mrp, mci, urp, uci;
+  std::vector<double> av, mv, uav, umv;
+  LRADI_TRY(host_csr(A, arp, aci, av));
+  LRADI_TRY(host_csr(M, mrp, mci, mv));
+  if (M->nrows != A->nrows) return set_error("mass matrix size differs from its operator"), LRADI_EINVAL;
+  csr_union(A->nrows, arp.data(), aci.data(), av.data(), mrp.data(), mci.data(), mv.data(), urp, uci, uav,
+            umv);
+  lradi_csr U{A->nrows, A->nrows, (int64_t)uci.size(), urp.data(), uci.data(), uav.data(), 0};
+  LRADI_TRY(upload(&U, st, need32));
+  LRADI_TRY(mval64.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)));
+  if (nnz > 0)
+    LRADI_HIP(hipMemcpyAsync(mval64.p, umv.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+  if (need32) {
+    LRADI_TRY(mval32.alloc(sizeof(float) * std::max<int64_t>(nnz, 1)));
+    if (nnz > 0) {
+      const int tpb = 256;
+      hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nnz + tpb - 1) / tpb)), dim3(tpb), 0, st,
+                         mval64.as<double>(), mval32.as<float>(), nnz);
+      LRADI_HIP(hipGetLastError());
+    }
+  }
+  LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
+  return LRADI_OK;
+}
+
 }  // namespace lradi
 
 // ---------------------------------------------------------------------------
@@ -696,17 +739,29 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
   if (!(tol > 0.0 && tol < 1.0)) return set_error("problem: tol must be in (0,1)"), LRADI_EINVAL;
   q.t0 = std::chrono::steady_clock::now();
   const bool f32 = o.precision == LRADI_FP32_INNER;
-  LRADI_TRY(q.A.upload(P.A, st, f32));
+  if (P.M)
+    LRADI_TRY(q.A.upload_pencil(P.A, P.M, st, f32));
+  else
+    LRADI_TRY(q.A.upload(P.A, st, f32));
   if (o.b_is_transposed) {
-    LRADI_TRY(q.Bt.upload(P.B, st, f32));
+    if (P.C)
+      LRADI_TRY(q.Bt.upload_pencil(P.B, P.C, st, f32));
+    else
+      LRADI_TRY(q.Bt.upload(P.B, st, f32));
   } else {
-    std::vector<int32_t> rp, ci, trp, tci;
-    std::vector<double> v, tv;
-    LRADI_TRY(host_csr(P.B, rp, ci, v));
+    std::vector<int32_t> trp, tci, crp, cci;
+    std::vector<double> tv, cv;
+    LRADI_TRY(host_csr_t(P.B, trp, tci, tv));
     const int mB = P.B->nrows;
-    csr_transpose(mB, rp.data(), ci.data(), v.data(), trp, tci, tv);
-    lradi_csr Bt{mB, mB, P.B->nnz, trp.data(), tci.data(), tv.data(), 0};
-    LRADI_TRY(q.Bt.upload(&Bt, st, f32));
+    lradi_csr Bt{mB, mB, (int64_t)tci.size(), trp.data(), tci.data(), tv.data(), 0};
+    if (P.C) {
+      LRADI_TRY(host_csr_t(P.C, crp, cci, cv));
+      const int mC = P.C->nrows;
+      lradi_csr Ct{mC, mC, (int64_t)cci.size(), crp.data(), cci.data(), cv.data(), 0};
+      LRADI_TRY(q.Bt.upload_pencil(&Bt, &Ct, st, f32));
+    } else {
+      LRADI_TRY(q.Bt.upload(&Bt, st, f32));
+    }
     LRADI_HIP(hipStreamSynchronize(st));
   }
   q.n = q.A.n;
@@ -1112,7 +1167,16 @@ int lradi_solve(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const doub
                 const double* g, int r, const double* shiftsA, const double* shiftsB, int nshifts,
                 const lradi_opts* opts, lradi_result** out) {
   if (!out) return set_error("lradi_solve: null output"), LRADI_EINVAL;
-  lradi_problem P{A, B, f, g, r, nshifts, shiftsA, shiftsB, 0.0};
+  lradi_problem P{A, B, f, g, r, nshifts, shiftsA, shiftsB, 0.0, nullptr, nullptr};
+  return lradi_batch_solve(c, 1, &P, opts, out);
+}
+
+int lradi_solve_gen(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const lradi_csr* M,
+                    const lradi_csr* C, const double* f, const double* g, int r,
+                    const double* shiftsA, const double* shiftsB, int nshifts, const lradi_opts* opts,
+                    lradi_result** out) {
+  if (!out) return set_error("lradi_solve_gen: null output"), LRADI_EINVAL;
+  lradi_problem P{A, B, f, g, r, nshifts, shiftsA, shiftsB, 0.0, M, C};
   return lradi_batch_solve(c, 1, &P, opts, out);
 }
 
@@ -1261,8 +1325,9 @@ struct lradi_server {
   // host copies of a submitted problem until the worker uploads it
   struct Pending {
     uint64_t ticket;
-    std::vector<int32_t> arp, aci, brp, bci;
-    std::vector<double> aval, bval, f, g, sA, sB;
+    std::vector<int32_t> arp, aci, brp, bci, mrp, mci, crp, cci;
+    std::vector<double> aval, bval, mval, cval, f, g, sA, sB;
+    bool hasM = false, hasC = false;
     int r = 0, n = 0, m = 0;
     double tol = 0.0;
     size_t footprint = 0;
@@ -1345,8 +1410,10 @@ void lradi_server::run() {
         rc = LRADI_EHIP;
       if (rc == LRADI_OK && hipMemcpy(gd.p, P.g.data(), sizeof(double) * P.g.size(), hipMemcpyHostToDevice) != hipSuccess)
         rc = LRADI_EHIP;
+      lradi_csr Mc{P.n, P.n, (int64_t)P.mci.size(), P.mrp.data(), P.mci.data(), P.mval.data(), 0};
+      lradi_csr Cc{P.m, P.m, (int64_t)P.cci.size(), P.crp.data(), P.cci.data(), P.cval.data(), 0};
       lradi_problem pr{&A, &B, fd.as<double>(), gd.as<double>(), P.r, (int32_t)P.sA.size(), P.sA.data(),
-                       P.sB.data(), P.tol};
+                       P.sB.data(), P.tol, P.hasM ? &Mc : nullptr, P.hasC ? &Cc : nullptr};
       if (rc == LRADI_OK) rc = prob_init(ctx, opts, pr, true, *q);
       Prob* raw = q.get();
       live[raw] = Live{std::move(q), P.ticket, P.footprint};
@@ -1461,6 +1528,14 @@ int lradi_server_submit(lradi_server* s, const lradi_problem* P, uint64_t* ticke
   q.tol = P->tol;
   LRADI_TRY(host_csr(P->A, q.arp, q.aci, q.aval));
   LRADI_TRY(host_csr(P->B, q.brp, q.bci, q.bval));
+  if (P->M) {
+    LRADI_TRY(host_csr(P->M, q.mrp, q.mci, q.mval));
+    q.hasM = true;
+  }
+  if (P->C) {
+    LRADI_TRY(host_csr(P->C, q.crp, q.cci, q.cval));
+    q.hasC = true;
+  }
   q.n = P->A->nrows;
   q.m = P->B->nrows;
   q.f.resize((size_t)q.n * q.r);
@@ -1469,7 +1544,10 @@ int lradi_server_submit(lradi_server* s, const lradi_problem* P, uint64_t* ticke
   LRADI_HIP(hipMemcpy(q.g.data(), P->g, sizeof(double) * q.g.size(), hipMemcpyDeviceToHost));
   q.sA.assign(P->shiftsA, P->shiftsA + P->nshifts);
   q.sB.assign(P->shiftsB, P->shiftsB + P->nshifts);
-  q.footprint = prob_footprint(q.n, q.m, q.r, (int64_t)q.aci.size(), (int64_t)q.bci.size(), s->opts);
+  // (a mass matrix adds its values on the union pattern: counted as extra
+  // nonzeros of the operator)
+  q.footprint = prob_footprint(q.n, q.m, q.r, (int64_t)(q.aci.size() + 2 * q.mci.size()),
+                               (int64_t)(q.bci.size() + 2 * q.cci.size()), s->opts);
   if ((int64_t)q.footprint > s->budget)
     return set_error("lradi_server_submit: footprint %zu bytes exceeds the budget", q.footprint), LRADI_ENOMEM;
   q.t_submit = std::chrono::steady_clock::now();

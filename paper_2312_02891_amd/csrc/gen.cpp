@@ -6,6 +6,7 @@
 // reproducible bit for bit.
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/lradi.h"
@@ -109,6 +110,46 @@ void csr_transpose(int n, const int32_t* rp, const int32_t* ci, const double* v,
       tci[dst] = i;
       tv[dst] = v[k];
     }
+}
+
+// Union pattern of two n x n CSR matrices P and Q (columns ascending per
+// row; duplicate entries within one matrix are summed) with both value
+// arrays on it: the pencil P + s Q is stored once, its values formed per
+// shift on the device.
+void csr_union(int n, const int32_t* prp, const int32_t* pci, const double* pv, const int32_t* qrp,
+               const int32_t* qci, const double* qv, std::vector<int32_t>& urp,
+               std::vector<int32_t>& uci, std::vector<double>& upv, std::vector<double>& uqv) {
+  urp.assign(n + 1, 0);
+  uci.clear();
+  upv.clear();
+  uqv.clear();
+  std::vector<std::pair<int32_t, int>> row;  // (column, which) sorted
+  std::vector<double> vals;
+  for (int i = 0; i < n; ++i) {
+    row.clear();
+    for (int64_t k = prp[i]; k < prp[i + 1]; ++k) row.push_back({pci[k], (int)(k - prp[i])});
+    const int np = (int)row.size();
+    for (int64_t k = qrp[i]; k < qrp[i + 1]; ++k) row.push_back({qci[k], np + (int)(k - qrp[i])});
+    std::stable_sort(row.begin(), row.end(),
+                     [](const std::pair<int32_t, int>& a, const std::pair<int32_t, int>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t e = 0; e < row.size(); ++e) {
+      const int32_t col = row[e].first;
+      const int src = row[e].second;
+      const double pvv = src < np ? pv[prp[i] + src] : 0.0;
+      const double qvv = src < np ? 0.0 : qv[qrp[i] + (src - np)];
+      if (!uci.empty() && (int64_t)uci.size() > urp[i] && uci.back() == col) {
+        upv.back() += pvv;
+        uqv.back() += qvv;
+      } else {
+        uci.push_back(col);
+        upv.push_back(pvv);
+        uqv.push_back(qvv);
+      }
+    }
+    urp[i + 1] = (int32_t)uci.size();
+  }
 }
 
 }  // namespace lradi

@@ -145,6 +145,11 @@ struct SysDesc {
   int pstride;          // stride of part rows (>= (m+1) r^2)
   int nnz;              // nonzeros of A
   int spmm_lanes;       // lanes per row of the shifted product (1, 2, 4)
+  // generalized equation: the system is (A + shift M) Z = W with M's values
+  // on A's (union) pattern; null for M = I (then the shift is added to the
+  // diagonal)
+  const void* mvalT;    // M's values in the basis precision
+  const double* mval64; // M's values in FP64 (refinement residual, M z)
 };
 
 // Mutable device-side control block of one inner solve.
@@ -211,7 +216,11 @@ struct DevCSR {
   int n = 0;
   int64_t nnz = 0;
   DevBuf rowptr, colind, val64, val32;
+  DevBuf mval64, mval32;  // the mass matrix of a pencil, on the same pattern
   int upload(const lradi_csr* A, hipStream_t st, bool need32);
+  // the pencil (A, M): union pattern, A's values and M's values
+  int upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);
+  bool has_mass() const { return mval64.p != nullptr; }
 };
 
 // ---------------------------------------------------------------------------

@@ -140,9 +140,13 @@ struct SpmmUnroll {
 // load stays unconditional (and in bounds) and all gathers of a group are in
 // flight together.  ci/val point either to LDS (offset base) or to the CSR
 // arrays (offset 0).
+// mv (nullable): the mass values on the same pattern, the coefficient then
+// is val + shift mv; diag: add shift x_i (M = I); neither when the staged
+// values already hold val + shift mv
 template <typename T, int R, int RC, int SU>
-__device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, const T* val, int off,
-                                T shift, const T* __restrict__ X, T* __restrict__ Y) {
+__device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, const T* val, const T* mv,
+                                bool diag, int off, T shift, const T* __restrict__ X,
+                                T* __restrict__ Y) {
   T acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = T(0);
@@ -153,7 +157,8 @@ __device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, co
     for (int u = 0; u < SU; ++u) {
       const int kk = min(k + u, k1 - 1) - off;
       col[u] = ci[kk];
-      a[u] = val[kk] * (T)(k + u < k1);
+      const T coef = mv ? val[kk] + shift * mv[kk] : val[kk];
+      a[u] = coef * (T)(k + u < k1);
     }
     T xv[SU][RC];
 #pragma unroll
@@ -167,16 +172,22 @@ __device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, co
 #pragma unroll
       for (int q = 0; q < RC; ++q) acc[q] += a[u] * xv[u][q];
   }
-  const T* xi = X + (size_t)i * R + q0;
   T* y = Y + (size_t)i * R + q0;
+  if (diag) {
+    const T* xi = X + (size_t)i * R + q0;
 #pragma unroll
-  for (int q = 0; q < RC; ++q) y[q] = acc[q] + shift * xi[q];
+    for (int q = 0; q < RC; ++q) y[q] = acc[q] + shift * xi[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < RC; ++q) y[q] = acc[q];
+  }
 }
 
 template <typename T, int R, int RL>
 __device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                 const T* __restrict__ val, T shift, const T* __restrict__ X,
-                                 T* __restrict__ Y, int r0, int* s_ci, T* s_val) {
+                                 const T* __restrict__ val, const T* __restrict__ mval, T shift,
+                                 const T* __restrict__ X, T* __restrict__ Y, int r0, int* s_ci,
+                                 T* s_val) {
   constexpr int RC = R / RL;
   constexpr int SU = SpmmUnroll<T>::v;
   constexpr int PER = kSpmmCap / kTPB;
@@ -199,7 +210,7 @@ __device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* _
     for (int p = 0; p < PER; ++p) {
       const int e = base + min(p * kTPB + (int)threadIdx.x, cnt - 1);
       cv[p] = ci[e];
-      vv[p] = val[e];
+      vv[p] = mval ? val[e] + shift * mval[e] : val[e];
     }
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
@@ -213,10 +224,11 @@ __device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* _
   __syncthreads();
   if (!live) return;
   const int q0 = ((int)threadIdx.x % RL) * RC;
+  const bool diag = mval == nullptr;
   if (staged)
-    spmm_row<T, R, RC, SU>(i, q0, k0, k1, s_ci, s_val, base, shift, X, Y);
+    spmm_row<T, R, RC, SU>(i, q0, k0, k1, s_ci, s_val, nullptr, diag, base, shift, X, Y);
   else
-    spmm_row<T, R, RC, SU>(i, q0, k0, k1, ci, val, 0, shift, X, Y);
+    spmm_row<T, R, RC, SU>(i, q0, k0, k1, ci, val, mval, diag, 0, shift, X, Y);
 }
 
 // RL lanes per row; the kernel for group RL serves the systems whose tiling
@@ -248,7 +260,8 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
     atomicAdd(prof + LRADI_PROF_SPMM, bytes);
   }
   const T* val = static_cast<const T*>(D.valT);
-  LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.n, D.rowptr, D.colind, val, sh, Vj, U, r0, s_ci, s_val));
+  const T* mval = static_cast<const T*>(D.mvalT);
+  LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.n, D.rowptr, D.colind, val, mval, sh, Vj, U, r0, s_ci, s_val));
 }
 
 // ---------------------------------------------------------------------------
@@ -990,12 +1003,13 @@ __device__ inline void resid_rows(const SysDesc& D, const RowCtx& c, double shif
       for (int q = 0; q < R; ++q) Z[(size_t)i * R + q] = 0.0;
     } else {
       double acc[R];
+      const double* __restrict__ mv = D.mval64;
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] = shift * Z[(size_t)i * R + q];
+      for (int q = 0; q < R; ++q) acc[q] = mv ? 0.0 : shift * Z[(size_t)i * R + q];
       const int k0 = rp[i], k1 = rp[i + 1];
       for (int k = k0; k < k1; ++k) {
         const int col = ci[k];
-        const double a = val[k];
+        const double a = mv ? val[k] + shift * mv[k] : val[k];
         const double* z = Z + (size_t)col * R;
 #pragma unroll
         for (int q = 0; q < R; ++q) acc[q] += a * z[q];
@@ -1085,7 +1099,7 @@ __global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restric
                                                      const T* __restrict__ X, T* __restrict__ Y) {
   __shared__ int s_ci[kSpmmCap];
   __shared__ T s_val[kSpmmCap];
-  spmm_tile<T, R, RL>(n, rp, ci, val, shift, X, Y, (int)blockIdx.x * spmm_tile_rows(RL), s_ci, s_val);
+  spmm_tile<T, R, RL>(n, rp, ci, val, nullptr, shift, X, Y, (int)blockIdx.x * spmm_tile_rows(RL), s_ci, s_val);
 }
 
 template <typename T, int RF>

@@ -59,7 +59,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("A", ctypes.POINTER(Csr)), ("B", ctypes.POINTER(Csr)), ("f", ctypes.c_void_p),
                 ("g", ctypes.c_void_p), ("r", ctypes.c_int32), ("nshifts", ctypes.c_int32),
                 ("shiftsA", ctypes.POINTER(ctypes.c_double)),
-                ("shiftsB", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double)]
+                ("shiftsB", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
+                ("M", ctypes.POINTER(Csr)), ("C", ctypes.POINTER(Csr))]
 
 
 class ServerCounters(ctypes.Structure):
@@ -109,6 +110,8 @@ def _load():
         "lradi_solve": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32, P(Opts),
                               P(vp)]),
         "lradi_batch_solve": (i32, [vp, i32, P(Problem), P(Opts), P(vp)]),
+        "lradi_solve_gen": (i32, [vp, P(Csr), P(Csr), P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32,
+                                  P(Opts), P(vp)]),
         "lradi_server_create": (i32, [vp, P(Opts), ctypes.c_int64, i32, P(vp)]),
         "lradi_server_submit": (i32, [vp, P(Problem), P(ctypes.c_uint64)]),
         "lradi_server_poll": (i32, [vp, ctypes.c_uint64, P(vp), P(dbl)]),
@@ -355,15 +358,18 @@ class Context:
                          rnorm=s.rnorm) for s in stats], st
 
     @staticmethod
-    def make_problem(A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0):
-        """(Problem struct, keep-alive list) for batch and serving calls."""
+    def make_problem(A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0, M=None, C=None):
+        """(Problem struct, keep-alive list) for batch and serving calls; M, C
+        (HostCsr or None) give the generalized equation."""
         sA = np.ascontiguousarray(shiftsA, dtype=np.float64)
         sB = np.ascontiguousarray(shiftsB, dtype=np.float64)
         assert f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()
         pr = Problem(ctypes.pointer(A.c), ctypes.pointer(B.c), f.data_ptr(), g.data_ptr(), f.shape[1],
                      len(sA), sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                     sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tol))
-        return pr, [A, B, f, g, sA, sB]
+                     sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tol),
+                     ctypes.pointer(M.c) if M is not None else None,
+                     ctypes.pointer(C.c) if C is not None else None)
+        return pr, [A, B, f, g, sA, sB, M, C]
 
     def batch_solve(self, problems, opts: Optional[Opts] = None):
         """problems: list of (A, B, f, g, shiftsA, shiftsB[, tol]); returns
@@ -406,20 +412,29 @@ class Context:
                                    len(D), ctypes.byref(out)), allow_warn=False)
         return out.value
 
-    def solve(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, opts: Optional[Opts] = None):
-        """Algorithm 1 on A X + X B = -f g^T (f, g: FP64 CUDA tensors); B is
-        B itself unless opts.b_is_transposed."""
+    def solve(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, opts: Optional[Opts] = None,
+              M: Optional[HostCsr] = None, C: Optional[HostCsr] = None):
+        """Algorithm 1 on A X + X B = -f g^T (f, g: FP64 CUDA tensors), or on
+        A X C + M X B = -f g^T when M or C is given; B (and C) are the
+        matrices themselves unless opts.b_is_transposed."""
         assert f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()
         r = f.shape[1]
         sA = np.ascontiguousarray(shiftsA, dtype=np.float64)
         sB = np.ascontiguousarray(shiftsB, dtype=np.float64)
         h = ctypes.c_void_p()
         self._sync()
-        st = _check(_lib.lradi_solve(self.h, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(f), _ptr(g),
-                                     r, sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                     sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(sA),
-                                     ctypes.byref(opts) if opts is not None else None,
-                                     ctypes.byref(h)))
+        po = ctypes.byref(opts) if opts is not None else None
+        psA = sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        psB = sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if M is None and C is None:
+            st = _check(_lib.lradi_solve(self.h, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(f), _ptr(g),
+                                         r, psA, psB, len(sA), po, ctypes.byref(h)))
+        else:
+            pM = ctypes.byref(M.c) if M is not None else None
+            pC = ctypes.byref(C.c) if C is not None else None
+            st = _check(_lib.lradi_solve_gen(self.h, ctypes.byref(A.c), ctypes.byref(B.c), pM, pC,
+                                             _ptr(f), _ptr(g), r, psA, psB, len(sA), po,
+                                             ctypes.byref(h)))
         res = Result(h.value, st)
         return res
 
@@ -437,8 +452,8 @@ class Server:
         self.h = h
         self.ctx = ctx
 
-    def submit(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0) -> int:
-        pr, keep = Context.make_problem(A, B, f, g, shiftsA, shiftsB, tol)
+    def submit(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0, M=None, C=None) -> int:
+        pr, keep = Context.make_problem(A, B, f, g, shiftsA, shiftsB, tol, M, C)
         t = ctypes.c_uint64()
         _torch().cuda.synchronize()
         _check(_lib.lradi_server_submit(self.h, ctypes.byref(pr), ctypes.byref(t)))
