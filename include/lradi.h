@@ -342,6 +342,14 @@ int lradi_residual(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B,
                    const double* Z, const double* D, const double* Y, int k,
                    double* rel_true_res);
 
+/* The same for the generalized equation: ||A X C + M X B + f g^T||_2 /
+ * ||f g^T||_2 with X = Z D Y^T; M, C csr (C^T when b_is_transposed) or NULL
+ * for the identity. */
+int lradi_residual_gen(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, const lradi_csr* M,
+                       const lradi_csr* C, int b_is_transposed, const double* f, const double* g,
+                       int r, const double* Z, const double* D, const double* Y, int k,
+                       double* rel_true_res);
+
 #ifdef __cplusplus
 }
 #endif

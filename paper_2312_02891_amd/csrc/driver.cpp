@@ -31,7 +31,8 @@ void csr_union(int n, const int32_t* prp, const int32_t* pci, const double* pv, 
                std::vector<int32_t>& uci, std::vector<double>& upv, std::vector<double>& uqv);
 int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
                   const double* f, const double* g, int r, const double* Z, const double* gam_d,
-                  const double* Y, int k, int maxit, double* sigma_out);
+                  const double* Y, int k, int maxit, double* sigma_out, const DevCSR* M = nullptr,
+                  const DevCSR* Mt = nullptr, const DevCSR* C = nullptr, const DevCSR* Ct = nullptr);
 
 // ---------------------------------------------------------------------------
 // errors
@@ -1284,33 +1285,54 @@ int lradi_result_time(const lradi_result* r, double* seconds) {
 
 void lradi_result_free(lradi_result* r) { delete r; }
 
-int lradi_residual(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, int b_is_transposed,
-                   const double* f, const double* g, int r, const double* Z, const double* D,
-                   const double* Y, int k, double* rel) {
+int lradi_residual_gen(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const lradi_csr* M,
+                       const lradi_csr* C, int b_is_transposed, const double* f, const double* g, int r,
+                       const double* Z, const double* D, const double* Y, int k, double* rel) {
   if (!c || !A || !B || !f || !g || !rel || (k > 0 && (!Z || !D || !Y)))
     return set_error("lradi_residual: null argument"), LRADI_EINVAL;
   if (r < 1 || r > kMaxR || k < 0) return set_error("lradi_residual: bad r or k"), LRADI_EINVAL;
   LRADI_HIP(hipSetDevice(c->device));
   hipStream_t st = c->stream;
-  DevCSR dA, dAt, dB, dBt;
+  DevCSR dA, dAt, dB, dBt, dM, dMt, dC, dCt;
   LRADI_TRY(upload_pair(A, st, dA, dAt));
   if (b_is_transposed) {
     LRADI_TRY(upload_pair(B, st, dBt, dB));
   } else {
     LRADI_TRY(upload_pair(B, st, dB, dBt));
   }
+  if (M) {
+    if (M->nrows != A->nrows) return set_error("lradi_residual: M size differs from A"), LRADI_EINVAL;
+    LRADI_TRY(upload_pair(M, st, dM, dMt));
+  }
+  if (C) {
+    if (C->nrows != B->nrows) return set_error("lradi_residual: C size differs from B"), LRADI_EINVAL;
+    if (b_is_transposed)
+      LRADI_TRY(upload_pair(C, st, dCt, dC));
+    else
+      LRADI_TRY(upload_pair(C, st, dC, dCt));
+  }
   DevBuf gam;
   LRADI_TRY(gam.alloc(sizeof(double) * std::max(k, 1)));
   if (k > 0) LRADI_HIP(hipMemcpyAsync(gam.p, D, sizeof(double) * k, hipMemcpyHostToDevice, st));
   const int maxit = std::min(2 * k * r + r + 2, 400);
   double sres = 0.0, sfg = 0.0;
-  LRADI_TRY(residual_norm(st, dA, dAt, dB, dBt, f, g, r, Z, gam.as<double>(), Y, k, maxit, &sres));
+  const DevCSR* pM = M ? &dM : nullptr;
+  const DevCSR* pMt = M ? &dMt : nullptr;
+  const DevCSR* pC = C ? &dC : nullptr;
+  const DevCSR* pCt = C ? &dCt : nullptr;
+  LRADI_TRY(residual_norm(st, dA, dAt, dB, dBt, f, g, r, Z, gam.as<double>(), Y, k, maxit, &sres, pM, pMt,
+                          pC, pCt));
   LRADI_TRY(residual_norm(st, dA, dAt, dB, dBt, f, g, r, Z, gam.as<double>(), Y, 0, r + 2, &sfg));
   LRADI_HIP(hipStreamSynchronize(st));
   *rel = (sfg > 0.0) ? sres / sfg : 0.0;
   return LRADI_OK;
 }
 
+int lradi_residual(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, int b_is_transposed,
+                   const double* f, const double* g, int r, const double* Z, const double* D,
+                   const double* Y, int k, double* rel) {
+  return lradi_residual_gen(c, A, B, nullptr, nullptr, b_is_transposed, f, g, r, Z, D, Y, k, rel);
+}
 
 // ---------------------------------------------------------------------------
 // serving

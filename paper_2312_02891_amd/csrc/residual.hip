@@ -179,14 +179,15 @@ struct Dev {
 
 int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
                   const double* f, const double* g, int r, const double* Z, const double* gam_d,
-                  const double* Y, int k, int maxit, double* sigma_out) {
+                  const double* Y, int k, int maxit, double* sigma_out, const DevCSR* M,
+                  const DevCSR* Mt, const DevCSR* C, const DevCSR* Ct) {
   const int n = A.n, m = B.n;
   const int J = maxit;
   if (k * r > kMaxCoef) return set_error("lradi_residual: k*r above %d", kMaxCoef), LRADI_EINVAL;
   Dev dv;
   dv.st = st;
   const int nwg_max = (std::max(n, m) + kRows - 1) / kRows;
-  DevBuf Ub, Vb, tn, tn2, tm, tm2, coef, scal;
+  DevBuf Ub, Vb, tn, tn2, tn3, tm, tm2, tm3, coef, scal;
   LRADI_TRY(dv.part.alloc(sizeof(double) * (size_t)nwg_max * std::max(kMaxCoef, J + 2)));
   LRADI_TRY(Ub.alloc(sizeof(double) * (size_t)n * (J + 1)));
   LRADI_TRY(Vb.alloc(sizeof(double) * (size_t)m * (J + 2)));
@@ -194,6 +195,8 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   LRADI_TRY(tn2.alloc(sizeof(double) * n));
   LRADI_TRY(tm.alloc(sizeof(double) * m));
   LRADI_TRY(tm2.alloc(sizeof(double) * m));
+  if (M) LRADI_TRY(tn3.alloc(sizeof(double) * n));
+  if (C) LRADI_TRY(tm3.alloc(sizeof(double) * m));
   LRADI_TRY(coef.alloc(sizeof(double) * (3 * kMaxCoef + 2 * (J + 2))));
   // scalars: [0] nrm2, [1..J+1] alpha, [J+2..2J+2] beta, [2J+3] sigma
   LRADI_TRY(scal.alloc(sizeof(double) * (2 * J + 8)));
@@ -211,25 +214,46 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   const size_t sZ = (size_t)n * r, sY = (size_t)m * r;
   auto nb256 = [](int x) { return dim3((x + 255) / 256); };
 
-  // R v -> p (n-vector); p must not be tn or tm
+  // R = A Z D Y^T C + M Z D Y^T B + f g^T (M, C = I when null)
+  // R v -> p (n-vector); p must not be tn, tn3, tm or tm3
   auto apply_R = [&](const double* v, double* p) -> int {
-    LRADI_TRY(dv.proj(Y, k, m, r, sY, v, c1));          // c1 = Y^T v
+    if (C) {
+      LRADI_TRY(dv.spmv(*C, v, tm3.as<double>(), 0));   // tm3 = C v
+      LRADI_TRY(dv.proj(Y, k, m, r, sY, tm3.as<double>(), c1));  // c1 = Y^T C v
+    } else {
+      LRADI_TRY(dv.proj(Y, k, m, r, sY, v, c1));        // c1 = Y^T v
+    }
     LRADI_TRY(dv.spmv(B, v, tm.as<double>(), 0));       // tm = B v
     LRADI_TRY(dv.proj(Y, k, m, r, sY, tm.as<double>(), c2));  // c2 = Y^T B v
     LRADI_TRY(dv.proj(g, 1, m, r, sY, v, c3));          // c3 = g^T v
     LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c1, 1.0, 0.0, tn.as<double>()));  // Z D c1
     LRADI_TRY(dv.spmv(A, tn.as<double>(), p, 0));       // p = A Z D c1
-    LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c2, 1.0, 1.0, p));
+    if (M) {
+      LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c2, 1.0, 0.0, tn3.as<double>()));
+      LRADI_TRY(dv.spmv(*M, tn3.as<double>(), p, 1));   // p += M Z D c2
+    } else {
+      LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c2, 1.0, 1.0, p));
+    }
     LRADI_TRY(dv.expand(f, 1, n, r, sZ, nullptr, c3, 1.0, 1.0, p));
     return LRADI_OK;
   };
-  // R^T u -> q (m-vector); q must not be tn2 or tm2
+  // R^T u -> q (m-vector); q must not be tn2, tn3, tm2 or tm3
   auto apply_Rt = [&](const double* u, double* q) -> int {
     LRADI_TRY(dv.spmv(At, u, tn2.as<double>(), 0));     // A^T u
     LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn2.as<double>(), c1));  // Z^T A^T u
-    LRADI_TRY(dv.proj(Z, k, n, r, sZ, u, c2));          // Z^T u
+    if (M) {
+      LRADI_TRY(dv.spmv(*Mt, u, tn3.as<double>(), 0));  // M^T u
+      LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn3.as<double>(), c2));  // Z^T M^T u
+    } else {
+      LRADI_TRY(dv.proj(Z, k, n, r, sZ, u, c2));        // Z^T u
+    }
     LRADI_TRY(dv.proj(f, 1, n, r, sZ, u, c3));          // f^T u
-    LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c1, 1.0, 0.0, q));
+    if (C) {
+      LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c1, 1.0, 0.0, tm3.as<double>()));
+      LRADI_TRY(dv.spmv(*Ct, tm3.as<double>(), q, 0));  // q = C^T Y D c1
+    } else {
+      LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c1, 1.0, 0.0, q));
+    }
     LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c2, 1.0, 0.0, tm2.as<double>()));
     LRADI_TRY(dv.spmv(Bt, tm2.as<double>(), q, 1));
     LRADI_TRY(dv.expand(g, 1, m, r, sY, nullptr, c3, 1.0, 1.0, q));

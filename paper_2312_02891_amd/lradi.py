@@ -128,6 +128,8 @@ def _load():
         "lradi_profile_reset": (i32, [vp]),
         "lradi_residual": (i32, [vp, P(Csr), P(Csr), i32, vp, vp, i32, vp, P(dbl), vp, i32,
                                  P(dbl)]),
+        "lradi_residual_gen": (i32, [vp, P(Csr), P(Csr), P(Csr), P(Csr), i32, vp, vp, i32, vp, P(dbl),
+                                     vp, i32, P(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -388,16 +390,21 @@ class Context:
         _check(st)
         return results, st
 
-    def residual(self, A: HostCsr, B: HostCsr, f, g, result: "Result", b_is_transposed=False):
-        """True ||A X + X B + f g^T||_2 / ||f g^T||_2 of a solve result
-        (lradi_residual on the result's device factors)."""
+    def residual(self, A: HostCsr, B: HostCsr, f, g, result: "Result", b_is_transposed=False,
+                 M: Optional[HostCsr] = None, C: Optional[HostCsr] = None):
+        """True ||A X C + M X B + f g^T||_2 / ||f g^T||_2 of a solve result
+        (M = C = I unless given; lradi_residual_gen on the result's device
+        factors)."""
         D = np.ascontiguousarray(result.gammas(), dtype=np.float64)
         out = ctypes.c_double()
         self._sync()
-        _check(_lib.lradi_residual(self.h, ctypes.byref(A.c), ctypes.byref(B.c), int(bool(b_is_transposed)),
-                                   _ptr(f), _ptr(g), f.shape[1], ctypes.c_void_p(result.Zptr),
-                                   D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                   ctypes.c_void_p(result.Yptr), result.k, ctypes.byref(out)),
+        _check(_lib.lradi_residual_gen(self.h, ctypes.byref(A.c), ctypes.byref(B.c),
+                                       ctypes.byref(M.c) if M is not None else None,
+                                       ctypes.byref(C.c) if C is not None else None,
+                                       int(bool(b_is_transposed)), _ptr(f), _ptr(g), f.shape[1],
+                                       ctypes.c_void_p(result.Zptr),
+                                       D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.c_void_p(result.Yptr), result.k, ctypes.byref(out)),
                allow_warn=False)
         return out.value
 

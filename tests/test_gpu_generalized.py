@@ -80,6 +80,37 @@ def test_generalized_matches_oracle(L, ctx, name, precision):
         assert row[8] == pytest.approx(u, rel=1e-12) and row[9] == pytest.approx(v, rel=1e-12)
 
 
+def test_generalized_true_residual_matches_oracle(L, ctx):
+    """lradi_residual_gen (Golub-Kahan-Lanczos through the factors, with M
+    and C) equals the oracle's exact low-rank evaluation, for the converged
+    solution and for arbitrary factors with a large residual."""
+    P = WL.GEN_SMALL
+    HA, HB, HM, HC, A, B, M, C, f, g, pA, pB = setup(P, L)
+    fd, gd = to_dev(f), to_dev(g)
+    res = ctx.solve(HA, HB, fd, gd, pA, pB, L.default_opts(tol=P.tol), M=HM, C=HC)
+    gpu = ctx.residual(HA, HB, fd, gd, res, M=HM, C=HC)
+    Z, d, Y = res.factors()
+    ora = OF.lowrank_residual_norm(A, B, f, g, Z, d, Y, M=M, C=C) / OF.lowrank_product_norm(f, g)
+    say("  residual gpu", gpu, "oracle", ora)
+    assert gpu == pytest.approx(ora, rel=1e-6)
+    rng = np.random.default_rng(9)
+    k, r = 3, P.r
+    Zs, Ys = rng.standard_normal((k, P.A.n, r)), rng.standard_normal((k, P.B.n, r))
+    gam = rng.uniform(1.0, 40.0, k)
+    fake = type("R", (), {})()
+    import torch
+    Zd = torch.from_numpy(np.ascontiguousarray(Zs)).cuda()
+    Yd = torch.from_numpy(np.ascontiguousarray(Ys)).cuda()
+    fake.Zptr, fake.Yptr, fake.k = Zd.data_ptr(), Yd.data_ptr(), k
+    fake.gammas = lambda: gam
+    gpu2 = ctx.residual(HA, HB, fd, gd, fake, M=HM, C=HC)
+    Zc = np.concatenate(list(Zs), axis=1)
+    Yc = np.concatenate(list(Ys), axis=1)
+    ora2 = OF.lowrank_residual_norm(A, B, f, g, Zc, np.repeat(gam, r), Yc, M=M, C=C) / \
+        OF.lowrank_product_norm(f, g)
+    assert gpu2 == pytest.approx(ora2, rel=1e-9)
+
+
 def test_exact_tolerance_reproduces_direct_iteration(L, ctx):
     """Inner solves to 1e-12 relative: every step's computed residual equals
     the oracle's and the norms ||M z_k||, ||C^T y_k|| recorded on the device
