@@ -49,7 +49,7 @@ extern "C" {
 #define LRADI_WNOCONV 1        /* kmax outer steps without reaching tau          */
 #define LRADI_WINNER 2         /* some inner solve stopped at its iteration cap   */
 
-/* ---- tolerance selections (Sec. 3.3) ---------------------------------- */
+/* ---- tolerance selections (Sec. 3.2) ---------------------------------- */
 #define LRADI_SEL_RELATIVE 0   /* delta^A = rho*||w||, delta^B = rho*||t||        */
 #define LRADI_SEL_FIXED 1      /* delta^A = delta^B = delta_fixed (Table 2 "fixed") */
 #define LRADI_SEL_MID 2        /* eq. (simple_tols)                               */

@@ -12,6 +12,8 @@ Modules:
   convdiff    CSR of the upwind convection-diffusion coefficient matrices
   fadi        LR-ADI with direct solves, residual and difference norms,
               dense Bartels-Stewart reference
-  controller  dynamic inner tolerances of Sec. 3.3
+  controller  dynamic inner tolerances of Sec. 3.2
+  lyap        Lyapunov special case (B = A^T, C = M^T, g = f), one solve
+              per step, written in its own residual-factor form
   gmres_ref   a plain block GMRES used to pin block-Krylov test cases
 """

@@ -1,5 +1,5 @@
 """Oracle (test infrastructure only): the dynamic inner-solve tolerances of
-Sec. 3.3 for the inexact LR-ADI iteration (Algorithm 1).
+Sec. 3.2 for the inexact LR-ADI iteration (Algorithm 1).
 
 Quantities at outer step k (1-based), all in FP64:
   nw = ||w_{k-1}||, nt = ||t_{k-1}||   spectral norms of the residual factors
@@ -7,7 +7,7 @@ Quantities at outer step k (1-based), all in FP64:
   eps                                   absolute residual-gap budget
   kmax, xi                              step budget and safeguard constant
 
-Selections (which point of the admissible region, Sec. 3.3.3):
+Selections (which point of the admissible region, Sec. 3.2.3):
   "relative": delta^A = rho*nw, delta^B = rho*nt (an exact-tolerance
               baseline, not from the paper)
   "fixed":    delta^A = delta^B = const (the "fixed" rows of Table 2)
@@ -25,7 +25,7 @@ from __future__ import annotations
 import math
 
 # bound on the constant c_k of Theorem 3 obtained from the Crouzeix-Palencia
-# estimate of ||C_k|| (Sec. 3.3.1)
+# estimate of ||C_k|| (Sec. 3.2.1)
 C_BOUND = 2.0 + math.sqrt(2.0)
 
 
@@ -78,6 +78,19 @@ def select_tightB(eh: float, nw: float, nt: float, dmin: float, dmax: float):
     return dA, dB
 
 
+def select_sym(eh: float, nw: float, nt: float, dmin: float, dmax: float):
+    """Equal tolerances delta^A = delta^B = delta, the largest equal pair on
+    the boundary of the condition of eq. (ADI_relax1_prak)/(ADI_relax2_prak):
+    delta (||t|| + ||w||) + 2 delta^2 = eh, the positive root of that
+    quadratic, clamped as in eq. (bound_tols).  A single inner solve that
+    serves both sides (the Lyapunov case B = A^T, g = f of the related
+    equations of Sec. 3.2.4) needs exactly such a pair."""
+    s = nw + nt
+    d = (-s + math.sqrt(s * s + 8.0 * eh)) / 4.0
+    d = max(min(d, dmax), dmin)
+    return d, d
+
+
 def tolerances(selection: str, k: int, nw: float, nt: float, u: float, v: float,
                eps: float, kmax: int = 50, xi: float = 1.0, dmin: float = 5e-10,
                dmax: float = 0.1, backlook: bool = True, fixed: float = 5e-10,
@@ -110,6 +123,8 @@ def tolerances(selection: str, k: int, nw: float, nt: float, u: float, v: float,
         dA, dB = select_tightA(eh, nw, nt, dmin, dmax)
     elif selection == "tightB":
         dA, dB = select_tightB(eh, nw, nt, dmin, dmax)
+    elif selection == "sym":
+        dA, dB = select_sym(eh, nw, nt, dmin, dmax)
     else:
         raise ValueError(selection)
     return dA / s, dB * s

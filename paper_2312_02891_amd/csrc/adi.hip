@@ -1,7 +1,7 @@
 // Outer LR-ADI kernels: setup (rescaling of f, g and ||f g^T||), the
 // tolerance controller before each step, the residual-factor update and
 // append after the inner solves, and the norm / stop test (Algorithm 1,
-// eqs. (lradi_basic), (adi_resexact), Sec. 3.3).
+// eqs. (lradi_basic), (adi_resexact), Sec. 3.2).
 //
 // A batch of problems maps problem p to inner systems 2p (A side: W, Z) and
 // 2p+1 (B side: T, Y).  Row kernels reuse the inner solver's row table.
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup_gram(const SysDesc* __restri
 }
 
 // Arm the inner systems of problem P for outer step C.k + 1: tolerances of
-// Sec. 3.3 from (||w||, ||t||, u, v), the step's shifts, the solution slots
+// Sec. 3.2 from (||w||, ||t||, u, v), the step's shifts, the solution slots
 // z_{k+1}, y_{k+1}, and fresh inner control blocks (Algorithm 1 loop body).
 __device__ inline void arm_step(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& B) {
   CtlParams cp;

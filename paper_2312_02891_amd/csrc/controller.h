@@ -1,5 +1,5 @@
 // Dynamic inner-solve tolerances of the inexact LR-ADI iteration
-// (Sec. 3.3): eqs. (ADI_relax1_prak), (ADI_relax2_prak), (bound_tols),
+// (Sec. 3.2): eqs. (ADI_relax1_prak), (ADI_relax2_prak), (bound_tols),
 // (simple_tols), (one_side) and the gap recursion (upd_resgap).
 // __host__ __device__ so that the host self-test runs the same code.
 #pragma once
@@ -19,7 +19,7 @@ struct CtlParams {
 };
 
 // c = 2 + sqrt(2): bound on max(||C_k(A)||, ||C_k(B)||) + 1 from the
-// Crouzeix-Palencia estimate (Sec. 3.3.1).
+// Crouzeix-Palencia estimate (Sec. 3.2.1).
 LRADI_HD inline double ctl_c() { return 2.0 + sqrt(2.0); }
 
 // eps_hat_k of eq. (ADI_relax1_prak) (backlook = 0) or eq. (ADI_relax2_prak)

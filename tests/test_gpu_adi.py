@@ -70,7 +70,7 @@ def test_config1_exact_tolerance_fp64(L, ctx):
 
 @pytest.mark.parametrize("sel", ["mid", "tightA", "tightB", "fixed"])
 def test_small_problem_dynamic_tolerances(L, ctx, sel):
-    """Relaxed (Sec. 3.3) and fixed inner tolerances on a 2-D problem with
+    """Relaxed (Sec. 3.2) and fixed inner tolerances on a 2-D problem with
     r = 3: converged, true residual below tau, X within 1e-6 of the exact
     ADI iterate at the same step."""
     say("adi small", sel)

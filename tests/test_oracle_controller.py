@@ -1,4 +1,4 @@
-"""Pins of the oracle's inner-tolerance controller (Sec. 3.3)."""
+"""Pins of the oracle's inner-tolerance controller (Sec. 3.2)."""
 import math
 import os
 
@@ -11,7 +11,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def test_norm_bound_constant():
-    """Sec. 3.3.1: c = 2 + sqrt(2) (Crouzeix-Palencia constant 1 + sqrt(2) plus 1);
+    """Sec. 3.2.1: c = 2 + sqrt(2) (Crouzeix-Palencia constant 1 + sqrt(2) plus 1);
     with kmax = 50 the no-back-looking threshold is eps / 1165.685."""
     assert C.C_BOUND == pytest.approx(3.414213562373095, rel=1e-15)
     assert 2 * C.C_BOUND ** 2 * 50 == pytest.approx(1165.685424949238, rel=1e-14)
@@ -158,3 +158,36 @@ def test_balance_keeps_unbalanced_factors_admissible():
     assert dB == dmin and C.gap_lhs(dA, dB, nw, nt) > 10 * eh
     dA, dB = C.tolerances("mid", k, nw, nt, 0.0, 0.0, eps, dmin=dmin, balance=True)
     assert C.gap_lhs(dA, dB, nw, nt) <= eh * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sym_selection_is_largest_equal_pair(seed):
+    """The symmetric selection lies on the boundary of the admissibility
+    condition (left-hand side == eps_hat), and bisection on that left-hand
+    side over equal pairs finds the same delta (brute force, independent of
+    the closed-form root)."""
+    rng = np.random.default_rng(seed)
+    nw, nt = 10 ** rng.uniform(-4, 1), 10 ** rng.uniform(-4, 1)
+    eh = 10 ** rng.uniform(-14, -9)
+    d, d2 = C.select_sym(eh, nw, nt, 1e-300, 1e300)
+    assert d == d2
+    assert C.gap_lhs(d, d, nw, nt) == pytest.approx(eh, rel=1e-12)
+    lo, hi = 0.0, eh / (nw + nt) * 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if C.gap_lhs(mid, mid, nw, nt) <= eh:
+            lo = mid
+        else:
+            hi = mid
+    assert d == pytest.approx(lo, rel=1e-12)
+
+
+def test_sym_selection_clamps_and_dispatch():
+    assert C.select_sym(1e6, 1e-3, 1e-3, 5e-10, 0.1) == (0.1, 0.1)
+    assert C.select_sym(0.0, 1.0, 1.0, 5e-10, 0.1) == (5e-10, 5e-10)
+    eh = C.eps_hat_2(1e-8, 50, 3, 1e-12, 2e-12)
+    dA, dB = C.tolerances("sym", 3, 0.02, 0.5, 1e-12, 2e-12, 1e-8)
+    assert (dA, dB) == C.select_sym(eh, 0.02, 0.5, 5e-10, 0.1)
+    # with ||w|| = ||t|| the balanced frame changes nothing
+    assert C.tolerances("sym", 3, 0.3, 0.3, 0.0, 0.0, 1e-8, balance=True) == \
+        C.tolerances("sym", 3, 0.3, 0.3, 0.0, 0.0, 1e-8)
