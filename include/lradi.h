@@ -55,6 +55,9 @@ extern "C" {
 #define LRADI_SEL_MID 2        /* eq. (simple_tols)                               */
 #define LRADI_SEL_TIGHT_A 3    /* eq. (one_side): delta^A = delta_min              */
 #define LRADI_SEL_TIGHT_B 4    /* mirror of eq. (one_side): delta^B = delta_min    */
+#define LRADI_SEL_SYM 5        /* delta^A = delta^B: the largest equal pair on the
+                                  boundary of eq. (ADI_relax1_prak)/(ADI_relax2_prak),
+                                  clamped by eq. (bound_tols)                     */
 
 /* ---- arithmetic of the inner Krylov solves ---------------------------- */
 #define LRADI_FP64 0           /* basis, SpMM and projections in FP64             */
@@ -241,6 +244,23 @@ int lradi_solve_gen(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, cons
                     const double* shiftsA, const double* shiftsB, int nshifts,
                     const lradi_opts* opts, lradi_result** out);
 
+/* The Lyapunov case of eq. (gsylv) named with the related equations of
+ * Sec. 3.2.4: A X M^T + M X A^T = -f f^T, i.e. B = A^T, C = M^T, g = f.
+ * With alpha_k = beta_k = shifts[k] (added to A: (A + p_k M) z_k = w_{k-1})
+ * the B-side system of eq. (lradi_g) is the A-side system and t_0 = w_0, so
+ * one inner solve per step serves both sides: y_k = z_k, t_k = w_k,
+ * gamma_k = -2 p_k and X = Z D Z^T.  The inner tolerance of a step is
+ * min(delta^A, delta^B) of opts->selection (LRADI_SEL_SYM gives the largest
+ * equal admissible pair); since r^B = r^A the gap recursion of
+ * eq. (upd_resgap) gives u = v.  A: n x n csr; M: n x n csr or NULL
+ * (identity); f: device, n x r row-major (not modified); shifts: host,
+ * nshifts.  opts->b_is_transposed and opts->rescale have no effect (f and g
+ * are one matrix).  The result's Y factor is Z (same device pointer, m = n);
+ * its history rows repeat the A-side values in the B-side columns, with 0
+ * B-side inner steps.  Errors as lradi_solve. */
+int lradi_solve_lyap(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, const double* f, int r,
+                     const double* shifts, int nshifts, const lradi_opts* opts, lradi_result** out);
+
 /* One Sylvester problem for lradi_batch_solve and the serving loop. */
 typedef struct {
   const lradi_csr* A;      /* n x n (host or device)                           */
@@ -259,6 +279,10 @@ typedef struct {
                               NULL for M = I                                  */
   const lradi_csr* C;      /* m x m (C^T when opts->b_is_transposed), or NULL
                               for C = I                                       */
+  int32_t lyapunov;        /* nonzero: the Lyapunov case A X M^T + M X A^T =
+                              -f f^T (B = A^T, C = M^T, g = f, shiftsB =
+                              shiftsA; B, g, shiftsB, C are ignored and may
+                              be NULL): one inner solve per step, Y = Z     */
 } lradi_problem;
 
 /* Algorithm 1 on nprob independent problems of uneven n, m, r advanced

@@ -11,6 +11,9 @@ struct AdiDesc {
   int n, m, r, kmax, nshifts;
   int selection, backlook, paper_abs, rescale;  // rescale 2: controller in the balanced frame
   int setup;              // 1: the setup kernels initialise this problem
+  int sym;                // Lyapunov case B = A^T, C = M^T, g = f, equal shifts:
+                          // system 2p+1 is an idle mirror (no workgroups), the
+                          // A side's solve serves both sides, T = W, Yf = Zf
   double tol, eps_in, delta_min, delta_max, xi, delta_fixed, rho;
   const double* shiftsA;  // device, nshifts
   const double* shiftsB;  // device, nshifts

@@ -4,7 +4,9 @@
 // eqs. (lradi_basic), (adi_resexact), Sec. 3.2).
 //
 // A batch of problems maps problem p to inner systems 2p (A side: W, Z) and
-// 2p+1 (B side: T, Y).  Row kernels reuse the inner solver's row table.
+// 2p+1 (B side: T, Y).  Row kernels reuse the inner solver's row table.  In
+// the Lyapunov case (B = A^T, C = M^T, g = f, equal shifts) system 2p+1 owns
+// no workgroups and stays finished; the A side's factors stand for both.
 #include "adi.h"
 #include "controller.h"
 #include "small.h"
@@ -137,11 +139,13 @@ __device__ inline void arm_step(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& 
   cp.balance = P.rescale == 2;
   double dA, dB;
   ctl_tolerances(cp, C.k + 1, C.nw, C.nt, C.u, C.v, &dA, &dB);
+  // one solve serves both sides of a Lyapunov problem: it must meet both
+  if (P.sym) dA = dB = fmin(dA, dB);
   C.dA = dA;
   C.dB = dB;
   const int js = C.k % P.nshifts;
   SysCtl* sides[2] = {&A, &B};
-  for (int side = 0; side < 2; ++side) {
+  for (int side = 0; side < (P.sym ? 1 : 2); ++side) {
     SysCtl& S = *sides[side];
     S.Z = side ? P.Yf + (size_t)C.k * P.m * P.r : P.Zf + (size_t)C.k * P.n * P.r;
     S.shift = side ? P.shiftsB[js] : P.shiftsA[js];
@@ -185,7 +189,12 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ 
   const SysDesc& DB = d[2 * p + 1];
   const int R = P.r;
   reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, Gf);
-  reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, Gg);
+  if (P.sym) {
+    for (int e = threadIdx.x; e < R * R; e += kTPB) Gg[e] = Gf[e];
+    __syncthreads();
+  } else {
+    reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, Gg);
+  }
   if (threadIdx.x == 0) {
     AdiCtl& C = ac[p];
     const double nf = sqrt(fmax(lambda_max_sym(Gf, R), 0.0));
@@ -346,8 +355,16 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
   const int R = P.r;
   reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, GW);
   reduce_rows(DA.partS, DA.nwg, 64, R * R, red_lds, GZ);
-  reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, GT);
-  reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
+  if (P.sym) {  // t_k = w_k, y_k = z_k
+    for (int e = threadIdx.x; e < R * R; e += kTPB) {
+      GT[e] = GW[e];
+      GY[e] = GZ[e];
+    }
+    __syncthreads();
+  } else {
+    reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, GT);
+    reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
+  }
   if (threadIdx.x == 0) {
     const int k = C.k;
     const int js = k % P.nshifts;
@@ -357,7 +374,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     const double nz = sqrt(fmax(lambda_max_sym(GZ, R), 0.0));
     const double ny = sqrt(fmax(lambda_max_sym(GY, R), 0.0));
     const double res = sqrt(fmax(lambda_max_prod(GW, GT, R), 0.0));
-    const double rA = A.rnorm, rB = B.rnorm;
+    const double rA = A.rnorm, rB = P.sym ? A.rnorm : B.rnorm;
     double u = C.u, v = C.v;
     ctl_update_gap(&u, &v, gamma, nz, ny, rA, rB);
     double* h = P.hist + (size_t)k * kHistCols;
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     h[4] = rA;
     h[5] = rB;
     h[6] = A.steps;
-    h[7] = B.steps;
+    h[7] = P.sym ? 0 : B.steps;
     h[8] = u;
     h[9] = v;
     h[10] = C.nw;

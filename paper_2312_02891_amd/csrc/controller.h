@@ -1,6 +1,7 @@
 // Dynamic inner-solve tolerances of the inexact LR-ADI iteration
 // (Sec. 3.2): eqs. (ADI_relax1_prak), (ADI_relax2_prak), (bound_tols),
-// (simple_tols), (one_side) and the gap recursion (upd_resgap).
+// (simple_tols), (one_side), the equal pair on the boundary of the first
+// two, and the gap recursion (upd_resgap).
 // __host__ __device__ so that the host self-test runs the same code.
 #pragma once
 
@@ -64,6 +65,11 @@ LRADI_HD inline void ctl_tolerances(const CtlParams& p, int k, double nw, double
   } else if (p.selection == LRADI_SEL_TIGHT_B) {
     b = lo;
     a = fmax(fmin((eh - b * nw) / (2.0 * b + nt), hi), lo);
+  } else if (p.selection == LRADI_SEL_SYM) {
+    // a = b on the boundary: 2 a^2 + a (||w|| + ||t||) = eh, positive root
+    const double sw = nw + nt;
+    a = fmax(fmin((-sw + sqrt(sw * sw + 8.0 * eh)) / 4.0, hi), lo);
+    b = a;
   } else {  // LRADI_SEL_MID: eq. (simple_tols) as printed
     a = fmax(0.5 * (fmin(hi, eh / nt) - lo), lo);
     b = fmax(fmin((eh - a * nt) / (2.0 * a + nw), hi), lo);

@@ -202,8 +202,10 @@ struct lradi_result {
   int n = 0, m = 0, r = 0, k = 0, kmax = 0;
   int status = LRADI_OK;
   double rel_res = 0.0, norm_fg = 0.0, seconds = 0.0;
+  bool sym = false;  // Lyapunov case: Y is Z (Yf unallocated)
   DevBuf Zf, Yf;
   std::vector<double> gam, hist;
+  const DevBuf& Y() const { return sym ? Zf : Yf; }
 };
 
 namespace lradi {
@@ -356,6 +358,23 @@ struct SysWork {
     return LRADI_OK;
   }
 
+  // the idle B side of a Lyapunov problem: no workgroups, no buffers, never
+  // armed (its descriptor only keeps the table's per-problem pairing)
+  void init_mirror(const SysWork& a) {
+    d = SysDesc{};
+    d.n = a.d.n;
+    d.r = a.d.r;
+    d.m = a.d.m;
+    d.nwg = 0;
+    d.rows_per_wg = a.d.rows_per_wg;
+    d.precision = a.d.precision;
+    d.max_inner = a.d.max_inner;
+    d.pstride = a.d.pstride;
+    d.spmm_lanes = a.d.spmm_lanes;
+    c = SysCtl{};
+    c.phase = PH_FINISHED;
+  }
+
   // pick the shifted-product tiling (V's first two blocks serve as scratch;
   // the solver overwrites them before use)
   int tune(lradi_ctx* ctx, const DevCSR& A, int policy) {
@@ -410,7 +429,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
     const int lanes = 1 << g;
     t.b.spoff[g] = (int)t.hsp.size();
     for (int s = 0; s < nsys; ++s) {
-      if (ws[s]->d.spmm_lanes != lanes) continue;
+      if (ws[s]->d.spmm_lanes != lanes || ws[s]->d.nwg == 0) continue;
       if (ws[s]->d.r % lanes != 0) return set_error("lanes per row must divide r"), LRADI_EINVAL;
       const int tr = spmm_tile_rows(lanes);
       const int tiles = (ws[s]->d.n + tr - 1) / tr;
@@ -635,7 +654,7 @@ int check_opts(const lradi_opts& o) {
   if (o.max_inner < 1) return set_error("max_inner must be >= 1"), LRADI_EINVAL;
   if (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER)
     return set_error("unknown precision"), LRADI_EINVAL;
-  if (o.selection < LRADI_SEL_RELATIVE || o.selection > LRADI_SEL_TIGHT_B)
+  if (o.selection < LRADI_SEL_RELATIVE || o.selection > LRADI_SEL_SYM)
     return set_error("unknown selection"), LRADI_EINVAL;
   if (!(o.delta_min > 0.0) || !(o.delta_max >= o.delta_min))
     return set_error("need 0 < delta_min <= delta_max"), LRADI_EINVAL;
@@ -723,12 +742,21 @@ struct Prob {
   std::unique_ptr<lradi_result> res;
   AdiCtl hc{};
   bool set_up = false;
+  bool sym = false;  // Lyapunov case: wb is an idle mirror, T = W, Y = Z
   std::chrono::steady_clock::time_point t0;
 };
 
 // Validate and upload one problem (transposing B on the host when needed).
-int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool copy_rhs, Prob& q) {
+int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool copy_rhs, Prob& q) {
   hipStream_t st = c->stream;
+  lradi_problem P = P0;
+  q.sym = P.lyapunov != 0;
+  if (q.sym) {  // B = A^T, C = M^T, g = f, alpha = beta: only the A side is stored
+    P.B = P.A;
+    P.g = P.f;
+    P.shiftsB = P.shiftsA;
+    P.C = nullptr;
+  }
   if (!P.A || !P.B || !P.f || !P.g || !P.shiftsA || !P.shiftsB)
     return set_error("problem: null argument"), LRADI_EINVAL;
   if (P.r < 1 || P.r > kMaxR) return set_error("problem: r must be in 1..%d", kMaxR), LRADI_EINVAL;
@@ -744,7 +772,9 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
     LRADI_TRY(q.A.upload_pencil(P.A, P.M, st, f32));
   else
     LRADI_TRY(q.A.upload(P.A, st, f32));
-  if (o.b_is_transposed) {
+  if (q.sym) {
+    // no B side
+  } else if (o.b_is_transposed) {
     if (P.C)
       LRADI_TRY(q.Bt.upload_pencil(P.B, P.C, st, f32));
     else
@@ -766,18 +796,22 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
     LRADI_HIP(hipStreamSynchronize(st));
   }
   q.n = q.A.n;
-  q.m = q.Bt.n;
+  q.m = q.sym ? q.A.n : q.Bt.n;
   q.r = P.r;
   q.nshifts = P.nshifts;
   q.tol = tol;
   const size_t n = q.n, m = q.m, r = q.r, K = o.kmax;
   if (copy_rhs) {
     LRADI_TRY(q.fown.alloc(sizeof(double) * n * r));
-    LRADI_TRY(q.gown.alloc(sizeof(double) * m * r));
     LRADI_HIP(hipMemcpyAsync(q.fown.p, P.f, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
-    LRADI_HIP(hipMemcpyAsync(q.gown.p, P.g, sizeof(double) * m * r, hipMemcpyDeviceToDevice, st));
     q.f = q.fown.as<double>();
-    q.g = q.gown.as<double>();
+    if (q.sym) {
+      q.g = q.f;
+    } else {
+      LRADI_TRY(q.gown.alloc(sizeof(double) * m * r));
+      LRADI_HIP(hipMemcpyAsync(q.gown.p, P.g, sizeof(double) * m * r, hipMemcpyDeviceToDevice, st));
+      q.g = q.gown.as<double>();
+    }
   } else {
     q.f = P.f;
     q.g = P.g;
@@ -787,10 +821,11 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
   q.res->m = q.m;
   q.res->r = q.r;
   q.res->kmax = o.kmax;
+  q.res->sym = q.sym;
   LRADI_TRY(q.res->Zf.alloc(sizeof(double) * K * n * r));
-  LRADI_TRY(q.res->Yf.alloc(sizeof(double) * K * m * r));
+  if (!q.sym) LRADI_TRY(q.res->Yf.alloc(sizeof(double) * K * m * r));
   LRADI_TRY(q.W.alloc(sizeof(double) * n * r));
-  LRADI_TRY(q.T.alloc(sizeof(double) * m * r));
+  if (!q.sym) LRADI_TRY(q.T.alloc(sizeof(double) * m * r));
   LRADI_TRY(q.shA.alloc(sizeof(double) * P.nshifts));
   LRADI_TRY(q.shB.alloc(sizeof(double) * P.nshifts));
   LRADI_TRY(q.gam.alloc(sizeof(double) * K));
@@ -799,9 +834,13 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
   LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   const double fl = floor_for(o);
   LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
-  LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
   LRADI_TRY(q.wa.tune(c, q.A, o.spmm_lanes));
-  LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
+  if (q.sym) {
+    q.wb.init_mirror(q.wa);
+  } else {
+    LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
+    LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
+  }
   LRADI_TRY(q.done.init());
   LRADI_HIP(hipStreamSynchronize(st));
   return LRADI_OK;
@@ -809,7 +848,8 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, bool co
 
 // Device bytes one problem holds while in flight: matrices, right-hand
 // sides, residual and solution factors, and its two inner workspaces.
-size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lradi_opts& o) {
+size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lradi_opts& o,
+                      bool sym = false) {
   const size_t tsz = o.precision == LRADI_FP64 ? 8 : 4;
   const size_t K = o.kmax, mm = o.restart;
   auto mat = [&](int64_t nrow, int64_t nnz) {
@@ -820,6 +860,7 @@ size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lra
     return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + 2 * kPS) * 8 +
            (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 12 * 256 + 4096;
   };
+  if (sym) return mat(n, nnzA) + (size_t)n * r * 8 * (2 + K) + K * (kHistCols + 1) * 8 + inner(n);
   return mat(n, nnzA) + mat(m, nnzB) + (size_t)(n + m) * r * 8 * (3 + K) + K * (kHistCols + 1) * 8 +
          inner(n) + inner(m);
 }
@@ -866,6 +907,7 @@ struct Engine {
       ad.paper_abs = o.paper_abs;
       ad.rescale = o.rescale;
       ad.setup = q->set_up ? 0 : 1;
+      ad.sym = q->sym ? 1 : 0;
       any_setup = any_setup || !q->set_up;
       ad.tol = q->tol;
       ad.eps_in = o.eps;
@@ -882,9 +924,9 @@ struct Engine {
       ad.f = q->f;
       ad.g = q->g;
       ad.W = q->W.as<double>();
-      ad.T = q->T.as<double>();
+      ad.T = q->sym ? ad.W : q->T.as<double>();
       ad.Zf = q->res->Zf.as<double>();
-      ad.Yf = q->res->Yf.as<double>();
+      ad.Yf = q->sym ? ad.Zf : q->res->Yf.as<double>();
       ad.gam = q->gam.as<double>();
       ad.hist = q->hist.as<double>();
       ad.host_done = q->done.d;
@@ -1181,6 +1223,13 @@ int lradi_solve_gen(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const 
   return lradi_batch_solve(c, 1, &P, opts, out);
 }
 
+int lradi_solve_lyap(lradi_ctx* c, const lradi_csr* A, const lradi_csr* M, const double* f, int r,
+                     const double* shifts, int nshifts, const lradi_opts* opts, lradi_result** out) {
+  if (!out) return set_error("lradi_solve_lyap: null output"), LRADI_EINVAL;
+  lradi_problem P{A, nullptr, f, nullptr, r, nshifts, shifts, nullptr, 0.0, M, nullptr, 1};
+  return lradi_batch_solve(c, 1, &P, opts, out);
+}
+
 int lradi_batch_solve(lradi_ctx* c, int nprob, const lradi_problem* probs, const lradi_opts* opts,
                       lradi_result** outs) {
   if (!c || nprob < 1 || !probs || !outs) return set_error("lradi_batch_solve: bad argument"), LRADI_EINVAL;
@@ -1252,7 +1301,7 @@ int lradi_result_factors(const lradi_result* r, const double** Z, const double**
   if (!r) return set_error("null result"), LRADI_EINVAL;
   if (Z) *Z = r->Zf.as<double>();
   if (D) *D = r->gam.data();
-  if (Y) *Y = r->Yf.as<double>();
+  if (Y) *Y = r->Y().as<double>();
   if (n) *n = r->n;
   if (m) *m = r->m;
   if (rr) *rr = r->r;
@@ -1264,7 +1313,7 @@ int lradi_result_copy(const lradi_result* r, double* Z, double* D, double* Y) {
   if (Z && r->k > 0)
     LRADI_HIP(hipMemcpy(Z, r->Zf.p, sizeof(double) * (size_t)r->k * r->n * r->r, hipMemcpyDeviceToHost));
   if (Y && r->k > 0)
-    LRADI_HIP(hipMemcpy(Y, r->Yf.p, sizeof(double) * (size_t)r->k * r->m * r->r, hipMemcpyDeviceToHost));
+    LRADI_HIP(hipMemcpy(Y, r->Y().p, sizeof(double) * (size_t)r->k * r->m * r->r, hipMemcpyDeviceToHost));
   if (D) std::copy(r->gam.begin(), r->gam.begin() + r->k, D);
   return LRADI_OK;
 }
@@ -1349,7 +1398,7 @@ struct lradi_server {
     uint64_t ticket;
     std::vector<int32_t> arp, aci, brp, bci, mrp, mci, crp, cci;
     std::vector<double> aval, bval, mval, cval, f, g, sA, sB;
-    bool hasM = false, hasC = false;
+    bool hasM = false, hasC = false, lyap = false;
     int r = 0, n = 0, m = 0;
     double tol = 0.0;
     size_t footprint = 0;
@@ -1427,15 +1476,17 @@ void lradi_server::run() {
       lradi_csr B{P.m, P.m, (int64_t)P.bci.size(), P.brp.data(), P.bci.data(), P.bval.data(), 0};
       DevBuf fd, gd;
       int rc = fd.alloc(sizeof(double) * P.f.size());
-      if (rc == LRADI_OK) rc = gd.alloc(sizeof(double) * P.g.size());
+      if (rc == LRADI_OK && !P.lyap) rc = gd.alloc(sizeof(double) * P.g.size());
       if (rc == LRADI_OK && hipMemcpy(fd.p, P.f.data(), sizeof(double) * P.f.size(), hipMemcpyHostToDevice) != hipSuccess)
         rc = LRADI_EHIP;
-      if (rc == LRADI_OK && hipMemcpy(gd.p, P.g.data(), sizeof(double) * P.g.size(), hipMemcpyHostToDevice) != hipSuccess)
+      if (rc == LRADI_OK && !P.lyap &&
+          hipMemcpy(gd.p, P.g.data(), sizeof(double) * P.g.size(), hipMemcpyHostToDevice) != hipSuccess)
         rc = LRADI_EHIP;
       lradi_csr Mc{P.n, P.n, (int64_t)P.mci.size(), P.mrp.data(), P.mci.data(), P.mval.data(), 0};
       lradi_csr Cc{P.m, P.m, (int64_t)P.cci.size(), P.crp.data(), P.cci.data(), P.cval.data(), 0};
       lradi_problem pr{&A, &B, fd.as<double>(), gd.as<double>(), P.r, (int32_t)P.sA.size(), P.sA.data(),
-                       P.sB.data(), P.tol, P.hasM ? &Mc : nullptr, P.hasC ? &Cc : nullptr};
+                       P.sB.data(), P.tol, P.hasM ? &Mc : nullptr, P.hasC ? &Cc : nullptr,
+                       P.lyap ? 1 : 0};
       if (rc == LRADI_OK) rc = prob_init(ctx, opts, pr, true, *q);
       Prob* raw = q.get();
       live[raw] = Live{std::move(q), P.ticket, P.footprint};
@@ -1541,35 +1592,39 @@ int lradi_server_create(lradi_ctx* c, const lradi_opts* opts, int64_t hbm_budget
 }
 
 int lradi_server_submit(lradi_server* s, const lradi_problem* P, uint64_t* ticket) {
-  if (!s || !P || !ticket || !P->A || !P->B || !P->f || !P->g || !P->shiftsA || !P->shiftsB)
+  const bool lyap = P && P->lyapunov != 0;
+  if (!s || !P || !ticket || !P->A || !P->f || !P->shiftsA || (!lyap && (!P->B || !P->g || !P->shiftsB)))
     return set_error("lradi_server_submit: null argument"), LRADI_EINVAL;
   if (P->r < 1 || P->r > kMaxR || P->nshifts < 1)
     return set_error("lradi_server_submit: bad r or nshifts"), LRADI_EINVAL;
   lradi_server::Pending q;
   q.r = P->r;
   q.tol = P->tol;
+  q.lyap = lyap;
   LRADI_TRY(host_csr(P->A, q.arp, q.aci, q.aval));
-  LRADI_TRY(host_csr(P->B, q.brp, q.bci, q.bval));
+  if (!lyap) LRADI_TRY(host_csr(P->B, q.brp, q.bci, q.bval));
   if (P->M) {
     LRADI_TRY(host_csr(P->M, q.mrp, q.mci, q.mval));
     q.hasM = true;
   }
-  if (P->C) {
+  if (P->C && !lyap) {
     LRADI_TRY(host_csr(P->C, q.crp, q.cci, q.cval));
     q.hasC = true;
   }
   q.n = P->A->nrows;
-  q.m = P->B->nrows;
+  q.m = lyap ? q.n : P->B->nrows;
   q.f.resize((size_t)q.n * q.r);
-  q.g.resize((size_t)q.m * q.r);
   LRADI_HIP(hipMemcpy(q.f.data(), P->f, sizeof(double) * q.f.size(), hipMemcpyDeviceToHost));
-  LRADI_HIP(hipMemcpy(q.g.data(), P->g, sizeof(double) * q.g.size(), hipMemcpyDeviceToHost));
+  if (!lyap) {
+    q.g.resize((size_t)q.m * q.r);
+    LRADI_HIP(hipMemcpy(q.g.data(), P->g, sizeof(double) * q.g.size(), hipMemcpyDeviceToHost));
+  }
   q.sA.assign(P->shiftsA, P->shiftsA + P->nshifts);
-  q.sB.assign(P->shiftsB, P->shiftsB + P->nshifts);
+  q.sB.assign(lyap ? P->shiftsA : P->shiftsB, (lyap ? P->shiftsA : P->shiftsB) + P->nshifts);
   // (a mass matrix adds its values on the union pattern: counted as extra
   // nonzeros of the operator)
   q.footprint = prob_footprint(q.n, q.m, q.r, (int64_t)(q.aci.size() + 2 * q.mci.size()),
-                               (int64_t)(q.bci.size() + 2 * q.cci.size()), s->opts);
+                               (int64_t)(q.bci.size() + 2 * q.cci.size()), s->opts, lyap);
   if ((int64_t)q.footprint > s->budget)
     return set_error("lradi_server_submit: footprint %zu bytes exceeds the budget", q.footprint), LRADI_ENOMEM;
   q.t_submit = std::chrono::steady_clock::now();

@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(_HERE, "liblradi.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENAN, EBREAKDOWN, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 WNOCONV, WINNER = 1, 2
-SEL_RELATIVE, SEL_FIXED, SEL_MID, SEL_TIGHT_A, SEL_TIGHT_B = 0, 1, 2, 3, 4
+SEL_RELATIVE, SEL_FIXED, SEL_MID, SEL_TIGHT_A, SEL_TIGHT_B, SEL_SYM = 0, 1, 2, 3, 4, 5
 FP64, FP32_INNER = 0, 1
 HIST_COLS = 16
 HIST_NAMES = ["k", "res_before", "deltaA", "deltaB", "rA", "rB", "stepsA", "stepsB", "u", "v",
               "norm_w", "norm_t", "norm_z", "norm_y", "gamma", "res_after"]
 
 SELECTIONS = {"relative": SEL_RELATIVE, "fixed": SEL_FIXED, "mid": SEL_MID,
-              "tightA": SEL_TIGHT_A, "tightB": SEL_TIGHT_B}
+              "tightA": SEL_TIGHT_A, "tightB": SEL_TIGHT_B, "sym": SEL_SYM}
 
 
 class LradiError(RuntimeError):
@@ -60,7 +60,8 @@ class Problem(ctypes.Structure):
                 ("g", ctypes.c_void_p), ("r", ctypes.c_int32), ("nshifts", ctypes.c_int32),
                 ("shiftsA", ctypes.POINTER(ctypes.c_double)),
                 ("shiftsB", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
-                ("M", ctypes.POINTER(Csr)), ("C", ctypes.POINTER(Csr))]
+                ("M", ctypes.POINTER(Csr)), ("C", ctypes.POINTER(Csr)),
+                ("lyapunov", ctypes.c_int32)]
 
 
 class ServerCounters(ctypes.Structure):
@@ -112,6 +113,7 @@ def _load():
         "lradi_batch_solve": (i32, [vp, i32, P(Problem), P(Opts), P(vp)]),
         "lradi_solve_gen": (i32, [vp, P(Csr), P(Csr), P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32,
                                   P(Opts), P(vp)]),
+        "lradi_solve_lyap": (i32, [vp, P(Csr), P(Csr), vp, i32, P(dbl), i32, P(Opts), P(vp)]),
         "lradi_server_create": (i32, [vp, P(Opts), ctypes.c_int64, i32, P(vp)]),
         "lradi_server_submit": (i32, [vp, P(Problem), P(ctypes.c_uint64)]),
         "lradi_server_poll": (i32, [vp, ctypes.c_uint64, P(vp), P(dbl)]),
@@ -360,25 +362,38 @@ class Context:
                          rnorm=s.rnorm) for s in stats], st
 
     @staticmethod
-    def make_problem(A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0, M=None, C=None):
+    def make_problem(A: HostCsr, B: Optional[HostCsr], f, g, shiftsA, shiftsB, tol=0.0, M=None, C=None,
+                     lyapunov=False):
         """(Problem struct, keep-alive list) for batch and serving calls; M, C
-        (HostCsr or None) give the generalized equation."""
+        (HostCsr or None) give the generalized equation.  lyapunov=True: the
+        case A X M^T + M X A^T = -f f^T, where B, g, shiftsB, C are not used
+        (may be None)."""
         sA = np.ascontiguousarray(shiftsA, dtype=np.float64)
-        sB = np.ascontiguousarray(shiftsB, dtype=np.float64)
-        assert f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()
-        pr = Problem(ctypes.pointer(A.c), ctypes.pointer(B.c), f.data_ptr(), g.data_ptr(), f.shape[1],
+        sB = sA if lyapunov else np.ascontiguousarray(shiftsB, dtype=np.float64)
+        assert f.is_cuda and f.is_contiguous()
+        if not lyapunov:
+            assert g.is_cuda and g.is_contiguous()
+        pr = Problem(ctypes.pointer(A.c), ctypes.pointer(B.c) if B is not None else None, f.data_ptr(),
+                     g.data_ptr() if g is not None else None, f.shape[1],
                      len(sA), sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                      sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tol),
                      ctypes.pointer(M.c) if M is not None else None,
-                     ctypes.pointer(C.c) if C is not None else None)
+                     ctypes.pointer(C.c) if C is not None else None, 1 if lyapunov else 0)
         return pr, [A, B, f, g, sA, sB, M, C]
 
+    @staticmethod
+    def lyap_problem(A: HostCsr, f, shifts, tol=0.0, M=None):
+        """A Lyapunov problem A X M^T + M X A^T = -f f^T for batch_solve."""
+        return dict(A=A, B=None, f=f, g=None, shiftsA=shifts, shiftsB=None, tol=tol, M=M,
+                    lyapunov=True)
+
     def batch_solve(self, problems, opts: Optional[Opts] = None):
-        """problems: list of (A, B, f, g, shiftsA, shiftsB[, tol]); returns
-        (list of Result, overall status)."""
+        """problems: list of (A, B, f, g, shiftsA, shiftsB[, tol, M, C]) or of
+        make_problem keyword dicts (lyap_problem); returns (list of Result,
+        overall status)."""
         structs, keep = [], []
         for pr in problems:
-            s_, k_ = self.make_problem(*pr)
+            s_, k_ = self.make_problem(**pr) if isinstance(pr, dict) else self.make_problem(*pr)
             structs.append(s_)
             keep.append(k_)
         n = len(structs)
@@ -405,6 +420,20 @@ class Context:
                                        ctypes.c_void_p(result.Zptr),
                                        D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        ctypes.c_void_p(result.Yptr), result.k, ctypes.byref(out)),
+               allow_warn=False)
+        return out.value
+
+    def residual_lyap(self, A: HostCsr, f, result: "Result", M: Optional[HostCsr] = None):
+        """True ||A X M^T + M X A^T + f f^T||_2 / ||f f^T||_2 of X = Z D Z^T:
+        lradi_residual_gen with B^T = A, C^T = M, g = f and Y = Z."""
+        D = np.ascontiguousarray(result.gammas(), dtype=np.float64)
+        out = ctypes.c_double()
+        self._sync()
+        pM = ctypes.byref(M.c) if M is not None else None
+        _check(_lib.lradi_residual_gen(self.h, ctypes.byref(A.c), ctypes.byref(A.c), pM, pM, 1,
+                                       _ptr(f), _ptr(f), f.shape[1], ctypes.c_void_p(result.Zptr),
+                                       D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.c_void_p(result.Zptr), result.k, ctypes.byref(out)),
                allow_warn=False)
         return out.value
 
@@ -445,6 +474,19 @@ class Context:
         res = Result(h.value, st)
         return res
 
+    def solve_lyap(self, A: HostCsr, f, shifts, opts: Optional[Opts] = None, M: Optional[HostCsr] = None):
+        """Lyapunov case A X M^T + M X A^T = -f f^T (M = I unless given): one
+        inner solve per step, shifts added to A; the result's Y is its Z."""
+        assert f.is_cuda and f.is_contiguous()
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        h = ctypes.c_void_p()
+        self._sync()
+        st = _check(_lib.lradi_solve_lyap(self.h, ctypes.byref(A.c), ctypes.byref(M.c) if M is not None else None,
+                                          _ptr(f), f.shape[1], sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          len(sh), ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.byref(h)))
+        return Result(h.value, st)
+
 
 class Server:
     """Continuous-batching request loop (lradi_server_*) on a context that the
@@ -461,6 +503,13 @@ class Server:
 
     def submit(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0, M=None, C=None) -> int:
         pr, keep = Context.make_problem(A, B, f, g, shiftsA, shiftsB, tol, M, C)
+        t = ctypes.c_uint64()
+        _torch().cuda.synchronize()
+        _check(_lib.lradi_server_submit(self.h, ctypes.byref(pr), ctypes.byref(t)))
+        return t.value
+
+    def submit_lyap(self, A: HostCsr, f, shifts, tol=0.0, M=None) -> int:
+        pr, keep = Context.make_problem(A, None, f, None, shifts, None, tol, M, None, lyapunov=True)
         t = ctypes.c_uint64()
         _torch().cuda.synchronize()
         _check(_lib.lradi_server_submit(self.h, ctypes.byref(pr), ctypes.byref(t)))

@@ -160,8 +160,8 @@ def test_householder_block(ST, n):
 @pytest.mark.parametrize("seed", range(30))
 def test_controller_matches_oracle(ST, seed):
     rng = np.random.default_rng(seed)
-    sel_names = ["relative", "fixed", "mid", "tightA", "tightB"]
-    sel = int(rng.integers(0, 5))
+    sel_names = ["relative", "fixed", "mid", "tightA", "tightB", "sym"]
+    sel = int(rng.integers(0, 6))
     bl = int(rng.integers(0, 2))
     pabs = int(rng.integers(0, 2))
     k = int(rng.integers(1, 60))
