@@ -41,10 +41,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented solve")
     ap.add_argument("--no-probe", action="store_true", help="skip the beyond-LLC SpMM probe")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "gen", "batch", "serve"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "gen", "lyap", "batch", "serve"],
                     help="c2: the metric's configuration (default); c3: 3-D mixed-precision "
                          "configuration, FP32-inner relaxed vs FP64 exact tolerance; gen: config "
-                         "2's operators as A X C + M X B = -f g^T with mass matrices; batch: "
+                         "2's operators as A X C + M X B = -f g^T with mass matrices; lyap: "
+                         "config 2's A as A X + X A^T = -f f^T, one solve per step vs the "
+                         "two-sided Sylvester path; batch: "
                          "256 independent problems; serve: Poisson request stream")
     ap.add_argument("--count", type=int, default=0, help="problems (batch) or requests (serve)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
@@ -71,6 +73,8 @@ def main():
         return bench_c3(args, L, WL)
     if args.workload == "gen":
         return bench_gen(args, L, WL)
+    if args.workload == "lyap":
+        return bench_lyap(args, L, WL)
     P = WL.C2
     HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
     HBt = L.convdiff(P.B.dim, P.B.N, tuple(-w for w in P.B.omega))   # B^T (bit-identical)
@@ -376,6 +380,78 @@ def bench_gen(args, L, WL):
                                   "shifts, tau=1e-8",
                       "n": P.A.n, "m": P.B.n, "steps": args.steps, **out,
                       "relaxed_saving_vs_fixed": round(1.0 - out["fp64_relaxed"]["s"] / out["fp64_fixed"]["s"], 3),
+                      "cpu_baseline": cpu}))
+
+
+def bench_lyap(args, L, WL):
+    """Lyapunov equation A X + X A^T = -f f^T on config 2's A (2-D 256^2,
+    omega (50, 20), r = 4, 24 shifts): the one-solve-per-step path (FP64 and
+    FP32 inner, equal-pair tolerances; FP64 with the mid selection's
+    min(delta^A, delta^B) and with fixed tolerances) against the two-sided
+    Sylvester path on (A, A^T, f, f) with the same tolerances, the true
+    residual of each, and (unless --no-cpu) the Lyapunov oracle timed on the
+    host with the X error of the FP64 run against it."""
+    import torch
+    P = WL.LYAP_C2
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    f, p = WL.lyap_inputs(P)
+    fd = torch.from_numpy(f).cuda()
+    ctx = L.Context(0)
+    out, keep = {}, {}
+    runs = (("lyap_fp64_sym", "lyap", dict(selection="sym")),
+            ("lyap_fp32_sym", "lyap", dict(selection="sym", precision="fp32")),
+            ("lyap_fp64_mid", "lyap", dict(selection="mid")),
+            ("lyap_fp64_fixed", "lyap", dict(selection="fixed")),
+            ("sylvester_fp64_sym", "sylv", dict(selection="sym", b_is_transposed=1)))
+    for name, kind, kw in runs:
+        o = L.default_opts(tol=P.tol, **kw)
+
+        def run():
+            if kind == "lyap":
+                return ctx.solve_lyap(HA, fd, p, o)
+            return ctx.solve(HA, HA, fd, fd, p, p, o)   # B^T = A given as B^T
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = run()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / max(args.steps, 1)
+        true = ctx.residual_lyap(HA, fd, r)
+        h = r.history()
+        out[name] = {"s": round(sec, 4), "k": r.k, "status": r.status, "rel_res_true": true,
+                     "inner_block_steps": int(h[:, 6].sum() + h[:, 7].sum())}
+        keep[name] = r
+        print(f"[bench lyap] {name}: {sec * 1e3:.1f} ms, k={r.k}, true res {true:.2e}, "
+              f"inner steps {out[name]['inner_block_steps']}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        from oracle import fadi as OF
+        from oracle import lyap as OL
+        from oracle.convdiff import convdiff_matrix
+        A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
+        w0 = time.perf_counter()
+        ora = OL.lyap_adi(A, f, p, tol=P.tol, kmax=50)
+        wall = time.perf_counter() - w0
+        Zg, dg, _ = keep["lyap_fp64_sym"].factors()
+        k = min(keep["lyap_fp64_sym"].k, ora.k)
+        rr = P.r
+        Zo, do = ora.Z[:, :k * rr], ora.D()[:k * rr]
+        xerr = OF.lowrank_diff_fro(Zg[:, :k * rr], dg[:k * rr], Zg[:, :k * rr], Zo, do, Zo)
+        xerr /= OF.lowrank_fro(Zo, do, Zo)
+        cpu = {"value": round(wall, 3), "unit": "s", "kind": "oracle", "oracle_outer_steps": ora.k,
+               "x_rel_err_lyap_fp64_vs_oracle": float(xerr),
+               "sample": "one full Lyapunov oracle solve (sparse LU per shift) of the same problem"}
+        print(f"[bench lyap] oracle: {wall:.2f} s, k={ora.k}, X err {xerr:.2e}", file=sys.stderr, flush=True)
+    ctx.close()
+    print(json.dumps({"workload": "Lyapunov A X + X A^T = -f f^T: A 2-D 256^2 upwind conv-diff omega "
+                                  "(50,20), r=4, 24 shifts, tau=1e-8",
+                      "n": P.A.n, "steps": args.steps, **out,
+                      "speedup_lyap_vs_sylvester_path": round(out["sylvester_fp64_sym"]["s"] /
+                                                              out["lyap_fp64_sym"]["s"], 3),
+                      "relaxed_saving_vs_fixed": round(1.0 - out["lyap_fp64_sym"]["s"] /
+                                                       out["lyap_fp64_fixed"]["s"], 3),
                       "cpu_baseline": cpu}))
 
 
