@@ -16,4 +16,7 @@ Modules:
   lyap        Lyapunov special case (B = A^T, C = M^T, g = f), one solve
               per step, written in its own residual-factor form
   gmres_ref   a plain block GMRES used to pin block-Krylov test cases
+              (optionally right-preconditioned)
+  precond     red-black ILU(0) of A + s I with Jacobi sweeps on the Schur
+              complement, the inner solver's right preconditioner
 """

@@ -36,11 +36,24 @@ def block_krylov_basis(S, W: np.ndarray, j: int) -> np.ndarray:
     return np.hstack(basis)
 
 
-def block_gmres_iterate(A, shift: float, W: np.ndarray, j: int) -> np.ndarray:
-    """Z_j of block GMRES on (A + shift I) Z = W after j block steps."""
+def block_gmres_iterate(A, shift: float, W: np.ndarray, j: int, precond=None) -> np.ndarray:
+    """Z_j of block GMRES on (A + shift I) Z = W after j block steps.  With a
+    right preconditioner (precond(X) = M X) the space is M K_j(S M, W) and
+    the minimised residual is still ||W - S Z||_F."""
     n = W.shape[0]
     S = sp.csr_matrix(A) + shift * sp.identity(n, format="csr")
-    V = block_krylov_basis(S, W, j)
-    SV = np.asarray(S @ V)
-    C, *_ = np.linalg.lstsq(SV, W, rcond=None)
-    return V @ C
+    if precond is None:
+        V = block_krylov_basis(S, W, j)
+        SV = np.asarray(S @ V)
+        C, *_ = np.linalg.lstsq(SV, W, rcond=None)
+        return V @ C
+
+    class _SM:
+        def __matmul__(self, X):
+            return np.asarray(S @ precond(X))
+
+    V = block_krylov_basis(_SM(), W, j)
+    MV = precond(V)
+    SMV = np.asarray(S @ MV)
+    C, *_ = np.linalg.lstsq(SMV, W, rcond=None)
+    return MV @ C

@@ -1,0 +1,108 @@
+"""Oracle (test infrastructure only): the right preconditioner of the inner
+block GMRES solves.
+
+The paper's inner Krylov solvers are preconditioned (Sec. 3.2.4 asks for
+right preconditioning so that the solver's residual is the true inner
+residual; Table 1 lists incomplete LU / Cholesky factorizations).  The
+preconditioner here is an incomplete LU factorization with zero fill,
+ILU(0), of S = A + s I in red-black order, for matrices whose sparsity graph
+is bipartite (the 2-D five-point and 3-D seven-point stencils of the test
+operators are).  Written as the block elimination it is:
+
+    S = [[D_r, E], [F, D_b]]   (red rows first; D_r, D_b diagonal),
+    y_r = v_r,                  y_b = v_b - F D_r^{-1} v_r,
+    z_b ~ T^{-1} y_b,           z_r = D_r^{-1} (v_r - E z_b),
+
+with T = D_b - F D_r^{-1} E the exact Schur complement on the black rows.
+ILU(0) keeps only T's diagonal (T's off-diagonal entries are fill outside
+S's pattern), so z_b = diag(T)^{-1} y_b; `sweeps` > 0 refines z_b by that
+many Jacobi steps on T y = ... (z_b += diag(T)^{-1} (y_b - T z_b)), which
+tends to the exact block solve (and M to S^{-1}) when Jacobi converges.
+
+Only tests/ and the bench's CPU baseline use this module.
+"""
+from __future__ import annotations
+
+from collections import deque
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def two_coloring(A) -> Optional[np.ndarray]:
+    """0/1 colour per row such that no off-diagonal entry of A or A^T joins
+    two rows of one colour, the lowest-numbered row of every connected
+    component coloured 0; None if the graph is not bipartite.  Breadth-first
+    search over the symmetrised pattern."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    G = (abs(A) + abs(A.T)).tocsr()
+    G.setdiag(0)
+    G.eliminate_zeros()
+    col = -np.ones(n, dtype=np.int64)
+    for s in range(n):
+        if col[s] >= 0:
+            continue
+        col[s] = 0
+        q = deque([s])
+        while q:
+            u = q.popleft()
+            for v in G.indices[G.indptr[u]:G.indptr[u + 1]]:
+                if col[v] < 0:
+                    col[v] = 1 - col[u]
+                    q.append(v)
+                elif col[v] == col[u]:
+                    return None
+    return col
+
+
+def rb_precond_apply(A, shift: float, V: np.ndarray, sweeps: int = 0) -> np.ndarray:
+    """M V for the red-black ILU(0) of A + shift I (module docstring), with
+    `sweeps` extra Jacobi steps on the Schur complement."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    col = two_coloring(A)
+    if col is None:
+        raise ValueError("sparsity graph is not bipartite")
+    red = np.where(col == 0)[0]
+    blk = np.where(col == 1)[0]
+    S = (A + shift * sp.identity(n, format="csr")).tocsr()
+    d = S.diagonal()
+    E = S[red][:, blk]
+    F = S[blk][:, red]
+    dr, db = d[red], d[blk]
+    V = np.asarray(V, dtype=np.float64)
+    vr, vb = V[red], V[blk]
+    yb = vb - F @ (vr / dr[:, None])
+    # the exact Schur complement and its diagonal
+    T = sp.diags(db) - F @ sp.diags(1.0 / dr) @ E
+    tdiag = T.diagonal()
+    zb = yb / tdiag[:, None]
+    for _ in range(sweeps):
+        zb = zb + (yb - T @ zb) / tdiag[:, None]
+    zr = (vr - E @ zb) / dr[:, None]
+    Z = np.empty_like(V)
+    Z[red] = zr
+    Z[blk] = zb
+    return Z
+
+
+def ilu0_dense(S: np.ndarray):
+    """Textbook ILU(0) (IKJ order) of a small dense-stored matrix: unit lower
+    L and upper U with (L U)_ij = S_ij wherever S_ij != 0, no fill elsewhere.
+    Pure loops, for pinning the block form on tiny inputs."""
+    n = S.shape[0]
+    nz = S != 0.0
+    Wm = S.astype(np.float64).copy()
+    for i in range(1, n):
+        for k in range(i):
+            if not nz[i, k]:
+                continue
+            Wm[i, k] = Wm[i, k] / Wm[k, k]
+            for j in range(k + 1, n):
+                if nz[i, j]:
+                    Wm[i, j] -= Wm[i, k] * Wm[k, j]
+    L = np.tril(Wm, -1) + np.eye(n)
+    U = np.triu(Wm)
+    return L, U

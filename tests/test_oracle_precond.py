@@ -1,0 +1,104 @@
+"""Pins of the red-black ILU(0) right preconditioner oracle and of the
+right-preconditioned block GMRES definition: the grid colouring in closed
+form, equality with the textbook ILU(0) factors of the red-black permuted
+matrix, convergence of the Schur sweeps to the exact inverse, and the
+exact-preconditioner special case of GMRES."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import precond as OP
+from oracle.convdiff import convdiff_matrix
+from oracle.gmres_ref import block_gmres_iterate
+from paper_2312_02891_amd import workloads as WL
+
+
+@pytest.mark.parametrize("dim,N", [(2, 5), (2, 6), (3, 4)])
+def test_grid_coloring_is_index_parity(dim, N):
+    """On the lexicographic grid (first axis fastest) the colour of point
+    (i_1, ..., i_d) is the parity of i_1 + ... + i_d: the unique 2-colouring
+    with point 0 red."""
+    A = convdiff_matrix(dim, N, tuple([3.0] * dim))
+    col = OP.two_coloring(A)
+    idx = np.indices([N] * dim).reshape(dim, -1, order="F")
+    # the first axis varies fastest in the lexicographic order
+    par = idx.sum(axis=0) % 2
+    assert np.array_equal(col, par)
+
+
+def test_non_bipartite_patterns_are_rejected():
+    tri = sp.csr_matrix(np.array([[2.0, 1, 1], [1, 2.0, 1], [1, 1, 2.0]]))
+    assert OP.two_coloring(tri) is None
+    rp, ci, v = WL.mass_csr(2, 5)
+    M = sp.csr_matrix((v, ci, rp), shape=(25, 25))
+    assert OP.two_coloring(M) is None
+    with pytest.raises(ValueError):
+        OP.rb_precond_apply(M, 1.0, np.ones((25, 1)))
+
+
+@pytest.mark.parametrize("dim,N,omega,shift", [(2, 5, (7.0, -3.0), -40.0), (3, 3, (2.0, 5.0, -1.0), -12.0),
+                                               (2, 6, (-20.0, 9.0), -3.0)])
+def test_zero_sweeps_equals_textbook_ilu0_in_red_black_order(dim, N, omega, shift):
+    """With no sweeps M = (L U)^{-1} where L U is the ILU(0) of
+    P (A + s I) P^T computed by the generic IKJ algorithm (P: red rows
+    first), undone by the same permutation."""
+    A = convdiff_matrix(dim, N, omega)
+    n = A.shape[0]
+    col = OP.two_coloring(A)
+    perm = np.concatenate([np.where(col == 0)[0], np.where(col == 1)[0]])
+    S = (A + shift * sp.identity(n)).toarray()[np.ix_(perm, perm)]
+    L, U = OP.ilu0_dense(S)
+    nz = S != 0.0
+    assert np.allclose((L @ U)[nz], S[nz], rtol=1e-13, atol=1e-12 * np.abs(S).max())
+    V = np.random.default_rng(1).standard_normal((n, 3))
+    want = np.empty_like(V)
+    want[perm] = np.linalg.solve(U, np.linalg.solve(L, V[perm]))
+    got = OP.rb_precond_apply(A, shift, V, sweeps=0)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-13 * np.abs(want).max())
+
+
+def test_sweeps_converge_to_the_exact_inverse():
+    """Jacobi on the Schur complement converges for this diagonally
+    dominant shifted operator, so M V -> (A + s I)^{-1} V."""
+    A = convdiff_matrix(2, 8, (10.0, -6.0))
+    s = -400.0
+    n = A.shape[0]
+    V = np.random.default_rng(2).standard_normal((n, 2))
+    X = spla.spsolve((A + s * sp.identity(n)).tocsc(), V)
+    errs = [np.linalg.norm(OP.rb_precond_apply(A, s, V, k) - X) / np.linalg.norm(X) for k in (0, 2, 8, 60)]
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < 1e-12
+
+
+def test_preconditioned_gmres_definition():
+    """An exact right preconditioner gives the solution after one block
+    step.  With the red-black preconditioner the j-step iterate lies in
+    M K_j(S M, W) and its residual is orthogonal to S M K_j(S M, W) (the
+    least-squares optimality condition), checked on a basis built here by
+    plain repeated products; it also beats the unpreconditioned iterate."""
+    A = convdiff_matrix(2, 9, (25.0, -12.0))
+    n = A.shape[0]
+    s = -30.0
+    S = (A + s * sp.identity(n)).tocsc()
+    W = np.random.default_rng(3).standard_normal((n, 2))
+    exact = lambda X: spla.spsolve(S, X).reshape(X.shape)
+    Z1 = block_gmres_iterate(A, s, W, 1, precond=exact)
+    assert np.allclose(Z1, exact(W), rtol=1e-10, atol=1e-12)
+    pre = lambda X: OP.rb_precond_apply(A, s, X, 1)
+    for j in (2, 4):
+        Zp = block_gmres_iterate(A, s, W, j, precond=pre)
+        Zn = block_gmres_iterate(A, s, W, j)
+        # Krylov blocks W, (S M) W, ..., (S M)^{j-1} W, orthonormalised once
+        blocks, cur = [], W
+        for _ in range(j):
+            blocks.append(cur)
+            cur = S @ pre(cur)
+        K, _ = np.linalg.qr(np.hstack(blocks))
+        MK = pre(K)
+        C, *_ = np.linalg.lstsq(MK, Zp, rcond=None)
+        assert np.linalg.norm(MK @ C - Zp) <= 1e-9 * np.linalg.norm(Zp)
+        res = W - S @ Zp
+        SMK = S @ MK
+        assert np.linalg.norm(SMK.T @ res) <= 1e-9 * np.linalg.norm(SMK) * np.linalg.norm(res)
+        assert np.linalg.norm(res) < np.linalg.norm(W - S @ Zn)
