@@ -59,6 +59,15 @@ extern "C" {
                                   boundary of eq. (ADI_relax1_prak)/(ADI_relax2_prak),
                                   clamped by eq. (bound_tols)                     */
 
+/* ---- inner right preconditioners (opts.precond) ---------------------- */
+#define LRADI_PRECOND_NONE 0
+/* ILU(0) of A + s I in red-black order: rows 2-coloured so that every
+ * off-diagonal entry joins a red and a black row; with S = [D_r E; F D_b]
+ * (red first) it applies z_b = diag(T)^-1 (v_b - F D_r^-1 v_r),
+ * T = D_b - F D_r^-1 E, refined by precond_sweeps Jacobi steps on T, then
+ * z_r = D_r^-1 (v_r - E z_b).  Both half-steps are parallel over rows. */
+#define LRADI_PRECOND_RBILU0 1
+
 /* ---- arithmetic of the inner Krylov solves ---------------------------- */
 #define LRADI_FP64 0           /* basis, SpMM and projections in FP64             */
 #define LRADI_FP32_INNER 1     /* basis, SpMM and projections in FP32; residual
@@ -131,7 +140,15 @@ typedef struct {
                           shape (timed once per context, see
                           lradi_spmm_tune); -1: built-in rule without timing;
                           1, 2, 4: forced (must divide r)                    */
-  int32_t reserved[3];
+  int32_t precond;     /* right preconditioner of the inner block GMRES
+                          (Sec. 3.2.4: right preconditioning keeps the
+                          solver's residual the true inner residual):
+                          LRADI_PRECOND_NONE or LRADI_PRECOND_RBILU0.  The
+                          latter needs M = C = I and a bipartite sparsity
+                          graph (else LRADI_EINVAL)                        */
+  int32_t precond_sweeps; /* LRADI_PRECOND_RBILU0: Jacobi sweeps on the
+                          Schur complement after the ILU(0) step, 0..16  */
+  int32_t reserved[1];
 } lradi_opts;
 
 /* Per inner solve statistics (lradi_shifted_solve). */

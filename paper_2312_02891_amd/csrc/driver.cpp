@@ -290,7 +290,9 @@ struct SysWork {
   SysDesc d{};
   SysCtl c{};  // host copy of the control block, valid at drain points
 
-  int init(const DevCSR* A, const double* W, int r, int m, int prec, int max_inner, double floor_rel) {
+  // sweeps < 0: no preconditioner; else A must carry the red-black data
+  int init(const DevCSR* A, const double* W, int r, int m, int prec, int max_inner, double floor_rel,
+           int sweeps = -1) {
     if (r < 1 || r > kMaxR || m < 1 || m > kMaxM)
       return set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM), LRADI_EINVAL;
     const size_t n = A->n, rr = r, mm = m;
@@ -310,7 +312,9 @@ struct SysWork {
                             mm * 4 * rr * rr * 8,      // Qs
                             (mm + 1) * rr * rr * 8,    // Gv
                             mm * rr * rr * 8,          // yv
-                            512 * 8};                  // sm
+                            512 * 8,                   // sm
+                            sweeps >= 0 ? (mm + 1) * n * rr * tsz : 0,  // P
+                            sweeps > 0 ? n * rr * tsz : 0};             // Q
     size_t total = 0;
     for (size_t z : sizes) total += align256(z);
     LRADI_TRY(buf.alloc(total));
@@ -353,6 +357,16 @@ struct SysWork {
     d.Gv = reinterpret_cast<double*>(take(sizes[10]));
     d.yv = reinterpret_cast<double*>(take(sizes[11]));
     d.sm = reinterpret_cast<double*>(take(sizes[12]));
+    if (sweeps >= 0) {
+      if (!A->has_rb()) return set_error("preconditioner data missing"), LRADI_EINVAL;
+      d.P = take(sizes[13]);
+      d.Q = sweeps > 0 ? take(sizes[14]) : nullptr;
+      d.rbrows = A->rbrows.as<int>();
+      d.nred = A->nred;
+      d.sweeps = sweeps;
+      d.diagT = (prec == LRADI_FP64) ? (const void*)A->diag64.p : (const void*)A->diag32.p;
+      d.tvalT = (prec == LRADI_FP64) ? (const void*)A->tval64.p : (const void*)A->tval32.p;
+    }
     c = SysCtl{};
     c.phase = PH_FINISHED;  // armed by the caller or by the outer kernels
     return LRADI_OK;
@@ -411,7 +425,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hd.resize(nsys);
   t.hc.resize(nsys);
   t.hmap.clear();
-  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1;
+  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -422,6 +436,12 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
     maxB = std::max(maxB, ws[s]->d.m + 1);
     if (ws[s]->d.nwg * ws[s]->d.r * ws[s]->d.r > kFuseCholMax) fuse = 0;
     if (ws[s]->d.r != rfix) rfix = 0;
+    if (ws[s]->d.rbrows) {
+      if (precond && ws[s]->d.sweeps != sweeps)
+        return set_error("all preconditioned systems of a batch must use one sweep count"), LRADI_EINVAL;
+      precond = 1;
+      sweeps = ws[s]->d.sweeps;
+    }
   }
   // shifted-product tiles, grouped by lanes per row
   t.hsp.clear();
@@ -460,6 +480,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.fuse_chol = fuse && rfix >= 1 && rfix <= 4;
   t.b.precision = prec;
   t.b.rfix = rfix;
+  t.b.precond = precond;
+  t.b.sweeps = sweeps;
   return LRADI_OK;
 }
 
@@ -663,8 +685,14 @@ int check_opts(const lradi_opts& o) {
   if (o.rescale < 0 || o.rescale > 2) return set_error("rescale must be 0, 1 or 2"), LRADI_EINVAL;
   if (!(o.spmm_lanes >= -1 && o.spmm_lanes <= 4 && o.spmm_lanes != 3))
     return set_error("spmm_lanes must be -1, 0, 1, 2 or 4"), LRADI_EINVAL;
+  if (o.precond != LRADI_PRECOND_NONE && o.precond != LRADI_PRECOND_RBILU0)
+    return set_error("unknown preconditioner"), LRADI_EINVAL;
+  if (o.precond_sweeps < 0 || o.precond_sweeps > 16)
+    return set_error("precond_sweeps must be in 0..16"), LRADI_EINVAL;
   return LRADI_OK;
 }
+
+int sweeps_for(const lradi_opts& o) { return o.precond == LRADI_PRECOND_RBILU0 ? o.precond_sweeps : -1; }
 
 double floor_for(const lradi_opts& o) {
   return o.precision == LRADI_FP64 ? 1e-14 : (o.fp32_floor > 0.0 ? o.fp32_floor : 3e-6);
@@ -695,6 +723,79 @@ int DevCSR::upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st
     }
   }
   LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
+  return LRADI_OK;
+}
+
+int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
+  std::vector<int32_t> rp, ci, trp, tci;
+  std::vector<double> v, tv;
+  LRADI_TRY(host_csr(A, rp, ci, v));
+  const int nn = A->nrows;
+  if (nn != n) return set_error("preconditioner: matrix size differs from the uploaded one"), LRADI_EINVAL;
+  csr_transpose(nn, rp.data(), ci.data(), v.data(), trp, tci, tv);
+  // breadth-first 2-colouring over the union of A's and A^T's off-diagonal
+  // patterns (stored zeros count), the lowest row of each component red
+  std::vector<int8_t> col(nn, -1);
+  std::vector<int32_t> queue(nn);
+  for (int s0 = 0; s0 < nn; ++s0) {
+    if (col[s0] >= 0) continue;
+    col[s0] = 0;
+    int head = 0, tail = 0;
+    queue[tail++] = s0;
+    while (head < tail) {
+      const int u = queue[head++];
+      for (int pass = 0; pass < 2; ++pass) {
+        const int32_t* R = pass ? trp.data() : rp.data();
+        const int32_t* C = pass ? tci.data() : ci.data();
+        for (int32_t k = R[u]; k < R[u + 1]; ++k) {
+          const int w = C[k];
+          if (w == u) continue;
+          if (col[w] < 0) {
+            col[w] = (int8_t)(1 - col[u]);
+            queue[tail++] = w;
+          } else if (col[w] == col[u]) {
+            return set_error("red-black preconditioner: the sparsity graph is not bipartite"), LRADI_EINVAL;
+          }
+        }
+      }
+    }
+  }
+  std::vector<int32_t> rows;
+  rows.reserve(nn);
+  for (int i = 0; i < nn; ++i)
+    if (col[i] == 0) rows.push_back(i);
+  const int nr = (int)rows.size();
+  for (int i = 0; i < nn; ++i)
+    if (col[i] == 1) rows.push_back(i);
+  // diagonal per row and, per nonzero (i, j), the entry (j, i) (row i of A^T)
+  std::vector<double> dg(nn, 0.0), tvals(std::max<size_t>(ci.size(), 1), 0.0);
+  for (int i = 0; i < nn; ++i) {
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] == i) dg[i] += v[k];
+      double a = 0.0;
+      for (int32_t kk = trp[i]; kk < trp[i + 1]; ++kk)
+        if (tci[kk] == ci[k]) a += tv[kk];
+      tvals[k] = a;
+    }
+  }
+  LRADI_TRY(rbrows.alloc(sizeof(int32_t) * nn));
+  LRADI_TRY(diag64.alloc(sizeof(double) * nn));
+  LRADI_TRY(tval64.alloc(sizeof(double) * tvals.size()));
+  LRADI_HIP(hipMemcpyAsync(rbrows.p, rows.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(diag64.p, dg.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(tval64.p, tvals.data(), sizeof(double) * tvals.size(), hipMemcpyHostToDevice, st));
+  if (need32) {
+    LRADI_TRY(diag32.alloc(sizeof(float) * nn));
+    LRADI_TRY(tval32.alloc(sizeof(float) * tvals.size()));
+    const int tpb = 256;
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + tpb - 1) / tpb)), dim3(tpb), 0, st, diag64.as<double>(),
+                       diag32.as<float>(), (int64_t)nn);
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((tvals.size() + tpb - 1) / tpb)), dim3(tpb), 0, st,
+                       tval64.as<double>(), tval32.as<float>(), (int64_t)tvals.size());
+    LRADI_HIP(hipGetLastError());
+  }
+  LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
+  nred = nr;
   return LRADI_OK;
 }
 
@@ -795,6 +896,23 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
     }
     LRADI_HIP(hipStreamSynchronize(st));
   }
+  const int sw = sweeps_for(o);
+  if (sw >= 0) {
+    if (P.M || P.C) return set_error("the red-black preconditioner needs M = C = I"), LRADI_EINVAL;
+    LRADI_TRY(q.A.prepare_rb(P.A, st, f32));
+    if (!q.sym) {
+      if (o.b_is_transposed) {
+        LRADI_TRY(q.Bt.prepare_rb(P.B, st, f32));
+      } else {
+        std::vector<int32_t> trp, tci;
+        std::vector<double> tv;
+        LRADI_TRY(host_csr_t(P.B, trp, tci, tv));
+        const int mB = P.B->nrows;
+        lradi_csr Bt{mB, mB, (int64_t)tci.size(), trp.data(), tci.data(), tv.data(), 0};
+        LRADI_TRY(q.Bt.prepare_rb(&Bt, st, f32));
+      }
+    }
+  }
   q.n = q.A.n;
   q.m = q.sym ? q.A.n : q.Bt.n;
   q.r = P.r;
@@ -833,12 +951,12 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   LRADI_HIP(hipMemcpyAsync(q.shA.p, P.shiftsA, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   const double fl = floor_for(o);
-  LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
+  LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw));
   LRADI_TRY(q.wa.tune(c, q.A, o.spmm_lanes));
   if (q.sym) {
     q.wb.init_mirror(q.wa);
   } else {
-    LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl));
+    LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw));
     LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
   }
   LRADI_TRY(q.done.init());
@@ -853,12 +971,17 @@ size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lra
   const size_t tsz = o.precision == LRADI_FP64 ? 8 : 4;
   const size_t K = o.kmax, mm = o.restart;
   auto mat = [&](int64_t nrow, int64_t nnz) {
-    return (size_t)(nrow + 1) * 4 + (size_t)nnz * (4 + 8 + (tsz == 4 ? 4 : 0));
+    // (the preconditioner keeps transposed values beside the matrix)
+    const size_t vals = (size_t)nnz * (8 + (tsz == 4 ? 4 : 0));
+    return (size_t)(nrow + 1) * 4 + (size_t)nnz * 4 + vals * (sweeps_for(o) >= 0 ? 2 : 1);
   };
+  const int sw = sweeps_for(o);
   auto inner = [&](size_t rows) {
     const size_t rpw = (size_t)choose_rows_per_wg((int)rows), nwg = (rows + rpw - 1) / rpw;
+    // preconditioned: the basis P_0..P_m, a sweep block, colour order, diagonal
+    const size_t pre = sw < 0 ? 0 : (mm + 1 + (sw > 0 ? 1 : 0)) * rows * r * tsz + rows * (4 + 8 + tsz);
     return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + 2 * kPS) * 8 +
-           (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 12 * 256 + 4096;
+           (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 12 * 256 + 4096 + pre;
   };
   if (sym) return mat(n, nnzA) + (size_t)n * r * 8 * (2 + K) + K * (kHistCols + 1) * 8 + inner(n);
   return mat(n, nnzA) + mat(m, nnzB) + (size_t)(n + m) * r * 8 * (3 + K) + K * (kHistCols + 1) * 8 +
@@ -1164,8 +1287,11 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
   lradi_default_opts(&o);
   if (opts) o = *opts;
   if (o.restart < 1 || o.restart > kMaxM || o.max_inner < 1 ||
-      (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER))
+      (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER) ||
+      (o.precond != LRADI_PRECOND_NONE && o.precond != LRADI_PRECOND_RBILU0) || o.precond_sweeps < 0 ||
+      o.precond_sweeps > 16)
     return set_error("lradi_shifted_solve: bad options"), LRADI_EINVAL;
+  const int sw = sweeps_for(o);
   LRADI_HIP(hipSetDevice(c->device));
   std::vector<DevCSR> mats(nsys);
   std::vector<std::unique_ptr<SysWork>> work(nsys);
@@ -1174,8 +1300,9 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     if (!W[s] || !Z[s] || !(delta[s] >= 0.0) || !std::isfinite(shift[s]))
       return set_error("lradi_shifted_solve: bad system %d", s), LRADI_EINVAL;
     LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
+    if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(A[s], c->stream, o.precision == LRADI_FP32_INNER));
     work[s] = std::make_unique<SysWork>();
-    LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o)));
+    LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o), sw));
     LRADI_TRY(work[s]->tune(c, mats[s], o.spmm_lanes));
     work[s]->arm(Z[s], shift[s], delta[s]);
     ws[s] = work[s].get();

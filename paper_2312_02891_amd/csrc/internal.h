@@ -150,6 +150,15 @@ struct SysDesc {
   // diagonal)
   const void* mvalT;    // M's values in the basis precision
   const double* mval64; // M's values in FP64 (refinement residual, M z)
+  // red-black ILU(0) right preconditioner (null rbrows: none): Arnoldi
+  // multiplies S P_j with P_j = M V_j, and Z += sum_b P_b y_b
+  const int* rbrows;    // red rows ascending, then black rows ascending
+  int nred;             // number of red rows
+  int sweeps;           // Jacobi sweeps on the Schur complement
+  const void* diagT;    // diagonal of A per row, basis precision
+  const void* tvalT;    // per nonzero (i, j): A's entry (j, i), basis precision
+  void* P;              // preconditioned basis blocks P_0..P_m, basis precision
+  void* Q;              // one block of scratch for the sweeps, basis precision
 };
 
 // Mutable device-side control block of one inner solve.
@@ -217,10 +226,18 @@ struct DevCSR {
   int64_t nnz = 0;
   DevBuf rowptr, colind, val64, val32;
   DevBuf mval64, mval32;  // the mass matrix of a pencil, on the same pattern
+  // red-black preconditioner data (prepare_rb)
+  DevBuf rbrows, diag64, diag32, tval64, tval32;
+  int nred = -1;
   int upload(const lradi_csr* A, hipStream_t st, bool need32);
   // the pencil (A, M): union pattern, A's values and M's values
   int upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);
   bool has_mass() const { return mval64.p != nullptr; }
+  // 2-colour the sparsity graph of A (the matrix uploaded here) and upload
+  // the colour-ordered rows, A's diagonal and its transposed values;
+  // LRADI_EINVAL if the graph is not bipartite
+  int prepare_rb(const lradi_csr* A, hipStream_t st, bool need32);
+  bool has_rb() const { return nred >= 0; }
 };
 
 // ---------------------------------------------------------------------------
@@ -243,6 +260,8 @@ struct Batch {
   int maxB;            // max over systems of m+1 (basis blocks)
   int precision;       // LRADI_FP64 / LRADI_FP32_INNER
   int rfix;            // common r of all systems, or 0 when they differ
+  int precond;         // some system carries the red-black preconditioner
+  int sweeps;          // its Jacobi sweeps (shared by the batch)
   int fuse_chol;       // 1: every scale workgroup reduces the small Gram
                        // partials and factors them itself (common r <= 4
                        // and small nwg r^2)

@@ -10,14 +10,16 @@
 // anything back per step.
 //
 // One Arnoldi step for the block V_j (n x r):
-//   U = (A + s I) V_j                          SpMM, basis precision
+//   [P_j = M V_j                               optional right preconditioner]
+//   U = (A + s I) V_j   (or (A + s I) P_j)     SpMM, basis precision
 //   H1 = V^T U,  U -= V H1                     block classical Gram-Schmidt
 //   H2 = V^T U,  U -= V H2                     ... repeated once (CGS2)
 //   U = V_{j+1} S with S = S2 S1               CholQR2 (two Cholesky QR passes)
 //   column block [H1 + H2; S] enters the incremental QR of the block
 //   Hessenberg matrix (one 2r x 2r orthogonal factor per column block), the
 //   rotated right-hand side gives the residual estimate.
-// At the end of a cycle: Z += V y, R = W - (A + s I) Z in FP64, ||R||_2 from
+// At the end of a cycle: Z += V y (P y when preconditioned),
+// R = W - (A + s I) Z in FP64, ||R||_2 from
 // the r x r Gram matrix, then stop or restart from R.
 #include <cstdio>
 
@@ -251,7 +253,8 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
     return;
   }
   if (ph != PH_ARNOLDI) return;
-  const T* Vj = static_cast<const T*>(D.V) + (size_t)ctl[e.x].j * D.n * D.r;
+  // right preconditioning multiplies P_j = M V_j instead of V_j
+  const T* Vj = static_cast<const T*>(D.rbrows ? D.P : D.V) + (size_t)ctl[e.x].j * D.n * D.r;
   const T sh = (T)ctl[e.x].shift;
   if (prof && e.y == 0 && threadIdx.x == 0) {
     // values + column indices + row pointers + input block + output block
@@ -262,6 +265,150 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
   const T* val = static_cast<const T*>(D.valT);
   const T* mval = static_cast<const T*>(D.mvalT);
   LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.n, D.rowptr, D.colind, val, mval, sh, Vj, U, r0, s_ci, s_val));
+}
+
+// ---------------------------------------------------------------------------
+// 0. Right preconditioner P_j = M V_j before the shifted product
+//    (PH_ARNOLDI, systems with rbrows): red-black ILU(0) of S = A + s I,
+//    S = [D_r E; F D_b] with the rows 2-coloured (every off-diagonal entry
+//    joins a red and a black row), T = D_b - F D_r^{-1} E:
+//      fwd    (black rows)  y_b = v_b - F D_r^{-1} v_r,  z_b = y_b / diag(T)
+//      sweep  (black rows)  z_b += (y_b - T z_b) / diag(T)      (sweeps times)
+//      back   (red rows)    z_r = (v_r - E z_b) / diag(D_r)
+//    A workgroup's row chunk indexes the colour-ordered row list.  With k
+//    sweeps the k + 1 black iterates alternate between Q and P_j so that
+//    the last one lands in P_j.
+template <typename T>
+struct RbCtx {
+  const int* rp;
+  const int* ci;
+  const T* val;
+  const T* tv;
+  const T* dg;
+  T sh;
+};
+
+template <typename T>
+__device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
+  RbCtx<T> x;
+  x.rp = D.rowptr;
+  x.ci = D.colind;
+  x.val = static_cast<const T*>(D.valT);
+  x.tv = static_cast<const T*>(D.tvalT);
+  x.dg = static_cast<const T*>(D.diagT);
+  x.sh = (T)shift;
+  return x;
+}
+
+__device__ inline void* rb_buf(const SysDesc& D, int j, int t) {
+  const size_t blk = (size_t)D.n * D.r * (D.precision == LRADI_FP64 ? 8 : 4);
+  return ((D.sweeps - t) % 2 == 0) ? static_cast<char*>(D.P) + (size_t)j * blk : D.Q;
+}
+
+// y_b and diag(T) of black row i (its off-diagonal neighbours are red);
+// with Z: also (T z)_i = (d_i + s) z_i - sum_j a_ij/(d_j + s) sum_l a_jl z_l
+template <typename T, int R, bool TZ>
+__device__ inline void rb_black_row(const RbCtx<T>& x, int i, const T* __restrict__ V,
+                                    const T* __restrict__ Z, T (&y)[R], T& tdiag, T (&tz)[R]) {
+  const T di = x.dg[i] + x.sh;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    y[q] = V[(size_t)i * R + q];
+    if constexpr (TZ) tz[q] = di * Z[(size_t)i * R + q];
+  }
+  tdiag = di;
+  for (int k = x.rp[i]; k < x.rp[i + 1]; ++k) {
+    const int j = x.ci[k];
+    if (j == i) continue;
+    const T w = x.val[k] / (x.dg[j] + x.sh);
+    tdiag -= w * x.tv[k];
+#pragma unroll
+    for (int q = 0; q < R; ++q) y[q] -= w * V[(size_t)j * R + q];
+    if constexpr (TZ) {
+      T ez[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) ez[q] = T(0);
+      for (int kk = x.rp[j]; kk < x.rp[j + 1]; ++kk) {
+        const int l = x.ci[kk];
+        if (l == j) continue;
+        const T a = x.val[kk];
+#pragma unroll
+        for (int q = 0; q < R; ++q) ez[q] += a * Z[(size_t)l * R + q];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) tz[q] -= w * ez[q];
+    }
+  }
+}
+
+template <typename T, int R>
+__device__ inline void rb_fwd_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* dst) {
+  const int nb = D.n - D.nred;
+  const int* rows = D.rbrows + D.nred;
+  for (int p = c.row0 + threadIdx.x; p < min(c.row1, nb); p += kTPB) {
+    const int i = rows[p];
+    T y[R], tz[R], td;
+    rb_black_row<T, R, false>(x, i, V, nullptr, y, td, tz);
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[(size_t)i * R + q] = y[q] / td;
+  }
+}
+
+template <typename T, int R>
+__device__ inline void rb_sweep_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V,
+                                     const T* src, T* dst) {
+  const int nb = D.n - D.nred;
+  const int* rows = D.rbrows + D.nred;
+  for (int p = c.row0 + threadIdx.x; p < min(c.row1, nb); p += kTPB) {
+    const int i = rows[p];
+    T y[R], tz[R], td;
+    rb_black_row<T, R, true>(x, i, V, src, y, td, tz);
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[(size_t)i * R + q] = src[(size_t)i * R + q] + (y[q] - tz[q]) / td;
+  }
+}
+
+template <typename T, int R>
+__device__ inline void rb_back_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj) {
+  for (int p = c.row0 + threadIdx.x; p < min(c.row1, D.nred); p += kTPB) {
+    const int i = D.rbrows[p];
+    T z[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) z[q] = V[(size_t)i * R + q];
+    for (int k = x.rp[i]; k < x.rp[i + 1]; ++k) {
+      const int l = x.ci[k];
+      if (l == i) continue;
+      const T a = x.val[k];
+#pragma unroll
+      for (int q = 0; q < R; ++q) z[q] -= a * Pj[(size_t)l * R + q];
+    }
+    const T di = x.dg[i] + x.sh;
+#pragma unroll
+    for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = z[q] / di;
+  }
+}
+
+// stage 0: fwd; 1..sweeps: sweep t; sweeps + 1: back
+template <typename T, int RF>
+__global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
+                                                  const int2* __restrict__ rowmap, int stage) {
+  const RowCtx c = row_ctx(d, rowmap);
+  const SysDesc& D = d[c.s];
+  if (ctl[c.s].phase != PH_ARNOLDI || !D.rbrows) return;
+  const int j = ctl[c.s].j;
+  const RbCtx<T> x = rb_ctx<T>(D, ctl[c.s].shift);
+  const T* V = static_cast<const T*>(D.V) + (size_t)j * D.n * D.r;
+  if (stage == 0) {
+    T* dst = static_cast<T*>(rb_buf(D, j, 0));
+    LRADI_RSEL(RF, D.r, rb_fwd_rows<T, RR>(D, c, x, V, dst));
+  } else if (stage <= D.sweeps) {
+    const T* src = static_cast<const T*>(rb_buf(D, j, stage - 1));
+    T* dst = static_cast<T*>(rb_buf(D, j, stage));
+    LRADI_RSEL(RF, D.r, rb_sweep_rows<T, RR>(D, c, x, V, src, dst));
+  } else {
+    T* Pj = static_cast<T*>(rb_buf(D, j, D.sweeps));
+    LRADI_RSEL(RF, D.r, rb_back_rows<T, RR>(D, c, x, V, Pj));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -942,11 +1089,12 @@ __global__ __launch_bounds__(LsqTPB<RF>::v) void k_lsq(const SysDesc* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// 13. Z += sum_b V_b y_b  (PH_CYCLE_END, at least one column)
+// 13. Z += sum_b V_b y_b  (PH_CYCLE_END, at least one column); with right
+//     preconditioning Z += sum_b P_b y_b, P_b = M V_b
 template <typename T, int R>
 __device__ inline void zupdate_rows(const SysDesc& D, const RowCtx& c, double* Z, int nb,
                                     const double* yl) {
-  const auto V = gmem(static_cast<const T*>(D.V));
+  const auto V = gmem(static_cast<const T*>(D.rbrows ? D.P : D.V));
   const size_t bs = (size_t)D.n * R;
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     double acc[R];
@@ -1107,6 +1255,9 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 rg(b.rowgrid), tb(kTPB), sg(b.nsys);
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
+  if (b.precond)
+    for (int stage = 0; stage <= b.sweeps + 1; ++stage)
+      hipLaunchKernelGGL((k_precond<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
     hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,

@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EHIP, ENAN, EBREAKDOWN, ECANCELED = 0, -1, -2, -3, -4, -5, -
 WNOCONV, WINNER = 1, 2
 SEL_RELATIVE, SEL_FIXED, SEL_MID, SEL_TIGHT_A, SEL_TIGHT_B, SEL_SYM = 0, 1, 2, 3, 4, 5
 FP64, FP32_INNER = 0, 1
+PRECOND_NONE, PRECOND_RBILU0 = 0, 1
 HIST_COLS = 16
 HIST_NAMES = ["k", "res_before", "deltaA", "deltaB", "rA", "rB", "stepsA", "stepsB", "u", "v",
               "norm_w", "norm_t", "norm_z", "norm_y", "gamma", "res_after"]
@@ -52,7 +53,8 @@ class Opts(ctypes.Structure):
                 ("max_inner", ctypes.c_int32), ("rescale", ctypes.c_int32),
                 ("b_is_transposed", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("spmm_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("spmm_lanes", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("precond_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Problem(ctypes.Structure):
@@ -162,6 +164,8 @@ def default_opts(**kw) -> Opts:
             v = SELECTIONS[v]
         if k == "precision" and isinstance(v, str):
             v = {"fp64": FP64, "fp32": FP32_INNER, "fp32-inner": FP32_INNER}[v]
+        if k == "precond" and isinstance(v, str):
+            v = {"none": PRECOND_NONE, "rbilu0": PRECOND_RBILU0}[v]
         if not hasattr(o, k):
             raise AttributeError(k)
         setattr(o, k, v)

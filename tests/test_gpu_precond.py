@@ -1,0 +1,169 @@
+"""GPU parity of the right-preconditioned inner block GMRES (red-black
+ILU(0) with Jacobi sweeps on the Schur complement) against the oracle's
+preconditioner and the preconditioned block minimal-residual definition,
+and of the LR-ADI iteration run with it."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import controller as OC
+from oracle import fadi as OF
+from oracle import precond as OP
+from oracle.convdiff import convdiff_matrix
+from oracle.gmres_ref import block_gmres_iterate
+from paper_2312_02891_amd import workloads as WL
+
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2312_02891_amd import lradi
+    return lradi
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("dim,N,omega", [(2, 15, (8.0, -5.0)), (3, 7, (4.0, -2.0, 6.0))])
+@pytest.mark.parametrize("r,j,sweeps", [(1, 1, 0), (2, 3, 0), (4, 6, 0), (3, 4, 2), (8, 3, 1)])
+def test_first_cycle_equals_preconditioned_minres_definition(L, ctx, dim, N, omega, r, j, sweeps):
+    """restart = j, step cap j: the returned Z is the minimiser of
+    ||W - S Z||_F over M K_j(S M, W), with M the oracle's red-black ILU(0)
+    (plus sweeps), to 1e-9."""
+    say("precond first cycle", dim, N, r, j, sweeps)
+    H = L.convdiff(dim, N, omega)
+    A = convdiff_matrix(dim, N, omega)
+    W = np.random.default_rng(300 + r * 10 + j).standard_normal((H.n, r))
+    shift = -300.0
+    o = L.default_opts(restart=j, max_inner=j, precond="rbilu0", precond_sweeps=sweeps)
+    Zs, stats, st = ctx.shifted_solve([H], [shift], [to_dev(W)], [0.0], o)
+    Z = Zs[0].cpu().numpy()
+    want = block_gmres_iterate(A, shift, W, j, precond=lambda X: OP.rb_precond_apply(A, shift, X, sweeps))
+    assert stats[0]["steps"] == j
+    assert np.linalg.norm(Z - want) <= 1e-9 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shift", [-2.0e5, -3.0e3, -25.0])
+def test_preconditioned_solve_reaches_delta_with_fewer_steps(L, ctx, prec, shift):
+    """Config 2's A (n = 65536, r = 4): the FP64 residual of the returned
+    block is below delta (checked by the oracle's sparse product), and the
+    preconditioned solve needs fewer block steps than the plain one."""
+    P = WL.C2
+    H = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
+    W = np.random.default_rng(7).standard_normal((H.n, 4))
+    delta = 1e-9 * np.linalg.norm(W, 2)
+    steps = {}
+    for sweeps in (None, 0, 2):
+        kw = {} if sweeps is None else dict(precond="rbilu0", precond_sweeps=sweeps)
+        o = L.default_opts(precision=prec, restart=30, max_inner=6000, **kw)
+        Zs, stats, st = ctx.shifted_solve([H], [shift], [to_dev(W)], [delta], o)
+        Z = Zs[0].cpu().numpy()
+        rn = np.linalg.norm(W - (A @ Z + shift * Z), 2)
+        assert st == L.OK and stats[0]["status"] == 0
+        assert rn <= delta * (1 + 1e-8)
+        steps[sweeps] = stats[0]["steps"]
+    say("  steps plain / rbilu0 / +2 sweeps", prec, shift, steps[None], steps[0], steps[2])
+    assert steps[0] < steps[None] and steps[2] < steps[0]
+
+
+def test_preconditioned_batch_equals_solo_runs(L, ctx):
+    """Systems of different n, r, dimension and shift share launches with
+    the preconditioner; each result is bit-identical to its solo run."""
+    specs = [(2, 21, (4.0, -9.0), 1, -50.0), (2, 40, (-20.0, 3.0), 3, -900.0),
+             (3, 9, (2.0, 2.0, -1.0), 8, -120.0), (2, 64, (30.0, 30.0), 5, -4000.0)]
+    mats, Ws, shifts, deltas = [], [], [], []
+    for i, (dim, N, om, r, s) in enumerate(specs):
+        H = L.convdiff(dim, N, om)
+        mats.append(H)
+        Ws.append(to_dev(np.random.default_rng(400 + i).standard_normal((H.n, r))))
+        shifts.append(s)
+        deltas.append(1e-9 * float(np.linalg.norm(Ws[-1].cpu().numpy(), 2)))
+    o = L.default_opts(restart=12, max_inner=3000, precond="rbilu0", precond_sweeps=1)
+    Zb, sb, _ = ctx.shifted_solve(mats, shifts, Ws, deltas, o)
+    for i in range(len(specs)):
+        Zi, si, _ = ctx.shifted_solve([mats[i]], [shifts[i]], [Ws[i]], [deltas[i]], o)
+        assert si[0]["steps"] == sb[i]["steps"]
+        assert np.array_equal(Zi[0].cpu().numpy(), Zb[i].cpu().numpy())
+
+
+@pytest.mark.parametrize("name,precision,sweeps", [("SMALL_2D", "fp64", 0), ("SMALL_2D", "fp32", 2),
+                                                   ("SMALL_3D", "fp64", 2), ("SMALL_3D", "fp32", 0)])
+def test_adi_with_preconditioned_inner_solves_matches_oracle(L, ctx, name, precision, sweeps):
+    """Algorithm 1 with preconditioned inner solves: the oracle's steps
+    (+-1), X within 1e-6 of the direct-solve iterate, true residual below
+    tau, tolerances and gap estimates as the oracle's formulas."""
+    say("adi precond", name, precision, sweeps)
+    P = getattr(WL, name)
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
+    A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
+    B = convdiff_matrix(P.B.dim, P.B.N, P.B.omega)
+    f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+    pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+    o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps)
+    res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
+    assert res.status == L.OK
+    full = OF.fadi(A, B, f, g, pA, pB, tol=P.tol, kmax=100)
+    ora = OF.fadi(A, B, f, g, pA, pB, kfixed=res.k)
+    Z, d, Y = res.factors()
+    xerr = OF.lowrank_diff_fro(Z, d, Y, ora.Z, ora.D(), ora.Y) / OF.lowrank_fro(ora.Z, ora.D(), ora.Y)
+    true = OF.lowrank_residual_norm(A, B, f, g, Z, d, Y) / ora.norm_fg
+    say("  k", res.k, "oracle", full.k, "X err", xerr, "true", true)
+    assert abs(res.k - full.k) <= 1 and xerr <= 1e-6 and true <= P.tol
+    u = v = 0.0
+    eps = P.tol * res.norm_fg
+    for row in res.history():
+        dA, dB = OC.tolerances("mid", int(row[0]), row[10], row[11], u, v, eps)
+        assert row[2] == pytest.approx(dA, rel=1e-12) and row[3] == pytest.approx(dB, rel=1e-12)
+        assert row[4] <= row[2] * (1 + 1e-12) and row[5] <= row[3] * (1 + 1e-12)
+        u, v = OC.update_gap(u, v, row[14], row[12], row[13], row[4], row[5])
+
+
+def test_preconditioned_lyapunov_equals_its_oracle(L, ctx):
+    """The Lyapunov path with the preconditioner: X within 1e-6 of the
+    Lyapunov oracle, true residual below tau."""
+    from oracle import lyap as OL
+    P = WL.LYAP_SMALL
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
+    f, p = WL.lyap_inputs(P)
+    o = L.default_opts(tol=P.tol, selection="sym", precond="rbilu0", precond_sweeps=1)
+    res = ctx.solve_lyap(HA, to_dev(f), p, o)
+    ora = OL.lyap_adi(A, f, p, kfixed=res.k)
+    Z, d, _ = res.factors()
+    xerr = OF.lowrank_diff_fro(Z, d, Z, ora.Z, ora.D(), ora.Z) / OF.lowrank_fro(ora.Z, ora.D(), ora.Z)
+    true = OF.lowrank_residual_norm(A, A.T, f, f, Z, d, Z) / OF.lowrank_product_norm(f, f)
+    assert res.status == L.OK and xerr <= 1e-6 and true <= P.tol
+
+
+def test_preconditioner_argument_errors(L, ctx):
+    """A mass matrix with the preconditioner, a non-bipartite pattern and an
+    out-of-range sweep count give LRADI_EINVAL before any launch."""
+    P = WL.GEN_SMALL
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
+    HM = L.HostCsr(*WL.mass_csr(P.A.dim, P.A.N))
+    f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+    pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+    o = L.default_opts(precond="rbilu0")
+    with pytest.raises(L.LradiError) as e:
+        ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o, M=HM)
+    assert e.value.status == L.EINVAL
+    W = to_dev(np.ones((HM.n, 1)))
+    with pytest.raises(L.LradiError) as e:
+        ctx.shifted_solve([HM], [1.0], [W], [1e-8], o)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.LradiError) as e:
+        ctx.shifted_solve([HA], [-10.0], [to_dev(np.ones((HA.n, 1)))], [1e-8],
+                          L.default_opts(precond="rbilu0", precond_sweeps=17))
+    assert e.value.status == L.EINVAL
