@@ -314,7 +314,9 @@ struct SysWork {
                             mm * rr * rr * 8,          // yv
                             512 * 8,                   // sm
                             sweeps >= 0 ? (mm + 1) * n * rr * tsz : 0,  // P
-                            sweeps > 0 ? n * rr * tsz : 0};             // Q
+                            sweeps > 0 ? n * rr * tsz : 0,              // Yb
+                            sweeps > 0 ? n * rr * tsz : 0,              // Eb
+                            sweeps > 0 ? n * tsz : 0};                  // It
     size_t total = 0;
     for (size_t z : sizes) total += align256(z);
     LRADI_TRY(buf.alloc(total));
@@ -360,7 +362,11 @@ struct SysWork {
     if (sweeps >= 0) {
       if (!A->has_rb()) return set_error("preconditioner data missing"), LRADI_EINVAL;
       d.P = take(sizes[13]);
-      d.Q = sweeps > 0 ? take(sizes[14]) : nullptr;
+      if (sweeps > 0) {
+        d.Yb = take(sizes[14]);
+        d.Eb = take(sizes[15]);
+        d.It = take(sizes[16]);
+      }
       d.rbrows = A->rbrows.as<int>();
       d.nred = A->nred;
       d.sweeps = sweeps;
@@ -979,7 +985,7 @@ size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lra
   auto inner = [&](size_t rows) {
     const size_t rpw = (size_t)choose_rows_per_wg((int)rows), nwg = (rows + rpw - 1) / rpw;
     // preconditioned: the basis P_0..P_m, a sweep block, colour order, diagonal
-    const size_t pre = sw < 0 ? 0 : (mm + 1 + (sw > 0 ? 1 : 0)) * rows * r * tsz + rows * (4 + 8 + tsz);
+    const size_t pre = sw < 0 ? 0 : (mm + 1 + (sw > 0 ? 2 : 0)) * rows * r * tsz + rows * (4 + 8 + 2 * tsz);
     return (mm + 2) * rows * r * tsz + rows * r * 8 + nwg * ((mm + 1) * r * r + 2 * kPS) * 8 +
            (mm * r) * (mm * r) * 8 + 16 * (mm + 1) * r * r * 8 + 12 * 256 + 4096 + pre;
   };

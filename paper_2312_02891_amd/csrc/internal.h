@@ -158,7 +158,9 @@ struct SysDesc {
   const void* diagT;    // diagonal of A per row, basis precision
   const void* tvalT;    // per nonzero (i, j): A's entry (j, i), basis precision
   void* P;              // preconditioned basis blocks P_0..P_m, basis precision
-  void* Q;              // one block of scratch for the sweeps, basis precision
+  void* Yb;             // sweeps: y of the black rows, n x r, basis precision
+  void* Eb;             // sweeps: D_r^{-1} E z of the red rows, n x r
+  void* It;             // sweeps: 1 / diag(T) per black row, n
 };
 
 // Mutable device-side control block of one inner solve.

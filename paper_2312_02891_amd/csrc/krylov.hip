@@ -272,12 +272,17 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
 //    (PH_ARNOLDI, systems with rbrows): red-black ILU(0) of S = A + s I,
 //    S = [D_r E; F D_b] with the rows 2-coloured (every off-diagonal entry
 //    joins a red and a black row), T = D_b - F D_r^{-1} E:
-//      fwd    (black rows)  y_b = v_b - F D_r^{-1} v_r,  z_b = y_b / diag(T)
-//      sweep  (black rows)  z_b += (y_b - T z_b) / diag(T)      (sweeps times)
-//      back   (red rows)    z_r = (v_r - E z_b) / diag(D_r)
-//    A workgroup's row chunk indexes the colour-ordered row list.  With k
-//    sweeps the k + 1 black iterates alternate between Q and P_j so that
-//    the last one lands in P_j.
+//      fwd   (black)  y = v_b - F D_r^{-1} v_r, 1/diag(T), z = y / diag(T)
+//      per sweep:
+//        red   (red)    e = D_r^{-1} E z
+//        black (black)  z += (y - D_b z + F e) / diag(T)      (= y - T z)
+//      back  (red)    z_r = D_r^{-1} (v_r - E z)
+//    A workgroup's row chunk indexes the colour-ordered row list.  The
+//    black iterate lives in the black rows of P_j and is updated in place
+//    (a black row reads only its own old value and the red e); y, e and
+//    1/diag(T) are per-system scratch blocks.  All gathers of a row are
+//    issued together (clamped indices, selected contributions), and each
+//    row sums its terms in CSR order.
 template <typename T>
 struct RbCtx {
   const int* rp;
@@ -300,95 +305,135 @@ __device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
   return x;
 }
 
-__device__ inline void* rb_buf(const SysDesc& D, int j, int t) {
-  const size_t blk = (size_t)D.n * D.r * (D.precision == LRADI_FP64 ? 8 : 4);
-  return ((D.sweeps - t) % 2 == 0) ? static_cast<char*>(D.P) + (size_t)j * blk : D.Q;
+constexpr int kRbUnroll = 8;
+
+// acc += sum over row i's off-diagonal entries of a_ik X[k]
+template <typename T, int R>
+__device__ inline void rb_gather(const RbCtx<T>& x, int i, const T* __restrict__ X, T (&acc)[R]) {
+  const int k0 = x.rp[i], k1 = x.rp[i + 1];
+  for (int k = k0; k < k1; k += kRbUnroll) {
+    int col[kRbUnroll];
+    T a[kRbUnroll];
+    bool ok[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const int kk = min(k + u, k1 - 1);
+      col[u] = x.ci[kk];
+      a[u] = x.val[kk];
+      ok[u] = (k + u < k1) && col[u] != i;
+    }
+    T xv[kRbUnroll][R];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < R; ++q) xv[u][q] = X[(size_t)col[u] * R + q];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = ok[u] ? acc[q] + a[u] * xv[u][q] : acc[q];
+  }
 }
 
-// y_b and diag(T) of black row i (its off-diagonal neighbours are red);
-// with Z: also (T z)_i = (d_i + s) z_i - sum_j a_ij/(d_j + s) sum_l a_jl z_l
-template <typename T, int R, bool TZ>
-__device__ inline void rb_black_row(const RbCtx<T>& x, int i, const T* __restrict__ V,
-                                    const T* __restrict__ Z, T (&y)[R], T& tdiag, T (&tz)[R]) {
-  const T di = x.dg[i] + x.sh;
+// black row i: y = v_i - sum_j a_ij v_j / (d_j + s), diag(T)_i = d_i + s -
+// sum_j a_ij a_ji / (d_j + s)
+template <typename T, int R>
+__device__ inline void rb_black_fwd(const RbCtx<T>& x, int i, const T* __restrict__ V, T (&y)[R], T& td) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    y[q] = V[(size_t)i * R + q];
-    if constexpr (TZ) tz[q] = di * Z[(size_t)i * R + q];
+  for (int q = 0; q < R; ++q) y[q] = V[(size_t)i * R + q];
+  td = x.dg[i] + x.sh;
+  const int k0 = x.rp[i], k1 = x.rp[i + 1];
+  for (int k = k0; k < k1; k += kRbUnroll) {
+    int col[kRbUnroll];
+    T a[kRbUnroll], t[kRbUnroll], dj[kRbUnroll];
+    bool ok[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const int kk = min(k + u, k1 - 1);
+      col[u] = x.ci[kk];
+      a[u] = x.val[kk];
+      t[u] = x.tv[kk];
+      ok[u] = (k + u < k1) && col[u] != i;
+    }
+    T xv[kRbUnroll][R];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      dj[u] = x.dg[col[u]];
+#pragma unroll
+      for (int q = 0; q < R; ++q) xv[u][q] = V[(size_t)col[u] * R + q];
+    }
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const T w = a[u] / (dj[u] + x.sh);
+      td = ok[u] ? td - w * t[u] : td;
+#pragma unroll
+      for (int q = 0; q < R; ++q) y[q] = ok[u] ? y[q] - w * xv[u][q] : y[q];
+    }
   }
-  tdiag = di;
-  for (int k = x.rp[i]; k < x.rp[i + 1]; ++k) {
-    const int j = x.ci[k];
-    if (j == i) continue;
-    const T w = x.val[k] / (x.dg[j] + x.sh);
-    tdiag -= w * x.tv[k];
+}
+
+struct RbBufs {
+  void* Pj;
+  void* Y;
+  void* E;
+  void* It;
+};
+
+template <typename T, int R>
+__device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, const RbBufs& b,
+                               int stage) {
+  T* Pj = static_cast<T*>(b.Pj);
+  T* Y = static_cast<T*>(b.Y);
+  T* E = static_cast<T*>(b.E);
+  T* It = static_cast<T*>(b.It);
+  const int nb = D.n - D.nred;
+  const bool black = stage == 0 || (stage <= 2 * D.sweeps && stage % 2 == 0);
+  const int* rows = black ? D.rbrows + D.nred : D.rbrows;
+  const int cnt = black ? nb : D.nred;
+  for (int p = c.row0 + threadIdx.x; p < min(c.row1, cnt); p += kTPB) {
+    const int i = rows[p];
+    if (stage == 0) {
+      T y[R], td;
+      rb_black_fwd<T, R>(x, i, V, y, td);
+      const T it = T(1) / td;
 #pragma unroll
-    for (int q = 0; q < R; ++q) y[q] -= w * V[(size_t)j * R + q];
-    if constexpr (TZ) {
-      T ez[R];
+      for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = y[q] * it;
+      if (D.sweeps > 0) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) ez[q] = T(0);
-      for (int kk = x.rp[j]; kk < x.rp[j + 1]; ++kk) {
-        const int l = x.ci[kk];
-        if (l == j) continue;
-        const T a = x.val[kk];
-#pragma unroll
-        for (int q = 0; q < R; ++q) ez[q] += a * Z[(size_t)l * R + q];
+        for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = y[q];
+        It[i] = it;
       }
+    } else if (stage > 2 * D.sweeps) {  // back: z_r = (v_r - E z) / (d_r + s)
+      T g[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) tz[q] -= w * ez[q];
+      for (int q = 0; q < R; ++q) g[q] = T(0);
+      rb_gather<T, R>(x, i, Pj, g);
+      const T di = x.dg[i] + x.sh;
+#pragma unroll
+      for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = (V[(size_t)i * R + q] - g[q]) / di;
+    } else if (!black) {  // red: e = (E z)_i / (d_i + s)
+      T g[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) g[q] = T(0);
+      rb_gather<T, R>(x, i, Pj, g);
+      const T di = x.dg[i] + x.sh;
+#pragma unroll
+      for (int q = 0; q < R; ++q) E[(size_t)i * R + q] = g[q] / di;
+    } else {  // black: z += (y - (d_i + s) z + F e) / diag(T)
+      T g[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) g[q] = T(0);
+      rb_gather<T, R>(x, i, E, g);
+      const T di = x.dg[i] + x.sh, it = It[i];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const T z = Pj[(size_t)i * R + q];
+        Pj[(size_t)i * R + q] = z + (Y[(size_t)i * R + q] - di * z + g[q]) * it;
+      }
     }
   }
 }
 
-template <typename T, int R>
-__device__ inline void rb_fwd_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* dst) {
-  const int nb = D.n - D.nred;
-  const int* rows = D.rbrows + D.nred;
-  for (int p = c.row0 + threadIdx.x; p < min(c.row1, nb); p += kTPB) {
-    const int i = rows[p];
-    T y[R], tz[R], td;
-    rb_black_row<T, R, false>(x, i, V, nullptr, y, td, tz);
-#pragma unroll
-    for (int q = 0; q < R; ++q) dst[(size_t)i * R + q] = y[q] / td;
-  }
-}
-
-template <typename T, int R>
-__device__ inline void rb_sweep_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V,
-                                     const T* src, T* dst) {
-  const int nb = D.n - D.nred;
-  const int* rows = D.rbrows + D.nred;
-  for (int p = c.row0 + threadIdx.x; p < min(c.row1, nb); p += kTPB) {
-    const int i = rows[p];
-    T y[R], tz[R], td;
-    rb_black_row<T, R, true>(x, i, V, src, y, td, tz);
-#pragma unroll
-    for (int q = 0; q < R; ++q) dst[(size_t)i * R + q] = src[(size_t)i * R + q] + (y[q] - tz[q]) / td;
-  }
-}
-
-template <typename T, int R>
-__device__ inline void rb_back_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj) {
-  for (int p = c.row0 + threadIdx.x; p < min(c.row1, D.nred); p += kTPB) {
-    const int i = D.rbrows[p];
-    T z[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) z[q] = V[(size_t)i * R + q];
-    for (int k = x.rp[i]; k < x.rp[i + 1]; ++k) {
-      const int l = x.ci[k];
-      if (l == i) continue;
-      const T a = x.val[k];
-#pragma unroll
-      for (int q = 0; q < R; ++q) z[q] -= a * Pj[(size_t)l * R + q];
-    }
-    const T di = x.dg[i] + x.sh;
-#pragma unroll
-    for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = z[q] / di;
-  }
-}
-
-// stage 0: fwd; 1..sweeps: sweep t; sweeps + 1: back
+// stage 0: fwd; 2t - 1, 2t: red and black halves of sweep t; 2 sweeps + 1: back
 template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap, int stage) {
@@ -397,18 +442,10 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   if (ctl[c.s].phase != PH_ARNOLDI || !D.rbrows) return;
   const int j = ctl[c.s].j;
   const RbCtx<T> x = rb_ctx<T>(D, ctl[c.s].shift);
-  const T* V = static_cast<const T*>(D.V) + (size_t)j * D.n * D.r;
-  if (stage == 0) {
-    T* dst = static_cast<T*>(rb_buf(D, j, 0));
-    LRADI_RSEL(RF, D.r, rb_fwd_rows<T, RR>(D, c, x, V, dst));
-  } else if (stage <= D.sweeps) {
-    const T* src = static_cast<const T*>(rb_buf(D, j, stage - 1));
-    T* dst = static_cast<T*>(rb_buf(D, j, stage));
-    LRADI_RSEL(RF, D.r, rb_sweep_rows<T, RR>(D, c, x, V, src, dst));
-  } else {
-    T* Pj = static_cast<T*>(rb_buf(D, j, D.sweeps));
-    LRADI_RSEL(RF, D.r, rb_back_rows<T, RR>(D, c, x, V, Pj));
-  }
+  const size_t blk = (size_t)D.n * D.r;
+  const T* V = static_cast<const T*>(D.V) + (size_t)j * blk;
+  const RbBufs b{static_cast<T*>(D.P) + (size_t)j * blk, D.Yb, D.Eb, D.It};
+  LRADI_RSEL(RF, D.r, rb_rows<T, RR>(D, c, x, V, b, stage));
 }
 
 // ---------------------------------------------------------------------------
@@ -1256,7 +1293,7 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
   if (b.precond)
-    for (int stage = 0; stage <= b.sweeps + 1; ++stage)
+    for (int stage = 0; stage <= 2 * b.sweeps + 1; ++stage)
       hipLaunchKernelGGL((k_precond<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
