@@ -147,7 +147,7 @@ typedef struct {
                           latter needs M = C = I and a bipartite sparsity
                           graph (else LRADI_EINVAL)                        */
   int32_t precond_sweeps; /* LRADI_PRECOND_RBILU0: Jacobi sweeps on the
-                          Schur complement after the ILU(0) step, 0..16  */
+                          Schur complement after the ILU(0) step, 0..64  */
   int32_t reserved[1];
 } lradi_opts;
 

@@ -316,7 +316,9 @@ struct SysWork {
                             sweeps >= 0 ? (mm + 1) * n * rr * tsz : 0,  // P
                             sweeps > 0 ? n * rr * tsz : 0,              // Yb
                             sweeps > 0 ? n * rr * tsz : 0,              // Eb
-                            sweeps > 0 ? n * tsz : 0};                  // It
+                            sweeps > 0 ? n * tsz : 0,                   // It
+                            sweeps > 0 ? (size_t)A->t2w * std::max(n - (size_t)A->nred, (size_t)1) * tsz
+                                       : 0};                            // t2val
     size_t total = 0;
     for (size_t z : sizes) total += align256(z);
     LRADI_TRY(buf.alloc(total));
@@ -366,12 +368,22 @@ struct SysWork {
         d.Yb = take(sizes[14]);
         d.Eb = take(sizes[15]);
         d.It = take(sizes[16]);
+        d.t2val = take(sizes[17]);
       }
+      d.t2w = A->t2w;
+      d.tpw = A->tpw;
+      d.t2ci = A->t2ci.as<int>();
+      d.pslot = A->pslot.as<int>();
+      d.pj = A->pj.as<int>();
+      d.pcT = (prec == LRADI_FP64) ? (const void*)A->pc64.p : (const void*)A->pc32.p;
       d.rbrows = A->rbrows.as<int>();
       d.nred = A->nred;
       d.sweeps = sweeps;
       d.diagT = (prec == LRADI_FP64) ? (const void*)A->diag64.p : (const void*)A->diag32.p;
-      d.tvalT = (prec == LRADI_FP64) ? (const void*)A->tval64.p : (const void*)A->tval32.p;
+      d.rbw = A->rbw;
+      d.ellci = A->ellci.as<int>();
+      d.ellvalT = (prec == LRADI_FP64) ? (const void*)A->ellval64.p : (const void*)A->ellval32.p;
+      d.elltvT = (prec == LRADI_FP64) ? (const void*)A->elltv64.p : (const void*)A->elltv32.p;
     }
     c = SysCtl{};
     c.phase = PH_FINISHED;  // armed by the caller or by the outer kernels
@@ -693,8 +705,8 @@ int check_opts(const lradi_opts& o) {
     return set_error("spmm_lanes must be -1, 0, 1, 2 or 4"), LRADI_EINVAL;
   if (o.precond != LRADI_PRECOND_NONE && o.precond != LRADI_PRECOND_RBILU0)
     return set_error("unknown preconditioner"), LRADI_EINVAL;
-  if (o.precond_sweeps < 0 || o.precond_sweeps > 16)
-    return set_error("precond_sweeps must be in 0..16"), LRADI_EINVAL;
+  if (o.precond_sweeps < 0 || o.precond_sweeps > 64)
+    return set_error("precond_sweeps must be in 0..64"), LRADI_EINVAL;
   return LRADI_OK;
 }
 
@@ -773,35 +785,121 @@ int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
   const int nr = (int)rows.size();
   for (int i = 0; i < nn; ++i)
     if (col[i] == 1) rows.push_back(i);
-  // diagonal per row and, per nonzero (i, j), the entry (j, i) (row i of A^T)
-  std::vector<double> dg(nn, 0.0), tvals(std::max<size_t>(ci.size(), 1), 0.0);
+  // diagonal per row; off-diagonal entries (col, a_i,col, a_col,i) per colour
+  // position in rbw slots, the transposed value from row i of A^T
+  std::vector<double> dg(nn, 0.0);
+  int w = 0;
   for (int i = 0; i < nn; ++i) {
+    int c = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
       if (ci[k] == i) dg[i] += v[k];
+      else ++c;
+    }
+    w = std::max(w, c);
+  }
+  const int W = std::max(w, 1);
+  std::vector<int32_t> eci((size_t)W * nn);
+  std::vector<double> eval((size_t)W * nn, 0.0), etv((size_t)W * nn, 0.0);
+  for (int p = 0; p < nn; ++p) {
+    const int i = rows[p];
+    int u = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] == i) continue;
       double a = 0.0;
       for (int32_t kk = trp[i]; kk < trp[i + 1]; ++kk)
         if (tci[kk] == ci[k]) a += tv[kk];
-      tvals[k] = a;
+      eci[(size_t)u * nn + p] = ci[k];
+      eval[(size_t)u * nn + p] = v[k];
+      etv[(size_t)u * nn + p] = a;
+      ++u;
+    }
+    for (; u < W; ++u) eci[(size_t)u * nn + p] = i;
+  }
+  // Schur complement T = D_b - F D_r^{-1} E on the black rows: its
+  // off-diagonal columns (distinct two-hop black neighbours l != i, in order
+  // of first appearance) and the paths i -> j -> l with coefficient
+  // a_ij a_jl
+  const int nbk = nn - nr;
+  std::vector<std::vector<int32_t>> tcols(nbk);
+  std::vector<std::vector<std::array<double, 3>>> paths(nbk);  // (slot, j, a_ij a_jl)
+  int w2 = 0, wp = 0;
+  for (int pb = 0; pb < nbk; ++pb) {
+    const int i = rows[nr + pb];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      if (j == i) continue;
+      for (int32_t kk = rp[j]; kk < rp[j + 1]; ++kk) {
+        const int l = ci[kk];
+        if (l == j || l == i) continue;
+        int slot = -1;
+        for (size_t q = 0; q < tcols[pb].size(); ++q)
+          if (tcols[pb][q] == l) slot = (int)q;
+        if (slot < 0) {
+          slot = (int)tcols[pb].size();
+          tcols[pb].push_back(l);
+        }
+        paths[pb].push_back({(double)slot, (double)j, v[k] * v[kk]});
+      }
+    }
+    w2 = std::max(w2, (int)tcols[pb].size());
+    wp = std::max(wp, (int)paths[pb].size());
+  }
+  const int W2 = std::max(w2, 1), WP = std::max(wp, 1);
+  const size_t nbs = (size_t)std::max(nbk, 1);
+  std::vector<int32_t> h_t2ci(W2 * nbs), h_pslot(WP * nbs, -1), h_pj(WP * nbs, 0);
+  std::vector<double> h_pc(WP * nbs, 0.0);
+  for (int pb = 0; pb < nbk; ++pb) {
+    const int i = rows[nr + pb];
+    for (int q = 0; q < W2; ++q)
+      h_t2ci[(size_t)q * nbs + pb] = q < (int)tcols[pb].size() ? tcols[pb][q] : i;
+    for (size_t q = 0; q < paths[pb].size(); ++q) {
+      h_pslot[q * nbs + pb] = (int32_t)paths[pb][q][0];
+      h_pj[q * nbs + pb] = (int32_t)paths[pb][q][1];
+      h_pc[q * nbs + pb] = paths[pb][q][2];
     }
   }
+  LRADI_TRY(t2ci.alloc(sizeof(int32_t) * h_t2ci.size()));
+  LRADI_TRY(pslot.alloc(sizeof(int32_t) * h_pslot.size()));
+  LRADI_TRY(pj.alloc(sizeof(int32_t) * h_pj.size()));
+  LRADI_TRY(pc64.alloc(sizeof(double) * h_pc.size()));
+  LRADI_HIP(hipMemcpyAsync(t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(pslot.p, h_pslot.data(), sizeof(int32_t) * h_pslot.size(), hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(pj.p, h_pj.data(), sizeof(int32_t) * h_pj.size(), hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(pc64.p, h_pc.data(), sizeof(double) * h_pc.size(), hipMemcpyHostToDevice, st));
+  if (need32) {
+    LRADI_TRY(pc32.alloc(sizeof(float) * h_pc.size()));
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((h_pc.size() + 255) / 256)), dim3(256), 0, st, pc64.as<double>(),
+                       pc32.as<float>(), (int64_t)h_pc.size());
+  }
+  const size_t ne = (size_t)W * nn;
   LRADI_TRY(rbrows.alloc(sizeof(int32_t) * nn));
   LRADI_TRY(diag64.alloc(sizeof(double) * nn));
-  LRADI_TRY(tval64.alloc(sizeof(double) * tvals.size()));
+  LRADI_TRY(ellci.alloc(sizeof(int32_t) * ne));
+  LRADI_TRY(ellval64.alloc(sizeof(double) * ne));
+  LRADI_TRY(elltv64.alloc(sizeof(double) * ne));
   LRADI_HIP(hipMemcpyAsync(rbrows.p, rows.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(diag64.p, dg.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(tval64.p, tvals.data(), sizeof(double) * tvals.size(), hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(ellci.p, eci.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(ellval64.p, eval.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(elltv64.p, etv.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
   if (need32) {
     LRADI_TRY(diag32.alloc(sizeof(float) * nn));
-    LRADI_TRY(tval32.alloc(sizeof(float) * tvals.size()));
+    LRADI_TRY(ellval32.alloc(sizeof(float) * ne));
+    LRADI_TRY(elltv32.alloc(sizeof(float) * ne));
     const int tpb = 256;
     hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + tpb - 1) / tpb)), dim3(tpb), 0, st, diag64.as<double>(),
                        diag32.as<float>(), (int64_t)nn);
-    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((tvals.size() + tpb - 1) / tpb)), dim3(tpb), 0, st,
-                       tval64.as<double>(), tval32.as<float>(), (int64_t)tvals.size());
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, ellval64.as<double>(),
+                       ellval32.as<float>(), (int64_t)ne);
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, elltv64.as<double>(),
+                       elltv32.as<float>(), (int64_t)ne);
     LRADI_HIP(hipGetLastError());
   }
   LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
   nred = nr;
+  rbw = W;
+  t2w = W2;
+  tpw = WP;
   return LRADI_OK;
 }
 
@@ -979,7 +1077,8 @@ size_t prob_footprint(int n, int m, int r, int64_t nnzA, int64_t nnzB, const lra
   auto mat = [&](int64_t nrow, int64_t nnz) {
     // (the preconditioner keeps transposed values beside the matrix)
     const size_t vals = (size_t)nnz * (8 + (tsz == 4 ? 4 : 0));
-    return (size_t)(nrow + 1) * 4 + (size_t)nnz * 4 + vals * (sweeps_for(o) >= 0 ? 2 : 1);
+    return (size_t)(nrow + 1) * 4 + (size_t)nnz * 4 + vals +
+           (sweeps_for(o) >= 0 ? (size_t)nnz * 4 + 2 * vals : 0);
   };
   const int sw = sweeps_for(o);
   auto inner = [&](size_t rows) {
@@ -1295,7 +1394,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
   if (o.restart < 1 || o.restart > kMaxM || o.max_inner < 1 ||
       (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER) ||
       (o.precond != LRADI_PRECOND_NONE && o.precond != LRADI_PRECOND_RBILU0) || o.precond_sweeps < 0 ||
-      o.precond_sweeps > 16)
+      o.precond_sweeps > 64)
     return set_error("lradi_shifted_solve: bad options"), LRADI_EINVAL;
   const int sw = sweeps_for(o);
   LRADI_HIP(hipSetDevice(c->device));

@@ -156,11 +156,28 @@ struct SysDesc {
   int nred;             // number of red rows
   int sweeps;           // Jacobi sweeps on the Schur complement
   const void* diagT;    // diagonal of A per row, basis precision
-  const void* tvalT;    // per nonzero (i, j): A's entry (j, i), basis precision
+  // off-diagonal entries by colour position p (row rbrows[p]), rbw slots
+  // each, slot-major (slot u of position p at u * n + p); unused slots hold
+  // the row itself with value 0
+  int rbw;
+  const int* ellci;
+  const void* ellvalT;  // A's entry (i, col), basis precision
+  const void* elltvT;   // A's entry (col, i), basis precision
   void* P;              // preconditioned basis blocks P_0..P_m, basis precision
   void* Yb;             // sweeps: y of the black rows, n x r, basis precision
-  void* Eb;             // sweeps: D_r^{-1} E z of the red rows, n x r
+  void* Eb;             // sweeps: the other black iterate, n x r
   void* It;             // sweeps: 1 / diag(T) per black row, n
+  // sweeps: the off-diagonal entries of T = D_b - F D_r^{-1} E by black
+  // position (pb = p - nred), slot-major with nb = n - nred: columns t2ci
+  // (t2w slots, unused: the row itself), values t2val (rebuilt for each
+  // shift), and the two-hop paths that make them: path v of black position
+  // pb adds -pc / (d_j + s) with j = pj to slot pslot
+  int t2w, tpw;
+  const int* t2ci;
+  const int* pslot;
+  const int* pj;
+  const void* pcT;
+  void* t2val;
 };
 
 // Mutable device-side control block of one inner solve.
@@ -229,8 +246,9 @@ struct DevCSR {
   DevBuf rowptr, colind, val64, val32;
   DevBuf mval64, mval32;  // the mass matrix of a pencil, on the same pattern
   // red-black preconditioner data (prepare_rb)
-  DevBuf rbrows, diag64, diag32, tval64, tval32;
-  int nred = -1;
+  DevBuf rbrows, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32;
+  DevBuf t2ci, pslot, pj, pc64, pc32;
+  int nred = -1, rbw = 0, t2w = 0, tpw = 0;
   int upload(const lradi_csr* A, hipStream_t st, bool need32);
   // the pencil (A, M): union pattern, A's values and M's values
   int upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);

@@ -272,55 +272,54 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
 //    (PH_ARNOLDI, systems with rbrows): red-black ILU(0) of S = A + s I,
 //    S = [D_r E; F D_b] with the rows 2-coloured (every off-diagonal entry
 //    joins a red and a black row), T = D_b - F D_r^{-1} E:
-//      fwd   (black)  y = v_b - F D_r^{-1} v_r, 1/diag(T), z = y / diag(T)
-//      per sweep:
-//        red   (red)    e = D_r^{-1} E z
-//        black (black)  z += (y - D_b z + F e) / diag(T)      (= y - T z)
-//      back  (red)    z_r = D_r^{-1} (v_r - E z)
-//    A workgroup's row chunk indexes the colour-ordered row list.  The
-//    black iterate lives in the black rows of P_j and is updated in place
-//    (a black row reads only its own old value and the red e); y, e and
-//    1/diag(T) are per-system scratch blocks.  All gathers of a row are
-//    issued together (clamped indices, selected contributions), and each
-//    row sums its terms in CSR order.
+//      fwd    (black)  y = v_b - F D_r^{-1} v_r, 1/diag(T), z = y / diag(T)
+//      sweep  (black)  z <- (y - T_off z) / diag(T)        (sweeps times)
+//      back   (red)    z_r = D_r^{-1} (v_r - E z)
+//    T_off (T without its diagonal, the two-hop black couplings) is built
+//    explicitly once per inner solve, so a sweep is one one-hop launch.  A
+//    workgroup's row chunk indexes the colour-ordered row list; the black
+//    iterates alternate between P_j and a scratch block.  All gathers of a
+//    row are issued together (clamped indices, selected contributions), and
+//    each row sums its terms in a fixed order.
 template <typename T>
 struct RbCtx {
-  const int* rp;
-  const int* ci;
+  const int* ci;  // slot-major colour-position table (rbw slots)
   const T* val;
   const T* tv;
   const T* dg;
+  int w, n;
   T sh;
 };
 
 template <typename T>
 __device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
   RbCtx<T> x;
-  x.rp = D.rowptr;
-  x.ci = D.colind;
-  x.val = static_cast<const T*>(D.valT);
-  x.tv = static_cast<const T*>(D.tvalT);
+  x.ci = D.ellci;
+  x.val = static_cast<const T*>(D.ellvalT);
+  x.tv = static_cast<const T*>(D.elltvT);
   x.dg = static_cast<const T*>(D.diagT);
+  x.w = D.rbw;
+  x.n = D.n;
   x.sh = (T)shift;
   return x;
 }
 
 constexpr int kRbUnroll = 8;
 
-// acc += sum over row i's off-diagonal entries of a_ik X[k]
+// acc += sum over the off-diagonal entries of row i (colour position p) of
+// a_ik X[k]; unused slots (col == i) are skipped by selection
 template <typename T, int R>
-__device__ inline void rb_gather(const RbCtx<T>& x, int i, const T* __restrict__ X, T (&acc)[R]) {
-  const int k0 = x.rp[i], k1 = x.rp[i + 1];
-  for (int k = k0; k < k1; k += kRbUnroll) {
+__device__ inline void rb_gather(const RbCtx<T>& x, int p, int i, const T* __restrict__ X, T (&acc)[R]) {
+  for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
     int col[kRbUnroll];
     T a[kRbUnroll];
     bool ok[kRbUnroll];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const int kk = min(k + u, k1 - 1);
-      col[u] = x.ci[kk];
-      a[u] = x.val[kk];
-      ok[u] = (k + u < k1) && col[u] != i;
+      const size_t e = (size_t)min(u0 + u, x.w - 1) * x.n + p;
+      col[u] = x.ci[e];
+      a[u] = x.val[e];
+      ok[u] = (u0 + u < x.w) && col[u] != i;
     }
     T xv[kRbUnroll][R];
 #pragma unroll
@@ -334,25 +333,24 @@ __device__ inline void rb_gather(const RbCtx<T>& x, int i, const T* __restrict__
   }
 }
 
-// black row i: y = v_i - sum_j a_ij v_j / (d_j + s), diag(T)_i = d_i + s -
-// sum_j a_ij a_ji / (d_j + s)
+// black row i (position p): y = v_i - sum_j a_ij v_j / (d_j + s),
+// diag(T)_i = d_i + s - sum_j a_ij a_ji / (d_j + s)
 template <typename T, int R>
-__device__ inline void rb_black_fwd(const RbCtx<T>& x, int i, const T* __restrict__ V, T (&y)[R], T& td) {
+__device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __restrict__ V, T (&y)[R], T& td) {
 #pragma unroll
   for (int q = 0; q < R; ++q) y[q] = V[(size_t)i * R + q];
   td = x.dg[i] + x.sh;
-  const int k0 = x.rp[i], k1 = x.rp[i + 1];
-  for (int k = k0; k < k1; k += kRbUnroll) {
+  for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
     int col[kRbUnroll];
     T a[kRbUnroll], t[kRbUnroll], dj[kRbUnroll];
     bool ok[kRbUnroll];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const int kk = min(k + u, k1 - 1);
-      col[u] = x.ci[kk];
-      a[u] = x.val[kk];
-      t[u] = x.tv[kk];
-      ok[u] = (k + u < k1) && col[u] != i;
+      const size_t e = (size_t)min(u0 + u, x.w - 1) * x.n + p;
+      col[u] = x.ci[e];
+      a[u] = x.val[e];
+      t[u] = x.tv[e];
+      ok[u] = (u0 + u < x.w) && col[u] != i;
     }
     T xv[kRbUnroll][R];
 #pragma unroll
@@ -363,77 +361,115 @@ __device__ inline void rb_black_fwd(const RbCtx<T>& x, int i, const T* __restric
     }
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const T w = a[u] / (dj[u] + x.sh);
-      td = ok[u] ? td - w * t[u] : td;
+      const T wgt = a[u] / (dj[u] + x.sh);
+      td = ok[u] ? td - wgt * t[u] : td;
 #pragma unroll
-      for (int q = 0; q < R; ++q) y[q] = ok[u] ? y[q] - w * xv[u][q] : y[q];
+      for (int q = 0; q < R; ++q) y[q] = ok[u] ? y[q] - wgt * xv[u][q] : y[q];
     }
   }
 }
 
-struct RbBufs {
-  void* Pj;
-  void* Y;
-  void* E;
-  void* It;
-};
+// T's off-diagonal values of black position pb for the current shift:
+// slot u = -sum of a_ij a_jl / (d_j + s) over the paths i -> j -> l that end
+// in that slot, in path order (once per inner solve: the shift is fixed)
+template <typename T>
+__device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int pb, int nb) {
+  const T* pc = static_cast<const T*>(D.pcT);
+  T* tv = static_cast<T*>(D.t2val);
+  for (int u = 0; u < D.t2w; ++u) tv[(size_t)u * nb + pb] = T(0);
+  for (int v = 0; v < D.tpw; ++v) {
+    const size_t e = (size_t)v * nb + pb;
+    const int slot = D.pslot[e];
+    if (slot < 0) break;
+    const int j = D.pj[e];
+    tv[(size_t)slot * nb + pb] -= pc[e] / (x.dg[j] + x.sh);
+  }
+}
 
+// one Jacobi sweep on T z = y for black position pb (row i):
+// dst_i = (y_i - sum_u T_il(u) src_l(u)) / diag(T)_i
 template <typename T, int R>
-__device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, const RbBufs& b,
-                               int stage) {
-  T* Pj = static_cast<T*>(b.Pj);
-  T* Y = static_cast<T*>(b.Y);
-  T* E = static_cast<T*>(b.E);
-  T* It = static_cast<T*>(b.It);
+__device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, int i, const T* __restrict__ src,
+                                    T* __restrict__ dst) {
+  const T* tv = static_cast<const T*>(D.t2val);
+  const T* Y = static_cast<const T*>(D.Yb);
+  T acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)i * R + q];
+  for (int u0 = 0; u0 < D.t2w; u0 += kRbUnroll) {
+    int col[kRbUnroll];
+    T a[kRbUnroll];
+    bool ok[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const size_t e = (size_t)min(u0 + u, D.t2w - 1) * nb + pb;
+      col[u] = D.t2ci[e];
+      a[u] = tv[e];
+      ok[u] = (u0 + u < D.t2w) && col[u] != i;
+    }
+    T xv[kRbUnroll][R];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < R; ++q) xv[u][q] = src[(size_t)col[u] * R + q];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
+  }
+  const T it = static_cast<const T*>(D.It)[i];
+#pragma unroll
+  for (int q = 0; q < R; ++q) dst[(size_t)i * R + q] = acc[q] * it;
+}
+
+// the black iterate of sweep t lives in P_j or in Eb, so that the last one
+// (t = sweeps) lands in P_j
+template <typename T>
+__device__ inline T* rb_iter(const SysDesc& D, T* Pj, int t) {
+  return ((D.sweeps - t) % 2 == 0) ? Pj : static_cast<T*>(D.Eb);
+}
+
+// stage 0: fwd (black rows; builds T's values at the first Arnoldi step of
+// an inner solve); 1..sweeps: Jacobi sweep t (black rows); sweeps + 1: back
+// (red rows)
+template <typename T, int R>
+__device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj,
+                               int stage, bool build) {
   const int nb = D.n - D.nred;
-  const bool black = stage == 0 || (stage <= 2 * D.sweeps && stage % 2 == 0);
-  const int* rows = black ? D.rbrows + D.nred : D.rbrows;
+  const bool black = stage <= D.sweeps;
+  const int off = black ? D.nred : 0;
   const int cnt = black ? nb : D.nred;
-  for (int p = c.row0 + threadIdx.x; p < min(c.row1, cnt); p += kTPB) {
-    const int i = rows[p];
+  for (int pp = c.row0 + threadIdx.x; pp < min(c.row1, cnt); pp += kTPB) {
+    const int p = off + pp;  // colour position
+    const int i = D.rbrows[p];
     if (stage == 0) {
       T y[R], td;
-      rb_black_fwd<T, R>(x, i, V, y, td);
+      rb_black_fwd<T, R>(x, p, i, V, y, td);
       const T it = T(1) / td;
+      T* z0 = rb_iter<T>(D, Pj, 0);
 #pragma unroll
-      for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = y[q] * it;
+      for (int q = 0; q < R; ++q) z0[(size_t)i * R + q] = y[q] * it;
       if (D.sweeps > 0) {
+        T* Y = static_cast<T*>(D.Yb);
 #pragma unroll
         for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = y[q];
-        It[i] = it;
+        static_cast<T*>(D.It)[i] = it;
+        if (build) rb_build_t<T>(D, x, pp, nb);
       }
-    } else if (stage > 2 * D.sweeps) {  // back: z_r = (v_r - E z) / (d_r + s)
+    } else if (black) {
+      rb_sweep_row<T, R>(D, pp, nb, i, rb_iter<T>(D, Pj, stage - 1), rb_iter<T>(D, Pj, stage));
+    } else {  // back: z_r = (v_r - E z) / (d_r + s)
       T g[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) g[q] = T(0);
-      rb_gather<T, R>(x, i, Pj, g);
+      rb_gather<T, R>(x, p, i, Pj, g);
       const T di = x.dg[i] + x.sh;
 #pragma unroll
       for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = (V[(size_t)i * R + q] - g[q]) / di;
-    } else if (!black) {  // red: e = (E z)_i / (d_i + s)
-      T g[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) g[q] = T(0);
-      rb_gather<T, R>(x, i, Pj, g);
-      const T di = x.dg[i] + x.sh;
-#pragma unroll
-      for (int q = 0; q < R; ++q) E[(size_t)i * R + q] = g[q] / di;
-    } else {  // black: z += (y - (d_i + s) z + F e) / diag(T)
-      T g[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) g[q] = T(0);
-      rb_gather<T, R>(x, i, E, g);
-      const T di = x.dg[i] + x.sh, it = It[i];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const T z = Pj[(size_t)i * R + q];
-        Pj[(size_t)i * R + q] = z + (Y[(size_t)i * R + q] - di * z + g[q]) * it;
-      }
     }
   }
 }
 
-// stage 0: fwd; 2t - 1, 2t: red and black halves of sweep t; 2 sweeps + 1: back
 template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap, int stage) {
@@ -444,8 +480,11 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   const RbCtx<T> x = rb_ctx<T>(D, ctl[c.s].shift);
   const size_t blk = (size_t)D.n * D.r;
   const T* V = static_cast<const T*>(D.V) + (size_t)j * blk;
-  const RbBufs b{static_cast<T*>(D.P) + (size_t)j * blk, D.Yb, D.Eb, D.It};
-  LRADI_RSEL(RF, D.r, rb_rows<T, RR>(D, c, x, V, b, stage));
+  T* Pj = static_cast<T*>(D.P) + (size_t)j * blk;
+  // the shift is fixed for an inner solve: T's values are built at its
+  // first Arnoldi step (first cycle, j = 0) and kept over restarts
+  const bool build = ctl[c.s].cycles == 1 && j == 0;
+  LRADI_RSEL(RF, D.r, rb_rows<T, RR>(D, c, x, V, Pj, stage, build));
 }
 
 // ---------------------------------------------------------------------------
@@ -1293,7 +1332,7 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
   if (b.precond)
-    for (int stage = 0; stage <= 2 * b.sweeps + 1; ++stage)
+    for (int stage = 0; stage <= b.sweeps + 1; ++stage)
       hipLaunchKernelGGL((k_precond<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)

@@ -165,5 +165,5 @@ def test_preconditioner_argument_errors(L, ctx):
     assert e.value.status == L.EINVAL
     with pytest.raises(L.LradiError) as e:
         ctx.shifted_solve([HA], [-10.0], [to_dev(np.ones((HA.n, 1)))], [1e-8],
-                          L.default_opts(precond="rbilu0", precond_sweeps=17))
+                          L.default_opts(precond="rbilu0", precond_sweeps=65))
     assert e.value.status == L.EINVAL
