@@ -163,7 +163,10 @@ typedef struct {
 /* Kernel classes reported by lradi_profile_read. */
 #define LRADI_PROF_GRAM 0      /* block projection V^T U (two launches per step)  */
 #define LRADI_PROF_SPMM 1      /* shifted product U = (A + s I) V_j               */
-#define LRADI_PROF_CLASSES 2
+#define LRADI_PROF_PRECOND 2   /* right preconditioner P_j = M V_j (sweeps + 2
+                                  launches per step; bytes exclude the once-
+                                  per-solve build of the Schur couplings)      */
+#define LRADI_PROF_CLASSES 3
 
 /* Accumulated measurements of one kernel class over the solves run with
  * opts.profile = 1 since the last lradi_profile_reset.  ms: summed

@@ -192,8 +192,8 @@ struct lradi_ctx {
   // kernel measurements (opts.profile)
   std::vector<TickProbe> probes;
   DevBuf prof_dev;  // LRADI_PROF_CLASSES unsigned long long byte counters
-  double prof_ms[LRADI_PROF_CLASSES] = {0.0, 0.0};
-  int64_t prof_launches[LRADI_PROF_CLASSES] = {0, 0};
+  double prof_ms[LRADI_PROF_CLASSES] = {};
+  int64_t prof_launches[LRADI_PROF_CLASSES] = {};
   // autotuned shifted-product tiling per (n, nnz, r, precision)
   std::map<std::array<int64_t, 4>, int> lanes_cache;
 };
@@ -512,8 +512,8 @@ int download_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   return LRADI_OK;
 }
 
-int probe_account(lradi_ctx* ctx, const TickProbe& p) {
-  float a = 0.f, b = 0.f, c = 0.f;
+int probe_account(lradi_ctx* ctx, const TickProbe& p, const Batch& bt) {
+  float a = 0.f, b = 0.f, c = 0.f, e = 0.f;
   LRADI_HIP(hipEventElapsedTime(&a, p.ev[0], p.ev[1]));
   LRADI_HIP(hipEventElapsedTime(&b, p.ev[2], p.ev[3]));
   LRADI_HIP(hipEventElapsedTime(&c, p.ev[4], p.ev[5]));
@@ -521,6 +521,11 @@ int probe_account(lradi_ctx* ctx, const TickProbe& p) {
   ctx->prof_launches[LRADI_PROF_GRAM] += 2;
   ctx->prof_ms[LRADI_PROF_SPMM] += (double)c;
   ctx->prof_launches[LRADI_PROF_SPMM] += 1;
+  if (bt.precond) {
+    LRADI_HIP(hipEventElapsedTime(&e, p.ev[6], p.ev[7]));
+    ctx->prof_ms[LRADI_PROF_PRECOND] += (double)e;
+    ctx->prof_launches[LRADI_PROF_PRECOND] += bt.sweeps + 2;
+  }
   return LRADI_OK;
 }
 
@@ -607,7 +612,7 @@ int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, boo
     if (t >= L) {
       const int rs = (int)((t - L) % (L + 1));
       LRADI_HIP(hipEventSynchronize(ctx->events[rs]));
-      if (profile) LRADI_TRY(probe_account(ctx, ctx->probes[rs]));
+      if (profile) LRADI_TRY(probe_account(ctx, ctx->probes[rs], b));
       if (summary && __atomic_load_n(ctx->ring.h + rs, __ATOMIC_ACQUIRE) == 0) break;
       if (stop && stop()) break;
     }
@@ -619,7 +624,7 @@ int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, boo
   LRADI_HIP(hipStreamSynchronize(st));
   if (profile)  // ticks issued after the last one read back
     for (long u = std::max(0L, t - L + 1); u <= t; ++u)
-      LRADI_TRY(probe_account(ctx, ctx->probes[u % (L + 1)]));
+      LRADI_TRY(probe_account(ctx, ctx->probes[u % (L + 1)], b));
   return LRADI_OK;
 }
 
@@ -1495,7 +1500,7 @@ int lradi_batch_solve(lradi_ctx* c, int nprob, const lradi_problem* probs, const
 int lradi_profile_read(lradi_ctx* c, int kc, lradi_kernel_profile* out) {
   if (!c || !out || kc < 0 || kc >= LRADI_PROF_CLASSES)
     return set_error("lradi_profile_read: bad argument"), LRADI_EINVAL;
-  unsigned long long bytes[LRADI_PROF_CLASSES] = {0, 0};
+  unsigned long long bytes[LRADI_PROF_CLASSES] = {};
   if (c->prof_dev.p) {
     LRADI_HIP(hipSetDevice(c->device));
     LRADI_HIP(hipMemcpy(bytes, c->prof_dev.p, sizeof(bytes), hipMemcpyDeviceToHost));

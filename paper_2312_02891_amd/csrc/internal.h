@@ -291,7 +291,7 @@ struct Batch {
 // Optional timing events around the instrumented launches of one tick:
 // [0,1] first projection, [2,3] second projection, [4,5] shifted product.
 struct TickProbe {
-  hipEvent_t ev[6];
+  hipEvent_t ev[8];
 };
 // One scheduling tick: a block Arnoldi step (or the rebuild of V_0) for every
 // system in PH_ARNOLDI / PH_RESTART, then the end-of-cycle work for every

@@ -470,12 +470,26 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
   }
 }
 
+// algorithmic bytes of one stage for one system (each array element read or
+// written once; the once-per-solve build of T's values not counted)
+template <typename T>
+__device__ inline unsigned long long rb_stage_bytes(const SysDesc& D, int stage) {
+  const unsigned long long nr = D.nred, nb = D.n - D.nred, n = D.n, R = D.r, t = sizeof(T);
+  if (stage == 0)
+    return nb * 4 + D.rbw * nb * (4 + 2 * t) + n * t + n * R * t + nb * R * t +
+           (D.sweeps > 0 ? nb * R * t + nb * t : 0);
+  if (stage <= D.sweeps) return nb * 4 + D.t2w * nb * (4 + t) + 3 * nb * R * t + nb * t;
+  return nr * 4 + D.rbw * nr * (4 + t) + nr * t + 2 * nr * R * t + nb * R * t;
+}
+
 template <typename T, int RF>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
-                                                  const int2* __restrict__ rowmap, int stage) {
+                                                  const int2* __restrict__ rowmap, int stage,
+                                                  unsigned long long* __restrict__ prof) {
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI || !D.rbrows) return;
+  if (prof && c.w == 0 && threadIdx.x == 0) atomicAdd(prof + LRADI_PROF_PRECOND, rb_stage_bytes<T>(D, stage));
   const int j = ctl[c.s].j;
   const RbCtx<T> x = rb_ctx<T>(D, ctl[c.s].shift);
   const size_t blk = (size_t)D.n * D.r;
@@ -1331,9 +1345,11 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 rg(b.rowgrid), tb(kTPB), sg(b.nsys);
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[6], st));
   if (b.precond)
     for (int stage = 0; stage <= b.sweeps + 1; ++stage)
-      hipLaunchKernelGGL((k_precond<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage);
+      hipLaunchKernelGGL((k_precond<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.prof_bytes);
+  if (pr) LRADI_HIP(hipEventRecord(pr->ev[7], st));
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
     hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,

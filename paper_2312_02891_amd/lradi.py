@@ -76,7 +76,7 @@ class KernelProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("bytes", ctypes.c_int64)]
 
 
-PROF_GRAM, PROF_SPMM = 0, 1
+PROF_GRAM, PROF_SPMM, PROF_PRECOND = 0, 1, 2
 
 
 class InnerStats(ctypes.Structure):

@@ -1,5 +1,6 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
-times (B passed as B^T, back-looking mid selection, default options).
+times (B passed as B^T, back-looking mid selection, red-black ILU(0) with
+24 Schur sweeps as right preconditioner), and unpreconditioned.
 
 Config 2 (2-D, n = 65536, m = 36864, r = 4) is compared with the oracle's
 direct-solve ADI at the same step count: X within 1e-6 (relative Frobenius)
@@ -58,11 +59,15 @@ def check_history(res, P):
         assert row[8] == pytest.approx(u, rel=1e-12) and row[9] == pytest.approx(v, rel=1e-12)
 
 
-def test_config2_full_size_matches_oracle(L, ctx):
-    say("full size config 2")
+@pytest.mark.parametrize("sweeps", [24, None])
+def test_config2_full_size_matches_oracle(L, ctx, sweeps):
+    """sweeps = 24: the preconditioned inner solves bench.py times; None:
+    unpreconditioned."""
+    say("full size config 2, sweeps", sweeps)
     P = WL.C2
     HA, HBt, f, g, pA, pB = bench_inputs(L, P)
-    o = L.default_opts(selection="mid", tol=P.tol, b_is_transposed=1)
+    pre = {} if sweeps is None else dict(precond="rbilu0", precond_sweeps=sweeps)
+    o = L.default_opts(selection="mid", tol=P.tol, b_is_transposed=1, **pre)
     res = ctx.solve(HA, HBt, to_dev(f), to_dev(g), pA, pB, o)
     assert res.status == L.OK
     check_history(res, P)
@@ -90,8 +95,9 @@ def test_config3_full_size_properties(L, ctx):
     A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
     B = convdiff_matrix(P.B.dim, P.B.N, P.B.omega)
     nfg = OF.lowrank_product_norm(f, g)
-    for prec in ("fp64", "fp32"):
-        res = ctx.solve(HA, HBt, fd, gd, pA, pB, L.default_opts(selection="mid", precision=prec, **base))
+    for prec, pre in (("fp64", {}), ("fp32", {}), ("fp64", dict(precond="rbilu0", precond_sweeps=24)),
+                      ("fp32", dict(precond="rbilu0", precond_sweeps=24))):
+        res = ctx.solve(HA, HBt, fd, gd, pA, pB, L.default_opts(selection="mid", precision=prec, **base, **pre))
         assert res.status == L.OK and res.k == exact.k
         check_history(res, P)
         Z, d, Y = res.factors()
