@@ -436,6 +436,24 @@ struct Table {
   Batch b{};
 };
 
+// Workgroups are dispatched to the chip's 8 XCDs round-robin by workgroup
+// index, and each XCD has its own L2.  Reorder a launch's (system, chunk)
+// entries so that XCD x gets the x-th contiguous run of chunks: row chunks
+// that gather each other's neighbours then meet in one L2.  Kernels index
+// their partial results by chunk, never by workgroup, so results do not
+// change.
+constexpr int kXcds = 8;
+void xcd_order(std::vector<int2>& v, size_t begin, size_t end) {
+  const size_t G = end - begin;
+  if (G <= (size_t)kXcds) return;
+  std::vector<int2> nat(v.begin() + begin, v.begin() + end);
+  const size_t q = G / kXcds, rem = G % kXcds;
+  for (size_t b = 0; b < G; ++b) {
+    const size_t x = b % kXcds, y = b / kXcds;
+    v[begin + b] = nat[x * q + std::min(x, rem) + y];
+  }
+}
+
 int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   const int nsys = (int)ws.size();
   if (nsys == 0) return set_error("empty batch"), LRADI_EINVAL;
@@ -474,7 +492,9 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       for (int w = 0; w < tiles; ++w) t.hsp.push_back(make_int2(s, w));
     }
     t.b.spcount[g] = (int)t.hsp.size() - t.b.spoff[g];
+    xcd_order(t.hsp, t.b.spoff[g], t.hsp.size());
   }
+  xcd_order(t.hmap, 0, t.hmap.size());
   if (t.dsp.bytes < sizeof(int2) * t.hsp.size()) LRADI_TRY(t.dsp.alloc(sizeof(int2) * t.hsp.size()));
   if (t.dd.bytes < sizeof(SysDesc) * nsys) LRADI_TRY(t.dd.alloc(sizeof(SysDesc) * nsys));
   if (t.dc.bytes < sizeof(SysCtl) * nsys) LRADI_TRY(t.dc.alloc(sizeof(SysCtl) * nsys));
