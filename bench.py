@@ -54,6 +54,9 @@ def parse():
                          "256 independent problems; serve: Poisson request stream")
     ap.add_argument("--count", type=int, default=0, help="problems (batch) or requests (serve)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
+    ap.add_argument("--precond-sweeps", type=int, default=PRECOND_SWEEPS,
+                    help="batch / serve: Schur sweeps of the red-black ILU(0) preconditioner "
+                         "(-1: unpreconditioned)")
     return ap.parse_args()
 
 
@@ -281,6 +284,11 @@ def _lowrank_diff(res_a, res_b):
     return float(torch.linalg.norm(R1 @ R2.T) / torch.linalg.norm(Rb1 @ Rb2.T))
 
 
+def _pre(sweeps):
+    """Preconditioner options for a sweep count (-1: none)."""
+    return {} if sweeps < 0 else dict(precond="rbilu0", precond_sweeps=sweeps)
+
+
 def bench_c3(args, L, WL):
     """3-D configuration (A 64^3 omega (20,10,5), B 48^3 omega (-10,15,5),
     r = 8, tau = 1e-8): FP32 inner Krylov work with the relaxed (back-looking
@@ -295,9 +303,12 @@ def bench_c3(args, L, WL):
     fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
     ctx = L.Context(0)
     base = dict(tol=P.tol, b_is_transposed=1)
+    pre = _pre(PRECOND_SWEEPS)
     variants = [("fp32_relaxed", L.default_opts(selection="mid", precision="fp32", **base)),
                 ("fp64_relaxed", L.default_opts(selection="mid", **base)),
-                ("fp64_exact", L.default_opts(selection="relative", rho=1e-12, **base))]
+                ("fp64_exact", L.default_opts(selection="relative", rho=1e-12, **base)),
+                ("fp32_relaxed_precond", L.default_opts(selection="mid", precision="fp32", **base, **pre)),
+                ("fp64_relaxed_precond", L.default_opts(selection="mid", **base, **pre))]
     out, keep = {}, {}
     for name, o in variants:
         for _ in range(args.warmup):
@@ -317,8 +328,10 @@ def bench_c3(args, L, WL):
         o.profile = 1
         ctx.solve(HA, HBt, fd, gd, pA, pB, o)
         o.profile = 0
-        for cls, key in ((L.PROF_GRAM, "gram"), (L.PROF_SPMM, "spmm")):
+        for cls, key in ((L.PROF_GRAM, "gram"), (L.PROF_SPMM, "spmm"), (L.PROF_PRECOND, "precond")):
             ms, launches, nbytes = ctx.profile_read(cls)
+            if launches == 0:
+                continue
             out[name][key + "_avg_us"] = round(ms * 1e3 / max(launches, 1), 2)
             out[name][key + "_GBs"] = round(nbytes / max(ms * 1e-3, 1e-12) / 1e9, 1)
         keep[name] = r
@@ -326,6 +339,10 @@ def bench_c3(args, L, WL):
               flush=True)
     out["fp32_relaxed"]["x_rel_err_vs_fp64_exact"] = _lowrank_diff(keep["fp32_relaxed"], keep["fp64_exact"])
     out["fp64_relaxed"]["x_rel_err_vs_fp64_exact"] = _lowrank_diff(keep["fp64_relaxed"], keep["fp64_exact"])
+    for name in ("fp32_relaxed_precond", "fp64_relaxed_precond"):
+        out[name]["x_rel_err_vs_fp64_exact"] = _lowrank_diff(keep[name], keep["fp64_exact"])
+    out["speedup_fp32_relaxed_precond_vs_fp64_exact"] = round(out["fp64_exact"]["s"] /
+                                                              out["fp32_relaxed_precond"]["s"], 3)
     out["speedup_fp32_relaxed_vs_fp64_exact"] = round(out["fp64_exact"]["s"] / out["fp32_relaxed"]["s"], 3)
     ctx.close()
     print(json.dumps({"workload": "3-D upwind conv-diff Sylvester, A 64^3 omega (20,10,5), B 48^3 "
@@ -418,7 +435,10 @@ def bench_lyap(args, L, WL):
     fd = torch.from_numpy(f).cuda()
     ctx = L.Context(0)
     out, keep = {}, {}
+    pre = _pre(PRECOND_SWEEPS)
     runs = (("lyap_fp64_sym", "lyap", dict(selection="sym")),
+            ("lyap_fp64_sym_precond", "lyap", dict(selection="sym", **pre)),
+            ("sylvester_fp64_sym_precond", "sylv", dict(selection="sym", b_is_transposed=1, **pre)),
             ("lyap_fp32_sym", "lyap", dict(selection="sym", precision="fp32")),
             ("lyap_fp64_mid", "lyap", dict(selection="mid")),
             ("lyap_fp64_fixed", "lyap", dict(selection="fixed")),
@@ -470,6 +490,8 @@ def bench_lyap(args, L, WL):
                       "n": P.A.n, "steps": args.steps, **out,
                       "speedup_lyap_vs_sylvester_path": round(out["sylvester_fp64_sym"]["s"] /
                                                               out["lyap_fp64_sym"]["s"], 3),
+                      "speedup_lyap_vs_sylvester_path_precond": round(out["sylvester_fp64_sym_precond"]["s"] /
+                                                                      out["lyap_fp64_sym_precond"]["s"], 3),
                       "relaxed_saving_vs_fixed": round(1.0 - out["lyap_fp64_sym"]["s"] /
                                                        out["lyap_fp64_fixed"]["s"], 3),
                       "cpu_baseline": cpu}))
@@ -496,7 +518,7 @@ def bench_batch(args, L, WL):
     items = _batch_items(WL, L, count)
     ctx = L.Context(0)
     # controller in the balanced frame: the batch mixes grid sides 32..128
-    o = L.default_opts(precision="fp32", rescale=2)
+    o = L.default_opts(precision="fp32", rescale=2, **_pre(args.precond_sweeps))
     ctx.batch_solve(items[: min(8, count)], o)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -512,6 +534,7 @@ def bench_batch(args, L, WL):
     ks = [r.k for r in res]
     ctx.close()
     print(json.dumps({"workload": f"batch of {count} 2-D problems, FP32 inner / FP64 outer",
+                      "precond_sweeps": args.precond_sweeps,
                       "batched_s": round(tb, 4), "sequential_s_est": round(ts, 4),
                       "sequential_sample": nseq, "speedup": round(ts / tb, 2),
                       "solves_per_s": round(count / tb, 2), "status": st,
@@ -537,7 +560,8 @@ def bench_serve(args, L, WL):
     ctx = L.Context(0)
     # FP32 inner / FP64 outer; the controller works in the balanced frame,
     # since n and m of one request can differ by three orders of magnitude
-    srv = L.Server(ctx, L.default_opts(precision="fp32", rescale=2), hbm_budget=0, max_active=64)
+    srv = L.Server(ctx, L.default_opts(precision="fp32", rescale=2, **_pre(args.precond_sweeps)), hbm_budget=0,
+                   max_active=64)
     tickets, lat, status = [], {}, {}
     t0 = time.perf_counter()
     i = 0
@@ -564,6 +588,7 @@ def bench_serve(args, L, WL):
     ctx.close()
     arr = np.array([lat[t] for t in tickets])
     print(json.dumps({"workload": f"{count} Poisson requests at {args.rate}/s",
+                      "precond_sweeps": args.precond_sweeps,
                       "p50_s": round(float(np.percentile(arr, 50)), 4),
                       "p99_s": round(float(np.percentile(arr, 99)), 4),
                       "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
