@@ -304,12 +304,18 @@ __device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
   return x;
 }
 
-constexpr int kRbUnroll = 8;
+// gathers in flight per row: eight entries for narrow blocks, six (a 3-D
+// Schur row's 18 couplings in three groups) for wide ones
+template <int R>
+struct RbUnroll {
+  static constexpr int v = R >= 5 ? 6 : 8;
+};
 
 // acc += sum over the off-diagonal entries of row i (colour position p) of
 // a_ik X[k]; unused slots (col == i) are skipped by selection
 template <typename T, int R>
 __device__ inline void rb_gather(const RbCtx<T>& x, int p, int i, const T* __restrict__ X, T (&acc)[R]) {
+  constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
     int col[kRbUnroll];
     T a[kRbUnroll];
@@ -340,6 +346,7 @@ __device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __
 #pragma unroll
   for (int q = 0; q < R; ++q) y[q] = V[(size_t)i * R + q];
   td = x.dg[i] + x.sh;
+  constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
     int col[kRbUnroll];
     T a[kRbUnroll], t[kRbUnroll], dj[kRbUnroll];
@@ -396,6 +403,7 @@ __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, int i, con
   T acc[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)i * R + q];
+  constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < D.t2w; u0 += kRbUnroll) {
     int col[kRbUnroll];
     T a[kRbUnroll];
@@ -432,17 +440,17 @@ __device__ inline T* rb_iter(const SysDesc& D, T* Pj, int t) {
 // stage 0: fwd (black rows; builds T's values at the first Arnoldi step of
 // an inner solve); 1..sweeps: Jacobi sweep t (black rows); sweeps + 1: back
 // (red rows)
-template <typename T, int R>
+template <typename T, int R, int KIND>
 __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj,
                                int stage, bool build) {
   const int nb = D.n - D.nred;
-  const bool black = stage <= D.sweeps;
+  constexpr bool black = KIND != 2;
   const int off = black ? D.nred : 0;
   const int cnt = black ? nb : D.nred;
   for (int pp = c.row0 + threadIdx.x; pp < min(c.row1, cnt); pp += kTPB) {
     const int p = off + pp;  // colour position
     const int i = D.rbrows[p];
-    if (stage == 0) {
+    if constexpr (KIND == 0) {
       T y[R], td;
       rb_black_fwd<T, R>(x, p, i, V, y, td);
       const T it = T(1) / td;
@@ -456,7 +464,7 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
         static_cast<T*>(D.It)[i] = it;
         if (build) rb_build_t<T>(D, x, pp, nb);
       }
-    } else if (black) {
+    } else if constexpr (KIND == 1) {
       rb_sweep_row<T, R>(D, pp, nb, i, rb_iter<T>(D, Pj, stage - 1), rb_iter<T>(D, Pj, stage));
     } else {  // back: z_r = (v_r - E z) / (d_r + s)
       T g[R];
@@ -482,7 +490,9 @@ __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D, int stage)
   return nr * 4 + D.rbw * nr * (4 + t) + nr * t + 2 * nr * R * t + nb * R * t;
 }
 
-template <typename T, int RF>
+// KIND 0: forward (stage 0), 1: sweep (stage 1..sweeps), 2: back; one
+// instance per kind, so each allocates only the registers it needs
+template <typename T, int RF, int KIND>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap, int stage,
                                                   unsigned long long* __restrict__ prof) {
@@ -498,7 +508,7 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   // the shift is fixed for an inner solve: T's values are built at its
   // first Arnoldi step (first cycle, j = 0) and kept over restarts
   const bool build = ctl[c.s].cycles == 1 && j == 0;
-  LRADI_RSEL(RF, D.r, rb_rows<T, RR>(D, c, x, V, Pj, stage, build));
+  LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, build));
 }
 
 // ---------------------------------------------------------------------------
@@ -1346,9 +1356,12 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const dim3 redg(b.nsys, (b.maxP + kRedOut - 1) / kRedOut);
   const double fl64 = 1e-24, fl32 = 1e-10;
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[6], st));
-  if (b.precond)
-    for (int stage = 0; stage <= b.sweeps + 1; ++stage)
-      hipLaunchKernelGGL((k_precond<T, RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.prof_bytes);
+  if (b.precond) {
+    hipLaunchKernelGGL((k_precond<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.prof_bytes);
+    for (int stage = 1; stage <= b.sweeps; ++stage)
+      hipLaunchKernelGGL((k_precond<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.prof_bytes);
+    hipLaunchKernelGGL((k_precond<T, RF, 2>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.sweeps + 1, b.prof_bytes);
+  }
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[7], st));
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
