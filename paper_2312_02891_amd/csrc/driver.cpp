@@ -371,11 +371,8 @@ struct SysWork {
         d.t2val = take(sizes[17]);
       }
       d.t2w = A->t2w;
-      d.tpw = A->tpw;
       d.t2ci = A->t2ci.as<int>();
-      d.pslot = A->pslot.as<int>();
-      d.pj = A->pj.as<int>();
-      d.pcT = (prec == LRADI_FP64) ? (const void*)A->pc64.p : (const void*)A->pc32.p;
+      d.rbpos = A->rbpos.as<int>();
       d.rbrows = A->rbrows.as<int>();
       d.nred = A->nred;
       d.sweeps = sweeps;
@@ -823,79 +820,76 @@ int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
     w = std::max(w, c);
   }
   const int W = std::max(w, 1);
-  std::vector<int32_t> eci((size_t)W * nn);
-  std::vector<double> eval((size_t)W * nn, 0.0), etv((size_t)W * nn, 0.0);
+  std::vector<int32_t> r_eci((size_t)W * nn);
+  std::vector<double> r_eval((size_t)W * nn, 0.0), r_etv((size_t)W * nn, 0.0);
   for (int p = 0; p < nn; ++p) {
     const int i = rows[p];
+    const size_t e0 = (size_t)p * W;
     int u = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
       if (ci[k] == i) continue;
       double a = 0.0;
       for (int32_t kk = trp[i]; kk < trp[i + 1]; ++kk)
         if (tci[kk] == ci[k]) a += tv[kk];
-      eci[(size_t)u * nn + p] = ci[k];
-      eval[(size_t)u * nn + p] = v[k];
-      etv[(size_t)u * nn + p] = a;
+      r_eci[e0 + u] = ci[k];
+      r_eval[e0 + u] = v[k];
+      r_etv[e0 + u] = a;
       ++u;
     }
-    for (; u < W; ++u) eci[(size_t)u * nn + p] = i;
+    for (; u < W; ++u) r_eci[e0 + u] = i;
   }
+  std::vector<int32_t> eci((size_t)W * nn);
+  std::vector<double> eval((size_t)W * nn), etv((size_t)W * nn);
+  for (int p0 = 0; p0 < nn; p0 += 256)  // blocked: the source block stays in cache
+    for (int u = 0; u < W; ++u)
+      for (int p = p0; p < std::min(nn, p0 + 256); ++p) {
+        eci[(size_t)u * nn + p] = r_eci[(size_t)p * W + u];
+        eval[(size_t)u * nn + p] = r_eval[(size_t)p * W + u];
+        etv[(size_t)u * nn + p] = r_etv[(size_t)p * W + u];
+      }
   // Schur complement T = D_b - F D_r^{-1} E on the black rows: its
-  // off-diagonal columns (distinct two-hop black neighbours l != i, in order
-  // of first appearance) and the paths i -> j -> l with coefficient
-  // a_ij a_jl
+  // off-diagonal columns, the distinct two-hop black neighbours l != i in
+  // order of first appearance (the values depend on the shift and are
+  // built on the device); slot_of[l] maps a column to its slot while its
+  // row is being built
   const int nbk = nn - nr;
-  std::vector<std::vector<int32_t>> tcols(nbk);
-  std::vector<std::vector<std::array<double, 3>>> paths(nbk);  // (slot, j, a_ij a_jl)
-  int w2 = 0, wp = 0;
+  const size_t nbs = (size_t)std::max(nbk, 1);
+  std::vector<int32_t> slot_of(nn, -1), ncol(nbs, 0);
+  std::vector<int32_t> cols;  // position-major, grown per row
+  cols.reserve(nbs * 8);
+  std::vector<size_t> cstart(nbs + 1, 0);
   for (int pb = 0; pb < nbk; ++pb) {
     const int i = rows[nr + pb];
+    cstart[pb] = cols.size();
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
       const int j = ci[k];
       if (j == i) continue;
       for (int32_t kk = rp[j]; kk < rp[j + 1]; ++kk) {
         const int l = ci[kk];
-        if (l == j || l == i) continue;
-        int slot = -1;
-        for (size_t q = 0; q < tcols[pb].size(); ++q)
-          if (tcols[pb][q] == l) slot = (int)q;
-        if (slot < 0) {
-          slot = (int)tcols[pb].size();
-          tcols[pb].push_back(l);
-        }
-        paths[pb].push_back({(double)slot, (double)j, v[k] * v[kk]});
+        if (l == j || l == i || slot_of[l] >= 0) continue;
+        slot_of[l] = (int32_t)(cols.size() - cstart[pb]);
+        cols.push_back(l);
       }
     }
-    w2 = std::max(w2, (int)tcols[pb].size());
-    wp = std::max(wp, (int)paths[pb].size());
+    for (size_t q = cstart[pb]; q < cols.size(); ++q) slot_of[cols[q]] = -1;
+    ncol[pb] = (int32_t)(cols.size() - cstart[pb]);
   }
-  const int W2 = std::max(w2, 1), WP = std::max(wp, 1);
-  const size_t nbs = (size_t)std::max(nbk, 1);
-  std::vector<int32_t> h_t2ci(W2 * nbs), h_pslot(WP * nbs, -1), h_pj(WP * nbs, 0);
-  std::vector<double> h_pc(WP * nbs, 0.0);
+  cstart[nbk] = cols.size();
+  int w2 = 0;
+  for (int pb = 0; pb < nbk; ++pb) w2 = std::max(w2, ncol[pb]);
+  const int W2 = std::max(w2, 1);
+  std::vector<int32_t> h_t2ci((size_t)W2 * nbs);
   for (int pb = 0; pb < nbk; ++pb) {
     const int i = rows[nr + pb];
     for (int q = 0; q < W2; ++q)
-      h_t2ci[(size_t)q * nbs + pb] = q < (int)tcols[pb].size() ? tcols[pb][q] : i;
-    for (size_t q = 0; q < paths[pb].size(); ++q) {
-      h_pslot[q * nbs + pb] = (int32_t)paths[pb][q][0];
-      h_pj[q * nbs + pb] = (int32_t)paths[pb][q][1];
-      h_pc[q * nbs + pb] = paths[pb][q][2];
-    }
+      h_t2ci[(size_t)q * nbs + pb] = q < ncol[pb] ? cols[cstart[pb] + q] : i;
   }
+  std::vector<int32_t> h_pos(nn);
+  for (int p = 0; p < nn; ++p) h_pos[rows[p]] = p;
   LRADI_TRY(t2ci.alloc(sizeof(int32_t) * h_t2ci.size()));
-  LRADI_TRY(pslot.alloc(sizeof(int32_t) * h_pslot.size()));
-  LRADI_TRY(pj.alloc(sizeof(int32_t) * h_pj.size()));
-  LRADI_TRY(pc64.alloc(sizeof(double) * h_pc.size()));
+  LRADI_TRY(rbpos.alloc(sizeof(int32_t) * nn));
   LRADI_HIP(hipMemcpyAsync(t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(pslot.p, h_pslot.data(), sizeof(int32_t) * h_pslot.size(), hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(pj.p, h_pj.data(), sizeof(int32_t) * h_pj.size(), hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(pc64.p, h_pc.data(), sizeof(double) * h_pc.size(), hipMemcpyHostToDevice, st));
-  if (need32) {
-    LRADI_TRY(pc32.alloc(sizeof(float) * h_pc.size()));
-    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((h_pc.size() + 255) / 256)), dim3(256), 0, st, pc64.as<double>(),
-                       pc32.as<float>(), (int64_t)h_pc.size());
-  }
+  LRADI_HIP(hipMemcpyAsync(rbpos.p, h_pos.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
   const size_t ne = (size_t)W * nn;
   LRADI_TRY(rbrows.alloc(sizeof(int32_t) * nn));
   LRADI_TRY(diag64.alloc(sizeof(double) * nn));
@@ -924,7 +918,6 @@ int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
   nred = nr;
   rbw = W;
   t2w = W2;
-  tpw = WP;
   return LRADI_OK;
 }
 

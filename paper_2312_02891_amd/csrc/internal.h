@@ -169,14 +169,12 @@ struct SysDesc {
   void* It;             // sweeps: 1 / diag(T) per black row, n
   // sweeps: the off-diagonal entries of T = D_b - F D_r^{-1} E by black
   // position (pb = p - nred), slot-major with nb = n - nred: columns t2ci
-  // (t2w slots, unused: the row itself), values t2val (rebuilt for each
-  // shift), and the two-hop paths that make them: path v of black position
-  // pb adds -pc / (d_j + s) with j = pj to slot pslot
-  int t2w, tpw;
+  // (t2w slots, unused: the row itself) and values t2val, rebuilt for each
+  // shift by walking two hops through the slot tables; rbpos[row] is the
+  // row's colour position
+  int t2w;
   const int* t2ci;
-  const int* pslot;
-  const int* pj;
-  const void* pcT;
+  const int* rbpos;
   void* t2val;
 };
 
@@ -247,8 +245,8 @@ struct DevCSR {
   DevBuf mval64, mval32;  // the mass matrix of a pencil, on the same pattern
   // red-black preconditioner data (prepare_rb)
   DevBuf rbrows, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32;
-  DevBuf t2ci, pslot, pj, pc64, pc32;
-  int nred = -1, rbw = 0, t2w = 0, tpw = 0;
+  DevBuf t2ci, rbpos;
+  int nred = -1, rbw = 0, t2w = 0;
   int upload(const lradi_csr* A, hipStream_t st, bool need32);
   // the pencil (A, M): union pattern, A's values and M's values
   int upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);

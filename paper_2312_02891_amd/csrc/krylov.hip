@@ -376,20 +376,30 @@ __device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __
   }
 }
 
-// T's off-diagonal values of black position pb for the current shift:
-// slot u = -sum of a_ij a_jl / (d_j + s) over the paths i -> j -> l that end
-// in that slot, in path order (once per inner solve: the shift is fixed)
+// T's off-diagonal values of black position pb (row i, colour position p)
+// for the current shift: slot q (column l) = -sum over the red neighbours j
+// of i that neighbour l of a_ij a_jl / (d_j + s), walking i's and then j's
+// slot tables in order (once per inner solve: the shift is fixed)
 template <typename T>
-__device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int pb, int nb) {
-  const T* pc = static_cast<const T*>(D.pcT);
+__device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, int pb, int nb, int i) {
   T* tv = static_cast<T*>(D.t2val);
-  for (int u = 0; u < D.t2w; ++u) tv[(size_t)u * nb + pb] = T(0);
-  for (int v = 0; v < D.tpw; ++v) {
-    const size_t e = (size_t)v * nb + pb;
-    const int slot = D.pslot[e];
-    if (slot < 0) break;
-    const int j = D.pj[e];
-    tv[(size_t)slot * nb + pb] -= pc[e] / (x.dg[j] + x.sh);
+  for (int q = 0; q < D.t2w; ++q) tv[(size_t)q * nb + pb] = T(0);
+  for (int u = 0; u < x.w; ++u) {
+    const size_t e = (size_t)u * x.n + p;
+    const int j = x.ci[e];
+    if (j == i) continue;  // unused slot
+    const T wj = x.val[e] / (x.dg[j] + x.sh);
+    const int pj = D.rbpos[j];
+    for (int u2 = 0; u2 < x.w; ++u2) {
+      const size_t e2 = (size_t)u2 * x.n + pj;
+      const int l = x.ci[e2];
+      if (l == j || l == i) continue;
+      for (int q = 0; q < D.t2w; ++q)
+        if (D.t2ci[(size_t)q * nb + pb] == l) {
+          tv[(size_t)q * nb + pb] -= wj * x.val[e2];
+          break;
+        }
+    }
   }
 }
 
@@ -462,7 +472,7 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
 #pragma unroll
         for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = y[q];
         static_cast<T*>(D.It)[i] = it;
-        if (build) rb_build_t<T>(D, x, pp, nb);
+        if (build) rb_build_t<T>(D, x, p, pp, nb, i);
       }
     } else if constexpr (KIND == 1) {
       rb_sweep_row<T, R>(D, pp, nb, i, rb_iter<T>(D, Pj, stage - 1), rb_iter<T>(D, Pj, stage));
