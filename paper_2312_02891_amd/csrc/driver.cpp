@@ -12,6 +12,7 @@
 #include <cstring>
 #include <condition_variable>
 #include <deque>
+#include <list>
 #include <functional>
 #include <map>
 #include <memory>
@@ -196,6 +197,9 @@ struct lradi_ctx {
   int64_t prof_launches[LRADI_PROF_CLASSES] = {};
   // autotuned shifted-product tiling per (n, nnz, r, precision)
   std::map<std::array<int64_t, 4>, int> lanes_cache;
+  // red-black preconditioner data of recently prepared matrices, most
+  // recent first, keyed by content
+  std::list<std::pair<uint64_t, std::shared_ptr<const lradi::RbData>>> rb_cache;
 };
 
 struct lradi_result {
@@ -317,8 +321,9 @@ struct SysWork {
                             sweeps > 0 ? n * rr * tsz : 0,              // Yb
                             sweeps > 0 ? n * rr * tsz : 0,              // Eb
                             sweeps > 0 ? n * tsz : 0,                   // It
-                            sweeps > 0 ? (size_t)A->t2w * std::max(n - (size_t)A->nred, (size_t)1) * tsz
-                                       : 0};                            // t2val
+                            sweeps > 0 && A->has_rb()
+                                ? (size_t)A->rb->t2w * std::max(n - (size_t)A->rb->nred, (size_t)1) * tsz
+                                : 0};                                   // t2val
     size_t total = 0;
     for (size_t z : sizes) total += align256(z);
     LRADI_TRY(buf.alloc(total));
@@ -370,17 +375,18 @@ struct SysWork {
         d.It = take(sizes[16]);
         d.t2val = take(sizes[17]);
       }
-      d.t2w = A->t2w;
-      d.t2ci = A->t2ci.as<int>();
-      d.rbpos = A->rbpos.as<int>();
-      d.rbrows = A->rbrows.as<int>();
-      d.nred = A->nred;
+      const lradi::RbData& B = *A->rb;
+      d.t2w = B.t2w;
+      d.t2ci = B.t2ci.as<int>();
+      d.rbpos = B.rbpos.as<int>();
+      d.rbrows = B.rbrows.as<int>();
+      d.nred = B.nred;
       d.sweeps = sweeps;
-      d.diagT = (prec == LRADI_FP64) ? (const void*)A->diag64.p : (const void*)A->diag32.p;
-      d.rbw = A->rbw;
-      d.ellci = A->ellci.as<int>();
-      d.ellvalT = (prec == LRADI_FP64) ? (const void*)A->ellval64.p : (const void*)A->ellval32.p;
-      d.elltvT = (prec == LRADI_FP64) ? (const void*)A->elltv64.p : (const void*)A->elltv32.p;
+      d.diagT = (prec == LRADI_FP64) ? (const void*)B.diag64.p : (const void*)B.diag32.p;
+      d.rbw = B.rbw;
+      d.ellci = B.ellci.as<int>();
+      d.ellvalT = (prec == LRADI_FP64) ? (const void*)B.ellval64.p : (const void*)B.ellval32.p;
+      d.elltvT = (prec == LRADI_FP64) ? (const void*)B.elltv64.p : (const void*)B.elltv32.p;
     }
     c = SysCtl{};
     c.phase = PH_FINISHED;  // armed by the caller or by the outer kernels
@@ -766,12 +772,74 @@ int DevCSR::upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st
   return LRADI_OK;
 }
 
-int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
+// prepared preconditioner data kept per context (most recently used)
+constexpr size_t kRbCacheEntries = 8;
+
+// 64-bit content key of a CSR matrix (size, pattern, values, FP32 copies)
+uint64_t csr_key(int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v, bool need32) {
+  uint64_t h = 0x243F6A8885A308D3ull ^ ((uint64_t)n << 1) ^ ((uint64_t)nnz << 33) ^ (need32 ? 1u : 0u);
+  auto mix = [&h](const void* p, size_t bytes) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+      uint64_t x;
+      std::memcpy(&x, c + i, 8);
+      h = (h ^ (x * 0x9E3779B97F4A7C15ull)) * 0xBF58476D1CE4E5B9ull;
+      h ^= h >> 31;
+    }
+    uint64_t x = 0;
+    std::memcpy(&x, c + i, bytes - i);
+    h = (h ^ (x * 0x9E3779B97F4A7C15ull)) * 0x94D049BB133111EBull;
+    h ^= h >> 29;
+  };
+  mix(rp, sizeof(int32_t) * (size_t)(n + 1));
+  if (nnz > 0) {
+    mix(ci, sizeof(int32_t) * (size_t)nnz);
+    mix(v, sizeof(double) * (size_t)nnz);
+  }
+  return h;
+}
+
+// f(begin, end) over [0, n) split across a few host threads (one range
+// when n is small)
+template <class F>
+void par_ranges(int n, F f) {
+  const int nt = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
+  if (n < 32768 || nt == 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) th.emplace_back(f, std::min(n, t * chunk), std::min(n, (t + 1) * chunk), t);
+  for (auto& x : th) x.join();
+}
+int par_threads(int n) {
+  const int nt = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
+  return n < 32768 ? 1 : nt;
+}
+
+int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, hipStream_t st, bool need32) {
   std::vector<int32_t> rp, ci, trp, tci;
   std::vector<double> v, tv;
-  LRADI_TRY(host_csr(A, rp, ci, v));
+  if (!A || A->nrows != n) return set_error("preconditioner: matrix size differs from the uploaded one"), LRADI_EINVAL;
+  // a matrix already prepared on this context (same contents) is reused
+  uint64_t key;
+  if (A->on_device) {
+    LRADI_TRY(host_csr(A, rp, ci, v));
+    key = csr_key(n, (int64_t)ci.size(), rp.data(), ci.data(), v.data(), need32);
+  } else {
+    key = csr_key(n, A->nnz, A->rowptr, A->colind, A->val, need32);
+  }
+  for (auto it = ctx->rb_cache.begin(); it != ctx->rb_cache.end(); ++it)
+    if (it->first == key) {
+      rb = it->second;
+      ctx->rb_cache.splice(ctx->rb_cache.begin(), ctx->rb_cache, it);
+      return LRADI_OK;
+    }
+  if (!A->on_device) LRADI_TRY(host_csr(A, rp, ci, v));
+  auto R = std::make_shared<RbData>();
   const int nn = A->nrows;
-  if (nn != n) return set_error("preconditioner: matrix size differs from the uploaded one"), LRADI_EINVAL;
   csr_transpose(nn, rp.data(), ci.data(), v.data(), trp, tci, tv);
   // breadth-first 2-colouring over the union of A's and A^T's off-diagonal
   // patterns (stored zeros count), the lowest row of each component red
@@ -822,31 +890,35 @@ int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
   const int W = std::max(w, 1);
   std::vector<int32_t> r_eci((size_t)W * nn);
   std::vector<double> r_eval((size_t)W * nn, 0.0), r_etv((size_t)W * nn, 0.0);
-  for (int p = 0; p < nn; ++p) {
-    const int i = rows[p];
-    const size_t e0 = (size_t)p * W;
-    int u = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      if (ci[k] == i) continue;
-      double a = 0.0;
-      for (int32_t kk = trp[i]; kk < trp[i + 1]; ++kk)
-        if (tci[kk] == ci[k]) a += tv[kk];
-      r_eci[e0 + u] = ci[k];
-      r_eval[e0 + u] = v[k];
-      r_etv[e0 + u] = a;
-      ++u;
+  par_ranges(nn, [&](int pa, int pe, int) {
+    for (int p = pa; p < pe; ++p) {
+      const int i = rows[p];
+      const size_t e0 = (size_t)p * W;
+      int u = 0;
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        if (ci[k] == i) continue;
+        double a = 0.0;
+        for (int32_t kk = trp[i]; kk < trp[i + 1]; ++kk)
+          if (tci[kk] == ci[k]) a += tv[kk];
+        r_eci[e0 + u] = ci[k];
+        r_eval[e0 + u] = v[k];
+        r_etv[e0 + u] = a;
+        ++u;
+      }
+      for (; u < W; ++u) r_eci[e0 + u] = i;
     }
-    for (; u < W; ++u) r_eci[e0 + u] = i;
-  }
+  });
   std::vector<int32_t> eci((size_t)W * nn);
   std::vector<double> eval((size_t)W * nn), etv((size_t)W * nn);
-  for (int p0 = 0; p0 < nn; p0 += 256)  // blocked: the source block stays in cache
-    for (int u = 0; u < W; ++u)
-      for (int p = p0; p < std::min(nn, p0 + 256); ++p) {
-        eci[(size_t)u * nn + p] = r_eci[(size_t)p * W + u];
-        eval[(size_t)u * nn + p] = r_eval[(size_t)p * W + u];
-        etv[(size_t)u * nn + p] = r_etv[(size_t)p * W + u];
-      }
+  par_ranges(nn, [&](int pa, int pe, int) {
+    for (int p0 = pa; p0 < pe; p0 += 256)  // blocked: the source block stays in cache
+      for (int u = 0; u < W; ++u)
+        for (int p = p0; p < std::min(pe, p0 + 256); ++p) {
+          eci[(size_t)u * nn + p] = r_eci[(size_t)p * W + u];
+          eval[(size_t)u * nn + p] = r_eval[(size_t)p * W + u];
+          etv[(size_t)u * nn + p] = r_etv[(size_t)p * W + u];
+        }
+  });
   // Schur complement T = D_b - F D_r^{-1} E on the black rows: its
   // off-diagonal columns, the distinct two-hop black neighbours l != i in
   // order of first appearance (the values depend on the shift and are
@@ -854,70 +926,83 @@ int DevCSR::prepare_rb(const lradi_csr* A, hipStream_t st, bool need32) {
   // row is being built
   const int nbk = nn - nr;
   const size_t nbs = (size_t)std::max(nbk, 1);
-  std::vector<int32_t> slot_of(nn, -1), ncol(nbs, 0);
-  std::vector<int32_t> cols;  // position-major, grown per row
-  cols.reserve(nbs * 8);
-  std::vector<size_t> cstart(nbs + 1, 0);
-  for (int pb = 0; pb < nbk; ++pb) {
-    const int i = rows[nr + pb];
-    cstart[pb] = cols.size();
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      const int j = ci[k];
-      if (j == i) continue;
-      for (int32_t kk = rp[j]; kk < rp[j + 1]; ++kk) {
-        const int l = ci[kk];
-        if (l == j || l == i || slot_of[l] >= 0) continue;
-        slot_of[l] = (int32_t)(cols.size() - cstart[pb]);
-        cols.push_back(l);
+  const int nth = par_threads(nbk);
+  std::vector<std::vector<int32_t>> tcols(nth);  // per thread, position-major
+  std::vector<std::vector<size_t>> tstart(nth);
+  std::vector<int32_t> ncol(nbs, 0);
+  par_ranges(nbk, [&](int pa, int pe, int t) {
+    std::vector<int32_t> slot_of(nn, -1);
+    std::vector<int32_t>& cols = tcols[t];
+    std::vector<size_t>& cs = tstart[t];
+    cols.reserve((size_t)(pe - pa) * 8);
+    cs.assign((size_t)(pe - pa) + 1, 0);
+    for (int pb = pa; pb < pe; ++pb) {
+      const int i = rows[nr + pb];
+      cs[pb - pa] = cols.size();
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = ci[k];
+        if (j == i) continue;
+        for (int32_t kk = rp[j]; kk < rp[j + 1]; ++kk) {
+          const int l = ci[kk];
+          if (l == j || l == i || slot_of[l] >= 0) continue;
+          slot_of[l] = (int32_t)(cols.size() - cs[pb - pa]);
+          cols.push_back(l);
+        }
       }
+      for (size_t q = cs[pb - pa]; q < cols.size(); ++q) slot_of[cols[q]] = -1;
+      ncol[pb] = (int32_t)(cols.size() - cs[pb - pa]);
     }
-    for (size_t q = cstart[pb]; q < cols.size(); ++q) slot_of[cols[q]] = -1;
-    ncol[pb] = (int32_t)(cols.size() - cstart[pb]);
-  }
-  cstart[nbk] = cols.size();
+    cs[pe - pa] = cols.size();
+  });
   int w2 = 0;
   for (int pb = 0; pb < nbk; ++pb) w2 = std::max(w2, ncol[pb]);
   const int W2 = std::max(w2, 1);
   std::vector<int32_t> h_t2ci((size_t)W2 * nbs);
-  for (int pb = 0; pb < nbk; ++pb) {
-    const int i = rows[nr + pb];
-    for (int q = 0; q < W2; ++q)
-      h_t2ci[(size_t)q * nbs + pb] = q < ncol[pb] ? cols[cstart[pb] + q] : i;
-  }
+  par_ranges(nbk, [&](int pa, int pe, int t) {
+    for (int pb = pa; pb < pe; ++pb) {
+      const int i = rows[nr + pb];
+      const size_t c0 = tstart[t][pb - pa];
+      for (int q = 0; q < W2; ++q)
+        h_t2ci[(size_t)q * nbs + pb] = q < ncol[pb] ? tcols[t][c0 + q] : i;
+    }
+  });
   std::vector<int32_t> h_pos(nn);
   for (int p = 0; p < nn; ++p) h_pos[rows[p]] = p;
-  LRADI_TRY(t2ci.alloc(sizeof(int32_t) * h_t2ci.size()));
-  LRADI_TRY(rbpos.alloc(sizeof(int32_t) * nn));
-  LRADI_HIP(hipMemcpyAsync(t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(rbpos.p, h_pos.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
+  LRADI_TRY(R->t2ci.alloc(sizeof(int32_t) * h_t2ci.size()));
+  LRADI_TRY(R->rbpos.alloc(sizeof(int32_t) * nn));
+  LRADI_HIP(hipMemcpyAsync(R->t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(R->rbpos.p, h_pos.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
   const size_t ne = (size_t)W * nn;
-  LRADI_TRY(rbrows.alloc(sizeof(int32_t) * nn));
-  LRADI_TRY(diag64.alloc(sizeof(double) * nn));
-  LRADI_TRY(ellci.alloc(sizeof(int32_t) * ne));
-  LRADI_TRY(ellval64.alloc(sizeof(double) * ne));
-  LRADI_TRY(elltv64.alloc(sizeof(double) * ne));
-  LRADI_HIP(hipMemcpyAsync(rbrows.p, rows.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(diag64.p, dg.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(ellci.p, eci.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(ellval64.p, eval.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(elltv64.p, etv.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
+  LRADI_TRY(R->rbrows.alloc(sizeof(int32_t) * nn));
+  LRADI_TRY(R->diag64.alloc(sizeof(double) * nn));
+  LRADI_TRY(R->ellci.alloc(sizeof(int32_t) * ne));
+  LRADI_TRY(R->ellval64.alloc(sizeof(double) * ne));
+  LRADI_TRY(R->elltv64.alloc(sizeof(double) * ne));
+  LRADI_HIP(hipMemcpyAsync(R->rbrows.p, rows.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(R->diag64.p, dg.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(R->ellci.p, eci.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(R->ellval64.p, eval.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
+  LRADI_HIP(hipMemcpyAsync(R->elltv64.p, etv.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
   if (need32) {
-    LRADI_TRY(diag32.alloc(sizeof(float) * nn));
-    LRADI_TRY(ellval32.alloc(sizeof(float) * ne));
-    LRADI_TRY(elltv32.alloc(sizeof(float) * ne));
+    LRADI_TRY(R->diag32.alloc(sizeof(float) * nn));
+    LRADI_TRY(R->ellval32.alloc(sizeof(float) * ne));
+    LRADI_TRY(R->elltv32.alloc(sizeof(float) * ne));
     const int tpb = 256;
-    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + tpb - 1) / tpb)), dim3(tpb), 0, st, diag64.as<double>(),
-                       diag32.as<float>(), (int64_t)nn);
-    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, ellval64.as<double>(),
-                       ellval32.as<float>(), (int64_t)ne);
-    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, elltv64.as<double>(),
-                       elltv32.as<float>(), (int64_t)ne);
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + tpb - 1) / tpb)), dim3(tpb), 0, st, R->diag64.as<double>(),
+                       R->diag32.as<float>(), (int64_t)nn);
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, R->ellval64.as<double>(),
+                       R->ellval32.as<float>(), (int64_t)ne);
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, R->elltv64.as<double>(),
+                       R->elltv32.as<float>(), (int64_t)ne);
     LRADI_HIP(hipGetLastError());
   }
   LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
-  nred = nr;
-  rbw = W;
-  t2w = W2;
+  R->nred = nr;
+  R->rbw = W;
+  R->t2w = W2;
+  rb = R;
+  ctx->rb_cache.emplace_front(key, R);
+  if (ctx->rb_cache.size() > kRbCacheEntries) ctx->rb_cache.pop_back();
   return LRADI_OK;
 }
 
@@ -1021,17 +1106,17 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   const int sw = sweeps_for(o);
   if (sw >= 0) {
     if (P.M || P.C) return set_error("the red-black preconditioner needs M = C = I"), LRADI_EINVAL;
-    LRADI_TRY(q.A.prepare_rb(P.A, st, f32));
+    LRADI_TRY(q.A.prepare_rb(c, P.A, st, f32));
     if (!q.sym) {
       if (o.b_is_transposed) {
-        LRADI_TRY(q.Bt.prepare_rb(P.B, st, f32));
+        LRADI_TRY(q.Bt.prepare_rb(c, P.B, st, f32));
       } else {
         std::vector<int32_t> trp, tci;
         std::vector<double> tv;
         LRADI_TRY(host_csr_t(P.B, trp, tci, tv));
         const int mB = P.B->nrows;
         lradi_csr Bt{mB, mB, (int64_t)tci.size(), trp.data(), tci.data(), tv.data(), 0};
-        LRADI_TRY(q.Bt.prepare_rb(&Bt, st, f32));
+        LRADI_TRY(q.Bt.prepare_rb(c, &Bt, st, f32));
       }
     }
   }
@@ -1423,7 +1508,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     if (!W[s] || !Z[s] || !(delta[s] >= 0.0) || !std::isfinite(shift[s]))
       return set_error("lradi_shifted_solve: bad system %d", s), LRADI_EINVAL;
     LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
-    if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(A[s], c->stream, o.precision == LRADI_FP32_INNER));
+    if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(c, A[s], c->stream, o.precision == LRADI_FP32_INNER));
     work[s] = std::make_unique<SysWork>();
     LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o), sw));
     LRADI_TRY(work[s]->tune(c, mats[s], o.spmm_lanes));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -238,15 +239,23 @@ struct DevBuf {
 };
 
 // Device copy of a CSR matrix in FP64 and FP32.
+// Red-black preconditioner data of one matrix: colour-ordered rows and each
+// row's colour position, the diagonal, the off-diagonal entries by colour
+// position in rbw slot-major slots (column, value, transposed value), and
+// the Schur complement's column pattern on the black rows (t2w slots).
+struct RbData {
+  DevBuf rbrows, rbpos, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32, t2ci;
+  int nred = 0, rbw = 0, t2w = 0;
+};
+
 struct DevCSR {
   int n = 0;
   int64_t nnz = 0;
   DevBuf rowptr, colind, val64, val32;
   DevBuf mval64, mval32;  // the mass matrix of a pencil, on the same pattern
-  // red-black preconditioner data (prepare_rb)
-  DevBuf rbrows, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32;
-  DevBuf t2ci, rbpos;
-  int nred = -1, rbw = 0, t2w = 0;
+  // red-black preconditioner data (prepare_rb), shared with the context's
+  // cache of prepared matrices
+  std::shared_ptr<const RbData> rb;
   int upload(const lradi_csr* A, hipStream_t st, bool need32);
   // the pencil (A, M): union pattern, A's values and M's values
   int upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);
@@ -254,8 +263,8 @@ struct DevCSR {
   // 2-colour the sparsity graph of A (the matrix uploaded here) and upload
   // the colour-ordered rows, A's diagonal and its transposed values;
   // LRADI_EINVAL if the graph is not bipartite
-  int prepare_rb(const lradi_csr* A, hipStream_t st, bool need32);
-  bool has_rb() const { return nred >= 0; }
+  int prepare_rb(lradi_ctx* ctx, const lradi_csr* A, hipStream_t st, bool need32);
+  bool has_rb() const { return rb != nullptr; }
 };
 
 // ---------------------------------------------------------------------------

@@ -167,3 +167,26 @@ def test_preconditioner_argument_errors(L, ctx):
         ctx.shifted_solve([HA], [-10.0], [to_dev(np.ones((HA.n, 1)))], [1e-8],
                           L.default_opts(precond="rbilu0", precond_sweeps=65))
     assert e.value.status == L.EINVAL
+
+
+def test_prepared_matrix_cache_is_keyed_by_contents(L, ctx):
+    """A context reuses the preconditioner data of a matrix it has prepared
+    before (same contents: bit-identical results); a matrix with the same
+    pattern but other values is prepared afresh (its result equals a fresh
+    context's)."""
+    H = L.convdiff(2, 33, (6.0, -11.0))
+    W = to_dev(np.random.default_rng(500).standard_normal((H.n, 3)))
+    o = L.default_opts(restart=10, max_inner=400, precond="rbilu0", precond_sweeps=2)
+    d = [1e-10 * float(np.linalg.norm(W.cpu().numpy(), 2))]
+    Z1 = ctx.shifted_solve([H], [-80.0], [W], d, o)[0][0].cpu().numpy()
+    Z2 = ctx.shifted_solve([H], [-80.0], [W], d, o)[0][0].cpu().numpy()
+    assert np.array_equal(Z1, Z2)
+    H2 = L.HostCsr(H.rowptr, H.colind, H.val * 1.5)
+    Z3 = ctx.shifted_solve([H2], [-80.0], [W], d, o)[0][0].cpu().numpy()
+    c2 = L.Context(0)
+    try:
+        Z4 = c2.shifted_solve([H2], [-80.0], [W], d, o)[0][0].cpu().numpy()
+    finally:
+        c2.close()
+    assert np.array_equal(Z3, Z4)
+    assert not np.array_equal(Z3, Z1)
