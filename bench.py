@@ -34,6 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # (the fastest count on config 2: 16 -> 24 -> 32 sweeps gave 0.158, 0.152,
 # 0.157 s per FP64 solve)
 PRECOND_SWEEPS = 24
+# the 3-D configuration's Schur rows couple 18 neighbours instead of 8, so a
+# sweep costs more there and fewer pay (2, 4, 8, 16 sweeps: 0.313, 0.296,
+# 0.286, 0.310 s per FP32 solve before the setup cache)
+C3_PRECOND_SWEEPS = 8
 
 
 def parse():
@@ -303,7 +307,7 @@ def bench_c3(args, L, WL):
     fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
     ctx = L.Context(0)
     base = dict(tol=P.tol, b_is_transposed=1)
-    pre = _pre(PRECOND_SWEEPS)
+    pre = _pre(C3_PRECOND_SWEEPS)
     variants = [("fp32_relaxed", L.default_opts(selection="mid", precision="fp32", **base)),
                 ("fp64_relaxed", L.default_opts(selection="mid", **base)),
                 ("fp64_exact", L.default_opts(selection="relative", rho=1e-12, **base)),
