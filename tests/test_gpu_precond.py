@@ -33,7 +33,8 @@ def ctx(L):
 
 
 @pytest.mark.parametrize("dim,N,omega", [(2, 15, (8.0, -5.0)), (3, 7, (4.0, -2.0, 6.0))])
-@pytest.mark.parametrize("r,j,sweeps", [(1, 1, 0), (2, 3, 0), (4, 6, 0), (3, 4, 2), (8, 3, 1)])
+@pytest.mark.parametrize("r,j,sweeps", [(1, 1, 0), (2, 3, 0), (4, 6, 0), (3, 4, 2), (8, 3, 1), (4, 5, 5),
+                                         (2, 4, 24), (1, 3, 7)])
 def test_first_cycle_equals_preconditioned_minres_definition(L, ctx, dim, N, omega, r, j, sweeps):
     """restart = j, step cap j: the returned Z is the minimiser of
     ||W - S Z||_F over M K_j(S M, W), with M the oracle's red-black ILU(0)
@@ -97,7 +98,8 @@ def test_preconditioned_batch_equals_solo_runs(L, ctx):
 
 
 @pytest.mark.parametrize("name,precision,sweeps", [("SMALL_2D", "fp64", 0), ("SMALL_2D", "fp32", 2),
-                                                   ("SMALL_3D", "fp64", 2), ("SMALL_3D", "fp32", 0)])
+                                                   ("SMALL_3D", "fp64", 2), ("SMALL_3D", "fp32", 0),
+                                                   ("SMALL_2D", "fp64", 24), ("SMALL_2D", "fp32", 9)])
 def test_adi_with_preconditioned_inner_solves_matches_oracle(L, ctx, name, precision, sweeps):
     """Algorithm 1 with preconditioned inner solves: the oracle's steps
     (+-1), X within 1e-6 of the direct-solve iterate, true residual below
