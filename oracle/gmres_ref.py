@@ -36,12 +36,13 @@ def block_krylov_basis(S, W: np.ndarray, j: int) -> np.ndarray:
     return np.hstack(basis)
 
 
-def block_gmres_iterate(A, shift: float, W: np.ndarray, j: int, precond=None) -> np.ndarray:
-    """Z_j of block GMRES on (A + shift I) Z = W after j block steps.  With a
-    right preconditioner (precond(X) = M X) the space is M K_j(S M, W) and
-    the minimised residual is still ||W - S Z||_F."""
+def block_gmres_iterate(A, shift: float, W: np.ndarray, j: int, precond=None, M=None) -> np.ndarray:
+    """Z_j of block GMRES on (A + shift I) Z = W (or (A + shift M) Z = W)
+    after j block steps.  With a right preconditioner (precond(X) = P X) the
+    space is P K_j(S P, W) and the minimised residual is still ||W - S Z||_F."""
     n = W.shape[0]
-    S = sp.csr_matrix(A) + shift * sp.identity(n, format="csr")
+    E = sp.identity(n, format="csr") if M is None else sp.csr_matrix(M)
+    S = sp.csr_matrix(A) + shift * E
     if precond is None:
         V = block_krylov_basis(S, W, j)
         SV = np.asarray(S @ V)

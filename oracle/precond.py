@@ -19,6 +19,11 @@ S's pattern), so z_b = diag(T)^{-1} y_b; `sweeps` > 0 refines z_b by that
 many Jacobi steps on T y = ... (z_b += diag(T)^{-1} (y_b - T z_b)), which
 tends to the exact block solve (and M to S^{-1}) when Jacobi converges.
 
+For a pencil A + s M (the generalized equation) the preconditioner is built
+from A + s diag(M 1), M replaced by its row sums (mass lumping): the same
+bipartite pattern as A, while the Krylov solver still multiplies by the
+true pencil.
+
 Only tests/ and the bench's CPU baseline use this module.
 """
 from __future__ import annotations
@@ -57,9 +62,10 @@ def two_coloring(A) -> Optional[np.ndarray]:
     return col
 
 
-def rb_precond_apply(A, shift: float, V: np.ndarray, sweeps: int = 0) -> np.ndarray:
-    """M V for the red-black ILU(0) of A + shift I (module docstring), with
-    `sweeps` extra Jacobi steps on the Schur complement."""
+def rb_precond_apply(A, shift: float, V: np.ndarray, sweeps: int = 0, mass=None) -> np.ndarray:
+    """M V for the red-black ILU(0) of A + shift I, or of A + shift diag(mass 1)
+    when a mass matrix is given (module docstring), with `sweeps` extra Jacobi
+    steps on the Schur complement."""
     A = sp.csr_matrix(A)
     n = A.shape[0]
     col = two_coloring(A)
@@ -67,7 +73,11 @@ def rb_precond_apply(A, shift: float, V: np.ndarray, sweeps: int = 0) -> np.ndar
         raise ValueError("sparsity graph is not bipartite")
     red = np.where(col == 0)[0]
     blk = np.where(col == 1)[0]
-    S = (A + shift * sp.identity(n, format="csr")).tocsr()
+    if mass is None:
+        S = (A + shift * sp.identity(n, format="csr")).tocsr()
+    else:
+        lump = np.asarray(sp.csr_matrix(mass).sum(axis=1)).ravel()
+        S = (A + shift * sp.diags(lump)).tocsr()
     d = S.diagonal()
     E = S[red][:, blk]
     F = S[blk][:, red]

@@ -102,3 +102,45 @@ def test_preconditioned_gmres_definition():
         SMK = S @ MK
         assert np.linalg.norm(SMK.T @ res) <= 1e-9 * np.linalg.norm(SMK) * np.linalg.norm(res)
         assert np.linalg.norm(res) < np.linalg.norm(W - S @ Zn)
+
+
+def test_lumped_mass_pencil_preconditioner():
+    """For a pencil the preconditioner is the red-black ILU(0) of
+    A + s diag(M 1): equal to the plain form applied to the matrix
+    A + s diag(M 1) with shift 0, to the textbook ILU(0) of that matrix, and
+    for M = I to the plain preconditioner bit for bit."""
+    A = convdiff_matrix(2, 6, (9.0, -4.0))
+    n = A.shape[0]
+    rp, ci, v = WL.mass_csr(2, 6)
+    M = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    s = -35.0
+    V = np.random.default_rng(12).standard_normal((n, 2))
+    lump = np.asarray(M.sum(axis=1)).ravel()
+    As = (A + s * sp.diags(lump)).tocsr()
+    for k in (0, 3):
+        got = OP.rb_precond_apply(A, s, V, k, mass=M)
+        assert np.allclose(got, OP.rb_precond_apply(As, 0.0, V, k), rtol=1e-13, atol=1e-15)
+    col = OP.two_coloring(A)
+    perm = np.concatenate([np.where(col == 0)[0], np.where(col == 1)[0]])
+    Sd = As.toarray()[np.ix_(perm, perm)]
+    Lf, Uf = OP.ilu0_dense(Sd)
+    want = np.empty_like(V)
+    want[perm] = np.linalg.solve(Uf, np.linalg.solve(Lf, V[perm]))
+    assert np.allclose(OP.rb_precond_apply(A, s, V, 0, mass=M), want, rtol=1e-12, atol=1e-14)
+    I = sp.identity(n, format="csr")
+    assert np.array_equal(OP.rb_precond_apply(A, s, V, 2, mass=I), OP.rb_precond_apply(A, s, V, 2))
+
+
+def test_pencil_gmres_definition_with_exact_preconditioner():
+    """block_gmres_iterate with M: an exact right preconditioner of the
+    pencil solves in one block step."""
+    A = convdiff_matrix(2, 7, (5.0, 3.0))
+    n = A.shape[0]
+    rp, ci, v = WL.mass_csr(2, 7)
+    M = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    s = -60.0
+    S = (A + s * M).tocsc()
+    W = np.random.default_rng(13).standard_normal((n, 2))
+    exact = lambda X: spla.spsolve(S, X).reshape(X.shape)
+    Z1 = block_gmres_iterate(A, s, W, 1, precond=exact, M=M)
+    assert np.allclose(Z1, exact(W), rtol=1e-10, atol=1e-12)
