@@ -383,6 +383,7 @@ struct SysWork {
       d.nred = B.nred;
       d.sweeps = sweeps;
       d.diagT = (prec == LRADI_FP64) ? (const void*)B.diag64.p : (const void*)B.diag32.p;
+      d.msT = B.ms64.p ? ((prec == LRADI_FP64) ? (const void*)B.ms64.p : (const void*)B.ms32.p) : nullptr;
       d.rbw = B.rbw;
       d.ellci = B.ellci.as<int>();
       d.ellvalT = (prec == LRADI_FP64) ? (const void*)B.ellval64.p : (const void*)B.ellval32.p;
@@ -792,10 +793,10 @@ uint64_t csr_key(int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const
     h = (h ^ (x * 0x9E3779B97F4A7C15ull)) * 0x94D049BB133111EBull;
     h ^= h >> 29;
   };
-  mix(rp, sizeof(int32_t) * (size_t)(n + 1));
+  if (rp) mix(rp, sizeof(int32_t) * (size_t)(n + 1));
   if (nnz > 0) {
-    mix(ci, sizeof(int32_t) * (size_t)nnz);
-    mix(v, sizeof(double) * (size_t)nnz);
+    if (ci) mix(ci, sizeof(int32_t) * (size_t)nnz);
+    if (v) mix(v, sizeof(double) * (size_t)nnz);
   }
   return h;
 }
@@ -819,10 +820,21 @@ int par_threads(int n) {
   return n < 32768 ? 1 : nt;
 }
 
-int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, hipStream_t st, bool need32) {
+int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32) {
   std::vector<int32_t> rp, ci, trp, tci;
   std::vector<double> v, tv;
   if (!A || A->nrows != n) return set_error("preconditioner: matrix size differs from the uploaded one"), LRADI_EINVAL;
+  // pencil: M's row sums weight the shift inside the preconditioner
+  std::vector<double> lump;
+  if (M) {
+    std::vector<int32_t> mrp, mci;
+    std::vector<double> mv;
+    LRADI_TRY(host_csr(M, mrp, mci, mv));
+    if (M->nrows != n) return set_error("mass matrix size differs from its operator"), LRADI_EINVAL;
+    lump.assign(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int32_t k = mrp[i]; k < mrp[i + 1]; ++k) lump[i] += mv[k];
+  }
   // a matrix already prepared on this context (same contents) is reused
   uint64_t key;
   if (A->on_device) {
@@ -831,6 +843,7 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, hipStream_t st, bool 
   } else {
     key = csr_key(n, A->nnz, A->rowptr, A->colind, A->val, need32);
   }
+  if (M) key = (key * 0x5851F42D4C957F2Dull) ^ csr_key(n, n, nullptr, nullptr, lump.data(), false);
   for (auto it = ctx->rb_cache.begin(); it != ctx->rb_cache.end(); ++it)
     if (it->first == key) {
       rb = it->second;
@@ -973,6 +986,15 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, hipStream_t st, bool 
   LRADI_HIP(hipMemcpyAsync(R->t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(R->rbpos.p, h_pos.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
   const size_t ne = (size_t)W * nn;
+  if (!lump.empty()) {
+    LRADI_TRY(R->ms64.alloc(sizeof(double) * nn));
+    LRADI_HIP(hipMemcpyAsync(R->ms64.p, lump.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
+    if (need32) {
+      LRADI_TRY(R->ms32.alloc(sizeof(float) * nn));
+      hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, R->ms64.as<double>(),
+                         R->ms32.as<float>(), (int64_t)nn);
+    }
+  }
   LRADI_TRY(R->rbrows.alloc(sizeof(int32_t) * nn));
   LRADI_TRY(R->diag64.alloc(sizeof(double) * nn));
   LRADI_TRY(R->ellci.alloc(sizeof(int32_t) * ne));
@@ -1105,18 +1127,24 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   }
   const int sw = sweeps_for(o);
   if (sw >= 0) {
-    if (P.M || P.C) return set_error("the red-black preconditioner needs M = C = I"), LRADI_EINVAL;
-    LRADI_TRY(q.A.prepare_rb(c, P.A, st, f32));
+    // the preconditioner is built from the operators' own patterns (A, B^T);
+    // a mass matrix enters through its row sums
+    LRADI_TRY(q.A.prepare_rb(c, P.A, P.M, st, f32));
     if (!q.sym) {
       if (o.b_is_transposed) {
-        LRADI_TRY(q.Bt.prepare_rb(c, P.B, st, f32));
+        LRADI_TRY(q.Bt.prepare_rb(c, P.B, P.C, st, f32));
       } else {
-        std::vector<int32_t> trp, tci;
-        std::vector<double> tv;
+        std::vector<int32_t> trp, tci, crp, cci;
+        std::vector<double> tv, cv;
         LRADI_TRY(host_csr_t(P.B, trp, tci, tv));
         const int mB = P.B->nrows;
         lradi_csr Bt{mB, mB, (int64_t)tci.size(), trp.data(), tci.data(), tv.data(), 0};
-        LRADI_TRY(q.Bt.prepare_rb(c, &Bt, st, f32));
+        lradi_csr Ct{};
+        if (P.C) {
+          LRADI_TRY(host_csr_t(P.C, crp, cci, cv));
+          Ct = lradi_csr{P.C->nrows, P.C->nrows, (int64_t)cci.size(), crp.data(), cci.data(), cv.data(), 0};
+        }
+        LRADI_TRY(q.Bt.prepare_rb(c, &Bt, P.C ? &Ct : nullptr, st, f32));
       }
     }
   }
@@ -1508,7 +1536,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     if (!W[s] || !Z[s] || !(delta[s] >= 0.0) || !std::isfinite(shift[s]))
       return set_error("lradi_shifted_solve: bad system %d", s), LRADI_EINVAL;
     LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
-    if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(c, A[s], c->stream, o.precision == LRADI_FP32_INNER));
+    if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(c, A[s], nullptr, c->stream, o.precision == LRADI_FP32_INNER));
     work[s] = std::make_unique<SysWork>();
     LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o), sw));
     LRADI_TRY(work[s]->tune(c, mats[s], o.spmm_lanes));

@@ -157,6 +157,8 @@ struct SysDesc {
   int nred;             // number of red rows
   int sweeps;           // Jacobi sweeps on the Schur complement
   const void* diagT;    // diagonal of A per row, basis precision
+  const void* msT;      // pencils: M's row sums (the preconditioner's shift
+                        // weights), basis precision; null for M = I
   // off-diagonal entries by colour position p (row rbrows[p]), rbw slots
   // each, slot-major (slot u of position p at u * n + p); unused slots hold
   // the row itself with value 0
@@ -245,6 +247,9 @@ struct DevBuf {
 // the Schur complement's column pattern on the black rows (t2w slots).
 struct RbData {
   DevBuf rbrows, rbpos, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32, t2ci;
+  // pencils A + s M: the preconditioner takes M's row sums (lumped mass)
+  // as the per-row weight of the shift; empty for M = I
+  DevBuf ms64, ms32;
   int nred = 0, rbw = 0, t2w = 0;
 };
 
@@ -263,7 +268,8 @@ struct DevCSR {
   // 2-colour the sparsity graph of A (the matrix uploaded here) and upload
   // the colour-ordered rows, A's diagonal and its transposed values;
   // LRADI_EINVAL if the graph is not bipartite
-  int prepare_rb(lradi_ctx* ctx, const lradi_csr* A, hipStream_t st, bool need32);
+  // (M: the mass matrix of a pencil, or null)
+  int prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);
   bool has_rb() const { return rb != nullptr; }
 };
 

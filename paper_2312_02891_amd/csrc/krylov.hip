@@ -287,9 +287,17 @@ struct RbCtx {
   const T* val;
   const T* tv;
   const T* dg;
+  const T* ms;    // pencils: M's row sums, else null (weight 1)
   int w, n;
   T sh;
 };
+
+// diagonal of the matrix the preconditioner factors: a_jj + s, or
+// a_jj + s (M 1)_j for a pencil
+template <typename T>
+__device__ inline T rb_dsh(const RbCtx<T>& x, int j) {
+  return x.dg[j] + x.sh * (x.ms ? x.ms[j] : T(1));
+}
 
 template <typename T>
 __device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
@@ -298,6 +306,7 @@ __device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
   x.val = static_cast<const T*>(D.ellvalT);
   x.tv = static_cast<const T*>(D.elltvT);
   x.dg = static_cast<const T*>(D.diagT);
+  x.ms = static_cast<const T*>(D.msT);
   x.w = D.rbw;
   x.n = D.n;
   x.sh = (T)shift;
@@ -345,7 +354,7 @@ template <typename T, int R>
 __device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __restrict__ V, T (&y)[R], T& td) {
 #pragma unroll
   for (int q = 0; q < R; ++q) y[q] = V[(size_t)i * R + q];
-  td = x.dg[i] + x.sh;
+  td = rb_dsh(x, i);
   constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
     int col[kRbUnroll];
@@ -362,13 +371,13 @@ __device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __
     T xv[kRbUnroll][R];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      dj[u] = x.dg[col[u]];
+      dj[u] = rb_dsh(x, col[u]);
 #pragma unroll
       for (int q = 0; q < R; ++q) xv[u][q] = V[(size_t)col[u] * R + q];
     }
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const T wgt = a[u] / (dj[u] + x.sh);
+      const T wgt = a[u] / dj[u];
       td = ok[u] ? td - wgt * t[u] : td;
 #pragma unroll
       for (int q = 0; q < R; ++q) y[q] = ok[u] ? y[q] - wgt * xv[u][q] : y[q];
@@ -388,7 +397,7 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
     const size_t e = (size_t)u * x.n + p;
     const int j = x.ci[e];
     if (j == i) continue;  // unused slot
-    const T wj = x.val[e] / (x.dg[j] + x.sh);
+    const T wj = x.val[e] / rb_dsh(x, j);
     const int pj = D.rbpos[j];
     for (int u2 = 0; u2 < x.w; ++u2) {
       const size_t e2 = (size_t)u2 * x.n + pj;
@@ -481,7 +490,7 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
 #pragma unroll
       for (int q = 0; q < R; ++q) g[q] = T(0);
       rb_gather<T, R>(x, p, i, Pj, g);
-      const T di = x.dg[i] + x.sh;
+      const T di = rb_dsh(x, i);
 #pragma unroll
       for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = (V[(size_t)i * R + q] - g[q]) / di;
     }
