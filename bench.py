@@ -374,8 +374,11 @@ def bench_gen(args, L, WL):
     keep = {}
     # kmax = 100 as for the paper's generalized finite-element example (Sec. 4):
     # the pencils' spectra are wider than the operators' and need more steps
+    pre = _pre(PRECOND_SWEEPS)
     for name, kw in (("fp64_relaxed", dict(selection="mid")), ("fp32_relaxed", dict(selection="mid", precision="fp32")),
-                     ("fp64_fixed", dict(selection="fixed"))):
+                     ("fp64_fixed", dict(selection="fixed")),
+                     ("fp64_relaxed_precond", dict(selection="mid", **pre)),
+                     ("fp32_relaxed_precond", dict(selection="mid", precision="fp32", **pre))):
         o = L.default_opts(tol=P.tol, kmax=100, **kw)
         for _ in range(args.warmup):
             ctx.solve(HA, HB, fd, gd, pA, pB, o, M=HM, C=HC)
@@ -421,6 +424,7 @@ def bench_gen(args, L, WL):
                                   "shifts, tau=1e-8",
                       "n": P.A.n, "m": P.B.n, "steps": args.steps, **out,
                       "relaxed_saving_vs_fixed": round(1.0 - out["fp64_relaxed"]["s"] / out["fp64_fixed"]["s"], 3),
+                      "speedup_precond_fp64": round(out["fp64_relaxed"]["s"] / out["fp64_relaxed_precond"]["s"], 3),
                       "cpu_baseline": cpu}))
 
 
