@@ -319,7 +319,7 @@ struct SysWork {
                             512 * 8,                   // sm
                             sweeps >= 0 ? (mm + 1) * n * rr * tsz : 0,  // P
                             sweeps > 0 ? n * rr * tsz : 0,              // Yb
-                            sweeps > 0 ? n * rr * tsz : 0,              // Eb
+                            sweeps > 0 ? 2 * n * rr * tsz : 0,          // Eb (two compact iterates)
                             sweeps > 0 ? n * tsz : 0,                   // It
                             sweeps > 0 && A->has_rb()
                                 ? (size_t)A->rb->t2w * std::max(n - (size_t)A->rb->nred, (size_t)1) * tsz
@@ -970,17 +970,18 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
   int w2 = 0;
   for (int pb = 0; pb < nbk; ++pb) w2 = std::max(w2, ncol[pb]);
   const int W2 = std::max(w2, 1);
+  std::vector<int32_t> h_pos(nn);
+  for (int p = 0; p < nn; ++p) h_pos[rows[p]] = p;
+  // columns as black positions (the sweeps keep their iterates in that
+  // order); unused slots hold the row's own position
   std::vector<int32_t> h_t2ci((size_t)W2 * nbs);
   par_ranges(nbk, [&](int pa, int pe, int t) {
     for (int pb = pa; pb < pe; ++pb) {
-      const int i = rows[nr + pb];
       const size_t c0 = tstart[t][pb - pa];
       for (int q = 0; q < W2; ++q)
-        h_t2ci[(size_t)q * nbs + pb] = q < ncol[pb] ? tcols[t][c0 + q] : i;
+        h_t2ci[(size_t)q * nbs + pb] = q < ncol[pb] ? h_pos[tcols[t][c0 + q]] - nr : pb;
     }
   });
-  std::vector<int32_t> h_pos(nn);
-  for (int p = 0; p < nn; ++p) h_pos[rows[p]] = p;
   LRADI_TRY(R->t2ci.alloc(sizeof(int32_t) * h_t2ci.size()));
   LRADI_TRY(R->rbpos.alloc(sizeof(int32_t) * nn));
   LRADI_HIP(hipMemcpyAsync(R->t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));

@@ -167,12 +167,12 @@ struct SysDesc {
   const void* ellvalT;  // A's entry (i, col), basis precision
   const void* elltvT;   // A's entry (col, i), basis precision
   void* P;              // preconditioned basis blocks P_0..P_m, basis precision
-  void* Yb;             // sweeps: y of the black rows, n x r, basis precision
-  void* Eb;             // sweeps: the other black iterate, n x r
-  void* It;             // sweeps: 1 / diag(T) per black row, n
+  void* Yb;             // sweeps: y of the black rows by black position, basis precision
+  void* Eb;             // sweeps: two black iterates by black position
+  void* It;             // sweeps: 1 / diag(T) by black position
   // sweeps: the off-diagonal entries of T = D_b - F D_r^{-1} E by black
   // position (pb = p - nred), slot-major with nb = n - nred: columns t2ci
-  // (t2w slots, unused: the row itself) and values t2val, rebuilt for each
+  // as black positions (t2w slots, unused: its own) and values t2val, rebuilt for each
   // shift by walking two hops through the slot tables; rbpos[row] is the
   // row's colour position
   int t2w;

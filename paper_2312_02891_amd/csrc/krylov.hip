@@ -403,8 +403,9 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
       const size_t e2 = (size_t)u2 * x.n + pj;
       const int l = x.ci[e2];
       if (l == j || l == i) continue;
+      const int pl = D.rbpos[l] - D.nred;  // T's columns are black positions
       for (int q = 0; q < D.t2w; ++q)
-        if (D.t2ci[(size_t)q * nb + pb] == l) {
+        if (D.t2ci[(size_t)q * nb + pb] == pl) {
           tv[(size_t)q * nb + pb] -= wj * x.val[e2];
           break;
         }
@@ -412,16 +413,17 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
   }
 }
 
-// one Jacobi sweep on T z = y for black position pb (row i):
-// dst_i = (y_i - sum_u T_il(u) src_l(u)) / diag(T)_i
+// one Jacobi sweep on T z = y for black position pb: dst row drow =
+// (y_pb - sum_u T(pb, l_u) src_{l_u}) / diag(T)_pb, with y, 1/diag(T) and
+// src in black-position order
 template <typename T, int R>
-__device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, int i, const T* __restrict__ src,
-                                    T* __restrict__ dst) {
+__device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
+                                    T* __restrict__ dst, size_t drow) {
   const T* tv = static_cast<const T*>(D.t2val);
   const T* Y = static_cast<const T*>(D.Yb);
   T acc[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)i * R + q];
+  for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)pb * R + q];
   constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < D.t2w; u0 += kRbUnroll) {
     int col[kRbUnroll];
@@ -432,7 +434,7 @@ __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, int i, con
       const size_t e = (size_t)min(u0 + u, D.t2w - 1) * nb + pb;
       col[u] = D.t2ci[e];
       a[u] = tv[e];
-      ok[u] = (u0 + u < D.t2w) && col[u] != i;
+      ok[u] = (u0 + u < D.t2w) && col[u] != pb;
     }
     T xv[kRbUnroll][R];
 #pragma unroll
@@ -444,16 +446,16 @@ __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, int i, con
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
   }
-  const T it = static_cast<const T*>(D.It)[i];
+  const T it = static_cast<const T*>(D.It)[pb];
 #pragma unroll
-  for (int q = 0; q < R; ++q) dst[(size_t)i * R + q] = acc[q] * it;
+  for (int q = 0; q < R; ++q) dst[drow * R + q] = acc[q] * it;
 }
 
-// the black iterate of sweep t lives in P_j or in Eb, so that the last one
-// (t = sweeps) lands in P_j
+// black iterate t (< sweeps) in black-position order: two compact blocks in
+// Eb, alternating; the last iterate goes to P_j's black rows instead
 template <typename T>
-__device__ inline T* rb_iter(const SysDesc& D, T* Pj, int t) {
-  return ((D.sweeps - t) % 2 == 0) ? Pj : static_cast<T*>(D.Eb);
+__device__ inline T* rb_compact(const SysDesc& D, int nb, int t) {
+  return static_cast<T*>(D.Eb) + (size_t)(t % 2) * nb * D.r;
 }
 
 // stage 0: fwd (black rows; builds T's values at the first Arnoldi step of
@@ -473,18 +475,26 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
       T y[R], td;
       rb_black_fwd<T, R>(x, p, i, V, y, td);
       const T it = T(1) / td;
-      T* z0 = rb_iter<T>(D, Pj, 0);
+      if (D.sweeps == 0) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) z0[(size_t)i * R + q] = y[q] * it;
-      if (D.sweeps > 0) {
+        for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = y[q] * it;
+      } else {
+        T* z0 = rb_compact<T>(D, nb, 0);
         T* Y = static_cast<T*>(D.Yb);
 #pragma unroll
-        for (int q = 0; q < R; ++q) Y[(size_t)i * R + q] = y[q];
-        static_cast<T*>(D.It)[i] = it;
+        for (int q = 0; q < R; ++q) {
+          z0[(size_t)pp * R + q] = y[q] * it;
+          Y[(size_t)pp * R + q] = y[q];
+        }
+        static_cast<T*>(D.It)[pp] = it;
         if (build) rb_build_t<T>(D, x, p, pp, nb, i);
       }
     } else if constexpr (KIND == 1) {
-      rb_sweep_row<T, R>(D, pp, nb, i, rb_iter<T>(D, Pj, stage - 1), rb_iter<T>(D, Pj, stage));
+      const T* src = rb_compact<T>(D, nb, stage - 1);
+      if (stage == D.sweeps)
+        rb_sweep_row<T, R>(D, pp, nb, src, Pj, (size_t)i);
+      else
+        rb_sweep_row<T, R>(D, pp, nb, src, rb_compact<T>(D, nb, stage), (size_t)pp);
     } else {  // back: z_r = (v_r - E z) / (d_r + s)
       T g[R];
 #pragma unroll
