@@ -287,7 +287,7 @@ typedef struct {
   const lradi_csr* B;      /* m x m: B, or B^T when opts->b_is_transposed      */
   const double* f;         /* device, n x r row-major (not modified)           */
   const double* g;         /* device, m x r row-major (not modified)           */
-  int32_t r;               /* 1..8                                             */
+  int32_t r;               /* 1..8, at most n and m                            */
   int32_t nshifts;
   const double* shiftsA;   /* host, nshifts (added to A)                       */
   const double* shiftsB;   /* host, nshifts (added to B^T)                     */

@@ -299,6 +299,8 @@ struct SysWork {
            int sweeps = -1) {
     if (r < 1 || r > kMaxR || m < 1 || m > kMaxM)
       return set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM), LRADI_EINVAL;
+    // a block of more columns than rows has no full-rank basis
+    if (r > A->n) return set_error("r (%d) exceeds the system size (%d)", r, A->n), LRADI_EINVAL;
     const size_t n = A->n, rr = r, mm = m;
     const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
     const int rpw = choose_rows_per_wg((int)n);

@@ -250,3 +250,39 @@ def test_prepared_matrix_cache_is_keyed_by_contents(L, ctx):
         c2.close()
     assert np.array_equal(Z3, Z4)
     assert not np.array_equal(Z3, Z1)
+
+
+def test_preconditioner_degenerate_patterns(L, ctx):
+    """Edge cases of the colouring: a diagonal matrix (every row isolated,
+    all red, no black rows: the preconditioner is the exact inverse, one
+    block step), a 1-D chain (tridiagonal, alternating colours) and n = 1.
+    Each solve reaches delta, checked on the host; a block wider than the
+    system (r > n) is rejected."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(600)
+    cases = []
+    d = rng.uniform(2.0, 5.0, 37)
+    cases.append(("diagonal", sp.diags(d).tocsr(), 1))
+    n = 29
+    T = sp.diags([-np.ones(n - 1) * 1.3, np.full(n, 4.0), -np.ones(n - 1) * 0.7], [-1, 0, 1]).tocsr()
+    cases.append(("chain", T, None))
+    cases.append(("one", sp.csr_matrix(np.array([[3.0]])), 1))
+    for name, A, steps in cases:
+        A.sort_indices()
+        H = L.HostCsr(A.indptr, A.indices, A.data)
+        W = rng.standard_normal((A.shape[0], min(2, A.shape[0])))
+        delta = 1e-10 * np.linalg.norm(W, 2)
+        for sweeps in (0, 3):
+            o = L.default_opts(restart=8, max_inner=200, precond="rbilu0", precond_sweeps=sweeps)
+            Zs, st, rc = ctx.shifted_solve([H], [-1.5], [to_dev(W)], [delta], o)
+            Z = Zs[0].cpu().numpy()
+            rn = np.linalg.norm(W - (A @ Z - 1.5 * Z), 2)
+            say("  degenerate", name, sweeps, "steps", st[0]["steps"], "rn", rn)
+            assert rc == L.OK and rn <= delta * (1 + 1e-8)
+            if steps is not None:
+                assert st[0]["steps"] == steps
+    H1 = L.HostCsr(np.array([0, 1]), np.array([0]), np.array([3.0]))
+    with pytest.raises(L.LradiError) as e:
+        ctx.shifted_solve([H1], [-1.5], [to_dev(np.ones((1, 2)))], [1e-10],
+                          L.default_opts(precond="rbilu0"))
+    assert e.value.status == L.EINVAL
