@@ -601,6 +601,8 @@ def bench_serve(args, L, WL):
                       "p99_s": round(float(np.percentile(arr, 99)), 4),
                       "solves_per_s": round(count / wall, 2), "wall_s": round(wall, 3),
                       "offered_rate": args.rate, "ok": sum(1 for v in status.values() if v == 0),
+                      "status_counts": {str(k): sum(1 for v in status.values() if v == k)
+                                        for k in sorted(set(status.values()))},
                       "outer_steps_run": stats["steps"]}))
 
 
