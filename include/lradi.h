@@ -233,9 +233,10 @@ int lradi_spmm_tune(lradi_ctx* ctx, const lradi_csr* A, int r, int precision, in
  * the inner solves of Algorithm 1, eq. (gfadi_incsolves).  All systems run
  * in the same kernel launches.  A[s]: csr (host or device); W[s]: device,
  * n_s x r[s] doubles; Z[s]: device, n_s x r[s] doubles, overwritten (zero
- * initial guess).  shift, delta, r: host arrays of nsys.  opts: precision,
- * restart, max_inner, fp32_floor are used (NULL = defaults).  stats: host
- * array of nsys, may be NULL.  Warning LRADI_WINNER if a step cap was hit. */
+ * initial guess).  shift, delta, r (1..8, at most n_s): host arrays of
+ * nsys.  opts: precision, restart, max_inner, fp32_floor, precond,
+ * precond_sweeps are used (NULL = defaults).  stats: host array of nsys, may
+ * be NULL.  Warning LRADI_WINNER if a step cap was hit. */
 int lradi_shifted_solve(lradi_ctx* ctx, int nsys, const lradi_csr* const* A,
                         const double* shift, const double* const* W, double* const* Z,
                         const int* r, const double* delta, const lradi_opts* opts,
