@@ -568,8 +568,10 @@ def bench_serve(args, L, WL):
     ctx = L.Context(0)
     # FP32 inner / FP64 outer; the controller works in the balanced frame,
     # since n and m of one request can differ by three orders of magnitude
-    srv = L.Server(ctx, L.default_opts(precision="fp32", rescale=2, **_pre(args.precond_sweeps)), hbm_budget=0,
-                   max_active=64)
+    # kmax 100: the tightest requests (tau down to 1e-10) can need more than
+    # the default 50 steps
+    srv = L.Server(ctx, L.default_opts(precision="fp32", rescale=2, kmax=100, **_pre(args.precond_sweeps)),
+                   hbm_budget=0, max_active=64)
     tickets, lat, status = [], {}, {}
     t0 = time.perf_counter()
     i = 0
