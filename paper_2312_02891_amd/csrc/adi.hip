@@ -344,6 +344,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
                                                        AdiCtl* __restrict__ ac, SysCtl* __restrict__ ctl) {
   __shared__ double red_lds[kTPB];
   __shared__ double GW[64], GZ[64], GT[64], GY[64];
+  __shared__ double nrm[5];
   const int p = blockIdx.x;
   const AdiDesc& P = ad[p];
   AdiCtl& C = ac[p];
@@ -365,15 +366,21 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, GT);
     reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
   }
+  // the five small eigenvalue problems run concurrently: the four Grams on
+  // lanes 0-3 of the first wavefront (one code path, in lockstep), the
+  // product on the second wavefront
+  if (threadIdx.x < 4) {
+    const double* G = threadIdx.x == 0 ? GW : threadIdx.x == 1 ? GT : threadIdx.x == 2 ? GZ : GY;
+    nrm[threadIdx.x] = sqrt(fmax(lambda_max_sym(G, R), 0.0));
+  } else if (threadIdx.x == 64) {
+    nrm[4] = sqrt(fmax(lambda_max_prod(GW, GT, R), 0.0));
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     const int k = C.k;
     const int js = k % P.nshifts;
     const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
-    const double nw = sqrt(fmax(lambda_max_sym(GW, R), 0.0));
-    const double nt = sqrt(fmax(lambda_max_sym(GT, R), 0.0));
-    const double nz = sqrt(fmax(lambda_max_sym(GZ, R), 0.0));
-    const double ny = sqrt(fmax(lambda_max_sym(GY, R), 0.0));
-    const double res = sqrt(fmax(lambda_max_prod(GW, GT, R), 0.0));
+    const double nw = nrm[0], nt = nrm[1], nz = nrm[2], ny = nrm[3], res = nrm[4];
     const double rA = A.rnorm, rB = P.sym ? A.rnorm : B.rnorm;
     double u = C.u, v = C.v;
     ctl_update_gap(&u, &v, gamma, nz, ny, rA, rB);
