@@ -393,6 +393,13 @@ template <typename T>
 __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, int pb, int nb, int i) {
   T* tv = static_cast<T*>(D.t2val);
   for (int q = 0; q < D.t2w; ++q) tv[(size_t)q * nb + pb] = T(0);
+  // rows of up to kT2Reg slots find a column's slot by comparing against
+  // their columns held in registers, wider rows by reading the table
+  constexpr int kT2Reg = 32;
+  const bool reg = D.t2w <= kT2Reg;
+  int cols[kT2Reg];
+#pragma unroll
+  for (int q = 0; q < kT2Reg; ++q) cols[q] = (reg && q < D.t2w) ? D.t2ci[(size_t)q * nb + pb] : -1;
   for (int u = 0; u < x.w; ++u) {
     const size_t e = (size_t)u * x.n + p;
     const int j = x.ci[e];
@@ -404,11 +411,15 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
       const int l = x.ci[e2];
       if (l == j || l == i) continue;
       const int pl = D.rbpos[l] - D.nred;  // T's columns are black positions
-      for (int q = 0; q < D.t2w; ++q)
-        if (D.t2ci[(size_t)q * nb + pb] == pl) {
-          tv[(size_t)q * nb + pb] -= wj * x.val[e2];
-          break;
-        }
+      int slot = -1;
+      if (reg) {
+#pragma unroll
+        for (int q = 0; q < kT2Reg; ++q) slot = (cols[q] == pl) ? q : slot;
+      } else {
+        for (int q = 0; q < D.t2w && slot < 0; ++q)
+          if (D.t2ci[(size_t)q * nb + pb] == pl) slot = q;
+      }
+      if (slot >= 0) tv[(size_t)slot * nb + pb] -= wj * x.val[e2];
     }
   }
 }
