@@ -125,15 +125,76 @@ LRADI_HD inline void jacobi_eig_t(double* a, double* q) {
   }
 }
 
-// Largest eigenvalue of a symmetric positive semidefinite N x N matrix.
+// Largest eigenvalue of a symmetric positive semidefinite N x N matrix:
+// Householder reduction to a tridiagonal matrix (scaled by a power of two
+// so that no square overflows), then bisection on the Sturm count (the
+// number of negative pivots of T - x I equals the number of eigenvalues
+// below x) between max_i t_ii and the Gershgorin bound, to the last bit.
 template <int N>
 LRADI_HD inline double lambda_max_sym_t(const double* G) {
+  if (N == 1) return G[0];
   double a[N * N];
-  LRADI_UNROLL for (int e = 0; e < N * N; ++e) a[e] = G[e];
-  jacobi_eig_t<N, false>(a, nullptr);
-  double m = 0.0;
-  LRADI_UNROLL for (int i = 0; i < N; ++i) m = fmax(m, a[i * N + i]);
-  return m;
+  double amax = 0.0;
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) amax = fmax(amax, fabs(G[e]));
+  if (!(amax > 0.0)) return amax == 0.0 ? 0.0 : amax;  // zero matrix, or NaN
+  int ex;
+  frexp(amax, &ex);
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) a[e] = ldexp(G[e], -ex);
+  double d[N], off[N];
+  LRADI_UNROLL for (int k = 0; k < N - 2; ++k) {
+    double s2 = 0.0;
+    LRADI_UNROLL for (int i = k + 1; i < N; ++i) s2 += a[i * N + k] * a[i * N + k];
+    const double x0 = a[(k + 1) * N + k];
+    const double alpha = s2 > 0.0 ? -copysign(sqrt(s2), x0) : 0.0;
+    double v[N];
+    LRADI_UNROLL for (int i = 0; i < N; ++i) v[i] = (i > k + 1) ? a[i * N + k] : 0.0;
+    v[k + 1] = x0 - alpha;
+    double vtv = 0.0;
+    LRADI_UNROLL for (int i = k + 1; i < N; ++i) vtv += v[i] * v[i];
+    off[k] = alpha;
+    if (!(vtv > 0.0)) continue;  // the column is already reduced
+    const double beta = 2.0 / vtv;
+    // trailing block A22 <- H A22 H, H = I - beta v v^T: p = beta A22 v,
+    // q = p - (beta v^T p / 2) v, A22 -= v q^T + q v^T
+    double pv[N];
+    double vtp = 0.0;
+    LRADI_UNROLL for (int i = k + 1; i < N; ++i) {
+      double t = 0.0;
+      LRADI_UNROLL for (int j = k + 1; j < N; ++j) t += a[i * N + j] * v[j];
+      pv[i] = beta * t;
+      vtp += v[i] * pv[i];
+    }
+    const double K = 0.5 * beta * vtp;
+    LRADI_UNROLL for (int i = k + 1; i < N; ++i) pv[i] -= K * v[i];
+    LRADI_UNROLL for (int i = k + 1; i < N; ++i)
+      LRADI_UNROLL for (int j = k + 1; j < N; ++j) a[i * N + j] -= v[i] * pv[j] + pv[i] * v[j];
+  }
+  LRADI_UNROLL for (int i = 0; i < N; ++i) d[i] = a[i * N + i];
+  off[N - 2] = a[(N - 1) * N + (N - 2)];
+  double lo = d[0], hi = -1e300, e2max = 0.0;
+  LRADI_UNROLL for (int i = 0; i < N; ++i) {
+    lo = fmax(lo, d[i]);
+    const double r = (i > 0 ? fabs(off[i - 1]) : 0.0) + (i < N - 1 ? fabs(off[i]) : 0.0);
+    hi = fmax(hi, d[i] + r);
+    if (i < N - 1) e2max = fmax(e2max, off[i] * off[i]);
+  }
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
+  for (int it = 0; it < 128 && hi > lo; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;  // adjacent doubles
+    int below = 0;
+    double q = d[0] - mid;
+    if (fabs(q) < pivmin) q = -pivmin;
+    below += q < 0.0;
+    LRADI_UNROLL for (int i = 1; i < N; ++i) {
+      q = d[i] - mid - off[i - 1] * off[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      below += q < 0.0;
+    }
+    if (below == N) hi = mid;
+    else lo = mid;
+  }
+  return ldexp(0.5 * (lo + hi), ex);
 }
 
 // Largest eigenvalue of the product Gw Gt of two symmetric positive

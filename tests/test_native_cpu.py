@@ -183,3 +183,26 @@ def test_controller_matches_oracle(ST, seed):
     ST.st_gap(ctypes.byref(uu), ctypes.byref(vv), -7.5, nw, nt, 1e-9, 3e-9)
     wu, wv = OC.update_gap(u, v, -7.5, nw, nt, 1e-9, 3e-9)
     assert uu.value == pytest.approx(wu, rel=1e-14) and vv.value == pytest.approx(wv, rel=1e-14)
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_lambda_max_sym_hard_cases(ST, n):
+    """The largest eigenvalue to 1e-13 relative on PSD matrices of wide
+    condition, rank-deficient ones, repeated eigenvalues, diagonal ones, and
+    scales near the ends of the double range; the zero matrix gives 0."""
+    rng = np.random.default_rng(300 + n)
+    cases = [_spd(rng, n, 1e12), np.diag(rng.uniform(0.1, 5.0, n)), np.eye(n) * 3.7]
+    X = rng.standard_normal((n, max(1, n // 2)))
+    cases.append(X @ X.T)                      # rank n // 2
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.full(n, 2.0)
+    ev[0] = 1e-9
+    cases.append(Q @ np.diag(ev) @ Q.T)        # repeated top eigenvalue
+    B = _spd(rng, n, 1e3)
+    cases += [B * 1e-280, B * 1e280]
+    for G in cases:
+        G = np.ascontiguousarray((G + G.T) / 2)
+        want = np.linalg.eigvalsh(G).max()
+        assert ST.st_lmax(_p(G), n) == pytest.approx(want, rel=1e-13, abs=1e-300)
+    Z = np.zeros((n, n))
+    assert ST.st_lmax(_p(Z), n) == 0.0
