@@ -286,3 +286,45 @@ def test_preconditioner_degenerate_patterns(L, ctx):
         ctx.shifted_solve([H1], [-1.5], [to_dev(np.ones((1, 2)))], [1e-10],
                           L.default_opts(precond="rbilu0"))
     assert e.value.status == L.EINVAL
+
+
+def test_preconditioned_mixed_batch_and_server_equal_solo(L, ctx):
+    """2-D and 3-D problems (different slot widths) with the preconditioner,
+    batched and then served: each result equals its solo run bit for bit."""
+    o = L.default_opts(precond="rbilu0", precond_sweeps=6)
+    probs, solos = [], []
+    for name in ("SMALL_2D", "SMALL_3D", "C1"):
+        P = getattr(WL, name)
+        HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+        HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
+        f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+        pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+        fd, gd = to_dev(f), to_dev(g)
+        probs.append((HA, HB, fd, gd, pA, pB, P.tol))
+        solos.append(ctx.solve(HA, HB, fd, gd, pA, pB, o))
+    res, st = ctx.batch_solve(probs, o)
+    assert st == L.OK
+    for a, b in zip(res, solos):
+        assert a.k == b.k
+        for x, y in zip(a.factors(), b.factors()):
+            assert np.array_equal(x, y)
+    c2 = L.Context(0)
+    srv = L.Server(c2, o)
+    try:
+        import time
+        tickets = [srv.submit(*p) for p in probs]
+        got, t0 = {}, time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 60:
+            for t in tickets:
+                if t not in got:
+                    r = srv.poll(t)
+                    if r is not None:
+                        got[t] = r[0]
+            time.sleep(0.01)
+        assert len(got) == len(tickets)
+        for t, ref in zip(tickets, solos):
+            for x, y in zip(got[t].factors(), ref.factors()):
+                assert np.array_equal(x, y)
+    finally:
+        srv.close()
+        c2.close()
