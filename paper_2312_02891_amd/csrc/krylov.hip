@@ -479,7 +479,11 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
   constexpr bool black = KIND != 2;
   const int off = black ? D.nred : 0;
   const int cnt = black ? nb : D.nred;
-  for (int pp = c.row0 + threadIdx.x; pp < min(c.row1, cnt); pp += kTPB) {
+  // the colour's rows spread evenly over all of the system's workgroups
+  // (about half a chunk each), not over the first half of them
+  const int bc = (cnt + D.nwg - 1) / D.nwg;
+  const int p0 = c.w * bc, p1 = min(cnt, p0 + bc);
+  for (int pp = p0 + threadIdx.x; pp < p1; pp += kTPB) {
     const int p = off + pp;  // colour position
     const int i = D.rbrows[p];
     if constexpr (KIND == 0) {
