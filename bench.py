@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # Jacobi sweeps on the Schur complement in the preconditioned inner solves
 # (the fastest count on config 2: 16 -> 24 -> 32 sweeps gave 0.158, 0.152,
 # 0.157 s per FP64 solve)
-PRECOND_SWEEPS = 24
+PRECOND_SWEEPS = 32
 # the 3-D configuration's Schur rows couple 18 neighbours instead of 8, so a
 # sweep costs more there and fewer pay (2, 4, 8, 16 sweeps: 0.313, 0.296,
 # 0.286, 0.310 s per FP32 solve before the setup cache)
@@ -125,6 +125,7 @@ def main():
         for name, kw in [("tight_fixed", dict(selection="fixed", **pre)),
                          ("fp32_inner_relaxed", dict(selection="mid", precision="fp32", **pre)),
                          ("relaxed_graph_replay", dict(selection="mid", use_graph=1, **pre)),
+                         ("relaxed_single_sweep_launches", dict(selection="mid", precond_pairs=0, **pre)),
                          ("unpreconditioned_relaxed", dict(selection="mid")),
                          ("unpreconditioned_fp32_inner_relaxed", dict(selection="mid", precision="fp32"))]:
             o = L.default_opts(**base, **kw)

@@ -148,7 +148,11 @@ typedef struct {
                           graph (else LRADI_EINVAL)                        */
   int32_t precond_sweeps; /* LRADI_PRECOND_RBILU0: Jacobi sweeps on the
                           Schur complement after the ILU(0) step, 0..64  */
-  int32_t reserved[1];
+  int32_t precond_pairs;  /* 1 (default): run the sweeps two per launch where
+                          the black rows tile well (each tile's first sweep
+                          also covers the rows its second one reads, kept in
+                          workgroup memory); the results equal one sweep
+                          per launch bit for bit.  0: one per launch       */
 } lradi_opts;
 
 /* Per inner solve statistics (lradi_shifted_solve). */

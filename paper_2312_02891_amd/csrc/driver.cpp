@@ -22,6 +22,7 @@
 
 #include "adi.h"
 #include "internal.h"
+#include "rbhost.h"
 
 namespace lradi {
 
@@ -296,7 +297,7 @@ struct SysWork {
 
   // sweeps < 0: no preconditioner; else A must carry the red-black data
   int init(const DevCSR* A, const double* W, int r, int m, int prec, int max_inner, double floor_rel,
-           int sweeps = -1) {
+           int sweeps = -1, bool pairs = false) {
     if (r < 1 || r > kMaxR || m < 1 || m > kMaxM)
       return set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM), LRADI_EINVAL;
     // a block of more columns than rows has no full-rank basis
@@ -384,6 +385,16 @@ struct SysWork {
       d.rbrows = B.rbrows.as<int>();
       d.nred = B.nred;
       d.sweeps = sweeps;
+      d.halo_off = B.halo_off.as<int>();
+      d.halo = B.halo.as<int>();
+      d.t2lc = B.t2lc.as<int>();
+      d.nhalo = B.nhalo;
+      // pairs where the tiles are the row workgroups' black chunks and
+      // their regions are small enough
+      const size_t nb = n - (size_t)B.nred, lds = (size_t)B.maxreg * rr * tsz;
+      const bool fit = B.ntile > 0 && B.tile == (int)((nb + nwg - 1) / nwg) && lds <= (size_t)kPairLdsMax &&
+                       (double)(nb + B.nhalo) <= kPairMaxRegion * (double)nb;
+      d.pair_lds = (pairs && sweeps >= 2 && fit) ? (int)lds : 0;
       d.diagT = (prec == LRADI_FP64) ? (const void*)B.diag64.p : (const void*)B.diag32.p;
       d.msT = B.ms64.p ? ((prec == LRADI_FP64) ? (const void*)B.ms64.p : (const void*)B.ms32.p) : nullptr;
       d.rbw = B.rbw;
@@ -467,7 +478,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hd.resize(nsys);
   t.hc.resize(nsys);
   t.hmap.clear();
-  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0;
+  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -483,6 +494,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
         return set_error("all preconditioned systems of a batch must use one sweep count"), LRADI_EINVAL;
       precond = 1;
       sweeps = ws[s]->d.sweeps;
+      if (ws[s]->d.pair_lds == 0) pairs = 0;
+      pair_lds = std::max(pair_lds, ws[s]->d.pair_lds);
     }
   }
   // shifted-product tiles, grouped by lanes per row
@@ -526,6 +539,9 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.rfix = rfix;
   t.b.precond = precond;
   t.b.sweeps = sweeps;
+  t.b.pairs = precond && pairs && sweeps >= 2;
+  t.b.pair_lds = t.b.pairs ? pair_lds : 0;
+  t.b.precond_launches = precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) : 0;
   return LRADI_OK;
 }
 
@@ -550,7 +566,7 @@ int probe_account(lradi_ctx* ctx, const TickProbe& p, const Batch& bt) {
   if (bt.precond) {
     LRADI_HIP(hipEventElapsedTime(&e, p.ev[6], p.ev[7]));
     ctx->prof_ms[LRADI_PROF_PRECOND] += (double)e;
-    ctx->prof_launches[LRADI_PROF_PRECOND] += bt.sweeps + 2;
+    ctx->prof_launches[LRADI_PROF_PRECOND] += bt.precond_launches;
   }
   return LRADI_OK;
 }
@@ -738,6 +754,7 @@ int check_opts(const lradi_opts& o) {
     return set_error("unknown preconditioner"), LRADI_EINVAL;
   if (o.precond_sweeps < 0 || o.precond_sweeps > 64)
     return set_error("precond_sweeps must be in 0..64"), LRADI_EINVAL;
+  if (o.precond_pairs != 0 && o.precond_pairs != 1) return set_error("precond_pairs must be 0 or 1"), LRADI_EINVAL;
   return LRADI_OK;
 }
 
@@ -803,25 +820,6 @@ uint64_t csr_key(int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const
   return h;
 }
 
-// f(begin, end) over [0, n) split across a few host threads (one range
-// when n is small)
-template <class F>
-void par_ranges(int n, F f) {
-  const int nt = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
-  if (n < 32768 || nt == 1) {
-    f(0, n, 0);
-    return;
-  }
-  std::vector<std::thread> th;
-  const int chunk = (n + nt - 1) / nt;
-  for (int t = 0; t < nt; ++t) th.emplace_back(f, std::min(n, t * chunk), std::min(n, (t + 1) * chunk), t);
-  for (auto& x : th) x.join();
-}
-int par_threads(int n) {
-  const int nt = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
-  return n < 32768 ? 1 : nt;
-}
-
 int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32) {
   std::vector<int32_t> rp, ci, trp, tci;
   std::vector<double> v, tv;
@@ -856,158 +854,35 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
   auto R = std::make_shared<RbData>();
   const int nn = A->nrows;
   csr_transpose(nn, rp.data(), ci.data(), v.data(), trp, tci, tv);
-  // breadth-first 2-colouring over the union of A's and A^T's off-diagonal
-  // patterns (stored zeros count), the lowest row of each component red
-  std::vector<int8_t> col(nn, -1);
-  std::vector<int32_t> queue(nn);
-  for (int s0 = 0; s0 < nn; ++s0) {
-    if (col[s0] >= 0) continue;
-    col[s0] = 0;
-    int head = 0, tail = 0;
-    queue[tail++] = s0;
-    while (head < tail) {
-      const int u = queue[head++];
-      for (int pass = 0; pass < 2; ++pass) {
-        const int32_t* R = pass ? trp.data() : rp.data();
-        const int32_t* C = pass ? tci.data() : ci.data();
-        for (int32_t k = R[u]; k < R[u + 1]; ++k) {
-          const int w = C[k];
-          if (w == u) continue;
-          if (col[w] < 0) {
-            col[w] = (int8_t)(1 - col[u]);
-            queue[tail++] = w;
-          } else if (col[w] == col[u]) {
-            return set_error("red-black preconditioner: the sparsity graph is not bipartite"), LRADI_EINVAL;
-          }
-        }
-      }
-    }
-  }
-  std::vector<int32_t> rows;
-  rows.reserve(nn);
-  for (int i = 0; i < nn; ++i)
-    if (col[i] == 0) rows.push_back(i);
-  const int nr = (int)rows.size();
-  for (int i = 0; i < nn; ++i)
-    if (col[i] == 1) rows.push_back(i);
-  // diagonal per row; off-diagonal entries (col, a_i,col, a_col,i) per colour
-  // position in rbw slots, the transposed value from row i of A^T
-  std::vector<double> dg(nn, 0.0);
-  int w = 0;
-  for (int i = 0; i < nn; ++i) {
-    int c = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      if (ci[k] == i) dg[i] += v[k];
-      else ++c;
-    }
-    w = std::max(w, c);
-  }
-  const int W = std::max(w, 1);
-  std::vector<int32_t> r_eci((size_t)W * nn);
-  std::vector<double> r_eval((size_t)W * nn, 0.0), r_etv((size_t)W * nn, 0.0);
-  par_ranges(nn, [&](int pa, int pe, int) {
-    for (int p = pa; p < pe; ++p) {
-      const int i = rows[p];
-      const size_t e0 = (size_t)p * W;
-      int u = 0;
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        if (ci[k] == i) continue;
-        double a = 0.0;
-        for (int32_t kk = trp[i]; kk < trp[i + 1]; ++kk)
-          if (tci[kk] == ci[k]) a += tv[kk];
-        r_eci[e0 + u] = ci[k];
-        r_eval[e0 + u] = v[k];
-        r_etv[e0 + u] = a;
-        ++u;
-      }
-      for (; u < W; ++u) r_eci[e0 + u] = i;
-    }
-  });
-  std::vector<int32_t> eci((size_t)W * nn);
-  std::vector<double> eval((size_t)W * nn), etv((size_t)W * nn);
-  par_ranges(nn, [&](int pa, int pe, int) {
-    for (int p0 = pa; p0 < pe; p0 += 256)  // blocked: the source block stays in cache
-      for (int u = 0; u < W; ++u)
-        for (int p = p0; p < std::min(pe, p0 + 256); ++p) {
-          eci[(size_t)u * nn + p] = r_eci[(size_t)p * W + u];
-          eval[(size_t)u * nn + p] = r_eval[(size_t)p * W + u];
-          etv[(size_t)u * nn + p] = r_etv[(size_t)p * W + u];
-        }
-  });
-  // Schur complement T = D_b - F D_r^{-1} E on the black rows: its
-  // off-diagonal columns, the distinct two-hop black neighbours l != i in
-  // order of first appearance (the values depend on the shift and are
-  // built on the device); slot_of[l] maps a column to its slot while its
-  // row is being built
-  const int nbk = nn - nr;
-  const size_t nbs = (size_t)std::max(nbk, 1);
-  const int nth = par_threads(nbk);
-  std::vector<std::vector<int32_t>> tcols(nth);  // per thread, position-major
-  std::vector<std::vector<size_t>> tstart(nth);
-  std::vector<int32_t> ncol(nbs, 0);
-  par_ranges(nbk, [&](int pa, int pe, int t) {
-    std::vector<int32_t> slot_of(nn, -1);
-    std::vector<int32_t>& cols = tcols[t];
-    std::vector<size_t>& cs = tstart[t];
-    cols.reserve((size_t)(pe - pa) * 8);
-    cs.assign((size_t)(pe - pa) + 1, 0);
-    for (int pb = pa; pb < pe; ++pb) {
-      const int i = rows[nr + pb];
-      cs[pb - pa] = cols.size();
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = ci[k];
-        if (j == i) continue;
-        for (int32_t kk = rp[j]; kk < rp[j + 1]; ++kk) {
-          const int l = ci[kk];
-          if (l == j || l == i || slot_of[l] >= 0) continue;
-          slot_of[l] = (int32_t)(cols.size() - cs[pb - pa]);
-          cols.push_back(l);
-        }
-      }
-      for (size_t q = cs[pb - pa]; q < cols.size(); ++q) slot_of[cols[q]] = -1;
-      ncol[pb] = (int32_t)(cols.size() - cs[pb - pa]);
-    }
-    cs[pe - pa] = cols.size();
-  });
-  int w2 = 0;
-  for (int pb = 0; pb < nbk; ++pb) w2 = std::max(w2, ncol[pb]);
-  const int W2 = std::max(w2, 1);
-  std::vector<int32_t> h_pos(nn);
-  for (int p = 0; p < nn; ++p) h_pos[rows[p]] = p;
-  // columns as black positions (the sweeps keep their iterates in that
-  // order); unused slots hold the row's own position
-  std::vector<int32_t> h_t2ci((size_t)W2 * nbs);
-  par_ranges(nbk, [&](int pa, int pe, int t) {
-    for (int pb = pa; pb < pe; ++pb) {
-      const size_t c0 = tstart[t][pb - pa];
-      for (int q = 0; q < W2; ++q)
-        h_t2ci[(size_t)q * nbs + pb] = q < ncol[pb] ? h_pos[tcols[t][c0 + q]] - nr : pb;
-    }
-  });
-  LRADI_TRY(R->t2ci.alloc(sizeof(int32_t) * h_t2ci.size()));
-  LRADI_TRY(R->rbpos.alloc(sizeof(int32_t) * nn));
-  LRADI_HIP(hipMemcpyAsync(R->t2ci.p, h_t2ci.data(), sizeof(int32_t) * h_t2ci.size(), hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(R->rbpos.p, h_pos.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
-  const size_t ne = (size_t)W * nn;
+  // one tile of black rows per row workgroup of the inner solves
+  const int rpw = choose_rows_per_wg(nn);
+  RbHost h;
+  if (!rb_host_build(nn, rp.data(), ci.data(), v.data(), trp.data(), tci.data(), tv.data(), (nn + rpw - 1) / rpw, h))
+    return set_error("red-black preconditioner: the sparsity graph is not bipartite"), LRADI_EINVAL;
+  auto up = [&](DevBuf& d, const void* src, size_t bytes) -> int {
+    LRADI_TRY(d.alloc(std::max(bytes, (size_t)4)));
+    if (bytes) LRADI_HIP(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
+    return LRADI_OK;
+  };
+  const size_t ne = (size_t)h.rbw * nn;
+  LRADI_TRY(up(R->t2ci, h.t2ci.data(), sizeof(int32_t) * h.t2ci.size()));
+  LRADI_TRY(up(R->t2lc, h.t2lc.data(), sizeof(int32_t) * h.t2lc.size()));
+  LRADI_TRY(up(R->halo_off, h.halo_off.data(), sizeof(int32_t) * h.halo_off.size()));
+  LRADI_TRY(up(R->halo, h.halo.data(), sizeof(int32_t) * h.halo.size()));
+  LRADI_TRY(up(R->rbpos, h.pos.data(), sizeof(int32_t) * nn));
   if (!lump.empty()) {
-    LRADI_TRY(R->ms64.alloc(sizeof(double) * nn));
-    LRADI_HIP(hipMemcpyAsync(R->ms64.p, lump.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
+    LRADI_TRY(up(R->ms64, lump.data(), sizeof(double) * nn));
     if (need32) {
       LRADI_TRY(R->ms32.alloc(sizeof(float) * nn));
       hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, R->ms64.as<double>(),
                          R->ms32.as<float>(), (int64_t)nn);
     }
   }
-  LRADI_TRY(R->rbrows.alloc(sizeof(int32_t) * nn));
-  LRADI_TRY(R->diag64.alloc(sizeof(double) * nn));
-  LRADI_TRY(R->ellci.alloc(sizeof(int32_t) * ne));
-  LRADI_TRY(R->ellval64.alloc(sizeof(double) * ne));
-  LRADI_TRY(R->elltv64.alloc(sizeof(double) * ne));
-  LRADI_HIP(hipMemcpyAsync(R->rbrows.p, rows.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(R->diag64.p, dg.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(R->ellci.p, eci.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(R->ellval64.p, eval.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
-  LRADI_HIP(hipMemcpyAsync(R->elltv64.p, etv.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
+  LRADI_TRY(up(R->rbrows, h.rows.data(), sizeof(int32_t) * nn));
+  LRADI_TRY(up(R->diag64, h.dg.data(), sizeof(double) * nn));
+  LRADI_TRY(up(R->ellci, h.eci.data(), sizeof(int32_t) * ne));
+  LRADI_TRY(up(R->ellval64, h.eval.data(), sizeof(double) * ne));
+  LRADI_TRY(up(R->elltv64, h.etv.data(), sizeof(double) * ne));
   if (need32) {
     LRADI_TRY(R->diag32.alloc(sizeof(float) * nn));
     LRADI_TRY(R->ellval32.alloc(sizeof(float) * ne));
@@ -1022,9 +897,13 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
     LRADI_HIP(hipGetLastError());
   }
   LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
-  R->nred = nr;
-  R->rbw = W;
-  R->t2w = W2;
+  R->nred = h.nred;
+  R->rbw = h.rbw;
+  R->t2w = h.t2w;
+  R->tile = h.tile;
+  R->ntile = h.ntile;
+  R->maxreg = h.maxreg;
+  R->nhalo = (int)h.halo.size();
   rb = R;
   ctx->rb_cache.emplace_front(key, R);
   if (ctx->rb_cache.size() > kRbCacheEntries) ctx->rb_cache.pop_back();
@@ -1189,12 +1068,14 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   LRADI_HIP(hipMemcpyAsync(q.shA.p, P.shiftsA, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   const double fl = floor_for(o);
-  LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw));
+  LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw,
+                      o.precond_pairs != 0));
   LRADI_TRY(q.wa.tune(c, q.A, o.spmm_lanes));
   if (q.sym) {
     q.wb.init_mirror(q.wa);
   } else {
-    LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw));
+    LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw,
+                        o.precond_pairs != 0));
     LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
   }
   LRADI_TRY(q.done.init());
@@ -1402,6 +1283,7 @@ void lradi_default_opts(lradi_opts* o) {
   o->b_is_transposed = 0;
   o->lookahead = 2;
   o->use_graph = 0;
+  o->precond_pairs = 1;
 }
 
 const char* lradi_strerror(int st) {
@@ -1528,7 +1410,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
   if (o.restart < 1 || o.restart > kMaxM || o.max_inner < 1 ||
       (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER) ||
       (o.precond != LRADI_PRECOND_NONE && o.precond != LRADI_PRECOND_RBILU0) || o.precond_sweeps < 0 ||
-      o.precond_sweeps > 64)
+      o.precond_sweeps > 64 || (o.precond_pairs != 0 && o.precond_pairs != 1))
     return set_error("lradi_shifted_solve: bad options"), LRADI_EINVAL;
   const int sw = sweeps_for(o);
   LRADI_HIP(hipSetDevice(c->device));
@@ -1541,7 +1423,8 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     LRADI_TRY(mats[s].upload(A[s], c->stream, o.precision == LRADI_FP32_INNER));
     if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(c, A[s], nullptr, c->stream, o.precision == LRADI_FP32_INNER));
     work[s] = std::make_unique<SysWork>();
-    LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o), sw));
+    LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o), sw,
+                            o.precond_pairs != 0));
     LRADI_TRY(work[s]->tune(c, mats[s], o.spmm_lanes));
     work[s]->arm(Z[s], shift[s], delta[s]);
     ws[s] = work[s].get();

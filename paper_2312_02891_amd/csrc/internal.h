@@ -22,6 +22,14 @@ constexpr int kSpmmCap = 2048;  // nonzeros of one SpMM tile staged in LDS
 // CholQR factors are formed inside the scale kernels when every system's
 // small Gram partials (nwg x r^2 values) are at most this many
 constexpr int kFuseCholMax = 8192;
+// paired Schur sweeps: a tile's region (rows + halo) iterate must fit this
+// many bytes of LDS, and the regions may hold at most kPairMaxRegion times
+// the black rows.  Breadth-first tiles of 2-D five-point grids come to
+// 1.2-1.4 times, of 3-D seven-point grids to 1.9-2.6 times; there the first
+// sweep's halo rows cost more than the launch a pair saves (64^3 and 48^3,
+// r = 8: 35 us per paired launch against 15 us per single one).
+constexpr int kPairLdsMax = 64 * 1024;
+constexpr double kPairMaxRegion = 1.6;
 
 // Device pointers held in descriptor tables are generic (flat) to the
 // compiler; casting them to the global address space lets it issue global
@@ -179,6 +187,16 @@ struct SysDesc {
   const int* t2ci;
   const int* rbpos;
   void* t2val;
+  // paired sweeps: the black positions in tiles of ceil(nb / nwg), tile w
+  // owned by row workgroup w; its halo (the black positions outside it
+  // that its rows' T columns reach) at halo[halo_off[w] .. halo_off[w + 1]),
+  // and t2lc, T's columns (slot-major like t2ci) as indices into the tile's
+  // region, its own rows first, then its halo
+  const int* halo_off;
+  const int* halo;
+  const int* t2lc;
+  int nhalo;            // total halo entries (algorithmic bytes)
+  int pair_lds;         // bytes of the largest region's iterate; 0: no pairs
 };
 
 // Mutable device-side control block of one inner solve.
@@ -250,7 +268,11 @@ struct RbData {
   // pencils A + s M: the preconditioner takes M's row sums (lumped mass)
   // as the per-row weight of the shift; empty for M = I
   DevBuf ms64, ms32;
+  // tiles of the black positions for paired sweeps (halo lists and T's
+  // columns as region-local indices; see RbHost)
+  DevBuf halo_off, halo, t2lc;
   int nred = 0, rbw = 0, t2w = 0;
+  int tile = 0, ntile = 0, maxreg = 0, nhalo = 0;
 };
 
 struct DevCSR {
@@ -295,6 +317,10 @@ struct Batch {
   int rfix;            // common r of all systems, or 0 when they differ
   int precond;         // some system carries the red-black preconditioner
   int sweeps;          // its Jacobi sweeps (shared by the batch)
+  int pairs;           // 1: two sweeps per launch (every preconditioned
+                       // system has pair_lds > 0)
+  int pair_lds;        // dynamic LDS bytes of a paired launch
+  int precond_launches;  // launches of one preconditioner application
   int fuse_chol;       // 1: every scale workgroup reduces the small Gram
                        // partials and factors them itself (common r <= 4
                        // and small nwg r^2)

@@ -424,15 +424,15 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
   }
 }
 
-// one Jacobi sweep on T z = y for black position pb: dst row drow =
-// (y_pb - sum_u T(pb, l_u) src_{l_u}) / diag(T)_pb, with y, 1/diag(T) and
-// src in black-position order
-template <typename T, int R>
-__device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
-                                    T* __restrict__ dst, size_t drow) {
+// acc = y_pb - sum_u T(pb, col_u) src(col_u) over T's off-diagonal slots of
+// black position pb, with the columns read from cols (slot-major, nb per
+// slot) and unused slots (col == self) skipped; the one arithmetic of every
+// Jacobi sweep, whichever table and source the columns refer to
+template <typename T, int R, typename Src>
+__device__ inline void rb_sweep_acc(const SysDesc& D, int pb, int nb, const int* __restrict__ cols, int self,
+                                    const Src& src, T (&acc)[R]) {
   const T* tv = static_cast<const T*>(D.t2val);
   const T* Y = static_cast<const T*>(D.Yb);
-  T acc[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)pb * R + q];
   constexpr int kRbUnroll = RbUnroll<R>::v;
@@ -443,20 +443,37 @@ __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* _
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
       const size_t e = (size_t)min(u0 + u, D.t2w - 1) * nb + pb;
-      col[u] = D.t2ci[e];
+      col[u] = cols[e];
       a[u] = tv[e];
-      ok[u] = (u0 + u < D.t2w) && col[u] != pb;
+      ok[u] = (u0 + u < D.t2w) && col[u] != self;
     }
     T xv[kRbUnroll][R];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u)
 #pragma unroll
-      for (int q = 0; q < R; ++q) xv[u][q] = src[(size_t)col[u] * R + q];
+      for (int q = 0; q < R; ++q) xv[u][q] = src(col[u], q);
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u)
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
   }
+}
+
+// a block of R values per black position, row-major
+template <typename T, int R>
+struct RbRows {
+  const T* __restrict__ p;
+  __device__ T operator()(int c, int q) const { return p[(size_t)c * R + q]; }
+};
+
+// one Jacobi sweep on T z = y for black position pb: dst row drow =
+// (y_pb - sum_u T(pb, l_u) src_{l_u}) / diag(T)_pb, with y, 1/diag(T) and
+// src in black-position order
+template <typename T, int R>
+__device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
+                                    T* __restrict__ dst, size_t drow) {
+  T acc[R];
+  rb_sweep_acc<T, R>(D, pb, nb, D.t2ci, pb, RbRows<T, R>{src}, acc);
   const T it = static_cast<const T*>(D.It)[pb];
 #pragma unroll
   for (int q = 0; q < R; ++q) dst[drow * R + q] = acc[q] * it;
@@ -469,12 +486,17 @@ __device__ inline T* rb_compact(const SysDesc& D, int nb, int t) {
   return static_cast<T*>(D.Eb) + (size_t)(t % 2) * nb * D.r;
 }
 
+// compact block holding the input of the sweep launch that starts with
+// sweep `stage`: launches alternate between the two blocks, one sweep per
+// launch, or two (pair) with a single last one for an odd count
+__device__ inline int rb_launch_index(int stage, int pair) { return pair ? (stage - 1) / 2 : stage - 1; }
+
 // stage 0: fwd (black rows; builds T's values at the first Arnoldi step of
 // an inner solve); 1..sweeps: Jacobi sweep t (black rows); sweeps + 1: back
 // (red rows)
 template <typename T, int R, int KIND>
 __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj,
-                               int stage, bool build) {
+                               int stage, int pair, bool build) {
   const int nb = D.n - D.nred;
   constexpr bool black = KIND != 2;
   const int off = black ? D.nred : 0;
@@ -505,11 +527,12 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
         if (build) rb_build_t<T>(D, x, p, pp, nb, i);
       }
     } else if constexpr (KIND == 1) {
-      const T* src = rb_compact<T>(D, nb, stage - 1);
+      const int ln = rb_launch_index(stage, pair);
+      const T* src = rb_compact<T>(D, nb, ln);
       if (stage == D.sweeps)
         rb_sweep_row<T, R>(D, pp, nb, src, Pj, (size_t)i);
       else
-        rb_sweep_row<T, R>(D, pp, nb, src, rb_compact<T>(D, nb, stage), (size_t)pp);
+        rb_sweep_row<T, R>(D, pp, nb, src, rb_compact<T>(D, nb, ln + 1), (size_t)pp);
     } else {  // back: z_r = (v_r - E z) / (d_r + s)
       T g[R];
 #pragma unroll
@@ -522,28 +545,73 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
   }
 }
 
+// sweeps `stage` and `stage` + 1 for the black tile of workgroup c.w: the
+// first over the tile's region (its rows and its halo, reading the launch's
+// input block) into LDS, the second over its rows from LDS (the columns as
+// region indices), to the other compact block or, when it is the last
+// sweep, to P_j's black rows.  Each row's arithmetic is that of a single
+// sweep, so the result equals two single-sweep launches bit for bit.
+template <typename T, int R>
+__device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int stage, T* lds) {
+  const int nb = D.n - D.nred;
+  const int bc = (nb + D.nwg - 1) / D.nwg;
+  const int p0 = c.w * bc, nin = min(nb, p0 + bc) - p0;
+  if (nin <= 0) return;  // (uniform over the workgroup)
+  const int h0 = D.halo_off[c.w], nreg = nin + (D.halo_off[c.w + 1] - h0);
+  const int ln = rb_launch_index(stage, 1);
+  const T* src = rb_compact<T>(D, nb, ln);
+  const T* It = static_cast<const T*>(D.It);
+  for (int k = threadIdx.x; k < nreg; k += kTPB) {
+    const int pb = k < nin ? p0 + k : D.halo[h0 + (k - nin)];
+    T acc[R];
+    rb_sweep_acc<T, R>(D, pb, nb, D.t2ci, pb, RbRows<T, R>{src}, acc);
+    const T it = It[pb];
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[k * R + q] = acc[q] * it;
+  }
+  __syncthreads();
+  const bool last = stage + 1 == D.sweeps;
+  T* dst = rb_compact<T>(D, nb, ln + 1);
+  for (int k = threadIdx.x; k < nin; k += kTPB) {
+    const int pb = p0 + k;
+    T acc[R];
+    rb_sweep_acc<T, R>(D, pb, nb, D.t2lc, k, RbRows<T, R>{lds}, acc);
+    const T it = It[pb];
+    const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
+    T* out = last ? Pj : dst;
+#pragma unroll
+    for (int q = 0; q < R; ++q) out[row * R + q] = acc[q] * it;
+  }
+}
+
 // algorithmic bytes of one stage for one system (each array element read or
-// written once; the once-per-solve build of T's values not counted)
-template <typename T>
-__device__ inline unsigned long long rb_stage_bytes(const SysDesc& D, int stage) {
+// written once; the once-per-solve build of T's values not counted); a
+// pair of sweeps reads T once and the intermediate iterate never leaves
+// LDS, so it counts one sweep plus its tables of region indices
+template <typename T, int KIND>
+__device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
   const unsigned long long nr = D.nred, nb = D.n - D.nred, n = D.n, R = D.r, t = sizeof(T);
-  if (stage == 0)
+  const unsigned long long sweep = nb * 4 + D.t2w * nb * (4 + t) + 3 * nb * R * t + nb * t;
+  if (KIND == 0)
     return nb * 4 + D.rbw * nb * (4 + 2 * t) + n * t + n * R * t + nb * R * t +
            (D.sweeps > 0 ? nb * R * t + nb * t : 0);
-  if (stage <= D.sweeps) return nb * 4 + D.t2w * nb * (4 + t) + 3 * nb * R * t + nb * t;
+  if (KIND == 1) return sweep;
+  if (KIND == 3) return sweep + D.t2w * nb * 4 + ((unsigned long long)D.nhalo + D.nwg + 1) * 4;
   return nr * 4 + D.rbw * nr * (4 + t) + nr * t + 2 * nr * R * t + nb * R * t;
 }
 
-// KIND 0: forward (stage 0), 1: sweep (stage 1..sweeps), 2: back; one
+// KIND 0: forward (stage 0), 1: sweep `stage`, 2: back, 3: sweeps `stage`
+// and `stage` + 1 (pair = 1: the launches of the sweeps are paired); one
 // instance per kind, so each allocates only the registers it needs
 template <typename T, int RF, int KIND>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
-                                                  const int2* __restrict__ rowmap, int stage,
+                                                  const int2* __restrict__ rowmap, int stage, int pair,
                                                   unsigned long long* __restrict__ prof) {
+  extern __shared__ double rb_lds[];  // KIND 3: a tile region's iterate
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI || !D.rbrows) return;
-  if (prof && c.w == 0 && threadIdx.x == 0) atomicAdd(prof + LRADI_PROF_PRECOND, rb_stage_bytes<T>(D, stage));
+  if (prof && c.w == 0 && threadIdx.x == 0) atomicAdd(prof + LRADI_PROF_PRECOND, rb_stage_bytes<T, KIND>(D));
   const int j = ctl[c.s].j;
   const RbCtx<T> x = rb_ctx<T>(D, ctl[c.s].shift);
   const size_t blk = (size_t)D.n * D.r;
@@ -552,7 +620,11 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   // the shift is fixed for an inner solve: T's values are built at its
   // first Arnoldi step (first cycle, j = 0) and kept over restarts
   const bool build = ctl[c.s].cycles == 1 && j == 0;
-  LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, build));
+  if constexpr (KIND == 3) {
+    LRADI_RSEL(RF, D.r, rb_pair<T, RR>(D, c, Pj, stage, reinterpret_cast<T*>(rb_lds)));
+  } else {
+    LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, pair, build));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1401,10 +1473,17 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const double fl64 = 1e-24, fl32 = 1e-10;
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[6], st));
   if (b.precond) {
-    hipLaunchKernelGGL((k_precond<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.prof_bytes);
-    for (int stage = 1; stage <= b.sweeps; ++stage)
-      hipLaunchKernelGGL((k_precond<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.prof_bytes);
-    hipLaunchKernelGGL((k_precond<T, RF, 2>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.sweeps + 1, b.prof_bytes);
+    hipLaunchKernelGGL((k_precond<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
+    int stage = 1;
+    if (b.pairs)
+      for (; stage + 1 <= b.sweeps; stage += 2)
+        hipLaunchKernelGGL((k_precond<T, RF, 3>), rg, tb, b.pair_lds, st, b.d, b.ctl, b.rowmap, stage, 1,
+                           b.prof_bytes);
+    for (; stage <= b.sweeps; ++stage)
+      hipLaunchKernelGGL((k_precond<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.pairs,
+                         b.prof_bytes);
+    hipLaunchKernelGGL((k_precond<T, RF, 2>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.sweeps + 1, b.pairs,
+                       b.prof_bytes);
   }
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[7], st));
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));

@@ -163,6 +163,10 @@ def test_preconditioner_argument_errors(L, ctx):
         ctx.shifted_solve([HA], [-10.0], [to_dev(np.ones((HA.n, 1)))], [1e-8],
                           L.default_opts(precond="rbilu0", precond_sweeps=65))
     assert e.value.status == L.EINVAL
+    with pytest.raises(L.LradiError) as e:
+        ctx.shifted_solve([HA], [-10.0], [to_dev(np.ones((HA.n, 1)))], [1e-8],
+                          L.default_opts(precond="rbilu0", precond_pairs=2))
+    assert e.value.status == L.EINVAL
 
 
 def _gen_setup(L, P):
@@ -206,6 +210,50 @@ def test_generalized_with_lumped_mass_preconditioner_matches_oracle(L, ctx, name
         "plain", hn[:, 6].sum() + hn[:, 7].sum())
     assert abs(res.k - full.k) <= 1 and xerr <= 1e-6 and true <= P.tol
     assert hp[:, 6].sum() + hp[:, 7].sum() < hn[:, 6].sum() + hn[:, 7].sum()
+
+
+@pytest.mark.parametrize("name,precision,sweeps,gen", [("SMALL_2D", "fp64", 24, False), ("SMALL_2D", "fp32", 5, False),
+                                                       ("C1", "fp64", 2, False), ("C1", "fp32", 24, False),
+                                                       ("SMALL_3D", "fp64", 3, False), ("GEN_SMALL", "fp64", 7, True)])
+def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, sweeps, gen):
+    """Two Jacobi sweeps per launch (the first over each tile's region into
+    workgroup memory) give the same factors, history and inner step counts
+    as one sweep per launch, bit for bit; on the 2-D grids the pairs are
+    taken (fewer preconditioner launches, counted by the profiler), on the
+    3-D ones, whose regions are about twice their tiles, they are not."""
+    say("paired sweeps", name, precision, sweeps)
+    P = getattr(WL, name)
+    if gen:
+        HA, HB, HM, HC, *_rest = _gen_setup(L, P)
+        f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+        pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts, massA=True, massB=True)
+        kw = dict(M=HM, C=HC)
+    else:
+        HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+        HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
+        f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+        pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+        kw = {}
+    fd, gd = to_dev(f), to_dev(g)
+    runs = []
+    for pairs in (1, 0):
+        o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps,
+                           precond_pairs=pairs, profile=1)
+        ctx.profile_reset()
+        res = ctx.solve(HA, HB, fd, gd, pA, pB, o, **kw)
+        assert res.status == L.OK
+        runs.append((res, ctx.profile_read(L.PROF_PRECOND)[1]))
+    (a, la), (b, lb) = runs
+    say("  k", a.k, "launches paired", la, "single", lb)
+    assert a.k == b.k
+    assert np.array_equal(a.history(), b.history())
+    for x, y in zip(a.factors(), b.factors()):
+        assert np.array_equal(x, y)
+    # 2-D tiles pair (regions about 1.3 times the tile); 3-D ones do not
+    if P.A.dim == 2:
+        assert la < lb
+    else:
+        assert la == lb
 
 
 def test_identity_mass_preconditioned_equals_plain(L, ctx):
