@@ -31,9 +31,12 @@ if ROOT not in sys.path:
 METRIC = "time-to-residual 1e-8 + SpMM HBM GB/s; inexact-FP32 vs exact-FP64; p99 lat"
 HBM_PEAK_GBS = 8000.0
 # Jacobi sweeps on the Schur complement in the preconditioned inner solves
-# (the fastest count on config 2: 16 -> 24 -> 32 sweeps gave 0.158, 0.152,
-# 0.157 s per FP64 solve)
+# of config 2, run two per launch (FP64 solve: 16, 20, 24, 28, 32, 40
+# sweeps gave 0.103, 0.092, 0.090, 0.089, 0.089, 0.089 s)
 PRECOND_SWEEPS = 32
+# the batch and serving workloads' small problems (grid sides 32..128) gain less
+# per sweep: 24 (batch of 256: 1.01 s at 24 against 1.14 s at 32)
+BATCH_PRECOND_SWEEPS = 24
 # the 3-D configuration's Schur rows couple 18 neighbours instead of 8, so a
 # sweep costs more there and fewer pay (2, 4, 8, 16 sweeps: 0.313, 0.296,
 # 0.286, 0.310 s per FP32 solve before the setup cache)
@@ -58,7 +61,7 @@ def parse():
                          "256 independent problems; serve: Poisson request stream")
     ap.add_argument("--count", type=int, default=0, help="problems (batch) or requests (serve)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
-    ap.add_argument("--precond-sweeps", type=int, default=PRECOND_SWEEPS,
+    ap.add_argument("--precond-sweeps", type=int, default=BATCH_PRECOND_SWEEPS,
                     help="batch / serve: Schur sweeps of the red-black ILU(0) preconditioner "
                          "(-1: unpreconditioned)")
     return ap.parse_args()
