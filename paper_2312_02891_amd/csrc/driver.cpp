@@ -388,6 +388,7 @@ struct SysWork {
       d.halo_off = B.halo_off.as<int>();
       d.halo = B.halo.as<int>();
       d.t2lc = B.t2lc.as<int>();
+      d.halo_ci = B.halo_ci.as<int>();
       d.nhalo = B.nhalo;
       // pairs where the tiles are the row workgroups' black chunks and
       // their regions are small enough
@@ -478,7 +479,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hd.resize(nsys);
   t.hc.resize(nsys);
   t.hmap.clear();
-  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0;
+  int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0,
+      pair_fast = 1;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -496,6 +498,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       sweeps = ws[s]->d.sweeps;
       if (ws[s]->d.pair_lds == 0) pairs = 0;
       pair_lds = std::max(pair_lds, ws[s]->d.pair_lds);
+      const int nb = ws[s]->d.n - ws[s]->d.nred, tile = (nb + ws[s]->d.nwg - 1) / ws[s]->d.nwg;
+      if (tile > kTPB || ws[s]->d.t2w > kPairRegSlots) pair_fast = 0;
     }
   }
   // shifted-product tiles, grouped by lanes per row
@@ -541,6 +545,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.sweeps = sweeps;
   t.b.pairs = precond && pairs && sweeps >= 2;
   t.b.pair_lds = t.b.pairs ? pair_lds : 0;
+  // (the register-held columns with wider or mixed blocks would spill)
+  t.b.pair_fast = t.b.pairs && pair_fast && rfix >= 1 && rfix <= 4;
   t.b.precond_launches = precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) : 0;
   return LRADI_OK;
 }
@@ -869,6 +875,7 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
   LRADI_TRY(up(R->t2lc, h.t2lc.data(), sizeof(int32_t) * h.t2lc.size()));
   LRADI_TRY(up(R->halo_off, h.halo_off.data(), sizeof(int32_t) * h.halo_off.size()));
   LRADI_TRY(up(R->halo, h.halo.data(), sizeof(int32_t) * h.halo.size()));
+  LRADI_TRY(up(R->halo_ci, h.halo_ci.data(), sizeof(int32_t) * h.halo_ci.size()));
   LRADI_TRY(up(R->rbpos, h.pos.data(), sizeof(int32_t) * nn));
   if (!lump.empty()) {
     LRADI_TRY(up(R->ms64, lump.data(), sizeof(double) * nn));

@@ -29,6 +29,7 @@ constexpr int kFuseCholMax = 8192;
 // sweep's halo rows cost more than the launch a pair saves (64^3 and 48^3,
 // r = 8: 35 us per paired launch against 15 us per single one).
 constexpr int kPairLdsMax = 64 * 1024;
+constexpr int kPairRegSlots = 8;
 constexpr double kPairMaxRegion = 1.6;
 
 // Device pointers held in descriptor tables are generic (flat) to the
@@ -195,7 +196,8 @@ struct SysDesc {
   const int* halo_off;
   const int* halo;
   const int* t2lc;
-  int nhalo;            // total halo entries (algorithmic bytes)
+  const int* halo_ci;   // the halo rows' T columns, slot-major over halo entries
+  int nhalo;            // total halo entries
   int pair_lds;         // bytes of the largest region's iterate; 0: no pairs
 };
 
@@ -270,7 +272,7 @@ struct RbData {
   DevBuf ms64, ms32;
   // tiles of the black positions for paired sweeps (halo lists and T's
   // columns as region-local indices; see RbHost)
-  DevBuf halo_off, halo, t2lc;
+  DevBuf halo_off, halo, t2lc, halo_ci;
   int nred = 0, rbw = 0, t2w = 0;
   int tile = 0, ntile = 0, maxreg = 0, nhalo = 0;
 };
@@ -320,6 +322,10 @@ struct Batch {
   int pairs;           // 1: two sweeps per launch (every preconditioned
                        // system has pair_lds > 0)
   int pair_lds;        // dynamic LDS bytes of a paired launch
+  int pair_fast;       // 1: every tile fits one row per thread, T has at
+                       // most kPairRegSlots slots and r is common and <= 4
+                       // (the paired kernel keeps the second sweep's region
+                       // columns in registers)
   int precond_launches;  // launches of one preconditioner application
   int fuse_chol;       // 1: every scale workgroup reduces the small Gram
                        // partials and factors them itself (common r <= 4

@@ -425,12 +425,12 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
 }
 
 // acc = y_pb - sum_u T(pb, col_u) src(col_u) over T's off-diagonal slots of
-// black position pb, with the columns read from cols (slot-major, nb per
-// slot) and unused slots (col == self) skipped; the one arithmetic of every
-// Jacobi sweep, whichever table and source the columns refer to
+// black position pb, with slot u's column at cols[u * cstride + crow] and
+// unused slots (col == self) skipped; the one arithmetic of every Jacobi
+// sweep, whichever table and source the columns refer to
 template <typename T, int R, typename Src>
-__device__ inline void rb_sweep_acc(const SysDesc& D, int pb, int nb, const int* __restrict__ cols, int self,
-                                    const Src& src, T (&acc)[R]) {
+__device__ inline void rb_sweep_acc(const SysDesc& D, int pb, int nb, const int* __restrict__ cols, int cstride,
+                                    int crow, int self, const Src& src, T (&acc)[R]) {
   const T* tv = static_cast<const T*>(D.t2val);
   const T* Y = static_cast<const T*>(D.Yb);
 #pragma unroll
@@ -442,9 +442,9 @@ __device__ inline void rb_sweep_acc(const SysDesc& D, int pb, int nb, const int*
     bool ok[kRbUnroll];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const size_t e = (size_t)min(u0 + u, D.t2w - 1) * nb + pb;
-      col[u] = cols[e];
-      a[u] = tv[e];
+      const int slot = min(u0 + u, D.t2w - 1);
+      col[u] = cols[(size_t)slot * cstride + crow];
+      a[u] = tv[(size_t)slot * nb + pb];
       ok[u] = (u0 + u < D.t2w) && col[u] != self;
     }
     T xv[kRbUnroll][R];
@@ -473,7 +473,7 @@ template <typename T, int R>
 __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
                                     T* __restrict__ dst, size_t drow) {
   T acc[R];
-  rb_sweep_acc<T, R>(D, pb, nb, D.t2ci, pb, RbRows<T, R>{src}, acc);
+  rb_sweep_acc<T, R>(D, pb, nb, D.t2ci, nb, pb, pb, RbRows<T, R>{src}, acc);
   const T it = static_cast<const T*>(D.It)[pb];
 #pragma unroll
   for (int q = 0; q < R; ++q) dst[drow * R + q] = acc[q] * it;
@@ -550,8 +550,12 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
 // input block) into LDS, the second over its rows from LDS (the columns as
 // region indices), to the other compact block or, when it is the last
 // sweep, to P_j's black rows.  Each row's arithmetic is that of a single
-// sweep, so the result equals two single-sweep launches bit for bit.
-template <typename T, int R>
+// sweep (the slots summed in the same order), so the result equals two
+// single-sweep launches bit for bit.  FAST (every tile at most kTPB rows,
+// T at most kPairRegSlots slots): each thread owns one tile row and holds
+// its region columns in registers from the start, so the second sweep
+// reads only LDS and cached operands.
+template <typename T, int R, bool FAST>
 __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int stage, T* lds) {
   const int nb = D.n - D.nred;
   const int bc = (nb + D.nwg - 1) / D.nwg;
@@ -561,10 +565,23 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
   const int ln = rb_launch_index(stage, 1);
   const T* src = rb_compact<T>(D, nb, ln);
   const T* It = static_cast<const T*>(D.It);
+  constexpr int kS = kPairRegSlots;
+  int lc[kS];
+  if constexpr (FAST) {
+    const int k = min((int)threadIdx.x, nin - 1);
+#pragma unroll
+    for (int u = 0; u < kS; ++u) lc[u] = D.t2lc[(size_t)min(u, D.t2w - 1) * nb + p0 + k];
+  }
+  const int nhs = max(D.nhalo, 1);
   for (int k = threadIdx.x; k < nreg; k += kTPB) {
-    const int pb = k < nin ? p0 + k : D.halo[h0 + (k - nin)];
+    // a halo row reads its columns from the halo's own table, so its
+    // gathers do not wait for its position
+    const bool in = k < nin;
+    const int g = max(h0 + (k - nin), 0);  // (used by halo rows only)
+    const int pb = in ? p0 + k : D.halo[g];
     T acc[R];
-    rb_sweep_acc<T, R>(D, pb, nb, D.t2ci, pb, RbRows<T, R>{src}, acc);
+    rb_sweep_acc<T, R>(D, pb, nb, in ? D.t2ci : D.halo_ci, in ? nb : nhs, in ? pb : g, pb,
+                       RbRows<T, R>{src}, acc);
     const T it = It[pb];
 #pragma unroll
     for (int q = 0; q < R; ++q) lds[k * R + q] = acc[q] * it;
@@ -572,15 +589,43 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
   __syncthreads();
   const bool last = stage + 1 == D.sweeps;
   T* dst = rb_compact<T>(D, nb, ln + 1);
-  for (int k = threadIdx.x; k < nin; k += kTPB) {
+  T* out = last ? Pj : dst;
+  if constexpr (FAST) {
+    const int k = threadIdx.x;
+    if (k >= nin) return;
     const int pb = p0 + k;
+    const T* tv = static_cast<const T*>(D.t2val);
+    const T* Y = static_cast<const T*>(D.Yb);
     T acc[R];
-    rb_sweep_acc<T, R>(D, pb, nb, D.t2lc, k, RbRows<T, R>{lds}, acc);
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)pb * R + q];
+    T a[kS], xv[kS][R];
+#pragma unroll
+    for (int u = 0; u < kS; ++u) {
+      a[u] = tv[(size_t)min(u, D.t2w - 1) * nb + pb];
+#pragma unroll
+      for (int q = 0; q < R; ++q) xv[u][q] = lds[lc[u] * R + q];
+    }
+#pragma unroll
+    for (int u = 0; u < kS; ++u) {
+      const bool ok = u < D.t2w && lc[u] != k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = ok ? acc[q] - a[u] * xv[u][q] : acc[q];
+    }
     const T it = It[pb];
     const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
-    T* out = last ? Pj : dst;
 #pragma unroll
     for (int q = 0; q < R; ++q) out[row * R + q] = acc[q] * it;
+  } else {
+    for (int k = threadIdx.x; k < nin; k += kTPB) {
+      const int pb = p0 + k;
+      T acc[R];
+      rb_sweep_acc<T, R>(D, pb, nb, D.t2lc, nb, pb, k, RbRows<T, R>{lds}, acc);
+      const T it = It[pb];
+      const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
+#pragma unroll
+      for (int q = 0; q < R; ++q) out[row * R + q] = acc[q] * it;
+    }
   }
 }
 
@@ -596,18 +641,19 @@ __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
     return nb * 4 + D.rbw * nb * (4 + 2 * t) + n * t + n * R * t + nb * R * t +
            (D.sweeps > 0 ? nb * R * t + nb * t : 0);
   if (KIND == 1) return sweep;
-  if (KIND == 3) return sweep + D.t2w * nb * 4 + ((unsigned long long)D.nhalo + D.nwg + 1) * 4;
+  if (KIND >= 3) return sweep + D.t2w * nb * 4 + ((unsigned long long)D.nhalo + D.nwg + 1) * 4;
   return nr * 4 + D.rbw * nr * (4 + t) + nr * t + 2 * nr * R * t + nb * R * t;
 }
 
 // KIND 0: forward (stage 0), 1: sweep `stage`, 2: back, 3: sweeps `stage`
-// and `stage` + 1 (pair = 1: the launches of the sweeps are paired); one
-// instance per kind, so each allocates only the registers it needs
+// and `stage` + 1, 4: the same with the region columns in registers (pair =
+// 1: the launches of the sweeps are paired); one instance per kind, so
+// each allocates only the registers it needs
 template <typename T, int RF, int KIND>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap, int stage, int pair,
                                                   unsigned long long* __restrict__ prof) {
-  extern __shared__ double rb_lds[];  // KIND 3: a tile region's iterate
+  extern __shared__ double rb_lds[];  // KIND 3, 4: a tile region's iterate
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI || !D.rbrows) return;
@@ -620,8 +666,8 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   // the shift is fixed for an inner solve: T's values are built at its
   // first Arnoldi step (first cycle, j = 0) and kept over restarts
   const bool build = ctl[c.s].cycles == 1 && j == 0;
-  if constexpr (KIND == 3) {
-    LRADI_RSEL(RF, D.r, rb_pair<T, RR>(D, c, Pj, stage, reinterpret_cast<T*>(rb_lds)));
+  if constexpr (KIND >= 3) {
+    LRADI_RSEL(RF, D.r, (rb_pair<T, RR, KIND == 4>(D, c, Pj, stage, reinterpret_cast<T*>(rb_lds))));
   } else {
     LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, pair, build));
   }
@@ -1476,9 +1522,14 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
     hipLaunchKernelGGL((k_precond<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
     int stage = 1;
     if (b.pairs)
-      for (; stage + 1 <= b.sweeps; stage += 2)
-        hipLaunchKernelGGL((k_precond<T, RF, 3>), rg, tb, b.pair_lds, st, b.d, b.ctl, b.rowmap, stage, 1,
-                           b.prof_bytes);
+      for (; stage + 1 <= b.sweeps; stage += 2) {
+        if (b.pair_fast)
+          hipLaunchKernelGGL((k_precond<T, RF, 4>), rg, tb, b.pair_lds, st, b.d, b.ctl, b.rowmap, stage, 1,
+                             b.prof_bytes);
+        else
+          hipLaunchKernelGGL((k_precond<T, RF, 3>), rg, tb, b.pair_lds, st, b.d, b.ctl, b.rowmap, stage, 1,
+                             b.prof_bytes);
+      }
     for (; stage <= b.sweeps; ++stage)
       hipLaunchKernelGGL((k_precond<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.pairs,
                          b.prof_bytes);

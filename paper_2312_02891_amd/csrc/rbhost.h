@@ -57,6 +57,10 @@ struct RbHost {
   int tile = 0, ntile = 0;
   int maxreg = 0;  // largest region (rows + halo) of a tile
   std::vector<int32_t> halo_off, halo, t2lc;
+  // the halo rows' T columns (as black positions), slot q of halo entry g
+  // at q * max(nhalo, 1) + g: a halo row's gathers need not wait for its
+  // position
+  std::vector<int32_t> halo_ci;
 };
 
 // Fills h for the n x n CSR matrix (rp, ci, v) with transpose (trp, tci, tv)
@@ -294,6 +298,10 @@ inline bool rb_host_build(int n, const int32_t* rp, const int32_t* ci, const dou
   h.halo.clear();
   h.halo.reserve((size_t)h.halo_off[ntile]);
   for (auto& x : thalo) h.halo.insert(h.halo.end(), x.begin(), x.end());
+  const size_t nh = h.halo.size(), nhs = std::max(nh, (size_t)1);
+  h.halo_ci.assign((size_t)W2 * nhs, 0);
+  for (int q = 0; q < W2; ++q)
+    for (size_t g = 0; g < nh; ++g) h.halo_ci[(size_t)q * nhs + g] = h.t2ci[(size_t)q * nbs + h.halo[g]];
 
   h.nred = nr;
   h.rbw = W;

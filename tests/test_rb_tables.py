@@ -48,7 +48,7 @@ def build(RB, A, tiles):
     if not ok:
         return None
     out = dict(zip(["nred", "rbw", "t2w", "tile", "ntile", "maxreg", "nhalo"], info.tolist()))
-    for name in ["rows", "pos", "eci", "t2ci", "t2lc", "halo_off", "halo"]:
+    for name in ["rows", "pos", "eci", "t2ci", "t2lc", "halo_off", "halo", "halo_ci"]:
         k = RB.st_rb_ints(name.encode(), None)
         a = np.zeros(k, dtype=np.int32)
         RB.st_rb_ints(name.encode(), P(a.ctypes.data))
@@ -144,6 +144,10 @@ def test_tables_against_definitions(RB, dim, N, omega, tiles):
         assert np.array_equal(region[lc], cols)
         maxreg = max(maxreg, nin + len(hl))
     assert h["maxreg"] == maxreg
+    # the halo rows' columns, copied per halo entry
+    nh = len(halo)
+    hci = h["halo_ci"].reshape(W2, max(nh, 1))[:, :nh]
+    assert np.array_equal(hci, t2ci[:, halo])
 
 
 def test_tiles_of_a_grid_are_compact(RB):
