@@ -10,6 +10,7 @@
 #include "adi.h"
 #include "controller.h"
 #include "small.h"
+#include "wavesmall.h"
 
 namespace lradi {
 namespace {
@@ -367,13 +368,16 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
   }
   // the five small eigenvalue problems run concurrently: the four Grams on
-  // lanes 0-3 of the first wavefront (one code path, in lockstep), the
-  // product on the second wavefront
-  if (threadIdx.x < 4) {
-    const double* G = threadIdx.x == 0 ? GW : threadIdx.x == 1 ? GT : threadIdx.x == 2 ? GZ : GY;
-    nrm[threadIdx.x] = sqrt(fmax(lambda_max_sym(G, R), 0.0));
-  } else if (threadIdx.x == 64) {
-    nrm[4] = sqrt(fmax(lambda_max_prod(GW, GT, R), 0.0));
+  // four 16-lane groups of the first wavefront, the product on the whole
+  // second wavefront (each with its bisection spread over its lanes)
+  if (threadIdx.x < 64) {
+    const int g = threadIdx.x / 16, l = threadIdx.x % 16;
+    const double* G = g == 0 ? GW : g == 1 ? GT : g == 2 ? GZ : GY;
+    const double v = sqrt(fmax(lambda_max_sym_lanes<16>(G, R, l, g * 16), 0.0));
+    if (l == 0) nrm[g] = v;
+  } else if (threadIdx.x < 128) {
+    const double v = sqrt(fmax(lambda_max_prod_lanes<64>(GW, GT, R, threadIdx.x - 64, 0), 0.0));
+    if (threadIdx.x == 64) nrm[4] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

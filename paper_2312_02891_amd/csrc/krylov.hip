@@ -25,6 +25,7 @@
 
 #include "internal.h"
 #include "small.h"
+#include "wavesmall.h"
 
 namespace lradi {
 namespace {
@@ -1458,17 +1459,20 @@ __global__ __launch_bounds__(kTPB) void k_decide(const SysDesc* __restrict__ d, 
   if (C.phase != PH_CYCLE_END) return;
   const int R = D.r;
   reduce_partS(D, R * R, red_lds, G);
+  bool bad = false;
+  for (int e = 0; e < R * R; ++e)
+    if (!(G[e] == G[e]) || G[e] - G[e] != 0.0) bad = true;
+  // ||R||_2^2 on the first wavefront's 64 lanes (multisection)
+  double lm = 0.0;
+  if (!bad && threadIdx.x < 64) lm = lambda_max_sym_lanes<64>(G, R, threadIdx.x, 0);
   if (threadIdx.x == 0) {
-    bool bad = false;
-    for (int e = 0; e < R * R; ++e)
-      if (!(G[e] == G[e]) || G[e] - G[e] != 0.0) bad = true;
     if (bad) {
       C.status = IS_NAN;
       C.phase = PH_FINISHED;
       C.rnorm = G[0];
       return;
     }
-    const double rn = sqrt(fmax(lambda_max_sym(G, R), 0.0));
+    const double rn = sqrt(fmax(lm, 0.0));
     C.rnorm = rn;
     C.first = 0;
     if (rn <= C.delta) {

@@ -130,17 +130,41 @@ LRADI_HD inline void jacobi_eig_t(double* a, double* q) {
 // so that no square overflows), then bisection on the Sturm count (the
 // number of negative pivots of T - x I equals the number of eigenvalues
 // below x) between max_i t_ii and the Gershgorin bound, to the last bit.
+// The steps are separate so that the bisection can also be spread over
+// the lanes of a wavefront (multisection, below).
 template <int N>
-LRADI_HD inline double lambda_max_sym_t(const double* G) {
-  if (N == 1) return G[0];
+struct LmaxTri {
+  double d[N], off[N];  // diagonal and off-diagonal of the scaled tridiagonal
+  double lo, hi;        // lambda_max in [lo, hi]
+  double pivmin;        // smallest admitted pivot magnitude
+  int ex;               // the matrix was scaled by 2^-ex
+  bool done;            // value is final (N = 1, zero matrix, NaN)
+  double value;
+};
+
+template <int N>
+LRADI_HD inline void lmax_prepare(const double* G, LmaxTri<N>& t) {
+  t.done = false;
+  t.ex = 0;
+  if (N == 1) {
+    t.done = true;
+    t.value = G[0];
+    return;
+  }
   double a[N * N];
   double amax = 0.0;
   LRADI_UNROLL for (int e = 0; e < N * N; ++e) amax = fmax(amax, fabs(G[e]));
-  if (!(amax > 0.0)) return amax == 0.0 ? 0.0 : amax;  // zero matrix, or NaN
+  if (!(amax > 0.0)) {  // zero matrix, or NaN
+    t.done = true;
+    t.value = amax == 0.0 ? 0.0 : amax;
+    return;
+  }
   int ex;
   frexp(amax, &ex);
+  t.ex = ex;
   LRADI_UNROLL for (int e = 0; e < N * N; ++e) a[e] = ldexp(G[e], -ex);
-  double d[N], off[N];
+  double* d = t.d;
+  double* off = t.off;
   LRADI_UNROLL for (int k = 0; k < N - 2; ++k) {
     double s2 = 0.0;
     LRADI_UNROLL for (int i = k + 1; i < N; ++i) s2 += a[i * N + k] * a[i * N + k];
@@ -159,9 +183,9 @@ LRADI_HD inline double lambda_max_sym_t(const double* G) {
     double pv[N];
     double vtp = 0.0;
     LRADI_UNROLL for (int i = k + 1; i < N; ++i) {
-      double t = 0.0;
-      LRADI_UNROLL for (int j = k + 1; j < N; ++j) t += a[i * N + j] * v[j];
-      pv[i] = beta * t;
+      double s = 0.0;
+      LRADI_UNROLL for (int j = k + 1; j < N; ++j) s += a[i * N + j] * v[j];
+      pv[i] = beta * s;
       vtp += v[i] * pv[i];
     }
     const double K = 0.5 * beta * vtp;
@@ -171,6 +195,7 @@ LRADI_HD inline double lambda_max_sym_t(const double* G) {
   }
   LRADI_UNROLL for (int i = 0; i < N; ++i) d[i] = a[i * N + i];
   off[N - 2] = a[(N - 1) * N + (N - 2)];
+  off[N - 1] = 0.0;
   double lo = d[0], hi = -1e300, e2max = 0.0;
   LRADI_UNROLL for (int i = 0; i < N; ++i) {
     lo = fmax(lo, d[i]);
@@ -178,23 +203,85 @@ LRADI_HD inline double lambda_max_sym_t(const double* G) {
     hi = fmax(hi, d[i] + r);
     if (i < N - 1) e2max = fmax(e2max, off[i] * off[i]);
   }
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
-  for (int it = 0; it < 128 && hi > lo; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (!(mid > lo && mid < hi)) break;  // adjacent doubles
-    int below = 0;
-    double q = d[0] - mid;
-    if (fabs(q) < pivmin) q = -pivmin;
+  t.lo = lo;
+  t.hi = hi;
+  t.pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
+}
+
+// true when every eigenvalue of the tridiagonal lies below x (all N Sturm
+// pivots of T - x I negative)
+template <int N>
+LRADI_HD inline bool lmax_above(const LmaxTri<N>& t, double x) {
+  int below = 0;
+  double q = t.d[0] - x;
+  if (fabs(q) < t.pivmin) q = -t.pivmin;
+  below += q < 0.0;
+  LRADI_UNROLL for (int i = 1; i < N; ++i) {
+    q = t.d[i] - x - t.off[i - 1] * t.off[i - 1] / q;
+    if (fabs(q) < t.pivmin) q = -t.pivmin;
     below += q < 0.0;
-    LRADI_UNROLL for (int i = 1; i < N; ++i) {
-      q = d[i] - mid - off[i - 1] * off[i - 1] / q;
-      if (fabs(q) < pivmin) q = -pivmin;
-      below += q < 0.0;
-    }
-    if (below == N) hi = mid;
-    else lo = mid;
   }
-  return ldexp(0.5 * (lo + hi), ex);
+  return below == N;
+}
+
+// bisection of [lo, hi] down to adjacent doubles; the unscaled midpoint
+template <int N>
+LRADI_HD inline double lmax_finish(LmaxTri<N>& t) {
+  for (int it = 0; it < 128 && t.hi > t.lo; ++it) {
+    const double mid = 0.5 * (t.lo + t.hi);
+    if (!(mid > t.lo && mid < t.hi)) break;  // adjacent doubles
+    if (lmax_above<N>(t, mid)) t.hi = mid;
+    else t.lo = mid;
+  }
+  return ldexp(0.5 * (t.lo + t.hi), t.ex);
+}
+
+template <int N>
+LRADI_HD inline double lambda_max_sym_t(const double* G) {
+  LmaxTri<N> t;
+  lmax_prepare<N>(G, t);
+  if (t.done) return t.value;
+  return lmax_finish<N>(t);
+}
+
+// Multisection: one round tests the L points lo + (l + 1)(hi - lo)/(L + 1),
+// l = 0..L-1, at once (one per lane) and keeps the sub-interval between
+// the last point below lambda_max and the first above it; `above` has bit
+// l set when point l lies above every eigenvalue.  Rounds run while all
+// the points are distinct from the ends; the bisection then finishes.
+LRADI_HD inline double msect_point(double lo, double hi, int l, int L) {
+  return lo + (hi - lo) * ((double)(l + 1) / (double)(L + 1));
+}
+LRADI_HD inline bool msect_fits(double lo, double hi, int L) {
+  return msect_point(lo, hi, 0, L) > lo && msect_point(lo, hi, L - 1, L) < hi;
+}
+LRADI_HD inline void msect_update(double& lo, double& hi, unsigned long long above, int L) {
+  if (above == 0) {
+    lo = msect_point(lo, hi, L - 1, L);
+    return;
+  }
+  int f = 0;
+  while (!((above >> f) & 1ull)) ++f;  // first point above
+  const double nhi = msect_point(lo, hi, f, L);
+  const double nlo = f > 0 ? msect_point(lo, hi, f - 1, L) : lo;
+  lo = nlo;
+  hi = nhi;
+}
+
+// the multisection with its L points tested one after another (the host
+// check of the rounds the GPU runs across lanes)
+template <int N, int L>
+LRADI_HD inline double lambda_max_sym_ms_t(const double* G) {
+  LmaxTri<N> t;
+  lmax_prepare<N>(G, t);
+  if (t.done) return t.value;
+  for (int r = 0; r < 64 && msect_fits(t.lo, t.hi, L); ++r) {
+    unsigned long long above = 0;
+    for (int l = 0; l < L; ++l)
+      if (lmax_above<N>(t, msect_point(t.lo, t.hi, l, L))) above |= 1ull << l;
+    msect_update(t.lo, t.hi, above, L);
+  }
+  return lmax_finish<N>(t);
 }
 
 // Largest eigenvalue of the product Gw Gt of two symmetric positive
@@ -202,8 +289,8 @@ LRADI_HD inline double lambda_max_sym_t(const double* G) {
 // lambda_max(diag(sqrt l) Q^T Gt Q diag(sqrt l)), a symmetric matrix.  So
 // ||W T^T||_2^2 = lambda_max((W^T W)(T^T T)) for tall blocks W, T.
 template <int N>
-LRADI_HD inline double lambda_max_prod_t(const double* Gw, const double* Gt) {
-  double a[N * N], q[N * N], m[N * N], t[N * N];
+LRADI_HD inline void prod_sym_t(const double* Gw, const double* Gt, double* m) {
+  double a[N * N], q[N * N], t[N * N];
   LRADI_UNROLL for (int e = 0; e < N * N; ++e) {
     a[e] = Gw[e];
     t[e] = Gt[e];
@@ -230,6 +317,11 @@ LRADI_HD inline double lambda_max_prod_t(const double* Gw, const double* Gt) {
       m[i * N + j] = v;
       m[j * N + i] = v;
     }
+}
+template <int N>
+LRADI_HD inline double lambda_max_prod_t(const double* Gw, const double* Gt) {
+  double m[N * N];
+  prod_sym_t<N>(Gw, Gt, m);
   return lambda_max_sym_t<N>(m);
 }
 
@@ -308,6 +400,12 @@ LRADI_HD inline void jacobi_eig(double* A, double* Q, int n) {
 LRADI_HD inline double lambda_max_sym(const double* G, int n) {
   double r = 0.0;
   LRADI_SMALL_SWITCH(n, r = lambda_max_sym_t<NN>(G));
+  return r;
+}
+template <int L>
+LRADI_HD inline double lambda_max_sym_ms(const double* G, int n) {
+  double r = 0.0;
+  LRADI_SMALL_SWITCH(n, r = (lambda_max_sym_ms_t<NN, L>(G)));
   return r;
 }
 LRADI_HD inline double lambda_max_prod(const double* Gw, const double* Gt, int n) {

@@ -9,6 +9,8 @@ int st_chol(const double* G, double* S, int n, double fl) { return lradi::chol_u
 void st_trinv(const double* S, double* X, int n) { lradi::tri_inv_upper(S, X, n); }
 void st_jacobi(double* A, double* Q, int n) { lradi::jacobi_eig(A, Q, n); }
 double st_lmax(const double* G, int n) { return lradi::lambda_max_sym(G, n); }
+double st_lmax_ms16(const double* G, int n) { return lradi::lambda_max_sym_ms<16>(G, n); }
+double st_lmax_ms64(const double* G, int n) { return lradi::lambda_max_sym_ms<64>(G, n); }
 double st_lmax_prod(const double* A, const double* B, int n) { return lradi::lambda_max_prod(A, B, n); }
 void st_house(double* M, double* Q, int n) { lradi::householder_2nxn(M, Q, n); }
 void st_tol(int selection, int backlook, int paper_abs, int k, double nw, double nt, double u,

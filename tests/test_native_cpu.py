@@ -66,6 +66,8 @@ def test_default_options_are_the_paper_settings(L):
     o = L.default_opts()
     assert o.tol == 1e-8 and o.delta_min == 1e-8 / 20 and o.delta_max == 0.1
     assert o.kmax == 50 and o.xi == 1.0 and o.selection == L.SEL_MID and o.backlook == 1
+    # no preconditioner unless asked for; its sweeps run in pairs where they tile
+    assert o.precond == L.PRECOND_NONE and o.precond_pairs == 1
 
 
 # --------------------------------------------------------------------------
@@ -80,6 +82,8 @@ def ST(tmp_path_factory):
     D = ctypes.c_double
     P = ctypes.POINTER(D)
     lib.st_lmax.restype = D
+    lib.st_lmax_ms16.restype = D
+    lib.st_lmax_ms64.restype = D
     lib.st_lmax_prod.restype = D
     lib.st_tol.argtypes = [ctypes.c_int] * 4 + [D] * 5 + [ctypes.c_int] + [D] * 5 + [ctypes.c_int, P, P]
     lib.st_gap.argtypes = [P, P] + [D] * 5
@@ -189,7 +193,9 @@ def test_controller_matches_oracle(ST, seed):
 def test_lambda_max_sym_hard_cases(ST, n):
     """The largest eigenvalue to 1e-13 relative on PSD matrices of wide
     condition, rank-deficient ones, repeated eigenvalues, diagonal ones, and
-    scales near the ends of the double range; the zero matrix gives 0."""
+    scales near the ends of the double range; the zero matrix gives 0.  The
+    same for the multisection the GPU spreads over 16 and 64 lanes (its
+    rounds run here one point after another)."""
     rng = np.random.default_rng(300 + n)
     cases = [_spd(rng, n, 1e12), np.diag(rng.uniform(0.1, 5.0, n)), np.eye(n) * 3.7]
     X = rng.standard_normal((n, max(1, n // 2)))
@@ -203,6 +209,8 @@ def test_lambda_max_sym_hard_cases(ST, n):
     for G in cases:
         G = np.ascontiguousarray((G + G.T) / 2)
         want = np.linalg.eigvalsh(G).max()
-        assert ST.st_lmax(_p(G), n) == pytest.approx(want, rel=1e-13, abs=1e-300)
+        for f in (ST.st_lmax, ST.st_lmax_ms16, ST.st_lmax_ms64):
+            assert f(_p(G), n) == pytest.approx(want, rel=1e-13, abs=1e-300)
     Z = np.zeros((n, n))
-    assert ST.st_lmax(_p(Z), n) == 0.0
+    for f in (ST.st_lmax, ST.st_lmax_ms16, ST.st_lmax_ms64):
+        assert f(_p(Z), n) == 0.0
