@@ -481,6 +481,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hmap.clear();
   int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0,
       pair_fast = 1;
+  long long black_rows = 0;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -499,6 +500,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       if (ws[s]->d.pair_lds == 0) pairs = 0;
       pair_lds = std::max(pair_lds, ws[s]->d.pair_lds);
       const int nb = ws[s]->d.n - ws[s]->d.nred, tile = (nb + ws[s]->d.nwg - 1) / ws[s]->d.nwg;
+      black_rows += nb;
       if (tile > kTPB || ws[s]->d.t2w > kPairRegSlots) pair_fast = 0;
     }
   }
@@ -543,7 +545,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.rfix = rfix;
   t.b.precond = precond;
   t.b.sweeps = sweeps;
-  t.b.pairs = precond && pairs && sweeps >= 2;
+  t.b.pairs = precond && pairs && sweeps >= 2 && black_rows <= kPairMaxRows;
   t.b.pair_lds = t.b.pairs ? pair_lds : 0;
   // (the register-held columns with wider or mixed blocks would spill)
   t.b.pair_fast = t.b.pairs && pair_fast && rfix >= 1 && rfix <= 4;
@@ -860,10 +862,12 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
   auto R = std::make_shared<RbData>();
   const int nn = A->nrows;
   csr_transpose(nn, rp.data(), ci.data(), v.data(), trp, tci, tv);
-  // one tile of black rows per row workgroup of the inner solves
+  // one tile of black rows per row workgroup of the inner solves (large
+  // matrices only)
   const int rpw = choose_rows_per_wg(nn);
+  const int tiles = nn >= kPairMinRows ? (nn + rpw - 1) / rpw : 0;
   RbHost h;
-  if (!rb_host_build(nn, rp.data(), ci.data(), v.data(), trp.data(), tci.data(), tv.data(), (nn + rpw - 1) / rpw, h))
+  if (!rb_host_build(nn, rp.data(), ci.data(), v.data(), trp.data(), tci.data(), tv.data(), tiles, h))
     return set_error("red-black preconditioner: the sparsity graph is not bipartite"), LRADI_EINVAL;
   auto up = [&](DevBuf& d, const void* src, size_t bytes) -> int {
     LRADI_TRY(d.alloc(std::max(bytes, (size_t)4)));

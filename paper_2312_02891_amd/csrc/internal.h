@@ -29,6 +29,18 @@ constexpr int kFuseCholMax = 8192;
 // sweep's halo rows cost more than the launch a pair saves (64^3 and 48^3,
 // r = 8: 35 us per paired launch against 15 us per single one).
 constexpr int kPairLdsMax = 64 * 1024;
+// matrices of fewer rows keep their black rows in ascending order and do
+// not pair: they are mostly solved in batches that fill the chip, where a
+// sweep is throughput-bound and whole grid rows per wavefront gather with
+// fuller cache lines than a tile's short row segments (256 problems of
+// 32^2..128^2: 1.04 s in ascending order, 1.16 s in tile order)
+constexpr int kPairMinRows = 32768;
+// pairs pay while a launch is latency-bound: a batch whose preconditioned
+// black rows exceed this many (about half the threads the chip holds)
+// fills the chip, and there the halo rows' extra work costs more than the
+// launch a pair saves (256 problems of 32^2..128^2: 1.16 s paired against
+// 1.01 s with single sweeps)
+constexpr long long kPairMaxRows = 262144;
 constexpr int kPairRegSlots = 8;
 constexpr double kPairMaxRegion = 1.6;
 

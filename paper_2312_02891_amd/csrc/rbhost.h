@@ -37,7 +37,8 @@ struct RbHost {
   int rbw = 0;   // off-diagonal slots per row (at least 1)
   int t2w = 0;   // off-diagonal slots of T per black row (at least 1)
   // colour order: red rows ascending, then the black rows tile by tile
-  // (ascending within a tile); pos[row] = its colour position
+  // (ascending within a tile; ascending overall without tiles);
+  // pos[row] = its colour position
   std::vector<int32_t> rows, pos;
   std::vector<double> dg;  // A's diagonal per row
   // slot u of colour position p at u * n + p: column, a_(i,col), a_(col,i);
@@ -64,7 +65,8 @@ struct RbHost {
 };
 
 // Fills h for the n x n CSR matrix (rp, ci, v) with transpose (trp, tci, tv)
-// and `tiles` tiles of ceil(nb / tiles) black positions (tiles >= 1).
+// and `tiles` tiles of ceil(nb / tiles) black positions; tiles = 0: the
+// black rows stay in ascending order and no tiles are made.
 // Returns false when the sparsity graph (A and A^T, stored zeros included)
 // is not bipartite.
 inline bool rb_host_build(int n, const int32_t* rp, const int32_t* ci, const double* v, const int32_t* trp,
@@ -154,9 +156,11 @@ inline bool rb_host_build(int n, const int32_t* rp, const int32_t* ci, const dou
   // runs out; its rows are then sorted by row index
   std::vector<int32_t> nat((size_t)n, -1);  // natural black position of a black row
   for (int pb = 0; pb < nbk; ++pb) nat[rows[nr + pb]] = pb;
-  const int tile = nbk > 0 ? (nbk + tiles - 1) / tiles : 0;
+  const int tile = (nbk > 0 && tiles > 0) ? (nbk + tiles - 1) / tiles : 0;
   std::vector<int32_t> perm(nbs);  // tile-order position -> natural position
-  {
+  if (tile == 0) {
+    for (int p = 0; p < nbk; ++p) perm[p] = p;
+  } else {
     std::vector<uint8_t> taken(nbs, 0);
     int filled = 0, seed = 0;
     while (filled < nbk) {

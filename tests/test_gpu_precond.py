@@ -52,6 +52,28 @@ def test_first_cycle_equals_preconditioned_minres_definition(L, ctx, dim, N, ome
     assert np.linalg.norm(Z - want) <= 1e-9 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("r,j,sweeps", [(2, 3, 5), (4, 4, 24), (1, 2, 2)])
+def test_first_cycle_with_paired_sweeps_equals_definition(L, ctx, r, j, sweeps):
+    """A 2-D grid above the pairing size (182^2 = 33124 rows, sweeps run two
+    per launch, an odd count ending with a single one): the first cycle's Z
+    is the oracle's preconditioned block minimal-residual iterate, to 1e-9."""
+    say("precond first cycle, paired", r, j, sweeps)
+    dim, N, omega = 2, 182, (30.0, -12.0)
+    H = L.convdiff(dim, N, omega)
+    A = convdiff_matrix(dim, N, omega)
+    W = np.random.default_rng(500 + r * 10 + j).standard_normal((H.n, r))
+    shift = -2000.0
+    o = L.default_opts(restart=j, max_inner=j, precond="rbilu0", precond_sweeps=sweeps, profile=1)
+    ctx.profile_reset()
+    Zs, stats, st = ctx.shifted_solve([H], [shift], [to_dev(W)], [0.0], o)
+    launches = ctx.profile_read(L.PROF_PRECOND)[1]
+    Z = Zs[0].cpu().numpy()
+    want = block_gmres_iterate(A, shift, W, j, precond=lambda X: OP.rb_precond_apply(A, shift, X, sweeps))
+    say("  preconditioner launches", launches)
+    assert stats[0]["steps"] == j
+    assert np.linalg.norm(Z - want) <= 1e-9 * np.linalg.norm(want)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("shift", [-2.0e5, -3.0e3, -25.0])
 def test_preconditioned_solve_reaches_delta_with_fewer_steps(L, ctx, prec, shift):
@@ -212,15 +234,17 @@ def test_generalized_with_lumped_mass_preconditioner_matches_oracle(L, ctx, name
     assert hp[:, 6].sum() + hp[:, 7].sum() < hn[:, 6].sum() + hn[:, 7].sum()
 
 
-@pytest.mark.parametrize("name,precision,sweeps,gen", [("SMALL_2D", "fp64", 24, False), ("SMALL_2D", "fp32", 5, False),
-                                                       ("C1", "fp64", 2, False), ("C1", "fp32", 24, False),
-                                                       ("SMALL_3D", "fp64", 3, False), ("GEN_SMALL", "fp64", 7, True)])
+@pytest.mark.parametrize("name,precision,sweeps,gen", [("C2", "fp64", 24, False), ("C2", "fp32", 5, False),
+                                                       ("C2", "fp64", 2, False), ("C2", "fp64", 7, True),
+                                                       ("SMALL_2D", "fp64", 24, False),
+                                                       ("SMALL_3D", "fp64", 3, False)])
 def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, sweeps, gen):
     """Two Jacobi sweeps per launch (the first over each tile's region into
     workgroup memory) give the same factors, history and inner step counts
-    as one sweep per launch, bit for bit; on the 2-D grids the pairs are
-    taken (fewer preconditioner launches, counted by the profiler), on the
-    3-D ones, whose regions are about twice their tiles, they are not."""
+    as one sweep per launch, bit for bit.  The pairs are taken on 2-D grids
+    of at least 32768 rows (fewer preconditioner launches, counted by the
+    profiler); not on smaller matrices (no tiles) nor on 3-D grids, whose
+    regions are about twice their tiles."""
     say("paired sweeps", name, precision, sweeps)
     P = getattr(WL, name)
     if gen:
@@ -238,7 +262,7 @@ def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, swee
     runs = []
     for pairs in (1, 0):
         o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps,
-                           precond_pairs=pairs, profile=1)
+                           precond_pairs=pairs, profile=1, kmax=100)
         ctx.profile_reset()
         res = ctx.solve(HA, HB, fd, gd, pA, pB, o, **kw)
         assert res.status == L.OK
@@ -249,11 +273,10 @@ def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, swee
     assert np.array_equal(a.history(), b.history())
     for x, y in zip(a.factors(), b.factors()):
         assert np.array_equal(x, y)
-    # 2-D tiles pair (regions about 1.3 times the tile); 3-D ones do not
-    if P.A.dim == 2:
-        assert la < lb
-    else:
-        assert la == lb
+    # 2-D tiles pair (regions about 1.4 times the tile); 3-D ones and
+    # matrices below 32768 rows do not
+    expect = P.A.dim == 2 and min(P.A.n, P.B.n) >= 32768
+    assert (la < lb) == expect
 
 
 def test_identity_mass_preconditioned_equals_plain(L, ctx):
@@ -376,3 +399,28 @@ def test_preconditioned_mixed_batch_and_server_equal_solo(L, ctx):
     finally:
         srv.close()
         c2.close()
+
+
+def test_pairs_only_for_batches_that_leave_the_chip_idle(L, ctx):
+    """Sweeps pair while a batch's preconditioned black rows stay within
+    262144 (latency-bound launches): two 256^2 systems pair, nine (294912
+    black rows) run one sweep per launch; both give the same bits as the
+    single-sweep option."""
+    H = L.convdiff(2, 256, (50.0, 20.0))
+    rng = np.random.default_rng(77)
+    for count, pairs_expected in ((2, True), (9, False)):
+        say("pair rule", count)
+        Ws = [to_dev(rng.standard_normal((H.n, 1))) for _ in range(count)]
+        shifts = [-100.0 * (s + 1) for s in range(count)]
+        runs = []
+        for pairs in (1, 0):
+            o = L.default_opts(precond="rbilu0", precond_sweeps=6, precond_pairs=pairs, profile=1)
+            ctx.profile_reset()
+            Zs, stats, st = ctx.shifted_solve([H] * count, shifts, Ws, [1e-8] * count, o)
+            assert st == L.OK
+            runs.append(([z.cpu().numpy() for z in Zs], ctx.profile_read(L.PROF_PRECOND)[1]))
+        (za, la), (zb, lb) = runs
+        say("  launches paired option", la, "single", lb)
+        for x, y in zip(za, zb):
+            assert np.array_equal(x, y)
+        assert (la < lb) == pairs_expected

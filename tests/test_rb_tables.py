@@ -150,6 +150,24 @@ def test_tables_against_definitions(RB, dim, N, omega, tiles):
     assert np.array_equal(hci, t2ci[:, halo])
 
 
+def test_without_tiles_black_rows_stay_ascending(RB):
+    """tiles = 0 (matrices below the pairing size): the black rows keep
+    their ascending order, no tiles or halos are made, and T's columns are
+    the same pattern as with tiles."""
+    A = convdiff_matrix(2, 24, (50.0, 20.0))
+    h = build(RB, A, 0)
+    col = OP.two_coloring(A)
+    nr = h["nred"]
+    assert np.array_equal(h["rows"][nr:], np.where(col == 1)[0])
+    assert h["tile"] == 0 and h["ntile"] == 0 and h["nhalo"] == 0 and h["halo_off"].tolist() == [0]
+    t = build(RB, A, 5)
+    nb = A.shape[0] - nr
+    W2 = h["t2w"]
+    pat = lambda hh: sorted(tuple(sorted(hh["rows"][nr + hh["t2ci"].reshape(W2, nb)[:, p]].tolist()))
+                            for p in range(nb))
+    assert t["t2w"] == W2 and pat(h) == pat(t)
+
+
 def test_tiles_of_a_grid_are_compact(RB):
     """On the 2-D 256^2 grid with one tile per row workgroup (128 black
     rows) the regions hold at most 1.6 times the black rows: the breadth
