@@ -151,8 +151,11 @@ typedef struct {
   int32_t precond_pairs;  /* 1 (default): run the sweeps two per launch where
                           the black rows tile well (each tile's first sweep
                           also covers the rows its second one reads, kept in
-                          workgroup memory); the results equal one sweep
-                          per launch bit for bit.  0: one per launch       */
+                          workgroup memory): matrices of at least 32768 rows
+                          whose tiles' regions stay within 1.6 times the
+                          tiles (2-D stencils), in batches of at most 262144
+                          black rows.  The results equal one sweep per
+                          launch bit for bit.  0: one per launch           */
 } lradi_opts;
 
 /* Per inner solve statistics (lradi_shifted_solve). */
