@@ -52,7 +52,7 @@ def test_first_cycle_equals_preconditioned_minres_definition(L, ctx, dim, N, ome
     assert np.linalg.norm(Z - want) <= 1e-9 * np.linalg.norm(want)
 
 
-@pytest.mark.parametrize("r,j,sweeps", [(2, 3, 5), (4, 4, 24), (1, 2, 2)])
+@pytest.mark.parametrize("r,j,sweeps", [(2, 3, 5), (4, 4, 24), (1, 2, 2), (8, 2, 3)])
 def test_first_cycle_with_paired_sweeps_equals_definition(L, ctx, r, j, sweeps):
     """A 2-D grid above the pairing size (182^2 = 33124 rows, sweeps run two
     per launch, an odd count ending with a single one): the first cycle's Z
@@ -424,3 +424,43 @@ def test_pairs_only_for_batches_that_leave_the_chip_idle(L, ctx):
         for x, y in zip(za, zb):
             assert np.array_equal(x, y)
         assert (la < lb) == pairs_expected
+
+
+def test_paired_sweeps_lyapunov_and_mixed_widths_equal_single_sweeps(L, ctx):
+    """Pairs on the Lyapunov path (one inner system per step beside an idle
+    mirror) and in a batch of mixed block widths (the kernels that dispatch
+    on r, with the columns read from the table) give the same bits as one
+    sweep per launch, with fewer launches."""
+    import torch
+    P = WL.LYAP_C2
+    HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
+    f, shifts = WL.lyap_inputs(P)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    runs = []
+    for pairs in (1, 0):
+        o = L.default_opts(tol=P.tol, selection="sym", precond="rbilu0", precond_sweeps=9, precond_pairs=pairs,
+                           profile=1)
+        ctx.profile_reset()
+        res = ctx.solve_lyap(HA, fd, shifts, o)
+        assert res.status == L.OK
+        runs.append((res, ctx.profile_read(L.PROF_PRECOND)[1]))
+    (a, la), (b, lb) = runs
+    say("  lyapunov k", a.k, "launches", la, lb)
+    assert a.k == b.k and la < lb
+    for x, y in zip(a.factors(), b.factors()):
+        assert np.array_equal(x, y)
+    H = L.convdiff(2, 256, (50.0, 20.0))
+    rng = np.random.default_rng(78)
+    Ws = [to_dev(rng.standard_normal((H.n, r))) for r in (1, 2, 3)]
+    runs = []
+    for pairs in (1, 0):
+        o = L.default_opts(precond="rbilu0", precond_sweeps=6, precond_pairs=pairs, profile=1)
+        ctx.profile_reset()
+        Zs, stats, st = ctx.shifted_solve([H] * 3, [-150.0, -900.0, -40.0], Ws, [1e-8] * 3, o)
+        assert st == L.OK
+        runs.append(([z.cpu().numpy() for z in Zs], ctx.profile_read(L.PROF_PRECOND)[1]))
+    (za, la), (zb, lb) = runs
+    say("  mixed widths launches", la, lb)
+    assert la < lb
+    for x, y in zip(za, zb):
+        assert np.array_equal(x, y)
