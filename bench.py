@@ -70,8 +70,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: this implementation runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is a design note, not code", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
