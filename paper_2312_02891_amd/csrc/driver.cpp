@@ -482,6 +482,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0,
       pair_fast = 1;
   long long black_rows = 0;
+  int max_tile = 0;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -501,7 +502,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       pair_lds = std::max(pair_lds, ws[s]->d.pair_lds);
       const int nb = ws[s]->d.n - ws[s]->d.nred, tile = (nb + ws[s]->d.nwg - 1) / ws[s]->d.nwg;
       black_rows += nb;
-      if (tile > kTPB || ws[s]->d.t2w > kPairRegSlots) pair_fast = 0;
+      max_tile = std::max(max_tile, tile);
+      if (ws[s]->d.t2w > kPairRegSlots) pair_fast = 0;
     }
   }
   // shifted-product tiles, grouped by lanes per row
@@ -548,7 +550,9 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.pairs = precond && pairs && sweeps >= 2 && black_rows <= kPairMaxRows;
   t.b.pair_lds = t.b.pairs ? pair_lds : 0;
   // (the register-held columns with wider or mixed blocks would spill)
-  t.b.pair_fast = t.b.pairs && pair_fast && rfix >= 1 && rfix <= 4;
+  // (even blocks take two lanes per tile row in that kernel)
+  t.b.pair_fast =
+      t.b.pairs && pair_fast && rfix >= 1 && rfix <= 4 && max_tile * (rfix % 2 == 0 ? 2 : 1) <= kTPB;
   t.b.precond_launches = precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) : 0;
   return LRADI_OK;
 }

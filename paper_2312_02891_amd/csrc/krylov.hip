@@ -552,9 +552,9 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
 // region indices), to the other compact block or, when it is the last
 // sweep, to P_j's black rows.  Each row's arithmetic is that of a single
 // sweep (the slots summed in the same order), so the result equals two
-// single-sweep launches bit for bit.  FAST (every tile at most kTPB rows,
-// T at most kPairRegSlots slots): each thread owns one tile row and holds
-// its region columns in registers from the start, so the second sweep
+// single-sweep launches bit for bit.  FAST (every tile at most kTPB / LPR
+// rows, T at most kPairRegSlots slots): each tile row has LPR lanes that
+// hold its region columns in registers from the start, so the second sweep
 // reads only LDS and cached operands.
 template <typename T, int R, bool FAST>
 __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int stage, T* lds) {
@@ -567,9 +567,12 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
   const T* src = rb_compact<T>(D, nb, ln);
   const T* It = static_cast<const T*>(D.It);
   constexpr int kS = kPairRegSlots;
+  // FAST: even blocks give each tile row two lanes (r/2 columns each), so
+  // the second sweep keeps all four wavefronts busy
+  constexpr int LPR = (R % 2 == 0) ? 2 : 1;
   int lc[kS];
   if constexpr (FAST) {
-    const int k = min((int)threadIdx.x, nin - 1);
+    const int k = min((int)threadIdx.x / LPR, nin - 1);
 #pragma unroll
     for (int u = 0; u < kS; ++u) lc[u] = D.t2lc[(size_t)min(u, D.t2w - 1) * nb + p0 + k];
   }
@@ -592,31 +595,32 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
   T* dst = rb_compact<T>(D, nb, ln + 1);
   T* out = last ? Pj : dst;
   if constexpr (FAST) {
-    const int k = threadIdx.x;
+    constexpr int RQ = R / LPR;
+    const int k = threadIdx.x / LPR, q0 = (threadIdx.x % LPR) * RQ;
     if (k >= nin) return;
     const int pb = p0 + k;
     const T* tv = static_cast<const T*>(D.t2val);
     const T* Y = static_cast<const T*>(D.Yb);
-    T acc[R];
+    T acc[RQ];
 #pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)pb * R + q];
-    T a[kS], xv[kS][R];
+    for (int q = 0; q < RQ; ++q) acc[q] = Y[(size_t)pb * R + q0 + q];
+    T a[kS], xv[kS][RQ];
 #pragma unroll
     for (int u = 0; u < kS; ++u) {
       a[u] = tv[(size_t)min(u, D.t2w - 1) * nb + pb];
 #pragma unroll
-      for (int q = 0; q < R; ++q) xv[u][q] = lds[lc[u] * R + q];
+      for (int q = 0; q < RQ; ++q) xv[u][q] = lds[lc[u] * R + q0 + q];
     }
 #pragma unroll
     for (int u = 0; u < kS; ++u) {
       const bool ok = u < D.t2w && lc[u] != k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] = ok ? acc[q] - a[u] * xv[u][q] : acc[q];
+      for (int q = 0; q < RQ; ++q) acc[q] = ok ? acc[q] - a[u] * xv[u][q] : acc[q];
     }
     const T it = It[pb];
     const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
 #pragma unroll
-    for (int q = 0; q < R; ++q) out[row * R + q] = acc[q] * it;
+    for (int q = 0; q < RQ; ++q) out[row * R + q0 + q] = acc[q] * it;
   } else {
     for (int k = threadIdx.x; k < nin; k += kTPB) {
       const int pb = p0 + k;
