@@ -7,8 +7,9 @@
  * as stated in eq. (sylv) and Algorithm 1 of Kuerschner, "Inexact linear solves
  * in the low-rank ADI iteration for large Sylvester equations".  The solution
  * is returned in factored form X ~ Z D Y^T with D = diag(gamma_1 I_r, ...,
- * gamma_k I_r) (Algorithm 1, output).  Only the case M = I, C = I and real
- * shifts is implemented.
+ * gamma_k I_r) (Algorithm 1, output).  The generalized equation
+ * A X C + M X B = -f g^T (eq. (gsylv)) and its Lyapunov case run on the same
+ * engine (lradi_solve_gen, lradi_solve_lyap).  Shifts are real.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -48,6 +49,14 @@ extern "C" {
 #define LRADI_ECANCELED (-6)   /* serving request cancelled before completion    */
 #define LRADI_WNOCONV 1        /* kmax outer steps without reaching tau          */
 #define LRADI_WINNER 2         /* some inner solve stopped at its iteration cap   */
+#define LRADI_WGAP 3           /* converged in the computed residual, but the
+                                  residual-gap estimate u_k + v_k of
+                                  eq. (upd_resgap) ended above the budget epsilon
+                                  of Thm 3 (clamps of eq. (bound_tols) overrode
+                                  the admissible tolerances), so the true
+                                  residual is not certified below 2 tol: it is
+                                  only bounded by tol + (u_k + v_k)/||f g^T||.
+                                  LRADI_WINNER takes precedence             */
 
 /* ---- tolerance selections (Sec. 3.2) ---------------------------------- */
 #define LRADI_SEL_RELATIVE 0   /* delta^A = rho*||w||, delta^B = rho*||t||        */
@@ -100,7 +109,9 @@ typedef struct {
 
 /* Options of one solve.  lradi_default_opts() fills the settings of the
  * paper's experiments (Sec. 4): tol 1e-8, delta_min = tol/20, delta_max =
- * 0.1, kmax = 50, xi = 1, back-looking mid selection. */
+ * 0.1, kmax = 50, xi = 1, back-looking mid selection; the dynamic
+ * selections are evaluated in the balanced frame (rescale = 2), which keeps
+ * the clamps of eq. (bound_tols) admissible when n and m differ a lot. */
 typedef struct {
   double tol;          /* outer tau: stop when ||w t^T|| < tol*||f g^T||      */
   double eps;          /* absolute gap budget epsilon of Thm 3; <= 0 selects
@@ -120,11 +131,13 @@ typedef struct {
   int32_t precision;   /* LRADI_FP64 or LRADI_FP32_INNER                      */
   int32_t restart;     /* block GMRES restart length m (blocks), 1..64        */
   int32_t max_inner;   /* cap on block Arnoldi steps per inner solve          */
-  int32_t rescale;     /* 1: scale f, g to equal spectral norm (Sec. 4).       *
-                        * 2: also evaluate the dynamic selections for the      *
-                        * pair (s w, t/s) at equal norms and map them back     *
-                        * (an extension: keeps delta_min admissible when the   *
-                        * factor norms drift apart; iterates are unchanged)    */
+  int32_t rescale;     /* 1: scale f, g to equal spectral norm (Sec. 4), the   *
+                        * paper's frame.  2 (default): also evaluate the       *
+                        * dynamic selections for the pair (s w, t/s) at equal  *
+                        * norms and map them back (an extension: keeps         *
+                        * delta_min admissible when the factor norms drift     *
+                        * apart, so u_k + v_k stays within epsilon).  0: no    *
+                        * rescaling                                           */
   int32_t b_is_transposed; /* 1: the B argument already holds B^T             */
   int32_t lookahead;   /* host scheduling depth (0 = synchronous), >= 0       */
   int32_t use_graph;   /* 1: capture one tick (inner step kernels, outer step

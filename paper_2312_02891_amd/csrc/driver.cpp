@@ -1214,6 +1214,10 @@ struct Engine {
     }
     int status = h.status;
     if (status == LRADI_OK && h.winner) status = LRADI_WINNER;
+    // Thm 3: ||R_true|| <= ||w_k t_k^T|| + u_k + v_k; the stop test bounds
+    // the first term by tol ||f g^T||, so the result is certified below
+    // 2 tol only while the gap estimate stayed within epsilon
+    if (status == LRADI_OK && h.u + h.v > h.eps) status = LRADI_WGAP;
     R->status = status;
     R->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q->t0).count();
     return LRADI_OK;
@@ -1294,7 +1298,7 @@ void lradi_default_opts(lradi_opts* o) {
   o->precision = LRADI_FP64;
   o->restart = 30;
   o->max_inner = 20000;
-  o->rescale = 1;
+  o->rescale = 2;
   o->b_is_transposed = 0;
   o->lookahead = 2;
   o->use_graph = 0;
@@ -1311,6 +1315,7 @@ const char* lradi_strerror(int st) {
     case LRADI_EBREAKDOWN: return "Krylov breakdown";
     case LRADI_WNOCONV: return "outer iteration reached kmax";
     case LRADI_WINNER: return "an inner solve reached its step cap";
+    case LRADI_WGAP: return "residual-gap estimate u + v above the budget epsilon";
     case LRADI_ECANCELED: return "request cancelled";
     default: return "unknown status";
   }

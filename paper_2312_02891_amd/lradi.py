@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblradi.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENAN, EBREAKDOWN, ECANCELED = 0, -1, -2, -3, -4, -5, -6
-WNOCONV, WINNER = 1, 2
+WNOCONV, WINNER, WGAP = 1, 2, 3
 SEL_RELATIVE, SEL_FIXED, SEL_MID, SEL_TIGHT_A, SEL_TIGHT_B, SEL_SYM = 0, 1, 2, 3, 4, 5
 FP64, FP32_INNER = 0, 1
 PRECOND_NONE, PRECOND_RBILU0 = 0, 1

@@ -68,15 +68,17 @@ def test_config1_exact_tolerance_fp64(L, ctx):
     assert np.allclose(hist[:, 14], ora.gammas, rtol=1e-15)
 
 
+@pytest.mark.parametrize("rescale", [1, 2])
 @pytest.mark.parametrize("sel", ["mid", "tightA", "tightB", "fixed"])
-def test_small_problem_dynamic_tolerances(L, ctx, sel):
+def test_small_problem_dynamic_tolerances(L, ctx, sel, rescale):
     """Relaxed (Sec. 3.2) and fixed inner tolerances on a 2-D problem with
-    r = 3: converged, true residual below tau, X within 1e-6 of the exact
+    r = 3, in the paper's frame (rescale = 1) and the balanced one (the
+    default): converged, true residual below tau, X within 1e-6 of the exact
     ADI iterate at the same step."""
-    say("adi small", sel)
+    say("adi small", sel, "rescale", rescale)
     P = WL.SMALL_2D
     HA, HB, A, B, f, g, pA, pB = setup(P, L)
-    o = L.default_opts(selection=sel, tol=P.tol)
+    o = L.default_opts(selection=sel, tol=P.tol, rescale=rescale)
     res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
     assert res.status in (L.OK,)
     compare(L, res, A, B, f, g, pA, pB, P.tol, kslack=1)
@@ -86,7 +88,7 @@ def test_small_problem_dynamic_tolerances(L, ctx, sel):
     eps = P.tol * res.norm_fg
     for row in hist:
         k = int(row[0])
-        dA, dB = OC.tolerances(sel, k, row[10], row[11], u, v, eps)
+        dA, dB = OC.tolerances(sel, k, row[10], row[11], u, v, eps, balance=rescale == 2)
         assert row[2] == pytest.approx(dA, rel=1e-12)
         assert row[3] == pytest.approx(dB, rel=1e-12)
         assert row[4] <= row[2] * (1 + 1e-12) and row[5] <= row[3] * (1 + 1e-12)

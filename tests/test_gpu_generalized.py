@@ -73,7 +73,7 @@ def test_generalized_matches_oracle(L, ctx, name, precision):
     u = v = 0.0
     eps = P.tol * res.norm_fg
     for row in res.history():
-        dA, dB = OC.tolerances("mid", int(row[0]), row[10], row[11], u, v, eps)
+        dA, dB = OC.tolerances("mid", int(row[0]), row[10], row[11], u, v, eps, balance=True)
         assert row[2] == pytest.approx(dA, rel=1e-12) and row[3] == pytest.approx(dB, rel=1e-12)
         assert row[4] <= row[2] * (1 + 1e-12) and row[5] <= row[3] * (1 + 1e-12)
         u, v = OC.update_gap(u, v, row[14], row[12], row[13], row[4], row[5])

@@ -66,6 +66,9 @@ def test_default_options_are_the_paper_settings(L):
     o = L.default_opts()
     assert o.tol == 1e-8 and o.delta_min == 1e-8 / 20 and o.delta_max == 0.1
     assert o.kmax == 50 and o.xi == 1.0 and o.selection == L.SEL_MID and o.backlook == 1
+    # the dynamic selections run in the balanced frame unless rescale = 1 asks
+    # for the paper's own frame
+    assert o.rescale == 2
     # no preconditioner unless asked for; its sweeps run in pairs where they tile
     assert o.precond == L.PRECOND_NONE and o.precond_pairs == 1
 

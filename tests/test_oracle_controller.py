@@ -71,6 +71,33 @@ def test_fig1_intercepts():
     assert dA == pytest.approx(3.3333333333333335e-04, rel=1e-12)
 
 
+def test_fig1_mid_selection_first_line():
+    """The first line of eq. (simple_tols) on Fig. 1's data: with delta_min = 0
+    and no delta_max cap, delta^A is half the delta^A-axis intercept of the
+    admissible region, eps_check/(c_check ||t||)/2 = 1.6667e-4, a value the
+    caption's numbers fix.  ||t|| and ||w|| differ by a factor of 200 there,
+    so a delta^A built from ||w|| instead (8.33e-7) or the midpoint with
+    +delta_min read the wrong way round cannot pass.  delta^B then lies on the
+    boundary Psi = 0, i.e. eq. (tolBfromtolA) evaluated at that delta^A."""
+    g = _fig1()
+    eh = g["eps_check"] / g["c_check"]
+    nw, nt = g["norm_w"], g["norm_t"]
+    dA, dB = C.select_mid(eh, nw, nt, 0.0, math.inf)
+    assert dA == pytest.approx(1.6666666666666666e-04, rel=1e-12)
+    assert dA == pytest.approx(0.5 * g["eps_check"] / (g["c_check"] * nt), rel=1e-14)
+    assert abs(dA - 0.5 * g["eps_check"] / (g["c_check"] * nw)) > 1e-4
+    # eq. (tolBfromtolA) with the caption's numbers: (eps - c dA ||t||) / (c (2 dA + ||w||))
+    want_dB = (g["eps_check"] - g["c_check"] * dA * nt) / (g["c_check"] * (2 * dA + nw))
+    assert dB == pytest.approx(want_dB, rel=1e-13)
+    assert dB == pytest.approx(7.142857142857143e-07, rel=1e-12)
+    # the pair is on the curve Psi = 0 of eq. (relax_AB) in the caption's form
+    psi = g["c_check"] * (dA * (nt + dB) + dB * (nw + dA))
+    assert psi == pytest.approx(g["eps_check"], rel=1e-13)
+    # a positive delta_min lowers delta^A by half of it (eq. (simple_tols))
+    dA2, _ = C.select_mid(eh, nw, nt, 1e-5, math.inf)
+    assert dA2 == pytest.approx(dA - 0.5e-5, rel=1e-13)
+
+
 @pytest.mark.parametrize("seed", range(20))
 def test_mid_selection_lies_on_boundary_curve(seed):
     """eq. (simple_tols) picks delta^A inside the box of eq. (relax_AB) and
