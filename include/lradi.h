@@ -415,6 +415,38 @@ int lradi_residual_gen(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, c
                        int r, const double* Z, const double* D, const double* Y, int k,
                        double* rel_true_res);
 
+/* ---- callers that cannot allocate -------------------------------------
+ * For callers that must not allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * lradi_residual_noalloc computes what lradi_residual (b_is_transposed = 0,
+ * M = C = I) computes, with the same kernels and the same arithmetic, but
+ * makes no device allocation (no hipMalloc / hipFree, no allocating library
+ * call): its Lanczos bases, partial sums and scalars live in a scratch array
+ * of lradi_residual_noalloc_limit() bytes (64 MiB) that the library holds on
+ * every device it runs on from module load until the process ends.  The
+ * caller passes every input on the device: A (n x n) and its transpose At,
+ * B (m x m) and its transpose Bt, all csr with on_device = 1 (int32 indices,
+ * FP64 values, valid structure: not checked here); f, g, Z, Y as in
+ * lradi_residual (device); D: host, k gammas (copied into the scratch).
+ * Inputs whose workspace exceeds the scratch (it grows with (n + m) times
+ * 2 k r, e.g. n = m = 4096 with k r = 120 fits, the 2-D 256^2 / 192^2
+ * configuration at k r = 164 does not) are rejected with LRADI_EINVAL and a
+ * message naming the sizes.  Calls on one device share its scratch array,
+ * which keeps the last call's contents; the library serialises them with a
+ * per-device lock, and the call returns after its stream finished.  A
+ * context must have been created on the device first (lradi_create looks
+ * up the scratch address there). */
+int lradi_residual_noalloc(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* At,
+                           const lradi_csr* B, const lradi_csr* Bt, const double* f,
+                           const double* g, int r, const double* Z, const double* D,
+                           const double* Y, int k, double* rel_true_res);
+/* Size in bytes of the scratch array of lradi_residual_noalloc. */
+int64_t lradi_residual_noalloc_limit(void);
+/* Number of device allocations the library has made in this process
+ * (diagnostics: lets a caller check that a call allocated nothing). */
+int64_t lradi_alloc_count(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -31,10 +32,6 @@ void csr_transpose(int n, const int32_t* rp, const int32_t* ci, const double* v,
 void csr_union(int n, const int32_t* prp, const int32_t* pci, const double* pv, const int32_t* qrp,
                const int32_t* qci, const double* qv, std::vector<int32_t>& urp,
                std::vector<int32_t>& uci, std::vector<double>& upv, std::vector<double>& uqv);
-int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
-                  const double* f, const double* g, int r, const double* Z, const double* gam_d,
-                  const double* Y, int k, int maxit, double* sigma_out, const DevCSR* M = nullptr,
-                  const DevCSR* Mt = nullptr, const DevCSR* C = nullptr, const DevCSR* Ct = nullptr);
 
 // ---------------------------------------------------------------------------
 // errors
@@ -50,9 +47,13 @@ void set_error(const char* fmt, ...) {
 
 // ---------------------------------------------------------------------------
 // buffers
+// device allocations made by the library since the process started
+std::atomic<int64_t> g_alloc_count{0};
+
 int DevBuf::alloc(size_t nbytes) {
   release();
   if (nbytes == 0) return LRADI_OK;
+  g_alloc_count.fetch_add(1, std::memory_order_relaxed);
   hipError_t e = hipMalloc(&p, nbytes);
   if (e != hipSuccess) {
     p = nullptr;
@@ -67,6 +68,36 @@ void DevBuf::release() {
   if (p) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch memory of lradi_residual_noalloc: a file-scope device array that
+// each device holds from module load to process end.  Host code never uses
+// its name as an address: the address on each device comes from
+// hipGetSymbolAddress (looked up once per device when a context is created
+// there) and is kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;                  // guards g_scratch_ptr and serialises the calls per device
+double* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+std::mutex g_scratch_call_mu[kMaxDevices];
+
+// With `device` current: record the address of `scratch` on it (once).
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return set_error("device ordinal %d above the scratch table", device), LRADI_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return LRADI_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    return LRADI_EHIP;
+  }
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return LRADI_OK;
 }
 
 namespace {
@@ -1330,6 +1361,10 @@ int lradi_create(lradi_ctx** out, int device, void* stream) {
   LRADI_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return set_error("lradi_create: no device %d", device), LRADI_EINVAL;
   LRADI_HIP(hipSetDevice(device));
+  // the no-alloc entry point's scratch address on this device; a failure
+  // here only disables that entry point (it looks the address up again and
+  // reports the error), so the context is created regardless
+  if (lradi::scratch_setup(device) != LRADI_OK) (void)hipGetLastError();
   auto* c = new lradi_ctx();
   c->device = device;
   if (stream) {
@@ -1650,6 +1685,59 @@ int lradi_residual(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, int b_i
                    const double* f, const double* g, int r, const double* Z, const double* D,
                    const double* Y, int k, double* rel) {
   return lradi_residual_gen(c, A, B, nullptr, nullptr, b_is_transposed, f, g, r, Z, D, Y, k, rel);
+}
+
+int64_t lradi_alloc_count(void) { return lradi::g_alloc_count.load(std::memory_order_relaxed); }
+
+int64_t lradi_residual_noalloc_limit(void) { return (int64_t)lradi::kScratchBytes; }
+
+int lradi_residual_noalloc(lradi_ctx* c, const lradi_csr* A, const lradi_csr* At, const lradi_csr* B,
+                           const lradi_csr* Bt, const double* f, const double* g, int r, const double* Z,
+                           const double* D, const double* Y, int k, double* rel) {
+  using namespace lradi;
+  if (!c || !A || !At || !B || !Bt || !f || !g || !rel || (k > 0 && (!Z || !D || !Y)))
+    return set_error("lradi_residual_noalloc: null argument"), LRADI_EINVAL;
+  if (r < 1 || r > kMaxR || k < 0) return set_error("lradi_residual_noalloc: bad r or k"), LRADI_EINVAL;
+  for (const lradi_csr* X : {A, At, B, Bt})
+    if (!X->on_device || X->nrows <= 0 || X->nrows != X->ncols || X->nnz < 0 || X->nnz > INT32_MAX ||
+        !X->rowptr || (X->nnz > 0 && (!X->colind || !X->val)))
+      return set_error("lradi_residual_noalloc: every matrix must be a square device csr (on_device = 1)"),
+             LRADI_EINVAL;
+  const int n = A->nrows, m = B->nrows;
+  if (At->nrows != n || Bt->nrows != m || At->nnz != A->nnz || Bt->nnz != B->nnz)
+    return set_error("lradi_residual_noalloc: At / Bt do not match A / B"), LRADI_EINVAL;
+  const int maxit = std::min(2 * k * r + r + 2, 400);
+  if (k * r > 1024) return set_error("lradi_residual_noalloc: k*r above 1024"), LRADI_EINVAL;
+  // scratch: the k gammas, then one residual workspace (the two evaluations
+  // run one after the other and share it)
+  const size_t gam_bytes = ((sizeof(double) * (size_t)std::max(k, 1) + 255) / 256) * 256;
+  const size_t need =
+      gam_bytes + std::max(residual_ws_bytes(n, m, maxit, false, false), residual_ws_bytes(n, m, r + 2, false, false));
+  if (need > kScratchBytes)
+    return set_error("lradi_residual_noalloc: n = %d, m = %d, k*r = %d need %zu bytes of scratch, above the "
+                     "%zu bytes this entry point holds (use lradi_residual)",
+                     n, m, k * r, need, kScratchBytes),
+           LRADI_EINVAL;
+  LRADI_HIP(hipSetDevice(c->device));
+  LRADI_TRY(scratch_setup(c->device));
+  std::lock_guard<std::mutex> lk(g_scratch_call_mu[c->device]);
+  double* base = g_scratch_ptr[c->device];
+  double* gam = base;
+  double* ws = base + gam_bytes / sizeof(double);
+  hipStream_t st = c->stream;
+  if (k > 0) LRADI_HIP(hipMemcpyAsync(gam, D, sizeof(double) * k, hipMemcpyHostToDevice, st));
+  auto ref = [](const lradi_csr* X) {
+    return CsrRef{X->nrows, X->rowptr, X->colind, X->val};
+  };
+  const CsrRef rA = ref(A), rAt = ref(At), rB = ref(B), rBt = ref(Bt);
+  double sres = 0.0, sfg = 0.0;
+  LRADI_TRY(residual_norm_ws(st, rA, rAt, rB, rBt, f, g, r, Z, gam, Y, k, maxit, &sres, nullptr, nullptr,
+                             nullptr, nullptr, ws));
+  LRADI_TRY(residual_norm_ws(st, rA, rAt, rB, rBt, f, g, r, Z, gam, Y, 0, r + 2, &sfg, nullptr, nullptr,
+                             nullptr, nullptr, ws));
+  LRADI_HIP(hipStreamSynchronize(st));
+  *rel = (sfg > 0.0) ? sres / sfg : 0.0;
+  return LRADI_OK;
 }
 
 // ---------------------------------------------------------------------------

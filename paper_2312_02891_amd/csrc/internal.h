@@ -309,6 +309,30 @@ struct DevCSR {
   bool has_rb() const { return rb != nullptr; }
 };
 
+// Borrowed view of a device CSR matrix (FP64 values).
+struct CsrRef {
+  int n = 0;
+  const int* rowptr = nullptr;
+  const int* colind = nullptr;
+  const double* val = nullptr;
+};
+inline CsrRef csr_ref(const DevCSR& A) {
+  return CsrRef{A.n, A.rowptr.as<int>(), A.colind.as<int>(), A.val64.as<double>()};
+}
+
+// True residual norm ||A X C + M X B + f g^T||_2 of X = Z diag(gam) Y^T by
+// Golub-Kahan-Lanczos (residual.hip): residual_norm allocates its workspace,
+// residual_norm_ws works in a caller-provided one of residual_ws_bytes.
+size_t residual_ws_bytes(int n, int m, int maxit, bool hasM, bool hasC);
+int residual_norm_ws(hipStream_t st, const CsrRef& A, const CsrRef& At, const CsrRef& B, const CsrRef& Bt,
+                     const double* f, const double* g, int r, const double* Z, const double* gam_d,
+                     const double* Y, int k, int maxit, double* sigma_out, const CsrRef* M,
+                     const CsrRef* Mt, const CsrRef* C, const CsrRef* Ct, double* ws);
+int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
+                  const double* f, const double* g, int r, const double* Z, const double* gam_d,
+                  const double* Y, int k, int maxit, double* sigma_out, const DevCSR* M = nullptr,
+                  const DevCSR* Mt = nullptr, const DevCSR* C = nullptr, const DevCSR* Ct = nullptr);
+
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels.hip)
 int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* rowptr,

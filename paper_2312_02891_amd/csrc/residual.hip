@@ -148,15 +148,15 @@ __global__ void k_bidiag_smax(const double* __restrict__ alpha, const double* __
 
 struct Dev {
   hipStream_t st;
-  DevBuf part;
+  double* part;
   int proj(const double* X, int nb, int n, int r, size_t stride, const double* v, double* out,
            double scale = 1.0) {
     const int nwg = (n + kRows - 1) / kRows;
     const int ncol = nb * r;
     if (ncol <= 0) return LRADI_OK;
-    hipLaunchKernelGGL(k_proj, dim3(nwg), dim3(256), 0, st, X, nb, n, r, stride, v, part.as<double>());
-    hipLaunchKernelGGL(k_proj_reduce, dim3((ncol + 255) / 256), dim3(256), 0, st, part.as<double>(),
-                       nwg, ncol, scale, out);
+    hipLaunchKernelGGL(k_proj, dim3(nwg), dim3(256), 0, st, X, nb, n, r, stride, v, part);
+    hipLaunchKernelGGL(k_proj_reduce, dim3((ncol + 255) / 256), dim3(256), 0, st, part, nwg, ncol, scale,
+                       out);
     LRADI_HIP(hipGetLastError());
     return LRADI_OK;
   }
@@ -167,46 +167,77 @@ struct Dev {
     LRADI_HIP(hipGetLastError());
     return LRADI_OK;
   }
-  int spmv(const DevCSR& A, const double* x, double* y, int acc) {
-    hipLaunchKernelGGL(k_spmv, dim3((A.n + 255) / 256), dim3(256), 0, st, A.n, A.rowptr.as<int>(),
-                       A.colind.as<int>(), A.val64.as<double>(), x, y, acc);
+  int spmv(const CsrRef& A, const double* x, double* y, int acc) {
+    hipLaunchKernelGGL(k_spmv, dim3((A.n + 255) / 256), dim3(256), 0, st, A.n, A.rowptr, A.colind, A.val, x,
+                       y, acc);
     LRADI_HIP(hipGetLastError());
     return LRADI_OK;
   }
 };
 
+// Workspace layout of one residual evaluation with at most J Lanczos steps
+// (offsets in doubles, every region starting on a 256-byte boundary).
+struct WsLayout {
+  size_t part, U, V, tn, tn2, tn3, tm, tm2, tm3, coef, scal, total;
+};
+
+size_t ws_round(size_t x) { return (x + 31) & ~(size_t)31; }
+
+WsLayout ws_layout(int n, int m, int J, bool hasM, bool hasC) {
+  const size_t nwg_max = (size_t)(std::max(n, m) + kRows - 1) / kRows;
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t cnt) {
+    const size_t at = o;
+    o += ws_round(std::max<size_t>(cnt, 1));
+    return at;
+  };
+  L.part = take(nwg_max * (size_t)std::max(kMaxCoef, J + 2));
+  L.U = take((size_t)n * (J + 1));
+  L.V = take((size_t)m * (J + 2));
+  L.tn = take(n);
+  L.tn2 = take(n);
+  L.tn3 = hasM ? take(n) : 0;
+  L.tm = take(m);
+  L.tm2 = take(m);
+  L.tm3 = hasC ? take(m) : 0;
+  L.coef = take(3 * (size_t)kMaxCoef + 2 * (size_t)(J + 2));
+  // scalars: [0] nrm2, [1..J+1] alpha, [J+2..2J+2] beta, [2J+4] sigma
+  L.scal = take(2 * (size_t)J + 8);
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
-int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
-                  const double* f, const double* g, int r, const double* Z, const double* gam_d,
-                  const double* Y, int k, int maxit, double* sigma_out, const DevCSR* M,
-                  const DevCSR* Mt, const DevCSR* C, const DevCSR* Ct) {
+size_t residual_ws_bytes(int n, int m, int maxit, bool hasM, bool hasC) {
+  return sizeof(double) * ws_layout(n, m, maxit, hasM, hasC).total;
+}
+
+int residual_norm_ws(hipStream_t st, const CsrRef& A, const CsrRef& At, const CsrRef& B, const CsrRef& Bt,
+                     const double* f, const double* g, int r, const double* Z, const double* gam_d,
+                     const double* Y, int k, int maxit, double* sigma_out, const CsrRef* M,
+                     const CsrRef* Mt, const CsrRef* C, const CsrRef* Ct, double* ws) {
   const int n = A.n, m = B.n;
   const int J = maxit;
   if (k * r > kMaxCoef) return set_error("lradi_residual: k*r above %d", kMaxCoef), LRADI_EINVAL;
+  const WsLayout W = ws_layout(n, m, J, M != nullptr, C != nullptr);
   Dev dv;
   dv.st = st;
-  const int nwg_max = (std::max(n, m) + kRows - 1) / kRows;
-  DevBuf Ub, Vb, tn, tn2, tn3, tm, tm2, tm3, coef, scal;
-  LRADI_TRY(dv.part.alloc(sizeof(double) * (size_t)nwg_max * std::max(kMaxCoef, J + 2)));
-  LRADI_TRY(Ub.alloc(sizeof(double) * (size_t)n * (J + 1)));
-  LRADI_TRY(Vb.alloc(sizeof(double) * (size_t)m * (J + 2)));
-  LRADI_TRY(tn.alloc(sizeof(double) * n));
-  LRADI_TRY(tn2.alloc(sizeof(double) * n));
-  LRADI_TRY(tm.alloc(sizeof(double) * m));
-  LRADI_TRY(tm2.alloc(sizeof(double) * m));
-  if (M) LRADI_TRY(tn3.alloc(sizeof(double) * n));
-  if (C) LRADI_TRY(tm3.alloc(sizeof(double) * m));
-  LRADI_TRY(coef.alloc(sizeof(double) * (3 * kMaxCoef + 2 * (J + 2))));
-  // scalars: [0] nrm2, [1..J+1] alpha, [J+2..2J+2] beta, [2J+3] sigma
-  LRADI_TRY(scal.alloc(sizeof(double) * (2 * J + 8)));
-  double* U = Ub.as<double>();
-  double* V = Vb.as<double>();
-  double* c1 = coef.as<double>();
+  dv.part = ws + W.part;
+  double* U = ws + W.U;
+  double* V = ws + W.V;
+  double* tn = ws + W.tn;
+  double* tn2 = ws + W.tn2;
+  double* tn3 = ws + W.tn3;
+  double* tm = ws + W.tm;
+  double* tm2 = ws + W.tm2;
+  double* tm3 = ws + W.tm3;
+  double* c1 = ws + W.coef;
   double* c2 = c1 + kMaxCoef;
   double* c3 = c2 + kMaxCoef;
   double* ho = c3 + kMaxCoef;  // reorthogonalisation coefficients
-  double* S = scal.as<double>();
+  double* S = ws + W.scal;
   double* nrm2 = S;
   double* alpha = S + 1;
   double* beta = S + 2 + J;
@@ -218,19 +249,19 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   // R v -> p (n-vector); p must not be tn, tn3, tm or tm3
   auto apply_R = [&](const double* v, double* p) -> int {
     if (C) {
-      LRADI_TRY(dv.spmv(*C, v, tm3.as<double>(), 0));   // tm3 = C v
-      LRADI_TRY(dv.proj(Y, k, m, r, sY, tm3.as<double>(), c1));  // c1 = Y^T C v
+      LRADI_TRY(dv.spmv(*C, v, tm3, 0));   // tm3 = C v
+      LRADI_TRY(dv.proj(Y, k, m, r, sY, tm3, c1));  // c1 = Y^T C v
     } else {
       LRADI_TRY(dv.proj(Y, k, m, r, sY, v, c1));        // c1 = Y^T v
     }
-    LRADI_TRY(dv.spmv(B, v, tm.as<double>(), 0));       // tm = B v
-    LRADI_TRY(dv.proj(Y, k, m, r, sY, tm.as<double>(), c2));  // c2 = Y^T B v
+    LRADI_TRY(dv.spmv(B, v, tm, 0));       // tm = B v
+    LRADI_TRY(dv.proj(Y, k, m, r, sY, tm, c2));  // c2 = Y^T B v
     LRADI_TRY(dv.proj(g, 1, m, r, sY, v, c3));          // c3 = g^T v
-    LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c1, 1.0, 0.0, tn.as<double>()));  // Z D c1
-    LRADI_TRY(dv.spmv(A, tn.as<double>(), p, 0));       // p = A Z D c1
+    LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c1, 1.0, 0.0, tn));  // Z D c1
+    LRADI_TRY(dv.spmv(A, tn, p, 0));       // p = A Z D c1
     if (M) {
-      LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c2, 1.0, 0.0, tn3.as<double>()));
-      LRADI_TRY(dv.spmv(*M, tn3.as<double>(), p, 1));   // p += M Z D c2
+      LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c2, 1.0, 0.0, tn3));
+      LRADI_TRY(dv.spmv(*M, tn3, p, 1));   // p += M Z D c2
     } else {
       LRADI_TRY(dv.expand(Z, k, n, r, sZ, gam_d, c2, 1.0, 1.0, p));
     }
@@ -239,23 +270,23 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   };
   // R^T u -> q (m-vector); q must not be tn2, tn3, tm2 or tm3
   auto apply_Rt = [&](const double* u, double* q) -> int {
-    LRADI_TRY(dv.spmv(At, u, tn2.as<double>(), 0));     // A^T u
-    LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn2.as<double>(), c1));  // Z^T A^T u
+    LRADI_TRY(dv.spmv(At, u, tn2, 0));     // A^T u
+    LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn2, c1));  // Z^T A^T u
     if (M) {
-      LRADI_TRY(dv.spmv(*Mt, u, tn3.as<double>(), 0));  // M^T u
-      LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn3.as<double>(), c2));  // Z^T M^T u
+      LRADI_TRY(dv.spmv(*Mt, u, tn3, 0));  // M^T u
+      LRADI_TRY(dv.proj(Z, k, n, r, sZ, tn3, c2));  // Z^T M^T u
     } else {
       LRADI_TRY(dv.proj(Z, k, n, r, sZ, u, c2));        // Z^T u
     }
     LRADI_TRY(dv.proj(f, 1, n, r, sZ, u, c3));          // f^T u
     if (C) {
-      LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c1, 1.0, 0.0, tm3.as<double>()));
-      LRADI_TRY(dv.spmv(*Ct, tm3.as<double>(), q, 0));  // q = C^T Y D c1
+      LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c1, 1.0, 0.0, tm3));
+      LRADI_TRY(dv.spmv(*Ct, tm3, q, 0));  // q = C^T Y D c1
     } else {
       LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c1, 1.0, 0.0, q));
     }
-    LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c2, 1.0, 0.0, tm2.as<double>()));
-    LRADI_TRY(dv.spmv(Bt, tm2.as<double>(), q, 1));
+    LRADI_TRY(dv.expand(Y, k, m, r, sY, gam_d, c2, 1.0, 0.0, tm2));
+    LRADI_TRY(dv.spmv(Bt, tm2, q, 1));
     LRADI_TRY(dv.expand(g, 1, m, r, sY, nullptr, c3, 1.0, 1.0, q));
     return LRADI_OK;
   };
@@ -275,13 +306,13 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   };
 
   // v_1
-  hipLaunchKernelGGL(k_start, nb256(m), dim3(256), 0, st, m, tm.as<double>());
-  LRADI_TRY(normalize(tm.as<double>(), m, V, S + 2 * J + 6));
+  hipLaunchKernelGGL(k_start, nb256(m), dim3(256), 0, st, m, tm);
+  LRADI_TRY(normalize(tm, m, V, S + 2 * J + 6));
   // u_1 = R v_1 / alpha_1 (apply_R uses tn internally, so write into U)
   LRADI_TRY(apply_R(V, U));
   LRADI_TRY(normalize(U, n, U, alpha));
   double prev = -1.0, cur = 0.0;
-  std::vector<double> hb(2);
+  double hb[2] = {0.0, 0.0};
   int it = 1;
   for (; it <= J; ++it) {
     // v_{it+1} = (R^T u_it - alpha_it v_it) / beta_it
@@ -303,8 +334,8 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
     // sigma_max of the it x it leading block (diagonal alpha_0..it-1, super beta_0..it-2)
     hipLaunchKernelGGL(k_bidiag_smax, dim3(1), dim3(64), 0, st, alpha, beta, it, sig);
     LRADI_HIP(hipGetLastError());
-    LRADI_HIP(hipMemcpyAsync(hb.data(), sig, sizeof(double), hipMemcpyDeviceToHost, st));
-    LRADI_HIP(hipMemcpyAsync(hb.data() + 1, beta + it - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    LRADI_HIP(hipMemcpyAsync(hb, sig, sizeof(double), hipMemcpyDeviceToHost, st));
+    LRADI_HIP(hipMemcpyAsync(hb + 1, beta + it - 1, sizeof(double), hipMemcpyDeviceToHost, st));
     LRADI_HIP(hipStreamSynchronize(st));
     cur = hb[0];
     if (it >= 3 && std::fabs(cur - prev) <= 1e-12 * cur) break;
@@ -313,6 +344,19 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
   }
   *sigma_out = cur;
   return LRADI_OK;
+}
+
+int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCSR& B, const DevCSR& Bt,
+                  const double* f, const double* g, int r, const double* Z, const double* gam_d,
+                  const double* Y, int k, int maxit, double* sigma_out, const DevCSR* M,
+                  const DevCSR* Mt, const DevCSR* C, const DevCSR* Ct) {
+  DevBuf ws;
+  LRADI_TRY(ws.alloc(residual_ws_bytes(A.n, B.n, maxit, M != nullptr, C != nullptr)));
+  const CsrRef rM = M ? csr_ref(*M) : CsrRef{}, rMt = Mt ? csr_ref(*Mt) : CsrRef{};
+  const CsrRef rC = C ? csr_ref(*C) : CsrRef{}, rCt = Ct ? csr_ref(*Ct) : CsrRef{};
+  return residual_norm_ws(st, csr_ref(A), csr_ref(At), csr_ref(B), csr_ref(Bt), f, g, r, Z, gam_d, Y, k,
+                          maxit, sigma_out, M ? &rM : nullptr, Mt ? &rMt : nullptr, C ? &rC : nullptr,
+                          Ct ? &rCt : nullptr, ws.as<double>());
 }
 
 }  // namespace lradi

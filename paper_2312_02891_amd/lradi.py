@@ -134,6 +134,10 @@ def _load():
                                  P(dbl)]),
         "lradi_residual_gen": (i32, [vp, P(Csr), P(Csr), P(Csr), P(Csr), i32, vp, vp, i32, vp, P(dbl),
                                      vp, i32, P(dbl)]),
+        "lradi_residual_noalloc": (i32, [vp, P(Csr), P(Csr), P(Csr), P(Csr), vp, vp, i32, vp, P(dbl), vp,
+                                         i32, P(dbl)]),
+        "lradi_residual_noalloc_limit": (ctypes.c_int64, []),
+        "lradi_alloc_count": (ctypes.c_int64, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -170,6 +174,30 @@ def default_opts(**kw) -> Opts:
             raise AttributeError(k)
         setattr(o, k, v)
     return o
+
+
+def alloc_count() -> int:
+    """Device allocations the library has made in this process."""
+    return int(_lib.lradi_alloc_count())
+
+
+def residual_noalloc_limit() -> int:
+    """Bytes of the scratch array behind Context.residual_noalloc."""
+    return int(_lib.lradi_residual_noalloc_limit())
+
+
+class DeviceCsr:
+    """CSR matrix whose arrays are torch tensors on the GPU (int32 row
+    pointers and column indices, FP64 values), passed with on_device = 1."""
+
+    def __init__(self, rowptr, colind, val):
+        torch = _torch()
+        self.rowptr = torch.as_tensor(np.ascontiguousarray(rowptr, dtype=np.int32)).cuda()
+        self.colind = torch.as_tensor(np.ascontiguousarray(colind, dtype=np.int32)).cuda()
+        self.val = torch.as_tensor(np.ascontiguousarray(val, dtype=np.float64)).cuda()
+        self.n = self.rowptr.numel() - 1
+        self.c = Csr(self.n, self.n, self.colind.numel(), self.rowptr.data_ptr(), self.colind.data_ptr(),
+                     self.val.data_ptr(), 1)
 
 
 class HostCsr:
@@ -424,6 +452,22 @@ class Context:
                                        ctypes.c_void_p(result.Zptr),
                                        D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        ctypes.c_void_p(result.Yptr), result.k, ctypes.byref(out)),
+               allow_warn=False)
+        return out.value
+
+    def residual_noalloc(self, A: "DeviceCsr", At: "DeviceCsr", B: "DeviceCsr", Bt: "DeviceCsr", f, g,
+                         result: "Result"):
+        """lradi_residual_noalloc: the true residual of a result (M = C = I)
+        with every matrix and its transpose already on the device; the call
+        allocates no device memory."""
+        D = np.ascontiguousarray(result.gammas(), dtype=np.float64)
+        out = ctypes.c_double()
+        self._sync()
+        _check(_lib.lradi_residual_noalloc(self.h, ctypes.byref(A.c), ctypes.byref(At.c), ctypes.byref(B.c),
+                                           ctypes.byref(Bt.c), _ptr(f), _ptr(g), f.shape[1],
+                                           ctypes.c_void_p(result.Zptr),
+                                           D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           ctypes.c_void_p(result.Yptr), result.k, ctypes.byref(out)),
                allow_warn=False)
         return out.value
 
