@@ -85,14 +85,21 @@ class FadiResult:
         return (self.Z * self.D()) @ self.Y.T
 
 
-def _direct_solver(Op: sp.spmatrix, cache: dict, shift: float, mass=None) -> Callable:
-    """LU of Op + shift * mass (mass = I when None), once per distinct shift."""
+def _direct_solver(Op: sp.spmatrix, cache: Optional[dict], shift: float, mass=None,
+                   permc_spec: Optional[str] = None) -> Callable:
+    """LU of Op + shift * mass (mass = I when None), once per distinct shift
+    (cache = None: factor for this one solve and discard).  permc_spec picks
+    SuperLU's column ordering (None: its default); it changes the fill of
+    the factors, not what is solved."""
     key = float(shift)
-    if key not in cache:
-        n = Op.shape[0]
-        E = sp.identity(n, format="csr") if mass is None else mass
-        cache[key] = spla.splu((Op + shift * E).tocsc())
-    lu = cache[key]
+    if cache is not None and key in cache:
+        return cache[key].solve
+    n = Op.shape[0]
+    E = sp.identity(n, format="csr") if mass is None else mass
+    kw = {} if permc_spec is None else {"permc_spec": permc_spec}
+    lu = spla.splu((Op + shift * E).tocsc(), **kw)
+    if cache is not None:
+        cache[key] = lu
     return lu.solve
 
 
@@ -100,14 +107,18 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
          pA: np.ndarray, pB: np.ndarray, tol: float = 1e-8, kmax: int = 50,
          rescale: bool = True, solve_A: Optional[Callable] = None,
          solve_B: Optional[Callable] = None, kfixed: Optional[int] = None,
-         M=None, C=None) -> FadiResult:
+         M=None, C=None, keep_factors: bool = True, permc_spec: Optional[str] = None,
+         log: Optional[Callable] = None) -> FadiResult:
     """Algorithm 1 with direct inner solves (the "direct solves" rows of Table 2).
 
     solve_A(k, shift, rhs) / solve_B(k, shift, rhs) may replace the direct
     solves (used by tests that plant inexact solves); by default each distinct
-    shift is LU-factorised once (SuperLU).  kfixed runs exactly that many steps
-    ignoring tau.  M, C (None = identity) give the generalized equation
-    (eq. (gsylv), iteration (lradi_g)).  Returns the factors, the computed
+    shift is LU-factorised once (SuperLU).  keep_factors = False factors per
+    solve and discards (for large 3-D operators whose factors do not fit
+    many at a time); permc_spec selects SuperLU's column ordering.  kfixed
+    runs exactly that many steps ignoring tau.  M, C (None = identity) give
+    the generalized equation (eq. (gsylv), iteration (lradi_g)).  log(k,
+    res) is called after each step.  Returns the factors, the computed
     residual history and the inner residual blocks."""
     A = sp.csr_matrix(A)
     Bt = sp.csr_matrix(B).T.tocsr()
@@ -118,7 +129,7 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
     if rescale:
         f, g = rescale_rhs(f, g)
     norm_fg = lowrank_product_norm(f, g)
-    cacheA, cacheB = {}, {}
+    cacheA, cacheB = ({}, {}) if keep_factors else (None, None)
     W, T = f.copy(), g.copy()
     Zs, Ys, gam, hist, rA, rB, nMz, nCy = [], [], [], [], [], [], [], []
     J = len(pA)
@@ -134,11 +145,11 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
                 break
         a, b = float(pA[k % J]), float(pB[k % J])
         if solve_A is None:
-            z = _direct_solver(A, cacheA, a, Mm)(W)
+            z = _direct_solver(A, cacheA, a, Mm, permc_spec)(W)
         else:
             z = solve_A(k, a, W)
         if solve_B is None:
-            y = _direct_solver(Bt, cacheB, b, Ct)(T)
+            y = _direct_solver(Bt, cacheB, b, Ct, permc_spec)(T)
         else:
             y = solve_B(k, b, T)
         z = np.asarray(z).reshape(W.shape)
@@ -157,6 +168,8 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
         gam.append(gk)
         k += 1
         hist.append(lowrank_product_norm(W, T) / norm_fg)
+        if log is not None:
+            log(k, hist[-1])
     n, r = f.shape
     m = g.shape[0]
     Z = np.hstack(Zs) if Zs else np.zeros((n, 0))
