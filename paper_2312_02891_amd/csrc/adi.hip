@@ -54,18 +54,17 @@ __device__ inline void reduce_rows(const double* partS, int nwg, int off, int P,
   const int p = t % P, g = t / P;
   double acc = 0.0;
   if (g < groups) {
-    // four independent sums keep four loads in flight per thread
     const double* X = partS + off + p;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // eight independent sums keep eight loads in flight per thread (a
+    // workgroup's partials sit kPS doubles apart, one line each)
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int w = g;
-    for (; w + 3 * groups < nwg; w += 4 * groups) {
-      a0 += X[(size_t)w * kPS];
-      a1 += X[(size_t)(w + groups) * kPS];
-      a2 += X[(size_t)(w + 2 * groups) * kPS];
-      a3 += X[(size_t)(w + 3 * groups) * kPS];
+    for (; w + 7 * groups < nwg; w += 8 * groups) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += X[(size_t)(w + u * groups) * kPS];
     }
-    for (; w < nwg; w += groups) a0 += X[(size_t)w * kPS];
-    acc = (a0 + a1) + (a2 + a3);
+    for (; w < nwg; w += groups) a[0] += X[(size_t)w * kPS];
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   red_lds[t] = acc;
   __syncthreads();
@@ -165,6 +164,8 @@ __device__ inline void arm_step(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& 
   }
 }
 
+__device__ inline bool gram_finite(double x) { return x == x && x - x == 0.0; }
+
 __device__ inline void mark_done(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& B) {
   C.done = 1;
   A.phase = PH_FINISHED;
@@ -198,9 +199,14 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ 
   }
   if (threadIdx.x == 0) {
     AdiCtl& C = ac[p];
+    // a NaN or Inf in f or g shows in its Gram matrix; the eigenvalue
+    // routines would turn it into a norm of 0 (fmax drops NaN), i.e. into
+    // the exact solution X = 0, so it is caught here
+    bool finite = true;
+    for (int e = 0; e < R * R; ++e) finite = finite && gram_finite(Gf[e]) && gram_finite(Gg[e]);
     const double nf = sqrt(fmax(lambda_max_sym(Gf, R), 0.0));
     const double ng = sqrt(fmax(lambda_max_sym(Gg, R), 0.0));
-    const double nfg = sqrt(fmax(lambda_max_prod(Gf, Gg, R), 0.0));
+    const double nfg = finite ? sqrt(fmax(lambda_max_prod(Gf, Gg, R), 0.0)) : nan("");
     double sf = 1.0, sg = 1.0;
     if (P.rescale && nf > 0.0 && ng > 0.0) {
       sf = sqrt(ng / nf);
@@ -414,7 +420,10 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     C.res = res;
     C.k = k + 1;
     if (A.status == IS_CAP || B.status == IS_CAP) C.winner = 1;
-    const bool bad = !(res == res) || res - res != 0.0 || A.status == IS_NAN || B.status == IS_NAN;
+    bool finite = true;
+    for (int e = 0; e < R * R; ++e)
+      finite = finite && gram_finite(GW[e]) && gram_finite(GT[e]) && gram_finite(GZ[e]) && gram_finite(GY[e]);
+    const bool bad = !finite || !(res == res) || res - res != 0.0 || A.status == IS_NAN || B.status == IS_NAN;
     if (bad) {
       C.status = LRADI_ENAN;
       mark_done(P, C, A, B);

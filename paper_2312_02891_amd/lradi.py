@@ -434,7 +434,10 @@ class Context:
         self._sync()
         st = _lib.lradi_batch_solve(self.h, n, arr, ctypes.byref(opts) if opts is not None else None, outs)
         results = [Result(outs[i], 0) if outs[i] else None for i in range(n)]
-        _check(st)
+        # per-problem failures (status in each result) still return every
+        # result; an error before any problem ran raises
+        if st < 0 and not any(outs[i] for i in range(n)):
+            _check(st)
         return results, st
 
     def residual(self, A: HostCsr, B: HostCsr, f, g, result: "Result", b_is_transposed=False,
