@@ -513,7 +513,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0,
       pair_fast = 1;
   long long black_rows = 0;
-  int max_tile = 0;
+  int max_tile = 0, pre_slices = 1;
   for (int s = 0; s < nsys; ++s) {
     if (ws[s]->d.precision != prec) return set_error("all systems of a batch must use one precision"), LRADI_EINVAL;
     t.hd[s] = ws[s]->d;
@@ -535,6 +535,11 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       black_rows += nb;
       max_tile = std::max(max_tile, tile);
       if (ws[s]->d.t2w > kPairRegSlots) pair_fast = 0;
+      // lanes per row of the row stages (the kernels' RbLanes): each lane
+      // gathers at least 16 bytes of a row
+      const int r = ws[s]->d.r, rb = r * (prec == LRADI_FP64 ? 8 : 4);
+      const int lanes = (r % 4 == 0 && rb >= 64) ? 4 : (r % 2 == 0 && rb >= 32) ? 2 : 1;
+      pre_slices = std::max(pre_slices, lanes);
     }
   }
   // shifted-product tiles, grouped by lanes per row
@@ -584,7 +589,9 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   // (even blocks take two lanes per tile row in that kernel)
   t.b.pair_fast =
       t.b.pairs && pair_fast && rfix >= 1 && rfix <= 4 && max_tile * (rfix % 2 == 0 ? 2 : 1) <= kTPB;
-  t.b.precond_launches = precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) : 0;
+  // forward, back, the sweeps, and (with sweeps) the launch that builds T
+  t.b.precond_launches = precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) + (sweeps > 0 ? 1 : 0) : 0;
+  t.b.pre_slices = pre_slices;
   return LRADI_OK;
 }
 

@@ -363,6 +363,8 @@ struct Batch {
                        // (the paired kernel keeps the second sweep's region
                        // columns in registers)
   int precond_launches;  // launches of one preconditioner application
+  int pre_slices;      // slices per row workgroup of the preconditioner's
+                       // row stages (second grid dimension, >= 1)
   int fuse_chol;       // 1: every scale workgroup reduces the small Gram
                        // partials and factors them itself (common r <= 4
                        // and small nwg r^2)

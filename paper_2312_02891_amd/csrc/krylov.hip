@@ -99,16 +99,16 @@ __device__ inline void reduce_small(const double* src, int nwg, int P, double* r
   double acc = 0.0;
   if (g < groups) {
     const double* X = src + p;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // eight independent sums keep eight loads in flight per thread (a
+    // workgroup's partials sit kPS doubles apart, one line each)
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int w = g;
-    for (; w + 3 * groups < nwg; w += 4 * groups) {
-      a0 += X[(size_t)w * kPS];
-      a1 += X[(size_t)(w + groups) * kPS];
-      a2 += X[(size_t)(w + 2 * groups) * kPS];
-      a3 += X[(size_t)(w + 3 * groups) * kPS];
+    for (; w + 7 * groups < nwg; w += 8 * groups) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += X[(size_t)(w + u * groups) * kPS];
     }
-    for (; w < nwg; w += groups) a0 += X[(size_t)w * kPS];
-    acc = (a0 + a1) + (a2 + a3);
+    for (; w < nwg; w += groups) a[0] += X[(size_t)w * kPS];
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   red_lds[t] = acc;
   __syncthreads();
@@ -321,10 +321,20 @@ struct RbUnroll {
   static constexpr int v = R >= 5 ? 6 : 8;
 };
 
-// acc += sum over the off-diagonal entries of row i (colour position p) of
-// a_ik X[k]; unused slots (col == i) are skipped by selection
+// lanes that share one row in the stages of one sweep launch: each owns
+// R / L consecutive columns, at least 16 bytes of every gathered row
 template <typename T, int R>
-__device__ inline void rb_gather(const RbCtx<T>& x, int p, int i, const T* __restrict__ X, T (&acc)[R]) {
+struct RbLanes {
+  static constexpr int v = (R % 4 == 0 && R * (int)sizeof(T) >= 64) ? 4
+                           : (R % 2 == 0 && R * (int)sizeof(T) >= 32) ? 2 : 1;
+};
+
+// acc[q] += sum over the off-diagonal entries of row i (colour position p)
+// of a_ik X[k][q0 + q], q < RQ; unused slots (col == i) are skipped by
+// selection
+template <typename T, int R, int RQ = R>
+__device__ inline void rb_gather(const RbCtx<T>& x, int p, int i, const T* __restrict__ X, int q0,
+                                 T (&acc)[RQ]) {
   constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
     int col[kRbUnroll];
@@ -337,24 +347,26 @@ __device__ inline void rb_gather(const RbCtx<T>& x, int p, int i, const T* __res
       a[u] = x.val[e];
       ok[u] = (u0 + u < x.w) && col[u] != i;
     }
-    T xv[kRbUnroll][R];
+    T xv[kRbUnroll][RQ];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u)
 #pragma unroll
-      for (int q = 0; q < R; ++q) xv[u][q] = X[(size_t)col[u] * R + q];
+      for (int q = 0; q < RQ; ++q) xv[u][q] = X[(size_t)col[u] * R + q0 + q];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u)
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] = ok[u] ? acc[q] + a[u] * xv[u][q] : acc[q];
+      for (int q = 0; q < RQ; ++q) acc[q] = ok[u] ? acc[q] + a[u] * xv[u][q] : acc[q];
   }
 }
 
 // black row i (position p): y = v_i - sum_j a_ij v_j / (d_j + s),
 // diag(T)_i = d_i + s - sum_j a_ij a_ji / (d_j + s)
-template <typename T, int R>
-__device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __restrict__ V, T (&y)[R], T& td) {
+// (columns q0 .. q0 + RQ - 1 of y; td in full)
+template <typename T, int R, int RQ = R>
+__device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __restrict__ V, int q0,
+                                    T (&y)[RQ], T& td) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) y[q] = V[(size_t)i * R + q];
+  for (int q = 0; q < RQ; ++q) y[q] = V[(size_t)i * R + q0 + q];
   td = rb_dsh(x, i);
   constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < x.w; u0 += kRbUnroll) {
@@ -369,19 +381,19 @@ __device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __
       t[u] = x.tv[e];
       ok[u] = (u0 + u < x.w) && col[u] != i;
     }
-    T xv[kRbUnroll][R];
+    T xv[kRbUnroll][RQ];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
       dj[u] = rb_dsh(x, col[u]);
 #pragma unroll
-      for (int q = 0; q < R; ++q) xv[u][q] = V[(size_t)col[u] * R + q];
+      for (int q = 0; q < RQ; ++q) xv[u][q] = V[(size_t)col[u] * R + q0 + q];
     }
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
       const T wgt = a[u] / dj[u];
       td = ok[u] ? td - wgt * t[u] : td;
 #pragma unroll
-      for (int q = 0; q < R; ++q) y[q] = ok[u] ? y[q] - wgt * xv[u][q] : y[q];
+      for (int q = 0; q < RQ; ++q) y[q] = ok[u] ? y[q] - wgt * xv[u][q] : y[q];
     }
   }
 }
@@ -429,13 +441,14 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
 // black position pb, with slot u's column at cols[u * cstride + crow] and
 // unused slots (col == self) skipped; the one arithmetic of every Jacobi
 // sweep, whichever table and source the columns refer to
-template <typename T, int R, typename Src>
+// (columns q0 .. q0 + RQ - 1)
+template <typename T, int R, typename Src, int RQ = R>
 __device__ inline void rb_sweep_acc(const SysDesc& D, int pb, int nb, const int* __restrict__ cols, int cstride,
-                                    int crow, int self, const Src& src, T (&acc)[R]) {
+                                    int crow, int self, const Src& src, int q0, T (&acc)[RQ]) {
   const T* tv = static_cast<const T*>(D.t2val);
   const T* Y = static_cast<const T*>(D.Yb);
 #pragma unroll
-  for (int q = 0; q < R; ++q) acc[q] = Y[(size_t)pb * R + q];
+  for (int q = 0; q < RQ; ++q) acc[q] = Y[(size_t)pb * R + q0 + q];
   constexpr int kRbUnroll = RbUnroll<R>::v;
   for (int u0 = 0; u0 < D.t2w; u0 += kRbUnroll) {
     int col[kRbUnroll];
@@ -448,15 +461,15 @@ __device__ inline void rb_sweep_acc(const SysDesc& D, int pb, int nb, const int*
       a[u] = tv[(size_t)slot * nb + pb];
       ok[u] = (u0 + u < D.t2w) && col[u] != self;
     }
-    T xv[kRbUnroll][R];
+    T xv[kRbUnroll][RQ];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u)
 #pragma unroll
-      for (int q = 0; q < R; ++q) xv[u][q] = src(col[u], q);
+      for (int q = 0; q < RQ; ++q) xv[u][q] = src(col[u], q0 + q);
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u)
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
+      for (int q = 0; q < RQ; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
   }
 }
 
@@ -470,14 +483,14 @@ struct RbRows {
 // one Jacobi sweep on T z = y for black position pb: dst row drow =
 // (y_pb - sum_u T(pb, l_u) src_{l_u}) / diag(T)_pb, with y, 1/diag(T) and
 // src in black-position order
-template <typename T, int R>
+template <typename T, int R, int RQ = R>
 __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
-                                    T* __restrict__ dst, size_t drow) {
-  T acc[R];
-  rb_sweep_acc<T, R>(D, pb, nb, D.t2ci, nb, pb, pb, RbRows<T, R>{src}, acc);
+                                    T* __restrict__ dst, size_t drow, int q0) {
+  T acc[RQ];
+  rb_sweep_acc<T, R, RbRows<T, R>, RQ>(D, pb, nb, D.t2ci, nb, pb, pb, RbRows<T, R>{src}, q0, acc);
   const T it = static_cast<const T*>(D.It)[pb];
 #pragma unroll
-  for (int q = 0; q < R; ++q) dst[drow * R + q] = acc[q] * it;
+  for (int q = 0; q < RQ; ++q) dst[drow * R + q0 + q] = acc[q] * it;
 }
 
 // black iterate t (< sweeps) in black-position order: two compact blocks in
@@ -492,56 +505,67 @@ __device__ inline T* rb_compact(const SysDesc& D, int nb, int t) {
 // launch, or two (pair) with a single last one for an odd count
 __device__ inline int rb_launch_index(int stage, int pair) { return pair ? (stage - 1) / 2 : stage - 1; }
 
-// stage 0: fwd (black rows; builds T's values at the first Arnoldi step of
-// an inner solve); 1..sweeps: Jacobi sweep t (black rows); sweeps + 1: back
-// (red rows)
+// KIND 0: fwd (black rows); 1: Jacobi sweep `stage` (black rows); 2: back
+// (red rows); 5: T's values for the shift (black rows, at the first Arnoldi
+// step of an inner solve, in a launch of its own so that the forward stage
+// keeps few registers)
 template <typename T, int R, int KIND>
 __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj,
-                               int stage, int pair, bool build) {
+                               int stage, int pair) {
   const int nb = D.n - D.nred;
   constexpr bool black = KIND != 2;
   const int off = black ? D.nred : 0;
   const int cnt = black ? nb : D.nred;
   // the colour's rows spread evenly over all of the system's workgroups
-  // (about half a chunk each), not over the first half of them
+  // (about half a chunk each), not over the first half of them; each
+  // workgroup's share is cut into gridDim.y slices, one per workgroup of
+  // the launch's second grid dimension, and each row is served by L lanes
+  // that own R / L columns each (every column sums its terms in the same
+  // order whatever L, so the results do not depend on it)
+  constexpr int L = KIND == 5 ? 1 : RbLanes<T, R>::v, RQ = R / L;
   const int bc = (cnt + D.nwg - 1) / D.nwg;
-  const int p0 = c.w * bc, p1 = min(cnt, p0 + bc);
-  for (int pp = p0 + threadIdx.x; pp < p1; pp += kTPB) {
+  const int sub = (bc + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int w0 = c.w * bc;
+  const int p0 = w0 + (int)blockIdx.y * sub, p1 = min(cnt, min(w0 + bc, p0 + sub));
+  const int lane = (int)threadIdx.x % L, q0 = lane * RQ;
+  for (int pp = p0 + (int)threadIdx.x / L; pp < p1; pp += kTPB / L) {
     const int p = off + pp;  // colour position
     const int i = D.rbrows[p];
     if constexpr (KIND == 0) {
-      T y[R], td;
-      rb_black_fwd<T, R>(x, p, i, V, y, td);
+      T y[RQ], td;
+      rb_black_fwd<T, R, RQ>(x, p, i, V, q0, y, td);
       const T it = T(1) / td;
       if (D.sweeps == 0) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = y[q] * it;
+        for (int q = 0; q < RQ; ++q) Pj[(size_t)i * R + q0 + q] = y[q] * it;
       } else {
         T* z0 = rb_compact<T>(D, nb, 0);
         T* Y = static_cast<T*>(D.Yb);
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          z0[(size_t)pp * R + q] = y[q] * it;
-          Y[(size_t)pp * R + q] = y[q];
+        for (int q = 0; q < RQ; ++q) {
+          z0[(size_t)pp * R + q0 + q] = y[q] * it;
+          Y[(size_t)pp * R + q0 + q] = y[q];
         }
-        static_cast<T*>(D.It)[pp] = it;
-        if (build) rb_build_t<T>(D, x, p, pp, nb, i);
+        if (lane == 0) static_cast<T*>(D.It)[pp] = it;
       }
+    } else if constexpr (KIND == 5) {
+      if (D.sweeps > 0) rb_build_t<T>(D, x, p, pp, nb, i);
     } else if constexpr (KIND == 1) {
       const int ln = rb_launch_index(stage, pair);
       const T* src = rb_compact<T>(D, nb, ln);
       if (stage == D.sweeps)
-        rb_sweep_row<T, R>(D, pp, nb, src, Pj, (size_t)i);
+        rb_sweep_row<T, R, RQ>(D, pp, nb, src, Pj, (size_t)i, q0);
       else
-        rb_sweep_row<T, R>(D, pp, nb, src, rb_compact<T>(D, nb, ln + 1), (size_t)pp);
+        rb_sweep_row<T, R, RQ>(D, pp, nb, src, rb_compact<T>(D, nb, ln + 1), (size_t)pp, q0);
     } else {  // back: z_r = (v_r - E z) / (d_r + s)
-      T g[R];
+      T g[RQ];
 #pragma unroll
-      for (int q = 0; q < R; ++q) g[q] = T(0);
-      rb_gather<T, R>(x, p, i, Pj, g);
+      for (int q = 0; q < RQ; ++q) g[q] = T(0);
+      rb_gather<T, R, RQ>(x, p, i, Pj, q0, g);
       const T di = rb_dsh(x, i);
 #pragma unroll
-      for (int q = 0; q < R; ++q) Pj[(size_t)i * R + q] = (V[(size_t)i * R + q] - g[q]) / di;
+      for (int q = 0; q < RQ; ++q)
+        Pj[(size_t)i * R + q0 + q] = (V[(size_t)i * R + q0 + q] - g[q]) / di;
     }
   }
 }
@@ -585,7 +609,7 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
     const int pb = in ? p0 + k : D.halo[g];
     T acc[R];
     rb_sweep_acc<T, R>(D, pb, nb, in ? D.t2ci : D.halo_ci, in ? nb : nhs, in ? pb : g, pb,
-                       RbRows<T, R>{src}, acc);
+                       RbRows<T, R>{src}, 0, acc);
     const T it = It[pb];
 #pragma unroll
     for (int q = 0; q < R; ++q) lds[k * R + q] = acc[q] * it;
@@ -625,7 +649,7 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
     for (int k = threadIdx.x; k < nin; k += kTPB) {
       const int pb = p0 + k;
       T acc[R];
-      rb_sweep_acc<T, R>(D, pb, nb, D.t2lc, nb, pb, k, RbRows<T, R>{lds}, acc);
+      rb_sweep_acc<T, R>(D, pb, nb, D.t2lc, nb, pb, k, RbRows<T, R>{lds}, 0, acc);
       const T it = It[pb];
       const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
 #pragma unroll
@@ -640,6 +664,7 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
 // LDS, so it counts one sweep plus its tables of region indices
 template <typename T, int KIND>
 __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
+  if (KIND == 5) return 0;  // once per inner solve, not per application
   const unsigned long long nr = D.nred, nb = D.n - D.nred, n = D.n, R = D.r, t = sizeof(T);
   const unsigned long long sweep = nb * 4 + D.t2w * nb * (4 + t) + 3 * nb * R * t + nb * t;
   if (KIND == 0)
@@ -652,7 +677,8 @@ __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
 
 // KIND 0: forward (stage 0), 1: sweep `stage`, 2: back, 3: sweeps `stage`
 // and `stage` + 1, 4: the same with the region columns in registers (pair =
-// 1: the launches of the sweeps are paired); one instance per kind, so
+// 1: the launches of the sweeps are paired), 5: T's values for the shift
+// (first Arnoldi step of an inner solve only); one instance per kind, so
 // each allocates only the registers it needs
 template <typename T, int RF, int KIND>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
@@ -662,7 +688,8 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_ARNOLDI || !D.rbrows) return;
-  if (prof && c.w == 0 && threadIdx.x == 0) atomicAdd(prof + LRADI_PROF_PRECOND, rb_stage_bytes<T, KIND>(D));
+  if (prof && c.w == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    atomicAdd(prof + LRADI_PROF_PRECOND, rb_stage_bytes<T, KIND>(D));
   const int j = ctl[c.s].j;
   const RbCtx<T> x = rb_ctx<T>(D, ctl[c.s].shift);
   const size_t blk = (size_t)D.n * D.r;
@@ -670,11 +697,13 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   T* Pj = static_cast<T*>(D.P) + (size_t)j * blk;
   // the shift is fixed for an inner solve: T's values are built at its
   // first Arnoldi step (first cycle, j = 0) and kept over restarts
-  const bool build = ctl[c.s].cycles == 1 && j == 0;
-  if constexpr (KIND >= 3) {
+  if constexpr (KIND == 5) {
+    if (!(ctl[c.s].cycles == 1 && j == 0)) return;
+  }
+  if constexpr (KIND == 3 || KIND == 4) {
     LRADI_RSEL(RF, D.r, (rb_pair<T, RR, KIND == 4>(D, c, Pj, stage, reinterpret_cast<T*>(rb_lds))));
   } else {
-    LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, pair, build));
+    LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, pair));
   }
 }
 
@@ -1527,7 +1556,11 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   const double fl64 = 1e-24, fl32 = 1e-10;
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[6], st));
   if (b.precond) {
-    hipLaunchKernelGGL((k_precond<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
+    // row stages: each workgroup's rows in pre_slices slices
+    const dim3 rgs(b.rowgrid, b.pre_slices > 1 ? b.pre_slices : 1);
+    if (b.sweeps > 0)
+      hipLaunchKernelGGL((k_precond<T, RF, 5>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
+    hipLaunchKernelGGL((k_precond<T, RF, 0>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
     int stage = 1;
     if (b.pairs)
       for (; stage + 1 <= b.sweeps; stage += 2) {
@@ -1539,9 +1572,9 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
                              b.prof_bytes);
       }
     for (; stage <= b.sweeps; ++stage)
-      hipLaunchKernelGGL((k_precond<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.pairs,
+      hipLaunchKernelGGL((k_precond<T, RF, 1>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, stage, b.pairs,
                          b.prof_bytes);
-    hipLaunchKernelGGL((k_precond<T, RF, 2>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.sweeps + 1, b.pairs,
+    hipLaunchKernelGGL((k_precond<T, RF, 2>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, b.sweeps + 1, b.pairs,
                        b.prof_bytes);
   }
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[7], st));
