@@ -221,6 +221,20 @@ int lradi_convdiff_size(int dim, int N, int64_t* n, int64_t* nnz);
 int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* rowptr,
                        int32_t* colind, double* val);
 
+/* Discretisations of the first-order term for lradi_gen_convdiff_scheme. */
+#define LRADI_SCHEME_UPWIND 0  /* as lradi_gen_convdiff: real spectrum        */
+#define LRADI_SCHEME_CENTRAL 1 /* central differences: coefficient of u at
+                                  p - s_c is -ih2 - (w_c ih)/2, at p + s_c it is
+                                  -ih2 + (w_c ih)/2, diagonal sum of 2 ih2
+                                  (then negated); once the mesh Peclet number
+                                  |w_c| h / 2 exceeds 1 the spectrum is complex
+                                  (the non-symmetric case of Sec. 3.2.4 with
+                                  complex shift parameters)                 */
+/* lradi_gen_convdiff with the first-order term discretised by `scheme`;
+ * same sizes, ordering and value recipe otherwise. */
+int lradi_gen_convdiff_scheme(int dim, int N, const double* omega, int scheme, int32_t* rowptr,
+                              int32_t* colind, double* val);
+
 /* Y = (A + shift I) X for one n x r block (the shifted product used by every
  * inner Krylov step).  A: csr (host or device); X, Y: device, n x r
  * row-major, double when precision = LRADI_FP64, float when

@@ -25,20 +25,32 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def convdiff_csr(dim: int, N: int, omega, negate: bool = True):
+def convdiff_csr(dim: int, N: int, omega, negate: bool = True, scheme: str = "upwind"):
     """Return (rowptr int32, colind int32, val float64) of A = -L_h (or L_h
-    when negate=False)."""
+    when negate=False).  scheme "central" discretises the first-order term by
+    central differences, w_c (u_{p+s_c} - u_{p-s_c}) / (2h): neighbours
+    -ih2 -+ (w_c ih)/2 (the product w_c ih halved, an exact scaling), diagonal
+    the sum of 2 ih2; its spectrum is complex once |w_c| h / 2 > 1."""
     if dim not in (2, 3):
         raise ValueError("dim must be 2 or 3")
     if len(omega) != dim:
         raise ValueError("omega needs one component per axis")
+    if scheme not in ("upwind", "central"):
+        raise ValueError("scheme must be upwind or central")
     ih = float(N + 1)
     ih2 = ih * ih
-    lo = [-ih2 - max(float(w), 0.0) * ih for w in omega]     # coefficient of u_{p - s_c}
-    hi = [-ih2 - max(-float(w), 0.0) * ih for w in omega]    # coefficient of u_{p + s_c}
-    diag = 0.0
-    for w in omega:
-        diag = diag + (2.0 * ih2 + abs(float(w)) * ih)
+    if scheme == "central":
+        lo = [-ih2 - (float(w) * ih) * 0.5 for w in omega]
+        hi = [-ih2 + (float(w) * ih) * 0.5 for w in omega]
+        diag = 0.0
+        for _ in omega:
+            diag = diag + 2.0 * ih2
+    else:
+        lo = [-ih2 - max(float(w), 0.0) * ih for w in omega]     # coefficient of u_{p - s_c}
+        hi = [-ih2 - max(-float(w), 0.0) * ih for w in omega]    # coefficient of u_{p + s_c}
+        diag = 0.0
+        for w in omega:
+            diag = diag + (2.0 * ih2 + abs(float(w)) * ih)
     n = N ** dim
     p = np.arange(n, dtype=np.int64)
     stride = [N ** c for c in range(dim)]
@@ -70,8 +82,8 @@ def convdiff_csr(dim: int, N: int, omega, negate: bool = True):
     return (rowptr.astype(np.int32), colind.astype(np.int32), vals.astype(np.float64))
 
 
-def convdiff_matrix(dim: int, N: int, omega, negate: bool = True) -> sp.csr_matrix:
+def convdiff_matrix(dim: int, N: int, omega, negate: bool = True, scheme: str = "upwind") -> sp.csr_matrix:
     """scipy CSR view of convdiff_csr."""
-    rp, ci, v = convdiff_csr(dim, N, omega, negate)
+    rp, ci, v = convdiff_csr(dim, N, omega, negate, scheme)
     n = N ** dim
     return sp.csr_matrix((v, ci, rp), shape=(n, n))

@@ -19,9 +19,12 @@ X ~ Z_k Gamma_k Y_k^*.  The loop runs while ||w_{k-1} t_{k-1}^*|| >= tau ||f g^T
 (the while-condition of Algorithm 1; spectral norm, Sec. 1.1).
 
 Shift naming used throughout: pA[k] is the shift added to A (beta_k of
-Algorithm 1), pB[k] the shift added to B^T (conj(alpha_k)); so
-gamma_k = -(pA[k] + pB[k]) for real shifts.  Shift arrays are cycled when the
-iteration runs longer than they are.
+Algorithm 1), pB[k] the shift added to B^T = B^* (conj(alpha_k) for the real
+B of every workload); so gamma_k = -(pA[k] + conj(pB[k])), which is
+-(pA[k] + pB[k]) for real shifts.  Complex shifts run the complex form of the
+iteration as printed (complex w_k, t_k, z_k, y_k, gamma_k; X ~ Z Gamma Y^*),
+which Sec. 3.2.4 keeps for complex shift parameters.  Shift arrays are cycled
+when the iteration runs longer than they are.
 
 Only tests/, the smoke check and the bench's CPU baseline use this module;
 the product path never imports it.
@@ -81,8 +84,8 @@ class FadiResult:
         return np.repeat(self.gammas, r)
 
     def X(self) -> np.ndarray:
-        """Dense Z Gamma Y^T (small problems only)."""
-        return (self.Z * self.D()) @ self.Y.T
+        """Dense Z Gamma Y^* (small problems only)."""
+        return (self.Z * self.D()) @ self.Y.conj().T
 
 
 def _direct_solver(Op: sp.spmatrix, cache: Optional[dict], shift: float, mass=None,
@@ -91,7 +94,7 @@ def _direct_solver(Op: sp.spmatrix, cache: Optional[dict], shift: float, mass=No
     (cache = None: factor for this one solve and discard).  permc_spec picks
     SuperLU's column ordering (None: its default); it changes the fill of
     the factors, not what is solved."""
-    key = float(shift)
+    key = complex(shift) if np.iscomplexobj(shift) else float(shift)
     if cache is not None and key in cache:
         return cache[key].solve
     n = Op.shape[0]
@@ -121,11 +124,11 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
     res) is called after each step.  Returns the factors, the computed
     residual history and the inner residual blocks."""
     A = sp.csr_matrix(A)
-    Bt = sp.csr_matrix(B).T.tocsr()
+    Bt = sp.csr_matrix(B).conj().T.tocsr()          # B^* (B^T for real B)
     Mm = None if M is None else sp.csr_matrix(M)
-    Ct = None if C is None else sp.csr_matrix(C).T.tocsr()
-    f = np.array(f, dtype=np.float64, copy=True)
-    g = np.array(g, dtype=np.float64, copy=True)
+    Ct = None if C is None else sp.csr_matrix(C).conj().T.tocsr()
+    f = np.array(f, dtype=np.result_type(f, np.float64), copy=True)
+    g = np.array(g, dtype=np.result_type(g, np.float64), copy=True)
     if rescale:
         f, g = rescale_rhs(f, g)
     norm_fg = lowrank_product_norm(f, g)
@@ -143,7 +146,9 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
         else:
             if k >= kmax or lowrank_product_norm(W, T) < tol * norm_fg:
                 break
-        a, b = float(pA[k % J]), float(pB[k % J])
+        a, b = pA[k % J], pB[k % J]
+        a = complex(a) if np.iscomplexobj(a) else float(a)
+        b = complex(b) if np.iscomplexobj(b) else float(b)
         if solve_A is None:
             z = _direct_solver(A, cacheA, a, Mm, permc_spec)(W)
         else:
@@ -158,9 +163,10 @@ def fadi(A: sp.spmatrix, B: sp.spmatrix, f: np.ndarray, g: np.ndarray,
         Cy = y if Ct is None else np.asarray(Ct @ y)
         rA.append(W - (A @ z + a * Mz))
         rB.append(T - (Bt @ y + b * Cy))
-        gk = -(a + b)
+        # gamma_k = -(beta_k + alpha_k) with pA = beta_k, pB = conj(alpha_k)
+        gk = -(a + np.conj(b))
         W = W + gk * Mz
-        T = T + gk * Cy
+        T = T + np.conj(gk) * Cy
         nMz.append(spectral_norm(Mz))
         nCy.append(spectral_norm(Cy))
         Zs.append(z)
@@ -186,40 +192,41 @@ def true_residual_dense(A, B, f, g, X, M=None, C=None) -> np.ndarray:
     AX = np.asarray(A @ X)
     AXC = AX if C is None else np.asarray((sp.csr_matrix(C).T @ AX.T).T)
     MX = X if M is None else np.asarray(sp.csr_matrix(M) @ X)
-    return AXC + np.asarray((B.T @ MX.T).T) + f @ g.T
+    return AXC + np.asarray((B.T @ MX.T).T) + f @ g.conj().T
 
 
 def lowrank_residual_norm(A, B, f, g, Z, d, Y, M=None, C=None) -> float:
-    """||A Z D Y^T C + M Z D Y^T B + f g^T||_2 exactly, without forming n x m
-    matrices: the residual equals U V^T with U = [A Z, M Z, f] and
-    V = [C^T Y D, B^T Y D, g]; with thin QRs U = Q_u R_u, V = Q_v R_v its norm
-    is ||R_u R_v^T||_2.  d holds the diagonal of D; M, C = None mean identity."""
+    """||A Z D Y^* C + M Z D Y^* B + f g^*||_2 exactly, without forming n x m
+    matrices: the residual equals U V^* with U = [A Z, M Z, f] and
+    V = [C^* Y D^*, B^* Y D^*, g]; with thin QRs U = Q_u R_u, V = Q_v R_v its
+    norm is ||R_u R_v^*||_2.  d holds the diagonal of D; M, C = None mean
+    identity (real matrices; Z, d, Y may be complex)."""
     A = sp.csr_matrix(A)
-    Bt = sp.csr_matrix(B).T.tocsr()
-    YD = Y * d
+    Bt = sp.csr_matrix(B).conj().T.tocsr()
+    YD = Y * np.conj(d)
     MZ = Z if M is None else np.asarray(sp.csr_matrix(M) @ Z)
-    CtYD = YD if C is None else np.asarray(sp.csr_matrix(C).T @ YD)
+    CtYD = YD if C is None else np.asarray(sp.csr_matrix(C).conj().T @ YD)
     U = np.hstack([np.asarray(A @ Z), MZ, f])
     V = np.hstack([CtYD, np.asarray(Bt @ YD), g])
     Ru = np.linalg.qr(U, mode="r")
     Rv = np.linalg.qr(V, mode="r")
-    return spectral_norm(Ru @ Rv.T)
+    return spectral_norm(Ru @ Rv.conj().T)
 
 
 def lowrank_diff_fro(Z1, d1, Y1, Z2, d2, Y2) -> float:
-    """||Z1 D1 Y1^T - Z2 D2 Y2^T||_F without forming the n x m matrices."""
+    """||Z1 D1 Y1^* - Z2 D2 Y2^*||_F without forming the n x m matrices."""
     L = np.hstack([Z1 * d1, -(Z2 * d2)])
     R = np.hstack([Y1, Y2])
     Rl = np.linalg.qr(L, mode="r")
     Rr = np.linalg.qr(R, mode="r")
-    return float(np.linalg.norm(Rl @ Rr.T, "fro"))
+    return float(np.linalg.norm(Rl @ Rr.conj().T, "fro"))
 
 
 def lowrank_fro(Z, d, Y) -> float:
-    """||Z D Y^T||_F without forming it."""
+    """||Z D Y^*||_F without forming it."""
     Rl = np.linalg.qr(Z * d, mode="r")
     Rr = np.linalg.qr(Y, mode="r")
-    return float(np.linalg.norm(Rl @ Rr.T, "fro"))
+    return float(np.linalg.norm(Rl @ Rr.conj().T, "fro"))
 
 
 def bartels_stewart(A, B, f, g) -> np.ndarray:

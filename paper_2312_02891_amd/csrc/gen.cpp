@@ -1,5 +1,6 @@
-// Host-side problem construction: the upwind convection-diffusion matrices of
-// Sec. 4 (eq. (ex:convdiff)) in CSR form, and a CSR transpose.
+// Host-side problem construction: the convection-diffusion matrices of Sec. 4
+// (eq. (ex:convdiff)) in CSR form, upwind or central first differences, and
+// a CSR transpose.
 //
 // This file must be compiled with -ffp-contract=off: every product and sum
 // of the value recipe is rounded on its own, so the stored FP64 values are
@@ -32,13 +33,17 @@ extern "C" int lradi_convdiff_size(int dim, int N, int64_t* n, int64_t* nnz) {
   return LRADI_OK;
 }
 
-extern "C" int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* rowptr,
-                                  int32_t* colind, double* val) {
+extern "C" int lradi_gen_convdiff_scheme(int dim, int N, const double* omega, int scheme,
+                                         int32_t* rowptr, int32_t* colind, double* val) {
   int64_t n = 0, nnz = 0;
   int st = lradi_convdiff_size(dim, N, &n, &nnz);
   if (st != LRADI_OK) return st;
   if (!omega || !rowptr || !colind || !val) {
     lradi::set_error("lradi_gen_convdiff: null pointer");
+    return LRADI_EINVAL;
+  }
+  if (scheme != LRADI_SCHEME_UPWIND && scheme != LRADI_SCHEME_CENTRAL) {
+    lradi::set_error("lradi_gen_convdiff: unknown scheme %d", scheme);
     return LRADI_EINVAL;
   }
   if (nnz > INT32_MAX) {
@@ -52,13 +57,21 @@ extern "C" int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* 
   double diag = 0.0;
   for (int c = 0; c < dim; ++c) {
     const double w = omega[c];
+    const double twoih2 = 2.0 * ih2;
+    if (scheme == LRADI_SCHEME_CENTRAL) {
+      // central first difference: w_c (u_{p+s} - u_{p-s}) / (2h)
+      const double half = (w * ih) * 0.5;
+      lo[c] = -ih2 - half;
+      hi[c] = -ih2 + half;
+      diag = diag + twoih2;
+      continue;
+    }
     const double wp = w > 0.0 ? w : 0.0;
     const double wm = (-w) > 0.0 ? (-w) : 0.0;
     const double tlo = wp * ih;
     const double thi = wm * ih;
     lo[c] = -ih2 - tlo;  // neighbour p - s_c
     hi[c] = -ih2 - thi;  // neighbour p + s_c
-    const double twoih2 = 2.0 * ih2;
     const double aw = std::fabs(w) * ih;
     const double term = twoih2 + aw;
     diag = diag + term;
@@ -90,6 +103,11 @@ extern "C" int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* 
     rowptr[p + 1] = (int32_t)k;
   }
   return (k == nnz) ? LRADI_OK : LRADI_EINVAL;
+}
+
+extern "C" int lradi_gen_convdiff(int dim, int N, const double* omega, int32_t* rowptr,
+                                  int32_t* colind, double* val) {
+  return lradi_gen_convdiff_scheme(dim, N, omega, LRADI_SCHEME_UPWIND, rowptr, colind, val);
 }
 
 namespace lradi {

@@ -104,6 +104,7 @@ def _load():
         "lradi_destroy": (i32, [vp]),
         "lradi_convdiff_size": (i32, [i32, i32, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "lradi_gen_convdiff": (i32, [i32, i32, P(dbl), vp, vp, vp]),
+        "lradi_gen_convdiff_scheme": (i32, [i32, i32, P(dbl), i32, vp, vp, vp]),
         "lradi_spmm": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32]),
         "lradi_spmm_bench": (i32, [vp, P(Csr), dbl, vp, vp, i32, i32, i32, i32, P(dbl),
                                    P(ctypes.c_int64)]),
@@ -216,8 +217,12 @@ class HostCsr:
         return len(self.colind)
 
 
-def convdiff(dim: int, N: int, omega: Sequence[float]) -> HostCsr:
-    """A = -L_h of the upwind convection-diffusion operator (library generator)."""
+SCHEME_UPWIND, SCHEME_CENTRAL = 0, 1
+
+
+def convdiff(dim: int, N: int, omega: Sequence[float], scheme: int = SCHEME_UPWIND) -> HostCsr:
+    """A = -L_h of the convection-diffusion operator (library generator),
+    upwind or central first differences."""
     n = ctypes.c_int64()
     nnz = ctypes.c_int64()
     _check(_lib.lradi_convdiff_size(dim, N, ctypes.byref(n), ctypes.byref(nnz)))
@@ -225,8 +230,8 @@ def convdiff(dim: int, N: int, omega: Sequence[float]) -> HostCsr:
     ci = np.empty(nnz.value, dtype=np.int32)
     v = np.empty(nnz.value, dtype=np.float64)
     om = (ctypes.c_double * dim)(*[float(w) for w in omega])
-    _check(_lib.lradi_gen_convdiff(dim, N, om, rp.ctypes.data, ci.ctypes.data, v.ctypes.data),
-           allow_warn=False)
+    _check(_lib.lradi_gen_convdiff_scheme(dim, N, om, int(scheme), rp.ctypes.data, ci.ctypes.data,
+                                          v.ctypes.data), allow_warn=False)
     return HostCsr(rp, ci, v)
 
 

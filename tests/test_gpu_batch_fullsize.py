@@ -1,0 +1,61 @@
+"""Batched workload at its real sizes: 16 of the 256 independent problems
+(2-D grids of side 32..128, convection components in [-40, 40], r in
+{1, 2, 4}), solved together with FP32 inner / FP64 outer work and the
+preconditioned inner solver the batch bench uses, each compared with the
+oracle's direct-solve iteration: same step count, X within 1e-6 at that
+step, true residual below tau."""
+import numpy as np
+import pytest
+
+from oracle import fadi as OF
+from oracle.convdiff import convdiff_matrix
+from paper_2312_02891_amd import workloads as WL
+
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = list(range(0, 256, 16))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2312_02891_amd import lradi
+    return lradi
+
+
+def test_batch_sample_at_full_size_matches_oracle(L):
+    probs = WL.batch_problems(256)
+    items, host = [], []
+    for i in SAMPLE:
+        P = probs[i]
+        HA = L.convdiff(2, P.A.N, P.A.omega)
+        HB = L.convdiff(2, P.B.N, P.B.omega)
+        f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
+        pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
+        items.append((HA, HB, to_dev(f), to_dev(g), pA, pB))
+        host.append((P, f, g, pA, pB))
+    ctx = L.Context(0)
+    o = L.default_opts(precision="fp32", precond="rbilu0", precond_sweeps=24)
+    res, st = ctx.batch_solve(items, o)
+    assert st == L.OK
+    worst = 0.0
+    for i, r, (P, f, g, pA, pB) in zip(SAMPLE, res, host):
+        A = convdiff_matrix(2, P.A.N, P.A.omega)
+        B = convdiff_matrix(2, P.B.N, P.B.omega)
+        full = OF.fadi(A, B, f, g, pA, pB, tol=P.tol, kmax=50)
+        Z, d, Y = r.factors()
+        kr = r.k * P.r
+        xerr = OF.lowrank_diff_fro(Z, d, Y, full.Z[:, :kr], full.D()[:kr], full.Y[:, :kr])
+        xerr /= OF.lowrank_fro(full.Z[:, :kr], full.D()[:kr], full.Y[:, :kr])
+        fs, gs = OF.rescale_rhs(f, g)
+        true = OF.lowrank_residual_norm(A, B, fs, gs, Z, d, Y) / full.norm_fg
+        say("  problem %3d: n %5d m %5d r %d k %2d (oracle %2d) X err %.2e true %.2e"
+            % (i, P.A.n, P.B.n, P.r, r.k, full.k, xerr, true))
+        worst = max(worst, xerr)
+        assert r.status == L.OK
+        assert r.k == full.k
+        assert xerr <= 1e-6
+        assert true <= P.tol
+    say("  worst X err", worst)
+    ctx.close()

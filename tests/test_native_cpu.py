@@ -51,6 +51,16 @@ def test_generator_bit_exact_against_oracle(L, dim, N, omega):
     assert np.array_equal(A.val.view(np.uint64), v.view(np.uint64))
 
 
+@pytest.mark.parametrize("dim,N,omega", [(2, 1, (1.0, 2.0)), (2, 40, (150.0, 100.0)), (2, 30, (-120.0, 90.0)),
+                                         (3, 14, (70.0, -50.0, 40.0)), (2, 37, (12.3456789, -7.25))])
+def test_central_generator_bit_exact_against_oracle(L, dim, N, omega):
+    A = L.convdiff(dim, N, omega, scheme=L.SCHEME_CENTRAL)
+    rp, ci, v = convdiff_csr(dim, N, omega, scheme="central")
+    assert np.array_equal(A.rowptr, rp)
+    assert np.array_equal(A.colind, ci)
+    assert np.array_equal(A.val.view(np.uint64), v.view(np.uint64))
+
+
 def test_generator_rejects_bad_arguments(L):
     lib = L.lib()
     n = ctypes.c_int64()
