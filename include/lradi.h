@@ -338,7 +338,34 @@ typedef struct {
                               -f f^T (B = A^T, C = M^T, g = f, shiftsB =
                               shiftsA; B, g, shiftsB, C are ignored and may
                               be NULL): one inner solve per step, Y = Z     */
+  const double* shiftsA_im;  /* complex shifts: imaginary parts (host,
+                              nshifts) of the shifts added to A, or NULL for
+                              real shifts; see lradi_solve_complex          */
+  const double* shiftsB_im;  /* imaginary parts of the shifts added to B^T  */
 } lradi_problem;
+
+/* Algorithm 1 with complex shift parameters in its complex form, the one
+ * Sec. 3.2.4 keeps for non-symmetric problems whose shift sets contain
+ * complex conjugate pairs (A, B, f, g real):
+ *   (A + pA_k I) z_k = w_{k-1},  w_k = w_{k-1} + gamma_k z_k,
+ *   (B^T + pB_k I) y_k = t_{k-1},  t_k = t_{k-1} + conj(gamma_k) y_k,
+ *   gamma_k = -(pA_k + conj(pB_k)),  X ~ Z diag(gamma_k I_r) Y^*,
+ * with pA_k = beta_k and pB_k = conj(alpha_k) of Algorithm 1.  Each inner
+ * solve is the real form of the complex shifted system on the stacked block
+ * [re; im] (2n rows); norms are those of the complex blocks (eq. (upd_resgap)
+ * takes |gamma_k|).  The shifts come as real and imaginary parts (host
+ * arrays of nshifts, cycled).  Needs r <= 4, no mass matrices and
+ * opts->precond = LRADI_PRECOND_NONE (LRADI_EINVAL otherwise).  The result
+ * is complex (lradi_result_is_complex): factor block k of Z is 2n x r with
+ * the real parts in rows 0..n-1 and the imaginary parts in rows n..2n-1
+ * (Y likewise, 2m x r), D holds (re, im) pairs of the gammas.  When the
+ * shifts come in conjugate pairs and the step count completes every pair,
+ * X is real up to rounding.  lradi_residual does not take complex factors.
+ * Other arguments and errors as lradi_solve. */
+int lradi_solve_complex(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* B, const double* f,
+                        const double* g, int r, const double* shiftsA_re, const double* shiftsA_im,
+                        const double* shiftsB_re, const double* shiftsB_im, int nshifts,
+                        const lradi_opts* opts, lradi_result** out);
 
 /* Algorithm 1 on nprob independent problems of uneven n, m, r advanced
  * together: every outer step of all unfinished problems runs in the same
@@ -397,8 +424,10 @@ int lradi_result_info(const lradi_result* res, int* k, int* status, double* rel_
 int lradi_result_factors(const lradi_result* res, const double** Z, const double** D,
                          const double** Y, int* n, int* m, int* r);
 /* Copy the factors to caller-owned host arrays of k*n*r, k and k*m*r
- * doubles (any may be NULL). */
+ * doubles (any may be NULL); complex results: k*2n*r, 2k and k*2m*r. */
 int lradi_result_copy(const lradi_result* res, double* Z, double* D, double* Y);
+/* 1 when the result holds complex factors (lradi_solve_complex). */
+int lradi_result_is_complex(const lradi_result* res, int* is_complex);
 /* Copy min(k, max_rows) history rows of LRADI_HIST_COLS doubles into rows
  * (host); returns the number of rows through *nrows. */
 int lradi_result_history(const lradi_result* res, double* rows, int max_rows, int* nrows);

@@ -17,6 +17,12 @@ struct AdiDesc {
   double tol, eps_in, delta_min, delta_max, xi, delta_fixed, rho;
   const double* shiftsA;  // device, nshifts
   const double* shiftsB;  // device, nshifts
+  // complex shifts (Sec. 3.2.4's complex form of the iteration): imaginary
+  // parts (device, nshifts); W, T, Zf, Yf then hold stacked blocks
+  // [re; im] of 2n (2m) rows and gam two doubles (re, im) per step
+  int cplx;
+  const double* shiftsA_im;
+  const double* shiftsB_im;
   const double* f;        // device, n x r
   const double* g;        // device, m x r
   double* W;              // residual factor w_k, n x r

@@ -118,7 +118,9 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup_gram(const SysDesc* __restri
   const AdiDesc& P = ad[c.s >> 1];
   if (!P.setup) return;
   const double* X = (c.s & 1) ? P.g : P.f;
-  LRADI_DISPATCH_R2(D.r, gram_self<RR>(X, c, lds, D.partS + (size_t)c.w * kPS));
+  RowC cm = c;  // complex systems: f, g have the matrix's rows only
+  if (D.cplx) cm.row1 = min(c.row1, D.nmat);
+  LRADI_DISPATCH_R2(D.r, gram_self<RR>(X, cm, lds, D.partS + (size_t)c.w * kPS));
 }
 
 // Arm the inner systems of problem P for outer step C.k + 1: tolerances of
@@ -145,10 +147,12 @@ __device__ inline void arm_step(const AdiDesc& P, AdiCtl& C, SysCtl& A, SysCtl& 
   C.dB = dB;
   const int js = C.k % P.nshifts;
   SysCtl* sides[2] = {&A, &B};
+  const size_t hz = P.cplx ? 2 : 1;  // stacked [re; im] blocks when complex
   for (int side = 0; side < (P.sym ? 1 : 2); ++side) {
     SysCtl& S = *sides[side];
-    S.Z = side ? P.Yf + (size_t)C.k * P.m * P.r : P.Zf + (size_t)C.k * P.n * P.r;
+    S.Z = side ? P.Yf + (size_t)C.k * hz * P.m * P.r : P.Zf + (size_t)C.k * hz * P.n * P.r;
     S.shift = side ? P.shiftsB[js] : P.shiftsA[js];
+    S.shift_im = P.cplx ? (side ? P.shiftsB_im[js] : P.shiftsA_im[js]) : 0.0;
     S.delta = side ? dB : dA;
     S.phase = PH_CYCLE_END;
     S.first = 1;
@@ -255,7 +259,46 @@ __global__ __launch_bounds__(kTPB) void k_adi_init_wt(const SysDesc* __restrict_
   double* Y = b ? P.T : P.W;
   const double sc = b ? ac[p].sg : ac[p].sf;
   const size_t e1 = (size_t)c.row1 * D.r;
-  for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) Y[e] = sc * X[e];
+  // complex systems: the imaginary half of w_0 = f (t_0 = g) is zero
+  const size_t ereal = (size_t)(D.cplx ? D.nmat : D.n) * D.r;
+  for (size_t e = (size_t)c.row0 * D.r + threadIdx.x; e < e1; e += kTPB) Y[e] = e < ereal ? sc * X[e] : 0.0;
+}
+
+// complex form: W += gamma Z (A side) or T += conj(gamma) Y (B side) on the
+// stacked blocks, local row i holding the real part at i and the imaginary
+// part at nmat + i; partial Hermitian Grams of the new factor (S at 0, K at
+// R^2) and of the new block (at 64 and 64 + R^2), S + i K = X^* X
+template <int R>
+__device__ inline void adi_update_rows_cplx(const SysDesc& D, double* Wt, const double* Zk, double gr,
+                                            double gi, const RowC& c, double* lds, double* dst) {
+  const int nm = D.nmat;
+  double gw[2 * R * R], gz[2 * R * R];
+#pragma unroll
+  for (int e = 0; e < 2 * R * R; ++e) gw[e] = gz[e] = 0.0;
+  const int i1 = min(c.row1, nm);
+  for (int i = c.row0 + threadIdx.x; i < i1; i += kTPB) {
+    double wr[R], wi[R], zr[R], zi[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      zr[q] = Zk[(size_t)i * R + q];
+      zi[q] = Zk[(size_t)(nm + i) * R + q];
+      wr[q] = Wt[(size_t)i * R + q] + (gr * zr[q] - gi * zi[q]);
+      wi[q] = Wt[(size_t)(nm + i) * R + q] + (gr * zi[q] + gi * zr[q]);
+      Wt[(size_t)i * R + q] = wr[q];
+      Wt[(size_t)(nm + i) * R + q] = wi[q];
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        gw[a * R + q] += wr[a] * wr[q] + wi[a] * wi[q];
+        gw[R * R + a * R + q] += wr[a] * wi[q] - wi[a] * wr[q];
+        gz[a * R + q] += zr[a] * zr[q] + zi[a] * zi[q];
+        gz[R * R + a * R + q] += zr[a] * zi[q] - zi[a] * zr[q];
+      }
+  }
+  bsum<2 * R * R>(gw, lds, dst);
+  bsum<2 * R * R>(gz, lds, dst + 64);
 }
 
 // generalized equation (eq. (lradi_g)): W += gamma M Z with M's rows on the
@@ -341,6 +384,13 @@ __global__ __launch_bounds__(kTPB) void k_adi_update(const SysDesc* __restrict__
   const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
   double* Wt = (c.s & 1) ? P.T : P.W;
   const double* Zk = ctl[c.s].Z;
+  if (P.cplx) {
+    // gamma = -(pA + conj(pB)); the B side adds conj(gamma) (Algorithm 1)
+    const double gi = -(P.shiftsA_im[js] - P.shiftsB_im[js]);
+    const double gis = (c.s & 1) ? -gi : gi;
+    LRADI_DISPATCH_R2(D.r, if constexpr (RR <= 4) adi_update_rows_cplx<RR>(D, Wt, Zk, gamma, gis, c, lds, D.partS + (size_t)c.w * kPS));
+    return;
+  }
   LRADI_DISPATCH_R2(D.r, adi_update_rows<RR>(D, Wt, Zk, gamma, c, lds, D.partS + (size_t)c.w * kPS));
 }
 
@@ -361,17 +411,45 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
   const SysDesc& DA = d[2 * p];
   const SysDesc& DB = d[2 * p + 1];
   const int R = P.r;
-  reduce_rows(DA.partS, DA.nwg, 0, R * R, red_lds, GW);
-  reduce_rows(DA.partS, DA.nwg, 64, R * R, red_lds, GZ);
+  // complex form: each partial holds a Hermitian Gram S + i K (S at 0, K at
+  // R^2); its real form [S -K; K S] (2R x 2R, symmetric) has the same
+  // eigenvalues twice, and the real forms multiply as the complex matrices
+  // do, so every norm below runs unchanged on the 2R x 2R real forms
+  const int PG = P.cplx ? 2 * R * R : R * R;
+  const int NE = P.cplx ? 2 * R : R;
+  reduce_rows(DA.partS, DA.nwg, 0, PG, red_lds, GW);
+  reduce_rows(DA.partS, DA.nwg, 64, PG, red_lds, GZ);
   if (P.sym) {  // t_k = w_k, y_k = z_k
-    for (int e = threadIdx.x; e < R * R; e += kTPB) {
+    for (int e = threadIdx.x; e < PG; e += kTPB) {
       GT[e] = GW[e];
       GY[e] = GZ[e];
     }
     __syncthreads();
   } else {
-    reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, GT);
-    reduce_rows(DB.partS, DB.nwg, 64, R * R, red_lds, GY);
+    reduce_rows(DB.partS, DB.nwg, 0, PG, red_lds, GT);
+    reduce_rows(DB.partS, DB.nwg, 64, PG, red_lds, GY);
+  }
+  bool finite = true;
+  for (int e = 0; e < PG; ++e)
+    finite = finite && gram_finite(GW[e]) && gram_finite(GT[e]) && gram_finite(GZ[e]) && gram_finite(GY[e]);
+  if (P.cplx) {
+    __shared__ double EW[64], EZ[64], ET[64], EY[64];
+    for (int e = threadIdx.x; e < NE * NE; e += kTPB) {
+      const int a = e / NE, b = e % NE, ha = a / R, hb = b / R, o = (a % R) * R + b % R;
+      const double sg = (ha == hb) ? 0.0 : (ha == 0 ? -1.0 : 1.0);
+      EW[e] = sg == 0.0 ? GW[o] : sg * GW[R * R + o];
+      EZ[e] = sg == 0.0 ? GZ[o] : sg * GZ[R * R + o];
+      ET[e] = sg == 0.0 ? GT[o] : sg * GT[R * R + o];
+      EY[e] = sg == 0.0 ? GY[o] : sg * GY[R * R + o];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE * NE; e += kTPB) {
+      GW[e] = EW[e];
+      GZ[e] = EZ[e];
+      GT[e] = ET[e];
+      GY[e] = EY[e];
+    }
+    __syncthreads();
   }
   // the five small eigenvalue problems run concurrently: the four Grams on
   // four 16-lane groups of the first wavefront, the product on the whole
@@ -379,10 +457,10 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
   if (threadIdx.x < 64) {
     const int g = threadIdx.x / 16, l = threadIdx.x % 16;
     const double* G = g == 0 ? GW : g == 1 ? GT : g == 2 ? GZ : GY;
-    const double v = sqrt(fmax(lambda_max_sym_lanes<16>(G, R, l, g * 16), 0.0));
+    const double v = sqrt(fmax(lambda_max_sym_lanes<16>(G, NE, l, g * 16), 0.0));
     if (l == 0) nrm[g] = v;
   } else if (threadIdx.x < 128) {
-    const double v = sqrt(fmax(lambda_max_prod_lanes<64>(GW, GT, R, threadIdx.x - 64, 0), 0.0));
+    const double v = sqrt(fmax(lambda_max_prod_lanes<64>(GW, GT, NE, threadIdx.x - 64, 0), 0.0));
     if (threadIdx.x == 64) nrm[4] = v;
   }
   __syncthreads();
@@ -390,10 +468,12 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     const int k = C.k;
     const int js = k % P.nshifts;
     const double gamma = -(P.shiftsA[js] + P.shiftsB[js]);
+    const double gamma_im = P.cplx ? -(P.shiftsA_im[js] - P.shiftsB_im[js]) : 0.0;
     const double nw = nrm[0], nt = nrm[1], nz = nrm[2], ny = nrm[3], res = nrm[4];
     const double rA = A.rnorm, rB = P.sym ? A.rnorm : B.rnorm;
     double u = C.u, v = C.v;
-    ctl_update_gap(&u, &v, gamma, nz, ny, rA, rB);
+    // eq. (upd_resgap) takes |gamma_k|, the modulus for complex shifts
+    ctl_update_gap(&u, &v, P.cplx ? hypot(gamma, gamma_im) : gamma, nz, ny, rA, rB);
     double* h = P.hist + (size_t)k * kHistCols;
     const double nfg = C.norm_fg;
     h[0] = k + 1;
@@ -412,7 +492,12 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     h[13] = ny;
     h[14] = gamma;
     h[15] = res / nfg;
-    P.gam[k] = gamma;
+    if (P.cplx) {
+      P.gam[2 * k] = gamma;
+      P.gam[2 * k + 1] = gamma_im;
+    } else {
+      P.gam[k] = gamma;
+    }
     C.u = u;
     C.v = v;
     C.nw = nw;
@@ -420,9 +505,6 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     C.res = res;
     C.k = k + 1;
     if (A.status == IS_CAP || B.status == IS_CAP) C.winner = 1;
-    bool finite = true;
-    for (int e = 0; e < R * R; ++e)
-      finite = finite && gram_finite(GW[e]) && gram_finite(GT[e]) && gram_finite(GZ[e]) && gram_finite(GY[e]);
     const bool bad = !finite || !(res == res) || res - res != 0.0 || A.status == IS_NAN || B.status == IS_NAN;
     if (bad) {
       C.status = LRADI_ENAN;

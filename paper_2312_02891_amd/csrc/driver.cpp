@@ -239,6 +239,7 @@ struct lradi_result {
   int status = LRADI_OK;
   double rel_res = 0.0, norm_fg = 0.0, seconds = 0.0;
   bool sym = false;  // Lyapunov case: Y is Z (Yf unallocated)
+  bool cplx = false; // complex shifts: stacked [re; im] factor blocks, gam (re, im) pairs
   DevBuf Zf, Yf;
   std::vector<double> gam, hist;
   const DevBuf& Y() const { return sym ? Zf : Yf; }
@@ -327,13 +328,17 @@ struct SysWork {
   SysCtl c{};  // host copy of the control block, valid at drain points
 
   // sweeps < 0: no preconditioner; else A must carry the red-black data
+  // cplx: the real form of a complex shifted system on 2 A->n rows (r <= 4,
+  // no preconditioner)
   int init(const DevCSR* A, const double* W, int r, int m, int prec, int max_inner, double floor_rel,
-           int sweeps = -1, bool pairs = false) {
+           int sweeps = -1, bool pairs = false, bool cplx = false) {
     if (r < 1 || r > kMaxR || m < 1 || m > kMaxM)
       return set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM), LRADI_EINVAL;
     // a block of more columns than rows has no full-rank basis
     if (r > A->n) return set_error("r (%d) exceeds the system size (%d)", r, A->n), LRADI_EINVAL;
-    const size_t n = A->n, rr = r, mm = m;
+    if (cplx && (r > 4 || sweeps >= 0 || A->has_mass()))
+      return set_error("complex shifts need r <= 4, M = C = I and no preconditioner"), LRADI_EINVAL;
+    const size_t n = (cplx ? 2 : 1) * (size_t)A->n, rr = r, mm = m;
     const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
     const int rpw = choose_rows_per_wg((int)n);
     const int nwg = (int)((n + rpw - 1) / rpw);
@@ -369,6 +374,8 @@ struct SysWork {
     };
     d = SysDesc{};
     d.n = (int)n;
+    d.cplx = cplx ? 1 : 0;
+    d.nmat = A->n;
     d.r = r;
     d.m = m;
     d.nwg = nwg;
@@ -444,6 +451,7 @@ struct SysWork {
   void init_mirror(const SysWork& a) {
     d = SysDesc{};
     d.n = a.d.n;
+    d.nmat = a.d.nmat;
     d.r = a.d.r;
     d.m = a.d.m;
     d.nwg = 0;
@@ -551,7 +559,8 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       if (ws[s]->d.spmm_lanes != lanes || ws[s]->d.nwg == 0) continue;
       if (ws[s]->d.r % lanes != 0) return set_error("lanes per row must divide r"), LRADI_EINVAL;
       const int tr = spmm_tile_rows(lanes);
-      const int tiles = (ws[s]->d.n + tr - 1) / tr;
+      // (complex systems: the tiles of each half of the stacked block)
+      const int tiles = ws[s]->d.cplx ? 2 * ((ws[s]->d.nmat + tr - 1) / tr) : (ws[s]->d.n + tr - 1) / tr;
       for (int w = 0; w < tiles; ++w) t.hsp.push_back(make_int2(s, w));
     }
     t.b.spcount[g] = (int)t.hsp.size() - t.b.spoff[g];
@@ -1001,8 +1010,9 @@ struct Prob {
   const double* g = nullptr;
   int n = 0, m = 0, r = 0, nshifts = 0;
   double tol = 0.0;
-  DevBuf shA, shB, W, T, gam, hist;
+  DevBuf shA, shB, shAi, shBi, W, T, gam, hist;
   SysWork wa, wb;
+  bool cplx = false;  // complex shifts (imaginary parts in shAi, shBi)
   PinnedInt done;
   std::unique_ptr<lradi_result> res;
   AdiCtl hc{};
@@ -1029,6 +1039,18 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   for (int i = 0; i < P.nshifts; ++i)
     if (!std::isfinite(P.shiftsA[i]) || !std::isfinite(P.shiftsB[i]))
       return set_error("problem: non-finite shift"), LRADI_EINVAL;
+  q.cplx = P.shiftsA_im != nullptr || P.shiftsB_im != nullptr;
+  if (q.cplx) {
+    if (!P.shiftsA_im || !P.shiftsB_im)
+      return set_error("problem: complex shifts need both imaginary parts"), LRADI_EINVAL;
+    for (int i = 0; i < P.nshifts; ++i)
+      if (!std::isfinite(P.shiftsA_im[i]) || !std::isfinite(P.shiftsB_im[i]))
+        return set_error("problem: non-finite shift"), LRADI_EINVAL;
+    if (q.sym || P.M || P.C || P.r > 4 || sweeps_for(o) >= 0)
+      return set_error("problem: complex shifts need r <= 4, M = C = I, no Lyapunov mirror and no "
+                       "preconditioner"),
+             LRADI_EINVAL;
+  }
   const double tol = (P.tol > 0.0) ? P.tol : o.tol;
   if (!(tol > 0.0 && tol < 1.0)) return set_error("problem: tol must be in (0,1)"), LRADI_EINVAL;
   q.t0 = std::chrono::steady_clock::now();
@@ -1110,25 +1132,33 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   q.res->r = q.r;
   q.res->kmax = o.kmax;
   q.res->sym = q.sym;
-  LRADI_TRY(q.res->Zf.alloc(sizeof(double) * K * n * r));
-  if (!q.sym) LRADI_TRY(q.res->Yf.alloc(sizeof(double) * K * m * r));
-  LRADI_TRY(q.W.alloc(sizeof(double) * n * r));
-  if (!q.sym) LRADI_TRY(q.T.alloc(sizeof(double) * m * r));
+  q.res->cplx = q.cplx;
+  const size_t hz = q.cplx ? 2 : 1;  // stacked [re; im] blocks when complex
+  LRADI_TRY(q.res->Zf.alloc(sizeof(double) * K * hz * n * r));
+  if (!q.sym) LRADI_TRY(q.res->Yf.alloc(sizeof(double) * K * hz * m * r));
+  LRADI_TRY(q.W.alloc(sizeof(double) * hz * n * r));
+  if (!q.sym) LRADI_TRY(q.T.alloc(sizeof(double) * hz * m * r));
   LRADI_TRY(q.shA.alloc(sizeof(double) * P.nshifts));
   LRADI_TRY(q.shB.alloc(sizeof(double) * P.nshifts));
-  LRADI_TRY(q.gam.alloc(sizeof(double) * K));
+  if (q.cplx) {
+    LRADI_TRY(q.shAi.alloc(sizeof(double) * P.nshifts));
+    LRADI_TRY(q.shBi.alloc(sizeof(double) * P.nshifts));
+    LRADI_HIP(hipMemcpyAsync(q.shAi.p, P.shiftsA_im, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
+    LRADI_HIP(hipMemcpyAsync(q.shBi.p, P.shiftsB_im, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
+  }
+  LRADI_TRY(q.gam.alloc(sizeof(double) * K * hz));
   LRADI_TRY(q.hist.alloc(sizeof(double) * K * kHistCols));
   LRADI_HIP(hipMemcpyAsync(q.shA.p, P.shiftsA, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   const double fl = floor_for(o);
   LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw,
-                      o.precond_pairs != 0));
+                      o.precond_pairs != 0, q.cplx));
   LRADI_TRY(q.wa.tune(c, q.A, o.spmm_lanes));
   if (q.sym) {
     q.wb.init_mirror(q.wa);
   } else {
     LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw,
-                        o.precond_pairs != 0));
+                        o.precond_pairs != 0, q.cplx));
     LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
   }
   LRADI_TRY(q.done.init());
@@ -1217,6 +1247,9 @@ struct Engine {
       ad.rho = o.rho;
       ad.shiftsA = q->shA.as<double>();
       ad.shiftsB = q->shB.as<double>();
+      ad.cplx = q->cplx ? 1 : 0;
+      ad.shiftsA_im = q->cplx ? q->shAi.as<double>() : nullptr;
+      ad.shiftsB_im = q->cplx ? q->shBi.as<double>() : nullptr;
       ad.f = q->f;
       ad.g = q->g;
       ad.W = q->W.as<double>();
@@ -1244,10 +1277,11 @@ struct Engine {
     R->k = h.k;
     R->norm_fg = h.norm_fg;
     R->rel_res = h.norm_fg > 0.0 ? h.res / h.norm_fg : 0.0;
-    R->gam.assign(std::max(h.k, 0), 0.0);
+    const size_t ng = (size_t)std::max(h.k, 0) * (q->cplx ? 2 : 1);
+    R->gam.assign(ng, 0.0);
     R->hist.assign((size_t)std::max(h.k, 0) * kHistCols, 0.0);
     if (h.k > 0) {
-      LRADI_HIP(hipMemcpy(R->gam.data(), q->gam.p, sizeof(double) * h.k, hipMemcpyDeviceToHost));
+      LRADI_HIP(hipMemcpy(R->gam.data(), q->gam.p, sizeof(double) * ng, hipMemcpyDeviceToHost));
       LRADI_HIP(hipMemcpy(R->hist.data(), q->hist.p, sizeof(double) * h.k * kHistCols, hipMemcpyDeviceToHost));
     }
     int status = h.status;
@@ -1541,6 +1575,26 @@ int lradi_solve_lyap(lradi_ctx* c, const lradi_csr* A, const lradi_csr* M, const
   return lradi_batch_solve(c, 1, &P, opts, out);
 }
 
+int lradi_solve_complex(lradi_ctx* c, const lradi_csr* A, const lradi_csr* B, const double* f,
+                        const double* g, int r, const double* shiftsA_re, const double* shiftsA_im,
+                        const double* shiftsB_re, const double* shiftsB_im, int nshifts,
+                        const lradi_opts* opts, lradi_result** out) {
+  if (!out) return set_error("lradi_solve_complex: null output"), LRADI_EINVAL;
+  if (!shiftsA_im || !shiftsB_im) return set_error("lradi_solve_complex: null imaginary parts"), LRADI_EINVAL;
+  lradi_problem P{};
+  P.A = A;
+  P.B = B;
+  P.f = f;
+  P.g = g;
+  P.r = r;
+  P.nshifts = nshifts;
+  P.shiftsA = shiftsA_re;
+  P.shiftsB = shiftsB_re;
+  P.shiftsA_im = shiftsA_im;
+  P.shiftsB_im = shiftsB_im;
+  return lradi_batch_solve(c, 1, &P, opts, out);
+}
+
 int lradi_batch_solve(lradi_ctx* c, int nprob, const lradi_problem* probs, const lradi_opts* opts,
                       lradi_result** outs) {
   if (!c || nprob < 1 || !probs || !outs) return set_error("lradi_batch_solve: bad argument"), LRADI_EINVAL;
@@ -1621,11 +1675,18 @@ int lradi_result_factors(const lradi_result* r, const double** Z, const double**
 
 int lradi_result_copy(const lradi_result* r, double* Z, double* D, double* Y) {
   if (!r) return set_error("null result"), LRADI_EINVAL;
+  const size_t hz = r->cplx ? 2 : 1;
   if (Z && r->k > 0)
-    LRADI_HIP(hipMemcpy(Z, r->Zf.p, sizeof(double) * (size_t)r->k * r->n * r->r, hipMemcpyDeviceToHost));
+    LRADI_HIP(hipMemcpy(Z, r->Zf.p, sizeof(double) * (size_t)r->k * hz * r->n * r->r, hipMemcpyDeviceToHost));
   if (Y && r->k > 0)
-    LRADI_HIP(hipMemcpy(Y, r->Y().p, sizeof(double) * (size_t)r->k * r->m * r->r, hipMemcpyDeviceToHost));
-  if (D) std::copy(r->gam.begin(), r->gam.begin() + r->k, D);
+    LRADI_HIP(hipMemcpy(Y, r->Y().p, sizeof(double) * (size_t)r->k * hz * r->m * r->r, hipMemcpyDeviceToHost));
+  if (D) std::copy(r->gam.begin(), r->gam.begin() + (size_t)r->k * hz, D);
+  return LRADI_OK;
+}
+
+int lradi_result_is_complex(const lradi_result* r, int* is_complex) {
+  if (!r || !is_complex) return set_error("null argument"), LRADI_EINVAL;
+  *is_complex = r->cplx ? 1 : 0;
   return LRADI_OK;
 }
 
@@ -1761,7 +1822,7 @@ struct lradi_server {
   struct Pending {
     uint64_t ticket;
     std::vector<int32_t> arp, aci, brp, bci, mrp, mci, crp, cci;
-    std::vector<double> aval, bval, mval, cval, f, g, sA, sB;
+    std::vector<double> aval, bval, mval, cval, f, g, sA, sB, sAi, sBi;
     bool hasM = false, hasC = false, lyap = false;
     int r = 0, n = 0, m = 0;
     double tol = 0.0;
@@ -1850,7 +1911,8 @@ void lradi_server::run() {
       lradi_csr Cc{P.m, P.m, (int64_t)P.cci.size(), P.crp.data(), P.cci.data(), P.cval.data(), 0};
       lradi_problem pr{&A, &B, fd.as<double>(), gd.as<double>(), P.r, (int32_t)P.sA.size(), P.sA.data(),
                        P.sB.data(), P.tol, P.hasM ? &Mc : nullptr, P.hasC ? &Cc : nullptr,
-                       P.lyap ? 1 : 0};
+                       P.lyap ? 1 : 0, P.sAi.empty() ? nullptr : P.sAi.data(),
+                       P.sBi.empty() ? nullptr : P.sBi.data()};
       if (rc == LRADI_OK) rc = prob_init(ctx, opts, pr, true, *q);
       Prob* raw = q.get();
       live[raw] = Live{std::move(q), P.ticket, P.footprint};
@@ -1985,9 +2047,14 @@ int lradi_server_submit(lradi_server* s, const lradi_problem* P, uint64_t* ticke
   }
   q.sA.assign(P->shiftsA, P->shiftsA + P->nshifts);
   q.sB.assign(lyap ? P->shiftsA : P->shiftsB, (lyap ? P->shiftsA : P->shiftsB) + P->nshifts);
+  if (P->shiftsA_im) q.sAi.assign(P->shiftsA_im, P->shiftsA_im + P->nshifts);
+  if (P->shiftsB_im) q.sBi.assign(P->shiftsB_im, P->shiftsB_im + P->nshifts);
+  const bool cplx = P->shiftsA_im || P->shiftsB_im;
   // (a mass matrix adds its values on the union pattern: counted as extra
   // nonzeros of the operator)
-  q.footprint = prob_footprint(q.n, q.m, q.r, (int64_t)(q.aci.size() + 2 * q.mci.size()),
+  // (complex problems hold stacked blocks of twice the rows)
+  q.footprint = prob_footprint((cplx ? 2 : 1) * q.n, (cplx ? 2 : 1) * q.m, q.r,
+                               (int64_t)(q.aci.size() + 2 * q.mci.size()),
                                (int64_t)(q.bci.size() + 2 * q.cci.size()), s->opts, lyap);
   if ((int64_t)q.footprint > s->budget)
     return set_error("lradi_server_submit: footprint %zu bytes exceeds the budget", q.footprint), LRADI_ENOMEM;

@@ -211,12 +211,20 @@ struct SysDesc {
   const int* halo_ci;   // the halo rows' T columns, slot-major over halo entries
   int nhalo;            // total halo entries
   int pair_lds;         // bytes of the largest region's iterate; 0: no pairs
+  // complex shift (s + i s_im, Sec. 3.2.4's complex form): the system is the
+  // real form of (A + (s + i s_im) I)(z_re + i z_im) = w_re + i w_im on the
+  // stacked block [re; im] of n = 2 nmat rows,
+  //   [A + s I, -s_im I; s_im I, A + s I] [z_re; z_im] = [w_re; w_im],
+  // and ||.||_2 of a residual is the complex block's spectral norm
+  int cplx;             // 1: complex system (r <= 4, no preconditioner)
+  int nmat;             // rows of A (n / 2 when complex, else n)
 };
 
 // Mutable device-side control block of one inner solve.
 struct SysCtl {
   double* Z;    // solution block, n x r (set per solve)
   double shift; // the system is (A + shift I) Z = W
+  double shift_im;  // complex systems: imaginary part of the shift
   int phase;
   int j;        // Arnoldi step index inside the cycle (basis blocks V_0..V_j exist)
   int ncols;    // block columns of the current least-squares problem

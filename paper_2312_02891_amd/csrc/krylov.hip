@@ -146,10 +146,13 @@ struct SpmmUnroll {
 // mv (nullable): the mass values on the same pattern, the coefficient then
 // is val + shift mv; diag: add shift x_i (M = I); neither when the staged
 // values already hold val + shift mv
+// Xc (nullable): complex systems' other half of the stacked block, added
+// with coefficient cs (the imaginary shift's coupling, -s_im for the real
+// rows and +s_im for the imaginary ones)
 template <typename T, int R, int RC, int SU>
 __device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, const T* val, const T* mv,
                                 bool diag, int off, T shift, const T* __restrict__ X,
-                                T* __restrict__ Y) {
+                                T* __restrict__ Y, const T* __restrict__ Xc = nullptr, T cs = T(0)) {
   T acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = T(0);
@@ -176,7 +179,12 @@ __device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, co
       for (int q = 0; q < RC; ++q) acc[q] += a[u] * xv[u][q];
   }
   T* y = Y + (size_t)i * R + q0;
-  if (diag) {
+  if (Xc) {
+    const T* xi = X + (size_t)i * R + q0;
+    const T* xc = Xc + (size_t)i * R + q0;
+#pragma unroll
+    for (int q = 0; q < RC; ++q) y[q] = (acc[q] + shift * xi[q]) + cs * xc[q];
+  } else if (diag) {
     const T* xi = X + (size_t)i * R + q0;
 #pragma unroll
     for (int q = 0; q < RC; ++q) y[q] = acc[q] + shift * xi[q];
@@ -190,7 +198,7 @@ template <typename T, int R, int RL>
 __device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                  const T* __restrict__ val, const T* __restrict__ mval, T shift,
                                  const T* __restrict__ X, T* __restrict__ Y, int r0, int* s_ci,
-                                 T* s_val) {
+                                 T* s_val, const T* __restrict__ Xc = nullptr, T cs = T(0)) {
   constexpr int RC = R / RL;
   constexpr int SU = SpmmUnroll<T>::v;
   constexpr int PER = kSpmmCap / kTPB;
@@ -229,9 +237,9 @@ __device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* _
   const int q0 = ((int)threadIdx.x % RL) * RC;
   const bool diag = mval == nullptr;
   if (staged)
-    spmm_row<T, R, RC, SU>(i, q0, k0, k1, s_ci, s_val, nullptr, diag, base, shift, X, Y);
+    spmm_row<T, R, RC, SU>(i, q0, k0, k1, s_ci, s_val, nullptr, diag, base, shift, X, Y, Xc, cs);
   else
-    spmm_row<T, R, RC, SU>(i, q0, k0, k1, ci, val, mval, diag, 0, shift, X, Y);
+    spmm_row<T, R, RC, SU>(i, q0, k0, k1, ci, val, mval, diag, 0, shift, X, Y, Xc, cs);
 }
 
 // RL lanes per row; the kernel for group RL serves the systems whose tiling
@@ -246,11 +254,17 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
   const int2 e = spmap[blockIdx.x];
   const SysDesc& D = d[e.x];
   const int ph = ctl[e.x].phase;
-  const int r0 = e.y * spmm_tile_rows(RL);
+  // complex systems: the tiles of each half of the stacked block apart
+  // (tile e.y of th per half), local rows r0.. of A in that half
+  const int tr = spmm_tile_rows(RL);
+  const int th = D.cplx ? (D.nmat + tr - 1) / tr : 0;
+  const int half = (D.cplx && e.y >= th) ? 1 : 0;
+  const int r0 = (e.y - half * th) * tr;
+  const size_t hoff = (size_t)half * D.nmat * D.r;
   T* U = static_cast<T*>(D.U);
   if (ph == PH_RESTART) {
-    const size_t e1 = (size_t)min(D.n, r0 + spmm_tile_rows(RL)) * D.r;
-    for (size_t q = (size_t)r0 * D.r + threadIdx.x; q < e1; q += kTPB) U[q] = (T)D.R[q];
+    const size_t e1 = hoff + (size_t)min(D.cplx ? D.nmat : D.n, r0 + tr) * D.r;
+    for (size_t q = hoff + (size_t)r0 * D.r + threadIdx.x; q < e1; q += kTPB) U[q] = (T)D.R[q];
     return;
   }
   if (ph != PH_ARNOLDI) return;
@@ -259,12 +273,20 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
   const T sh = (T)ctl[e.x].shift;
   if (prof && e.y == 0 && threadIdx.x == 0) {
     // values + column indices + row pointers + input block + output block
-    const unsigned long long bytes = (unsigned long long)D.nnz * (sizeof(T) + 4) +
-                                     4ull * (D.n + 1) + 2ull * sizeof(T) * D.n * D.r;
+    // (a complex system reads A once per half)
+    const unsigned long long halves = D.cplx ? 2 : 1;
+    const unsigned long long bytes = halves * ((unsigned long long)D.nnz * (sizeof(T) + 4) +
+                                               4ull * (D.nmat + 1)) + 2ull * sizeof(T) * D.n * D.r;
     atomicAdd(prof + LRADI_PROF_SPMM, bytes);
   }
   const T* val = static_cast<const T*>(D.valT);
   const T* mval = static_cast<const T*>(D.mvalT);
+  if (D.cplx) {
+    const T si = (T)ctl[e.x].shift_im;
+    const T* Xc = Vj + (size_t)(1 - half) * D.nmat * D.r;
+    LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.nmat, D.rowptr, D.colind, val, nullptr, sh, Vj + hoff, U + hoff, r0, s_ci, s_val, Xc, half ? si : -si));
+    return;
+  }
   LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.n, D.rowptr, D.colind, val, mval, sh, Vj, U, r0, s_ci, s_val));
 }
 
@@ -1471,6 +1493,75 @@ __device__ inline void resid_rows(const SysDesc& D, const RowCtx& c, double shif
   block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
 }
 
+// complex systems: local row i < nmat gives both halves of the stacked
+// residual, R_re = W_re - ((A + s) Z_re - s_im Z_im), R_im = W_im - ((A + s)
+// Z_im + s_im Z_re), and the partials of the complex Gram R^* R: its real
+// part S = R_re^T R_re + R_im^T R_im at [0, R^2), its imaginary part
+// K = R_re^T R_im - R_im^T R_re at [R^2, 2 R^2)
+template <int R>
+__device__ inline void resid_rows_cplx(const SysDesc& D, const RowCtx& c, double shift, double shift_im,
+                                       double* Z, bool first, double* lds) {
+  const double* __restrict__ val = D.val64;
+  const int* __restrict__ rp = D.rowptr;
+  const int* __restrict__ ci = D.colind;
+  const int nm = D.nmat;
+  double g2[2 * R * R];
+#pragma unroll
+  for (int e = 0; e < 2 * R * R; ++e) g2[e] = 0.0;
+  const int i1 = min(c.row1, nm);
+  for (int i = c.row0 + threadIdx.x; i < i1; i += kTPB) {
+    double re[R], im[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      re[q] = D.W[(size_t)i * R + q];
+      im[q] = D.W[(size_t)(nm + i) * R + q];
+    }
+    if (first) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        Z[(size_t)i * R + q] = 0.0;
+        Z[(size_t)(nm + i) * R + q] = 0.0;
+      }
+    } else {
+      const double* Zr = Z;
+      const double* Zi = Z + (size_t)nm * R;
+      double ar[R], ai[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        ar[q] = shift * Zr[(size_t)i * R + q] - shift_im * Zi[(size_t)i * R + q];
+        ai[q] = shift * Zi[(size_t)i * R + q] + shift_im * Zr[(size_t)i * R + q];
+      }
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int col = ci[k];
+        const double a = val[k];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          ar[q] += a * Zr[(size_t)col * R + q];
+          ai[q] += a * Zi[(size_t)col * R + q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        re[q] -= ar[q];
+        im[q] -= ai[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      D.R[(size_t)i * R + q] = re[q];
+      D.R[(size_t)(nm + i) * R + q] = im[q];
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        g2[a * R + q] += re[a] * re[q] + im[a] * im[q];
+        g2[R * R + a * R + q] += re[a] * im[q] - im[a] * re[q];
+      }
+  }
+  block_sum_store<2 * R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+}
+
 template <int RF>
 __global__ __launch_bounds__(kTPB) void k_resid(const SysDesc* __restrict__ d,
                                                 const SysCtl* __restrict__ ctl,
@@ -1479,6 +1570,10 @@ __global__ __launch_bounds__(kTPB) void k_resid(const SysDesc* __restrict__ d,
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   if (ctl[c.s].phase != PH_CYCLE_END) return;
+  if (D.cplx) {
+    LRADI_RSEL(RF, D.r, if constexpr (RR <= 4) resid_rows_cplx<RR>(D, c, ctl[c.s].shift, ctl[c.s].shift_im, ctl[c.s].Z, ctl[c.s].first != 0, lds));
+    return;
+  }
   LRADI_RSEL(RF, D.r, resid_rows<RR>(D, c, ctl[c.s].shift, ctl[c.s].Z, ctl[c.s].first != 0, lds));
 }
 
@@ -1491,13 +1586,30 @@ __global__ __launch_bounds__(kTPB) void k_decide(const SysDesc* __restrict__ d, 
   SysCtl& C = ctl[s];
   if (C.phase != PH_CYCLE_END) return;
   const int R = D.r;
-  reduce_partS(D, R * R, red_lds, G);
+  // complex systems: the Hermitian Gram S + i K of the complex residual;
+  // its eigenvalues are those of the real symmetric [S -K; K S] (each
+  // twice), so the same routine on 2R x 2R gives ||R||_2^2
+  const int P = D.cplx ? 2 * R * R : R * R;
+  __shared__ double E[64];
+  reduce_partS(D, P, red_lds, G);
   bool bad = false;
-  for (int e = 0; e < R * R; ++e)
+  for (int e = 0; e < P; ++e)
     if (!(G[e] == G[e]) || G[e] - G[e] != 0.0) bad = true;
+  const double* M = G;
+  int NE = R;
+  if (D.cplx) {
+    NE = 2 * R;
+    for (int e = threadIdx.x; e < NE * NE; e += kTPB) {
+      const int a = e / NE, b = e % NE, ha = a / R, hb = b / R, aa = a % R, bb = b % R;
+      const double sv = G[aa * R + bb], kv = G[R * R + aa * R + bb];
+      E[e] = (ha == hb) ? sv : (ha == 0 ? -kv : kv);
+    }
+    __syncthreads();
+    M = E;
+  }
   // ||R||_2^2 on the first wavefront's 64 lanes (multisection)
   double lm = 0.0;
-  if (!bad && threadIdx.x < 64) lm = lambda_max_sym_lanes<64>(G, R, threadIdx.x, 0);
+  if (!bad && threadIdx.x < 64) lm = lambda_max_sym_lanes<64>(M, NE, threadIdx.x, 0);
   if (threadIdx.x == 0) {
     if (bad) {
       C.status = IS_NAN;

@@ -63,7 +63,9 @@ class Problem(ctypes.Structure):
                 ("shiftsA", ctypes.POINTER(ctypes.c_double)),
                 ("shiftsB", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
                 ("M", ctypes.POINTER(Csr)), ("C", ctypes.POINTER(Csr)),
-                ("lyapunov", ctypes.c_int32)]
+                ("lyapunov", ctypes.c_int32),
+                ("shiftsA_im", ctypes.POINTER(ctypes.c_double)),
+                ("shiftsB_im", ctypes.POINTER(ctypes.c_double))]
 
 
 class ServerCounters(ctypes.Structure):
@@ -117,6 +119,9 @@ def _load():
         "lradi_solve_gen": (i32, [vp, P(Csr), P(Csr), P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), i32,
                                   P(Opts), P(vp)]),
         "lradi_solve_lyap": (i32, [vp, P(Csr), P(Csr), vp, i32, P(dbl), i32, P(Opts), P(vp)]),
+        "lradi_solve_complex": (i32, [vp, P(Csr), P(Csr), vp, vp, i32, P(dbl), P(dbl), P(dbl), P(dbl), i32,
+                                      P(Opts), P(vp)]),
+        "lradi_result_is_complex": (i32, [vp, P(i32)]),
         "lradi_server_create": (i32, [vp, P(Opts), ctypes.c_int64, i32, P(vp)]),
         "lradi_server_submit": (i32, [vp, P(Problem), P(ctypes.c_uint64)]),
         "lradi_server_poll": (i32, [vp, ctypes.c_uint64, P(vp), P(dbl)]),
@@ -264,10 +269,25 @@ class Result:
         sec = ctypes.c_double()
         _check(_lib.lradi_result_time(self.h, ctypes.byref(sec)))
         self.seconds = sec.value
+        cx = ctypes.c_int()
+        _check(_lib.lradi_result_is_complex(self.h, ctypes.byref(cx)))
+        self.is_complex = bool(cx.value)
 
     def factors(self):
-        """(Z n x kr, d kr, Y m x kr) as host numpy arrays (blocks side by side)."""
+        """(Z n x kr, d kr, Y m x kr) as host numpy arrays (blocks side by
+        side); complex arrays for complex results."""
         k, n, m, r = self.k, self.n, self.m, self.r
+        if self.is_complex:
+            Z = np.empty((k, 2 * n, r))
+            Y = np.empty((k, 2 * m, r))
+            D = np.empty(2 * max(k, 1))
+            _check(_lib.lradi_result_copy(self.h, Z.ctypes.data, D.ctypes.data, Y.ctypes.data))
+            Zc = Z[:, :n, :] + 1j * Z[:, n:, :]
+            Yc = Y[:, :m, :] + 1j * Y[:, m:, :]
+            Zc = np.concatenate([Zc[i] for i in range(k)], axis=1) if k else np.zeros((n, 0), complex)
+            Yc = np.concatenate([Yc[i] for i in range(k)], axis=1) if k else np.zeros((m, 0), complex)
+            d = np.repeat(D[0:2 * k:2] + 1j * D[1:2 * k:2], r)
+            return Zc, d, Yc
         Z = np.empty((k, n, r))
         Y = np.empty((k, m, r))
         D = np.empty(max(k, 1))
@@ -278,6 +298,10 @@ class Result:
         return Zc, d, Yc
 
     def gammas(self):
+        if self.is_complex:
+            D = np.empty(2 * max(self.k, 1))
+            _check(_lib.lradi_result_copy(self.h, None, D.ctypes.data, None))
+            return D[0:2 * self.k:2] + 1j * D[1:2 * self.k:2]
         D = np.empty(max(self.k, 1))
         _check(_lib.lradi_result_copy(self.h, None, D.ctypes.data, None))
         return D[: self.k]
@@ -405,8 +429,12 @@ class Context:
         (HostCsr or None) give the generalized equation.  lyapunov=True: the
         case A X M^T + M X A^T = -f f^T, where B, g, shiftsB, C are not used
         (may be None)."""
-        sA = np.ascontiguousarray(shiftsA, dtype=np.float64)
-        sB = sA if lyapunov else np.ascontiguousarray(shiftsB, dtype=np.float64)
+        cx = np.iscomplexobj(shiftsA) or (shiftsB is not None and np.iscomplexobj(shiftsB))
+        sA = np.ascontiguousarray(np.real(shiftsA), dtype=np.float64)
+        sB = sA if lyapunov else np.ascontiguousarray(np.real(shiftsB), dtype=np.float64)
+        sAi = np.ascontiguousarray(np.imag(shiftsA), dtype=np.float64) if cx else None
+        sBi = np.ascontiguousarray(np.imag(shiftsB), dtype=np.float64) if cx else None
+        dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None  # noqa: E731
         assert f.is_cuda and f.is_contiguous()
         if not lyapunov:
             assert g.is_cuda and g.is_contiguous()
@@ -415,8 +443,9 @@ class Context:
                      len(sA), sA.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                      sB.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tol),
                      ctypes.pointer(M.c) if M is not None else None,
-                     ctypes.pointer(C.c) if C is not None else None, 1 if lyapunov else 0)
-        return pr, [A, B, f, g, sA, sB, M, C]
+                     ctypes.pointer(C.c) if C is not None else None, 1 if lyapunov else 0,
+                     dp(sAi), dp(sBi))
+        return pr, [A, B, f, g, sA, sB, M, C, sAi, sBi]
 
     @staticmethod
     def lyap_problem(A: HostCsr, f, shifts, tol=0.0, M=None):
@@ -529,6 +558,22 @@ class Context:
                                              ctypes.byref(h)))
         res = Result(h.value, st)
         return res
+
+    def solve_complex(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, opts: Optional[Opts] = None):
+        """Algorithm 1 with complex shifts (complex arrays pA added to A, pB
+        added to B^T) in its complex form; the result's factors are complex."""
+        assert f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()
+        a = np.asarray(shiftsA, dtype=np.complex128)
+        b = np.asarray(shiftsB, dtype=np.complex128)
+        arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a.real, a.imag, b.real, b.imag)]
+        ptr = [x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for x in arr]
+        h = ctypes.c_void_p()
+        self._sync()
+        st = _check(_lib.lradi_solve_complex(self.h, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(f), _ptr(g),
+                                             f.shape[1], ptr[0], ptr[1], ptr[2], ptr[3], len(a),
+                                             ctypes.byref(opts) if opts is not None else None,
+                                             ctypes.byref(h)))
+        return Result(h.value, st)
 
     def solve_lyap(self, A: HostCsr, f, shifts, opts: Optional[Opts] = None, M: Optional[HostCsr] = None):
         """Lyapunov case A X M^T + M X A^T = -f f^T (M = I unless given): one
