@@ -621,7 +621,8 @@ int probe_account(lradi_ctx* ctx, const TickProbe& p, const Batch& bt) {
   ctx->prof_ms[LRADI_PROF_GRAM] += (double)a + (double)b;
   ctx->prof_launches[LRADI_PROF_GRAM] += 2;
   ctx->prof_ms[LRADI_PROF_SPMM] += (double)c;
-  ctx->prof_launches[LRADI_PROF_SPMM] += 1;
+  // one launch per tiling group that has tiles (lanes per row 1, 2, 4)
+  ctx->prof_launches[LRADI_PROF_SPMM] += (bt.spcount[0] > 0) + (bt.spcount[1] > 0) + (bt.spcount[2] > 0);
   if (bt.precond) {
     LRADI_HIP(hipEventElapsedTime(&e, p.ev[6], p.ev[7]));
     ctx->prof_ms[LRADI_PROF_PRECOND] += (double)e;

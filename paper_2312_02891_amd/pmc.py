@@ -116,7 +116,8 @@ def main(argv=None):
     s.add_argument("--calib-fetch", required=True)
     s.add_argument("--calib-write", required=True)
     s.add_argument("--kernel", required=True)
-    s.add_argument("--calib-kernel", default="copyBuffer|elementwise|copy")
+    # the copies only: the fill that creates the source buffer reads nothing
+    s.add_argument("--calib-kernel", default="copyBuffer")
     s.add_argument("--mib", type=int, default=512)
     s.add_argument("--source", nargs="*", default=[])
     s.add_argument("--json", default=None)
