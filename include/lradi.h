@@ -246,8 +246,10 @@ int lradi_spmm(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X,
 /* Measurement helper for the shifted product: copies A to the device once,
  * then launches the product Y = (A + shift I) X reps times back to back and
  * returns the average launch time in milliseconds (HIP events on the
- * context's stream) and the algorithmic bytes of one launch (values,
- * column indices, row pointers, X read once, Y written once).  lanes: the
+ * context's stream) and the algorithmic bytes of one launch (each nonzero's
+ * value and column index once, X read once, Y written once; the row
+ * structure, O(n / 32) slice starts in the product's layout, is not
+ * counted).  lanes: the
  * tiling (1, 2, 4 lanes per row, dividing r), or 0 for the one the solver
  * would pick (lradi_spmm_tune). */
 int lradi_spmm_bench(lradi_ctx* ctx, const lradi_csr* A, double shift, const void* X, void* Y,

@@ -107,6 +107,29 @@ __global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, int64
   if (i < n) b[i] = (float)a[i];
 }
 
+// one thread per (padded) row: its slots of the slice's blocks, padding
+// (own row, 0); mval null: no mass values
+template <typename T>
+__global__ void k_sell_fill(int n, int nsl, const int* __restrict__ rp, const int* __restrict__ sslot,
+                            const int* __restrict__ ci, const double* __restrict__ val,
+                            const double* __restrict__ mval, unsigned char* __restrict__ blk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nsl * kSellH) return;
+  const int i = (int)t, s = i / kSellH, l = i % kSellH;
+  const int k0 = i < n ? rp[i] : 0;
+  const int len = i < n ? rp[i + 1] - k0 : 0;
+  const int sb = sell_block_bytes((int)sizeof(T), mval != nullptr);
+  unsigned char* base = blk + (size_t)sslot[s] * sb;
+  const int w = sslot[s + 1] - sslot[s];
+  for (int u = 0; u < w; ++u) {
+    unsigned char* b = base + (size_t)u * sb;
+    const bool in = u < len;
+    reinterpret_cast<int*>(b)[l] = in ? ci[k0 + u] : (i < n ? i : n - 1);
+    reinterpret_cast<T*>(b + kSellH * 4)[l] = in ? (T)val[k0 + u] : T(0);
+    if (mval) reinterpret_cast<T*>(b + kSellH * (4 + sizeof(T)))[l] = in ? (T)mval[k0 + u] : T(0);
+  }
+}
+
 bool is_device_ptr(const void* p) {
   hipPointerAttribute_t at;
   if (hipPointerGetAttributes(&at, p) != hipSuccess) {
@@ -118,7 +141,42 @@ bool is_device_ptr(const void* p) {
 
 }  // namespace
 
-int DevCSR::upload(const lradi_csr* A, hipStream_t st, bool need32) {
+int DevCSR::build_sell(const int32_t* rph, hipStream_t st, bool need32) {
+  // slot-block starts per slice: each slice as wide as its longest row
+  nsl = (n + kSellH - 1) / kSellH;
+  std::vector<int> ss(nsl + 1);
+  int64_t e = 0;
+  for (int s = 0; s < nsl; ++s) {
+    int w = 1;
+    for (int i = s * kSellH; i < std::min(n, s * kSellH + kSellH); ++i) w = std::max(w, rph[i + 1] - rph[i]);
+    ss[s] = (int)e;
+    e += w;
+    if (e > INT32_MAX) return set_error("sliced layout exceeds int32 slot indexing"), LRADI_EINVAL;
+  }
+  ss[nsl] = (int)e;
+  const bool mass = has_mass();
+  LRADI_TRY(sslot.alloc(sizeof(int) * ss.size()));
+  LRADI_HIP(hipMemcpyAsync(sslot.p, ss.data(), sizeof(int) * ss.size(), hipMemcpyHostToDevice, st));
+  const int tpb = 256;
+  const dim3 g((unsigned)(((int64_t)nsl * kSellH + tpb - 1) / tpb)), tb(tpb);
+  const double* mv = mass ? mval64.as<double>() : nullptr;
+  LRADI_TRY(sblk64.alloc((size_t)e * sell_block_bytes(8, mass)));
+  hipLaunchKernelGGL(k_sell_fill<double>, g, tb, 0, st, n, nsl, rowptr.as<int>(), sslot.as<int>(),
+                     colind.as<int>(), val64.as<double>(), mv, sblk64.as<unsigned char>());
+  LRADI_HIP(hipGetLastError());
+  if (need32) {
+    // FP32 values rounded from the FP64 ones, as val32
+    LRADI_TRY(sblk32.alloc((size_t)e * sell_block_bytes(4, mass)));
+    hipLaunchKernelGGL(k_sell_fill<float>, g, tb, 0, st, n, nsl, rowptr.as<int>(), sslot.as<int>(),
+                       colind.as<int>(), val64.as<double>(), mv, sblk32.as<unsigned char>());
+    LRADI_HIP(hipGetLastError());
+  }
+  // the host slot-block starts must outlive their copy
+  LRADI_HIP(hipStreamSynchronize(st));
+  return LRADI_OK;
+}
+
+int DevCSR::upload(const lradi_csr* A, hipStream_t st, bool need32, bool sell) {
   if (!A || A->nrows <= 0 || A->nrows != A->ncols || A->nnz < 0 || !A->rowptr ||
       (A->nnz > 0 && (!A->colind || !A->val))) {
     set_error("invalid csr argument (square, nrows > 0, non-null arrays required)");
@@ -187,6 +245,16 @@ int DevCSR::upload(const lradi_csr* A, hipStream_t st, bool need32) {
                          val64.as<double>(), val32.as<float>(), nnz);
       LRADI_HIP(hipGetLastError());
     }
+  }
+  if (sell) {
+    std::vector<int32_t> hrp;
+    const int32_t* rph = A->rowptr;
+    if (A->on_device) {
+      hrp.resize(n + 1);
+      LRADI_HIP(hipMemcpy(hrp.data(), A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+      rph = hrp.data();
+    }
+    LRADI_TRY(build_sell(rph, st, need32));
   }
   return LRADI_OK;
 }
@@ -257,20 +325,30 @@ int choose_rows_per_wg(int n) {
 }
 
 // ---------------------------------------------------------------------------
+// Standalone shifted product on a DevCSR's sliced layout.  Operands well
+// beyond the 256 MB last-level cache stream with the nontemporal hint, so
+// that the matrix and the output do not evict the rows of X the stencil
+// gathers again.
+constexpr double kLlcBytes = 256.0 * (1 << 20);
+int spmm_plain_csr(hipStream_t st, const DevCSR& A, int r, int prec, int lanes, double shift, const void* X,
+                   void* Y) {
+  const double tsz = prec == LRADI_FP64 ? 8.0 : 4.0;
+  const double bytes = (double)A.nnz * (tsz + 4.0) + 2.0 * tsz * A.n * r;
+  if (A.has_mass()) return set_error("internal: plain shifted product of a pencil"), LRADI_EINVAL;
+  const unsigned char* blk = prec == LRADI_FP64 ? A.sblk64.as<unsigned char>() : A.sblk32.as<unsigned char>();
+  return launch_spmm_plain(st, A.n, r, prec, lanes, A.sslot.as<int>(), blk, shift, X, Y, bytes > 0.75 * kLlcBytes);
+}
+
 // Shifted-product autotuner: lanes per row (1, 2, 4 dividing r), timed with
 // HIP events on the context's stream; results cached per matrix shape.
 int spmm_time(lradi_ctx* c, const DevCSR& A, int r, int prec, int lanes, const void* X, void* Y,
               int reps, double* ms) {
-  const void* val = prec == LRADI_FP64 ? A.val64.p : A.val32.p;
   hipEvent_t e0, e1;
   LRADI_HIP(hipEventCreate(&e0));
   LRADI_HIP(hipEventCreate(&e1));
-  int rc = launch_spmm_plain(c->stream, A.n, r, prec, lanes, A.rowptr.as<int>(), A.colind.as<int>(), val,
-                             0.5, X, Y);  // warm-up
+  int rc = spmm_plain_csr(c->stream, A, r, prec, lanes, 0.5, X, Y);  // warm-up
   if (rc == LRADI_OK) rc = hipEventRecord(e0, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
-  for (int i = 0; i < reps && rc == LRADI_OK; ++i)
-    rc = launch_spmm_plain(c->stream, A.n, r, prec, lanes, A.rowptr.as<int>(), A.colind.as<int>(), val, 0.5,
-                           X, Y);
+  for (int i = 0; i < reps && rc == LRADI_OK; ++i) rc = spmm_plain_csr(c->stream, A, r, prec, lanes, 0.5, X, Y);
   if (rc == LRADI_OK) rc = hipEventRecord(e1, c->stream) == hipSuccess ? LRADI_OK : LRADI_EHIP;
   float t = 0.f;
   if (rc == LRADI_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRADI_OK : LRADI_EHIP;
@@ -338,6 +416,7 @@ struct SysWork {
     if (r > A->n) return set_error("r (%d) exceeds the system size (%d)", r, A->n), LRADI_EINVAL;
     if (cplx && (r > 4 || sweeps >= 0 || A->has_mass()))
       return set_error("complex shifts need r <= 4, M = C = I and no preconditioner"), LRADI_EINVAL;
+    if (!A->has_sell()) return set_error("internal: matrix uploaded without its sliced layout"), LRADI_EINVAL;
     const size_t n = (cplx ? 2 : 1) * (size_t)A->n, rr = r, mm = m;
     const size_t tsz = (prec == LRADI_FP64) ? 8 : 4;
     const int rpw = choose_rows_per_wg((int)n);
@@ -389,6 +468,8 @@ struct SysWork {
     d.mvalT = A->has_mass() ? ((prec == LRADI_FP64) ? (const void*)A->mval64.p : (const void*)A->mval32.p)
                             : nullptr;
     d.mval64 = A->has_mass() ? A->mval64.as<double>() : nullptr;
+    d.sslot = A->sslot.as<int>();
+    d.sblk = (prec == LRADI_FP64) ? A->sblk64.as<unsigned char>() : A->sblk32.as<unsigned char>();
     d.floor_rel = floor_rel;
     d.W = W;
     d.pstride = (int)pstride;
@@ -778,8 +859,8 @@ int upload_pair(const lradi_csr* M, hipStream_t st, DevCSR& dM, DevCSR& dMt) {
   csr_transpose(n, rp.data(), ci.data(), v.data(), trp, tci, tv);
   lradi_csr a{n, n, M->nnz, rp.data(), ci.data(), v.data(), 0};
   lradi_csr t{n, n, M->nnz, trp.data(), tci.data(), tv.data(), 0};
-  LRADI_TRY(dM.upload(&a, st, false));
-  LRADI_TRY(dMt.upload(&t, st, false));
+  LRADI_TRY(dM.upload(&a, st, false, false));
+  LRADI_TRY(dMt.upload(&t, st, false, false));
   LRADI_HIP(hipStreamSynchronize(st));
   return LRADI_OK;
 }
@@ -835,7 +916,7 @@ int DevCSR::upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st
   csr_union(A->nrows, arp.data(), aci.data(), av.data(), mrp.data(), mci.data(), mv.data(), urp, uci, uav,
             umv);
   lradi_csr U{A->nrows, A->nrows, (int64_t)uci.size(), urp.data(), uci.data(), uav.data(), 0};
-  LRADI_TRY(upload(&U, st, need32));
+  LRADI_TRY(upload(&U, st, need32, false));
   LRADI_TRY(mval64.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)));
   if (nnz > 0)
     LRADI_HIP(hipMemcpyAsync(mval64.p, umv.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
@@ -848,6 +929,7 @@ int DevCSR::upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st
       LRADI_HIP(hipGetLastError());
     }
   }
+  LRADI_TRY(build_sell(urp.data(), st, need32));
   LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
   return LRADI_OK;
 }
@@ -1447,9 +1529,7 @@ int lradi_spmm(lradi_ctx* c, const lradi_csr* A, double shift, const void* X, vo
   LRADI_TRY(dA.upload(A, c->stream, precision == LRADI_FP32_INNER));
   int lanes = 1;
   LRADI_TRY(spmm_lanes_for(c, dA, r, precision, -1, nullptr, nullptr, &lanes));
-  const void* val = (precision == LRADI_FP64) ? dA.val64.p : dA.val32.p;
-  LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, lanes, dA.rowptr.as<int>(),
-                              dA.colind.as<int>(), val, shift, X, Y));
+  LRADI_TRY(spmm_plain_csr(c->stream, dA, r, precision, lanes, shift, X, Y));
   LRADI_HIP(hipStreamSynchronize(c->stream));
   return LRADI_OK;
 }
@@ -1468,13 +1548,11 @@ int lradi_spmm_bench(lradi_ctx* c, const lradi_csr* A, double shift, const void*
   double ms = 0.0;
   LRADI_TRY(spmm_time(c, dA, r, precision, use, X, Y, reps, &ms));
   // leave Y = (A + shift I) X
-  const void* val = (precision == LRADI_FP64) ? dA.val64.p : dA.val32.p;
-  LRADI_TRY(launch_spmm_plain(c->stream, dA.n, r, precision, use, dA.rowptr.as<int>(), dA.colind.as<int>(),
-                              val, shift, X, Y));
+  LRADI_TRY(spmm_plain_csr(c->stream, dA, r, precision, use, shift, X, Y));
   LRADI_HIP(hipStreamSynchronize(c->stream));
   *avg_ms = ms;
   const int64_t tsz = precision == LRADI_FP64 ? 8 : 4;
-  if (bytes) *bytes = dA.nnz * (tsz + 4) + 4 * ((int64_t)dA.n + 1) + 2 * tsz * (int64_t)dA.n * r;
+  if (bytes) *bytes = dA.nnz * (tsz + 4) + 2 * tsz * (int64_t)dA.n * r;
   return LRADI_OK;
 }
 

@@ -18,7 +18,6 @@ constexpr int kTPB = 256;       // threads of a row workgroup (4 wavefronts)
 constexpr int kSmallTPB = 64;   // threads of a per-system workgroup (1 wavefront)
 constexpr int kHistCols = LRADI_HIST_COLS;
 constexpr int kPS = 128;        // stride of the small Gram partial rows
-constexpr int kSpmmCap = 2048;  // nonzeros of one SpMM tile staged in LDS
 // CholQR factors are formed inside the scale kernels when every system's
 // small Gram partials (nwg x r^2 values) are at most this many
 constexpr int kFuseCholMax = 8192;
@@ -115,14 +114,34 @@ __device__ inline int wave_rs_base(int lane) {
 }
 
 // Shifted-product tiling: `lanes` lanes share one matrix row, each owning
-// r / lanes of its columns, so a tile covers kTPB / lanes rows.  lanes is 1,
-// 2 or 4 and divides r.
+// r / lanes of its columns, so a tile covers kTPB / lanes rows (a wavefront
+// 64 / lanes of them).  lanes is 1, 2 or 4 and divides r.
 constexpr int spmm_tile_rows(int lanes) { return kTPB / lanes; }
-// Default lanes per row: the widest split that still leaves each lane 16
-// contiguous bytes of every gathered row of X (one 128-bit load).
+// The shifted product reads the matrix in a blocked sliced ELL layout:
+// slices of kSellH consecutive rows, each padded to its longest row (at
+// least one slot), padding entries (own row, value 0).  A slice is a run of
+// slot blocks, one per slot u: the kSellH column indices of slot u, then its
+// kSellH values (then, for a pencil, M's kSellH values), so a wavefront's
+// column and value loads of a slot are contiguous and adjacent, without
+// staging through LDS.  Slice s owns slot blocks sslot[s] .. sslot[s+1]-1.
+constexpr int kSellH = 32;
+__host__ __device__ constexpr int sell_block_bytes(int tsz, bool mass) { return kSellH * (4 + tsz * (mass ? 2 : 1)); }
+// The product launches one workgroup per tile, tiles assigned to the eight
+// XCDs (workgroup b runs on XCD b % 8) in contiguous bands, so that the
+// rows a stencil couples across planes are gathered through the same L2.
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int xcd_grid(int tiles) { return kXcds * ((tiles + kXcds - 1) / kXcds); }
+__device__ inline int xcd_band_tile(int b, int grid) {
+  const int band = grid / kXcds;
+  return (b % kXcds) * band + b / kXcds;
+}
+// Default lanes per row: the widest split that still leaves each lane 32
+// contiguous bytes of every gathered row of X (two 128-bit loads; narrower
+// splits multiply the per-slot column and value loads without adding bytes
+// in flight).
 inline int spmm_rule_lanes(int r, int tsz) {
   int rl = 1;
-  while (rl < 4 && r % (2 * rl) == 0 && r * tsz / (2 * rl) >= 16) rl *= 2;
+  while (rl < 4 && r % (2 * rl) == 0 && r * tsz / (2 * rl) >= 32) rl *= 2;
   return rl;
 }
 
@@ -148,6 +167,11 @@ struct SysDesc {
   const int* rowptr;
   const int* colind;
   const void* valT;     // values in the basis precision
+  // the same matrix in the shifted product's blocked sliced ELL layout
+  // (kSellH): slot-block starts per slice and the blocks (columns, values
+  // and, for pencils, M's values in the basis precision)
+  const int* sslot;
+  const unsigned char* sblk;
   const double* val64;  // FP64 values (refinement residual)
   double floor_rel;     // a cycle stops once est <= floor_rel * (start norm)
   const double* W;      // right-hand side, n x r
@@ -302,10 +326,18 @@ struct DevCSR {
   int64_t nnz = 0;
   DevBuf rowptr, colind, val64, val32;
   DevBuf mval64, mval32;  // the mass matrix of a pencil, on the same pattern
+  // blocked sliced ELL copy for the shifted product (kSellH rows per
+  // slice): slot-block starts (nsl + 1) and the FP64 / FP32 blocks (with M's
+  // values for a pencil); built by build_sell (upload() when asked for,
+  // upload_pencil() once M's values are there)
+  int nsl = 0;
+  DevBuf sslot, sblk64, sblk32;
+  bool has_sell() const { return sslot.p != nullptr; }
+  int build_sell(const int32_t* host_rowptr, hipStream_t st, bool need32);
   // red-black preconditioner data (prepare_rb), shared with the context's
   // cache of prepared matrices
   std::shared_ptr<const RbData> rb;
-  int upload(const lradi_csr* A, hipStream_t st, bool need32);
+  int upload(const lradi_csr* A, hipStream_t st, bool need32, bool sell = true);
   // the pencil (A, M): union pattern, A's values and M's values
   int upload_pencil(const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32);
   bool has_mass() const { return mval64.p != nullptr; }
@@ -343,8 +375,11 @@ int residual_norm(hipStream_t st, const DevCSR& A, const DevCSR& At, const DevCS
 
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels.hip)
-int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* rowptr,
-                      const int* colind, const void* val, double shift, const void* X, void* Y);
+// Y = (A + shift I) X on the blocked sliced ELL copy of a DevCSR (no mass
+// values); nt: matrix loads and output stores with the nontemporal hint
+// (operands far beyond the last-level cache)
+int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* sslot,
+                      const unsigned char* sblk, double shift, const void* X, void* Y, bool nt);
 
 // The batched inner solver: all systems of a batch share one precision.
 struct Batch {

@@ -127,131 +127,115 @@ __device__ inline void reduce_partS(const SysDesc& D, int P, double* red_lds, do
 // ---------------------------------------------------------------------------
 // 1. U = (A + s I) V_j  (PH_ARNOLDI)   or   U = R rounded  (PH_RESTART)
 //
-// One tile = kTPB / RL consecutive rows.  Its nonzeros (a contiguous range
-// of the CSR arrays) are first copied to LDS with coalesced loads; then RL
-// lanes work on each row, each for R / RL columns, and walk the row's
-// nonzeros SU at a time with all gathers of a group in flight together.
-// Every output element sums its terms in the same order for every RL, so
-// the result does not depend on the tiling.
+// One tile = kTPB / RL consecutive rows, a wavefront 64 / RL of them (two
+// slices of the sliced ELL layout for RL = 1, one for RL = 2, half of one
+// for RL = 4).  RL lanes work on each row, each for R / RL columns, and walk
+// the slice's slots SU at a time with all gathers of a group in flight
+// together; the column and value loads of a slot are contiguous across the
+// slice's rows.  A row's terms are summed in its CSR order (padding slots
+// add exact zeros), so the result does not depend on the tiling.
 template <typename T>
 struct SpmmUnroll {
   static constexpr int v = sizeof(T) == 8 ? 4 : 8;
 };
 
-// One row, columns q0..q0+RC: nonzeros SU at a time; a group's last slots
-// beyond the row repeat its final entry with a zero coefficient, so every
-// load stays unconditional (and in bounds) and all gathers of a group are in
-// flight together.  ci/val point either to LDS (offset base) or to the CSR
-// arrays (offset 0).
-// mv (nullable): the mass values on the same pattern, the coefficient then
-// is val + shift mv; diag: add shift x_i (M = I); neither when the staged
-// values already hold val + shift mv
+template <bool NT, typename V>
+__device__ inline V sell_ld(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+// Rows r0 .. r0 + kTPB / RL - 1 of Y = (A + shift M) X (M = I: diag).
+// mass: the blocks carry M's values, the coefficient then is val + shift mv.
 // Xc (nullable): complex systems' other half of the stacked block, added
 // with coefficient cs (the imaginary shift's coupling, -s_im for the real
-// rows and +s_im for the imaginary ones)
-template <typename T, int R, int RC, int SU>
-__device__ inline void spmm_row(int i, int q0, int k0, int k1, const int* ci, const T* val, const T* mv,
-                                bool diag, int off, T shift, const T* __restrict__ X,
-                                T* __restrict__ Y, const T* __restrict__ Xc = nullptr, T cs = T(0)) {
+// rows and +s_im for the imaginary ones).  NT: matrix loads and output
+// stores with the nontemporal hint.
+template <typename T, int R, int RL, bool NT>
+__device__ inline void sell_tile(int n, const int* __restrict__ sslot, const unsigned char* __restrict__ blk,
+                                 bool mass, T shift, const T* __restrict__ X, T* __restrict__ Y, int r0,
+                                 const T* __restrict__ Xc = nullptr, T cs = T(0)) {
+  constexpr int RC = R / RL;
+  constexpr int SU = SpmmUnroll<T>::v;
+  const int lane = (int)threadIdx.x % 64;
+  const int rw = r0 + ((int)threadIdx.x / 64) * (64 / RL);  // first row of this wavefront
+  if (rw >= n) return;                                       // uniform per wavefront
+  const int i = rw + lane / RL;
+  const int nsl = (n + kSellH - 1) / kSellH;
+  const int s = min(i / kSellH, nsl - 1);  // lanes past the last slice read its entries, store nothing
+  const int b0 = sslot[s];
+  const int w = sslot[s + 1] - b0;
+  int wmax = w;
+  if constexpr (RL == 1) wmax = max(w, __shfl_xor(w, 32));  // a wavefront spans two slices
+  // this lane's row inside its slice: slot u's column at cp[u * cst], its
+  // value at vp[u * vst] (M's at mp[u * vst])
+  const int sb = sell_block_bytes((int)sizeof(T), mass);
+  const unsigned char* base = blk + (size_t)b0 * sb;
+  const int l = i % kSellH;
+  const int* cp = reinterpret_cast<const int*>(base) + l;
+  const T* vp = reinterpret_cast<const T*>(base + kSellH * 4) + l;
+  const T* mp = reinterpret_cast<const T*>(base + kSellH * (4 + sizeof(T))) + l;
+  const int cst = sb / 4, vst = sb / (int)sizeof(T);
+  const int q0 = (lane % RL) * RC;
   T acc[RC];
 #pragma unroll
   for (int q = 0; q < RC; ++q) acc[q] = T(0);
-  for (int k = k0; k < k1; k += SU) {
+  for (int u = 0; u < wmax; u += SU) {
     int col[SU];
     T a[SU];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-      const int kk = min(k + u, k1 - 1) - off;
-      col[u] = ci[kk];
-      const T coef = mv ? val[kk] + shift * mv[kk] : val[kk];
-      a[u] = coef * (T)(k + u < k1);
+    for (int j = 0; j < SU; ++j) {
+      const int uu = min(u + j, w - 1);
+      col[j] = sell_ld<NT>(cp + uu * cst);
+      T c = sell_ld<NT>(vp + uu * vst);
+      if (mass) c = c + shift * sell_ld<NT>(mp + uu * vst);
+      a[j] = c * (T)(u + j < w);
     }
     T xv[SU][RC];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-      const T* x = X + (size_t)col[u] * R + q0;
+    for (int j = 0; j < SU; ++j) {
+      const T* x = X + (size_t)col[j] * R + q0;
 #pragma unroll
-      for (int q = 0; q < RC; ++q) xv[u][q] = x[q];
+      for (int q = 0; q < RC; ++q) xv[j][q] = x[q];
     }
 #pragma unroll
-    for (int u = 0; u < SU; ++u)
+    for (int j = 0; j < SU; ++j)
 #pragma unroll
-      for (int q = 0; q < RC; ++q) acc[q] += a[u] * xv[u][q];
+      for (int q = 0; q < RC; ++q) acc[q] += a[j] * xv[j][q];
   }
-  T* y = Y + (size_t)i * R + q0;
+  if (i >= n) return;
+  T out[RC];
+  const T* xi = X + (size_t)i * R + q0;
   if (Xc) {
-    const T* xi = X + (size_t)i * R + q0;
     const T* xc = Xc + (size_t)i * R + q0;
 #pragma unroll
-    for (int q = 0; q < RC; ++q) y[q] = (acc[q] + shift * xi[q]) + cs * xc[q];
-  } else if (diag) {
-    const T* xi = X + (size_t)i * R + q0;
+    for (int q = 0; q < RC; ++q) out[q] = (acc[q] + shift * xi[q]) + cs * xc[q];
+  } else if (!mass) {
 #pragma unroll
-    for (int q = 0; q < RC; ++q) y[q] = acc[q] + shift * xi[q];
+    for (int q = 0; q < RC; ++q) out[q] = acc[q] + shift * xi[q];
   } else {
 #pragma unroll
-    for (int q = 0; q < RC; ++q) y[q] = acc[q];
+    for (int q = 0; q < RC; ++q) out[q] = acc[q];
   }
-}
-
-template <typename T, int R, int RL>
-__device__ inline void spmm_tile(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                 const T* __restrict__ val, const T* __restrict__ mval, T shift,
-                                 const T* __restrict__ X, T* __restrict__ Y, int r0, int* s_ci,
-                                 T* s_val, const T* __restrict__ Xc = nullptr, T cs = T(0)) {
-  constexpr int RC = R / RL;
-  constexpr int SU = SpmmUnroll<T>::v;
-  constexpr int PER = kSpmmCap / kTPB;
-  const int r1 = min(n, r0 + spmm_tile_rows(RL));
-  const int i = r0 + (int)threadIdx.x / RL;
-  const bool live = i < r1;
-  int k0 = 0, k1 = 0;
-  if (live) {
-    k0 = rp[i];
-    k1 = rp[i + 1];
-  }
-  const int base = rp[r0], cnt = rp[r1] - base;
-  const bool staged = cnt <= kSpmmCap;
-  if (staged && cnt > 0) {
-    // all PER loads of a thread in flight at once (indices clamped into the
-    // tile), then the stores of the ones inside it
-    int cv[PER];
-    T vv[PER];
+  T* y = Y + (size_t)i * R + q0;
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = base + min(p * kTPB + (int)threadIdx.x, cnt - 1);
-      cv[p] = ci[e];
-      vv[p] = mval ? val[e] + shift * mval[e] : val[e];
-    }
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = p * kTPB + (int)threadIdx.x;
-      if (e < cnt) {
-        s_ci[e] = cv[p];
-        s_val[e] = vv[p];
-      }
-    }
+  for (int q = 0; q < RC; ++q) {
+    if constexpr (NT) __builtin_nontemporal_store(out[q], y + q);
+    else y[q] = out[q];
   }
-  __syncthreads();
-  if (!live) return;
-  const int q0 = ((int)threadIdx.x % RL) * RC;
-  const bool diag = mval == nullptr;
-  if (staged)
-    spmm_row<T, R, RC, SU>(i, q0, k0, k1, s_ci, s_val, nullptr, diag, base, shift, X, Y, Xc, cs);
-  else
-    spmm_row<T, R, RC, SU>(i, q0, k0, k1, ci, val, mval, diag, 0, shift, X, Y, Xc, cs);
 }
 
 // RL lanes per row; the kernel for group RL serves the systems whose tiling
-// uses RL (RF > 0: all systems have r = RF; RF == 0: r read at run time)
+// uses RL (RF > 0: all systems have r = RF; RF == 0: r read at run time).
+// Launched on xcd_grid(count) workgroups: entry xcd_band_tile(b) of spmap.
 template <typename T, int RF, int RL>
 __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
                                                    const SysCtl* __restrict__ ctl,
-                                                   const int2* __restrict__ spmap,
+                                                   const int2* __restrict__ spmap, int count,
                                                    unsigned long long* __restrict__ prof) {
-  __shared__ int s_ci[kSpmmCap];
-  __shared__ T s_val[kSpmmCap];
-  const int2 e = spmap[blockIdx.x];
+  const int ent = xcd_band_tile((int)blockIdx.x, (int)gridDim.x);
+  if (ent >= count) return;
+  const int2 e = spmap[ent];
   const SysDesc& D = d[e.x];
   const int ph = ctl[e.x].phase;
   // complex systems: the tiles of each half of the stacked block apart
@@ -272,22 +256,21 @@ __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d
   const T* Vj = static_cast<const T*>(D.rbrows ? D.P : D.V) + (size_t)ctl[e.x].j * D.n * D.r;
   const T sh = (T)ctl[e.x].shift;
   if (prof && e.y == 0 && threadIdx.x == 0) {
-    // values + column indices + row pointers + input block + output block
-    // (a complex system reads A once per half)
+    // each nonzero's value (and M's value) and column index + input block +
+    // output block (a complex system reads A once per half)
     const unsigned long long halves = D.cplx ? 2 : 1;
-    const unsigned long long bytes = halves * ((unsigned long long)D.nnz * (sizeof(T) + 4) +
-                                               4ull * (D.nmat + 1)) + 2ull * sizeof(T) * D.n * D.r;
+    const unsigned long long per_nz = sizeof(T) * (D.mvalT ? 2 : 1) + 4;
+    const unsigned long long bytes = halves * (unsigned long long)D.nnz * per_nz + 2ull * sizeof(T) * D.n * D.r;
     atomicAdd(prof + LRADI_PROF_SPMM, bytes);
   }
-  const T* val = static_cast<const T*>(D.valT);
-  const T* mval = static_cast<const T*>(D.mvalT);
+  const bool mass = D.mvalT != nullptr;
   if (D.cplx) {
     const T si = (T)ctl[e.x].shift_im;
     const T* Xc = Vj + (size_t)(1 - half) * D.nmat * D.r;
-    LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.nmat, D.rowptr, D.colind, val, nullptr, sh, Vj + hoff, U + hoff, r0, s_ci, s_val, Xc, half ? si : -si));
+    LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) sell_tile<T, RR, RL, false>(D.nmat, D.sslot, D.sblk, false, sh, Vj + hoff, U + hoff, r0, Xc, half ? si : -si));
     return;
   }
-  LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) spmm_tile<T, RR, RL>(D.n, D.rowptr, D.colind, val, mval, sh, Vj, U, r0, s_ci, s_val));
+  LRADI_RSEL(RF, D.r, if constexpr (RR % RL == 0) sell_tile<T, RR, RL, false>(D.n, D.sslot, D.sblk, mass, sh, Vj, U, r0));
 }
 
 // ---------------------------------------------------------------------------
@@ -1650,15 +1633,14 @@ __global__ __launch_bounds__(kTPB) void k_summary(const SysCtl* __restrict__ ctl
 }
 
 // plain Y = (A + s I) X for one block (no phases); the same tile routine as
-// the solver's shifted product
-template <typename T, int R, int RL>
-__global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci,
-                                                     const T* __restrict__ val, T shift,
+// the solver's shifted product, tiles in XCD bands
+template <typename T, int R, int RL, bool NT>
+__global__ __launch_bounds__(kTPB) void k_spmm_plain(int n, int ntiles, const int* __restrict__ sslot,
+                                                     const unsigned char* __restrict__ blk, T shift,
                                                      const T* __restrict__ X, T* __restrict__ Y) {
-  __shared__ int s_ci[kSpmmCap];
-  __shared__ T s_val[kSpmmCap];
-  spmm_tile<T, R, RL>(n, rp, ci, val, nullptr, shift, X, Y, (int)blockIdx.x * spmm_tile_rows(RL), s_ci, s_val);
+  const int t = xcd_band_tile((int)blockIdx.x, (int)gridDim.x);
+  if (t >= ntiles) return;
+  sell_tile<T, R, RL, NT>(n, sslot, blk, false, shift, X, Y, t * spmm_tile_rows(RL));
 }
 
 template <typename T, int RF>
@@ -1692,16 +1674,16 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[7], st));
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
-    hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,
-                       b.spmap + b.spoff[0], b.prof_bytes);
+    hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(xcd_grid(b.spcount[0])), tb, 0, st, b.d, b.ctl,
+                       b.spmap + b.spoff[0], b.spcount[0], b.prof_bytes);
   if constexpr (RF == 0 || RF % 2 == 0)
     if (b.spcount[1] > 0)
-      hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(b.spcount[1]), tb, 0, st, b.d, b.ctl,
-                         b.spmap + b.spoff[1], b.prof_bytes);
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(xcd_grid(b.spcount[1])), tb, 0, st, b.d, b.ctl,
+                         b.spmap + b.spoff[1], b.spcount[1], b.prof_bytes);
   if constexpr (RF == 0 || RF % 4 == 0)
     if (b.spcount[2] > 0)
-      hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(b.spcount[2]), tb, 0, st, b.d, b.ctl,
-                         b.spmap + b.spoff[2], b.prof_bytes);
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(xcd_grid(b.spcount[2])), tb, 0, st, b.d, b.ctl,
+                         b.spmap + b.spoff[2], b.spcount[2], b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[5], st));
   const dim3 gg(b.rowgrid, (b.maxB + kGramBlocks - 1) / kGramBlocks);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[0], st));
@@ -1756,19 +1738,20 @@ int launch_summary(hipStream_t st, const Batch& b, int* host_slot) {
 }
 
 namespace {
-template <typename T>
-int spmm_plain_t(hipStream_t st, int n, int r, int lanes, const int* rowptr, const int* colind,
-                 const T* val, T shift, const T* X, T* Y) {
-  const dim3 g((n + spmm_tile_rows(lanes) - 1) / spmm_tile_rows(lanes)), tb(kTPB);
+template <typename T, bool NT>
+int spmm_plain_t(hipStream_t st, int n, int r, int lanes, const int* sslot, const unsigned char* blk, T shift,
+                 const T* X, T* Y) {
+  const int ntiles = (n + spmm_tile_rows(lanes) - 1) / spmm_tile_rows(lanes);
+  const dim3 g(xcd_grid(ntiles)), tb(kTPB);
   LRADI_DISPATCH_R(r, {
     if (lanes == 1) {
-      hipLaunchKernelGGL((k_spmm_plain<T, RR, 1>), g, tb, 0, st, n, rowptr, colind, val, shift, X, Y);
+      hipLaunchKernelGGL((k_spmm_plain<T, RR, 1, NT>), g, tb, 0, st, n, ntiles, sslot, blk, shift, X, Y);
     } else if (lanes == 2) {
       if constexpr (RR % 2 == 0)
-        hipLaunchKernelGGL((k_spmm_plain<T, RR, 2>), g, tb, 0, st, n, rowptr, colind, val, shift, X, Y);
+        hipLaunchKernelGGL((k_spmm_plain<T, RR, 2, NT>), g, tb, 0, st, n, ntiles, sslot, blk, shift, X, Y);
     } else {
       if constexpr (RR % 4 == 0)
-        hipLaunchKernelGGL((k_spmm_plain<T, RR, 4>), g, tb, 0, st, n, rowptr, colind, val, shift, X, Y);
+        hipLaunchKernelGGL((k_spmm_plain<T, RR, 4, NT>), g, tb, 0, st, n, ntiles, sslot, blk, shift, X, Y);
     }
   });
   LRADI_HIP(hipGetLastError());
@@ -1776,16 +1759,21 @@ int spmm_plain_t(hipStream_t st, int n, int r, int lanes, const int* rowptr, con
 }
 }  // namespace
 
-int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* rowptr,
-                      const int* colind, const void* val, double shift, const void* X, void* Y) {
+int launch_spmm_plain(hipStream_t st, int n, int r, int precision, int lanes, const int* sslot,
+                      const unsigned char* blk, double shift, const void* X, void* Y, bool nt) {
   if (n <= 0) return LRADI_OK;
   if (r < 1 || r > kMaxR || !(lanes == 1 || lanes == 2 || lanes == 4) || r % lanes != 0)
     return LRADI_EINVAL;
-  if (precision == LRADI_FP64)
-    return spmm_plain_t<double>(st, n, r, lanes, rowptr, colind, static_cast<const double*>(val), shift,
-                                static_cast<const double*>(X), static_cast<double*>(Y));
-  return spmm_plain_t<float>(st, n, r, lanes, rowptr, colind, static_cast<const float*>(val), (float)shift,
-                             static_cast<const float*>(X), static_cast<float*>(Y));
+  if (precision == LRADI_FP64) {
+    auto x = static_cast<const double*>(X);
+    auto y = static_cast<double*>(Y);
+    return nt ? spmm_plain_t<double, true>(st, n, r, lanes, sslot, blk, shift, x, y)
+              : spmm_plain_t<double, false>(st, n, r, lanes, sslot, blk, shift, x, y);
+  }
+  auto x = static_cast<const float*>(X);
+  auto y = static_cast<float*>(Y);
+  return nt ? spmm_plain_t<float, true>(st, n, r, lanes, sslot, blk, (float)shift, x, y)
+            : spmm_plain_t<float, false>(st, n, r, lanes, sslot, blk, (float)shift, x, y);
 }
 
 }  // namespace lradi
