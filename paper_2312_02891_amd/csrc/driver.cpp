@@ -580,7 +580,6 @@ struct Table {
 // that gather each other's neighbours then meet in one L2.  Kernels index
 // their partial results by chunk, never by workgroup, so results do not
 // change.
-constexpr int kXcds = 8;
 void xcd_order(std::vector<int2>& v, size_t begin, size_t end) {
   const size_t G = end - begin;
   if (G <= (size_t)kXcds) return;

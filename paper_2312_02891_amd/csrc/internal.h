@@ -126,9 +126,10 @@ constexpr int spmm_tile_rows(int lanes) { return kTPB / lanes; }
 // staging through LDS.  Slice s owns slot blocks sslot[s] .. sslot[s+1]-1.
 constexpr int kSellH = 32;
 __host__ __device__ constexpr int sell_block_bytes(int tsz, bool mass) { return kSellH * (4 + tsz * (mass ? 2 : 1)); }
-// The product launches one workgroup per tile, tiles assigned to the eight
-// XCDs (workgroup b runs on XCD b % 8) in contiguous bands, so that the
-// rows a stencil couples across planes are gathered through the same L2.
+// Workgroup b of a launch runs on XCD b % 8.  Row chunks and product tiles
+// are assigned to the XCDs in contiguous bands (the solver's tables by the
+// host, the standalone product by xcd_band_tile), so that the rows a
+// stencil couples across planes are gathered through the same L2.
 constexpr int kXcds = 8;
 __host__ __device__ constexpr int xcd_grid(int tiles) { return kXcds * ((tiles + kXcds - 1) / kXcds); }
 __device__ inline int xcd_band_tile(int b, int grid) {

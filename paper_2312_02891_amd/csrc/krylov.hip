@@ -227,15 +227,13 @@ __device__ inline void sell_tile(int n, const int* __restrict__ sslot, const uns
 
 // RL lanes per row; the kernel for group RL serves the systems whose tiling
 // uses RL (RF > 0: all systems have r = RF; RF == 0: r read at run time).
-// Launched on xcd_grid(count) workgroups: entry xcd_band_tile(b) of spmap.
+// One workgroup per spmap entry (the host lists the entries in XCD bands).
 template <typename T, int RF, int RL>
 __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
                                                    const SysCtl* __restrict__ ctl,
-                                                   const int2* __restrict__ spmap, int count,
+                                                   const int2* __restrict__ spmap,
                                                    unsigned long long* __restrict__ prof) {
-  const int ent = xcd_band_tile((int)blockIdx.x, (int)gridDim.x);
-  if (ent >= count) return;
-  const int2 e = spmap[ent];
+  const int2 e = spmap[blockIdx.x];
   const SysDesc& D = d[e.x];
   const int ph = ctl[e.x].phase;
   // complex systems: the tiles of each half of the stacked block apart
@@ -1674,16 +1672,16 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[7], st));
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
-    hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(xcd_grid(b.spcount[0])), tb, 0, st, b.d, b.ctl,
-                       b.spmap + b.spoff[0], b.spcount[0], b.prof_bytes);
+    hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,
+                       b.spmap + b.spoff[0], b.prof_bytes);
   if constexpr (RF == 0 || RF % 2 == 0)
     if (b.spcount[1] > 0)
-      hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(xcd_grid(b.spcount[1])), tb, 0, st, b.d, b.ctl,
-                         b.spmap + b.spoff[1], b.spcount[1], b.prof_bytes);
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(b.spcount[1]), tb, 0, st, b.d, b.ctl,
+                       b.spmap + b.spoff[1], b.prof_bytes);
   if constexpr (RF == 0 || RF % 4 == 0)
     if (b.spcount[2] > 0)
-      hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(xcd_grid(b.spcount[2])), tb, 0, st, b.d, b.ctl,
-                         b.spmap + b.spoff[2], b.spcount[2], b.prof_bytes);
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(b.spcount[2]), tb, 0, st, b.d, b.ctl,
+                       b.spmap + b.spoff[2], b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[5], st));
   const dim3 gg(b.rowgrid, (b.maxB + kGramBlocks - 1) / kGramBlocks);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[0], st));
