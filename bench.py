@@ -43,9 +43,10 @@ PRECOND_SWEEPS = 32
 # per sweep: 24 (batch of 256: 1.01 s at 24 against 1.14 s at 32)
 BATCH_PRECOND_SWEEPS = 24
 # the 3-D configuration's Schur rows couple 18 neighbours instead of 8, so a
-# sweep costs more there and fewer pay (2, 4, 8, 16 sweeps: 0.313, 0.296,
-# 0.286, 0.310 s per FP32 solve before the setup cache)
-C3_PRECOND_SWEEPS = 8
+# sweep costs more there and fewer pay: FP64 relaxed solves with 2, 4, 6, 8,
+# 10, 12, 16, 20, 24, 32, 40 sweeps took 151.6, 120.4, 107.6, 102.0, 98.6,
+# 96.9, 95.0, 95.3, 98.3, 100.0, 105.3 ms (FP32 inner: 78-81 ms from 8 to 16)
+C3_PRECOND_SWEEPS = 16
 
 
 def parse():

@@ -55,16 +55,22 @@ __device__ inline void reduce_rows(const double* partS, int nwg, int off, int P,
   double acc = 0.0;
   if (g < groups) {
     const double* X = partS + off + p;
-    // eight independent sums keep eight loads in flight per thread (a
+    // sixteen independent sums keep sixteen loads in flight per thread (a
     // workgroup's partials sit kPS doubles apart, one line each)
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int w = g;
-    for (; w + 7 * groups < nwg; w += 8 * groups) {
+    double a[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += X[(size_t)(w + u * groups) * kPS];
+    for (int u = 0; u < 16; ++u) a[u] = 0.0;
+    int w = g;
+    for (; w + 15 * groups < nwg; w += 16 * groups) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] += X[(size_t)(w + u * groups) * kPS];
     }
     for (; w < nwg; w += groups) a[0] += X[(size_t)w * kPS];
-    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+      for (int u = 0; u < h; ++u) a[u] += a[u + h];
+    acc = a[0];
   }
   red_lds[t] = acc;
   __syncthreads();

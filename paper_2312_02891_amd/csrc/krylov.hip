@@ -90,7 +90,7 @@ __device__ inline void block_sum_store(double (&v)[NV], double* lds, double* out
 
 // Sum the per-workgroup r x r (P values) partial rows partS[w][0..P) over
 // w in a fixed order with a 256-thread workgroup; result in out (shared).
-// Each thread keeps four independent partial sums so that its loads are in
+// Each thread keeps sixteen independent partial sums so that its loads are in
 // flight together.
 __device__ inline void reduce_small(const double* src, int nwg, int P, double* red_lds, double* out) {
   const int t = threadIdx.x;
@@ -99,16 +99,22 @@ __device__ inline void reduce_small(const double* src, int nwg, int P, double* r
   double acc = 0.0;
   if (g < groups) {
     const double* X = src + p;
-    // eight independent sums keep eight loads in flight per thread (a
+    // sixteen independent sums keep sixteen loads in flight per thread (a
     // workgroup's partials sit kPS doubles apart, one line each)
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int w = g;
-    for (; w + 7 * groups < nwg; w += 8 * groups) {
+    double a[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += X[(size_t)(w + u * groups) * kPS];
+    for (int u = 0; u < 16; ++u) a[u] = 0.0;
+    int w = g;
+    for (; w + 15 * groups < nwg; w += 16 * groups) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] += X[(size_t)(w + u * groups) * kPS];
     }
     for (; w < nwg; w += groups) a[0] += X[(size_t)w * kPS];
-    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+      for (int u = 0; u < h; ++u) a[u] += a[u + h];
+    acc = a[0];
   }
   red_lds[t] = acc;
   __syncthreads();
@@ -438,6 +444,14 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
       if (slot >= 0) tv[(size_t)slot * nb + pb] -= wj * x.val[e2];
     }
   }
+  // the blocked copy read by the one-sweep launches
+  constexpr int sb = sell_block_bytes((int)sizeof(T), false);
+  unsigned char* g = D.t2blk + (size_t)(pb / kSellH) * D.t2w * sb;
+  const int l = pb % kSellH;
+  for (int q = 0; q < D.t2w; ++q) {
+    reinterpret_cast<int*>(g + (size_t)q * sb)[l] = D.t2ci[(size_t)q * nb + pb];
+    reinterpret_cast<T*>(g + (size_t)q * sb + kSellH * 4)[l] = tv[(size_t)q * nb + pb];
+  }
 }
 
 // acc = y_pb - sum_u T(pb, col_u) src(col_u) over T's off-diagonal slots of
@@ -485,12 +499,42 @@ struct RbRows {
 
 // one Jacobi sweep on T z = y for black position pb: dst row drow =
 // (y_pb - sum_u T(pb, l_u) src_{l_u}) / diag(T)_pb, with y, 1/diag(T) and
-// src in black-position order
+// src in black-position order; T's columns and values from the blocked copy
+// (the same slots in the same order as rb_sweep_acc, so the same bits)
 template <typename T, int R, int RQ = R>
 __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
                                     T* __restrict__ dst, size_t drow, int q0) {
+  constexpr int sb = sell_block_bytes((int)sizeof(T), false);
+  const unsigned char* g = D.t2blk + (size_t)(pb / kSellH) * D.t2w * sb;
+  const int* cp = reinterpret_cast<const int*>(g) + pb % kSellH;
+  const T* vp = reinterpret_cast<const T*>(g + kSellH * 4) + pb % kSellH;
+  constexpr int cst = sb / 4, vst = sb / (int)sizeof(T);
+  const T* Y = static_cast<const T*>(D.Yb);
   T acc[RQ];
-  rb_sweep_acc<T, R, RbRows<T, R>, RQ>(D, pb, nb, D.t2ci, nb, pb, pb, RbRows<T, R>{src}, q0, acc);
+#pragma unroll
+  for (int q = 0; q < RQ; ++q) acc[q] = Y[(size_t)pb * R + q0 + q];
+  constexpr int kRbUnroll = RbUnroll<R>::v;
+  for (int u0 = 0; u0 < D.t2w; u0 += kRbUnroll) {
+    int col[kRbUnroll];
+    T a[kRbUnroll];
+    bool ok[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const int slot = min(u0 + u, D.t2w - 1);
+      col[u] = cp[slot * cst];
+      a[u] = vp[slot * vst];
+      ok[u] = (u0 + u < D.t2w) && col[u] != pb;
+    }
+    T xv[kRbUnroll][RQ];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) xv[u][q] = src[(size_t)col[u] * R + q0 + q];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
+  }
   const T it = static_cast<const T*>(D.It)[pb];
 #pragma unroll
   for (int q = 0; q < RQ; ++q) dst[drow * R + q0 + q] = acc[q] * it;
