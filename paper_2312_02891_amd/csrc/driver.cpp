@@ -441,11 +441,7 @@ struct SysWork {
                             sweeps > 0 ? n * tsz : 0,                   // It
                             sweeps > 0 && A->has_rb()
                                 ? (size_t)A->rb->t2w * std::max(n - (size_t)A->rb->nred, (size_t)1) * tsz
-                                : 0,                                    // t2val
-                            sweeps > 0 && A->has_rb()
-                                ? (size_t)A->rb->t2w * ((n - (size_t)A->rb->nred + kSellH - 1) / kSellH) *
-                                      sell_block_bytes((int)tsz, false)
-                                : 0};                                   // t2blk
+                                : 0};                                   // t2val
     size_t total = 0;
     for (size_t z : sizes) total += align256(z);
     LRADI_TRY(buf.alloc(total));
@@ -500,7 +496,6 @@ struct SysWork {
         d.Eb = take(sizes[15]);
         d.It = take(sizes[16]);
         d.t2val = take(sizes[17]);
-        d.t2blk = reinterpret_cast<unsigned char*>(take(sizes[18]));
       }
       const lradi::RbData& B = *A->rb;
       d.t2w = B.t2w;

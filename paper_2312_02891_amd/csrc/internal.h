@@ -225,10 +225,6 @@ struct SysDesc {
   const int* t2ci;
   const int* rbpos;
   void* t2val;
-  // the same couplings for the one-sweep launches in blocked form: groups of
-  // kSellH black positions, per slot the group's kSellH columns (black
-  // positions) and then its kSellH values, written with T's values
-  unsigned char* t2blk;
   // paired sweeps: the black positions in tiles of ceil(nb / nwg), tile w
   // owned by row workgroup w; its halo (the black positions outside it
   // that its rows' T columns reach) at halo[halo_off[w] .. halo_off[w + 1]),

@@ -444,14 +444,6 @@ __device__ inline void rb_build_t(const SysDesc& D, const RbCtx<T>& x, int p, in
       if (slot >= 0) tv[(size_t)slot * nb + pb] -= wj * x.val[e2];
     }
   }
-  // the blocked copy read by the one-sweep launches
-  constexpr int sb = sell_block_bytes((int)sizeof(T), false);
-  unsigned char* g = D.t2blk + (size_t)(pb / kSellH) * D.t2w * sb;
-  const int l = pb % kSellH;
-  for (int q = 0; q < D.t2w; ++q) {
-    reinterpret_cast<int*>(g + (size_t)q * sb)[l] = D.t2ci[(size_t)q * nb + pb];
-    reinterpret_cast<T*>(g + (size_t)q * sb + kSellH * 4)[l] = tv[(size_t)q * nb + pb];
-  }
 }
 
 // acc = y_pb - sum_u T(pb, col_u) src(col_u) over T's off-diagonal slots of
@@ -499,42 +491,12 @@ struct RbRows {
 
 // one Jacobi sweep on T z = y for black position pb: dst row drow =
 // (y_pb - sum_u T(pb, l_u) src_{l_u}) / diag(T)_pb, with y, 1/diag(T) and
-// src in black-position order; T's columns and values from the blocked copy
-// (the same slots in the same order as rb_sweep_acc, so the same bits)
+// src in black-position order
 template <typename T, int R, int RQ = R>
 __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src,
                                     T* __restrict__ dst, size_t drow, int q0) {
-  constexpr int sb = sell_block_bytes((int)sizeof(T), false);
-  const unsigned char* g = D.t2blk + (size_t)(pb / kSellH) * D.t2w * sb;
-  const int* cp = reinterpret_cast<const int*>(g) + pb % kSellH;
-  const T* vp = reinterpret_cast<const T*>(g + kSellH * 4) + pb % kSellH;
-  constexpr int cst = sb / 4, vst = sb / (int)sizeof(T);
-  const T* Y = static_cast<const T*>(D.Yb);
   T acc[RQ];
-#pragma unroll
-  for (int q = 0; q < RQ; ++q) acc[q] = Y[(size_t)pb * R + q0 + q];
-  constexpr int kRbUnroll = RbUnroll<R>::v;
-  for (int u0 = 0; u0 < D.t2w; u0 += kRbUnroll) {
-    int col[kRbUnroll];
-    T a[kRbUnroll];
-    bool ok[kRbUnroll];
-#pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u) {
-      const int slot = min(u0 + u, D.t2w - 1);
-      col[u] = cp[slot * cst];
-      a[u] = vp[slot * vst];
-      ok[u] = (u0 + u < D.t2w) && col[u] != pb;
-    }
-    T xv[kRbUnroll][RQ];
-#pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u)
-#pragma unroll
-      for (int q = 0; q < RQ; ++q) xv[u][q] = src[(size_t)col[u] * R + q0 + q];
-#pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u)
-#pragma unroll
-      for (int q = 0; q < RQ; ++q) acc[q] = ok[u] ? acc[q] - a[u] * xv[u][q] : acc[q];
-  }
+  rb_sweep_acc<T, R, RbRows<T, R>, RQ>(D, pb, nb, D.t2ci, nb, pb, pb, RbRows<T, R>{src}, q0, acc);
   const T it = static_cast<const T*>(D.It)[pb];
 #pragma unroll
   for (int q = 0; q < RQ; ++q) dst[drow * R + q0 + q] = acc[q] * it;
