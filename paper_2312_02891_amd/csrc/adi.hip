@@ -207,6 +207,29 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ 
   } else {
     reduce_rows(DB.partS, DB.nwg, 0, R * R, red_lds, Gg);
   }
+  // ||f g^T||_2^2 = lambda_max(L^T (g^T g) L) with f^T f = L L^T (see the
+  // step end)
+  __shared__ double LF[64], MF[64];
+  if (threadIdx.x == 0) {
+    LRADI_SMALL_SWITCH(R, {
+      double a[NN * NN];
+      for (int e = 0; e < NN * NN; ++e) a[e] = Gf[e];
+      psd_chol_lower_t<NN>(a);
+      for (int e = 0; e < NN * NN; ++e) LF[e] = a[e];
+    });
+  }
+  __syncthreads();
+  {
+    const int t = (int)threadIdx.x;
+    if (t < R * R && t / R <= t % R) {
+      const int i = t / R, j = t % R;
+      double v = 0.0;
+      LRADI_SMALL_SWITCH(R, v = prod_chol_entry_t<NN>(LF, Gg, i, j));
+      MF[i * R + j] = v;
+      MF[j * R + i] = v;
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     AdiCtl& C = ac[p];
     // a NaN or Inf in f or g shows in its Gram matrix; the eigenvalue
@@ -216,7 +239,7 @@ __global__ __launch_bounds__(kTPB) void k_adi_setup(const SysDesc* __restrict__ 
     for (int e = 0; e < R * R; ++e) finite = finite && gram_finite(Gf[e]) && gram_finite(Gg[e]);
     const double nf = sqrt(fmax(lambda_max_sym(Gf, R), 0.0));
     const double ng = sqrt(fmax(lambda_max_sym(Gg, R), 0.0));
-    const double nfg = finite ? sqrt(fmax(lambda_max_prod(Gf, Gg, R), 0.0)) : nan("");
+    const double nfg = finite ? sqrt(fmax(lambda_max_sym(MF, R), 0.0)) : nan("");
     double sf = 1.0, sg = 1.0;
     if (P.rescale && nf > 0.0 && ng > 0.0) {
       sf = sqrt(ng / nf);
@@ -457,16 +480,41 @@ __global__ __launch_bounds__(kTPB) void k_adi_step_end(const SysDesc* __restrict
     }
     __syncthreads();
   }
+  // ||w t^T||_2^2 = lambda_max(L^T (T^T T) L) with W^T W = L L^T: one thread
+  // factors, the second wavefront forms the symmetric matrix entry by entry
+  // (registers for one small matrix per lane, not three)
+  __shared__ double LW[64], MP[64];
+  if (threadIdx.x == 64) {
+    LRADI_SMALL_SWITCH(NE, {
+      double a[NN * NN];
+      for (int e = 0; e < NN * NN; ++e) a[e] = GW[e];
+      psd_chol_lower_t<NN>(a);
+      for (int e = 0; e < NN * NN; ++e) LW[e] = a[e];
+    });
+  }
+  __syncthreads();
+  {
+    const int t = (int)threadIdx.x - 64;
+    if (t >= 0 && t < NE * NE && t / NE <= t % NE) {
+      const int i = t / NE, j = t % NE;
+      double v = 0.0;
+      LRADI_SMALL_SWITCH(NE, v = prod_chol_entry_t<NN>(LW, GT, i, j));
+      MP[i * NE + j] = v;
+      MP[j * NE + i] = v;
+    }
+  }
+  __syncthreads();
   // the five small eigenvalue problems run concurrently: the four Grams on
-  // four 16-lane groups of the first wavefront, the product on the whole
-  // second wavefront (each with its bisection spread over its lanes)
+  // four 16-lane groups of the first wavefront, the product's symmetric form
+  // on the whole second wavefront (each with its bisection spread over its
+  // lanes)
   if (threadIdx.x < 64) {
     const int g = threadIdx.x / 16, l = threadIdx.x % 16;
     const double* G = g == 0 ? GW : g == 1 ? GT : g == 2 ? GZ : GY;
     const double v = sqrt(fmax(lambda_max_sym_lanes<16>(G, NE, l, g * 16), 0.0));
     if (l == 0) nrm[g] = v;
   } else if (threadIdx.x < 128) {
-    const double v = sqrt(fmax(lambda_max_prod_lanes<64>(GW, GT, NE, threadIdx.x - 64, 0), 0.0));
+    const double v = sqrt(fmax(lambda_max_sym_lanes<64>(MP, NE, threadIdx.x - 64, 0), 0.0));
     if (threadIdx.x == 64) nrm[4] = v;
   }
   __syncthreads();

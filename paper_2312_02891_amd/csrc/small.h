@@ -325,6 +325,63 @@ LRADI_HD inline double lambda_max_prod_t(const double* Gw, const double* Gt) {
   return lambda_max_sym_t<N>(m);
 }
 
+// The same largest eigenvalue through a Cholesky factor instead of an
+// eigendecomposition: with Gw = L L^T (L lower triangular), Gw Gt and
+// L^T Gt L have the same eigenvalues, and the latter is symmetric.  The
+// factorization works in place on the lower triangle of a (row-major
+// N x N, the upper triangle is zeroed); a pivot at or below N u max_i a_ii
+// (u the unit roundoff) is taken as zero with its column, so rank-deficient
+// Grams (dependent or zero columns of W) factor without breakdown, the
+// dropped part being of the order of the rounding in Gw.  A NaN pivot is
+// dropped too: callers check their Grams for NaN and Inf themselves.
+template <int N>
+LRADI_HD inline void psd_chol_lower_t(double* a) {
+  double dmax = 0.0;
+  LRADI_UNROLL for (int i = 0; i < N; ++i) dmax = fmax(dmax, a[i * N + i]);
+  const double tiny = (double)N * 1.1102230246251565e-16 * dmax;
+  LRADI_UNROLL for (int j = 0; j < N; ++j) {
+    LRADI_UNROLL for (int i = 0; i < j; ++i) a[i * N + j] = 0.0;
+    double d = a[j * N + j];
+    LRADI_UNROLL for (int k = 0; k < j; ++k) d -= a[j * N + k] * a[j * N + k];
+    const bool keep = d > tiny;
+    const double ljj = keep ? sqrt(d) : 0.0;
+    a[j * N + j] = ljj;
+    LRADI_UNROLL for (int i = j + 1; i < N; ++i) {
+      double t = a[i * N + j];
+      LRADI_UNROLL for (int k = 0; k < j; ++k) t -= a[i * N + k] * a[j * N + k];
+      a[i * N + j] = keep ? t / ljj : 0.0;
+    }
+  }
+}
+
+// entry (i, j) of L^T Gt L for lower-triangular L (row-major N x N), in a
+// fixed summation order; i <= j gives the upper triangle, which callers
+// mirror so that the matrix is exactly symmetric
+template <int N>
+LRADI_HD inline double prod_chol_entry_t(const double* L, const double* Gt, int i, int j) {
+  double s = 0.0;
+  for (int k = i; k < N; ++k) {  // L[k][i] = 0 for k < i
+    double t = 0.0;
+    for (int l = j; l < N; ++l) t += Gt[k * N + l] * L[l * N + j];
+    s += L[k * N + i] * t;
+  }
+  return s;
+}
+
+template <int N>
+LRADI_HD inline double lambda_max_prod_chol_t(const double* Gw, const double* Gt) {
+  double a[N * N], m[N * N];
+  LRADI_UNROLL for (int e = 0; e < N * N; ++e) a[e] = Gw[e];
+  psd_chol_lower_t<N>(a);
+  for (int i = 0; i < N; ++i)
+    for (int j = i; j < N; ++j) {
+      const double v = prod_chol_entry_t<N>(a, Gt, i, j);
+      m[i * N + j] = v;
+      m[j * N + i] = v;
+    }
+  return lambda_max_sym_t<N>(m);
+}
+
 // Householder QR of the 2N x N matrix M (row-major, overwritten with R in
 // its top N rows and zeros below).  Q (2N x 2N, row-major) is returned
 // explicitly with Q^T M_in = [R; 0].
@@ -411,6 +468,11 @@ LRADI_HD inline double lambda_max_sym_ms(const double* G, int n) {
 LRADI_HD inline double lambda_max_prod(const double* Gw, const double* Gt, int n) {
   double r = 0.0;
   LRADI_SMALL_SWITCH(n, r = lambda_max_prod_t<NN>(Gw, Gt));
+  return r;
+}
+LRADI_HD inline double lambda_max_prod_chol(const double* Gw, const double* Gt, int n) {
+  double r = 0.0;
+  LRADI_SMALL_SWITCH(n, r = lambda_max_prod_chol_t<NN>(Gw, Gt));
   return r;
 }
 LRADI_HD inline void householder_2nxn(double* M, double* Q, int n) {

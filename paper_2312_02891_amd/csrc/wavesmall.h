@@ -35,17 +35,4 @@ __device__ inline double lambda_max_sym_lanes(const double* G, int n, int lane, 
   return r;
 }
 
-// largest eigenvalue of Gw Gt (see lambda_max_prod_t), the last step
-// across the group's lanes
-template <int L>
-__device__ inline double lambda_max_prod_lanes(const double* Gw, const double* Gt, int n, int lane, int base) {
-  double r = 0.0;
-  LRADI_SMALL_SWITCH(n, {
-    double m[NN * NN];
-    prod_sym_t<NN>(Gw, Gt, m);
-    r = lambda_max_sym_lanes_t<NN, L>(m, lane, base);
-  });
-  return r;
-}
-
 }  // namespace lradi

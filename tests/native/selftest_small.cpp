@@ -12,6 +12,7 @@ double st_lmax(const double* G, int n) { return lradi::lambda_max_sym(G, n); }
 double st_lmax_ms16(const double* G, int n) { return lradi::lambda_max_sym_ms<16>(G, n); }
 double st_lmax_ms64(const double* G, int n) { return lradi::lambda_max_sym_ms<64>(G, n); }
 double st_lmax_prod(const double* A, const double* B, int n) { return lradi::lambda_max_prod(A, B, n); }
+double st_lmax_prod_chol(const double* A, const double* B, int n) { return lradi::lambda_max_prod_chol(A, B, n); }
 void st_house(double* M, double* Q, int n) { lradi::householder_2nxn(M, Q, n); }
 void st_tol(int selection, int backlook, int paper_abs, int k, double nw, double nt, double u,
             double v, double eps, int kmax, double xi, double dmin, double dmax, double dfix,

@@ -98,6 +98,7 @@ def ST(tmp_path_factory):
     lib.st_lmax_ms16.restype = D
     lib.st_lmax_ms64.restype = D
     lib.st_lmax_prod.restype = D
+    lib.st_lmax_prod_chol.restype = D
     lib.st_tol.argtypes = [ctypes.c_int] * 4 + [D] * 5 + [ctypes.c_int] + [D] * 5 + [ctypes.c_int, P, P]
     lib.st_gap.argtypes = [P, P] + [D] * 5
     return lib
@@ -159,6 +160,26 @@ def test_lambda_max_of_gram_product_is_lowrank_norm(ST, n):
     Gw, Gt = np.ascontiguousarray(Wm.T @ Wm), np.ascontiguousarray(Tm.T @ Tm)
     got = np.sqrt(ST.st_lmax_prod(_p(Gw), _p(Gt), n))
     assert got == pytest.approx(np.linalg.norm(Wm @ Tm.T, 2), rel=1e-12)
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_lambda_max_of_gram_product_through_cholesky(ST, n):
+    """The step end's form of ||W T^T||_2^2: L^T (T^T T) L with W^T W = L L^T,
+    also for rank-deficient W (a repeated and a zero column) and T = 0."""
+    rng = np.random.default_rng(30 + n)
+    Wm, Tm = rng.standard_normal((40, n)), rng.standard_normal((30, n))
+    cases = [(Wm, Tm)]
+    if n >= 3:
+        Wd = Wm.copy()
+        Wd[:, 1] = Wd[:, 0]
+        Wd[:, 2] = 0.0
+        cases.append((Wd, Tm))
+    cases.append((Wm, np.zeros_like(Tm)))
+    for W, T in cases:
+        Gw, Gt = np.ascontiguousarray(W.T @ W), np.ascontiguousarray(T.T @ T)
+        got = np.sqrt(max(ST.st_lmax_prod_chol(_p(Gw), _p(Gt), n), 0.0))
+        want = np.linalg.norm(W @ T.T, 2)
+        assert got == pytest.approx(want, rel=1e-12, abs=1e-14 * np.linalg.norm(W) * np.linalg.norm(T))
 
 
 @pytest.mark.parametrize("n", range(1, 9))
