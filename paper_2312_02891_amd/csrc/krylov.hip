@@ -68,6 +68,48 @@ __device__ inline RowCtx row_ctx(const SysDesc* d, const int2* rowmap) {
   return c;
 }
 
+// one chunk (values C0 .. C0+N-1 of v) of block_sum_store_sym's
+// reduce-scatter, into lds[wave * NV + C0 + ...]
+template <int NV, int C0, int N>
+__device__ inline void block_sum_chunk(const double (&v)[NV], double* lds) {
+  constexpr int P2 = pow2c(N);
+  using RS = WaveRS<P2, 1>;
+  static_assert(RS::NOUT == 1, "at most 64 values");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double w[P2];
+#pragma unroll
+  for (int k = 0; k < P2; ++k) w[k] = k < N ? v[C0 + k] : 0.0;
+  wave_reduce_scatter<P2, 1>(w, lane);
+  const int idx = wave_rs_base<P2, 1>(lane);
+  if ((lane & RS::DUP) == 0 && idx < N) lds[wave * NV + C0 + idx] = w[0];
+}
+
+// The Gram of a block's R columns from its packed upper triangle: v holds
+// entry (a, q), a <= q, at a R - a (a - 1) / 2 + q - a.  Sums the packed
+// values over the 256 threads in a fixed order (at most 32 values per
+// reduce-scatter, so that the padded copies stay small) and stores the full
+// symmetric R x R matrix to out.  lds needs 4 R (R + 1) / 2 doubles.
+template <int R>
+__device__ inline void block_sum_store_sym(double (&v)[R * (R + 1) / 2], double* lds, double* out) {
+  constexpr int NV = R * (R + 1) / 2;
+  constexpr int N0 = NV < 32 ? NV : 32;
+  block_sum_chunk<NV, 0, N0>(v, lds);
+  if constexpr (NV > N0) block_sum_chunk<NV, N0, NV - N0>(v, lds);
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV; k += kTPB) {
+    int a = 0, rem = k;
+    while (rem >= R - a) {
+      rem -= R - a;
+      ++a;
+    }
+    const int q = a + rem;
+    const double s = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
+    out[a * R + q] = s;
+    out[q * R + a] = s;
+  }
+  __syncthreads();
+}
+
 // Sum NV per-thread values over the 256 threads of the workgroup in a fixed
 // order and store the totals to out[0..NV).  lds needs 4*NV doubles.
 template <int NV>
@@ -904,10 +946,11 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
   const auto V = gmem(static_cast<const T*>(D.V));
   const auto U = gmem_w(static_cast<T*>(D.U));
   const size_t bs = (size_t)D.n * R;
-  double g2[GRAM ? R * R : 1];
+  constexpr int NG = R * (R + 1) / 2;  // the Gram's packed upper triangle
+  double g2[GRAM ? NG : 1];
   if constexpr (GRAM) {
 #pragma unroll
-    for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+    for (int e = 0; e < NG; ++e) g2[e] = 0.0;
   }
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     T u[R];
@@ -951,13 +994,14 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
       }
     }
     if constexpr (GRAM) {
+      int e = 0;
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
-        for (int q = 0; q < R; ++q) g2[a * R + q] += (double)u[a] * (double)u[q];
+        for (int q = a; q < R; ++q) g2[e++] += (double)u[a] * (double)u[q];
     }
   }
-  if constexpr (GRAM) block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+  if constexpr (GRAM) block_sum_store_sym<R>(g2, lds, D.partS + (size_t)c.w * kPS);
 }
 
 template <typename T, int RF, bool SECOND>
@@ -1043,15 +1087,22 @@ __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, Sy
 template <typename T, int R, bool GRAM>
 __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const double* Si, T* dst,
                                   double* lds, double* gout) {
-  double sl[R * R];
+  // S^{-1} is upper triangular: its entries (a, q), a <= q, packed by rows
+  double sl[R * (R + 1) / 2];
+  {
+    int e = 0;
 #pragma unroll
-  for (int e = 0; e < R * R; ++e) sl[e] = Si[e];
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int q = a; q < R; ++q) sl[e++] = Si[a * R + q];
+  }
   const auto U = gmem(static_cast<const T*>(D.U));
   const auto dg = gmem_w(dst);
-  double g2[GRAM ? R * R : 1];
+  constexpr int NG = R * (R + 1) / 2;  // the Gram's packed upper triangle
+  double g2[GRAM ? NG : 1];
   if constexpr (GRAM) {
 #pragma unroll
-    for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+    for (int e = 0; e < NG; ++e) g2[e] = 0.0;
   }
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     double u[R], o[R];
@@ -1061,7 +1112,7 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
     for (int q = 0; q < R; ++q) {
       double v = 0.0;
 #pragma unroll
-      for (int a = 0; a <= q; ++a) v += u[a] * sl[a * R + q];
+      for (int a = 0; a <= q; ++a) v += u[a] * sl[a * R - a * (a - 1) / 2 + (q - a)];
       o[q] = v;
     }
     T ot[R];
@@ -1071,13 +1122,14 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
       dg[(size_t)i * R + q] = ot[q];
     }
     if constexpr (GRAM) {
+      int e = 0;
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
-        for (int q = 0; q < R; ++q) g2[a * R + q] += (double)ot[a] * (double)ot[q];
+        for (int q = a; q < R; ++q) g2[e++] += (double)ot[a] * (double)ot[q];
     }
   }
-  if constexpr (GRAM) block_sum_store<R * R>(g2, lds, gout + (size_t)c.w * kPS);
+  if constexpr (GRAM) block_sum_store_sym<R>(g2, lds, gout + (size_t)c.w * kPS);
 }
 
 template <typename T, int RF, int PASS>
