@@ -35,6 +35,8 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-residual 1e-8 + SpMM HBM GB/s; inexact-FP32 vs exact-FP64; p99 lat"
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector (non-matrix) peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Jacobi sweeps on the Schur complement in the preconditioned inner solves
 # of config 2, run two per launch (FP64 solve: 16, 20, 24, 28, 32, 40
 # sweeps gave 0.103, 0.092, 0.090, 0.089, 0.089, 0.089 s)
@@ -490,6 +492,25 @@ def bench_headline(args, L, WL):
                 "avg_launch_us": d["avg_launch_us"], "launches": d["launches"], "total_ms": d["total_ms"]}
         extra["kernel_classes"] = rates
         print(f"[bench] kernel classes: {json.dumps(rates)}", file=sys.stderr, flush=True)
+        # the same classes for the FP32-inner relaxed solve, with the
+        # projection's arithmetic rate: every basis element read takes part
+        # in r multiply-adds, (j+1)/(j+2) of the bytes are basis bytes, so
+        # flops = 2 r (bytes / 4) (j+1)/(j+2) <= r/2 flop per byte at r = 8
+        ctx.profile_reset()
+        solve(L.default_opts(selection="mid", profile=1, precision="fp32", **base, **pre))
+        rates32 = {}
+        for cls, key in ((L.PROF_PRECOND, "precond"), (L.PROF_GRAM, "gram"), (L.PROF_SPMM, "spmm")):
+            ms, launches, nbytes = ctx.profile_read(cls)
+            avg_us = ms * 1e3 / max(launches, 1)
+            per_launch = nbytes / max(launches, 1)
+            rates32[key] = {"avg_launch_us": round(avg_us, 2), "bytes_per_launch": round(per_launch),
+                            "GBs": round(per_launch / max(avg_us * 1e-6, 1e-30) / 1e9, 1),
+                            "launches": launches, "total_ms": round(ms, 2)}
+        g32 = rates32["gram"]
+        g32["TFLOPs_upper_bound"] = round(g32["GBs"] * P.r / 2 / 1e3, 2)
+        g32["fp32_vector_peak_TFLOPs"] = FP32_VECTOR_PEAK_TFLOPS
+        extra["kernel_classes_fp32_inner"] = rates32
+        print(f"[bench] kernel classes, FP32 inner: {json.dumps(rates32)}", file=sys.stderr, flush=True)
 
     if not args.no_probe:
         extra.update(_spmm_probe(L, WL, ctx))

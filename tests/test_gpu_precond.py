@@ -266,9 +266,13 @@ def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, swee
         ctx.profile_reset()
         res = ctx.solve(HA, HB, fd, gd, pA, pB, o, **kw)
         assert res.status == L.OK
-        runs.append((res, ctx.profile_read(L.PROF_PRECOND)[1]))
+        # preconditioner launches per tick: the number of ticks the host
+        # issues depends on how far ahead of the device it runs, so the
+        # launches are counted per shifted-product launch (one per tick and
+        # tiling group, the same groups in both runs)
+        runs.append((res, ctx.profile_read(L.PROF_PRECOND)[1] / ctx.profile_read(L.PROF_SPMM)[1]))
     (a, la), (b, lb) = runs
-    say("  k", a.k, "launches paired", la, "single", lb)
+    say("  k", a.k, "preconditioner launches per product launch: paired", la, "single", lb)
     assert a.k == b.k
     assert np.array_equal(a.history(), b.history())
     for x, y in zip(a.factors(), b.factors()):
@@ -276,7 +280,10 @@ def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, swee
     # 2-D tiles pair (regions about 1.4 times the tile); 3-D ones and
     # matrices below 32768 rows do not
     expect = P.A.dim == 2 and min(P.A.n, P.B.n) >= 32768
-    assert (la < lb) == expect
+    if expect:
+        assert la < lb
+    else:
+        assert la == pytest.approx(lb, rel=1e-12)
 
 
 def test_identity_mass_preconditioned_equals_plain(L, ctx):
