@@ -1496,9 +1496,10 @@ __device__ inline void resid_rows(const SysDesc& D, const RowCtx& c, double shif
   const double* __restrict__ val = D.val64;
   const int* __restrict__ rp = D.rowptr;
   const int* __restrict__ ci = D.colind;
-  double g2[R * R];
+  constexpr int NG = R * (R + 1) / 2;  // R^T R's packed upper triangle
+  double g2[NG];
 #pragma unroll
-  for (int e = 0; e < R * R; ++e) g2[e] = 0.0;
+  for (int e = 0; e < NG; ++e) g2[e] = 0.0;
   for (int i = c.row0 + threadIdx.x; i < c.row1; i += kTPB) {
     double rr[R];
 #pragma unroll
@@ -1511,25 +1512,42 @@ __device__ inline void resid_rows(const SysDesc& D, const RowCtx& c, double shif
       const double* __restrict__ mv = D.mval64;
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] = mv ? 0.0 : shift * Z[(size_t)i * R + q];
+      // the row's nonzeros four at a time, every gather of a group in
+      // flight together (clamped indices, zero coefficients past the row);
+      // the terms are added in the row's order
+      constexpr int G = 4;
       const int k0 = rp[i], k1 = rp[i + 1];
-      for (int k = k0; k < k1; ++k) {
-        const int col = ci[k];
-        const double a = mv ? val[k] + shift * mv[k] : val[k];
-        const double* z = Z + (size_t)col * R;
+      for (int k = k0; k < k1; k += G) {
+        int col[G];
+        double a[G];
 #pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] += a * z[q];
+        for (int u = 0; u < G; ++u) {
+          const int kk = min(k + u, k1 - 1);
+          col[u] = ci[kk];
+          a[u] = (mv ? val[kk] + shift * mv[kk] : val[kk]) * (double)(k + u < k1);
+        }
+        double z[G][R];
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+          for (int q = 0; q < R; ++q) z[u][q] = Z[(size_t)col[u] * R + q];
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q] += a[u] * z[u][q];
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) rr[q] -= acc[q];
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) D.R[(size_t)i * R + q] = rr[q];
+    int e = 0;
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
-      for (int q = 0; q < R; ++q) g2[a * R + q] += rr[a] * rr[q];
+      for (int q = a; q < R; ++q) g2[e++] += rr[a] * rr[q];
   }
-  block_sum_store<R * R>(g2, lds, D.partS + (size_t)c.w * kPS);
+  block_sum_store_sym<R>(g2, lds, D.partS + (size_t)c.w * kPS);
 }
 
 // complex systems: local row i < nmat gives both halves of the stacked
