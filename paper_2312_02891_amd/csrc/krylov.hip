@@ -1082,25 +1082,43 @@ __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, Sy
   }
 }
 
-// 9./11. pass 0: U = U S1^{-1} in place and partial U^T U;
-//        pass 1: V_{j+1} (PH_ARNOLDI) or V_0 (PH_RESTART) = U S2^{-1}.
-template <typename T, int R, bool GRAM>
-__device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const double* Si, T* dst,
-                                  double* lds, double* gout) {
-  // S^{-1} is upper triangular: its entries (a, q), a <= q, packed by rows
-  double sl[R * (R + 1) / 2];
-  {
+// 9./11. pass 0: the partial Gram of U S1^{-1} (rows formed in registers,
+//        U itself is left as it is);
+//        pass 1: V_{j+1} (PH_ARNOLDI) or V_0 (PH_RESTART) = (U S1^{-1}) S2^{-1},
+//        U S1^{-1} formed again exactly as in pass 0 (rounded to the basis
+//        precision in both), so the result equals writing U S1^{-1} back in
+//        pass 0 and scaling it in pass 1, bit for bit, one write of U fewer.
+template <int R>
+struct PackedTri {
+  // an upper-triangular R x R matrix's entries (a, q), a <= q, by rows
+  double v[R * (R + 1) / 2];
+  __device__ explicit PackedTri(const double* S) {
     int e = 0;
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
-      for (int q = a; q < R; ++q) sl[e++] = Si[a * R + q];
+      for (int q = a; q < R; ++q) v[e++] = S[a * R + q];
   }
+  // o = u S (row vector times the matrix)
+  __device__ void apply(const double (&u)[R], double (&o)[R]) const {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a <= q; ++a) s += u[a] * v[a * R - a * (a - 1) / 2 + (q - a)];
+      o[q] = s;
+    }
+  }
+};
+
+template <typename T, int R, int PASS>
+__device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const double* S1i, const double* S2i,
+                                  T* dst, double* lds, double* gout) {
+  const PackedTri<R> s1(S1i);
   const auto U = gmem(static_cast<const T*>(D.U));
-  const auto dg = gmem_w(dst);
   constexpr int NG = R * (R + 1) / 2;  // the Gram's packed upper triangle
-  double g2[GRAM ? NG : 1];
-  if constexpr (GRAM) {
+  double g2[PASS == 0 ? NG : 1];
+  if constexpr (PASS == 0) {
 #pragma unroll
     for (int e = 0; e < NG; ++e) g2[e] = 0.0;
   }
@@ -1108,28 +1126,28 @@ __device__ inline void scale_rows(const SysDesc& D, const RowCtx& c, const doubl
     double u[R], o[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) u[q] = (double)U[(size_t)i * R + q];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      double v = 0.0;
-#pragma unroll
-      for (int a = 0; a <= q; ++a) v += u[a] * sl[a * R - a * (a - 1) / 2 + (q - a)];
-      o[q] = v;
-    }
+    s1.apply(u, o);
     T ot[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      ot[q] = (T)o[q];
-      dg[(size_t)i * R + q] = ot[q];
-    }
-    if constexpr (GRAM) {
+    for (int q = 0; q < R; ++q) ot[q] = (T)o[q];
+    if constexpr (PASS == 0) {
       int e = 0;
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
         for (int q = a; q < R; ++q) g2[e++] += (double)ot[a] * (double)ot[q];
+    } else {
+      const PackedTri<R> s2(S2i);
+      double w[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) w[q] = (double)ot[q];
+      s2.apply(w, o);
+      const auto dg = gmem_w(dst);
+#pragma unroll
+      for (int q = 0; q < R; ++q) dg[(size_t)i * R + q] = (T)o[q];
     }
   }
-  if constexpr (GRAM) block_sum_store_sym<R>(g2, lds, gout + (size_t)c.w * kPS);
+  if constexpr (PASS == 0) block_sum_store_sym<R>(g2, lds, gout + (size_t)c.w * kPS);
 }
 
 template <typename T, int RF, int PASS>
@@ -1147,6 +1165,7 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
   const int ph = ctl[c.s].phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
   const double* Si = D.sm + (PASS == 0 ? SM_S1I : SM_S2I);
+  const double* S1i = D.sm + SM_S1I;  // pass 1 applies S1^{-1} again
   if constexpr (RF >= 1 && RF <= 4) {
    if (fuse) {
     // this pass's Cholesky factor, formed by every workgroup from the small
@@ -1173,14 +1192,16 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
     Si = SS + D.r * D.r;
    }
   }
-  T* dst;
-  if (PASS == 0) {
-    dst = static_cast<T*>(D.U);
-  } else {
+  T* dst = nullptr;
+  if (PASS == 1) {
     const int tgt = (ph == PH_ARNOLDI) ? ctl[c.s].j + 1 : 0;
     dst = static_cast<T*>(D.V) + (size_t)tgt * D.n * D.r;
   }
-  LRADI_RSEL(RF, D.r, scale_rows<T, RR, PASS == 0>(D, c, Si, dst, lds, D.partS2));
+  if constexpr (PASS == 0) {
+    LRADI_RSEL(RF, D.r, scale_rows<T, RR, 0>(D, c, Si, nullptr, nullptr, lds, D.partS2));
+  } else {
+    LRADI_RSEL(RF, D.r, scale_rows<T, RR, 1>(D, c, S1i, Si, dst, lds, D.partS2));
+  }
 }
 
 // ---------------------------------------------------------------------------
