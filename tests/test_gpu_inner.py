@@ -127,6 +127,60 @@ def test_spmm_tilings_are_bitwise_identical(L, ctx, mat, r, prec):
     assert np.abs(ref.double().cpu().numpy() - want).max() <= tol * scale
 
 
+def _ragged_csr(n, seed):
+    """Rows of every length the sliced layout has to pad: empty rows, runs of
+    empty rows spanning whole 32-row slices, single entries, a row of 300
+    nonzeros and random short rows; n not a multiple of 32."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        if 64 <= i < 160 or i % 7 == 3:
+            cols = np.array([], dtype=np.int64)
+        elif i == 200:
+            cols = np.unique(rng.integers(0, n, 300))
+        elif i % 5 == 1:
+            cols = np.array([i])
+        else:
+            cols = np.unique(np.concatenate([[i], rng.integers(0, n, rng.integers(1, 12))]))
+        rows.append(cols)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(c) for c in rows])
+    ci = np.concatenate(rows).astype(np.int64)
+    v = rng.standard_normal(len(ci))
+    return rp, ci, v
+
+
+@pytest.mark.parametrize("r,prec", [(1, "f64"), (4, "f64"), (8, "f64"), (8, "f32"), (6, "f32")])
+def test_spmm_sliced_layout_ragged_rows(L, ctx, r, prec):
+    """The sliced ELL copy of a matrix with empty rows (also whole empty
+    slices), one-entry rows, a 300-entry row and a ragged last slice: every
+    tiling gives the same bits, and the product matches the oracle's."""
+    import torch
+    say("spmm ragged", r, prec)
+    n = 1001
+    rp, ci, v = _ragged_csr(n, 5 + r)
+    H = L.HostCsr(rp, ci, v)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    X = torch.from_numpy(np.random.default_rng(r).standard_normal((n, r))).to(dt).cuda()
+    s = 17.5
+    ref = ctx.spmm(H, s, X)
+    for lanes in (1, 2, 4):
+        if r % lanes:
+            continue
+        Y = torch.empty_like(X)
+        ctx.spmm_bench(H, s, X, reps=1, lanes=lanes, out=Y)
+        torch.cuda.synchronize()
+        assert torch.equal(Y, ref), f"lanes={lanes} differs"
+    Xd = X.double().cpu().numpy()
+    Ad = A if prec == "f64" else sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices,
+                                                A.indptr), A.shape)
+    want = Ad @ Xd + s * Xd
+    scale = (abs(Ad) @ np.abs(Xd) + abs(s) * np.abs(Xd)).max()
+    tol = 1e-14 if prec == "f64" else 2e-6
+    assert np.abs(ref.double().cpu().numpy() - want).max() <= tol * scale
+
+
 def test_spmm_autotuner_choice_is_valid_and_cached(L, ctx):
     """The tuner returns an admissible tiling for a product above its size
     threshold, and the same one again from its cache."""
