@@ -144,3 +144,87 @@ def test_pencil_gmres_definition_with_exact_preconditioner():
     exact = lambda X: spla.spsolve(S, X).reshape(X.shape)
     Z1 = block_gmres_iterate(A, s, W, 1, precond=exact, M=M)
     assert np.allclose(Z1, exact(W), rtol=1e-10, atol=1e-12)
+
+
+def _schur_dense(S, col):
+    """Schur complement on the black rows of a small dense S (definition)."""
+    r, b = np.where(col == 0)[0], np.where(col == 1)[0]
+    return S[np.ix_(b, b)] - S[np.ix_(b, r)] @ np.linalg.solve(S[np.ix_(r, r)], S[np.ix_(r, b)])
+
+
+@pytest.mark.parametrize("dim,N,omega,shift", [(2, 9, (25.0, -12.0), -30.0), (2, 10, (4.0, 7.0), -3.0),
+                                               (3, 5, (20.0, 10.0, 5.0), -40.0), (3, 6, (-10.0, 15.0, 5.0), 0.0)])
+def test_chebyshev_bounds_enclose_the_real_spectrum(dim, N, omega, shift):
+    """For upwind convection-diffusion operators (diagonally similar to
+    symmetric ones) J = I - diag(T)^{-1} T has a real spectrum, and the two
+    Gershgorin-type bounds enclose it."""
+    A = convdiff_matrix(dim, N, omega)
+    S = (A + shift * sp.identity(A.shape[0])).toarray()
+    col = OP.two_coloring(A)
+    T = _schur_dense(S, col)
+    J = np.eye(T.shape[0]) - T / np.diag(T)[:, None]
+    ev = np.linalg.eigvals(J)
+    assert np.abs(ev.imag).max() < 1e-10
+    lo, hi = OP.schur_poly_bounds(sp.csr_matrix(T), np.diag(S)[col == 1])
+    assert lo <= ev.real.min() + 1e-12 and ev.real.max() <= hi + 1e-12
+    assert lo <= 0.0 < hi < 1.0
+
+
+def test_chebyshev_error_is_the_scaled_chebyshev_polynomial():
+    """After k Chebyshev steps from zero the black-row error is
+    T_{k+1}(G / sigma) / T_{k+1}(1 / sigma) applied to the exact Schur solve,
+    G = I - gamma diag(T)^{-1} T: evaluated here through G's eigenvectors and
+    numpy's Chebyshev series, independently of the three-term recurrence."""
+    A = convdiff_matrix(2, 9, (25.0, -12.0))
+    n = A.shape[0]
+    s = -30.0
+    S = (A + s * sp.identity(n)).toarray()
+    col = OP.two_coloring(A)
+    blk = col == 1
+    T = _schur_dense(S, col)
+    V = np.random.default_rng(21).standard_normal((n, 2))
+    xs = np.linalg.solve(S, V)[blk]  # black part of S^{-1} V = T^{-1} y_b
+    lo, hi = OP.schur_poly_bounds(sp.csr_matrix(T), np.diag(S)[blk])
+    gamma = 2.0 / (2.0 - lo - hi)
+    sigma = (hi - lo) / (2.0 - lo - hi)
+    G = np.eye(T.shape[0]) - gamma * T / np.diag(T)[:, None]
+    mu, X = np.linalg.eig(G)
+    for k in (1, 2, 5, 9):
+        c = np.zeros(k + 2)
+        c[k + 1] = 1.0
+        p = np.polynomial.chebyshev.chebval(mu / sigma, c) / np.polynomial.chebyshev.chebval(1.0 / sigma, c)
+        err = (X @ (p[:, None] * np.linalg.solve(X, xs))).real
+        got = OP.rb_precond_apply(A, s, V, k, poly="chebyshev")[blk]
+        assert np.linalg.norm((xs - got) - err) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_chebyshev_beats_jacobi_and_converges():
+    """Past a few steps the Chebyshev error falls below the Jacobi one (for
+    very few steps Jacobi can be ahead: it damps the oscillatory modes
+    faster than the uniform Chebyshev bound), and both reach the exact
+    inverse."""
+    A = convdiff_matrix(3, 6, (20.0, 10.0, 5.0))
+    n = A.shape[0]
+    s = -15.0
+    V = np.random.default_rng(22).standard_normal((n, 3))
+    X = spla.spsolve((A + s * sp.identity(n)).tocsc(), V)
+    e = lambda k, poly: np.linalg.norm(OP.rb_precond_apply(A, s, V, k, poly=poly) - X) / np.linalg.norm(X)
+    for k in (10, 16):
+        assert e(k, "chebyshev") < 0.5 * e(k, "jacobi")
+    assert e(80, "chebyshev") < 1e-12
+    # no steps: the ILU(0) step whichever the polynomial
+    assert np.array_equal(OP.rb_precond_apply(A, s, V, 0, poly="chebyshev"), OP.rb_precond_apply(A, s, V, 0))
+
+
+def test_chebyshev_falls_back_to_jacobi_without_diagonal_dominance():
+    """The 1-D Laplacian stencil (-1, 2, -1) without a shift: interior rows of
+    J sum to exactly 1, so hi = 1 and the steps are the Jacobi ones."""
+    n = 31
+    A = sp.diags([-np.ones(n - 1), 2.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    col = OP.two_coloring(A)
+    T = _schur_dense(A.toarray(), col)
+    assert OP.schur_poly_bounds(sp.csr_matrix(T), np.full(int(col.sum()), 2.0))[1] == 1.0
+    V = np.random.default_rng(23).standard_normal((n, 2))
+    assert np.array_equal(OP.rb_precond_apply(A, 0.0, V, 5, poly="chebyshev"), OP.rb_precond_apply(A, 0.0, V, 5))
+    with pytest.raises(ValueError):
+        OP.rb_precond_apply(A, 0.0, V, 5, poly="cg")
