@@ -37,18 +37,29 @@ METRIC = "time-to-residual 1e-8 + SpMM HBM GB/s; inexact-FP32 vs exact-FP64; p99
 HBM_PEAK_GBS = 8000.0
 # MI355X FP32 vector (non-matrix) peak
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# Jacobi sweeps on the Schur complement in the preconditioned inner solves
-# of config 2, run two per launch (FP64 solve: 16, 20, 24, 28, 32, 40
-# sweeps gave 0.103, 0.092, 0.090, 0.089, 0.089, 0.089 s)
+# Steps on the Schur complement in the preconditioned inner solves of
+# config 2: Chebyshev steps, one per launch (FP64 solve: 12, 16, 24, 32
+# steps gave 57.3, 51.6, 48.5, 48.0 ms), against Jacobi sweeps run two per
+# launch (16, 20, 24, 28, 32, 40 sweeps: 103, 92, 90, 89, 89, 89 ms; 85.4 ms
+# at 32 in the run of the Chebyshev scan)
 PRECOND_SWEEPS = 32
+C2_PRECOND_POLY = 1
 # the batch and serving workloads' small problems (grid sides 32..128) gain less
 # per sweep: 24 (batch of 256: 1.01 s at 24 against 1.14 s at 32)
 BATCH_PRECOND_SWEEPS = 24
+BATCH_PRECOND_POLY = 0
 # the 3-D configuration's Schur rows couple 18 neighbours instead of 8, so a
-# sweep costs more there and fewer pay: FP64 relaxed solves with 2, 4, 6, 8,
-# 10, 12, 16, 20, 24, 32, 40 sweeps took 151.6, 120.4, 107.6, 102.0, 98.6,
-# 96.9, 95.0, 95.3, 98.3, 100.0, 105.3 ms (FP32 inner: 78-81 ms from 8 to 16)
-C3_PRECOND_SWEEPS = 16
+# step costs more there: FP64 relaxed solves with 4, 6, 8, 10, 12, 16, 20,
+# 24, 32, 40 Chebyshev steps took 76.4, 66.1, 62.0, 59.3, 57.8, 55.8, 56.7,
+# 55.3, 60.7, 65.0 ms (inner block steps 109 + 82 at 4 down to 26 + 21 at
+# 40); with Jacobi sweeps 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40 took 151.6,
+# 120.4, 107.6, 102.0, 98.6, 96.9, 95.0, 95.3, 98.3, 100.0, 105.3 ms (before
+# later changes of the other kernels; 92.4 ms at 16 in the Chebyshev scan)
+C3_PRECOND_SWEEPS = 24
+# 0: Jacobi sweeps; 1: Chebyshev steps on the same splitting
+C3_PRECOND_POLY = 1
+# Example 1 (symmetric 3-D operators): Jacobi sweeps, as its tests run it
+EX1_PRECOND_SWEEPS = 16
 
 
 def parse():
@@ -74,6 +85,16 @@ def parse():
     ap.add_argument("--precond-sweeps", type=int, default=BATCH_PRECOND_SWEEPS,
                     help="batch / serve: Schur sweeps of the red-black ILU(0) preconditioner "
                          "(-1: unpreconditioned)")
+    ap.add_argument("--precond-poly", type=int, default=BATCH_PRECOND_POLY, choices=[0, 1],
+                    help="batch / serve: 1 for Chebyshev steps on the Schur complement")
+    ap.add_argument("--c2-sweeps", type=int, default=PRECOND_SWEEPS,
+                    help="c2: Schur sweeps (or Chebyshev steps) of the preconditioner")
+    ap.add_argument("--c2-poly", type=int, default=C2_PRECOND_POLY, choices=[0, 1],
+                    help="c2: 1 for Chebyshev steps on the Schur complement, 0 for Jacobi sweeps")
+    ap.add_argument("--c3-sweeps", type=int, default=C3_PRECOND_SWEEPS,
+                    help="c3: Schur sweeps (or Chebyshev steps) of the preconditioner")
+    ap.add_argument("--c3-poly", type=int, default=C3_PRECOND_POLY, choices=[0, 1],
+                    help="c3: 1 for Chebyshev steps on the Schur complement, 0 for Jacobi sweeps")
     return ap.parse_args()
 
 
@@ -117,7 +138,7 @@ def bench_c2(args, L, WL):
     fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
     ctx = L.Context(0)
     base = dict(tol=P.tol, b_is_transposed=1)
-    pre = dict(precond="rbilu0", precond_sweeps=PRECOND_SWEEPS)
+    pre = _pre(args.c2_sweeps, args.c2_poly)
     relaxed = L.default_opts(selection="mid", **base, **pre)
 
     def solve(opts):
@@ -149,6 +170,7 @@ def bench_c2(args, L, WL):
                          ("fp32_inner_relaxed", dict(selection="mid", precision="fp32", **pre)),
                          ("relaxed_graph_replay", dict(selection="mid", use_graph=1, **pre)),
                          ("relaxed_single_sweep_launches", dict(selection="mid", precond_pairs=0, **pre)),
+                         ("relaxed_jacobi32_paired", dict(selection="mid", **_pre(32))),
                          ("unpreconditioned_relaxed", dict(selection="mid")),
                          ("unpreconditioned_fp32_inner_relaxed", dict(selection="mid", precision="fp32"))]:
             o = L.default_opts(**base, **kw)
@@ -222,7 +244,8 @@ def bench_c2(args, L, WL):
                                "FP64, relaxed (back-looking mid) inner tolerances",
                    "n": P.A.n, "m": P.B.n, "r": P.r, "nshifts": P.nshifts, "tol": P.tol,
                    "inner": f"right-preconditioned block GMRES(30) + FP64 refinement; red-black "
-                            f"ILU(0) with {PRECOND_SWEEPS} Jacobi sweeps on the Schur complement",
+                            f"ILU(0) with {args.c2_sweeps} "
+                            f"{'Chebyshev steps' if args.c2_poly else 'Jacobi sweeps'} on the Schur complement",
                    "seed": P.seed},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -306,9 +329,15 @@ def _lowrank_diff(res_a, res_b):
     return float(torch.linalg.norm(R1 @ R2.T) / torch.linalg.norm(Rb1 @ Rb2.T))
 
 
-def _pre(sweeps):
-    """Preconditioner options for a sweep count (-1: none)."""
-    return {} if sweeps < 0 else dict(precond="rbilu0", precond_sweeps=sweeps)
+def _pre(sweeps, poly=0):
+    """Preconditioner options for a sweep count (-1: none); poly 1: Chebyshev
+    steps on the Schur complement instead of Jacobi sweeps."""
+    if sweeps < 0:
+        return {}
+    o = dict(precond="rbilu0", precond_sweeps=sweeps)
+    if poly and sweeps > 0:
+        o["precond_poly"] = 1
+    return o
 
 
 def _host_info():
@@ -400,7 +429,8 @@ def bench_headline(args, L, WL):
     pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
     fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
     base = dict(tol=P.tol, b_is_transposed=1)
-    pre = _pre(C3_PRECOND_SWEEPS)
+    pre = _pre(args.c3_sweeps, args.c3_poly)
+    steps_name = "Chebyshev steps" if pre.get("precond_poly") else "Jacobi sweeps"
     relaxed = L.default_opts(selection="mid", **base, **pre)
     fp = _fingerprint_c3()
 
@@ -443,6 +473,7 @@ def bench_headline(args, L, WL):
                          ("fp64_exact_precond", dict(selection="relative", rho=1e-12, **pre)),
                          ("fp32_inner_exact_precond", dict(selection="relative", rho=1e-12,
                                                            precision="fp32", **pre)),
+                         ("fp64_relaxed_jacobi16", dict(selection="mid", **_pre(16))),
                          ("fp64_relaxed", dict(selection="mid")),
                          ("fp32_inner_relaxed", dict(selection="mid", precision="fp32")),
                          ("fp64_exact", dict(selection="relative", rho=1e-12))]:
@@ -467,7 +498,8 @@ def bench_headline(args, L, WL):
         extra["speedup_fp32_relaxed_vs_fp64_exact_unprecond"] = round(
             times["fp64_exact"] / times["fp32_inner_relaxed"], 3)
         extra["speedup_precond_fp64_relaxed"] = round(times["fp64_relaxed"] / sec, 3)
-        extra["config2_fp64_relaxed_precond"] = _config2_quick(L, WL, ctx)
+        extra["speedup_chebyshev_vs_jacobi16"] = round(times["fp64_relaxed_jacobi16"] / sec, 3)
+        extra["config2_fp64_relaxed_precond"] = _config2_quick(L, WL, ctx, args)
 
     roof = None
     if not args.no_roofline:
@@ -539,7 +571,7 @@ def bench_headline(args, L, WL):
                                "FP64, relaxed (back-looking mid) inner tolerances",
                    "n": P.A.n, "m": P.B.n, "r": P.r, "nshifts": P.nshifts, "tol": P.tol,
                    "inner": f"right-preconditioned block GMRES(30) + FP64 refinement; red-black "
-                            f"ILU(0) with {C3_PRECOND_SWEEPS} Jacobi sweeps on the Schur complement",
+                            f"ILU(0) with {args.c3_sweeps} {steps_name} on the Schur complement",
                    "seed": P.seed},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -548,7 +580,7 @@ def bench_headline(args, L, WL):
     print(json.dumps(line))
 
 
-def _config2_quick(L, WL, ctx):
+def _config2_quick(L, WL, ctx, args):
     """The 2-D FP64 configuration's relaxed, preconditioned solve (median of 3)."""
     import numpy as np
     import torch
@@ -558,7 +590,7 @@ def _config2_quick(L, WL, ctx):
     f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
     pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
     fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
-    o = L.default_opts(selection="mid", tol=P.tol, b_is_transposed=1, **_pre(PRECOND_SWEEPS))
+    o = L.default_opts(selection="mid", tol=P.tol, b_is_transposed=1, **_pre(args.c2_sweeps, args.c2_poly))
     ctx.solve(HA, HBt, fd, gd, pA, pB, o)
     ts = []
     for _ in range(3):
@@ -816,8 +848,9 @@ def bench_ex1(args, L, WL):
     and 30^3, r = 5, 20 shifts, tau = 1e-8) with the inner-tolerance
     strategies the paper compares for it: dynamic thresholds with and without
     back-looking, the two one-sided selections, fixed tolerances and exact
-    inner solves, FP64, right-preconditioned (red-black ILU(0), C3_PRECOND_SWEEPS
-    Schur sweeps; the paper used incomplete Cholesky on a CPU), plus FP32
+    inner solves, FP64, right-preconditioned (red-black ILU(0), EX1_PRECOND_SWEEPS
+    Jacobi sweeps on the Schur complement; the paper used incomplete Cholesky
+    on a CPU), plus FP32
     inner work with back-looking.  Per run: median seconds, outer steps, inner
     block steps per side, true residual; and the saving of each dynamic run
     against fixed tolerances (the paper reports 17-25% for this example)."""
@@ -829,7 +862,7 @@ def bench_ex1(args, L, WL):
     pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
     fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
     ctx = L.Context(0)
-    pre = _pre(C3_PRECOND_SWEEPS)
+    pre = _pre(EX1_PRECOND_SWEEPS)
     runs = [("dynamic_bl", dict(selection="mid", backlook=1)),
             ("dynamic_plain", dict(selection="mid", backlook=0)),
             ("dynamic_bl_A", dict(selection="tightA")),
@@ -863,7 +896,7 @@ def bench_ex1(args, L, WL):
     ctx.close()
     print(json.dumps({"workload": "Sec. 4 Example 1 analogue: symmetric 3-D Laplacians 50^3 (n=125000) and "
                                   "30^3 (m=27000), r=5, 20 Wachspress shifts, tau=1e-8, FP64, "
-                                  f"red-black ILU(0) with {C3_PRECOND_SWEEPS} Schur sweeps",
+                                  f"red-black ILU(0) with {EX1_PRECOND_SWEEPS} Jacobi sweeps",
                       "n": P.A.n, "m": P.B.n, "runs": out, "saving_vs_fixed": savings}))
 
 
@@ -908,7 +941,7 @@ def bench_batch(args, L, WL):
     ctx = L.Context(0)
     # controller in the balanced frame (the library default): the batch
     # mixes grid sides 32..128
-    o = L.default_opts(precision="fp32", **_pre(args.precond_sweeps))
+    o = L.default_opts(precision="fp32", **_pre(args.precond_sweeps, args.precond_poly))
     ctx.batch_solve(items[: min(8, count)], o)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -919,7 +952,7 @@ def bench_batch(args, L, WL):
     # the same batch with event-timed launches: aggregate shifted-product and
     # preconditioner rates over all problems
     ctx.profile_reset()
-    op = L.default_opts(precision="fp32", profile=1, **_pre(args.precond_sweeps))
+    op = L.default_opts(precision="fp32", profile=1, **_pre(args.precond_sweeps, args.precond_poly))
     ctx.batch_solve(items, op)
     agg = {}
     for cls, key in ((L.PROF_SPMM, "spmm"), (L.PROF_GRAM, "gram"), (L.PROF_PRECOND, "precond")):
@@ -954,7 +987,7 @@ def bench_batch(args, L, WL):
                          f"process per core"}
         print(f"[bench batch] oracle on {cores} cores: {wall:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps({"workload": f"batch of {count} 2-D problems, FP32 inner / FP64 outer",
-                      "precond_sweeps": args.precond_sweeps,
+                      "precond_sweeps": args.precond_sweeps, "precond_poly": args.precond_poly,
                       "batched_s": round(tb, 4), "sequential_s": round(ts, 4),
                       "speedup": round(ts / tb, 2), "solves_per_s": round(count / tb, 2), "status": st,
                       "outer_steps_min_max": [min(ks), max(ks)],
@@ -1035,7 +1068,7 @@ def bench_serve(args, L, WL):
     import torch
     count = args.count or 2000
     warm = 100
-    opts = L.default_opts(precision="fp32", kmax=100, **_pre(args.precond_sweeps))
+    opts = L.default_opts(precision="fp32", kmax=100, **_pre(args.precond_sweeps, args.precond_poly))
     ctx = L.Context(0)
     reqs = WL.serving_requests(count + warm, rate=args.rate)
     prepared = _serve_prepare(L, WL, reqs)
@@ -1094,7 +1127,7 @@ def bench_serve(args, L, WL):
         print(f"[serve] oracle sample: {json.dumps(orac)}", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps({"workload": f"{count} Poisson requests after {warm} warm-up, offered {args.rate}/s",
-                      "precond_sweeps": args.precond_sweeps, "runs": runs, "true_residual": resid,
+                      "precond_sweeps": args.precond_sweeps, "precond_poly": args.precond_poly, "runs": runs, "true_residual": resid,
                       "x_vs_oracle_sample": orac}))
 
 

@@ -169,6 +169,20 @@ typedef struct {
                           tiles (2-D stencils), in batches of at most 262144
                           black rows.  The results equal one sweep per
                           launch bit for bit.  0: one per launch           */
+  int32_t precond_poly;   /* LRADI_PRECOND_RBILU0 with precond_sweeps > 0:
+                          0 (default): the sweeps are Jacobi steps; 1:
+                          Chebyshev steps (Golub-Varga semi-iteration on the
+                          same splitting) over the interval that two
+                          Gershgorin-type bounds give for the spectrum of
+                          I - diag(T)^-1 T, recomputed per shift; they
+                          assume that spectrum real, which holds when T is
+                          diagonally similar to a symmetric matrix (e.g.
+                          constant-coefficient upwind stencils); without
+                          diagonal dominance (bound >= 1) the steps fall
+                          back to Jacobi.  Same products with T per step;
+                          one sweep per launch (no pairs).  An extension,
+                          not in the paper                                */
+  int32_t pad_;
 } lradi_opts;
 
 /* Per inner solve statistics (lradi_shifted_solve). */

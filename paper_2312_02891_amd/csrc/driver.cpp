@@ -411,7 +411,7 @@ struct SysWork {
   // cplx: the real form of a complex shifted system on 2 A->n rows (r <= 4,
   // no preconditioner)
   int init(const DevCSR* A, const double* W, int r, int m, int prec, int max_inner, double floor_rel,
-           int sweeps = -1, bool pairs = false, bool cplx = false) {
+           int sweeps = -1, bool pairs = false, bool cplx = false, int poly = 0) {
     if (r < 1 || r > kMaxR || m < 1 || m > kMaxM)
       return set_error("r must be in 1..%d and restart in 1..%d", kMaxR, kMaxM), LRADI_EINVAL;
     // a block of more columns than rows has no full-rank basis
@@ -436,7 +436,7 @@ struct SysWork {
                             mm * 4 * rr * rr * 8,      // Qs
                             (mm + 1) * rr * rr * 8,    // Gv
                             mm * rr * rr * 8,          // yv
-                            512 * 8,                   // sm
+                            kSmDoubles * 8,            // sm
                             sweeps >= 0 ? (mm + 1) * n * rr * tsz : 0,  // P
                             sweeps > 0 ? n * rr * tsz : 0,              // Yb
                             sweeps > 0 ? 2 * n * rr * tsz : 0,          // Eb (two compact iterates)
@@ -506,6 +506,7 @@ struct SysWork {
       d.rbrows = B.rbrows.as<int>();
       d.nred = B.nred;
       d.sweeps = sweeps;
+      d.poly = sweeps > 0 ? poly : 0;
       d.halo_off = B.halo_off.as<int>();
       d.halo = B.halo.as<int>();
       d.t2lc = B.t2lc.as<int>();
@@ -516,7 +517,8 @@ struct SysWork {
       const size_t nb = n - (size_t)B.nred, lds = (size_t)B.maxreg * rr * tsz;
       const bool fit = B.ntile > 0 && B.tile == (int)((nb + nwg - 1) / nwg) && lds <= (size_t)kPairLdsMax &&
                        (double)(nb + B.nhalo) <= kPairMaxRegion * (double)nb;
-      d.pair_lds = (pairs && sweeps >= 2 && fit) ? (int)lds : 0;
+      // (the paired kernel takes Jacobi steps only)
+      d.pair_lds = (pairs && sweeps >= 2 && fit && d.poly == 0) ? (int)lds : 0;
       d.diagT = (prec == LRADI_FP64) ? (const void*)B.diag64.p : (const void*)B.diag32.p;
       d.msT = B.ms64.p ? ((prec == LRADI_FP64) ? (const void*)B.ms64.p : (const void*)B.ms32.p) : nullptr;
       d.rbw = B.rbw;
@@ -601,7 +603,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.hc.resize(nsys);
   t.hmap.clear();
   int maxP = 1, maxB = 1, rfix = ws[0]->d.r, fuse = 1, precond = 0, sweeps = 0, pairs = 1, pair_lds = 0,
-      pair_fast = 1;
+      pair_fast = 1, poly = 0;
   long long black_rows = 0;
   int max_tile = 0, pre_slices = 1;
   for (int s = 0; s < nsys; ++s) {
@@ -620,6 +622,7 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
       precond = 1;
       sweeps = ws[s]->d.sweeps;
       if (ws[s]->d.pair_lds == 0) pairs = 0;
+      if (ws[s]->d.poly) poly = 1;
       pair_lds = std::max(pair_lds, ws[s]->d.pair_lds);
       const int nb = ws[s]->d.n - ws[s]->d.nred, tile = (nb + ws[s]->d.nwg - 1) / ws[s]->d.nwg;
       black_rows += nb;
@@ -674,14 +677,17 @@ int upload_table(lradi_ctx* ctx, const std::vector<SysWork*>& ws, Table& t) {
   t.b.rfix = rfix;
   t.b.precond = precond;
   t.b.sweeps = sweeps;
+  t.b.poly = poly;
   t.b.pairs = precond && pairs && sweeps >= 2 && black_rows <= kPairMaxRows;
   t.b.pair_lds = t.b.pairs ? pair_lds : 0;
   // (the register-held columns with wider or mixed blocks would spill)
   // (even blocks take two lanes per tile row in that kernel)
   t.b.pair_fast =
       t.b.pairs && pair_fast && rfix >= 1 && rfix <= 4 && max_tile * (rfix % 2 == 0 ? 2 : 1) <= kTPB;
-  // forward, back, the sweeps, and (with sweeps) the launch that builds T
-  t.b.precond_launches = precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) + (sweeps > 0 ? 1 : 0) : 0;
+  // forward, back, the sweeps, and (with sweeps) the launches that build T
+  // and the Chebyshev bounds
+  t.b.precond_launches =
+      precond ? 2 + (t.b.pairs ? (sweeps + 1) / 2 : sweeps) + (sweeps > 0 ? 1 + poly : 0) : 0;
   t.b.pre_slices = pre_slices;
   return LRADI_OK;
 }
@@ -897,6 +903,7 @@ int check_opts(const lradi_opts& o) {
   if (o.precond_sweeps < 0 || o.precond_sweeps > 64)
     return set_error("precond_sweeps must be in 0..64"), LRADI_EINVAL;
   if (o.precond_pairs != 0 && o.precond_pairs != 1) return set_error("precond_pairs must be 0 or 1"), LRADI_EINVAL;
+  if (o.precond_poly != 0 && o.precond_poly != 1) return set_error("precond_poly must be 0 or 1"), LRADI_EINVAL;
   return LRADI_OK;
 }
 
@@ -1236,13 +1243,13 @@ int prob_init(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P0, bool c
   LRADI_HIP(hipMemcpyAsync(q.shB.p, P.shiftsB, sizeof(double) * P.nshifts, hipMemcpyHostToDevice, st));
   const double fl = floor_for(o);
   LRADI_TRY(q.wa.init(&q.A, q.W.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw,
-                      o.precond_pairs != 0, q.cplx));
+                      o.precond_pairs != 0, q.cplx, o.precond_poly));
   LRADI_TRY(q.wa.tune(c, q.A, o.spmm_lanes));
   if (q.sym) {
     q.wb.init_mirror(q.wa);
   } else {
     LRADI_TRY(q.wb.init(&q.Bt, q.T.as<double>(), q.r, o.restart, o.precision, o.max_inner, fl, sw,
-                        o.precond_pairs != 0, q.cplx));
+                        o.precond_pairs != 0, q.cplx, o.precond_poly));
     LRADI_TRY(q.wb.tune(c, q.Bt, o.spmm_lanes));
   }
   LRADI_TRY(q.done.init());
@@ -1459,6 +1466,7 @@ void lradi_default_opts(lradi_opts* o) {
   o->lookahead = 2;
   o->use_graph = 0;
   o->precond_pairs = 1;
+  o->precond_poly = 0;
 }
 
 const char* lradi_strerror(int st) {
@@ -1586,7 +1594,8 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
   if (o.restart < 1 || o.restart > kMaxM || o.max_inner < 1 ||
       (o.precision != LRADI_FP64 && o.precision != LRADI_FP32_INNER) ||
       (o.precond != LRADI_PRECOND_NONE && o.precond != LRADI_PRECOND_RBILU0) || o.precond_sweeps < 0 ||
-      o.precond_sweeps > 64 || (o.precond_pairs != 0 && o.precond_pairs != 1))
+      o.precond_sweeps > 64 || (o.precond_pairs != 0 && o.precond_pairs != 1) ||
+      (o.precond_poly != 0 && o.precond_poly != 1))
     return set_error("lradi_shifted_solve: bad options"), LRADI_EINVAL;
   const int sw = sweeps_for(o);
   LRADI_HIP(hipSetDevice(c->device));
@@ -1600,7 +1609,7 @@ int lradi_shifted_solve(lradi_ctx* c, int nsys, const lradi_csr* const* A, const
     if (sw >= 0) LRADI_TRY(mats[s].prepare_rb(c, A[s], nullptr, c->stream, o.precision == LRADI_FP32_INNER));
     work[s] = std::make_unique<SysWork>();
     LRADI_TRY(work[s]->init(&mats[s], W[s], r[s], o.restart, o.precision, o.max_inner, floor_for(o), sw,
-                            o.precond_pairs != 0));
+                            o.precond_pairs != 0, false, o.precond_poly));
     LRADI_TRY(work[s]->tune(c, mats[s], o.spmm_lanes));
     work[s]->arm(Z[s], shift[s], delta[s]);
     ws[s] = work[s].get();

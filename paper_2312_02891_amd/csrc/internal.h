@@ -202,6 +202,8 @@ struct SysDesc {
   const int* rbrows;    // red rows ascending, then black rows ascending
   int nred;             // number of red rows
   int sweeps;           // Jacobi sweeps on the Schur complement
+  int poly;             // 1: the sweeps are Chebyshev steps (bounds and
+                        // coefficients in sm + SM_CHEB), 0: Jacobi
   const void* diagT;    // diagonal of A per row, basis precision
   const void* msT;      // pencils: M's row sums (the preconditioner's shift
                         // weights), basis precision; null for M = I
@@ -265,7 +267,13 @@ struct SysCtl {
 };
 
 // small scratch slots (offsets into SysDesc::sm, 64 doubles each)
-enum SmSlot { SM_S1 = 0, SM_S1I = 64, SM_S2 = 128, SM_S2I = 192, SM_G = 256, SM_T = 320 };
+// SM_CHEB: the Chebyshev sweeps' spectral bounds of the current shift (hi,
+// then max(0, max P_ii / T_ii), as non-negative doubles combined by integer
+// atomic max), gamma (0: Jacobi fallback) and omega_2 .. omega_{sweeps+1}
+enum SmSlot { SM_S1 = 0, SM_S1I = 64, SM_S2 = 128, SM_S2I = 192, SM_G = 256, SM_T = 320, SM_CHEB = 384 };
+constexpr int kChebGamma = 2, kChebOmega = 3;  // offsets in SM_CHEB
+constexpr int kSmDoubles = 512;  // per-system small scratch (doubles)
+static_assert(SM_CHEB + kChebOmega + 64 <= kSmDoubles, "Chebyshev table exceeds the small scratch");
 
 // ---------------------------------------------------------------------------
 // error state
@@ -399,6 +407,8 @@ struct Batch {
   int rfix;            // common r of all systems, or 0 when they differ
   int precond;         // some system carries the red-black preconditioner
   int sweeps;          // its Jacobi sweeps (shared by the batch)
+  int poly;            // some system takes Chebyshev steps (a launch of
+                       // their spectral bounds per inner solve)
   int pairs;           // 1: two sweeps per launch (every preconditioned
                        // system has pair_lds > 0)
   int pair_lds;        // dynamic LDS bytes of a paired launch

@@ -449,6 +449,46 @@ __device__ inline void rb_black_fwd(const RbCtx<T>& x, int p, int i, const T* __
   }
 }
 
+// diag(T)_i of black row i (colour position p), the forward stage's formula
+template <typename T>
+__device__ inline T rb_tdiag(const RbCtx<T>& x, int p, int i) {
+  T td = rb_dsh(x, i);
+  for (int u = 0; u < x.w; ++u) {
+    const size_t e = (size_t)u * x.n + p;
+    const int j = x.ci[e];
+    if (j == i) continue;  // unused slot
+    const T wgt = x.val[e] / rb_dsh(x, j);
+    td = td - wgt * x.tv[e];
+  }
+  return td;
+}
+
+// Chebyshev steps on T z = y (the Golub-Varga semi-iterative method on the
+// Jacobi splitting, J = I - diag(T)^{-1} T).  With J's spectrum real and in
+// [lo, hi], hi < 1: the extrapolated step G x + gamma c, G = gamma J +
+// (1 - gamma) I, c = diag(T)^{-1} y, gamma = 2 / (2 - lo - hi), has spectral
+// radius sigma = (hi - lo) / (2 - lo - hi); from x_0 = 0, x_1 = gamma c and
+// x_{k+1} = omega_{k+1} (G x_k + gamma c - x_{k-1}) + x_{k-1}, omega_2 =
+// 2 / (2 - sigma^2), omega_{k+1} = 1 / (1 - sigma^2 omega_k / 4).  cb holds
+// hi and -lo (SM_CHEB); gamma 0 means no dominance (hi >= 1): Jacobi steps.
+__device__ inline double cheb_gamma(const double* cb) {
+  const double hi = cb[0], lo = -cb[1];
+  return hi < 1.0 ? 2.0 / (2.0 - lo - hi) : 0.0;
+}
+
+__device__ inline void cheb_table(double* cb, int k) {
+  const double g = cheb_gamma(cb);
+  cb[kChebGamma] = g;
+  if (g == 0.0) return;
+  const double hi = cb[0], lo = -cb[1];
+  const double sg = (hi - lo) / (2.0 - lo - hi), s2 = sg * sg;
+  double om = 0.0;
+  for (int t = 1; t <= k; ++t) {
+    om = t == 1 ? 2.0 / (2.0 - s2) : 1.0 / (1.0 - s2 * om / 4.0);
+    cb[kChebOmega + t - 1] = om;
+  }
+}
+
 // T's off-diagonal values of black position pb (row i, colour position p)
 // for the current shift: slot q (column l) = -sum over the red neighbours j
 // of i that neighbour l of a_ij a_jl / (d_j + s), walking i's and then j's
@@ -544,6 +584,81 @@ __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* _
   for (int q = 0; q < RQ; ++q) dst[drow * R + q0 + q] = acc[q] * it;
 }
 
+// one Chebyshev step for black position pb: dst row drow = prev + om (G
+// x_s + gamma c - prev) with x_s = src, G x_s + gamma c = x_s + gamma (J x_s +
+// c - x_s), J x_s + c the Jacobi update of rb_sweep_row and prev = x_{s-1}
+// (null: x_0 = 0); prev and dst may be the same block (each row reads its
+// own entries before writing them)
+template <typename T, int R, int RQ = R>
+__device__ inline void rb_cheb_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src, const T* prev,
+                                   T* dst, size_t drow, int q0, T gam, T om) {
+  T acc[RQ];
+  rb_sweep_acc<T, R, RbRows<T, R>, RQ>(D, pb, nb, D.t2ci, nb, pb, pb, RbRows<T, R>{src}, q0, acc);
+  const T it = static_cast<const T*>(D.It)[pb];
+#pragma unroll
+  for (int q = 0; q < RQ; ++q) {
+    const T xs = src[(size_t)pb * R + q0 + q];
+    const T xp = prev ? prev[(size_t)pb * R + q0 + q] : T(0);
+    const T g = xs + gam * (acc[q] * it - xs);
+    dst[drow * R + q0 + q] = xp + om * (g - xp);
+  }
+}
+
+// Spectral bounds of the Chebyshev steps for the current shift, once per
+// inner solve after T's values and 1/diag(T) are built: per black position
+// pb the row sum of the symmetrised J, sum_l sqrt(|T_pl T_lp| / |T_pp T_ll|),
+// and P_pp / T_pp = S_pp / T_pp - 1 (P = F D_r^{-1} E); their maxima over the
+// system (floored at 0) by integer atomic max of the non-negative doubles'
+// bit patterns into SM_CHEB, which T's build cleared.  Both are Gershgorin
+// bounds when T is diagonally similar to a symmetric matrix.
+template <typename T>
+__device__ inline void rb_bounds(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x) {
+  const int nb = D.n - D.nred;
+  const int bc = (nb + D.nwg - 1) / D.nwg;
+  const int sub = (bc + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int w0 = c.w * bc;
+  const int p0 = w0 + (int)blockIdx.y * sub, p1 = min(nb, min(w0 + bc, p0 + sub));
+  const T* tv = static_cast<const T*>(D.t2val);
+  const T* It = static_cast<const T*>(D.It);
+  double hi = 0.0, lr = 0.0;
+  for (int pb = p0 + (int)threadIdx.x; pb < p1; pb += kTPB) {
+    const double ip = (double)It[pb];
+    double sum = 0.0;
+    for (int u = 0; u < D.t2w; ++u) {
+      const int l = D.t2ci[(size_t)u * nb + pb];
+      if (l == pb) continue;  // unused slot
+      double b = 0.0;  // T_lp: row l's slot with column pb
+      for (int q = 0; q < D.t2w; ++q)
+        if (D.t2ci[(size_t)q * nb + l] == pb) {
+          b = (double)tv[(size_t)q * nb + l];
+          break;
+        }
+      sum += sqrt(fabs((double)tv[(size_t)u * nb + pb] * b * ip * (double)It[l]));
+    }
+    hi = fmax(hi, sum);
+    lr = fmax(lr, (double)rb_dsh(x, D.rbrows[D.nred + pb]) * ip - 1.0);
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    hi = fmax(hi, __shfl_xor(hi, o));
+    lr = fmax(lr, __shfl_xor(lr, o));
+  }
+  __shared__ double red[2][kTPB / 64];
+  if (threadIdx.x % 64 == 0) {
+    red[0][threadIdx.x / 64] = hi;
+    red[1][threadIdx.x / 64] = lr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kTPB / 64; ++k) {
+      hi = fmax(hi, red[0][k]);
+      lr = fmax(lr, red[1][k]);
+    }
+    unsigned long long* cb = reinterpret_cast<unsigned long long*>(D.sm + SM_CHEB);
+    atomicMax(cb, (unsigned long long)__double_as_longlong(hi));
+    atomicMax(cb + 1, (unsigned long long)__double_as_longlong(lr));
+  }
+}
+
 // black iterate t (< sweeps) in black-position order: two compact blocks in
 // Eb, alternating; the last iterate goes to P_j's black rows instead
 template <typename T>
@@ -556,10 +671,10 @@ __device__ inline T* rb_compact(const SysDesc& D, int nb, int t) {
 // launch, or two (pair) with a single last one for an odd count
 __device__ inline int rb_launch_index(int stage, int pair) { return pair ? (stage - 1) / 2 : stage - 1; }
 
-// KIND 0: fwd (black rows); 1: Jacobi sweep `stage` (black rows); 2: back
-// (red rows); 5: T's values for the shift (black rows, at the first Arnoldi
-// step of an inner solve, in a launch of its own so that the forward stage
-// keeps few registers)
+// KIND 0: fwd (black rows); 1: Jacobi or Chebyshev sweep `stage` (black
+// rows); 2: back (red rows); 5: T's values for the shift, and with Chebyshev
+// steps 1/diag(T) (black rows, at the first Arnoldi step of an inner solve,
+// in a launch of its own so that the forward stage keeps few registers)
 template <typename T, int R, int KIND>
 __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>& x, const T* V, T* Pj,
                                int stage, int pair) {
@@ -579,6 +694,15 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
   const int w0 = c.w * bc;
   const int p0 = w0 + (int)blockIdx.y * sub, p1 = min(cnt, min(w0 + bc, p0 + sub));
   const int lane = (int)threadIdx.x % L, q0 = lane * RQ;
+  // Chebyshev steps (gamma 0: none, or the Jacobi fallback): the forward
+  // stage's x_1 = gamma c, a sweep's gamma and omega_{stage+1}
+  T cg = T(0), com = T(0);
+  if constexpr (KIND == 0 || KIND == 1) {
+    if (D.poly && D.sweeps > 0) {
+      cg = (T)cheb_gamma(D.sm + SM_CHEB);
+      if constexpr (KIND == 1) com = (T)D.sm[SM_CHEB + kChebOmega + stage - 1];
+    }
+  }
   for (int pp = p0 + (int)threadIdx.x / L; pp < p1; pp += kTPB / L) {
     const int p = off + pp;  // colour position
     const int i = D.rbrows[p];
@@ -594,20 +718,26 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
         T* Y = static_cast<T*>(D.Yb);
 #pragma unroll
         for (int q = 0; q < RQ; ++q) {
-          z0[(size_t)pp * R + q0 + q] = y[q] * it;
+          z0[(size_t)pp * R + q0 + q] = cg != T(0) ? cg * (y[q] * it) : y[q] * it;
           Y[(size_t)pp * R + q0 + q] = y[q];
         }
         if (lane == 0) static_cast<T*>(D.It)[pp] = it;
       }
     } else if constexpr (KIND == 5) {
-      if (D.sweeps > 0) rb_build_t<T>(D, x, p, pp, nb, i);
+      if (D.sweeps > 0) {
+        rb_build_t<T>(D, x, p, pp, nb, i);
+        if (D.poly) static_cast<T*>(D.It)[pp] = T(1) / rb_tdiag(x, p, i);
+      }
     } else if constexpr (KIND == 1) {
       const int ln = rb_launch_index(stage, pair);
       const T* src = rb_compact<T>(D, nb, ln);
-      if (stage == D.sweeps)
-        rb_sweep_row<T, R, RQ>(D, pp, nb, src, Pj, (size_t)i, q0);
+      T* nxt = rb_compact<T>(D, nb, ln + 1);
+      T* dst = stage == D.sweeps ? Pj : nxt;
+      const size_t drow = stage == D.sweeps ? (size_t)i : (size_t)pp;
+      if (cg != T(0))
+        rb_cheb_row<T, R, RQ>(D, pp, nb, src, stage >= 2 ? nxt : nullptr, dst, drow, q0, cg, com);
       else
-        rb_sweep_row<T, R, RQ>(D, pp, nb, src, rb_compact<T>(D, nb, ln + 1), (size_t)pp, q0);
+        rb_sweep_row<T, R, RQ>(D, pp, nb, src, dst, drow, q0);
     } else {  // back: z_r = (v_r - E z) / (d_r + s)
       T g[RQ];
 #pragma unroll
@@ -715,22 +845,24 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
 // LDS, so it counts one sweep plus its tables of region indices
 template <typename T, int KIND>
 __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
-  if (KIND == 5) return 0;  // once per inner solve, not per application
+  if (KIND >= 5) return 0;  // once per inner solve, not per application
   const unsigned long long nr = D.nred, nb = D.n - D.nred, n = D.n, R = D.r, t = sizeof(T);
   const unsigned long long sweep = nb * 4 + D.t2w * nb * (4 + t) + 3 * nb * R * t + nb * t;
   if (KIND == 0)
     return nb * 4 + D.rbw * nb * (4 + 2 * t) + n * t + n * R * t + nb * R * t +
            (D.sweeps > 0 ? nb * R * t + nb * t : 0);
-  if (KIND == 1) return sweep;
+  // a Chebyshev step also reads its own rows of x_s and x_{s-1}
+  if (KIND == 1) return sweep + (D.poly ? 2 * nb * R * t : 0);
   if (KIND >= 3) return sweep + D.t2w * nb * 4 + ((unsigned long long)D.nhalo + D.nwg + 1) * 4;
   return nr * 4 + D.rbw * nr * (4 + t) + nr * t + 2 * nr * R * t + nb * R * t;
 }
 
 // KIND 0: forward (stage 0), 1: sweep `stage`, 2: back, 3: sweeps `stage`
 // and `stage` + 1, 4: the same with the region columns in registers (pair =
-// 1: the launches of the sweeps are paired), 5: T's values for the shift
-// (first Arnoldi step of an inner solve only); one instance per kind, so
-// each allocates only the registers it needs
+// 1: the launches of the sweeps are paired), 5: T's values for the shift,
+// 6: the Chebyshev steps' spectral bounds (5 and 6 at the first Arnoldi step
+// of an inner solve only); one instance per kind, so each allocates only the
+// registers it needs
 template <typename T, int RF, int KIND>
 __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap, int stage, int pair,
@@ -748,10 +880,25 @@ __global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d,
   T* Pj = static_cast<T*>(D.P) + (size_t)j * blk;
   // the shift is fixed for an inner solve: T's values are built at its
   // first Arnoldi step (first cycle, j = 0) and kept over restarts
-  if constexpr (KIND == 5) {
-    if (!(ctl[c.s].cycles == 1 && j == 0)) return;
+  const bool first = ctl[c.s].cycles == 1 && j == 0;
+  if constexpr (KIND == 5 || KIND == 6) {
+    if (!first) return;
   }
-  if constexpr (KIND == 3 || KIND == 4) {
+  if constexpr (KIND == 5) {
+    // the bounds' maxima start from zero for each shift
+    if (D.poly && c.w == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      D.sm[SM_CHEB] = 0.0;
+      D.sm[SM_CHEB + 1] = 0.0;
+    }
+  }
+  if constexpr (KIND == 0) {
+    // the coefficients, once the bounds' launch has finished
+    if (D.poly && D.sweeps > 0 && first && c.w == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+      cheb_table(D.sm + SM_CHEB, D.sweeps);
+  }
+  if constexpr (KIND == 6) {
+    if (D.poly && D.sweeps > 0) rb_bounds<T>(D, c, x);
+  } else if constexpr (KIND == 3 || KIND == 4) {
     LRADI_RSEL(RF, D.r, (rb_pair<T, RR, KIND == 4>(D, c, Pj, stage, reinterpret_cast<T*>(rb_lds))));
   } else {
     LRADI_RSEL(RF, D.r, rb_rows<T, RR, KIND>(D, c, x, V, Pj, stage, pair));
@@ -1749,6 +1896,8 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
     const dim3 rgs(b.rowgrid, b.pre_slices > 1 ? b.pre_slices : 1);
     if (b.sweeps > 0)
       hipLaunchKernelGGL((k_precond<T, RF, 5>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
+    if (b.sweeps > 0 && b.poly)
+      hipLaunchKernelGGL((k_precond<T, RF, 6>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
     hipLaunchKernelGGL((k_precond<T, RF, 0>), rgs, tb, 0, st, b.d, b.ctl, b.rowmap, 0, b.pairs, b.prof_bytes);
     int stage = 1;
     if (b.pairs)

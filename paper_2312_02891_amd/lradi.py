@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
                 ("b_is_transposed", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("spmm_lanes", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("precond_sweeps", ctypes.c_int32), ("precond_pairs", ctypes.c_int32)]
+                ("precond_sweeps", ctypes.c_int32), ("precond_pairs", ctypes.c_int32),
+                ("precond_poly", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):

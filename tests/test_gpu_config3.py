@@ -3,7 +3,8 @@
 Reduced grids (A 24^3, B 18^3) with the configuration's convection vectors,
 r = 8 and 24 shifts, where the oracle's direct solves take seconds: every
 inner-solver variant (FP64 or FP32 inner Krylov work, with or without the
-red-black ILU(0) preconditioner, relaxed or exact-tolerance inner solves)
+red-black ILU(0) preconditioner and with Jacobi or Chebyshev steps on its
+Schur complement, relaxed or exact-tolerance inner solves)
 takes the oracle's number of outer steps, its X is within 1e-6 (relative
 Frobenius) of the oracle's X at that step and its true residual is below
 tau.  The full-size grids (64^3, 48^3) are compared with the oracle's stored
@@ -29,7 +30,11 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 # (name, options): relaxed = back-looking mid selection (Sec. 3.2), exact =
 # inner residual below 1e-12 ||rhs|| per solve
 PRE8 = dict(precond="rbilu0", precond_sweeps=8)
+CHEB = dict(precond="rbilu0", precond_sweeps=24, precond_poly=1)   # the bench's headline inner solver
 VARIANTS = [
+    ("fp64_relaxed_cheb", dict(selection="mid", **CHEB)),
+    ("fp32_relaxed_cheb", dict(selection="mid", precision="fp32", **CHEB)),
+    ("fp64_exact_cheb", dict(selection="relative", rho=1e-12, **CHEB)),
     ("fp64_relaxed", dict(selection="mid")),
     ("fp32_relaxed", dict(selection="mid", precision="fp32")),
     ("fp64_relaxed_precond", dict(selection="mid", **PRE8)),
@@ -123,9 +128,11 @@ def sketch_of(res, Ps, Qs):
     return [d[j * r] * (PZ[:, j * r:(j + 1) * r] @ YQ[j * r:(j + 1) * r, :]) for j in range(res.k)]
 
 
-@pytest.mark.parametrize("name,kw", [v for v in VARIANTS if v[0] in
-                                     ("fp64_relaxed_precond", "fp32_relaxed_precond", "fp64_exact")],
-                         ids=["fp64_relaxed_precond", "fp32_relaxed_precond", "fp64_exact"])
+FULL = ("fp64_relaxed_cheb", "fp32_relaxed_cheb", "fp64_exact_cheb", "fp64_relaxed_precond", "fp32_relaxed_precond",
+        "fp64_exact")
+
+
+@pytest.mark.parametrize("name,kw", [v for v in VARIANTS if v[0] in FULL], ids=[v[0] for v in VARIANTS if v[0] in FULL])
 def test_full_config3_matches_oracle_fingerprint(L, ctx, name, kw):
     """Full 3-D configuration against the oracle's stored fingerprint: same
     step count and gammas, and the sketch P^T X Q within 1e-6 relative
