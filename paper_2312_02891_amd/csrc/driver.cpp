@@ -502,6 +502,7 @@ struct SysWork {
       const lradi::RbData& B = *A->rb;
       d.t2w = B.t2w;
       d.t2ci = B.t2ci.as<int>();
+      d.t2rev = B.t2rev.as<int>();
       d.rbpos = B.rbpos.as<int>();
       d.rbrows = B.rbrows.as<int>();
       d.nred = B.nred;
@@ -742,6 +743,7 @@ struct TickGraphs {
       LRADI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       int rc = launch_tick(st, b, nullptr);
       if (rc == LRADI_OK && after) rc = after();
+      if (rc == LRADI_OK) rc = launch_tick_tail(st, b);
       if (rc == LRADI_OK && summary) rc = launch_summary(st, b, ctx->ring.d + s);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &g);
@@ -796,6 +798,7 @@ int run_ticks(lradi_ctx* ctx, const Batch& b, int lookahead, long max_ticks, boo
     } else {
       LRADI_TRY(launch_tick(st, b, profile ? &ctx->probes[slot] : nullptr));
       if (after) LRADI_TRY(after());
+      LRADI_TRY(launch_tick_tail(st, b));
       if (summary) LRADI_TRY(launch_summary(st, b, ctx->ring.d + slot));
     }
     LRADI_HIP(hipEventRecord(ctx->events[slot], st));
@@ -1018,6 +1021,7 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
   };
   const size_t ne = (size_t)h.rbw * nn;
   LRADI_TRY(up(R->t2ci, h.t2ci.data(), sizeof(int32_t) * h.t2ci.size()));
+  LRADI_TRY(up(R->t2rev, h.t2rev.data(), sizeof(int32_t) * h.t2rev.size()));
   LRADI_TRY(up(R->t2lc, h.t2lc.data(), sizeof(int32_t) * h.t2lc.size()));
   LRADI_TRY(up(R->halo_off, h.halo_off.data(), sizeof(int32_t) * h.halo_off.size()));
   LRADI_TRY(up(R->halo, h.halo.data(), sizeof(int32_t) * h.halo.size()));

@@ -225,6 +225,7 @@ struct SysDesc {
   // row's colour position
   int t2w;
   const int* t2ci;
+  const int* t2rev;     // the transposed entry's slot per slot (RbHost::t2rev)
   const int* rbpos;
   void* t2val;
   // paired sweeps: the black positions in tiles of ceil(nb / nwg), tile w
@@ -319,7 +320,7 @@ struct DevBuf {
 // position in rbw slot-major slots (column, value, transposed value), and
 // the Schur complement's column pattern on the black rows (t2w slots).
 struct RbData {
-  DevBuf rbrows, rbpos, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32, t2ci;
+  DevBuf rbrows, rbpos, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32, t2ci, t2rev;
   // pencils A + s M: the preconditioner takes M's row sums (lumped mass)
   // as the per-row weight of the shift; empty for M = I
   DevBuf ms64, ms32;
@@ -434,6 +435,9 @@ struct TickProbe {
 // system in PH_ARNOLDI / PH_RESTART, then the end-of-cycle work for every
 // system in PH_CYCLE_END.
 int launch_tick(hipStream_t st, const Batch& b, const TickProbe* probe = nullptr);
+// After the outer step end of a tick: the first cycle end of the freshly
+// armed solves and the V_0 rebuild of every restarting system.
+int launch_tick_tail(hipStream_t st, const Batch& b);
 // Count of systems not yet finished, written to a host-visible int.
 int launch_summary(hipStream_t st, const Batch& b, int* host_slot);
 

@@ -280,10 +280,11 @@ template <typename T, int RF, int RL>
 __global__ __launch_bounds__(kTPB) void k_spmm_arn(const SysDesc* __restrict__ d,
                                                    const SysCtl* __restrict__ ctl,
                                                    const int2* __restrict__ spmap,
-                                                   unsigned long long* __restrict__ prof) {
+                                                   unsigned long long* __restrict__ prof, int only) {
   const int2 e = spmap[blockIdx.x];
   const SysDesc& D = d[e.x];
   const int ph = ctl[e.x].phase;
+  if (only >= 0 && ph != only) return;
   // complex systems: the tiles of each half of the stacked block apart
   // (tile e.y of th per half), local rows r0.. of A in that half
   const int tr = spmm_tile_rows(RL);
@@ -624,16 +625,26 @@ __device__ inline void rb_bounds(const SysDesc& D, const RowCtx& c, const RbCtx<
   for (int pb = p0 + (int)threadIdx.x; pb < p1; pb += kTPB) {
     const double ip = (double)It[pb];
     double sum = 0.0;
-    for (int u = 0; u < D.t2w; ++u) {
-      const int l = D.t2ci[(size_t)u * nb + pb];
-      if (l == pb) continue;  // unused slot
-      double b = 0.0;  // T_lp: row l's slot with column pb
-      for (int q = 0; q < D.t2w; ++q)
-        if (D.t2ci[(size_t)q * nb + l] == pb) {
-          b = (double)tv[(size_t)q * nb + l];
-          break;
-        }
-      sum += sqrt(fabs((double)tv[(size_t)u * nb + pb] * b * ip * (double)It[l]));
+    // kBGrp slots at a time, their loads issued together
+    constexpr int kBGrp = 6;
+    for (int u0 = 0; u0 < D.t2w; u0 += kBGrp) {
+      int l[kBGrp], q[kBGrp];
+      double a[kBGrp], b[kBGrp], il[kBGrp];
+#pragma unroll
+      for (int g = 0; g < kBGrp; ++g) {
+        const size_t e = (size_t)min(u0 + g, D.t2w - 1) * nb + pb;
+        l[g] = D.t2ci[e];
+        q[g] = D.t2rev[e];  // T_lp: row l's slot with column pb
+        a[g] = (double)tv[e];
+      }
+#pragma unroll
+      for (int g = 0; g < kBGrp; ++g) {
+        const bool ok = u0 + g < D.t2w && l[g] != pb && q[g] >= 0;  // (unused slots hold pb)
+        b[g] = ok ? (double)tv[(size_t)max(q[g], 0) * nb + l[g]] : 0.0;
+        il[g] = ok ? (double)It[l[g]] : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < kBGrp; ++g) sum += sqrt(fabs(a[g] * b[g] * ip * il[g]));
     }
     hi = fmax(hi, sum);
     lr = fmax(lr, (double)rb_dsh(x, D.rbrows[D.nred + pb]) * ip - 1.0);
@@ -1154,12 +1165,13 @@ __device__ inline void update_rows(const SysDesc& D, const RowCtx& c, int nb, bo
 template <typename T, int RF, bool SECOND>
 __global__ __launch_bounds__(kTPB) void k_update(const SysDesc* __restrict__ d,
                                                  const SysCtl* __restrict__ ctl,
-                                                 const int2* __restrict__ rowmap) {
+                                                 const int2* __restrict__ rowmap, int only) {
   extern __shared__ double hl[];  // maxP doubles: the projection coefficients
   __shared__ double lds[4 * kMaxR * kMaxR];
   const RowCtx c = row_ctx(d, rowmap);
   const SysDesc& D = d[c.s];
   const int ph = ctl[c.s].phase;
+  if (only >= 0 && ph != only) return;
   bool do_update;
   if (ph == PH_ARNOLDI) {
     do_update = true;
@@ -1214,13 +1226,14 @@ __device__ inline void chol_body(const SysDesc& D, SysCtl& C, int slot, double f
 }
 
 __global__ __launch_bounds__(kTPB) void k_chol(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl,
-                                               int slot, double rel_floor64, double rel_floor32) {
+                                               int slot, double rel_floor64, double rel_floor32, int only) {
   __shared__ double red_lds[kTPB];
   __shared__ double G[64];
   const int s = blockIdx.x;
   const SysDesc& D = d[s];
   const int ph = ctl[s].phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  if (only >= 0 && ph != only) return;
   const int R = D.r;
   reduce_small(slot == 0 ? D.partS : D.partS2, D.nwg, R * R, red_lds, G);
   if (threadIdx.x == 0) {
@@ -1301,7 +1314,7 @@ template <typename T, int RF, int PASS>
 __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
                                                 SysCtl* __restrict__ ctl,
                                                 const int2* __restrict__ rowmap, int fuse,
-                                                double fl64, double fl32) {
+                                                double fl64, double fl32, int only) {
   __shared__ double lds[4 * kMaxR * kMaxR];
   __shared__ double red_lds[kTPB];
   __shared__ double G[64];
@@ -1311,6 +1324,7 @@ __global__ __launch_bounds__(kTPB) void k_scale(const SysDesc* __restrict__ d,
   const SysDesc& D = d[c.s];
   const int ph = ctl[c.s].phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  if (only >= 0 && ph != only) return;
   const double* Si = D.sm + (PASS == 0 ? SM_S1I : SM_S2I);
   const double* S1i = D.sm + SM_S1I;  // pass 1 applies S1^{-1} again
   if constexpr (RF >= 1 && RF <= 4) {
@@ -1599,7 +1613,7 @@ __device__ inline void lsq_body(const SysDesc& D, SysCtl& C, int ph, double* h, 
 }
 
 template <int RF>
-__global__ __launch_bounds__(LsqTPB<RF>::v) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl) {
+__global__ __launch_bounds__(LsqTPB<RF>::v) void k_lsq(const SysDesc* __restrict__ d, SysCtl* __restrict__ ctl, int only) {
   extern __shared__ double h[];  // maxP doubles: the Hessenberg column block
   __shared__ double Sf[64];
   __shared__ double Qj[16 * 16];
@@ -1610,6 +1624,7 @@ __global__ __launch_bounds__(LsqTPB<RF>::v) void k_lsq(const SysDesc* __restrict
   SysCtl& C = ctl[s];
   const int ph = C.phase;
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+  if (only >= 0 && ph != only) return;
   LRADI_RSEL(RF, D.r, lsq_body<RR, LsqTPB<RF>::v>(D, C, ph, h, Sf, Qj, hw, &done_s));
 }
 
@@ -1919,15 +1934,15 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[4], st));
   if (b.spcount[0] > 0)
     hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,
-                       b.spmap + b.spoff[0], b.prof_bytes);
+                       b.spmap + b.spoff[0], b.prof_bytes, -1);
   if constexpr (RF == 0 || RF % 2 == 0)
     if (b.spcount[1] > 0)
       hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(b.spcount[1]), tb, 0, st, b.d, b.ctl,
-                       b.spmap + b.spoff[1], b.prof_bytes);
+                       b.spmap + b.spoff[1], b.prof_bytes, -1);
   if constexpr (RF == 0 || RF % 4 == 0)
     if (b.spcount[2] > 0)
       hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(b.spcount[2]), tb, 0, st, b.d, b.ctl,
-                       b.spmap + b.spoff[2], b.prof_bytes);
+                       b.spmap + b.spoff[2], b.prof_bytes, -1);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[5], st));
   const dim3 gg(b.rowgrid, (b.maxB + kGramBlocks - 1) / kGramBlocks);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[0], st));
@@ -1935,22 +1950,74 @@ int tick_impl(hipStream_t st, const Batch& b, const TickProbe* pr) {
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[1], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 1);
   const size_t shP = sizeof(double) * (size_t)b.maxP;
-  hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL((k_update<T, RF, false>), rg, tb, shP, st, b.d, b.ctl, b.rowmap, -1);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[2], st));
   hipLaunchKernelGGL((k_gram_vu<T, RF>), gg, tb, 0, st, b.d, b.ctl, b.rowmap, b.prof_bytes);
   if (pr) LRADI_HIP(hipEventRecord(pr->ev[3], st));
   hipLaunchKernelGGL(k_reduce_vu, redg, tb, 0, st, b.d, b.ctl, 0);
-  hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
-  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32);
-  hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32);
-  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32);
-  hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32);
-  hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(LsqTPB<RF>::v), shP, st, b.d, b.ctl);
+  hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, shP, st, b.d, b.ctl, b.rowmap, -1);
+  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32, -1);
+  hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32, -1);
+  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32, -1);
+  hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32, -1);
+  hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(LsqTPB<RF>::v), shP, st, b.d, b.ctl, -1);
   hipLaunchKernelGGL((k_zupdate<T, RF>), rg, tb, shP, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
   hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);
   LRADI_HIP(hipGetLastError());
   return LRADI_OK;
+}
+
+// The tail of a tick, after the outer step ends: the first cycle end of the
+// solves that were just armed (R = W, its norm, then restart or finish),
+// then the rebuild of V_0 for every system that restarts (CholQR2 of R and
+// the start of a cycle), so that every system enters the next tick in
+// PH_ARNOLDI, PH_FINISHED or (when nothing was armed) unchanged, and an
+// inner solve of s block steps takes s ticks.  The restart launches serve
+// PH_RESTART only (systems in PH_ARNOLDI did their step in this tick).
+template <typename T, int RF>
+int tail_impl(hipStream_t st, const Batch& b) {
+  const dim3 rg(b.rowgrid), tb(kTPB), sg(b.nsys);
+  const double fl64 = 1e-24, fl32 = 1e-10;
+  const size_t shP = sizeof(double) * (size_t)b.maxP;
+  hipLaunchKernelGGL((k_resid<RF>), rg, tb, 0, st, b.d, b.ctl, b.rowmap);
+  hipLaunchKernelGGL(k_decide, sg, tb, 0, st, b.d, b.ctl);
+  if (b.spcount[0] > 0)
+    hipLaunchKernelGGL((k_spmm_arn<T, RF, 1>), dim3(b.spcount[0]), tb, 0, st, b.d, b.ctl,
+                       b.spmap + b.spoff[0], b.prof_bytes, (int)PH_RESTART);
+  if constexpr (RF == 0 || RF % 2 == 0)
+    if (b.spcount[1] > 0)
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 2>), dim3(b.spcount[1]), tb, 0, st, b.d, b.ctl,
+                         b.spmap + b.spoff[1], b.prof_bytes, (int)PH_RESTART);
+  if constexpr (RF == 0 || RF % 4 == 0)
+    if (b.spcount[2] > 0)
+      hipLaunchKernelGGL((k_spmm_arn<T, RF, 4>), dim3(b.spcount[2]), tb, 0, st, b.d, b.ctl,
+                         b.spmap + b.spoff[2], b.prof_bytes, (int)PH_RESTART);
+  hipLaunchKernelGGL((k_update<T, RF, true>), rg, tb, shP, st, b.d, b.ctl, b.rowmap, (int)PH_RESTART);
+  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 0, fl64, fl32, (int)PH_RESTART);
+  hipLaunchKernelGGL((k_scale<T, RF, 0>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32,
+                     (int)PH_RESTART);
+  if (!b.fuse_chol) hipLaunchKernelGGL(k_chol, sg, tb, 0, st, b.d, b.ctl, 1, fl64, fl32, (int)PH_RESTART);
+  hipLaunchKernelGGL((k_scale<T, RF, 1>), rg, tb, 0, st, b.d, b.ctl, b.rowmap, b.fuse_chol, fl64, fl32,
+                     (int)PH_RESTART);
+  hipLaunchKernelGGL((k_lsq<RF>), sg, dim3(LsqTPB<RF>::v), shP, st, b.d, b.ctl, (int)PH_RESTART);
+  LRADI_HIP(hipGetLastError());
+  return LRADI_OK;
+}
+
+template <typename T>
+int tail_dispatch(hipStream_t st, const Batch& b) {
+  switch (b.rfix) {
+    case 1: return tail_impl<T, 1>(st, b);
+    case 2: return tail_impl<T, 2>(st, b);
+    case 3: return tail_impl<T, 3>(st, b);
+    case 4: return tail_impl<T, 4>(st, b);
+    case 5: return tail_impl<T, 5>(st, b);
+    case 6: return tail_impl<T, 6>(st, b);
+    case 7: return tail_impl<T, 7>(st, b);
+    case 8: return tail_impl<T, 8>(st, b);
+    default: return tail_impl<T, 0>(st, b);
+  }
 }
 
 template <typename T>
@@ -1973,6 +2040,11 @@ int tick_dispatch(hipStream_t st, const Batch& b, const TickProbe* pr) {
 int launch_tick(hipStream_t st, const Batch& b, const TickProbe* probe) {
   if (b.precision == LRADI_FP64) return tick_dispatch<double>(st, b, probe);
   return tick_dispatch<float>(st, b, probe);
+}
+
+int launch_tick_tail(hipStream_t st, const Batch& b) {
+  if (b.precision == LRADI_FP64) return tail_dispatch<double>(st, b);
+  return tail_dispatch<float>(st, b);
 }
 
 int launch_summary(hipStream_t st, const Batch& b, int* host_slot) {

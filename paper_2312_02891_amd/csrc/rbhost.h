@@ -49,6 +49,10 @@ struct RbHost {
   // pb at q * max(nb, 1) + pb, in order of first appearance along the two
   // hops i -> red j -> black l; unused slots hold pb itself
   std::vector<int32_t> t2ci;
+  // t2rev: for slot q of pb with column c != pb, the slot of c whose column
+  // is pb (T_c,pb beside T_pb,c), slot-major like t2ci; -1 for unused slots
+  // and where c has no such slot
+  std::vector<int32_t> t2rev;
   // tiles: tile t holds the black positions [t * tile, min(nb, (t + 1) *
   // tile)), grown breadth first over T's graph so that it is compact; its
   // halo is the black positions outside it that its rows' T columns reach,
@@ -247,6 +251,20 @@ inline bool rb_host_build(int n, const int32_t* rp, const int32_t* ci, const dou
       const int64_t c0 = soff[old], nc = soff[old + 1] - c0;
       for (int q = 0; q < W2; ++q) h.t2ci[(size_t)q * nbs + pb] = q < nc ? pos[scol[c0 + q]] - nr : pb;
     }
+  });
+
+  h.t2rev.assign((size_t)W2 * nbs, -1);
+  par_ranges(nbk, [&](int pa, int pe, int) {
+    for (int pb = pa; pb < pe; ++pb)
+      for (int q = 0; q < W2; ++q) {
+        const int c = h.t2ci[(size_t)q * nbs + pb];
+        if (c == pb) continue;
+        for (int q2 = 0; q2 < W2; ++q2)
+          if (h.t2ci[(size_t)q2 * nbs + c] == pb) {
+            h.t2rev[(size_t)q * nbs + pb] = q2;
+            break;
+          }
+      }
   });
 
   // halos and region-local columns, tile by tile

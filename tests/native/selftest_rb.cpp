@@ -33,7 +33,7 @@ int st_rb_build(int n, const int32_t* rp, const int32_t* ci, const double* v, in
   std::memcpy(info, x, sizeof(x));
   return 1;
 }
-// integer tables: rows, pos, eci, t2ci, t2lc, halo_off, halo, halo_ci; returns the
+// integer tables: rows, pos, eci, t2ci, t2rev, t2lc, halo_off, halo, halo_ci; returns the
 // length (dst may be null to ask for it)
 long st_rb_ints(const char* name, int32_t* dst) {
   const std::vector<int32_t>* v = nullptr;
@@ -41,6 +41,7 @@ long st_rb_ints(const char* name, int32_t* dst) {
   else if (!std::strcmp(name, "pos")) v = &g_h.pos;
   else if (!std::strcmp(name, "eci")) v = &g_h.eci;
   else if (!std::strcmp(name, "t2ci")) v = &g_h.t2ci;
+  else if (!std::strcmp(name, "t2rev")) v = &g_h.t2rev;
   else if (!std::strcmp(name, "t2lc")) v = &g_h.t2lc;
   else if (!std::strcmp(name, "halo_off")) v = &g_h.halo_off;
   else if (!std::strcmp(name, "halo")) v = &g_h.halo;

@@ -2,7 +2,7 @@
 tables (built with g++ from the same header the library compiles): the
 colour order against the oracle's 2-colouring, A's entries by colour
 position, the Schur complement's column pattern against the sparsity of
-F E computed here with SciPy, and the tiles of black positions used by the
+F E computed here with SciPy (and each slot's transposed slot), and the tiles of black positions used by the
 paired sweeps (a partition, each tile's halo exactly the columns its rows
 reach outside it, every region-local column index in range and pointing at
 the right position)."""
@@ -48,7 +48,7 @@ def build(RB, A, tiles):
     if not ok:
         return None
     out = dict(zip(["nred", "rbw", "t2w", "tile", "ntile", "maxreg", "nhalo"], info.tolist()))
-    for name in ["rows", "pos", "eci", "t2ci", "t2lc", "halo_off", "halo", "halo_ci"]:
+    for name in ["rows", "pos", "eci", "t2ci", "t2rev", "t2lc", "halo_off", "halo", "halo_ci"]:
         k = RB.st_rb_ints(name.encode(), None)
         a = np.zeros(k, dtype=np.int32)
         RB.st_rb_ints(name.encode(), P(a.ctypes.data))
@@ -123,6 +123,16 @@ def test_tables_against_definitions(RB, dim, N, omega, tiles):
         assert len(set(used.tolist())) == len(used)
         assert sorted(used.tolist()) == sorted(Tp.indices[Tp.indptr[pb]:Tp.indptr[pb + 1]].tolist())
     assert W2 == max(1, max(np.diff(Tp.indptr)))
+    # the transposed entry's slot: column pb in row c's slots (the pattern of
+    # T is symmetric here), -1 on unused slots
+    t2rev = h["t2rev"].reshape(W2, nb)
+    for pb in range(nb):
+        for q in range(W2):
+            c = t2ci[q, pb]
+            if c == pb:
+                assert t2rev[q, pb] == -1
+            else:
+                assert t2rev[q, pb] >= 0 and t2ci[t2rev[q, pb], c] == pb
     # tiles: consecutive ranges of `tile`, rows ascending inside each
     tile, ntile = h["tile"], h["ntile"]
     assert tile == (nb + tiles - 1) // tiles and ntile == (nb + tile - 1) // tile
