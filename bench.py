@@ -38,21 +38,26 @@ HBM_PEAK_GBS = 8000.0
 # MI355X FP32 vector (non-matrix) peak
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Steps on the Schur complement in the preconditioned inner solves of
-# config 2: Chebyshev steps, one per launch (FP64 solve: 12, 16, 24, 32
-# steps gave 57.3, 51.6, 48.5, 48.0 ms), against Jacobi sweeps run two per
-# launch (16, 20, 24, 28, 32, 40 sweeps: 103, 92, 90, 89, 89, 89 ms; 85.4 ms
-# at 32 in the run of the Chebyshev scan)
-PRECOND_SWEEPS = 32
+# config 2: Chebyshev steps, one per launch (FP64 solve, median of 5: 24,
+# 32, 40, 48 steps gave 43.7, 42.8, 41.7, 41.2 ms; replaying captured ticks
+# 1 ms slower each), against Jacobi sweeps run two per launch (16, 20, 24,
+# 28, 32, 40 sweeps: 103, 92, 90, 89, 89, 89 ms before the tick tail; 86.2
+# ms at 32 after it)
+PRECOND_SWEEPS = 48
 C2_PRECOND_POLY = 1
-# the batch and serving workloads' small problems (grid sides 32..128) gain less
-# per sweep: 24 (batch of 256: 1.01 s at 24 against 1.14 s at 32)
-BATCH_PRECOND_SWEEPS = 24
-BATCH_PRECOND_POLY = 0
+# Jacobi sweeps, two per launch, of the generalized (lumped-mass) and
+# Lyapunov workloads on config 2's operators
+PAIRED_JACOBI_SWEEPS = 32
+# the batch and serving workloads' small problems (grid sides 32..128):
+# Chebyshev steps, 16 (batch of 256: 0.995 s; 24: 1.02 s; Jacobi sweeps 24:
+# 1.22 s and 32: 1.14 s before the tick tail)
+BATCH_PRECOND_SWEEPS = 16
+BATCH_PRECOND_POLY = 1
 # the 3-D configuration's Schur rows couple 18 neighbours instead of 8, so a
-# step costs more there: FP64 relaxed solves with 4, 6, 8, 10, 12, 16, 20,
-# 24, 32, 40 Chebyshev steps took 76.4, 66.1, 62.0, 59.3, 57.8, 55.8, 56.7,
-# 55.3, 60.7, 65.0 ms (inner block steps 109 + 82 at 4 down to 26 + 21 at
-# 40); with Jacobi sweeps 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40 took 151.6,
+# step costs more there: FP64 relaxed solves with 12, 16, 20, 24, 32
+# Chebyshev steps took 54.2, 51.6, 52.4, 50.2, 54.8 ms (median of 5; before
+# the tick tail 4, 6, 8, 10 steps took 76.4, 66.1, 62.0, 59.3 ms; inner block
+# steps 109 + 82 at 4 down to 28 + 25 at 32); with Jacobi sweeps 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40 took 151.6,
 # 120.4, 107.6, 102.0, 98.6, 96.9, 95.0, 95.3, 98.3, 100.0, 105.3 ms (before
 # later changes of the other kernels; 92.4 ms at 16 in the Chebyshev scan)
 C3_PRECOND_SWEEPS = 24
@@ -647,7 +652,7 @@ def bench_gen(args, L, WL):
     keep = {}
     # kmax = 100 as for the paper's generalized finite-element example (Sec. 4):
     # the pencils' spectra are wider than the operators' and need more steps
-    pre = _pre(PRECOND_SWEEPS)
+    pre = _pre(PAIRED_JACOBI_SWEEPS)
     for name, kw in (("fp64_relaxed", dict(selection="mid")), ("fp32_relaxed", dict(selection="mid", precision="fp32")),
                      ("fp64_fixed", dict(selection="fixed")),
                      ("fp64_relaxed_precond", dict(selection="mid", **pre)),
@@ -716,7 +721,7 @@ def bench_lyap(args, L, WL):
     fd = torch.from_numpy(f).cuda()
     ctx = L.Context(0)
     out, keep = {}, {}
-    pre = _pre(PRECOND_SWEEPS)
+    pre = _pre(PAIRED_JACOBI_SWEEPS)
     runs = (("lyap_fp64_sym", "lyap", dict(selection="sym")),
             ("lyap_fp64_sym_precond", "lyap", dict(selection="sym", **pre)),
             ("sylvester_fp64_sym_precond", "sylv", dict(selection="sym", b_is_transposed=1, **pre)),
