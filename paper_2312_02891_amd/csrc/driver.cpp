@@ -15,6 +15,7 @@
 #include <deque>
 #include <list>
 #include <functional>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -300,6 +301,11 @@ struct lradi_ctx {
   // red-black preconditioner data of recently prepared matrices, most
   // recent first, keyed by content
   std::list<std::pair<uint64_t, std::shared_ptr<const lradi::RbData>>> rb_cache;
+  // host halves of those tables built ahead of their upload by other threads
+  // (a batch's matrices in parallel, the server's requests at submission),
+  // same keys; an entry is taken by the upload that uses it
+  std::mutex rb_pre_mu;
+  std::list<std::pair<uint64_t, std::shared_ptr<const lradi::RbHost>>> rb_pre;
 };
 
 struct lradi_result {
@@ -973,12 +979,13 @@ uint64_t csr_key(int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const
   return h;
 }
 
-int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32) {
-  std::vector<int32_t> rp, ci, trp, tci;
-  std::vector<double> v, tv;
-  if (!A || A->nrows != n) return set_error("preconditioner: matrix size differs from the uploaded one"), LRADI_EINVAL;
+// The cache key of a matrix's preconditioner data (its contents, and a
+// pencil's lumped mass), with M's row sums in lump and, for a device matrix,
+// A's host copy in rp, ci, v.
+int rb_key(const lradi_csr* A, const lradi_csr* M, bool need32, std::vector<int32_t>& rp,
+           std::vector<int32_t>& ci, std::vector<double>& v, std::vector<double>& lump, uint64_t* key) {
+  const int n = A->nrows;
   // pencil: M's row sums weight the shift inside the preconditioner
-  std::vector<double> lump;
   if (M) {
     std::vector<int32_t> mrp, mci;
     std::vector<double> mv;
@@ -988,32 +995,88 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
     for (int i = 0; i < n; ++i)
       for (int32_t k = mrp[i]; k < mrp[i + 1]; ++k) lump[i] += mv[k];
   }
-  // a matrix already prepared on this context (same contents) is reused
-  uint64_t key;
   if (A->on_device) {
     LRADI_TRY(host_csr(A, rp, ci, v));
-    key = csr_key(n, (int64_t)ci.size(), rp.data(), ci.data(), v.data(), need32);
+    *key = csr_key(n, (int64_t)ci.size(), rp.data(), ci.data(), v.data(), need32);
   } else {
-    key = csr_key(n, A->nnz, A->rowptr, A->colind, A->val, need32);
+    *key = csr_key(n, A->nnz, A->rowptr, A->colind, A->val, need32);
   }
-  if (M) key = (key * 0x5851F42D4C957F2Dull) ^ csr_key(n, n, nullptr, nullptr, lump.data(), false);
+  if (M) *key = (*key * 0x5851F42D4C957F2Dull) ^ csr_key(n, n, nullptr, nullptr, lump.data(), false);
+  return LRADI_OK;
+}
+
+// the host tables of a (host) matrix: colouring, slot tables, Schur
+// pattern, tiles (false: not bipartite)
+bool rb_host_tables(int nn, const int32_t* rp, const int32_t* ci, const double* v, RbHost& h) {
+  std::vector<int32_t> trp, tci;
+  std::vector<double> tv;
+  csr_transpose(nn, rp, ci, v, trp, tci, tv);
+  // one tile of black rows per row workgroup of the inner solves (large
+  // matrices only)
+  const int rpw = choose_rows_per_wg(nn);
+  const int tiles = nn >= kPairMinRows ? (nn + rpw - 1) / rpw : 0;
+  return rb_host_build(nn, rp, ci, v, trp.data(), tci.data(), tv.data(), tiles, h);
+}
+
+constexpr size_t kRbPreEntries = 64;
+
+// Build the host tables of a host-resident matrix ahead of its upload (any
+// thread; device matrices and failures are left to prepare_rb).
+void rb_prebuild(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, bool need32,
+                 size_t cap = kRbPreEntries) {
+  if (!A || A->on_device || (M && M->on_device) || A->nrows <= 0) return;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v, lump;
+  uint64_t key = 0;
+  if (rb_key(A, M, need32, rp, ci, v, lump, &key) != LRADI_OK) return;
+  {
+    std::lock_guard<std::mutex> lk(ctx->rb_pre_mu);
+    for (auto& e : ctx->rb_pre)
+      if (e.first == key) return;
+  }
+  if (host_csr(A, rp, ci, v) != LRADI_OK) return;
+  auto h = std::make_shared<RbHost>();
+  if (!rb_host_tables(A->nrows, rp.data(), ci.data(), v.data(), *h)) return;
+  std::lock_guard<std::mutex> lk(ctx->rb_pre_mu);
+  ctx->rb_pre.emplace_front(key, std::move(h));
+  while (ctx->rb_pre.size() > std::max(cap, kRbPreEntries)) ctx->rb_pre.pop_back();
+}
+
+int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, hipStream_t st, bool need32) {
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v, lump;
+  if (!A || A->nrows != n) return set_error("preconditioner: matrix size differs from the uploaded one"), LRADI_EINVAL;
+  // a matrix already prepared on this context (same contents) is reused
+  uint64_t key = 0;
+  LRADI_TRY(rb_key(A, M, need32, rp, ci, v, lump, &key));
+  // host tables built ahead by another thread (taken even when the device
+  // data turns out to be cached, so that no entry is left behind)
+  std::shared_ptr<const RbHost> hp;
+  {
+    std::lock_guard<std::mutex> lk(ctx->rb_pre_mu);
+    for (auto it = ctx->rb_pre.begin(); it != ctx->rb_pre.end(); ++it)
+      if (it->first == key) {
+        hp = it->second;
+        ctx->rb_pre.erase(it);
+        break;
+      }
+  }
   for (auto it = ctx->rb_cache.begin(); it != ctx->rb_cache.end(); ++it)
     if (it->first == key) {
       rb = it->second;
       ctx->rb_cache.splice(ctx->rb_cache.begin(), ctx->rb_cache, it);
       return LRADI_OK;
     }
-  if (!A->on_device) LRADI_TRY(host_csr(A, rp, ci, v));
   auto R = std::make_shared<RbData>();
   const int nn = A->nrows;
-  csr_transpose(nn, rp.data(), ci.data(), v.data(), trp, tci, tv);
-  // one tile of black rows per row workgroup of the inner solves (large
-  // matrices only)
-  const int rpw = choose_rows_per_wg(nn);
-  const int tiles = nn >= kPairMinRows ? (nn + rpw - 1) / rpw : 0;
-  RbHost h;
-  if (!rb_host_build(nn, rp.data(), ci.data(), v.data(), trp.data(), tci.data(), tv.data(), tiles, h))
-    return set_error("red-black preconditioner: the sparsity graph is not bipartite"), LRADI_EINVAL;
+  if (!hp) {
+    if (!A->on_device) LRADI_TRY(host_csr(A, rp, ci, v));
+    auto hb = std::make_shared<RbHost>();
+    if (!rb_host_tables(nn, rp.data(), ci.data(), v.data(), *hb))
+      return set_error("red-black preconditioner: the sparsity graph is not bipartite"), LRADI_EINVAL;
+    hp = std::move(hb);
+  }
+  const RbHost& h = *hp;
   auto up = [&](DevBuf& d, const void* src, size_t bytes) -> int {
     LRADI_TRY(d.alloc(std::max(bytes, (size_t)4)));
     if (bytes) LRADI_HIP(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
@@ -1067,6 +1130,49 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
   return LRADI_OK;
 }
 
+
+// Host tables of a problem's preconditioned matrices ahead of its set-up:
+// side 0 is A (with M), side 1 the matrix the B-side solves use (B given
+// as B^T, or B's host transpose, with C likewise).  Host matrices only.
+void prebuild_side(lradi_ctx* c, const lradi_opts& o, const lradi_problem& P, int side, size_t cap) {
+  if (sweeps_for(o) < 0 || P.shiftsA_im || P.shiftsB_im) return;  // (complex: no preconditioner)
+  const bool f32 = o.precision == LRADI_FP32_INNER;
+  if (side == 0) {
+    rb_prebuild(c, P.A, P.M, f32, cap);
+    return;
+  }
+  if (P.lyapunov || !P.B) return;
+  if (o.b_is_transposed) {
+    rb_prebuild(c, P.B, P.C, f32, cap);
+    return;
+  }
+  if (P.B->on_device || (P.C && P.C->on_device)) return;
+  std::vector<int32_t> trp, tci, crp, cci;
+  std::vector<double> tv, cv;
+  if (host_csr_t(P.B, trp, tci, tv) != LRADI_OK) return;
+  lradi_csr Bt{P.B->nrows, P.B->nrows, (int64_t)tci.size(), trp.data(), tci.data(), tv.data(), 0};
+  lradi_csr Ct{};
+  if (P.C) {
+    if (host_csr_t(P.C, crp, cci, cv) != LRADI_OK) return;
+    Ct = lradi_csr{P.C->nrows, P.C->nrows, (int64_t)cci.size(), crp.data(), cci.data(), cv.data(), 0};
+  }
+  rb_prebuild(c, &Bt, P.C ? &Ct : nullptr, f32, cap);
+}
+
+// all of a batch's tables on up to 16 host threads
+void prebuild_batch(lradi_ctx* c, const lradi_opts& o, const lradi_problem* probs, int nprob) {
+  if (sweeps_for(o) < 0 || nprob < 2) return;
+  const int hw = std::max(1, (int)std::thread::hardware_concurrency());
+  const int nt = std::max(1, std::min({16, hw, 2 * nprob}));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int t; (t = next.fetch_add(1)) < 2 * nprob;) prebuild_side(c, o, probs[t / 2], t % 2, 2 * (size_t)nprob);
+  };
+  std::vector<std::thread> th;
+  for (int i = 1; i < nt; ++i) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+}
 }  // namespace lradi
 
 // ---------------------------------------------------------------------------
@@ -1697,6 +1803,8 @@ int lradi_batch_solve(lradi_ctx* c, int nprob, const lradi_problem* probs, const
   if (opts) o = *opts;
   LRADI_TRY(check_opts(o));
   LRADI_HIP(hipSetDevice(c->device));
+  // the preconditioner's host tables of all problems in parallel first
+  prebuild_batch(c, o, probs, nprob);
   std::vector<std::unique_ptr<Prob>> ps(nprob);
   for (int i = 0; i < nprob; ++i) {
     ps[i] = std::make_unique<Prob>();
@@ -1921,7 +2029,53 @@ struct lradi_server {
     double tol = 0.0;
     size_t footprint = 0;
     std::chrono::steady_clock::time_point t_submit;
+    // the preconditioner's host tables, built by the preparation threads
+    // from the arrays above (which keep their storage when the request
+    // moves): waited for before admission and before the request is dropped
+    std::shared_future<void> prep;
   };
+  // a few host threads that build submitted requests' preconditioner tables
+  // while the worker runs the device
+  struct PrepPool {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::function<void()>> jobs;
+    bool stop = false;
+    std::vector<std::thread> th;
+    void start(int n) {
+      for (int i = 0; i < n; ++i) th.emplace_back([this] { loop(); });
+    }
+    void loop() {
+      for (;;) {
+        std::function<void()> f;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return stop || !jobs.empty(); });
+          if (jobs.empty()) return;  // (stop, and every job done)
+          f = std::move(jobs.front());
+          jobs.pop_front();
+        }
+        f();
+      }
+    }
+    void push(std::function<void()> f) {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        jobs.push_back(std::move(f));
+      }
+      cv.notify_one();
+    }
+    void finish() {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
+      }
+      cv.notify_all();
+      for (auto& t : th) t.join();
+      th.clear();
+    }
+  };
+  PrepPool pool;
   struct Done {
     lradi_result* res = nullptr;
     double latency = 0.0;
@@ -1989,6 +2143,7 @@ void lradi_server::run() {
       st.queued = (int)queue.size();
     }
     for (Pending& P : admit) {
+      if (P.prep.valid()) P.prep.wait();
       auto q = std::make_unique<Prob>();
       lradi_csr A{P.n, P.n, (int64_t)P.aci.size(), P.arp.data(), P.aci.data(), P.aval.data(), 0};
       lradi_csr B{P.m, P.m, (int64_t)P.bci.size(), P.brp.data(), P.bci.data(), P.bval.data(), 0};
@@ -2105,6 +2260,8 @@ int lradi_server_create(lradi_ctx* c, const lradi_opts* opts, int64_t hbm_budget
   s->budget = hbm_budget;
   s->max_active = max_active;
   s->st.bytes_budget = hbm_budget;
+  if (sweeps_for(o) >= 0)
+    s->pool.start(std::max(2, std::min(8, (int)std::thread::hardware_concurrency() / 2)));
   s->worker = std::thread([s] { s->run(); });
   *out = s;
   return LRADI_OK;
@@ -2152,6 +2309,33 @@ int lradi_server_submit(lradi_server* s, const lradi_problem* P, uint64_t* ticke
   if ((int64_t)q.footprint > s->budget)
     return set_error("lradi_server_submit: footprint %zu bytes exceeds the budget", q.footprint), LRADI_ENOMEM;
   q.t_submit = std::chrono::steady_clock::now();
+  if (!s->pool.th.empty() && !cplx) {
+    // the preconditioner's host tables on a preparation thread, from views of
+    // this request's arrays
+    auto done = std::make_shared<std::promise<void>>();
+    q.prep = done->get_future().share();
+    const lradi_csr A{q.n, q.n, (int64_t)q.aci.size(), q.arp.data(), q.aci.data(), q.aval.data(), 0};
+    const lradi_csr B{q.m, q.m, (int64_t)q.bci.size(), q.brp.data(), q.bci.data(), q.bval.data(), 0};
+    const lradi_csr M{q.n, q.n, (int64_t)q.mci.size(), q.mrp.data(), q.mci.data(), q.mval.data(), 0};
+    const lradi_csr C{q.m, q.m, (int64_t)q.cci.size(), q.crp.data(), q.cci.data(), q.cval.data(), 0};
+    const bool hasM = q.hasM, hasC = q.hasC;
+    lradi_ctx* ctx = s->ctx;
+    const lradi_opts o = s->opts;
+    s->pool.push([=] {
+      try {
+        lradi_problem pr{};
+        pr.A = &A;
+        pr.B = lyap ? nullptr : &B;
+        pr.M = hasM ? &M : nullptr;
+        pr.C = hasC ? &C : nullptr;
+        pr.lyapunov = lyap ? 1 : 0;
+        for (int side = 0; side < 2; ++side) prebuild_side(ctx, o, pr, side, kRbPreEntries);
+      } catch (...) {
+        // (the worker builds the tables itself)
+      }
+      done->set_value();
+    });
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     q.ticket = s->next_ticket++;
@@ -2183,6 +2367,7 @@ int lradi_server_cancel(lradi_server* s, uint64_t ticket) {
   std::lock_guard<std::mutex> lk(s->mu);
   for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
     if (it->ticket == ticket) {
+      if (it->prep.valid()) it->prep.wait();  // (its tables are read from the request's arrays)
       auto* R = new lradi_result();
       R->status = LRADI_ECANCELED;
       lradi_server::Done d;
@@ -2216,6 +2401,7 @@ int lradi_server_destroy(lradi_server* s) {
   }
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  s->pool.finish();  // (pending jobs read queued requests' arrays)
   for (auto& kv : s->done) delete kv.second.res;
   delete s;
   return LRADI_OK;

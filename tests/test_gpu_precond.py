@@ -99,9 +99,13 @@ def test_preconditioned_solve_reaches_delta_with_fewer_steps(L, ctx, prec, shift
     assert steps[0] < steps[None] and steps[2] < steps[0]
 
 
-def test_preconditioned_batch_equals_solo_runs(L, ctx):
+@pytest.mark.parametrize("steps", [dict(precond_sweeps=1), dict(precond_sweeps=6, precond_poly=1)],
+                         ids=["jacobi1", "chebyshev6"])
+def test_preconditioned_batch_equals_solo_runs(L, ctx, steps):
     """Systems of different n, r, dimension and shift share launches with
-    the preconditioner; each result is bit-identical to its solo run."""
+    the preconditioner (Jacobi sweeps, or Chebyshev steps whose bounds each
+    system computes for its own shift); each result is bit-identical to its
+    solo run."""
     specs = [(2, 21, (4.0, -9.0), 1, -50.0), (2, 40, (-20.0, 3.0), 3, -900.0),
              (3, 9, (2.0, 2.0, -1.0), 8, -120.0), (2, 64, (30.0, 30.0), 5, -4000.0)]
     mats, Ws, shifts, deltas = [], [], [], []
@@ -111,7 +115,7 @@ def test_preconditioned_batch_equals_solo_runs(L, ctx):
         Ws.append(to_dev(np.random.default_rng(400 + i).standard_normal((H.n, r))))
         shifts.append(s)
         deltas.append(1e-9 * float(np.linalg.norm(Ws[-1].cpu().numpy(), 2)))
-    o = L.default_opts(restart=12, max_inner=3000, precond="rbilu0", precond_sweeps=1)
+    o = L.default_opts(restart=12, max_inner=3000, precond="rbilu0", **steps)
     Zb, sb, _ = ctx.shifted_solve(mats, shifts, Ws, deltas, o)
     for i in range(len(specs)):
         Zi, si, _ = ctx.shifted_solve([mats[i]], [shifts[i]], [Ws[i]], [deltas[i]], o)

@@ -39,7 +39,7 @@ def small_requests(L, count, seed=5):
 # serving bench's (FP32 inner Krylov work, preconditioned, kmax 100)
 SERVE_OPTS = {
     "defaults": {},
-    "serve_bench": dict(precision="fp32", kmax=100, precond="rbilu0", precond_sweeps=24),
+    "serve_bench": dict(precision="fp32", kmax=100, precond="rbilu0", precond_sweeps=16, precond_poly=1),
 }
 
 
