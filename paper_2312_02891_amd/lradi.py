@@ -606,14 +606,16 @@ class Server:
     def submit(self, A: HostCsr, B: HostCsr, f, g, shiftsA, shiftsB, tol=0.0, M=None, C=None) -> int:
         pr, keep = Context.make_problem(A, B, f, g, shiftsA, shiftsB, tol, M, C)
         t = ctypes.c_uint64()
-        _torch().cuda.synchronize()
+        # f and g are ready once the producing stream is (not a device-wide
+        # sync, which would wait for the server's own work too)
+        _torch().cuda.current_stream().synchronize()
         _check(_lib.lradi_server_submit(self.h, ctypes.byref(pr), ctypes.byref(t)))
         return t.value
 
     def submit_lyap(self, A: HostCsr, f, shifts, tol=0.0, M=None) -> int:
         pr, keep = Context.make_problem(A, None, f, None, shifts, None, tol, M, None, lyapunov=True)
         t = ctypes.c_uint64()
-        _torch().cuda.synchronize()
+        _torch().cuda.current_stream().synchronize()
         _check(_lib.lradi_server_submit(self.h, ctypes.byref(pr), ctypes.byref(t)))
         return t.value
 
