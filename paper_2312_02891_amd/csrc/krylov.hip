@@ -367,10 +367,13 @@ __device__ inline RbCtx<T> rb_ctx(const SysDesc& D, double shift) {
 }
 
 // gathers in flight per row: eight entries for narrow blocks, six (a 3-D
-// Schur row's 18 couplings in three groups) for wide ones
+// Schur row's 18 couplings in three groups) for wide ones, three for r = 7,
+// whose rows take one lane each (seven values per gather: six in flight
+// needed 248 VGPRs, and kernels serving mixed widths inherit the widest
+// variant's count)
 template <int R>
 struct RbUnroll {
-  static constexpr int v = R >= 5 ? 6 : 8;
+  static constexpr int v = R == 7 ? 3 : R >= 5 ? 6 : 8;
 };
 
 // lanes that share one row in the stages of one sweep launch: each owns

@@ -32,7 +32,8 @@ def ctx(L):
 
 @pytest.mark.parametrize("dim,N,omega,shift", [(2, 15, (8.0, -5.0), -300.0), (3, 7, (4.0, -2.0, 6.0), -300.0),
                                                (3, 9, (20.0, 10.0, 5.0), -40.0)])
-@pytest.mark.parametrize("r,j,sweeps", [(1, 2, 1), (2, 3, 2), (4, 4, 5), (8, 3, 8), (3, 2, 13), (8, 2, 16)])
+@pytest.mark.parametrize("r,j,sweeps", [(1, 2, 1), (2, 3, 2), (4, 4, 5), (8, 3, 8), (3, 2, 13), (8, 2, 16),
+                                         (7, 2, 6), (5, 3, 4)])
 def test_first_cycle_with_chebyshev_steps_equals_definition(L, ctx, dim, N, omega, shift, r, j, sweeps):
     """restart = j, step cap j: Z minimises ||W - S Z||_F over M K_j(S M, W)
     with M the oracle's red-black ILU(0) and `sweeps` Chebyshev steps, to
