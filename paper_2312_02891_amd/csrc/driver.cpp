@@ -1077,45 +1077,61 @@ int DevCSR::prepare_rb(lradi_ctx* ctx, const lradi_csr* A, const lradi_csr* M, h
     hp = std::move(hb);
   }
   const RbHost& h = *hp;
-  auto up = [&](DevBuf& d, const void* src, size_t bytes) -> int {
-    LRADI_TRY(d.alloc(std::max(bytes, (size_t)4)));
-    if (bytes) LRADI_HIP(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
-    return LRADI_OK;
-  };
   const size_t ne = (size_t)h.rbw * nn;
-  LRADI_TRY(up(R->t2ci, h.t2ci.data(), sizeof(int32_t) * h.t2ci.size()));
-  LRADI_TRY(up(R->t2rev, h.t2rev.data(), sizeof(int32_t) * h.t2rev.size()));
-  LRADI_TRY(up(R->t2lc, h.t2lc.data(), sizeof(int32_t) * h.t2lc.size()));
-  LRADI_TRY(up(R->halo_off, h.halo_off.data(), sizeof(int32_t) * h.halo_off.size()));
-  LRADI_TRY(up(R->halo, h.halo.data(), sizeof(int32_t) * h.halo.size()));
-  LRADI_TRY(up(R->halo_ci, h.halo_ci.data(), sizeof(int32_t) * h.halo_ci.size()));
-  LRADI_TRY(up(R->rbpos, h.pos.data(), sizeof(int32_t) * nn));
-  if (!lump.empty()) {
-    LRADI_TRY(up(R->ms64, lump.data(), sizeof(double) * nn));
-    if (need32) {
-      LRADI_TRY(R->ms32.alloc(sizeof(float) * nn));
-      hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, R->ms64.as<double>(),
-                         R->ms32.as<float>(), (int64_t)nn);
-    }
+  const bool mass = !lump.empty();
+  // every table in one allocation (256-byte aligned slices): a table slice
+  // holds at least 4 bytes; the FP32 copies and the lumped mass are absent
+  // (null) when not needed
+  struct Slice {
+    DevView* v;
+    const void* src;
+    size_t bytes;
+    bool present;
+  };
+  const Slice sl[] = {
+      {&R->t2ci, h.t2ci.data(), sizeof(int32_t) * h.t2ci.size(), true},
+      {&R->t2rev, h.t2rev.data(), sizeof(int32_t) * h.t2rev.size(), true},
+      {&R->t2lc, h.t2lc.data(), sizeof(int32_t) * h.t2lc.size(), true},
+      {&R->halo_off, h.halo_off.data(), sizeof(int32_t) * h.halo_off.size(), true},
+      {&R->halo, h.halo.data(), sizeof(int32_t) * h.halo.size(), true},
+      {&R->halo_ci, h.halo_ci.data(), sizeof(int32_t) * h.halo_ci.size(), true},
+      {&R->rbpos, h.pos.data(), sizeof(int32_t) * nn, true},
+      {&R->rbrows, h.rows.data(), sizeof(int32_t) * nn, true},
+      {&R->diag64, h.dg.data(), sizeof(double) * nn, true},
+      {&R->ellci, h.eci.data(), sizeof(int32_t) * ne, true},
+      {&R->ellval64, h.eval.data(), sizeof(double) * ne, true},
+      {&R->elltv64, h.etv.data(), sizeof(double) * ne, true},
+      {&R->ms64, mass ? lump.data() : nullptr, sizeof(double) * nn, mass},
+      {&R->ms32, nullptr, sizeof(float) * nn, mass && need32},
+      {&R->diag32, nullptr, sizeof(float) * nn, need32},
+      {&R->ellval32, nullptr, sizeof(float) * ne, need32},
+      {&R->elltv32, nullptr, sizeof(float) * ne, need32},
+  };
+  size_t total = 0;
+  for (const Slice& x : sl)
+    if (x.present) total += align256(std::max(x.bytes, (size_t)4));
+  LRADI_TRY(R->arena.alloc(total));
+  char* q = R->arena.as<char>();
+  for (const Slice& x : sl) {
+    x.v->p = nullptr;
+    if (!x.present) continue;
+    x.v->p = q;
+    if (x.src && x.bytes) LRADI_HIP(hipMemcpyAsync(q, x.src, x.bytes, hipMemcpyHostToDevice, st));
+    q += align256(std::max(x.bytes, (size_t)4));
   }
-  LRADI_TRY(up(R->rbrows, h.rows.data(), sizeof(int32_t) * nn));
-  LRADI_TRY(up(R->diag64, h.dg.data(), sizeof(double) * nn));
-  LRADI_TRY(up(R->ellci, h.eci.data(), sizeof(int32_t) * ne));
-  LRADI_TRY(up(R->ellval64, h.eval.data(), sizeof(double) * ne));
-  LRADI_TRY(up(R->elltv64, h.etv.data(), sizeof(double) * ne));
+  const int tpb = 256;
+  if (mass && need32)
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + tpb - 1) / tpb)), dim3(tpb), 0, st, R->ms64.as<double>(),
+                       R->ms32.as<float>(), (int64_t)nn);
   if (need32) {
-    LRADI_TRY(R->diag32.alloc(sizeof(float) * nn));
-    LRADI_TRY(R->ellval32.alloc(sizeof(float) * ne));
-    LRADI_TRY(R->elltv32.alloc(sizeof(float) * ne));
-    const int tpb = 256;
     hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nn + tpb - 1) / tpb)), dim3(tpb), 0, st, R->diag64.as<double>(),
                        R->diag32.as<float>(), (int64_t)nn);
     hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, R->ellval64.as<double>(),
                        R->ellval32.as<float>(), (int64_t)ne);
     hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ne + tpb - 1) / tpb)), dim3(tpb), 0, st, R->elltv64.as<double>(),
                        R->elltv32.as<float>(), (int64_t)ne);
-    LRADI_HIP(hipGetLastError());
   }
+  LRADI_HIP(hipGetLastError());
   LRADI_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
   R->nred = h.nred;
   R->rbw = h.rbw;

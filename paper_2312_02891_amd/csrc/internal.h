@@ -319,14 +319,21 @@ struct DevBuf {
 // row's colour position, the diagonal, the off-diagonal entries by colour
 // position in rbw slot-major slots (column, value, transposed value), and
 // the Schur complement's column pattern on the black rows (t2w slots).
+// A table inside another buffer (not owned).
+struct DevView {
+  void* p = nullptr;
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
 struct RbData {
-  DevBuf rbrows, rbpos, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32, t2ci, t2rev;
+  DevBuf arena;  // every table below, in one allocation
+  DevView rbrows, rbpos, diag64, diag32, ellci, ellval64, ellval32, elltv64, elltv32, t2ci, t2rev;
   // pencils A + s M: the preconditioner takes M's row sums (lumped mass)
-  // as the per-row weight of the shift; empty for M = I
-  DevBuf ms64, ms32;
+  // as the per-row weight of the shift; null for M = I
+  DevView ms64, ms32;
   // tiles of the black positions for paired sweeps (halo lists and T's
   // columns as region-local indices; see RbHost)
-  DevBuf halo_off, halo, t2lc, halo_ci;
+  DevView halo_off, halo, t2lc, halo_ci;
   int nred = 0, rbw = 0, t2w = 0;
   int tile = 0, ntile = 0, maxreg = 0, nhalo = 0;
 };
