@@ -123,14 +123,15 @@ def test_preconditioned_batch_equals_solo_runs(L, ctx, steps):
         assert np.array_equal(Zi[0].cpu().numpy(), Zb[i].cpu().numpy())
 
 
-@pytest.mark.parametrize("name,precision,sweeps", [("SMALL_2D", "fp64", 0), ("SMALL_2D", "fp32", 2),
-                                                   ("SMALL_3D", "fp64", 2), ("SMALL_3D", "fp32", 0),
-                                                   ("SMALL_2D", "fp64", 24), ("SMALL_2D", "fp32", 9)])
-def test_adi_with_preconditioned_inner_solves_matches_oracle(L, ctx, name, precision, sweeps):
+@pytest.mark.parametrize("name,precision,sweeps,poly", [("SMALL_2D", "fp64", 0, 0), ("SMALL_2D", "fp32", 2, 0),
+                                                        ("SMALL_3D", "fp64", 2, 0), ("SMALL_3D", "fp32", 0, 0),
+                                                        ("SMALL_2D", "fp64", 24, 0), ("SMALL_2D", "fp32", 9, 0),
+                                                        ("SMALL_2D", "fp64", 12, 1), ("SMALL_3D", "fp32", 8, 1)])
+def test_adi_with_preconditioned_inner_solves_matches_oracle(L, ctx, name, precision, sweeps, poly):
     """Algorithm 1 with preconditioned inner solves: the oracle's steps
     (+-1), X within 1e-6 of the direct-solve iterate, true residual below
     tau, tolerances and gap estimates as the oracle's formulas."""
-    say("adi precond", name, precision, sweeps)
+    say("adi precond", name, precision, sweeps, poly)
     P = getattr(WL, name)
     HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
     HB = L.convdiff(P.B.dim, P.B.N, P.B.omega)
@@ -138,7 +139,7 @@ def test_adi_with_preconditioned_inner_solves_matches_oracle(L, ctx, name, preci
     B = convdiff_matrix(P.B.dim, P.B.N, P.B.omega)
     f, g = WL.rhs_factors(P.seed, P.A.n, P.B.n, P.r)
     pA, pB = WL.wachspress_shifts(P.A, P.B, P.nshifts)
-    o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps)
+    o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps, precond_poly=poly)
     res = ctx.solve(HA, HB, to_dev(f), to_dev(g), pA, pB, o)
     assert res.status == L.OK
     full = OF.fadi(A, B, f, g, pA, pB, tol=P.tol, kmax=100)
@@ -157,7 +158,9 @@ def test_adi_with_preconditioned_inner_solves_matches_oracle(L, ctx, name, preci
         u, v = OC.update_gap(u, v, row[14], row[12], row[13], row[4], row[5])
 
 
-def test_preconditioned_lyapunov_equals_its_oracle(L, ctx):
+@pytest.mark.parametrize("steps", [dict(precond_sweeps=1), dict(precond_sweeps=8, precond_poly=1)],
+                         ids=["jacobi1", "chebyshev8"])
+def test_preconditioned_lyapunov_equals_its_oracle(L, ctx, steps):
     """The Lyapunov path with the preconditioner: X within 1e-6 of the
     Lyapunov oracle, true residual below tau."""
     from oracle import lyap as OL
@@ -165,7 +168,7 @@ def test_preconditioned_lyapunov_equals_its_oracle(L, ctx):
     HA = L.convdiff(P.A.dim, P.A.N, P.A.omega)
     A = convdiff_matrix(P.A.dim, P.A.N, P.A.omega)
     f, p = WL.lyap_inputs(P)
-    o = L.default_opts(tol=P.tol, selection="sym", precond="rbilu0", precond_sweeps=1)
+    o = L.default_opts(tol=P.tol, selection="sym", precond="rbilu0", **steps)
     res = ctx.solve_lyap(HA, to_dev(f), p, o)
     ora = OL.lyap_adi(A, f, p, kfixed=res.k)
     Z, d, _ = res.factors()
@@ -210,18 +213,19 @@ def _gen_setup(L, P):
     return HA, HB, HM, HC, A, B, M, C, f, g, pA, pB
 
 
-@pytest.mark.parametrize("name,precision,sweeps", [("GEN_SMALL", "fp64", 4), ("GEN_SMALL", "fp32", 0),
-                                                   ("GEN_SMALL_3D", "fp64", 2), ("GEN_SMALL_3D", "fp32", 5)])
-def test_generalized_with_lumped_mass_preconditioner_matches_oracle(L, ctx, name, precision, sweeps):
+@pytest.mark.parametrize("name,precision,sweeps,poly", [("GEN_SMALL", "fp64", 4, 0), ("GEN_SMALL", "fp32", 0, 0),
+                                                        ("GEN_SMALL_3D", "fp64", 2, 0), ("GEN_SMALL_3D", "fp32", 5, 0),
+                                                        ("GEN_SMALL", "fp64", 10, 1), ("GEN_SMALL_3D", "fp32", 6, 1)])
+def test_generalized_with_lumped_mass_preconditioner_matches_oracle(L, ctx, name, precision, sweeps, poly):
     """Pencils A + s M preconditioned by the red-black ILU(0) of
     A + s diag(M 1): the generalized iteration keeps the oracle's steps
     (+-1), X within 1e-6 of the direct-solve iterate and a true residual
     below tau, with fewer inner steps than unpreconditioned."""
-    say("generalized precond", name, precision, sweeps)
+    say("generalized precond", name, precision, sweeps, poly)
     P = getattr(WL, name)
     HA, HB, HM, HC, A, B, M, C, f, g, pA, pB = _gen_setup(L, P)
     fd, gd = to_dev(f), to_dev(g)
-    o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps)
+    o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps, precond_poly=poly)
     res = ctx.solve(HA, HB, fd, gd, pA, pB, o, M=HM, C=HC)
     plain = ctx.solve(HA, HB, fd, gd, pA, pB, L.default_opts(tol=P.tol, precision=precision), M=HM, C=HC)
     assert res.status == L.OK
