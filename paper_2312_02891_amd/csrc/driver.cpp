@@ -1182,7 +1182,13 @@ void prebuild_batch(lradi_ctx* c, const lradi_opts& o, const lradi_problem* prob
   const int nt = std::max(1, std::min({16, hw, 2 * nprob}));
   std::atomic<int> next{0};
   auto work = [&]() {
-    for (int t; (t = next.fetch_add(1)) < 2 * nprob;) prebuild_side(c, o, probs[t / 2], t % 2, 2 * (size_t)nprob);
+    for (int t; (t = next.fetch_add(1)) < 2 * nprob;) {
+      try {
+        prebuild_side(c, o, probs[t / 2], t % 2, 2 * (size_t)nprob);
+      } catch (...) {
+        // (the set-up builds this matrix's tables itself)
+      }
+    }
   };
   std::vector<std::thread> th;
   for (int i = 1; i < nt; ++i) th.emplace_back(work);
