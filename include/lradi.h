@@ -73,8 +73,9 @@ extern "C" {
 /* ILU(0) of A + s I in red-black order: rows 2-coloured so that every
  * off-diagonal entry joins a red and a black row; with S = [D_r E; F D_b]
  * (red first) it applies z_b = diag(T)^-1 (v_b - F D_r^-1 v_r),
- * T = D_b - F D_r^-1 E, refined by precond_sweeps Jacobi steps on T, then
- * z_r = D_r^-1 (v_r - E z_b).  Both half-steps are parallel over rows. */
+ * T = D_b - F D_r^-1 E, refined by precond_sweeps Jacobi steps (or, with
+ * precond_poly = 1, Chebyshev steps) on T, then z_r = D_r^-1 (v_r - E z_b).
+ * Both half-steps are parallel over rows. */
 #define LRADI_PRECOND_RBILU0 1
 
 /* ---- arithmetic of the inner Krylov solves ---------------------------- */
@@ -159,8 +160,9 @@ typedef struct {
                           LRADI_PRECOND_NONE or LRADI_PRECOND_RBILU0.  The
                           latter needs M = C = I and a bipartite sparsity
                           graph (else LRADI_EINVAL)                        */
-  int32_t precond_sweeps; /* LRADI_PRECOND_RBILU0: Jacobi sweeps on the
-                          Schur complement after the ILU(0) step, 0..64  */
+  int32_t precond_sweeps; /* LRADI_PRECOND_RBILU0: Jacobi sweeps (Chebyshev
+                          steps with precond_poly = 1) on the Schur
+                          complement after the ILU(0) step, 0..64       */
   int32_t precond_pairs;  /* 1 (default): run the sweeps two per launch where
                           the black rows tile well (each tile's first sweep
                           also covers the rows its second one reads, kept in
