@@ -1024,8 +1024,19 @@ def _serve_run(L, ctx, opts, prepared, warm, label):
     t0 = time.perf_counter()
     base = prepared[0][0]
     i, t_note, t_first, t_last = 0, 0.0, None, None
+    # peak device memory: the server's summed footprint of the problems in
+    # flight, and the device's used bytes (sampled every 10 ms)
+    import torch
+    free0, total = torch.cuda.mem_get_info()
+    peak_fp, peak_active, min_free, t_sample = 0, 0, free0, -1.0
     while len(got) < count:
         now = time.perf_counter() - t0
+        if now - t_sample > 0.01:
+            t_sample = now
+            st_now = srv.stats()
+            peak_fp = max(peak_fp, int(st_now["bytes_in_use"]))
+            peak_active = max(peak_active, int(st_now["active"]))
+            min_free = min(min_free, torch.cuda.mem_get_info()[0])
         if now - t_note > 5.0:
             t_note = now
             print(f"[serve {label}] t={now:.1f}s submitted={i} completed={len(got)}", file=sys.stderr,
@@ -1052,6 +1063,9 @@ def _serve_run(L, ctx, opts, prepared, warm, label):
     out = {"offered_rate": None, "requests": n, "warmup_requests": warm,
            "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
            "solves_per_s": round(n / (t_last - t_first), 2),
+           "peak_footprint_in_flight_GB": round(peak_fp / 1e9, 3), "peak_active_problems": peak_active,
+           "peak_device_used_GB": round((total - min_free) / 1e9, 3),
+           "device_used_before_GB": round((total - free0) / 1e9, 3),
            "p50_first_half_s": round(float(np.percentile(lat[: n // 2], 50)), 4),
            "p50_second_half_s": round(float(np.percentile(lat[n // 2:], 50)), 4),
            "status_counts": {str(k): sum(1 for m in meas if m[1] == k) for k in sorted({m[1] for m in meas})},
