@@ -182,8 +182,10 @@ typedef struct {
                           constant-coefficient upwind stencils); without
                           diagonal dominance (bound >= 1) the steps fall
                           back to Jacobi.  Same products with T per step;
-                          one sweep per launch (no pairs).  An extension,
-                          not in the paper                                */
+                          paired as the sweeps (precond_pairs), with four
+                          iterate blocks of the black rows instead of two
+                          where pairs can run.  An extension, not in the
+                          paper                                           */
   int32_t pad_;
 } lradi_opts;
 

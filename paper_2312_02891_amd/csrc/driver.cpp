@@ -430,6 +430,20 @@ struct SysWork {
     const int rpw = choose_rows_per_wg((int)n);
     const int nwg = (int)((n + rpw - 1) / rpw);
     const size_t pstride = (mm + 1) * rr * rr;
+    // pairs where the tiles are the row workgroups' black chunks and their
+    // regions are small enough
+    size_t nblack = n, plds = 0;
+    bool fit = false;
+    if (sweeps >= 0 && A->has_rb()) {
+      const lradi::RbData& B = *A->rb;
+      nblack = n - (size_t)B.nred;
+      plds = (size_t)B.maxreg * rr * tsz;
+      fit = pairs && sweeps >= 2 && B.ntile > 0 && B.tile == (int)((nblack + nwg - 1) / nwg) &&
+            plds <= (size_t)kPairLdsMax && (double)(nblack + B.nhalo) <= kPairMaxRegion * (double)nblack;
+    }
+    // compact iterates: two, or four for Chebyshev steps that may run in
+    // pairs (two read and two written per paired launch)
+    const bool four = fit && sweeps > 0 && poly != 0;
     const size_t sizes[] = {(mm + 1) * n * rr * tsz,  // V
                             n * rr * tsz,              // U
                             n * rr * 8,                // R
@@ -445,7 +459,7 @@ struct SysWork {
                             kSmDoubles * 8,            // sm
                             sweeps >= 0 ? (mm + 1) * n * rr * tsz : 0,  // P
                             sweeps > 0 ? n * rr * tsz : 0,              // Yb
-                            sweeps > 0 ? 2 * n * rr * tsz : 0,          // Eb (two compact iterates)
+                            sweeps > 0 ? (four ? 4 * nblack : 2 * n) * rr * tsz : 0,  // Eb
                             sweeps > 0 ? n * tsz : 0,                   // It
                             sweeps > 0 && A->has_rb()
                                 ? (size_t)A->rb->t2w * std::max(n - (size_t)A->rb->nred, (size_t)1) * tsz
@@ -519,13 +533,7 @@ struct SysWork {
       d.t2lc = B.t2lc.as<int>();
       d.halo_ci = B.halo_ci.as<int>();
       d.nhalo = B.nhalo;
-      // pairs where the tiles are the row workgroups' black chunks and
-      // their regions are small enough
-      const size_t nb = n - (size_t)B.nred, lds = (size_t)B.maxreg * rr * tsz;
-      const bool fit = B.ntile > 0 && B.tile == (int)((nb + nwg - 1) / nwg) && lds <= (size_t)kPairLdsMax &&
-                       (double)(nb + B.nhalo) <= kPairMaxRegion * (double)nb;
-      // (the paired kernel takes Jacobi steps only)
-      d.pair_lds = (pairs && sweeps >= 2 && fit && d.poly == 0) ? (int)lds : 0;
+      d.pair_lds = fit ? (int)plds : 0;
       d.diagT = (prec == LRADI_FP64) ? (const void*)B.diag64.p : (const void*)B.diag32.p;
       d.msT = B.ms64.p ? ((prec == LRADI_FP64) ? (const void*)B.ms64.p : (const void*)B.ms32.p) : nullptr;
       d.rbw = B.rbw;

@@ -217,6 +217,7 @@ struct SysDesc {
   void* P;              // preconditioned basis blocks P_0..P_m, basis precision
   void* Yb;             // sweeps: y of the black rows by black position, basis precision
   void* Eb;             // sweeps: two black iterates by black position
+                        // (four for Chebyshev steps with pair_lds > 0)
   void* It;             // sweeps: 1 / diag(T) by black position
   // sweeps: the off-diagonal entries of T = D_b - F D_r^{-1} E by black
   // position (pb = p - nred), slot-major with nb = n - nred: columns t2ci

@@ -588,11 +588,21 @@ __device__ inline void rb_sweep_row(const SysDesc& D, int pb, int nb, const T* _
   for (int q = 0; q < RQ; ++q) dst[drow * R + q0 + q] = acc[q] * it;
 }
 
-// one Chebyshev step for black position pb: dst row drow = prev + om (G
-// x_s + gamma c - prev) with x_s = src, G x_s + gamma c = x_s + gamma (J x_s +
-// c - x_s), J x_s + c the Jacobi update of rb_sweep_row and prev = x_{s-1}
-// (null: x_0 = 0); prev and dst may be the same block (each row reads its
-// own entries before writing them)
+// one entry of a Chebyshev step: x_{s+1} = xp + om (G x_s + gamma c - xp)
+// with G x_s + gamma c = xs + gamma (J x_s + c - xs), J x_s + c = acc * it
+// the Jacobi update, xs = x_s and xp = x_{s-1}.  The fused multiply-adds
+// are written out: left to contraction, a kernel that also forms acc * it
+// for a Jacobi step may share that product and round differently, and
+// single and paired steps must give the same bits.
+template <typename T>
+__device__ inline T cheb_entry(T acc, T it, T xs, T xp, T gam, T om) {
+  const T g = fma(gam, fma(acc, it, -xs), xs);
+  return fma(om, g - xp, xp);
+}
+
+// one Chebyshev step for black position pb: dst row drow from x_s = src
+// and x_{s-1} = prev (null: x_0 = 0); prev and dst may be the same block
+// (each row reads its own entries before writing them)
 template <typename T, int R, int RQ = R>
 __device__ inline void rb_cheb_row(const SysDesc& D, int pb, int nb, const T* __restrict__ src, const T* prev,
                                    T* dst, size_t drow, int q0, T gam, T om) {
@@ -603,8 +613,7 @@ __device__ inline void rb_cheb_row(const SysDesc& D, int pb, int nb, const T* __
   for (int q = 0; q < RQ; ++q) {
     const T xs = src[(size_t)pb * R + q0 + q];
     const T xp = prev ? prev[(size_t)pb * R + q0 + q] : T(0);
-    const T g = xs + gam * (acc[q] * it - xs);
-    dst[drow * R + q0 + q] = xp + om * (g - xp);
+    dst[drow * R + q0 + q] = cheb_entry(acc[q], it, xs, xp, gam, om);
   }
 }
 
@@ -685,6 +694,19 @@ __device__ inline T* rb_compact(const SysDesc& D, int nb, int t) {
 // launch, or two (pair) with a single last one for an odd count
 __device__ inline int rb_launch_index(int stage, int pair) { return pair ? (stage - 1) / 2 : stage - 1; }
 
+// Chebyshev steps of a system whose sweeps can run in pairs: Eb holds four
+// compact blocks and iterate x_t (1 <= t <= sweeps) sits in block (t - 1)
+// mod 4.  A paired launch reads x_s and x_{s-1} across its tile's region and
+// writes x_{s+1} (the next launch's previous iterate) and x_{s+2}: four
+// distinct blocks, so no workgroup overwrites what another still reads.
+// Single steps keep the same places, so pairs and single steps mix.
+__device__ inline bool rb_four(const SysDesc& D) { return D.poly && D.pair_lds > 0; }
+
+template <typename T>
+__device__ inline T* rb_iter4(const SysDesc& D, int nb, int t) {
+  return static_cast<T*>(D.Eb) + (size_t)((t - 1) % 4) * nb * D.r;
+}
+
 // KIND 0: fwd (black rows); 1: Jacobi or Chebyshev sweep `stage` (black
 // rows); 2: back (red rows); 5: T's values for the shift, and with Chebyshev
 // steps 1/diag(T) (black rows, at the first Arnoldi step of an inner solve,
@@ -743,6 +765,18 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
         if (D.poly) static_cast<T*>(D.It)[pp] = T(1) / rb_tdiag(x, p, i);
       }
     } else if constexpr (KIND == 1) {
+      if (rb_four(D)) {  // x_stage (and x_{stage-1}) to x_{stage+1}
+        const bool last = stage == D.sweeps;
+        const T* src = rb_iter4<T>(D, nb, stage);
+        T* dst = last ? Pj : rb_iter4<T>(D, nb, stage + 1);
+        const size_t drow = last ? (size_t)i : (size_t)pp;
+        if (cg != T(0))
+          rb_cheb_row<T, R, RQ>(D, pp, nb, src, stage >= 2 ? rb_iter4<T>(D, nb, stage - 1) : nullptr, dst, drow,
+                                q0, cg, com);
+        else
+          rb_sweep_row<T, R, RQ>(D, pp, nb, src, dst, drow, q0);
+        continue;
+      }
       const int ln = rb_launch_index(stage, pair);
       const T* src = rb_compact<T>(D, nb, ln);
       T* nxt = rb_compact<T>(D, nb, ln + 1);
@@ -771,10 +805,13 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
 // region indices), to the other compact block or, when it is the last
 // sweep, to P_j's black rows.  Each row's arithmetic is that of a single
 // sweep (the slots summed in the same order), so the result equals two
-// single-sweep launches bit for bit.  FAST (every tile at most kTPB / LPR
-// rows, T at most kPairRegSlots slots): each tile row has LPR lanes that
-// hold its region columns in registers from the start, so the second sweep
-// reads only LDS and cached operands.
+// single-sweep launches bit for bit.  Chebyshev steps (four iterate blocks):
+// the first step also reads the region's rows of x_{s-1} and writes the
+// tile's rows of x_{s+1} for the next launch, the second reads its own rows
+// of x_s.  FAST (every tile at most kTPB / LPR rows, T at most kPairRegSlots
+// slots): each tile row has LPR lanes that hold its region columns in
+// registers from the start, so the second sweep reads only LDS and cached
+// operands.
 template <typename T, int R, bool FAST>
 __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int stage, T* lds) {
   const int nb = D.n - D.nred;
@@ -783,7 +820,24 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
   if (nin <= 0) return;  // (uniform over the workgroup)
   const int h0 = D.halo_off[c.w], nreg = nin + (D.halo_off[c.w + 1] - h0);
   const int ln = rb_launch_index(stage, 1);
-  const T* src = rb_compact<T>(D, nb, ln);
+  const bool four = rb_four(D), last = stage + 1 == D.sweeps;
+  const T* src = four ? rb_iter4<T>(D, nb, stage) : rb_compact<T>(D, nb, ln);
+  T* dst = four ? (last ? nullptr : rb_iter4<T>(D, nb, stage + 2)) : rb_compact<T>(D, nb, ln + 1);
+  T* out = last ? Pj : dst;
+  // Chebyshev steps (gamma 0: the Jacobi fallback): omega_{stage+1} and
+  // omega_{stage+2}, x_{stage-1} (none for stage 1: x_0 = 0) and the block
+  // of x_{stage+1}, which only a later launch reads
+  T gam = T(0), om1 = T(0), om2 = T(0);
+  const T* prev = nullptr;
+  T* mid = nullptr;
+  if (four) {
+    gam = (T)cheb_gamma(D.sm + SM_CHEB);
+    om1 = (T)D.sm[SM_CHEB + kChebOmega + stage - 1];
+    om2 = (T)D.sm[SM_CHEB + kChebOmega + stage];
+    if (stage >= 2) prev = rb_iter4<T>(D, nb, stage - 1);
+    if (!last) mid = rb_iter4<T>(D, nb, stage + 1);
+  }
+  const bool cheb = gam != T(0);
   const T* It = static_cast<const T*>(D.It);
   constexpr int kS = kPairRegSlots;
   // FAST: even blocks give each tile row two lanes (r/2 columns each), so
@@ -806,13 +860,21 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
     rb_sweep_acc<T, R>(D, pb, nb, in ? D.t2ci : D.halo_ci, in ? nb : nhs, in ? pb : g, pb,
                        RbRows<T, R>{src}, 0, acc);
     const T it = It[pb];
+    if (cheb) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) lds[k * R + q] = acc[q] * it;
+      for (int q = 0; q < R; ++q) {
+        const T xp = prev ? prev[(size_t)pb * R + q] : T(0);
+        lds[k * R + q] = cheb_entry(acc[q], it, src[(size_t)pb * R + q], xp, gam, om1);
+      }
+      if (in && mid)
+#pragma unroll
+        for (int q = 0; q < R; ++q) mid[(size_t)pb * R + q] = lds[k * R + q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[k * R + q] = acc[q] * it;
+    }
   }
   __syncthreads();
-  const bool last = stage + 1 == D.sweeps;
-  T* dst = rb_compact<T>(D, nb, ln + 1);
-  T* out = last ? Pj : dst;
   if constexpr (FAST) {
     constexpr int RQ = R / LPR;
     const int k = threadIdx.x / LPR, q0 = (threadIdx.x % LPR) * RQ;
@@ -839,7 +901,9 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
     const T it = It[pb];
     const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
 #pragma unroll
-    for (int q = 0; q < RQ; ++q) out[row * R + q0 + q] = acc[q] * it;
+    for (int q = 0; q < RQ; ++q)
+      out[row * R + q0 + q] =
+          cheb ? cheb_entry(acc[q], it, lds[k * R + q0 + q], src[(size_t)pb * R + q0 + q], gam, om2) : acc[q] * it;
   } else {
     for (int k = threadIdx.x; k < nin; k += kTPB) {
       const int pb = p0 + k;
@@ -848,7 +912,9 @@ __device__ inline void rb_pair(const SysDesc& D, const RowCtx& c, T* Pj, int sta
       const T it = It[pb];
       const size_t row = last ? (size_t)D.rbrows[D.nred + pb] : (size_t)pb;
 #pragma unroll
-      for (int q = 0; q < R; ++q) out[row * R + q] = acc[q] * it;
+      for (int q = 0; q < R; ++q)
+        out[row * R + q] =
+            cheb ? cheb_entry(acc[q], it, lds[k * R + q], src[(size_t)pb * R + q], gam, om2) : acc[q] * it;
     }
   }
 }
@@ -867,7 +933,9 @@ __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
            (D.sweeps > 0 ? nb * R * t + nb * t : 0);
   // a Chebyshev step also reads its own rows of x_s and x_{s-1}
   if (KIND == 1) return sweep + (D.poly ? 2 * nb * R * t : 0);
-  if (KIND >= 3) return sweep + D.t2w * nb * 4 + ((unsigned long long)D.nhalo + D.nwg + 1) * 4;
+  // (a pair of Chebyshev steps: x_{s-1} read and x_{s+1} written once)
+  if (KIND >= 3)
+    return sweep + D.t2w * nb * 4 + ((unsigned long long)D.nhalo + D.nwg + 1) * 4 + (D.poly ? 2 * nb * R * t : 0);
   return nr * 4 + D.rbw * nr * (4 + t) + nr * t + 2 * nr * R * t + nb * R * t;
 }
 

@@ -2,7 +2,7 @@
 the oracle's definition: the first restart cycle's iterate equals the
 preconditioned block minimal-residual iterate with the oracle's Chebyshev
 preconditioner; without diagonal dominance the steps are the Jacobi ones
-bit for bit; the paired sweep launches are not used with them.  The ADI
+bit for bit; paired launches equal single ones bit for bit.  The ADI
 parity of the reduced and full 3-D configuration with these steps is in
 test_gpu_config3.py."""
 import numpy as np
@@ -86,26 +86,51 @@ def test_chebyshev_without_dominance_is_jacobi_bitwise(L, ctx):
     assert np.array_equal(out[0][0], out[1][0])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_chebyshev_steps_run_one_per_launch(L, ctx, prec):
-    """A 2-D grid above the pairing size: with Chebyshev steps the sweeps
-    run one per launch whatever precond_pairs says (the results agree bit
-    for bit), and a relaxed-accuracy solve needs fewer block steps than
-    with as many Jacobi sweeps."""
+@pytest.mark.parametrize("prec,r", [("fp64", 4), ("fp32", 4), ("fp64", 2), ("fp32", 1), ("fp64", 3)])
+def test_chebyshev_steps_run_in_pairs(L, ctx, prec, r):
+    """A 2-D grid above the pairing size: the Chebyshev steps run two per
+    launch (fewer preconditioner launches per product launch) with the same
+    bits as one per launch, and a relaxed-accuracy solve needs fewer block
+    steps than with as many Jacobi sweeps."""
     dim, N, omega = 2, 182, (30.0, -12.0)
     H = L.convdiff(dim, N, omega)
-    W = to_dev(np.random.default_rng(72).standard_normal((H.n, 4)))
+    W = to_dev(np.random.default_rng(72).standard_normal((H.n, r)))
     delta = 1e-8 * float(np.linalg.norm(W.cpu().numpy(), 2))
     res = {}
     for poly, pairs in ((1, 1), (1, 0), (0, 1)):
         o = L.default_opts(precision=prec, restart=30, max_inner=3000, precond="rbilu0", precond_sweeps=8,
-                           precond_poly=poly, precond_pairs=pairs)
+                           precond_poly=poly, precond_pairs=pairs, profile=1)
+        ctx.profile_reset()
         Zs, stats, st = ctx.shifted_solve([H], [-60.0], [W], [delta], o)
         assert st == L.OK and stats[0]["status"] == 0
-        res[(poly, pairs)] = (Zs[0].cpu().numpy(), stats[0]["steps"])
-    say("  steps chebyshev / jacobi", prec, res[(1, 1)][1], res[(0, 1)][1])
+        per = ctx.profile_read(L.PROF_PRECOND)[1] / ctx.profile_read(L.PROF_SPMM)[1]
+        res[(poly, pairs)] = (Zs[0].cpu().numpy(), stats[0]["steps"], per)
+    say("  steps chebyshev / jacobi", prec, r, res[(1, 1)][1], res[(0, 1)][1], "launches per product, paired",
+        res[(1, 1)][2], "single", res[(1, 0)][2])
     assert np.array_equal(res[(1, 1)][0], res[(1, 0)][0])
+    assert res[(1, 1)][2] < res[(1, 0)][2]
     assert res[(1, 1)][1] < res[(0, 1)][1]
+
+
+def test_chebyshev_four_block_single_steps_equal_pairs(L, ctx):
+    """Systems set up for paired Chebyshev steps (four iterate blocks) in a
+    batch with more than 262144 black rows, which is not paired, take their
+    steps one per launch in the same four blocks: each result equals the
+    system's solo paired solve bit for bit."""
+    H = L.convdiff(2, 182, (30.0, -12.0))
+    nsys = 17  # 17 x 16562 black rows
+    rng = np.random.default_rng(73)
+    Ws = [to_dev(rng.standard_normal((H.n, 2))) for _ in range(nsys)]
+    shifts = [-60.0 - 7.0 * k for k in range(nsys)]
+    deltas = [1e-7 * float(np.linalg.norm(W.cpu().numpy(), 2)) for W in Ws]
+    o = L.default_opts(restart=30, max_inner=3000, precond="rbilu0", precond_sweeps=7, precond_poly=1,
+                       precond_pairs=1)
+    Zs, stats, st = ctx.shifted_solve([H] * nsys, shifts, Ws, deltas, o)
+    assert st == L.OK
+    for k in (0, 8, 16):
+        Zk, sk, st = ctx.shifted_solve([H], [shifts[k]], [Ws[k]], [deltas[k]], o)
+        assert st == L.OK and sk[0]["steps"] == stats[k]["steps"]
+        assert np.array_equal(Zk[0].cpu().numpy(), Zs[k].cpu().numpy())
 
 
 def test_precond_poly_argument_errors(L, ctx):

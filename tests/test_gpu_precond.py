@@ -242,18 +242,24 @@ def test_generalized_with_lumped_mass_preconditioner_matches_oracle(L, ctx, name
     assert hp[:, 6].sum() + hp[:, 7].sum() < hn[:, 6].sum() + hn[:, 7].sum()
 
 
-@pytest.mark.parametrize("name,precision,sweeps,gen", [("C2", "fp64", 24, False), ("C2", "fp32", 5, False),
-                                                       ("C2", "fp64", 2, False), ("C2", "fp64", 7, True),
-                                                       ("SMALL_2D", "fp64", 24, False),
-                                                       ("SMALL_3D", "fp64", 3, False)])
-def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, sweeps, gen):
-    """Two Jacobi sweeps per launch (the first over each tile's region into
-    workgroup memory) give the same factors, history and inner step counts
-    as one sweep per launch, bit for bit.  The pairs are taken on 2-D grids
-    of at least 32768 rows (fewer preconditioner launches, counted by the
-    profiler); not on smaller matrices (no tiles) nor on 3-D grids, whose
-    regions are about twice their tiles."""
-    say("paired sweeps", name, precision, sweeps)
+@pytest.mark.parametrize("name,precision,sweeps,gen,poly", [("C2", "fp64", 24, False, 0), ("C2", "fp32", 5, False, 0),
+                                                            ("C2", "fp64", 2, False, 0), ("C2", "fp64", 7, True, 0),
+                                                            ("SMALL_2D", "fp64", 24, False, 0),
+                                                            ("SMALL_3D", "fp64", 3, False, 0),
+                                                            ("C2", "fp64", 48, False, 1), ("C2", "fp32", 5, False, 1),
+                                                            ("C2", "fp64", 2, False, 1), ("C2", "fp32", 16, False, 1),
+                                                            ("C2", "fp64", 7, True, 1),
+                                                            ("SMALL_2D", "fp64", 9, False, 1)])
+def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, sweeps, gen, poly):
+    """Two Jacobi sweeps or Chebyshev steps per launch (the first over each
+    tile's region into workgroup memory) give the same factors, history and
+    inner step counts as one per launch, bit for bit (Chebyshev steps: the
+    paired run keeps its iterates in four blocks, the single one in two,
+    and an odd count ends with a single step in the four blocks).  The pairs
+    are taken on 2-D grids of at least 32768 rows (fewer preconditioner
+    launches, counted by the profiler); not on smaller matrices (no tiles)
+    nor on 3-D grids, whose regions are about twice their tiles."""
+    say("paired sweeps", name, precision, sweeps, "chebyshev" if poly else "jacobi")
     P = getattr(WL, name)
     if gen:
         HA, HB, HM, HC, *_rest = _gen_setup(L, P)
@@ -270,7 +276,7 @@ def test_paired_sweeps_equal_single_sweeps_bitwise(L, ctx, name, precision, swee
     runs = []
     for pairs in (1, 0):
         o = L.default_opts(tol=P.tol, precision=precision, precond="rbilu0", precond_sweeps=sweeps,
-                           precond_pairs=pairs, profile=1, kmax=100)
+                           precond_pairs=pairs, precond_poly=poly, profile=1, kmax=100)
         ctx.profile_reset()
         res = ctx.solve(HA, HB, fd, gd, pA, pB, o, **kw)
         assert res.status == L.OK
