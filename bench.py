@@ -653,10 +653,12 @@ def bench_gen(args, L, WL):
     # kmax = 100 as for the paper's generalized finite-element example (Sec. 4):
     # the pencils' spectra are wider than the operators' and need more steps
     pre = _pre(PAIRED_JACOBI_SWEEPS)
+    cheb = _pre(PRECOND_SWEEPS, 1)
     for name, kw in (("fp64_relaxed", dict(selection="mid")), ("fp32_relaxed", dict(selection="mid", precision="fp32")),
                      ("fp64_fixed", dict(selection="fixed")),
                      ("fp64_relaxed_precond", dict(selection="mid", **pre)),
-                     ("fp32_relaxed_precond", dict(selection="mid", precision="fp32", **pre))):
+                     ("fp32_relaxed_precond", dict(selection="mid", precision="fp32", **pre)),
+                     ("fp64_relaxed_precond_cheb", dict(selection="mid", **cheb))):
         o = L.default_opts(tol=P.tol, kmax=100, **kw)
         for _ in range(args.warmup):
             ctx.solve(HA, HB, fd, gd, pA, pB, o, M=HM, C=HC)
@@ -703,6 +705,8 @@ def bench_gen(args, L, WL):
                       "n": P.A.n, "m": P.B.n, "steps": args.steps, **out,
                       "relaxed_saving_vs_fixed": round(1.0 - out["fp64_relaxed"]["s"] / out["fp64_fixed"]["s"], 3),
                       "speedup_precond_fp64": round(out["fp64_relaxed"]["s"] / out["fp64_relaxed_precond"]["s"], 3),
+                      "speedup_precond_cheb_fp64": round(out["fp64_relaxed"]["s"] /
+                                                         out["fp64_relaxed_precond_cheb"]["s"], 3),
                       "cpu_baseline": cpu}))
 
 
@@ -722,8 +726,10 @@ def bench_lyap(args, L, WL):
     ctx = L.Context(0)
     out, keep = {}, {}
     pre = _pre(PAIRED_JACOBI_SWEEPS)
+    cheb = _pre(PRECOND_SWEEPS, 1)
     runs = (("lyap_fp64_sym", "lyap", dict(selection="sym")),
             ("lyap_fp64_sym_precond", "lyap", dict(selection="sym", **pre)),
+            ("lyap_fp64_sym_precond_cheb", "lyap", dict(selection="sym", **cheb)),
             ("sylvester_fp64_sym_precond", "sylv", dict(selection="sym", b_is_transposed=1, **pre)),
             ("lyap_fp32_sym", "lyap", dict(selection="sym", precision="fp32")),
             ("lyap_fp64_mid", "lyap", dict(selection="mid")),
