@@ -739,6 +739,25 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
       if constexpr (KIND == 1) com = (T)D.sm[SM_CHEB + kChebOmega + stage - 1];
     }
   }
+  // a step's blocks: x_stage (input), x_{stage+1} (output unless it is the
+  // last step) and x_{stage-1} for a Chebyshev step (none at stage 1: x_0 =
+  // 0); in the two-block layout x_{stage-1} is the output block, which each
+  // row reads before writing
+  const T* ssrc = nullptr;
+  const T* sprev = nullptr;
+  T* snxt = nullptr;
+  if constexpr (KIND == 1) {
+    if (rb_four(D)) {
+      ssrc = rb_iter4<T>(D, nb, stage);
+      snxt = rb_iter4<T>(D, nb, stage + 1);
+      sprev = stage >= 2 ? rb_iter4<T>(D, nb, stage - 1) : nullptr;
+    } else {
+      const int ln = rb_launch_index(stage, pair);
+      ssrc = rb_compact<T>(D, nb, ln);
+      snxt = rb_compact<T>(D, nb, ln + 1);
+      sprev = stage >= 2 ? snxt : nullptr;
+    }
+  }
   for (int pp = p0 + (int)threadIdx.x / L; pp < p1; pp += kTPB / L) {
     const int p = off + pp;  // colour position
     const int i = D.rbrows[p];
@@ -765,27 +784,14 @@ __device__ inline void rb_rows(const SysDesc& D, const RowCtx& c, const RbCtx<T>
         if (D.poly) static_cast<T*>(D.It)[pp] = T(1) / rb_tdiag(x, p, i);
       }
     } else if constexpr (KIND == 1) {
-      if (rb_four(D)) {  // x_stage (and x_{stage-1}) to x_{stage+1}
-        const bool last = stage == D.sweeps;
-        const T* src = rb_iter4<T>(D, nb, stage);
-        T* dst = last ? Pj : rb_iter4<T>(D, nb, stage + 1);
-        const size_t drow = last ? (size_t)i : (size_t)pp;
-        if (cg != T(0))
-          rb_cheb_row<T, R, RQ>(D, pp, nb, src, stage >= 2 ? rb_iter4<T>(D, nb, stage - 1) : nullptr, dst, drow,
-                                q0, cg, com);
-        else
-          rb_sweep_row<T, R, RQ>(D, pp, nb, src, dst, drow, q0);
-        continue;
-      }
-      const int ln = rb_launch_index(stage, pair);
-      const T* src = rb_compact<T>(D, nb, ln);
-      T* nxt = rb_compact<T>(D, nb, ln + 1);
-      T* dst = stage == D.sweeps ? Pj : nxt;
+      // (one call of each step kind, so that the kernel keeps one copy of
+      // the gathers and its registers)
+      T* dst = stage == D.sweeps ? Pj : snxt;
       const size_t drow = stage == D.sweeps ? (size_t)i : (size_t)pp;
       if (cg != T(0))
-        rb_cheb_row<T, R, RQ>(D, pp, nb, src, stage >= 2 ? nxt : nullptr, dst, drow, q0, cg, com);
+        rb_cheb_row<T, R, RQ>(D, pp, nb, ssrc, sprev, dst, drow, q0, cg, com);
       else
-        rb_sweep_row<T, R, RQ>(D, pp, nb, src, dst, drow, q0);
+        rb_sweep_row<T, R, RQ>(D, pp, nb, ssrc, dst, drow, q0);
     } else {  // back: z_r = (v_r - E z) / (d_r + s)
       T g[RQ];
 #pragma unroll
