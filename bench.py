@@ -38,11 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # MI355X FP32 vector (non-matrix) peak
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Steps on the Schur complement in the preconditioned inner solves of
-# config 2: Chebyshev steps, one per launch (FP64 solve, median of 5: 24,
-# 32, 40, 48 steps gave 43.7, 42.8, 41.7, 41.2 ms; replaying captured ticks
-# 1 ms slower each), against Jacobi sweeps run two per launch (16, 20, 24,
-# 28, 32, 40 sweeps: 103, 92, 90, 89, 89, 89 ms before the tick tail; 86.2
-# ms at 32 after it)
+# config 2: Chebyshev steps, two per launch (FP64 solve, median of 5: 32,
+# 48, 64 steps gave 37.7, 35.6, 36.2 ms; one per launch 24, 32, 40, 48 gave
+# 43.7, 42.8, 41.7, 41.2 ms, replaying captured ticks 1 ms slower each),
+# against Jacobi sweeps run two per launch (16, 20, 24, 28, 32, 40 sweeps:
+# 103, 92, 90, 89, 89, 89 ms before the tick tail; 86.2 ms at 32 after it)
 PRECOND_SWEEPS = 48
 C2_PRECOND_POLY = 1
 # Jacobi sweeps, two per launch, of the generalized (lumped-mass) and
