@@ -950,9 +950,12 @@ __device__ inline unsigned long long rb_stage_bytes(const SysDesc& D) {
 // 1: the launches of the sweeps are paired), 5: T's values for the shift,
 // 6: the Chebyshev steps' spectral bounds (5 and 6 at the first Arnoldi step
 // of an inner solve only); one instance per kind, so each allocates only the
-// registers it needs
+// registers it needs.  The sweep kind at r = 8 is held to six waves per
+// SIMD (80 VGPRs without spills, against 88 and five waves unbounded: its
+// launches on the 3-D configuration ran about 1% faster); at other widths
+// the same bound spills, so they keep the compiler's choice.
 template <typename T, int RF, int KIND>
-__global__ __launch_bounds__(kTPB) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
+__global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(KIND == 1 && RF == 8 ? 6 : 1))) void k_precond(const SysDesc* __restrict__ d, const SysCtl* __restrict__ ctl,
                                                   const int2* __restrict__ rowmap, int stage, int pair,
                                                   unsigned long long* __restrict__ prof) {
   extern __shared__ double rb_lds[];  // KIND 3, 4: a tile region's iterate
